@@ -1,0 +1,800 @@
+/*
+ * ORACLE -- test infrastructure only.
+ *
+ * A plain, slow, FP64 CPU statement of what the mapping hot path computes,
+ * used by the tests, the smoke check and the benchmark's CPU baseline to
+ * check the device library.  It shares no code with the device library and
+ * must never be called by it.
+ *
+ * What it computes (SPH-to-Voronoi "Exact" mapping, Sec. 1 and Sec. 2.3, with
+ * the M4 cubic-spline kernel truncated at 2h, Sec. 2.4.2):
+ *   w_ic = integral over Voronoi cell c of W(|r - x_i|, h_i) dV
+ *   M_c  = sum_i m_i w_ic,  rho_c = M_c / V_c          (forward mapping)
+ *   c_i  = sum_c w_ic                                   (coverage)
+ *   q_i  = sum_c w_ic q_c / c_i                         (inverse mapping)
+ * and the tree-node pseudo-particle builder of Sec. 2.4 (tree walk with the
+ * opening-angle criterion, eq. opening_angle; node smoothing lengths from
+ * eqs. h_node, n_node, hnode_func, hnode_func_deriv, hnode_newton_raphson and
+ * hnode_estval with the bisection and fallback rules of Sec. 2.4.2).
+ *
+ * Route for w_ic (the paper cites the analytic solution but does not print
+ * it): the cell is a convex polyhedron, so w = sum_f sgn(d_f) I_f where I_f is
+ * the kernel integral over the cone with apex x and base face f and d_f the
+ * signed distance from x to the face plane (positive on the cell side).  In
+ * spherical coordinates about x, I_f = (1/4pi) int_{Omega_f} Phi(R(Omega))
+ * dOmega with Phi(q) the fraction of kernel mass inside radius q.  Writing the
+ * face in polar coordinates about the foot point P0 and splitting it into the
+ * signed triangles (P0, A, B) of its edges gives
+ *   I_f = (1/4pi) sum_e sgn(p_e) int_{phi_A}^{phi_B} Psi_d(U(phi)) dphi,
+ *   U(phi) = sqrt(d^2 + p_e^2 sec^2 phi),
+ *   Psi_d(U) = |d| int_{|d|}^{U} Phi(u)/u^2 du,
+ * (lengths in units of h).  Psi is taken in closed form from the radial
+ * antiderivative of Phi(u)/u^2; the angular integral is done by adaptive
+ * Gauss-Kronrod (7/15) with breakpoints where U crosses 1 and 2.
+ *
+ * Parity-pinned by the tests against: the kernel normalisation and Phi, an
+ * independent slab integral of the half-space, 3-D quadrature of a cube,
+ * Monte-Carlo sampling of the kernel over random convex cells, partition of
+ * unity over tessellations, symmetry (edge 1/4, corner 1/8), additivity under
+ * plane splits and the exact 0/1 limits.
+ *
+ * Build: gcc -O2 -std=c99 -fopenmp -ffp-contract=off -shared -fPIC oracle.c -lm
+ * (no FMA contraction: the candidate-pair test and the tree sums are defined
+ * operation by operation).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ------------------------------------------------------------------ kernel */
+/* M4 cubic spline shape, W(r,h) = w(r/h) / (pi h^3), zero beyond 2h. */
+double ora_w(double q) {
+  if (q < 1.0) return 1.0 - 1.5 * q * q + 0.75 * q * q * q;
+  if (q < 2.0) return 0.25 * (2.0 - q) * (2.0 - q) * (2.0 - q);
+  return 0.0;
+}
+
+/* dw/dq */
+double ora_dw(double q) {
+  if (q < 1.0) return -3.0 * q + 2.25 * q * q;
+  if (q < 2.0) return -0.75 * (2.0 - q) * (2.0 - q);
+  return 0.0;
+}
+
+/* Phi(q) = 4 int_0^q s^2 w(s) ds, the fraction of kernel mass within q. */
+double ora_Phi(double q) {
+  if (q <= 0.0) return 0.0;
+  if (q < 1.0) return (4.0 / 3.0) * q * q * q - 1.2 * pow(q, 5) + 0.5 * pow(q, 6);
+  if (q < 2.0)
+    return -1.0 / 15.0 + (8.0 / 3.0) * q * q * q - 3.0 * pow(q, 4) + 1.2 * pow(q, 5) - pow(q, 6) / 6.0;
+  return 1.0;
+}
+
+/* A continuous antiderivative of Phi(u)/u^2 on u > 0. */
+double ora_G(double u) {
+  if (u < 1.0) return (2.0 / 3.0) * u * u - 0.3 * pow(u, 4) + 0.1 * pow(u, 5);
+  if (u < 2.0)
+    return 1.0 / (15.0 * u) + (4.0 / 3.0) * u * u - u * u * u + 0.3 * pow(u, 4) - pow(u, 5) / 30.0 - 0.2;
+  return 1.4 - 1.0 / u;
+}
+
+/* Psi_d(U) = |d| int_{|d|}^{U} Phi(u)/u^2 du  (ad = |d| > 0, U >= ad). */
+double ora_Psi(double ad, double U) { return ad * (ora_G(U) - ora_G(ad)); }
+
+/* ---------------------------------------------------- adaptive quadrature */
+static const double gk_x[8] = {0.991455371120812639206854697526329, 0.949107912342758524526189684047851,
+                               0.864864423359769072789712788640926, 0.741531185599394439863864773280788,
+                               0.586087235467691130294144845693013, 0.405845151377397166906606412076961,
+                               0.207784955007898467600689403773245, 0.000000000000000000000000000000000};
+static const double gk_wk[8] = {0.022935322010529224963732008058970, 0.063092092629978553290700663189204,
+                                0.104790010322250183839876322541518, 0.140653259715525918745189590510238,
+                                0.169004726639267902826583426598550, 0.190350578064785409913256402421014,
+                                0.204432940075298892414161999234649, 0.209482141084727828012999174891714};
+static const double gk_wg[4] = {0.129484966168869693270611432679082, 0.279705391489276667901467771423780,
+                                0.381830050505118944950369775488975, 0.417959183673469387755102040816327};
+
+typedef struct {
+  double ad, p2, d2;
+} edge_t;
+
+/* integrand Psi_d(U(phi)) of one right-triangle fan */
+static double fan_integrand(const edge_t *e, double phi) {
+  double c = cos(phi);
+  double U = sqrt(e->d2 + e->p2 / (c * c));
+  return ora_Psi(e->ad, U);
+}
+
+static double gk15(const edge_t *e, double a, double b, double *err) {
+  double c = 0.5 * (a + b), hw = 0.5 * (b - a);
+  double fc = fan_integrand(e, c);
+  double rk = fc * gk_wk[7], rg = fc * gk_wg[3];
+  for (int j = 0; j < 7; ++j) {
+    double dx = hw * gk_x[j];
+    double f1 = fan_integrand(e, c - dx), f2 = fan_integrand(e, c + dx);
+    rk += gk_wk[j] * (f1 + f2);
+    if (j % 2 == 1) rg += gk_wg[j / 2] * (f1 + f2);
+  }
+  *err = fabs((rk - rg) * hw);
+  return rk * hw;
+}
+
+static double adapt(const edge_t *e, double a, double b, double tol, int depth) {
+  double err;
+  double r = gk15(e, a, b, &err);
+  if (err <= tol || depth >= 50 || b - a < 1e-15) return r;
+  double m = 0.5 * (a + b);
+  return adapt(e, a, m, 0.5 * tol, depth + 1) + adapt(e, m, b, 0.5 * tol, depth + 1);
+}
+
+/* int_{pa}^{pb} Psi_d(U(phi)) dphi with breakpoints at phi = 0 and where
+   U = 1 or U = 2. */
+static double fan_integral(double ad, double p, double pa, double pb) {
+  edge_t e = {ad, p * p, ad * ad};
+  double bp[8];
+  int nb = 0;
+  bp[nb++] = pa;
+  double cand[5];
+  int nc = 0;
+  cand[nc++] = 0.0;
+  for (int k = 1; k <= 2; ++k) {
+    double r2 = (double)(k * k) - e.d2; /* p^2 sec^2 = k^2 - d^2 */
+    if (r2 > e.p2) {
+      double ph = acos(fabs(p) / sqrt(r2));
+      cand[nc++] = ph;
+      cand[nc++] = -ph;
+    }
+  }
+  /* sort candidates ascending */
+  for (int i = 1; i < nc; ++i)
+    for (int j = i; j > 0 && cand[j] < cand[j - 1]; --j) {
+      double t = cand[j];
+      cand[j] = cand[j - 1];
+      cand[j - 1] = t;
+    }
+  for (int i = 0; i < nc; ++i)
+    if (cand[i] > pa && cand[i] < pb) bp[nb++] = cand[i];
+  bp[nb++] = pb;
+  double s = 0.0;
+  for (int i = 0; i + 1 < nb; ++i) s += adapt(&e, bp[i], bp[i + 1], 1e-14, 0);
+  return s;
+}
+
+/* ------------------------------------------------------------ geometry */
+static void v_sub(const double *a, const double *b, double *o) {
+  o[0] = a[0] - b[0];
+  o[1] = a[1] - b[1];
+  o[2] = a[2] - b[2];
+}
+static double v_dot(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void v_cross(const double *a, const double *b, double *o) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* Area vector (Newell) of a polygon and its vertex centroid. */
+static void poly_area_vec(int nv, const double *const *V, double *avec, double *cen) {
+  cen[0] = cen[1] = cen[2] = 0.0;
+  for (int k = 0; k < nv; ++k)
+    for (int j = 0; j < 3; ++j) cen[j] += V[k][j];
+  for (int j = 0; j < 3; ++j) cen[j] /= nv;
+  avec[0] = avec[1] = avec[2] = 0.0;
+  for (int k = 0; k < nv; ++k) {
+    double a[3], b[3], c[3];
+    v_sub(V[k], cen, a);
+    v_sub(V[(k + 1) % nv], cen, b);
+    v_cross(a, b, c);
+    for (int j = 0; j < 3; ++j) avec[j] += 0.5 * c[j];
+  }
+}
+
+/* Kernel integral of particle (x, h) over the cone with apex x and base the
+   convex polygon V[0..nv-1], whose orientation gives the outward normal n
+   (CCW seen from outside).  Returns sgn(d) I_f. */
+static double face_term(const double *x, double h, int nv, const double *const *V, const double *nhat,
+                        const double *cen) {
+  double xc[3];
+  v_sub(cen, x, xc);
+  double d = v_dot(nhat, xc); /* > 0: x on the inner side */
+  if (d == 0.0) return 0.0;
+  double ad = fabs(d) / h;
+  double P0[3] = {x[0] + d * nhat[0], x[1] + d * nhat[1], x[2] + d * nhat[2]};
+  double sum = 0.0;
+  for (int k = 0; k < nv; ++k) {
+    const double *A = V[k], *B = V[(k + 1) % nv];
+    double ab[3];
+    v_sub(B, A, ab);
+    double len = sqrt(v_dot(ab, ab));
+    if (len == 0.0) continue;
+    double e[3] = {ab[0] / len, ab[1] / len, ab[2] / len};
+    double mvec[3];
+    v_cross(nhat, e, mvec); /* in-plane normal pointing into the polygon */
+    double pa[3], pb[3];
+    v_sub(P0, A, pa);
+    double p = v_dot(pa, mvec) / h; /* > 0: foot on the inner side */
+    if (p == 0.0) continue;
+    double ta[3];
+    v_sub(A, P0, ta);
+    v_sub(B, P0, pb);
+    double tA = v_dot(ta, e) / h, tB = v_dot(pb, e) / h;
+    double phA = atan2(tA, fabs(p)), phB = atan2(tB, fabs(p));
+    double s = fan_integral(ad, p, phA, phB);
+    sum += (p > 0 ? 1.0 : -1.0) * s;
+  }
+  return (d > 0 ? 1.0 : -1.0) * sum / (4.0 * M_PI);
+}
+
+/* w = integral of W(|r-x|,h) over one convex cell given as faces.
+   cell_ref: a point strictly inside the cell (used to orient the faces). */
+static double cell_weight_faces(const double *x, double h, int nf, const int *fsz,
+                                const double *const *fv /* concatenated vertex pointers */,
+                                const double *inside) {
+  double w = 0.0;
+  int off = 0;
+  for (int f = 0; f < nf; ++f) {
+    int nv = fsz[f];
+    const double *const *V = fv + off;
+    off += nv;
+    if (nv < 3) continue;
+    double avec[3], cen[3];
+    poly_area_vec(nv, V, avec, cen);
+    double an = sqrt(v_dot(avec, avec));
+    if (an == 0.0) continue;
+    double nhat[3] = {avec[0] / an, avec[1] / an, avec[2] / an};
+    double gc[3];
+    v_sub(cen, inside, gc);
+    if (v_dot(nhat, gc) < 0.0) {
+      /* reversed orientation: walk the polygon backwards */
+      const double *R[512];
+      if (nv > 512) continue;
+      for (int k = 0; k < nv; ++k) R[k] = V[nv - 1 - k];
+      double nn[3] = {-nhat[0], -nhat[1], -nhat[2]};
+      w += face_term(x, h, nv, R, nn, cen);
+    } else {
+      w += face_term(x, h, nv, V, nhat, cen);
+    }
+  }
+  return w;
+}
+
+/* ----------------------------------------------- tessellation accessors */
+typedef struct {
+  int64_t n_cells;
+  const double *gen;      /* [C][3] */
+  const double *vert;     /* [V][3] */
+  const int64_t *cfo;     /* [C+1]  */
+  const int64_t *fvo;     /* [F+1]  */
+  const int32_t *fv;      /* [FV]   */
+} tess_t;
+
+static double cell_weight(const tess_t *T, int64_t c, const double *x, double h) {
+  int64_t f0 = T->cfo[c], f1 = T->cfo[c + 1];
+  int nf = (int)(f1 - f0);
+  int tot = (int)(T->fvo[f1] - T->fvo[f0]);
+  int *fsz = (int *)malloc(sizeof(int) * (nf > 0 ? nf : 1));
+  const double **fvp = (const double **)malloc(sizeof(double *) * (tot > 0 ? tot : 1));
+  double inside[3] = {0, 0, 0};
+  int k = 0;
+  for (int64_t f = f0; f < f1; ++f) {
+    fsz[f - f0] = (int)(T->fvo[f + 1] - T->fvo[f]);
+    for (int64_t t = T->fvo[f]; t < T->fvo[f + 1]; ++t) {
+      fvp[k] = T->vert + 3 * (int64_t)T->fv[t];
+      for (int j = 0; j < 3; ++j) inside[j] += fvp[k][j];
+      ++k;
+    }
+  }
+  /* the vertex-incidence average of a convex cell lies strictly inside */
+  for (int j = 0; j < 3; ++j) inside[j] /= (k > 0 ? k : 1);
+  double w = cell_weight_faces(x, h, nf, fsz, fvp, inside);
+  free(fsz);
+  free(fvp);
+  return w;
+}
+
+/* Volume by the divergence theorem over the (outward-oriented) faces. */
+double ora_cell_volume_t(const tess_t *T, int64_t c) {
+  int64_t f0 = T->cfo[c], f1 = T->cfo[c + 1];
+  double inside[3] = {0, 0, 0};
+  int k = 0;
+  for (int64_t t = T->fvo[f0]; t < T->fvo[f1]; ++t, ++k)
+    for (int j = 0; j < 3; ++j) inside[j] += T->vert[3 * (int64_t)T->fv[t] + j];
+  for (int j = 0; j < 3; ++j) inside[j] /= (k > 0 ? k : 1);
+  double vol = 0.0;
+  for (int64_t f = f0; f < f1; ++f) {
+    int nv = (int)(T->fvo[f + 1] - T->fvo[f]);
+    if (nv < 3 || nv > 512) continue;
+    const double *V[512];
+    for (int q = 0; q < nv; ++q) V[q] = T->vert + 3 * (int64_t)T->fv[T->fvo[f] + q];
+    double avec[3], cen[3];
+    poly_area_vec(nv, V, avec, cen);
+    double gc[3];
+    v_sub(cen, inside, gc);
+    vol += fabs(v_dot(gc, avec)) / 3.0;
+  }
+  return vol;
+}
+
+/* --------------------------------------------- canonical candidate pairs */
+/* Bounding radius of cell c about its generator: the smallest binary32 R
+   with R*R >= max_v |v - g|^2 (FP64, (dx*dx + dy*dy) + dz*dz). */
+float ora_cell_radius_t(const tess_t *T, int64_t c) {
+  const double *g = T->gen + 3 * c;
+  double r2 = 0.0;
+  for (int64_t t = T->fvo[T->cfo[c]]; t < T->fvo[T->cfo[c + 1]]; ++t) {
+    const double *v = T->vert + 3 * (int64_t)T->fv[t];
+    double dx = v[0] - g[0], dy = v[1] - g[1], dz = v[2] - g[2];
+    double s = (dx * dx + dy * dy) + dz * dz;
+    if (s > r2) r2 = s;
+  }
+  float R = (float)sqrt(r2);
+  while ((double)R * (double)R < r2) R = nextafterf(R, INFINITY);
+  while (R > 0.0f) {
+    float Rm = nextafterf(R, 0.0f);
+    if ((double)Rm * (double)Rm >= r2) R = Rm;
+    else break;
+  }
+  return R;
+}
+
+/* The canonical binary32 test: (c,i) is a candidate pair iff
+   d2 < s*s with dx = fl(x_i) - fl(g_x) (likewise y, z),
+   d2 = (dx*dx + dy*dy) + dz*dz and s = R_c + 2 fl(h_i). */
+static int canon_pair(const double *x, double h, const double *g, float R) {
+  float dx = (float)x[0] - (float)g[0];
+  float dy = (float)x[1] - (float)g[1];
+  float dz = (float)x[2] - (float)g[2];
+  float d2 = (dx * dx + dy * dy) + dz * dz;
+  float s = R + 2.0f * (float)h;
+  return d2 < s * s;
+}
+
+/* ------------------------------------------------------------ public API */
+
+/* Candidate pairs and weights of the listed cells (brute force over all
+   particles).  Pass 1 (w == NULL): counts[k] = number of pairs of cells[k].
+   Pass 2: for each listed cell, in order, particle indices ascending into
+   idx[] and weights into w[] (offsets are the running sum of counts). */
+void ora_pairs_weights(int64_t n_cells, const double *gen, const double *vert, const int64_t *cfo,
+                       const int64_t *fvo, const int32_t *fv, int64_t n_part, const double *xyz,
+                       const double *h, int64_t n_list, const int64_t *cells, int64_t *counts,
+                       const int64_t *offsets, int32_t *idx, double *w) {
+  tess_t T = {n_cells, gen, vert, cfo, fvo, fv};
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t k = 0; k < n_list; ++k) {
+    int64_t c = cells[k];
+    float R = ora_cell_radius_t(&T, c);
+    const double *g = gen + 3 * c;
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < n_part; ++i) {
+      if (!canon_pair(xyz + 3 * i, h[i], g, R)) continue;
+      if (w) {
+        int64_t o = offsets[k] + cnt;
+        idx[o] = (int32_t)i;
+        w[o] = cell_weight(&T, c, xyz + 3 * i, h[i]);
+      }
+      ++cnt;
+    }
+    if (!w) counts[k] = cnt;
+  }
+}
+
+/* Weight of one particle over one cell, regardless of the pair test. */
+double ora_weight(int64_t n_cells, const double *gen, const double *vert, const int64_t *cfo,
+                  const int64_t *fvo, const int32_t *fv, int64_t c, const double *x, double h) {
+  tess_t T = {n_cells, gen, vert, cfo, fvo, fv};
+  return cell_weight(&T, c, x, h);
+}
+
+/* Cell volumes and canonical radii of the listed cells. */
+void ora_cell_info(int64_t n_cells, const double *gen, const double *vert, const int64_t *cfo,
+                   const int64_t *fvo, const int32_t *fv, int64_t n_list, const int64_t *cells,
+                   double *vol, float *radius) {
+  tess_t T = {n_cells, gen, vert, cfo, fvo, fv};
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < n_list; ++k) {
+    if (vol) vol[k] = ora_cell_volume_t(&T, cells[k]);
+    if (radius) radius[k] = ora_cell_radius_t(&T, cells[k]);
+  }
+}
+
+/* Forward mapping of the listed cells: M_c = sum_i m_i w_ic over the
+   canonical pairs in ascending particle order, rho_c = M_c / V_c.
+   Also returns the number of pairs per listed cell. */
+void ora_map_cells(int64_t n_cells, const double *gen, const double *vert, const int64_t *cfo,
+                   const int64_t *fvo, const int32_t *fv, int64_t n_part, const double *xyz,
+                   const double *h, const double *m, int64_t n_list, const int64_t *cells, double *mass,
+                   double *rho, int64_t *npairs) {
+  tess_t T = {n_cells, gen, vert, cfo, fvo, fv};
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t k = 0; k < n_list; ++k) {
+    int64_t c = cells[k];
+    float R = ora_cell_radius_t(&T, c);
+    const double *g = gen + 3 * c;
+    double M = 0.0;
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < n_part; ++i) {
+      if (!canon_pair(xyz + 3 * i, h[i], g, R)) continue;
+      M += m[i] * cell_weight(&T, c, xyz + 3 * i, h[i]);
+      ++cnt;
+    }
+    mass[k] = M;
+    rho[k] = M / ora_cell_volume_t(&T, c);
+    if (npairs) npairs[k] = cnt;
+  }
+}
+
+/* Coverage c_i = sum_c w_ic and inverse mapping q_i = sum_c w_ic q_c / c_i
+   (q_i = 0 when c_i = 0) of the listed particles, brute force over cells.
+   q (nullable): [n_cells][ncomp] cell values; out_q [n_list][ncomp]. */
+void ora_particles(int64_t n_cells, const double *gen, const double *vert, const int64_t *cfo,
+                   const int64_t *fvo, const int32_t *fv, int64_t n_part, const double *xyz,
+                   const double *h, int64_t n_list, const int64_t *parts, const double *q, int32_t ncomp,
+                   double *cov, double *out_q) {
+  tess_t T = {n_cells, gen, vert, cfo, fvo, fv};
+  float *R = (float *)malloc(sizeof(float) * (n_cells > 0 ? n_cells : 1));
+#pragma omp parallel for schedule(static)
+  for (int64_t c = 0; c < n_cells; ++c) R[c] = ora_cell_radius_t(&T, c);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t k = 0; k < n_list; ++k) {
+    int64_t i = parts[k];
+    double ci = 0.0;
+    double acc[16];
+    for (int j = 0; j < ncomp && j < 16; ++j) acc[j] = 0.0;
+    for (int64_t c = 0; c < n_cells; ++c) {
+      if (!canon_pair(xyz + 3 * i, h[i], gen + 3 * c, R[c])) continue;
+      double w = cell_weight(&T, c, xyz + 3 * i, h[i]);
+      ci += w;
+      if (q)
+        for (int j = 0; j < ncomp && j < 16; ++j) acc[j] += w * q[c * ncomp + j];
+    }
+    cov[k] = ci;
+    if (q && out_q)
+      for (int j = 0; j < ncomp && j < 16; ++j) out_q[k * ncomp + j] = ci > 0.0 ? acc[j] / ci : 0.0;
+  }
+  free(R);
+}
+
+/* Weight of a particle over a single convex cell given as explicit faces:
+   nf faces, fsz[f] vertices each, verts concatenated [sum fsz][3];
+   `inside` is a point strictly inside the cell. */
+double ora_weight_poly(const double *x, double h, int nf, const int *fsz, const double *verts,
+                       const double *inside) {
+  int tot = 0;
+  for (int f = 0; f < nf; ++f) tot += fsz[f];
+  const double **fvp = (const double **)malloc(sizeof(double *) * (tot > 0 ? tot : 1));
+  for (int k = 0; k < tot; ++k) fvp[k] = verts + 3 * k;
+  double w = cell_weight_faces(x, h, nf, fsz, fvp, inside);
+  free(fvp);
+  return w;
+}
+
+/* Angular fan integral, exposed for unit tests:
+   int_{pa}^{pb} Psi_{ad}(sqrt(ad^2 + p^2 sec^2 phi)) dphi. */
+double ora_fan_integral(double ad, double p, double pa, double pb) { return fan_integral(ad, p, pa, pb); }
+
+/* ================================================= pseudo-particle builder */
+/*
+ * Sec. 2.4.1-2.4.2 with the octree variant of the gravity tree: cubic
+ * subdivision of the box, leaves hold at most leaf_max particles (or sit at
+ * max_depth).  Node position = centre of mass, size s = distance from the
+ * centre of mass to the furthest member (Sec. 2.2.1).  Node sums are formed
+ * bottom-up: a leaf sums its members in ascending particle index, an internal
+ * node sums its children in octant order (x bit, then y bit, then z bit as
+ * 1, 2, 4).
+ *
+ * Walk (Sec. 2.2.2, 2.4.1): depth first from the root.  A node is accepted
+ * when for every source r - s > r_part and not (theta^2 r^2 < s^2)
+ * (eq. opening_angle); an accepted node with one member is emitted as that
+ * real particle, otherwise as a pseudo-particle (mass, centre of mass).  A
+ * rejected leaf is opened: its members are emitted as real particles with
+ * their own h (ascending index).
+ *
+ * Node smoothing lengths (Sec. 2.4.2): for each pseudo-particle a,
+ * n(h) = sum_b W(|r_a - r_b|, h) over every emitted unit b (accepted nodes and
+ * the opened leaves standing in for their particles), self term included;
+ * f(h) = hfact n^(-1/3) - h, f'(h) = -(1/3) hfact n' n^(-4/3) - 1; Newton from
+ * h0 = hfact 2 s until |h_new - h| / h0 < eps.  Newton fails after 30 steps,
+ * when an iterate leaves [1e-2 h0, 1e2 h0] or when |f'| < 1e-12; then
+ * bisection on [1e-2 h0, 1e2 h0] to a bracket below eps h0 if f changes sign
+ * there, else h = h0.  Above `bypass` pseudo-particles every h = h0.
+ * Branch codes: 0 Newton, 1 bisection, 2 fallback h0, 3 bypass.
+ */
+typedef struct {
+  int64_t first;   /* first member in the tree's particle order */
+  int64_t count;
+  int32_t child[8];
+  int32_t is_leaf;
+  double M, S[3];  /* mass and sum of m x */
+  double com[3];
+  double s2;       /* max squared member distance from the com */
+} onode_t;
+
+typedef struct {
+  const double *x;
+  const double *m;
+  int leaf_max, max_depth;
+  int64_t *order; /* particle order (grouped by node) */
+  onode_t *nodes;
+  int64_t n_nodes, cap;
+} otree_t;
+
+static int cmp_i64(const void *a, const void *b) {
+  int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+  return (x > y) - (x < y);
+}
+
+static int32_t otree_build(otree_t *T, int64_t first, int64_t count, const double lo[3], double size,
+                           int depth) {
+  if (T->n_nodes == T->cap) {
+    T->cap = T->cap * 2 + 64;
+    T->nodes = (onode_t *)realloc(T->nodes, sizeof(onode_t) * T->cap);
+  }
+  int32_t id = (int32_t)T->n_nodes++;
+  onode_t nd;
+  memset(&nd, 0, sizeof nd);
+  nd.first = first;
+  nd.count = count;
+  for (int k = 0; k < 8; ++k) nd.child[k] = -1;
+  int64_t *ord = T->order + first;
+  if (count <= T->leaf_max || depth >= T->max_depth) {
+    nd.is_leaf = 1;
+    qsort(ord, (size_t)count, sizeof(int64_t), cmp_i64);
+    for (int64_t t = 0; t < count; ++t) {
+      int64_t j = ord[t];
+      nd.M += T->m[j];
+      for (int k = 0; k < 3; ++k) nd.S[k] += T->m[j] * T->x[3 * j + k];
+    }
+  } else {
+    double half = 0.5 * size;
+    double mid[3] = {lo[0] + half, lo[1] + half, lo[2] + half};
+    /* stable partition into octants (ascending index preserved) */
+    int64_t *tmp = (int64_t *)malloc(sizeof(int64_t) * count);
+    int64_t cnt[8] = {0}, off[8];
+    for (int64_t t = 0; t < count; ++t) {
+      const double *p = T->x + 3 * ord[t];
+      int o = (p[0] >= mid[0]) | ((p[1] >= mid[1]) << 1) | ((p[2] >= mid[2]) << 2);
+      cnt[o]++;
+    }
+    off[0] = 0;
+    for (int o = 1; o < 8; ++o) off[o] = off[o - 1] + cnt[o - 1];
+    int64_t pos[8];
+    memcpy(pos, off, sizeof pos);
+    for (int64_t t = 0; t < count; ++t) {
+      const double *p = T->x + 3 * ord[t];
+      int o = (p[0] >= mid[0]) | ((p[1] >= mid[1]) << 1) | ((p[2] >= mid[2]) << 2);
+      tmp[pos[o]++] = ord[t];
+    }
+    memcpy(ord, tmp, sizeof(int64_t) * count);
+    free(tmp);
+    for (int o = 0; o < 8; ++o) {
+      if (!cnt[o]) continue;
+      double clo[3] = {(o & 1) ? mid[0] : lo[0], (o & 2) ? mid[1] : lo[1], (o & 4) ? mid[2] : lo[2]};
+      int32_t c = otree_build(T, first + off[o], cnt[o], clo, half, depth + 1);
+      nd.child[o] = c;
+      nd.M += T->nodes[c].M;
+      for (int k = 0; k < 3; ++k) nd.S[k] += T->nodes[c].S[k];
+    }
+  }
+  for (int k = 0; k < 3; ++k) nd.com[k] = nd.S[k] / nd.M;
+  nd.s2 = 0.0;
+  for (int64_t t = 0; t < count; ++t) {
+    const double *p = T->x + 3 * ord[t];
+    double dx = p[0] - nd.com[0], dy = p[1] - nd.com[1], dz = p[2] - nd.com[2];
+    double s = (dx * dx + dy * dy) + dz * dz;
+    if (s > nd.s2) nd.s2 = s;
+  }
+  T->nodes[id] = nd;
+  return id;
+}
+
+static int accepted(const onode_t *nd, int n_src, const double *src, double r_part, double theta) {
+  double s = sqrt(nd->s2);
+  for (int k = 0; k < n_src; ++k) {
+    double dx = nd->com[0] - src[3 * k], dy = nd->com[1] - src[3 * k + 1], dz = nd->com[2] - src[3 * k + 2];
+    double r2 = (dx * dx + dy * dy) + dz * dz;
+    double r = sqrt(r2);
+    if (!(r - s > r_part)) return 0;
+    if ((theta * theta) * r2 < nd->s2) return 0;
+  }
+  return 1;
+}
+
+typedef struct {
+  int64_t n;
+  int32_t *kind;    /* 0 real particle, 1 pseudo-particle */
+  int64_t *first;   /* lowest member particle index */
+  int64_t *count;   /* members */
+  double *pos;      /* [][3] */
+  double *mass, *h, *s;
+  int32_t *unit;    /* h-solve unit of the entry */
+  /* h-solve units: accepted nodes and opened leaves */
+  int64_t n_units;
+  double *upos;     /* [][3] */
+} emit_t;
+
+static void walk(const otree_t *T, int32_t id, int n_src, const double *src, double r_part, double theta,
+                 const double *hp, emit_t *E) {
+  const onode_t *nd = &T->nodes[id];
+  if (accepted(nd, n_src, src, r_part, theta)) {
+    int64_t u = E->n_units++;
+    for (int k = 0; k < 3; ++k) E->upos[3 * u + k] = nd->com[k];
+    int64_t e = E->n++;
+    E->unit[e] = (int32_t)u;
+    E->count[e] = nd->count;
+    if (nd->count == 1) {
+      int64_t j = T->order[nd->first];
+      E->kind[e] = 0;
+      E->first[e] = j;
+      for (int k = 0; k < 3; ++k) E->pos[3 * e + k] = T->x[3 * j + k];
+      E->mass[e] = T->m[j];
+      E->h[e] = hp[j];
+      E->s[e] = 0.0;
+    } else {
+      int64_t mn = T->order[nd->first];
+      for (int64_t t = 1; t < nd->count; ++t)
+        if (T->order[nd->first + t] < mn) mn = T->order[nd->first + t];
+      E->kind[e] = 1;
+      E->first[e] = mn;
+      for (int k = 0; k < 3; ++k) E->pos[3 * e + k] = nd->com[k];
+      E->mass[e] = nd->M;
+      E->h[e] = 0.0;
+      E->s[e] = sqrt(nd->s2);
+    }
+    return;
+  }
+  if (nd->is_leaf) {
+    int64_t u = E->n_units++;
+    for (int k = 0; k < 3; ++k) E->upos[3 * u + k] = nd->com[k];
+    for (int64_t t = 0; t < nd->count; ++t) { /* members are in ascending index */
+      int64_t j = T->order[nd->first + t];
+      int64_t e = E->n++;
+      E->unit[e] = (int32_t)u;
+      E->kind[e] = 0;
+      E->first[e] = j;
+      E->count[e] = 1;
+      for (int k = 0; k < 3; ++k) E->pos[3 * e + k] = T->x[3 * j + k];
+      E->mass[e] = T->m[j];
+      E->h[e] = hp[j];
+      E->s[e] = 0.0;
+    }
+    return;
+  }
+  for (int o = 0; o < 8; ++o)
+    if (nd->child[o] >= 0) walk(T, nd->child[o], n_src, src, r_part, theta, hp, E);
+}
+
+/* n(h) and dn/dh at node position a over the units */
+static void node_sums(const double *a, double h, int64_t nu, const double *upos, double *n, double *dn) {
+  double sw = 0.0, sd = 0.0, ih = 1.0 / h;
+  for (int64_t b = 0; b < nu; ++b) {
+    double dx = a[0] - upos[3 * b], dy = a[1] - upos[3 * b + 1], dz = a[2] - upos[3 * b + 2];
+    double q = sqrt((dx * dx + dy * dy) + dz * dz) * ih;
+    if (q >= 2.0) continue;
+    double w = ora_w(q);
+    sw += w;
+    sd += -(3.0 * w + q * ora_dw(q));
+  }
+  *n = sw * ih * ih * ih / M_PI;
+  *dn = sd * ih * ih * ih * ih / M_PI;
+}
+
+static double hfun(const double *a, double h, int64_t nu, const double *upos, double hfact) {
+  double n, dn;
+  node_sums(a, h, nu, upos, &n, &dn);
+  return hfact * pow(n, -1.0 / 3.0) - h;
+}
+
+/* The node h-solve for one pseudo-particle; returns the branch code. */
+int ora_node_h(const double *a, double s, int64_t nu, const double *upos, double hfact, double eps,
+               double *h_out, int *iters) {
+  double h0 = hfact * 2.0 * s;
+  double lo = 1e-2 * h0, hi = 1e2 * h0;
+  double h = h0;
+  int it;
+  for (it = 0; it < 30; ++it) {
+    double n, dn;
+    node_sums(a, h, nu, upos, &n, &dn);
+    double f = hfact * pow(n, -1.0 / 3.0) - h;
+    double fp = -(1.0 / 3.0) * hfact * dn * pow(n, -4.0 / 3.0) - 1.0;
+    if (!(fabs(fp) >= 1e-12)) break;
+    double hn = h - f / fp;
+    if (!(hn >= lo && hn <= hi)) break;
+    if (fabs(hn - h) / h0 < eps) {
+      *h_out = hn;
+      if (iters) *iters = it + 1;
+      return 0;
+    }
+    h = hn;
+  }
+  if (iters) *iters = it;
+  double flo = hfun(a, lo, nu, upos, hfact), fhi = hfun(a, hi, nu, upos, hfact);
+  if (flo == 0.0) {
+    *h_out = lo;
+    return 1;
+  }
+  if (fhi == 0.0) {
+    *h_out = hi;
+    return 1;
+  }
+  if ((flo < 0.0) == (fhi < 0.0)) {
+    *h_out = h0;
+    return 2;
+  }
+  while (hi - lo >= eps * h0) {
+    double mid = 0.5 * (lo + hi);
+    double fm = hfun(a, mid, nu, upos, hfact);
+    if (fm == 0.0) {
+      *h_out = mid;
+      return 1;
+    }
+    if ((fm < 0.0) == (flo < 0.0)) {
+      lo = mid;
+      flo = fm;
+    } else {
+      hi = mid;
+    }
+  }
+  *h_out = 0.5 * (lo + hi);
+  return 1;
+}
+
+/* Full builder.  Outputs (capacity n entries each; pos [n][3]):
+   kind, first (lowest member index), count, pos, mass, h, s (node size),
+   branch (-1 for real particles), unit (h-solve unit of the entry).
+   Returns the number of emitted entries; *n_units_out = number of units,
+   upos_out (capacity n*3) their positions; *n_nodes_out = tree size. */
+int64_t ora_pseudo_build(int64_t n, const double *x, const double *m, const double *hp, int32_t n_src,
+                         const double *src, double r_part, double theta, double hfact, double eps,
+                         int32_t leaf_max, int32_t max_depth, int64_t bypass, int32_t *kind, int64_t *first,
+                         int64_t *count, double *pos, double *mass, double *h, double *s, int32_t *branch,
+                         int32_t *unit, int64_t *n_units_out, double *upos_out, int64_t *n_nodes_out) {
+  otree_t T;
+  T.x = x;
+  T.m = m;
+  T.leaf_max = leaf_max;
+  T.max_depth = max_depth;
+  T.order = (int64_t *)malloc(sizeof(int64_t) * (n > 0 ? n : 1));
+  for (int64_t i = 0; i < n; ++i) T.order[i] = i;
+  T.nodes = NULL;
+  T.n_nodes = T.cap = 0;
+  double lo[3] = {0.0, 0.0, 0.0};
+  otree_build(&T, 0, n, lo, 1.0, 0);
+  emit_t E;
+  E.n = 0;
+  E.kind = kind;
+  E.first = first;
+  E.count = count;
+  E.pos = pos;
+  E.mass = mass;
+  E.h = h;
+  E.s = s;
+  E.unit = unit;
+  E.n_units = 0;
+  E.upos = upos_out;
+  walk(&T, 0, n_src, src, r_part, theta, hp, &E);
+  int64_t n_pseudo = 0;
+  for (int64_t e = 0; e < E.n; ++e) n_pseudo += kind[e] == 1;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t e = 0; e < E.n; ++e) {
+    if (kind[e] != 1) {
+      branch[e] = -1;
+      continue;
+    }
+    if (n_pseudo > bypass) {
+      h[e] = hfact * 2.0 * s[e];
+      branch[e] = 3;
+      continue;
+    }
+    branch[e] = ora_node_h(pos + 3 * e, s[e], E.n_units, E.upos, hfact, eps, &h[e], NULL);
+  }
+  *n_units_out = E.n_units;
+  *n_nodes_out = T.n_nodes;
+  free(T.order);
+  free(T.nodes);
+  return E.n;
+}

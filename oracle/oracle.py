@@ -1,0 +1,216 @@
+"""ORACLE -- test infrastructure only (ctypes wrapper of oracle.c).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this module.  The device library never does.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_SO = os.path.join(_HERE, "liboracle.so")
+_L = None
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp"
+        subprocess.run(["gcc", "-O2", "-std=gnu99", "-fopenmp", "-ffp-contract=off", "-shared", "-fPIC",
+                        _SRC, "-o", tmp, "-lm"], check=True)
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def _lib():
+    global _L
+    if _L is None:
+        if not os.path.exists(_SO):
+            build(True)
+        L = ctypes.CDLL(_SO)
+        vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        L.ora_w.restype = dbl
+        L.ora_w.argtypes = [dbl]
+        L.ora_Phi.restype = dbl
+        L.ora_Phi.argtypes = [dbl]
+        L.ora_G.restype = dbl
+        L.ora_G.argtypes = [dbl]
+        L.ora_Psi.restype = dbl
+        L.ora_Psi.argtypes = [dbl, dbl]
+        L.ora_fan_integral.restype = dbl
+        L.ora_fan_integral.argtypes = [dbl, dbl, dbl, dbl]
+        L.ora_weight_poly.restype = dbl
+        L.ora_weight_poly.argtypes = [vp, dbl, ctypes.c_int, vp, vp, vp]
+        tess = [i64, vp, vp, vp, vp, vp]
+        L.ora_pairs_weights.restype = None
+        L.ora_pairs_weights.argtypes = tess + [i64, vp, vp, i64, vp, vp, vp, vp, vp]
+        L.ora_weight.restype = dbl
+        L.ora_weight.argtypes = tess + [i64, vp, dbl]
+        L.ora_cell_info.restype = None
+        L.ora_cell_info.argtypes = tess + [i64, vp, vp, vp]
+        L.ora_map_cells.restype = None
+        L.ora_map_cells.argtypes = tess + [i64, vp, vp, vp, i64, vp, vp, vp, vp]
+        L.ora_particles.restype = None
+        L.ora_particles.argtypes = tess + [i64, vp, vp, i64, vp, vp, i32, vp, vp]
+        L.ora_node_h.restype = ctypes.c_int
+        L.ora_node_h.argtypes = [vp, dbl, i64, vp, dbl, dbl, vp, vp]
+        L.ora_pseudo_build.restype = i64
+        L.ora_pseudo_build.argtypes = [i64, vp, vp, vp, i32, vp, dbl, dbl, dbl, dbl, i32, i32, i64] + [vp] * 12
+        _L = L
+    return _L
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def _tess_args(t):
+    return [t.n_cells, _p(t.generators), _p(t.vertices), _p(t.cell_face_off), _p(t.face_vtx_off), _p(t.face_vtx)]
+
+
+# ---------------------------------------------------------------- kernel
+def w(q: float) -> float:
+    return _lib().ora_w(q)
+
+
+def Phi(q: float) -> float:
+    return _lib().ora_Phi(q)
+
+
+def G(u: float) -> float:
+    return _lib().ora_G(u)
+
+
+def Psi(ad: float, U: float) -> float:
+    return _lib().ora_Psi(ad, U)
+
+
+def fan_integral(ad, p, pa, pb) -> float:
+    return _lib().ora_fan_integral(ad, p, pa, pb)
+
+
+# ---------------------------------------------------------- single cells
+def weight_poly(x, h, faces, inside=None) -> float:
+    """Kernel integral of particle (x,h) over one convex cell given as a list
+    of [k,3] vertex arrays (either orientation)."""
+    fsz = np.array([len(f) for f in faces], dtype=np.int32)
+    verts = _c(np.concatenate([np.asarray(f, float) for f in faces]), np.float64)
+    if inside is None:
+        inside = verts.mean(axis=0)
+    x = _c(x, np.float64)
+    inside = _c(inside, np.float64)
+    return _lib().ora_weight_poly(_p(x), float(h), len(faces), _p(fsz), _p(verts), _p(inside))
+
+
+# --------------------------------------------------------- tessellations
+def weight(t, c: int, x, h: float) -> float:
+    x = _c(x, np.float64)
+    return _lib().ora_weight(*_tess_args(t), int(c), _p(x), float(h))
+
+
+def cell_info(t, cells=None):
+    """(volumes, canonical binary32 radii) of the listed cells."""
+    cells = np.arange(t.n_cells, dtype=np.int64) if cells is None else _c(cells, np.int64)
+    vol = np.empty(len(cells))
+    rad = np.empty(len(cells), dtype=np.float32)
+    _lib().ora_cell_info(*_tess_args(t), len(cells), _p(cells), _p(vol), _p(rad))
+    return vol, rad
+
+
+def pairs_weights(t, pos, h, cells=None):
+    """Canonical candidate pairs of the listed cells with their weights:
+    (offsets[len(cells)+1], particle idx, w)."""
+    cells = np.arange(t.n_cells, dtype=np.int64) if cells is None else _c(cells, np.int64)
+    pos = _c(pos, np.float64)
+    h = _c(h, np.float64)
+    L = _lib()
+    counts = np.zeros(len(cells), dtype=np.int64)
+    L.ora_pairs_weights(*_tess_args(t), pos.shape[0], _p(pos), _p(h), len(cells), _p(cells), _p(counts),
+                        None, None, None)
+    off = np.zeros(len(cells) + 1, dtype=np.int64)
+    np.cumsum(counts, out=off[1:])
+    idx = np.empty(int(off[-1]), dtype=np.int32)
+    wv = np.empty(int(off[-1]))
+    L.ora_pairs_weights(*_tess_args(t), pos.shape[0], _p(pos), _p(h), len(cells), _p(cells), _p(counts),
+                        _p(off), _p(idx), _p(wv))
+    return off, idx, wv
+
+
+def map_cells(t, pos, h, m, cells=None):
+    """Forward mapping of the listed cells: (M_c, rho_c, n_pairs)."""
+    cells = np.arange(t.n_cells, dtype=np.int64) if cells is None else _c(cells, np.int64)
+    pos, h, m = _c(pos, np.float64), _c(h, np.float64), _c(m, np.float64)
+    mass = np.empty(len(cells))
+    rho = np.empty(len(cells))
+    npairs = np.empty(len(cells), dtype=np.int64)
+    _lib().ora_map_cells(*_tess_args(t), pos.shape[0], _p(pos), _p(h), _p(m), len(cells), _p(cells),
+                         _p(mass), _p(rho), _p(npairs))
+    return mass, rho, npairs
+
+
+def particles(t, pos, h, parts=None, q=None):
+    """Coverage c_i and inverse-mapped values q_i of the listed particles.
+    q: cell values [n_cells] or [n_cells, k]."""
+    pos, h = _c(pos, np.float64), _c(h, np.float64)
+    parts = np.arange(pos.shape[0], dtype=np.int64) if parts is None else _c(parts, np.int64)
+    cov = np.empty(len(parts))
+    outq = None
+    ncomp = 0
+    qq = None
+    if q is not None:
+        qq = _c(q, np.float64)
+        ncomp = 1 if qq.ndim == 1 else qq.shape[1]
+        if ncomp > 16:
+            raise ValueError("at most 16 components")
+        outq = np.empty((len(parts), ncomp))
+    _lib().ora_particles(*_tess_args(t), pos.shape[0], _p(pos), _p(h), len(parts), _p(parts), _p(qq), ncomp,
+                         _p(cov), _p(outq))
+    if outq is not None and qq.ndim == 1:
+        outq = outq[:, 0]
+    return cov, outq
+
+
+# ----------------------------------------------------- pseudo-particles
+def node_h(a, s, upos, hfact=1.2, eps=1e-2):
+    """(h, branch, newton iterations) of one node over the unit positions."""
+    a = _c(a, np.float64)
+    upos = _c(upos, np.float64)
+    h = np.zeros(1)
+    it = np.zeros(1, dtype=np.int32)
+    br = _lib().ora_node_h(_p(a), float(s), upos.shape[0], _p(upos), hfact, eps, _p(h), _p(it))
+    return float(h[0]), int(br), int(it[0])
+
+
+def pseudo_build(pos, m, h, sources, r_part=0.2, theta=0.5, hfact=1.2, eps=1e-2, leaf_max=8, max_depth=21,
+                 bypass=1_000_000):
+    """Tree-walk pseudo-particles and node smoothing lengths.  Returns a dict
+    of arrays in emission order."""
+    pos, m, h = _c(pos, np.float64), _c(m, np.float64), _c(h, np.float64)
+    src = _c(np.asarray(sources, float).reshape(-1, 3), np.float64)
+    n = pos.shape[0]
+    kind = np.empty(n, dtype=np.int32)
+    first = np.empty(n, dtype=np.int64)
+    count = np.empty(n, dtype=np.int64)
+    opos = np.empty((n, 3))
+    mass = np.empty(n)
+    oh = np.empty(n)
+    s = np.empty(n)
+    branch = np.empty(n, dtype=np.int32)
+    unit = np.empty(n, dtype=np.int32)
+    nu = np.zeros(1, dtype=np.int64)
+    upos = np.empty((n, 3))
+    nn = np.zeros(1, dtype=np.int64)
+    k = _lib().ora_pseudo_build(n, _p(pos), _p(m), _p(h), src.shape[0], _p(src), r_part, theta, hfact, eps,
+                                leaf_max, max_depth, bypass, _p(kind), _p(first), _p(count), _p(opos), _p(mass),
+                                _p(oh), _p(s), _p(branch), _p(unit), _p(nu), _p(upos), _p(nn))
+    k = int(k)
+    return dict(kind=kind[:k], first=first[:k], count=count[:k], pos=opos[:k], mass=mass[:k], h=oh[:k], s=s[:k],
+                branch=branch[:k], unit=unit[:k], upos=upos[:int(nu[0])], n_nodes=int(nn[0]))
