@@ -1,0 +1,170 @@
+"""Throughput of the Exact-mapping hot path on one MI355X.
+
+One step = one pass of the hot path over the device-resident inputs of the
+262,144-particle log-normal turbulent cloud (sigma_lnrho = 1.5, P(k) ~ k^-4,
+equal masses, SPH h with h = 1.2 (m/rho)^(1/3), Voronoi grid of the same
+points in the unit box):
+  particle staging, Morton sort + search hierarchy, candidate-pair count and
+  fill, per-cell sort, Exact integral of every candidate pair, particle-major
+  transpose with coverage, cell masses and densities (forward mapping), and
+  the inverse mapping of one cell field back onto the particles.
+The tessellation upload and its preprocessing (once per tessellation) are
+timed separately.
+
+Prints ONE JSON line.  Metric: particle-cell pair integrals per second.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Per-item arithmetic of the exact-integral kernel (FLOPs; square roots,
+# divisions, reciprocals, atan2 and asinh counted as one each), multiplied by
+# the device work counters of the same workload:
+FLOP_FACE_TEST = 6        # plane distance of the particle
+FLOP_FACE_INT = 32        # scaled distance, sphere cull, foot point, C_f, accumulation
+FLOP_EDGE_VISIT = 46      # edge direction, in-plane normal, p, tau_A, tau_B, a^2
+FLOP_EDGE_INT = 10        # clip to U < 2, regime split
+FLOP_FD = 60              # one evaluation of |d| F (3 transcendentals + polynomials)
+PEAK = {"mixed": 157.3, "fp64": 78.6}  # MI355X vector FP32 (packed) / FP64, TFLOP/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--n", type=int, default=262144)
+    ap.add_argument("--cpu-sample", type=int, default=800, help="cells of the oracle CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU sharding is a design in DESIGN.md, not a measured path", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2410_15227_amd as pkg
+    from paper_2410_15227_amd import workloads
+
+    t0 = time.time()
+    wl = workloads.turbulent(args.n, seed=2)
+    log(f"inputs: turbulent_{args.n} built in {time.time() - t0:.1f}s "
+        f"(faces={wl.tess.n_faces}, h range {wl.h.min():.2e}..{wl.h.max():.2e})")
+    ctx = pkg.Context(0)
+    dev = ctx.device
+    xyz = torch.tensor(wl.pos, dtype=torch.float64, device=dev)
+    h = torch.tensor(wl.h, dtype=torch.float64, device=dev)
+    m = torch.tensor(wl.m, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    dt = ctx.upload(wl.tess)
+    torch.cuda.synchronize()
+    tess_ms = (time.time() - t0) * 1e3
+    C = wl.tess.n_cells
+    mass = torch.empty(C, dtype=torch.float64, device=dev)
+    dens = torch.empty(C, dtype=torch.float64, device=dev)
+    cov = torch.empty(args.n, dtype=torch.float64, device=dev)
+    qcell = torch.tensor(np.sin(7 * wl.tess.generators[:, 0]) ** 2, dtype=torch.float64, device=dev)
+    qpart = torch.empty(args.n, dtype=torch.float64, device=dev)
+
+    def step():
+        res = pkg.map_particles_to_cells(ctx, dt, xyz, h, m, precision=args.precision, keep_pairs=True,
+                                         out_mass=mass, out_density=dens, out_coverage=cov)
+        pkg.map_cells_to_particles(ctx, res.pairs, qcell, out=qpart)
+        return res
+
+    # work counters (separate, untimed pass)
+    ctx.set_counting(True)
+    res = step()
+    torch.cuda.synchronize()
+    ctr = ctx.work_counters()
+    ctx.set_counting(False)
+    n_pairs = res.pairs.n_pairs
+    res.pairs.free()
+    for _ in range(args.warmup):
+        step().pairs.free()
+    torch.cuda.synchronize()
+    ctx.reset_timing()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = step()
+        r.pairs.free()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.set_timing(False)
+    k_ms, k_n = ctx.kernel_time("exact_integral")
+    other = {name: ctx.kernel_time(name) for name in ["pair_count", "pair_fill", "transpose", "cell_reduce",
+                                                     "reverse"]}
+    ms_step = el * 1e3 / args.steps
+    value = n_pairs * args.steps / el
+
+    flop = (FLOP_FACE_TEST * ctr[1] + FLOP_FACE_INT * ctr[2] + FLOP_EDGE_VISIT * ctr[3] + FLOP_EDGE_INT * ctr[4]
+            + FLOP_FD * (ctr[5] + ctr[6]))
+    flop_per_pair = flop / max(n_pairs, 1)
+    k_avg_s = k_ms / max(k_n, 1) / 1e3
+    achieved = flop / k_avg_s / 1e12 if k_avg_s > 0 else 0.0
+    peak = PEAK[args.precision]
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": "exact_integral", "kernel_ms": round(k_ms / max(k_n, 1), 4),
+                "flop_per_pair": round(flop_per_pair, 1)}
+
+    cpu = None
+    if not args.no_cpu and args.cpu_sample > 0:
+        from oracle import oracle
+        g = np.random.default_rng(99)
+        cells = np.sort(g.choice(C, args.cpu_sample, replace=False))
+        t0 = time.perf_counter()
+        Mref, _, npairs = oracle.map_cells(wl.tess, wl.pos, wl.h, wl.m, cells)
+        cpu_s = time.perf_counter() - t0
+        Mg = mass.cpu().numpy()[cells]
+        cpu = {"value": round(float(npairs.sum()) / cpu_s, 1), "unit": "pair integrals/s",
+               "cores": oracle.threads(), "kind": "oracle",
+               "sample": f"{args.cpu_sample} seeded cells of turbulent_{args.n} ({int(npairs.sum())} pairs, "
+                         f"brute-force pair test over all particles, {cpu_s:.1f}s)",
+               "max_rel_mass_err_vs_gpu": float(np.max(np.abs(Mg - Mref) / Mref))}
+
+    out = {
+        "metric": "particle-cell pair integrals/s",
+        "value": round(value, 1),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"turbulent_{args.n}", "n_particles": args.n, "n_cells": C,
+                   "n_pairs": int(n_pairs), "precision": args.precision, "sigma_lnrho": 1.5,
+                   "tess_upload_ms": round(tess_ms, 2)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in other.items()},
+        "work_counters": ctr,
+    }
+    print(json.dumps(out), flush=True)
+    dt.free()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

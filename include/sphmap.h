@@ -1,0 +1,228 @@
+/*
+ * sphmap: Exact SPH-particle <-> Voronoi-cell mapping and tree-node
+ * pseudo-particles on AMD Instinct MI355X (gfx950).
+ *
+ * The mapping transfers the SPH density field onto a Voronoi grid whose
+ * generation sites need not coincide with the particles, by integrating each
+ * particle's M4 cubic-spline kernel (truncated at 2h) analytically over every
+ * cell it overlaps (Sec. 1; Sec. 2.3, forward mapping; kernel in Sec. 2.4.2):
+ *     w_ic  = integral over cell c of W(|r - x_i|, h_i) dV
+ *     M_c   = sum_i m_i w_ic,      rho_c = M_c / V_c
+ * and transfers cell quantities back onto the particles (Sec. 2.3, inverse
+ * mapping):
+ *     q_i   = sum_c w_ic q_c / c_i,   c_i = sum_c w_ic  (q_i = 0 if c_i = 0).
+ * The pseudo-particle builder collapses gravity-tree nodes far from the
+ * ionising sources into pseudo-particles and solves their smoothing lengths
+ * (Sec. 2.4.1 eq. opening_angle; Sec. 2.4.2 eqs. h_node .. hnode_estval).
+ *
+ * Conventions for every entry point:
+ *  - Pointers prefixed d_ are DEVICE pointers (memory of the context's
+ *    device); pointers prefixed h_ are HOST pointers.  The caller owns every
+ *    buffer it passes in and out; the library never frees caller memory.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *    on it; device outputs are valid once the stream has reached that point.
+ *    Calls that must size an output (pair lists, pseudo-particle counts)
+ *    synchronise the stream once internally.
+ *  - Return value: 0 on success or a negative SPHMAP_E* code.  Arguments and
+ *    shapes are validated before anything is enqueued.  sphmap_last_error()
+ *    gives a message for the last failing call on that context.
+ *  - Contexts are independent; a context must not be used by two host
+ *    threads at once.
+ */
+#ifndef SPHMAP_H
+#define SPHMAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPHMAP_OK 0
+#define SPHMAP_EINVAL (-1) /* bad argument, size or layout                  */
+#define SPHMAP_ENOMEM (-2) /* device allocation failed                      */
+#define SPHMAP_EGEOM (-3)  /* tessellation fails validation                 */
+#define SPHMAP_EHIP (-4)   /* HIP runtime error                             */
+#define SPHMAP_ERANGE (-5) /* output capacity too small                     */
+
+#define SPHMAP_PREC_FP64 0  /* every step of the integral in binary64        */
+#define SPHMAP_PREC_MIXED 1 /* binary32 closed form, binary64 for degenerate
+                               pieces and for every accumulation            */
+
+typedef struct sphmap_ctx sphmap_ctx;     /* device, workspace, timers       */
+typedef struct sphmap_tess sphmap_tess;   /* device-resident tessellation     */
+typedef struct sphmap_pairs sphmap_pairs; /* retained pair list and weights   */
+
+/* Library version (major*10000 + minor*100 + patch). */
+int sphmap_version(void);
+
+/* Create a context on HIP device `device`.  *out receives the handle. */
+int sphmap_create(int32_t device, sphmap_ctx **out);
+/* Release a context and everything it still owns (tessellations and pair
+   lists created from it must be freed first or become invalid). */
+int sphmap_destroy(sphmap_ctx *ctx);
+/* Message of the last failing call on ctx ("" if none); valid until the
+   next call on ctx. */
+const char *sphmap_last_error(const sphmap_ctx *ctx);
+
+/* ------------------------------------------------------------------------
+ * Tessellation upload (Sec. 2.3: the grid code receives the generation sites
+ * and builds the Voronoi grid; here the grid is given).  Cells are convex
+ * polyhedra given as faces grouped by cell:
+ *   h_generators  [n_cells][3]      generation site of each cell (strictly
+ *                                   inside its cell)
+ *   h_vertices    [n_vertices][3]
+ *   h_cell_face_off [n_cells+1]     faces of cell c: cell_face_off[c] ..
+ *                                   cell_face_off[c+1]-1 (non-decreasing,
+ *                                   cell_face_off[0] = 0)
+ *   h_face_vtx_off  [n_faces+1]     vertex list of face f: face_vtx[
+ *                                   face_vtx_off[f] .. face_vtx_off[f+1]-1]
+ *   h_face_vtx    [face_vtx_off[n_faces]]  vertex indices, each face a
+ *                                   cyclic convex polygon in EITHER
+ *                                   orientation (oriented internally so its
+ *                                   normal points away from the generator)
+ * Faces of zero area are accepted and contribute nothing.  All arrays are
+ * copied; the host memory may be reused after return.  The preprocessing
+ * (face planes, volumes, bounding radii) is enqueued on `stream`.
+ * Errors: EINVAL for inconsistent offsets or out-of-range indices.
+ * ---------------------------------------------------------------------- */
+int sphmap_tess_upload(sphmap_ctx *ctx, int64_t n_cells, int64_t n_faces, int64_t n_vertices,
+                       const double *h_generators, const double *h_vertices, const int64_t *h_cell_face_off,
+                       const int64_t *h_face_vtx_off, const int32_t *h_face_vtx, void *stream,
+                       sphmap_tess **out);
+int sphmap_tess_free(sphmap_ctx *ctx, sphmap_tess *tess);
+/* Cell volumes V_c (divergence theorem) and the binary32 bounding radius R_c
+   of each cell about its generator (the smallest binary32 R with R*R >= the
+   binary64 max_v |v - g_c|^2).  Either output may be NULL. */
+int sphmap_tess_cell_info(sphmap_ctx *ctx, const sphmap_tess *tess, double *d_volume, float *d_radius,
+                          void *stream);
+
+/* ------------------------------------------------------------------------
+ * Forward mapping (Sec. 1; Sec. 2.3 "forward mapping"; kernel Sec. 2.4.2).
+ *   d_xyz [n][3], d_h [n], d_m [n]   particle positions, smoothing lengths,
+ *                                    masses (binary64, device)
+ *   precision                        SPHMAP_PREC_FP64 or SPHMAP_PREC_MIXED
+ *   normalize                        0: raw integrals (kernel mass beyond a
+ *                                    non-periodic wall is lost);
+ *                                    1: masses rescaled by 1/c_i so that
+ *                                    sum_c M_c = sum_i m_i
+ *   d_cell_mass [n_cells]            M_c
+ *   d_cell_density [n_cells]         M_c / V_c (nullable)
+ *   d_coverage [n]                   c_i = sum_c w_ic (nullable unless
+ *                                    normalize = 1)
+ *   pairs_out                        nullable; receives a retained pair list
+ *                                    (free with sphmap_pairs_free)
+ * Candidate pairs (c,i) are those with d2 < s*s evaluated in binary32,
+ * round to nearest, without contraction: dx = fl(x_i) - fl(g_x) (same for y,
+ * z), d2 = (dx*dx + dy*dy) + dz*dz, s = R_c + 2 fl(h_i).  Every pair whose
+ * kernel support overlaps the cell is a candidate; candidates that do not
+ * overlap get w = 0 exactly.  Cells take their pairs in ascending particle
+ * index and M_c is summed in that order (deterministic).
+ * Errors: EINVAL (n < 1, n >= 2^31, null required pointer, bad precision).
+ * ---------------------------------------------------------------------- */
+int map_particles_to_cells(sphmap_ctx *ctx, const sphmap_tess *tess, int64_t n, const double *d_xyz,
+                           const double *d_h, const double *d_m, int32_t precision, int32_t normalize,
+                           double *d_cell_mass, double *d_cell_density, double *d_coverage, void *stream,
+                           sphmap_pairs **pairs_out);
+
+/* Number of candidate pairs, cells and particles of a retained pair list. */
+int sphmap_pairs_info(const sphmap_pairs *pairs, int64_t *n_pairs, int64_t *n_cells, int64_t *n_particles);
+/* Copy the retained list into caller device buffers (any may be NULL):
+   d_cell_off [n_cells+1] (int64), d_particle [n_pairs] (int32, ascending
+   within each cell), d_w [n_pairs] (binary64 weights w_ic). */
+int sphmap_pairs_export(sphmap_ctx *ctx, const sphmap_pairs *pairs, int64_t *d_cell_off, int32_t *d_particle,
+                        double *d_w, void *stream);
+int sphmap_pairs_free(sphmap_ctx *ctx, sphmap_pairs *pairs);
+
+/* ------------------------------------------------------------------------
+ * Inverse mapping (Sec. 2.3, the ionic fractions returned onto the
+ * (pseudo-)particles): q_i = sum_c w_ic q_c / c_i, c_i = sum_c w_ic, q_i = 0
+ * where c_i = 0.  Uses the weights of a retained pair list.
+ *   d_cell_values [n_cells][n_components]      (row-major, binary64)
+ *   d_particle_values [n][n_components]
+ * Each particle's sums run over its cells in ascending cell index
+ * (deterministic).  Errors: EINVAL (null pointers, n_components < 1).
+ * ---------------------------------------------------------------------- */
+int map_cells_to_particles(sphmap_ctx *ctx, const sphmap_pairs *pairs, const double *d_cell_values,
+                           int32_t n_components, double *d_particle_values, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Pseudo-particles (Sec. 2.4).  The particles (positions in [0,1)^3) are
+ * grouped by an octree of the unit cube (cubic subdivision, at most
+ * leaf_max particles per leaf, at most max_depth levels).  Node position =
+ * centre of mass, node size s = distance from the centre of mass to the
+ * furthest member (Sec. 2.2.1); node sums are formed bottom-up, leaves over
+ * their members in ascending index, internal nodes over their children in
+ * octant order.  Walking depth first from the root, a node is accepted when
+ * for every source r - s > r_part and not (theta^2 r^2 < s^2)
+ * (eq. opening_angle, r = distance from the source to the centre of mass);
+ * a rejected leaf is opened and its particles are emitted with their own h.
+ * An accepted node with one member is emitted as that particle.
+ * Each pseudo-particle's smoothing length solves eq. hnode_func with
+ * n_node = sum_b W(|r_a - r_b|, h) over every emitted unit b (accepted nodes
+ * and opened leaves, the latter standing in for their particles, Sec.
+ * 2.4.2 last paragraph), self term included: Newton from h0 = h_fact 2 s
+ * (eq. hnode_estval) until |h_new - h|/h0 < eps_h; Newton fails after 30
+ * steps, when an iterate leaves [1e-2 h0, 1e2 h0] or when |f'| < 1e-12; then
+ * bisection on [1e-2 h0, 1e2 h0] if f changes sign there, else h = h0; with
+ * more than bypass_threshold pseudo-particles every h = h0.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  double r_part;             /* radius around sources kept at particle level   */
+  double theta;              /* opening angle                                  */
+  double h_fact;             /* h = h_fact n^(-1/3)                           */
+  double eps_h;              /* Newton tolerance relative to h0               */
+  int32_t leaf_max;          /* particles per leaf (at most)                  */
+  int32_t max_depth;         /* octree levels below the root (<= 21)          */
+  int64_t bypass_threshold;  /* use h0 for all above this many pseudo-particles */
+} sphmap_pseudo_opts;
+
+typedef struct {
+  int64_t n_nodes;           /* octree nodes                                  */
+  int64_t n_units;           /* emitted units (accepted nodes + opened leaves) */
+  int64_t n_pseudo;          /* pseudo-particles                               */
+  int64_t n_real;            /* particles emitted as themselves                */
+  int64_t branch_count[4];   /* h-solve branch: Newton, bisection, h0, bypass  */
+} sphmap_pseudo_stats;
+
+/* Inputs d_xyz [n][3], d_h [n], d_m [n] (device); h_sources [n_src][3] (host).
+   Outputs (device, capacity entries each, emission order = depth-first, an
+   opened leaf's particles in ascending index):
+     d_out_xyz [cap][3], d_out_h, d_out_m, d_out_s (node size, 0 for real)
+     d_out_kind (0 real particle, 1 pseudo-particle)
+     d_out_first (lowest member particle index), d_out_count (members)
+     d_out_branch (h-solve branch 0..3, -1 for real particles)
+   Any output except d_out_xyz, d_out_h, d_out_m may be NULL.
+   *n_out (host) receives the number of entries; ERANGE if it exceeds
+   capacity (nothing written then).  stats (host) may be NULL. */
+int build_pseudo_particles(sphmap_ctx *ctx, int64_t n, const double *d_xyz, const double *d_h, const double *d_m,
+                           int32_t n_src, const double *h_sources, const sphmap_pseudo_opts *opts,
+                           int64_t capacity, double *d_out_xyz, double *d_out_h, double *d_out_m, double *d_out_s,
+                           int32_t *d_out_kind, int64_t *d_out_first, int64_t *d_out_count,
+                           int32_t *d_out_branch, int64_t *n_out, sphmap_pseudo_stats *stats, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Kernel timing: when enabled, HIP events are recorded on the launch stream
+ * around each launch of the named kernels ("exact_integral", "pair_fill",
+ * "pair_count", "cell_reduce", "reverse", "transpose", "node_hsolve").
+ * sphmap_kernel_time synchronises on the recorded events and returns the
+ * summed milliseconds and the number of launches since the last reset.
+ * ---------------------------------------------------------------------- */
+int sphmap_set_timing(sphmap_ctx *ctx, int32_t enabled);
+int sphmap_kernel_time(sphmap_ctx *ctx, const char *name, double *total_ms, int64_t *launches);
+int sphmap_reset_timing(sphmap_ctx *ctx);
+
+/* Work counters of the last forward mapping (host, 8 values): [0] pairs,
+   [1] faces tested, [2] faces integrated (within 2h), [3] edges visited,
+   [4] edges integrated (edge line within 2h), [5] closed-form evaluations in
+   the inner regime (U < 1), [6] in the outer regime (1 <= U < 2), [7] edges
+   the mixed path evaluated in binary64.  Counting costs time; it is only
+   done when enabled (sphmap_set_counting). */
+int sphmap_set_counting(sphmap_ctx *ctx, int32_t enabled);
+int sphmap_work_counters(sphmap_ctx *ctx, int64_t *out8);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPHMAP_H */

@@ -43,6 +43,7 @@
  * operation by operation).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -50,6 +51,9 @@
 #ifndef M_PI
 #define M_PI 3.14159265358979323846
 #endif
+
+/* OpenMP threads the oracle's parallel loops use. */
+int ora_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------ kernel */
 /* M4 cubic spline shape, W(r,h) = w(r/h) / (pi h^3), zero beyond 2h. */

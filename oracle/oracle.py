@@ -33,6 +33,8 @@ def _lib():
             build(True)
         L = ctypes.CDLL(_SO)
         vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        L.ora_threads.restype = ctypes.c_int
+        L.ora_threads.argtypes = []
         L.ora_w.restype = dbl
         L.ora_w.argtypes = [dbl]
         L.ora_Phi.restype = dbl
@@ -74,6 +76,11 @@ def _c(a, dt):
 
 def _tess_args(t):
     return [t.n_cells, _p(t.generators), _p(t.vertices), _p(t.cell_face_off), _p(t.face_vtx_off), _p(t.face_vtx)]
+
+
+def threads() -> int:
+    """OpenMP threads the oracle uses."""
+    return int(_lib().ora_threads())
 
 
 # ---------------------------------------------------------------- kernel

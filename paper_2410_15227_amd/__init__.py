@@ -1,0 +1,263 @@
+"""Exact SPH <-> Voronoi mapping and tree-node pseudo-particles on MI355X.
+
+Thin Python binding of libsphmap (include/sphmap.h): argument marshalling
+only.  Device memory and streams come from PyTorch (ROCm); every step of the
+computation runs in the library's HIP kernels.
+
+    ctx  = Context(0)
+    tess = ctx.upload(tessellation)                # workloads.Tessellation
+    out  = map_particles_to_cells(ctx, tess, xyz, h, m, precision="mixed",
+                                  keep_pairs=True)
+    q    = map_cells_to_particles(ctx, out.pairs, cell_values)
+    ps   = build_pseudo_particles(ctx, xyz, h, m, sources)
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+from . import _native
+from ._native import PREC_FP64, PREC_MIXED, SphmapError
+
+__all__ = ["Context", "DeviceTessellation", "Pairs", "MapResult", "map_particles_to_cells",
+           "map_cells_to_particles", "build_pseudo_particles", "SphmapError", "PREC_FP64", "PREC_MIXED"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_f64(x, device, shape_last=None):
+    torch = _torch()
+    t = torch.as_tensor(x, dtype=torch.float64, device=device).contiguous()
+    if shape_last is not None and (t.ndim != 2 or t.shape[1] != shape_last):
+        raise ValueError(f"expected [n,{shape_last}] array")
+    return t
+
+
+class Context:
+    """A library context on one HIP device (torch device index)."""
+
+    def __init__(self, device: int = 0):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the mapping runs only on the HIP device")
+        self.device = torch.device("cuda", device)
+        torch.cuda.set_device(self.device)
+        L = _native.lib()
+        h = ctypes.c_void_p()
+        _native.check(L.sphmap_create(device, ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            _native.lib().sphmap_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, rc):
+        _native.check(rc, self.handle)
+
+    def upload(self, tess, stream=None) -> "DeviceTessellation":
+        return DeviceTessellation(self, tess, stream)
+
+    # timing / counters -------------------------------------------------
+    def set_timing(self, on: bool = True):
+        self.check(_native.lib().sphmap_set_timing(self.handle, 1 if on else 0))
+
+    def kernel_time(self, name: str):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self.check(_native.lib().sphmap_kernel_time(self.handle, name.encode(), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def reset_timing(self):
+        self.check(_native.lib().sphmap_reset_timing(self.handle))
+
+    def set_counting(self, on: bool = True):
+        self.check(_native.lib().sphmap_set_counting(self.handle, 1 if on else 0))
+
+    def work_counters(self):
+        arr = (ctypes.c_int64 * 8)()
+        self.check(_native.lib().sphmap_work_counters(self.handle, arr))
+        return list(arr)
+
+
+class DeviceTessellation:
+    """A tessellation resident on the device (see include/sphmap.h)."""
+
+    def __init__(self, ctx: Context, tess, stream=None):
+        import numpy as np
+        self.ctx = ctx
+        self.n_cells = int(tess.n_cells)
+        g = np.ascontiguousarray(tess.generators, dtype=np.float64)
+        v = np.ascontiguousarray(tess.vertices, dtype=np.float64)
+        cfo = np.ascontiguousarray(tess.cell_face_off, dtype=np.int64)
+        fvo = np.ascontiguousarray(tess.face_vtx_off, dtype=np.int64)
+        fv = np.ascontiguousarray(tess.face_vtx, dtype=np.int32)
+        h = ctypes.c_void_p()
+        L = _native.lib()
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        ctx.check(L.sphmap_tess_upload(ctx.handle, self.n_cells, len(fvo) - 1, len(v), p(g), p(v), p(cfo), p(fvo),
+                                       p(fv), _stream_handle(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def cell_info(self, stream=None):
+        torch = _torch()
+        vol = torch.empty(self.n_cells, dtype=torch.float64, device=self.ctx.device)
+        rad = torch.empty(self.n_cells, dtype=torch.float32, device=self.ctx.device)
+        self.ctx.check(_native.lib().sphmap_tess_cell_info(self.ctx.handle, self.handle, _ptr(vol), _ptr(rad),
+                                                            _stream_handle(stream)))
+        return vol, rad
+
+    def free(self):
+        if self.handle:
+            _native.lib().sphmap_tess_free(self.ctx.handle, self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if self.ctx.handle:
+                self.free()
+        except Exception:
+            pass
+
+
+class Pairs:
+    """A retained candidate-pair list with its weights."""
+
+    def __init__(self, ctx: Context, handle):
+        self.ctx = ctx
+        self.handle = handle
+        n = ctypes.c_int64()
+        c = ctypes.c_int64()
+        q = ctypes.c_int64()
+        ctx.check(_native.lib().sphmap_pairs_info(handle, ctypes.byref(n), ctypes.byref(c), ctypes.byref(q)))
+        self.n_pairs, self.n_cells, self.n_particles = n.value, c.value, q.value
+
+    def export(self, stream=None):
+        """(cell_off int64 [C+1], particle int32 [P], w float64 [P]) on the device."""
+        torch = _torch()
+        dev = self.ctx.device
+        off = torch.empty(self.n_cells + 1, dtype=torch.int64, device=dev)
+        part = torch.empty(max(self.n_pairs, 1), dtype=torch.int32, device=dev)
+        w = torch.empty(max(self.n_pairs, 1), dtype=torch.float64, device=dev)
+        self.ctx.check(_native.lib().sphmap_pairs_export(self.ctx.handle, self.handle, _ptr(off), _ptr(part), _ptr(w),
+                                                          _stream_handle(stream)))
+        return off, part[:self.n_pairs], w[:self.n_pairs]
+
+    def free(self):
+        if self.handle:
+            _native.lib().sphmap_pairs_free(self.ctx.handle, self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if self.ctx.handle:
+                self.free()
+        except Exception:
+            pass
+
+
+@dataclasses.dataclass
+class MapResult:
+    mass: object
+    density: object
+    coverage: object
+    pairs: Pairs | None
+
+
+def map_particles_to_cells(ctx: Context, tess: DeviceTessellation, xyz, h, m, precision: str | int = "mixed",
+                           normalize: bool = False, keep_pairs: bool = False, with_coverage: bool = True,
+                           out_mass=None, out_density=None, out_coverage=None, stream=None) -> MapResult:
+    """Forward Exact mapping: cell masses M_c, densities M_c/V_c and the
+    particle coverage c_i (see include/sphmap.h)."""
+    torch = _torch()
+    dev = ctx.device
+    xyz = _dev_f64(xyz, dev, 3)
+    h = _dev_f64(h, dev)
+    m = _dev_f64(m, dev)
+    n = xyz.shape[0]
+    if h.shape != (n,) or m.shape != (n,):
+        raise ValueError("h and m must have shape [n]")
+    prec = {"fp64": PREC_FP64, "mixed": PREC_MIXED}.get(precision, precision)
+    mass = out_mass if out_mass is not None else torch.empty(tess.n_cells, dtype=torch.float64, device=dev)
+    dens = out_density if out_density is not None else torch.empty(tess.n_cells, dtype=torch.float64, device=dev)
+    cov = out_coverage
+    if cov is None and with_coverage:
+        cov = torch.empty(n, dtype=torch.float64, device=dev)
+    ph = ctypes.c_void_p()
+    ctx.check(_native.lib().map_particles_to_cells(ctx.handle, tess.handle, n, _ptr(xyz), _ptr(h), _ptr(m), int(prec),
+                                                   1 if normalize else 0, _ptr(mass), _ptr(dens), _ptr(cov),
+                                                   _stream_handle(stream), ctypes.byref(ph) if keep_pairs else None))
+    pairs = Pairs(ctx, ph) if keep_pairs else None
+    return MapResult(mass, dens, cov, pairs)
+
+
+def map_cells_to_particles(ctx: Context, pairs: Pairs, cell_values, out=None, stream=None):
+    """Inverse mapping q_i = sum_c w_ic q_c / c_i ([C] or [C,k] -> [n] or [n,k])."""
+    torch = _torch()
+    q = torch.as_tensor(cell_values, dtype=torch.float64, device=ctx.device).contiguous()
+    if q.shape[0] != pairs.n_cells:
+        raise ValueError("cell_values must have one row per cell")
+    k = 1 if q.ndim == 1 else q.shape[1]
+    shape = (pairs.n_particles,) if q.ndim == 1 else (pairs.n_particles, k)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=ctx.device)
+    ctx.check(_native.lib().map_cells_to_particles(ctx.handle, pairs.handle, _ptr(q), k, _ptr(out),
+                                                   _stream_handle(stream)))
+    return out
+
+
+def build_pseudo_particles(ctx: Context, xyz, h, m, sources, r_part: float = 0.2, theta: float = 0.5,
+                           h_fact: float = 1.2, eps_h: float = 1e-2, leaf_max: int = 8, max_depth: int = 21,
+                           bypass_threshold: int = 1_000_000, stream=None) -> dict:
+    """Tree-node pseudo-particles and their smoothing lengths (Sec. 2.4).
+    Returns a dict of device tensors in emission order plus 'stats'."""
+    import numpy as np
+    torch = _torch()
+    dev = ctx.device
+    xyz = _dev_f64(xyz, dev, 3)
+    h = _dev_f64(h, dev)
+    m = _dev_f64(m, dev)
+    n = xyz.shape[0]
+    src = np.ascontiguousarray(np.asarray(sources, dtype=np.float64).reshape(-1, 3))
+    opts = _native.PseudoOpts(r_part, theta, h_fact, eps_h, leaf_max, max_depth, bypass_threshold)
+    cap = n
+    o = dict(xyz=torch.empty((cap, 3), dtype=torch.float64, device=dev),
+             h=torch.empty(cap, dtype=torch.float64, device=dev),
+             m=torch.empty(cap, dtype=torch.float64, device=dev),
+             s=torch.empty(cap, dtype=torch.float64, device=dev),
+             kind=torch.empty(cap, dtype=torch.int32, device=dev),
+             first=torch.empty(cap, dtype=torch.int64, device=dev),
+             count=torch.empty(cap, dtype=torch.int64, device=dev),
+             branch=torch.empty(cap, dtype=torch.int32, device=dev))
+    n_out = ctypes.c_int64()
+    st = _native.PseudoStats()
+    ctx.check(_native.lib().build_pseudo_particles(
+        ctx.handle, n, _ptr(xyz), _ptr(h), _ptr(m), src.shape[0], src.ctypes.data_as(ctypes.c_void_p),
+        ctypes.byref(opts), cap, _ptr(o["xyz"]), _ptr(o["h"]), _ptr(o["m"]), _ptr(o["s"]), _ptr(o["kind"]),
+        _ptr(o["first"]), _ptr(o["count"]), _ptr(o["branch"]), ctypes.byref(n_out), ctypes.byref(st),
+        _stream_handle(stream)))
+    k = n_out.value
+    res = {key: val[:k] for key, val in o.items()}
+    res["stats"] = dict(n_nodes=st.n_nodes, n_units=st.n_units, n_pseudo=st.n_pseudo, n_real=st.n_real,
+                        branch_count=list(st.branch_count))
+    return res

@@ -1,0 +1,104 @@
+"""Loader of the HIP library libsphmap.so and its C signatures.
+
+The library is built in-tree by paper_2410_15227_amd.build (hipcc, gfx950).
+There is no fallback: if the library is missing every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsphmap.so")
+
+OK, EINVAL, ENOMEM, EGEOM, EHIP, ERANGE = 0, -1, -2, -3, -4, -5
+PREC_FP64, PREC_MIXED = 0, 1
+
+# every symbol include/sphmap.h declares
+EXPORTS = [
+    "sphmap_version", "sphmap_create", "sphmap_destroy", "sphmap_last_error",
+    "sphmap_tess_upload", "sphmap_tess_free", "sphmap_tess_cell_info",
+    "map_particles_to_cells", "sphmap_pairs_info", "sphmap_pairs_export", "sphmap_pairs_free",
+    "map_cells_to_particles", "build_pseudo_particles",
+    "sphmap_set_timing", "sphmap_kernel_time", "sphmap_reset_timing",
+    "sphmap_set_counting", "sphmap_work_counters",
+]
+
+
+class PseudoOpts(ctypes.Structure):
+    _fields_ = [("r_part", ctypes.c_double), ("theta", ctypes.c_double), ("h_fact", ctypes.c_double),
+                ("eps_h", ctypes.c_double), ("leaf_max", ctypes.c_int32), ("max_depth", ctypes.c_int32),
+                ("bypass_threshold", ctypes.c_int64)]
+
+
+class PseudoStats(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("n_units", ctypes.c_int64), ("n_pseudo", ctypes.c_int64),
+                ("n_real", ctypes.c_int64), ("branch_count", ctypes.c_int64 * 4)]
+
+
+class SphmapError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"sphmap error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2410_15227_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        pp = ctypes.POINTER(ctypes.c_void_p)
+        L.sphmap_version.restype = ctypes.c_int
+        L.sphmap_version.argtypes = []
+        L.sphmap_create.restype = ctypes.c_int
+        L.sphmap_create.argtypes = [i32, pp]
+        L.sphmap_destroy.restype = ctypes.c_int
+        L.sphmap_destroy.argtypes = [vp]
+        L.sphmap_last_error.restype = ctypes.c_char_p
+        L.sphmap_last_error.argtypes = [vp]
+        L.sphmap_tess_upload.restype = ctypes.c_int
+        L.sphmap_tess_upload.argtypes = [vp, i64, i64, i64, vp, vp, vp, vp, vp, vp, pp]
+        L.sphmap_tess_free.restype = ctypes.c_int
+        L.sphmap_tess_free.argtypes = [vp, vp]
+        L.sphmap_tess_cell_info.restype = ctypes.c_int
+        L.sphmap_tess_cell_info.argtypes = [vp, vp, vp, vp, vp]
+        L.map_particles_to_cells.restype = ctypes.c_int
+        L.map_particles_to_cells.argtypes = [vp, vp, i64, vp, vp, vp, i32, i32, vp, vp, vp, vp, pp]
+        L.sphmap_pairs_info.restype = ctypes.c_int
+        L.sphmap_pairs_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.sphmap_pairs_export.restype = ctypes.c_int
+        L.sphmap_pairs_export.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.sphmap_pairs_free.restype = ctypes.c_int
+        L.sphmap_pairs_free.argtypes = [vp, vp]
+        L.map_cells_to_particles.restype = ctypes.c_int
+        L.map_cells_to_particles.argtypes = [vp, vp, vp, i32, vp, vp]
+        L.build_pseudo_particles.restype = ctypes.c_int
+        L.build_pseudo_particles.argtypes = [vp, i64, vp, vp, vp, i32, vp, ctypes.POINTER(PseudoOpts), i64,
+                                             vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i64),
+                                             ctypes.POINTER(PseudoStats), vp]
+        L.sphmap_set_timing.restype = ctypes.c_int
+        L.sphmap_set_timing.argtypes = [vp, i32]
+        L.sphmap_kernel_time.restype = ctypes.c_int
+        L.sphmap_kernel_time.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+        L.sphmap_reset_timing.restype = ctypes.c_int
+        L.sphmap_reset_timing.argtypes = [vp]
+        L.sphmap_set_counting.restype = ctypes.c_int
+        L.sphmap_set_counting.argtypes = [vp, i32]
+        L.sphmap_work_counters.restype = ctypes.c_int
+        L.sphmap_work_counters.argtypes = [vp, ctypes.POINTER(i64)]
+        _lib = L
+    return _lib
+
+
+def check(rc: int, ctx_handle=None):
+    if rc != OK:
+        msg = ""
+        if ctx_handle is not None:
+            msg = lib().sphmap_last_error(ctx_handle).decode(errors="replace")
+        raise SphmapError(rc, msg)

@@ -1,0 +1,346 @@
+// C-ABI entry points of libsphmap (declared in include/sphmap.h).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "common.hpp"
+
+struct sphmap_ctx {
+  sphmap::Ctx c;
+};
+struct sphmap_tess {
+  sphmap::TessDev t;
+};
+struct sphmap_pairs {
+  sphmap::PairsDev p;
+};
+
+namespace {
+
+template <typename F>
+int guarded(sphmap_ctx *ctx, F &&fn) {
+  try {
+    if (ctx) {
+      ctx->c.last_error.clear();
+      SPH_HIP(hipSetDevice(ctx->c.device));
+    }
+    fn();
+    return SPHMAP_OK;
+  } catch (const sphmap::Error &e) {
+    if (ctx) ctx->c.last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    if (ctx) ctx->c.last_error = "host allocation failed";
+    return SPHMAP_ENOMEM;
+  } catch (...) {
+    if (ctx) ctx->c.last_error = "unexpected exception";
+    return SPHMAP_EHIP;
+  }
+}
+
+inline hipStream_t as_stream(void *s) { return (hipStream_t)s; }
+
+}  // namespace
+
+extern "C" {
+
+int sphmap_version(void) { return 100; }
+
+int sphmap_create(int32_t device, sphmap_ctx **out) {
+  if (!out) return SPHMAP_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SPHMAP_EINVAL;
+  std::unique_ptr<sphmap_ctx> ctx(new sphmap_ctx);
+  ctx->c.device = device;
+  int rc = guarded(ctx.get(), [&] {
+    ctx->c.d_counters = ctx->c.arena.get<int64_t>("counters", 8);
+    ctx->c.d_status = ctx->c.arena.get<int>("status", 4);
+    SPH_HIP(hipMemset(ctx->c.d_counters, 0, 8 * sizeof(int64_t)));
+    SPH_HIP(hipMemset(ctx->c.d_status, 0, 4 * sizeof(int)));
+  });
+  if (rc != SPHMAP_OK) return rc;
+  *out = ctx.release();
+  return SPHMAP_OK;
+}
+
+int sphmap_destroy(sphmap_ctx *ctx) {
+  if (!ctx) return SPHMAP_EINVAL;
+  (void)hipSetDevice(ctx->c.device);
+  (void)hipDeviceSynchronize();
+  for (auto &kv : ctx->c.timers)
+    for (auto &r : kv.second) {
+      (void)hipEventDestroy(r.start);
+      (void)hipEventDestroy(r.stop);
+    }
+  delete ctx->c.scratch_pairs;
+  ctx->c.scratch_pairs = nullptr;
+  delete ctx;
+  return SPHMAP_OK;
+}
+
+const char *sphmap_last_error(const sphmap_ctx *ctx) { return ctx ? ctx->c.last_error.c_str() : "null context"; }
+
+int sphmap_tess_upload(sphmap_ctx *ctx, int64_t n_cells, int64_t n_faces, int64_t n_vertices,
+                       const double *h_generators, const double *h_vertices, const int64_t *h_cell_face_off,
+                       const int64_t *h_face_vtx_off, const int32_t *h_face_vtx, void *stream, sphmap_tess **out) {
+  if (!ctx || !out) return SPHMAP_EINVAL;
+  *out = nullptr;
+  std::unique_ptr<sphmap_tess> T(new sphmap_tess);
+  int rc = guarded(ctx, [&] {
+    SPH_REQUIRE(n_cells >= 1 && n_cells < ((int64_t)1 << 31), SPHMAP_EINVAL, "n_cells out of range");
+    SPH_REQUIRE(n_faces >= 0 && n_faces < ((int64_t)1 << 31), SPHMAP_EINVAL, "n_faces out of range");
+    SPH_REQUIRE(n_vertices >= 0 && n_vertices < ((int64_t)1 << 31), SPHMAP_EINVAL, "n_vertices out of range");
+    SPH_REQUIRE(h_generators && h_vertices && h_cell_face_off && h_face_vtx_off && h_face_vtx, SPHMAP_EINVAL,
+                "null tessellation array");
+    SPH_REQUIRE(h_cell_face_off[0] == 0 && h_cell_face_off[n_cells] == n_faces, SPHMAP_EINVAL,
+                "cell_face_off must start at 0 and end at n_faces");
+    for (int64_t c = 0; c < n_cells; ++c)
+      SPH_REQUIRE(h_cell_face_off[c + 1] >= h_cell_face_off[c], SPHMAP_EINVAL, "cell_face_off not non-decreasing");
+    SPH_REQUIRE(h_face_vtx_off[0] == 0, SPHMAP_EINVAL, "face_vtx_off must start at 0");
+    for (int64_t f = 0; f < n_faces; ++f)
+      SPH_REQUIRE(h_face_vtx_off[f + 1] >= h_face_vtx_off[f], SPHMAP_EINVAL, "face_vtx_off not non-decreasing");
+    const int64_t FV = h_face_vtx_off[n_faces];
+    for (int64_t k = 0; k < FV; ++k)
+      SPH_REQUIRE(h_face_vtx[k] >= 0 && h_face_vtx[k] < n_vertices, SPHMAP_EINVAL, "face vertex index out of range");
+    double lo[3] = {HUGE_VAL, HUGE_VAL, HUGE_VAL}, hi[3] = {-HUGE_VAL, -HUGE_VAL, -HUGE_VAL};
+    for (int64_t v = 0; v < n_vertices; ++v)
+      for (int j = 0; j < 3; ++j) {
+        double x = h_vertices[3 * v + j];
+        SPH_REQUIRE(std::isfinite(x), SPHMAP_EINVAL, "non-finite vertex");
+        lo[j] = std::min(lo[j], x);
+        hi[j] = std::max(hi[j], x);
+      }
+    for (int64_t c = 0; c < 3 * n_cells; ++c)
+      SPH_REQUIRE(std::isfinite(h_generators[c]), SPHMAP_EINVAL, "non-finite generator");
+    sphmap::TessDev &t = T->t;
+    t.n_cells = n_cells;
+    t.n_faces = n_faces;
+    t.n_vertices = n_vertices;
+    t.n_fv = FV;
+    t.device = ctx->c.device;
+    double size = 0;
+    for (int j = 0; j < 3; ++j) {
+      t.box_lo[j] = n_vertices ? lo[j] : 0.0;
+      size = std::max(size, n_vertices ? hi[j] - lo[j] : 1.0);
+    }
+    t.box_size = size > 0 ? size * (1.0 + 1e-12) : 1.0;
+    hipStream_t s = as_stream(stream);
+    t.gen = t.mem.get<double>("gen", 3 * n_cells);
+    t.vert = t.mem.get<double>("vert", 3 * std::max<int64_t>(n_vertices, 1));
+    t.cell_face_off = t.mem.get<int64_t>("cfo", n_cells + 1);
+    t.face_vtx_off = t.mem.get<int64_t>("fvo", n_faces + 1);
+    t.face_vtx = t.mem.get<int32_t>("fv", std::max<int64_t>(FV, 1));
+    SPH_HIP(hipMemcpyAsync(t.gen, h_generators, 3 * n_cells * sizeof(double), hipMemcpyHostToDevice, s));
+    if (n_vertices)
+      SPH_HIP(hipMemcpyAsync(t.vert, h_vertices, 3 * n_vertices * sizeof(double), hipMemcpyHostToDevice, s));
+    SPH_HIP(hipMemcpyAsync(t.cell_face_off, h_cell_face_off, (n_cells + 1) * sizeof(int64_t), hipMemcpyHostToDevice,
+                           s));
+    SPH_HIP(hipMemcpyAsync(t.face_vtx_off, h_face_vtx_off, (n_faces + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    if (FV) SPH_HIP(hipMemcpyAsync(t.face_vtx, h_face_vtx, FV * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    sphmap::tess_prepare(ctx->c, t, s);
+  });
+  if (rc != SPHMAP_OK) return rc;
+  *out = T.release();
+  return SPHMAP_OK;
+}
+
+int sphmap_tess_free(sphmap_ctx *ctx, sphmap_tess *tess) {
+  if (!ctx || !tess) return SPHMAP_EINVAL;
+  (void)hipSetDevice(ctx->c.device);
+  (void)hipDeviceSynchronize();
+  delete tess;
+  return SPHMAP_OK;
+}
+
+int sphmap_tess_cell_info(sphmap_ctx *ctx, const sphmap_tess *tess, double *d_volume, float *d_radius,
+                          void *stream) {
+  if (!ctx || !tess) return SPHMAP_EINVAL;
+  return guarded(ctx, [&] {
+    hipStream_t s = as_stream(stream);
+    const auto &t = tess->t;
+    if (d_volume)
+      SPH_HIP(hipMemcpyAsync(d_volume, t.volume, t.n_cells * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (d_radius)
+      SPH_HIP(hipMemcpyAsync(d_radius, t.radius, t.n_cells * sizeof(float), hipMemcpyDeviceToDevice, s));
+  });
+}
+
+int map_particles_to_cells(sphmap_ctx *ctx, const sphmap_tess *tess, int64_t n, const double *d_xyz,
+                           const double *d_h, const double *d_m, int32_t precision, int32_t normalize,
+                           double *d_cell_mass, double *d_cell_density, double *d_coverage, void *stream,
+                           sphmap_pairs **pairs_out) {
+  if (!ctx) return SPHMAP_EINVAL;
+  if (pairs_out) *pairs_out = nullptr;
+  std::unique_ptr<sphmap_pairs> owned;
+  int rc = guarded(ctx, [&] {
+    SPH_REQUIRE(tess, SPHMAP_EINVAL, "null tessellation");
+    SPH_REQUIRE(n >= 1 && n < ((int64_t)1 << 31), SPHMAP_EINVAL, "n out of range [1, 2^31)");
+    SPH_REQUIRE(d_xyz && d_h && d_m && d_cell_mass, SPHMAP_EINVAL, "null required pointer");
+    SPH_REQUIRE(precision == SPHMAP_PREC_FP64 || precision == SPHMAP_PREC_MIXED, SPHMAP_EINVAL, "bad precision");
+    SPH_REQUIRE(normalize == 0 || normalize == 1, SPHMAP_EINVAL, "normalize must be 0 or 1");
+    SPH_REQUIRE(tess->t.device == ctx->c.device, SPHMAP_EINVAL, "tessellation belongs to another device");
+    hipStream_t s = as_stream(stream);
+    sphmap::Ctx &C = ctx->c;
+    sphmap::PairsDev *P;
+    if (pairs_out) {
+      owned.reset(new sphmap_pairs);
+      P = &owned->p;
+    } else {
+      if (!C.scratch_pairs) C.scratch_pairs = new sphmap::PairsDev;
+      P = C.scratch_pairs;
+    }
+    P->device = C.device;
+    sphmap::PartDev pd{n, d_xyz, d_h, d_m, C.arena.get<float4>("x32", n)};
+    sphmap::particles_prepare(C, pd, s);
+    sphmap::find_pairs(C, tess->t, pd, *P, s);
+    sphmap::exact_integral(C, tess->t, pd, *P, precision, s);
+    sphmap::particle_major(C, *P, s);
+    sphmap::cell_reduce(C, tess->t, pd, *P, normalize != 0, d_cell_mass, d_cell_density, s);
+    if (d_coverage)
+      SPH_HIP(hipMemcpyAsync(d_coverage, P->coverage, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (C.counting) {
+      SPH_HIP(hipMemcpyAsync(C.counters, C.d_counters, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      SPH_HIP(hipStreamSynchronize(s));
+      C.counters[0] = P->n_pairs;
+    }
+  });
+  if (rc == SPHMAP_OK && pairs_out) *pairs_out = owned.release();
+  return rc;
+}
+
+int sphmap_pairs_info(const sphmap_pairs *pairs, int64_t *n_pairs, int64_t *n_cells, int64_t *n_particles) {
+  if (!pairs) return SPHMAP_EINVAL;
+  if (n_pairs) *n_pairs = pairs->p.n_pairs;
+  if (n_cells) *n_cells = pairs->p.n_cells;
+  if (n_particles) *n_particles = pairs->p.n_particles;
+  return SPHMAP_OK;
+}
+
+int sphmap_pairs_export(sphmap_ctx *ctx, const sphmap_pairs *pairs, int64_t *d_cell_off, int32_t *d_particle,
+                        double *d_w, void *stream) {
+  if (!ctx || !pairs) return SPHMAP_EINVAL;
+  return guarded(ctx, [&] {
+    hipStream_t s = as_stream(stream);
+    const auto &P = pairs->p;
+    if (d_cell_off)
+      SPH_HIP(hipMemcpyAsync(d_cell_off, P.cell_off, (P.n_cells + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    if (d_particle && P.n_pairs)
+      SPH_HIP(hipMemcpyAsync(d_particle, P.pair_p, P.n_pairs * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    if (d_w && P.n_pairs)
+      SPH_HIP(hipMemcpyAsync(d_w, P.w, P.n_pairs * sizeof(double), hipMemcpyDeviceToDevice, s));
+  });
+}
+
+int sphmap_pairs_free(sphmap_ctx *ctx, sphmap_pairs *pairs) {
+  if (!ctx || !pairs) return SPHMAP_EINVAL;
+  (void)hipSetDevice(ctx->c.device);
+  (void)hipDeviceSynchronize();
+  delete pairs;
+  return SPHMAP_OK;
+}
+
+int map_cells_to_particles(sphmap_ctx *ctx, const sphmap_pairs *pairs, const double *d_cell_values,
+                           int32_t n_components, double *d_particle_values, void *stream) {
+  if (!ctx) return SPHMAP_EINVAL;
+  return guarded(ctx, [&] {
+    SPH_REQUIRE(pairs, SPHMAP_EINVAL, "null pair list");
+    SPH_REQUIRE(d_cell_values && d_particle_values, SPHMAP_EINVAL, "null value array");
+    SPH_REQUIRE(n_components >= 1, SPHMAP_EINVAL, "n_components must be >= 1");
+    SPH_REQUIRE(pairs->p.device == ctx->c.device, SPHMAP_EINVAL, "pair list belongs to another device");
+    sphmap::reverse_map(ctx->c, pairs->p, d_cell_values, n_components, d_particle_values, as_stream(stream));
+  });
+}
+
+int build_pseudo_particles(sphmap_ctx *ctx, int64_t n, const double *d_xyz, const double *d_h, const double *d_m,
+                           int32_t n_src, const double *h_sources, const sphmap_pseudo_opts *opts, int64_t capacity,
+                           double *d_out_xyz, double *d_out_h, double *d_out_m, double *d_out_s, int32_t *d_out_kind,
+                           int64_t *d_out_first, int64_t *d_out_count, int32_t *d_out_branch, int64_t *n_out,
+                           sphmap_pseudo_stats *stats, void *stream) {
+  if (!ctx) return SPHMAP_EINVAL;
+  return guarded(ctx, [&] {
+    SPH_REQUIRE(n >= 1 && n < ((int64_t)1 << 31), SPHMAP_EINVAL, "n out of range [1, 2^31)");
+    SPH_REQUIRE(d_xyz && d_h && d_m, SPHMAP_EINVAL, "null particle array");
+    SPH_REQUIRE(n_src >= 1 && h_sources, SPHMAP_EINVAL, "at least one source is required");
+    SPH_REQUIRE(opts, SPHMAP_EINVAL, "null options");
+    SPH_REQUIRE(opts->leaf_max >= 1, SPHMAP_EINVAL, "leaf_max must be >= 1");
+    SPH_REQUIRE(opts->max_depth >= 1 && opts->max_depth <= 21, SPHMAP_EINVAL, "max_depth must be in [1, 21]");
+    SPH_REQUIRE(opts->theta >= 0 && opts->h_fact > 0 && opts->eps_h > 0, SPHMAP_EINVAL, "bad option value");
+    SPH_REQUIRE(d_out_xyz && d_out_h && d_out_m && n_out, SPHMAP_EINVAL, "null required output");
+    sphmap::PseudoArgs a;
+    a.n = n;
+    a.xyz = d_xyz;
+    a.h = d_h;
+    a.m = d_m;
+    a.n_src = n_src;
+    a.src = h_sources;
+    a.opts = *opts;
+    a.capacity = capacity;
+    a.o_xyz = d_out_xyz;
+    a.o_h = d_out_h;
+    a.o_m = d_out_m;
+    a.o_s = d_out_s;
+    a.o_kind = d_out_kind;
+    a.o_first = d_out_first;
+    a.o_count = d_out_count;
+    a.o_branch = d_out_branch;
+    a.n_out = 0;
+    std::memset(&a.stats, 0, sizeof a.stats);
+    sphmap::pseudo_build(ctx->c, a, as_stream(stream));
+    *n_out = a.n_out;
+    if (stats) *stats = a.stats;
+  });
+}
+
+int sphmap_set_timing(sphmap_ctx *ctx, int32_t enabled) {
+  if (!ctx) return SPHMAP_EINVAL;
+  ctx->c.timing = enabled != 0;
+  return SPHMAP_OK;
+}
+
+int sphmap_kernel_time(sphmap_ctx *ctx, const char *name, double *total_ms, int64_t *launches) {
+  if (!ctx || !name) return SPHMAP_EINVAL;
+  return guarded(ctx, [&] {
+    double tot = 0;
+    int64_t cnt = 0;
+    auto it = ctx->c.timers.find(name);
+    if (it != ctx->c.timers.end())
+      for (auto &r : it->second) {
+        SPH_HIP(hipEventSynchronize(r.stop));
+        float ms = 0;
+        SPH_HIP(hipEventElapsedTime(&ms, r.start, r.stop));
+        tot += ms;
+        ++cnt;
+      }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = cnt;
+  });
+}
+
+int sphmap_reset_timing(sphmap_ctx *ctx) {
+  if (!ctx) return SPHMAP_EINVAL;
+  return guarded(ctx, [&] {
+    for (auto &kv : ctx->c.timers)
+      for (auto &r : kv.second) {
+        SPH_HIP(hipEventSynchronize(r.stop));
+        SPH_HIP(hipEventDestroy(r.start));
+        SPH_HIP(hipEventDestroy(r.stop));
+      }
+    ctx->c.timers.clear();
+  });
+}
+
+int sphmap_set_counting(sphmap_ctx *ctx, int32_t enabled) {
+  if (!ctx) return SPHMAP_EINVAL;
+  ctx->c.counting = enabled != 0;
+  return SPHMAP_OK;
+}
+
+int sphmap_work_counters(sphmap_ctx *ctx, int64_t *out8) {
+  if (!ctx || !out8) return SPHMAP_EINVAL;
+  for (int k = 0; k < 8; ++k) out8[k] = ctx->c.counters[k];
+  return SPHMAP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,200 @@
+// Internal declarations shared by the device sources of libsphmap.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/sphmap.h"
+
+namespace sphmap {
+
+// ------------------------------------------------------------ error model
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define SPH_HIP(expr)                                                                              \
+  do {                                                                                             \
+    hipError_t e_ = (expr);                                                                        \
+    if (e_ != hipSuccess)                                                                          \
+      throw ::sphmap::Error{SPHMAP_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)};      \
+  } while (0)
+
+#define SPH_REQUIRE(cond, code, what)                                                              \
+  do {                                                                                             \
+    if (!(cond)) throw ::sphmap::Error{code, std::string(what)};                                   \
+  } while (0)
+
+#define SPH_LAUNCH_CHECK() SPH_HIP(hipGetLastError())
+
+// --------------------------------------------------------- device buffers
+struct Buffer {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+// Grow-only device allocations keyed by purpose, owned by a context or a
+// handle.  get() never shrinks; contents are not preserved on growth.
+struct Arena {
+  std::map<std::string, Buffer> bufs;
+  void *get(const std::string &name, size_t bytes);
+  template <typename T>
+  T *get(const std::string &name, size_t count) {
+    return (T *)get(name, count * sizeof(T) + 16);
+  }
+  void release();
+  ~Arena() { release(); }
+};
+
+// ----------------------------------------------------------------- timing
+struct TimerRecord {
+  hipEvent_t start, stop;
+};
+
+struct PairsDev;
+
+struct Ctx {
+  int device = 0;
+  PairsDev *scratch_pairs = nullptr;  // pair list of calls that do not keep one
+  Arena arena;
+  std::string last_error;
+  bool timing = false;
+  bool counting = false;
+  std::map<std::string, std::vector<TimerRecord>> timers;
+  int64_t counters[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t *d_counters = nullptr;  // device copy of the work counters
+  int *d_status = nullptr;        // device status word (non-finite results)
+  void *pinned = nullptr;         // small pinned host scratch
+};
+
+// RAII scope that records events around one launch when timing is on.
+struct KernelTimer {
+  Ctx *ctx;
+  const char *name;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  KernelTimer(Ctx *c, const char *n, hipStream_t st) : ctx(c), name(n), s(st) {
+    if (ctx->timing) {
+      SPH_HIP(hipEventCreate(&a));
+      SPH_HIP(hipEventCreate(&b));
+      SPH_HIP(hipEventRecord(a, s));
+    }
+  }
+  void done() {
+    if (a) {
+      SPH_HIP(hipEventRecord(b, s));
+      ctx->timers[name].push_back({a, b});
+      a = b = nullptr;
+    }
+  }
+  ~KernelTimer() {
+    if (a) {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  }
+};
+
+// ------------------------------------------------------------ tessellation
+struct TessDev {
+  int64_t n_cells = 0, n_faces = 0, n_vertices = 0, n_fv = 0;
+  int device = 0;
+  double box_lo[3] = {0, 0, 0};  // bounding cube of the vertices
+  double box_size = 1.0;
+  Arena mem;
+  // as given
+  double *gen = nullptr;          // [C][3]
+  double *vert = nullptr;         // [V][3]
+  int64_t *cell_face_off = nullptr;
+  int64_t *face_vtx_off = nullptr;
+  int32_t *face_vtx = nullptr;
+  // prepared on the device
+  int32_t *face_cell = nullptr;   // [F]
+  double4 *fplane = nullptr;      // outward unit normal, plane offset about g (<= 0: skip face)
+  double4 *fsphere = nullptr;     // centroid about g, radius
+  double *fvpos = nullptr;        // [FV][3] oriented vertex positions about g
+  float4 *fvpos32 = nullptr;      // [FV] binary32 copies (w unused)
+  float4 *fplane32 = nullptr;     // binary32 copies of fplane
+  double *volume = nullptr;       // [C]
+  float *radius = nullptr;        // [C]
+  float4 *gen32 = nullptr;        // [C] fl(g), R_c in w
+  int32_t *cell_order = nullptr;  // [C] cells in Morton order of the generators
+};
+
+// ---------------------------------------------------------------- pairs
+struct PairsDev {
+  int64_t n_pairs = 0, n_cells = 0, n_particles = 0;
+  int device = 0;
+  Arena mem;
+  int64_t *cell_off = nullptr;  // [C+1]
+  int32_t *pair_p = nullptr;    // [P]
+  int32_t *pair_c = nullptr;    // [P]
+  double *w = nullptr;          // [P]
+  int64_t *part_off = nullptr;  // [N+1]
+  int32_t *pm_cell = nullptr;   // [P] particle-major cell index
+  double *pm_w = nullptr;       // [P] particle-major weights
+  double *coverage = nullptr;   // [N]
+};
+
+// ---------------------------------------------------------- primitives
+// exclusive scan of n int64 values in place-safe (in may equal out);
+// returns nothing; the total is written to out[n] if write_total.
+void scan_exclusive_i64(Arena &ar, const int64_t *in, int64_t *out, int64_t n, bool write_total, hipStream_t s);
+// stable LSD radix sort of (key, value) pairs on the low `bits` bits.
+void radix_sort_u64(Arena &ar, uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s);
+void radix_sort_u32(Arena &ar, uint32_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s);
+// 63-bit Morton keys (21 bits per axis) of points in [lo, lo+size)^3,
+// interleaved x (bit 0), y (bit 1), z (bit 2) at each level.
+void morton_keys(const double *xyz, int stride, int64_t n, double lo0, double lo1, double lo2, double size,
+                 uint64_t *keys, int32_t *idx, hipStream_t s);
+void fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
+void iota_i32(int32_t *p, int64_t n, hipStream_t s);
+
+// ------------------------------------------------------------ launchers
+void tess_prepare(Ctx &ctx, TessDev &t, hipStream_t s);
+
+struct PartDev {
+  int64_t n;
+  const double *xyz;  // [n][3]
+  const double *h;
+  const double *m;
+  float4 *x32;        // fl(x), fl(y), fl(z), fl(h)
+};
+void particles_prepare(Ctx &ctx, PartDev &p, hipStream_t s);
+
+// candidate pairs into P (allocates P's cell_off/pair_p/pair_c)
+void find_pairs(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, hipStream_t s);
+// weights
+void exact_integral(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, int precision, hipStream_t s);
+// transpose + coverage
+void particle_major(Ctx &ctx, PairsDev &P, hipStream_t s);
+// M_c and rho_c (scale: optional per-particle mass factor 1/c_i)
+void cell_reduce(Ctx &ctx, const TessDev &t, const PartDev &p, const PairsDev &P, bool normalize, double *mass,
+                 double *rho, hipStream_t s);
+void reverse_map(Ctx &ctx, const PairsDev &P, const double *cell_values, int ncomp, double *out, hipStream_t s);
+
+struct PseudoArgs {
+  int64_t n;
+  const double *xyz, *h, *m;
+  int n_src;
+  const double *src;  // host [n_src][3]
+  sphmap_pseudo_opts opts;
+  int64_t capacity;
+  double *o_xyz, *o_h, *o_m, *o_s;
+  int32_t *o_kind;
+  int64_t *o_first, *o_count;
+  int32_t *o_branch;
+  int64_t n_out;
+  sphmap_pseudo_stats stats;
+};
+void pseudo_build(Ctx &ctx, PseudoArgs &a, hipStream_t s);
+
+inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace sphmap

@@ -1,0 +1,277 @@
+// Candidate particle-cell pairs.
+//
+// A pair (c, i) is a candidate when the canonical binary32 test holds:
+//   dx = fl(x_i) - fl(g_x) (same for y, z), d2 = (dx*dx + dy*dy) + dz*dz,
+//   s = R_c + 2 fl(h_i), candidate iff d2 < s*s
+// with R_c the canonical bounding radius of cell c.  The number of candidate
+// pairs is the method's unit of work (the paper's runtime grows with the
+// number of particle-cell pairs, Sec. 1).
+//
+// Search structure: particles sorted by Morton key, grouped 16 at a time into
+// a 16-ary hierarchy of boxes that bound the particles' 2h balls (inflated so
+// that the box test can never reject a pair the canonical test accepts).
+// Smoothing lengths span a factor ~20 in log-normal clouds, so a single
+// uniform hash grid would be either overfull in dense regions or hold each
+// large-h particle in many buckets; the Morton hierarchy is a uniform grid
+// at every level and adapts to both.  One thread per cell walks it, cells in
+// Morton order of their sites so that a wave's walks stay coherent.  A count
+// pass sizes the CSR, a fill pass writes it, and each cell's list is then
+// sorted by particle index.
+#include "common.hpp"
+
+namespace sphmap {
+namespace {
+
+constexpr int kFan = 16;        // children per hierarchy node
+constexpr int kMaxLevels = 10;  // 16^10 > 2^31 particles
+
+struct Hier {
+  int levels;                 // number of box levels (level 1 = groups of particles)
+  int64_t n[kMaxLevels + 1];  // nodes per level (n[0] = particles)
+  float4 *lo[kMaxLevels + 1];
+  float4 *hi[kMaxLevels + 1];
+  const float4 *sx;           // sorted particles: fl(x), fl(y), fl(z), fl(h)
+  const int32_t *sidx;        // sorted -> original particle index
+  float margin_abs;           // absolute slack of the box test
+};
+
+__global__ void k_gather_sorted(int64_t n, const int32_t *sidx, const float4 *x32, float4 *sx) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) sx[k] = x32[sidx[k]];
+}
+
+// level-1 boxes over groups of kFan sorted particles, each ball inflated by
+// 1e-5 relative plus an absolute slack
+__global__ void k_leaf_boxes(int64_t n, const float4 *sx, int64_t nb, float4 *lo, float4 *hi, float slack) {
+  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  float l0 = INFINITY, l1 = INFINITY, l2 = INFINITY, h0 = -INFINITY, h1 = -INFINITY, h2 = -INFINITY;
+  for (int64_t k = b * kFan; k < min(n, (b + 1) * kFan); ++k) {
+    float4 p = sx[k];
+    float r = 2.0f * p.w * 1.00001f + slack;
+    l0 = fminf(l0, p.x - r);
+    l1 = fminf(l1, p.y - r);
+    l2 = fminf(l2, p.z - r);
+    h0 = fmaxf(h0, p.x + r);
+    h1 = fmaxf(h1, p.y + r);
+    h2 = fmaxf(h2, p.z + r);
+  }
+  lo[b] = make_float4(l0 - slack, l1 - slack, l2 - slack, 0.0f);
+  hi[b] = make_float4(h0 + slack, h1 + slack, h2 + slack, 0.0f);
+}
+
+__global__ void k_up_boxes(int64_t nc, const float4 *clo, const float4 *chi, int64_t nb, float4 *lo, float4 *hi) {
+  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  float4 l = make_float4(INFINITY, INFINITY, INFINITY, 0.0f), h = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
+  for (int64_t k = b * kFan; k < min(nc, (b + 1) * kFan); ++k) {
+    float4 a = clo[k], c = chi[k];
+    l.x = fminf(l.x, a.x);
+    l.y = fminf(l.y, a.y);
+    l.z = fminf(l.z, a.z);
+    h.x = fmaxf(h.x, c.x);
+    h.y = fmaxf(h.y, c.y);
+    h.z = fmaxf(h.z, c.z);
+  }
+  lo[b] = l;
+  hi[b] = h;
+}
+
+__device__ inline bool box_hit(const float4 &lo, const float4 &hi, const float4 &g, float r2) {
+  float dx = fmaxf(fmaxf(lo.x - g.x, g.x - hi.x), 0.0f);
+  float dy = fmaxf(fmaxf(lo.y - g.y, g.y - hi.y), 0.0f);
+  float dz = fmaxf(fmaxf(lo.z - g.z, g.z - hi.z), 0.0f);
+  return dx * dx + dy * dy + dz * dz <= r2;
+}
+
+// The canonical binary32 test, evaluated without contraction.
+__device__ inline bool canon_pair(const float4 &p, const float4 &g) {
+#pragma clang fp contract(off)
+  float dx = p.x - g.x, dy = p.y - g.y, dz = p.z - g.z;
+  float d2 = (dx * dx + dy * dy) + dz * dz;
+  float s = g.w + 2.0f * p.w;
+  return d2 < s * s;
+}
+
+template <bool kFill>
+__global__ void __launch_bounds__(128) k_pairs(Hier H, int64_t C, const int32_t *cell_order, const float4 *gen32,
+                                              int64_t *counts, const int64_t *off, int32_t *pair_p,
+                                              int32_t *pair_c) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= C) return;
+  const int32_t c = cell_order[t];
+  const float4 g = gen32[c];
+  const float rr = g.w * 1.00001f + H.margin_abs;
+  const float r2 = rr * rr;
+  int64_t cnt = 0;
+  int64_t base = kFill ? off[c] : 0;
+  // explicit stack of (level, node)
+  int32_t st_node[kFan * kMaxLevels];
+  int8_t st_lvl[kFan * kMaxLevels];
+  int sp = 0;
+  const int top = H.levels;
+  for (int64_t j = H.n[top] - 1; j >= 0; --j)
+    if (box_hit(H.lo[top][j], H.hi[top][j], g, r2)) {
+      st_node[sp] = (int32_t)j;
+      st_lvl[sp] = (int8_t)top;
+      ++sp;
+    }
+  while (sp > 0) {
+    --sp;
+    const int l = st_lvl[sp];
+    const int64_t j = st_node[sp];
+    if (l == 1) {
+      const int64_t e = min(H.n[0], (j + 1) * kFan);
+      for (int64_t k = j * kFan; k < e; ++k) {
+        if (canon_pair(H.sx[k], g)) {
+          if (kFill) {
+            pair_p[base + cnt] = H.sidx[k];
+            pair_c[base + cnt] = c;
+          }
+          ++cnt;
+        }
+      }
+    } else {
+      const int lc = l - 1;
+      const int64_t e = min(H.n[lc], (j + 1) * kFan);
+      for (int64_t k = e - 1; k >= j * kFan; --k)
+        if (box_hit(H.lo[lc][k], H.hi[lc][k], g, r2)) {
+          st_node[sp] = (int32_t)k;
+          st_lvl[sp] = (int8_t)lc;
+          ++sp;
+        }
+    }
+  }
+  if (!kFill) counts[c] = cnt;
+}
+
+// Sort each cell's particle list ascending (bitonic in LDS for lists up to
+// kSortCap entries; longer lists by a single-lane heap sort).
+constexpr int kSortCap = 4096;
+
+__global__ void __launch_bounds__(256) k_sort_segments(int64_t C, const int64_t *off, int32_t *pair_p) {
+  __shared__ int32_t buf[kSortCap];
+  const int64_t c = blockIdx.x;
+  const int64_t s = off[c], e = off[c + 1];
+  const int n = (int)(e - s);
+  if (n <= 1) return;
+  if (n <= kSortCap) {
+    int m = 2;
+    while (m < n) m <<= 1;
+    for (int k = threadIdx.x; k < m; k += blockDim.x) buf[k] = k < n ? pair_p[s + k] : INT32_MAX;
+    __syncthreads();
+    for (int size = 2; size <= m; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int k = threadIdx.x; k < m; k += blockDim.x) {
+          int q = k ^ stride;
+          if (q > k) {
+            bool up = (k & size) == 0;
+            int32_t a = buf[k], b = buf[q];
+            if ((a > b) == up) {
+              buf[k] = b;
+              buf[q] = a;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int k = threadIdx.x; k < n; k += blockDim.x) pair_p[s + k] = buf[k];
+  } else if (threadIdx.x == 0) {
+    int32_t *a = pair_p + s;
+    auto sift = [&](int root, int end) {
+      while (true) {
+        int ch = 2 * root + 1;
+        if (ch >= end) break;
+        if (ch + 1 < end && a[ch] < a[ch + 1]) ++ch;
+        if (a[root] < a[ch]) {
+          int32_t t = a[root];
+          a[root] = a[ch];
+          a[ch] = t;
+          root = ch;
+        } else {
+          break;
+        }
+      }
+    };
+    for (int st = n / 2 - 1; st >= 0; --st) sift(st, n);
+    for (int end = n - 1; end > 0; --end) {
+      int32_t t = a[0];
+      a[0] = a[end];
+      a[end] = t;
+      sift(0, end);
+    }
+  }
+}
+
+}  // namespace
+
+void find_pairs(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, hipStream_t s) {
+  Arena &ar = ctx.arena;
+  const int64_t N = p.n, C = t.n_cells;
+  // Morton order of the particles in the tessellation's bounding cube
+  uint64_t *keys = ar.get<uint64_t>("pp_keys", N);
+  int32_t *sidx = ar.get<int32_t>("pp_sidx", N);
+  morton_keys(p.xyz, 3, N, t.box_lo[0], t.box_lo[1], t.box_lo[2], t.box_size, keys, sidx, s);
+  radix_sort_u64(ar, keys, sidx, N, 63, s);
+  float4 *sx = ar.get<float4>("pp_sx", N);
+  k_gather_sorted<<<(unsigned)div_up(N, 256), 256, 0, s>>>(N, sidx, p.x32, sx);
+  SPH_LAUNCH_CHECK();
+  Hier H;
+  H.sx = sx;
+  H.sidx = sidx;
+  H.n[0] = N;
+  H.lo[0] = H.hi[0] = nullptr;
+  const float slack = (float)(1e-6 * t.box_size);
+  H.margin_abs = 2.0f * slack;
+  int l = 0;
+  int64_t cnt = N;
+  do {
+    ++l;
+    SPH_REQUIRE(l <= kMaxLevels, SPHMAP_EINVAL, "too many particles for the search hierarchy");
+    int64_t nb = div_up(cnt, kFan);
+    H.n[l] = nb;
+    H.lo[l] = ar.get<float4>("pp_lo" + std::to_string(l), nb);
+    H.hi[l] = ar.get<float4>("pp_hi" + std::to_string(l), nb);
+    if (l == 1)
+      k_leaf_boxes<<<(unsigned)div_up(nb, 256), 256, 0, s>>>(N, sx, nb, H.lo[1], H.hi[1], slack);
+    else
+      k_up_boxes<<<(unsigned)div_up(nb, 256), 256, 0, s>>>(cnt, H.lo[l - 1], H.hi[l - 1], nb, H.lo[l], H.hi[l]);
+    SPH_LAUNCH_CHECK();
+    cnt = nb;
+  } while (cnt > kFan);
+  H.levels = l;
+
+  P.n_cells = C;
+  P.n_particles = N;
+  int64_t *counts = ar.get<int64_t>("pp_counts", C + 1);
+  P.cell_off = P.mem.get<int64_t>("cell_off", C + 1);
+  {
+    KernelTimer kt(&ctx, "pair_count", s);
+    k_pairs<false><<<(unsigned)div_up(C, 128), 128, 0, s>>>(H, C, t.cell_order, t.gen32, counts, nullptr, nullptr,
+                                                             nullptr);
+    SPH_LAUNCH_CHECK();
+    kt.done();
+  }
+  scan_exclusive_i64(ar, counts, P.cell_off, C, true, s);
+  int64_t total = 0;
+  SPH_HIP(hipMemcpyAsync(&total, P.cell_off + C, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  SPH_HIP(hipStreamSynchronize(s));
+  SPH_REQUIRE(total < ((int64_t)1 << 31), SPHMAP_EINVAL, "more than 2^31 candidate pairs");
+  P.n_pairs = total;
+  P.pair_p = P.mem.get<int32_t>("pair_p", total);
+  P.pair_c = P.mem.get<int32_t>("pair_c", total);
+  {
+    KernelTimer kt(&ctx, "pair_fill", s);
+    k_pairs<true><<<(unsigned)div_up(C, 128), 128, 0, s>>>(H, C, t.cell_order, t.gen32, nullptr, P.cell_off,
+                                                            P.pair_p, P.pair_c);
+    SPH_LAUNCH_CHECK();
+    kt.done();
+  }
+  if (C > 0) {
+    k_sort_segments<<<(unsigned)C, 256, 0, s>>>(C, P.cell_off, P.pair_p);
+    SPH_LAUNCH_CHECK();
+  }
+}
+
+}  // namespace sphmap

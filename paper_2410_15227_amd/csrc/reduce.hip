@@ -1,0 +1,177 @@
+// Accumulations over the pair list.
+//
+//  cell_reduce     M_c = sum_i m_i w_ic (forward mapping, Sec. 2.3) over the
+//                  cell's pairs, rho_c = M_c / V_c.  One wave per cell; lanes
+//                  take the cell's pairs in stride and a fixed butterfly
+//                  combines them, so the result does not depend on the launch.
+//  particle_major  the pair list re-ordered by particle (stable radix sort of
+//                  the particle index, so each particle's cells stay in
+//                  ascending cell order) with c_i = sum_c w_ic.
+//  reverse_map     q_i = sum_c w_ic q_c / c_i (inverse mapping, Sec. 2.3).
+#include "common.hpp"
+
+namespace sphmap {
+namespace {
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ void __launch_bounds__(256) k_cell_mass(int64_t C, const int64_t *off, const int32_t *pair_p,
+                                                  const double *w, const double *m, const double *cov,
+                                                  const double *vol, double *mass, double *rho) {
+  const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (c >= C) return;
+  const int64_t s = off[c], e = off[c + 1];
+  double acc = 0.0;
+  for (int64_t k = s + lane; k < e; k += 64) {
+    const int32_t i = pair_p[k];
+    double mi = m[i];
+    if (cov) mi = cov[i] > 0.0 ? mi / cov[i] : 0.0;
+    acc += mi * w[k];
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    mass[c] = acc;
+    if (rho) rho[c] = acc / vol[c];
+  }
+}
+
+__global__ void k_count_particles(int64_t P, const int32_t *pair_p, unsigned long long *cnt) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < P) atomicAdd(&cnt[pair_p[k]], 1ull);
+}
+
+__global__ void k_copy_u32(int64_t P, const int32_t *src, uint32_t *dst) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < P) dst[k] = (uint32_t)src[k];
+}
+
+// one wave per particle: gather its pairs in ascending cell order
+__global__ void __launch_bounds__(256) k_coverage(int64_t N, const int64_t *poff, const int32_t *perm,
+                                                 const int32_t *pair_c, const double *w, int32_t *pm_cell,
+                                                 double *pm_w, double *cov) {
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (i >= N) return;
+  const int64_t s = poff[i], e = poff[i + 1];
+  double acc = 0.0;
+  for (int64_t j = s + lane; j < e; j += 64) {
+    const int32_t k = perm[j];
+    const double wk = w[k];
+    pm_cell[j] = pair_c[k];
+    pm_w[j] = wk;
+    acc += wk;
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) cov[i] = acc;
+}
+
+template <int kComp>
+__global__ void __launch_bounds__(256) k_reverse(int64_t N, int ncomp, const int64_t *poff, const int32_t *pm_cell,
+                                                const double *pm_w, const double *cov, const double *q,
+                                                double *out) {
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const int lane = threadIdx.x & 15;  // 16 lanes per particle
+  if (i >= N) return;
+  const int nc = kComp > 0 ? kComp : ncomp;
+  const int64_t s = poff[i], e = poff[i + 1];
+  double acc[kComp > 0 ? kComp : 1];
+  for (int j = 0; j < (kComp > 0 ? kComp : 1); ++j) acc[j] = 0.0;
+  if (kComp > 0) {
+    for (int64_t j = s + lane; j < e; j += 16) {
+      const double wj = pm_w[j];
+      const int64_t c = pm_cell[j];
+#pragma unroll
+      for (int r = 0; r < kComp; ++r) acc[r] += wj * q[c * kComp + r];
+    }
+#pragma unroll
+    for (int r = 0; r < kComp; ++r) {
+      double v = acc[r];
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+      acc[r] = v;
+    }
+    if (lane == 0) {
+      const double ci = cov[i];
+      for (int r = 0; r < kComp; ++r) out[i * kComp + r] = ci > 0.0 ? acc[r] / ci : 0.0;
+    }
+  } else {
+    const double ci = cov[i];
+    for (int r = 0; r < nc; ++r) {
+      double v = 0.0;
+      for (int64_t j = s + lane; j < e; j += 16) v += pm_w[j] * q[(int64_t)pm_cell[j] * nc + r];
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+      if (lane == 0) out[i * nc + r] = ci > 0.0 ? v / ci : 0.0;
+    }
+  }
+}
+
+}  // namespace
+
+void cell_reduce(Ctx &ctx, const TessDev &t, const PartDev &p, const PairsDev &P, bool normalize, double *mass,
+                 double *rho, hipStream_t s) {
+  const int64_t C = t.n_cells;
+  if (C == 0) return;
+  KernelTimer kt(&ctx, "cell_reduce", s);
+  k_cell_mass<<<(unsigned)div_up(C * 64, 256), 256, 0, s>>>(C, P.cell_off, P.pair_p, P.w, p.m,
+                                                            normalize ? P.coverage : nullptr, t.volume, mass, rho);
+  SPH_LAUNCH_CHECK();
+  kt.done();
+}
+
+void particle_major(Ctx &ctx, PairsDev &P, hipStream_t s) {
+  Arena &ar = ctx.arena;
+  const int64_t N = P.n_particles, NP = P.n_pairs;
+  P.part_off = P.mem.get<int64_t>("part_off", N + 1);
+  P.pm_cell = P.mem.get<int32_t>("pm_cell", NP);
+  P.pm_w = P.mem.get<double>("pm_w", NP);
+  P.coverage = P.mem.get<double>("coverage", N);
+  KernelTimer kt(&ctx, "transpose", s);
+  unsigned long long *cnt = ar.get<unsigned long long>("pm_cnt", N + 1);
+  SPH_HIP(hipMemsetAsync(cnt, 0, (N + 1) * sizeof(unsigned long long), s));
+  if (NP > 0) {
+    k_count_particles<<<(unsigned)div_up(NP, 256), 256, 0, s>>>(NP, P.pair_p, cnt);
+    SPH_LAUNCH_CHECK();
+  }
+  scan_exclusive_i64(ar, (const int64_t *)cnt, P.part_off, N, true, s);
+  if (NP > 0) {
+    uint32_t *keys = ar.get<uint32_t>("pm_keys", NP);
+    int32_t *perm = ar.get<int32_t>("pm_perm", NP);
+    k_copy_u32<<<(unsigned)div_up(NP, 256), 256, 0, s>>>(NP, P.pair_p, keys);
+    SPH_LAUNCH_CHECK();
+    iota_i32(perm, NP, s);
+    int bits = 1;
+    while (bits < 32 && ((int64_t)1 << bits) < N) ++bits;
+    radix_sort_u32(ar, keys, perm, NP, bits, s);
+    k_coverage<<<(unsigned)div_up(N * 64, 256), 256, 0, s>>>(N, P.part_off, perm, P.pair_c, P.w, P.pm_cell, P.pm_w,
+                                                             P.coverage);
+    SPH_LAUNCH_CHECK();
+  } else {
+    SPH_HIP(hipMemsetAsync(P.coverage, 0, N * sizeof(double), s));
+  }
+  kt.done();
+}
+
+void reverse_map(Ctx &ctx, const PairsDev &P, const double *q, int ncomp, double *out, hipStream_t s) {
+  const int64_t N = P.n_particles;
+  if (N == 0) return;
+  KernelTimer kt(&ctx, "reverse", s);
+  const unsigned grid = (unsigned)div_up(N * 16, 256);
+  if (ncomp == 1)
+    k_reverse<1><<<grid, 256, 0, s>>>(N, 1, P.part_off, P.pm_cell, P.pm_w, P.coverage, q, out);
+  else if (ncomp == 2)
+    k_reverse<2><<<grid, 256, 0, s>>>(N, 2, P.part_off, P.pm_cell, P.pm_w, P.coverage, q, out);
+  else if (ncomp == 4)
+    k_reverse<4><<<grid, 256, 0, s>>>(N, 4, P.part_off, P.pm_cell, P.pm_w, P.coverage, q, out);
+  else
+    k_reverse<0><<<grid, 256, 0, s>>>(N, ncomp, P.part_off, P.pm_cell, P.pm_w, P.coverage, q, out);
+  SPH_LAUNCH_CHECK();
+  kt.done();
+}
+
+}  // namespace sphmap

@@ -1,0 +1,192 @@
+// Tessellation preprocessing (once per uploaded tessellation) and particle
+// staging.
+//
+// Per face: the Newell area vector gives the plane; the face is oriented so
+// that its normal points away from the cell's generation site (the site is
+// strictly inside its Voronoi cell), its vertices are rewritten about the
+// site in that orientation (counter-clockwise seen from outside), and a
+// bounding sphere about the vertex centroid is kept for culling.  Per cell:
+// the volume (sum of pyramids from the site) and the canonical binary32
+// bounding radius used by the candidate-pair test.
+#include "common.hpp"
+
+namespace sphmap {
+namespace {
+
+__global__ void k_face_cell(const int64_t *cfo, int64_t C, int32_t *face_cell) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  for (int64_t f = cfo[c]; f < cfo[c + 1]; ++f) face_cell[f] = (int32_t)c;
+}
+
+__global__ void k_face_prep(int64_t F, const int32_t *face_cell, const double *gen, const double *vert,
+                            const int64_t *fvo, const int32_t *fv, double4 *fplane, double4 *fsphere,
+                            double *fvpos, float4 *fvpos32, float4 *fplane32, int *bad) {
+  int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  const int64_t c = face_cell[f];
+  const double gx = gen[3 * c], gy = gen[3 * c + 1], gz = gen[3 * c + 2];
+  const int64_t s = fvo[f], e = fvo[f + 1];
+  const int nv = (int)(e - s);
+  double cx = 0, cy = 0, cz = 0;
+  for (int64_t k = s; k < e; ++k) {
+    const double *v = vert + 3 * (int64_t)fv[k];
+    cx += v[0] - gx;
+    cy += v[1] - gy;
+    cz += v[2] - gz;
+  }
+  if (nv > 0) {
+    cx /= nv;
+    cy /= nv;
+    cz /= nv;
+  }
+  double ax = 0, ay = 0, az = 0, rad2 = 0;
+  for (int k = 0; k < nv; ++k) {
+    const double *v = vert + 3 * (int64_t)fv[s + k];
+    const double *w = vert + 3 * (int64_t)fv[s + (k + 1) % nv];
+    double px = v[0] - gx - cx, py = v[1] - gy - cy, pz = v[2] - gz - cz;
+    double qx = w[0] - gx - cx, qy = w[1] - gy - cy, qz = w[2] - gz - cz;
+    ax += 0.5 * (py * qz - pz * qy);
+    ay += 0.5 * (pz * qx - px * qz);
+    az += 0.5 * (px * qy - py * qx);
+    rad2 = fmax(rad2, px * px + py * py + pz * pz);
+  }
+  double an = sqrt(ax * ax + ay * ay + az * az);
+  double nx = 0, ny = 0, nz = 0, off = -1.0;
+  bool rev = false;
+  if (nv >= 3 && an > 0.0) {
+    nx = ax / an;
+    ny = ay / an;
+    nz = az / an;
+    off = nx * cx + ny * cy + nz * cz;
+    if (off < 0.0) {
+      rev = true;
+      nx = -nx;
+      ny = -ny;
+      nz = -nz;
+      off = -off;
+    }
+    if (!(off > 0.0)) {
+      atomicAdd(bad, 1);  // generation site on the face plane: not a valid cell
+      off = -1.0;
+    }
+  }
+  fplane[f] = make_double4(nx, ny, nz, off);
+  fplane32[f] = make_float4((float)nx, (float)ny, (float)nz, (float)off);
+  fsphere[f] = make_double4(cx, cy, cz, sqrt(rad2));
+  for (int k = 0; k < nv; ++k) {
+    int src = rev ? (nv - 1 - k) : k;
+    const double *v = vert + 3 * (int64_t)fv[s + src];
+    double px = v[0] - gx, py = v[1] - gy, pz = v[2] - gz;
+    fvpos[3 * (s + k) + 0] = px;
+    fvpos[3 * (s + k) + 1] = py;
+    fvpos[3 * (s + k) + 2] = pz;
+    fvpos32[s + k] = make_float4((float)px, (float)py, (float)pz, 0.0f);
+  }
+}
+
+// Canonical radius: smallest binary32 R with R*R >= max_v |v - g|^2 where
+// the squared distance is (dx*dx + dy*dy) + dz*dz in binary64 without
+// contraction.
+__device__ float canonical_radius(double r2) {
+  float R = (float)sqrt(r2);
+  while ((double)R * (double)R < r2) R = nextafterf(R, INFINITY);
+  while (R > 0.0f) {
+    float Rm = nextafterf(R, 0.0f);
+    if ((double)Rm * (double)Rm >= r2) R = Rm;
+    else break;
+  }
+  return R;
+}
+
+__global__ void k_cell_prep(int64_t C, const double *gen, const double *vert, const int64_t *cfo, const int64_t *fvo,
+                            const int32_t *fv, const double4 *fplane, const double4 *fsphere, double *volume,
+                            float *radius, float4 *gen32) {
+#pragma clang fp contract(off)
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const double gx = gen[3 * c], gy = gen[3 * c + 1], gz = gen[3 * c + 2];
+  double r2 = 0.0, vol = 0.0;
+  for (int64_t f = cfo[c]; f < cfo[c + 1]; ++f) {
+    for (int64_t k = fvo[f]; k < fvo[f + 1]; ++k) {
+      const double *v = vert + 3 * (int64_t)fv[k];
+      double dx = v[0] - gx, dy = v[1] - gy, dz = v[2] - gz;
+      double s = (dx * dx + dy * dy) + dz * dz;
+      if (s > r2) r2 = s;
+    }
+  }
+  // volume: pyramids from the site, height = plane offset, base = face area
+  for (int64_t f = cfo[c]; f < cfo[c + 1]; ++f) {
+    double4 pl = fplane[f];
+    if (!(pl.w > 0.0)) continue;
+    const int64_t s = fvo[f], e = fvo[f + 1];
+    const int nv = (int)(e - s);
+    double4 sp = fsphere[f];
+    double ax = 0, ay = 0, az = 0;
+    for (int k = 0; k < nv; ++k) {
+      const double *v = vert + 3 * (int64_t)fv[s + k];
+      const double *w = vert + 3 * (int64_t)fv[s + (k + 1) % nv];
+      double px = v[0] - gx - sp.x, py = v[1] - gy - sp.y, pz = v[2] - gz - sp.z;
+      double qx = w[0] - gx - sp.x, qy = w[1] - gy - sp.y, qz = w[2] - gz - sp.z;
+      ax += 0.5 * (py * qz - pz * qy);
+      ay += 0.5 * (pz * qx - px * qz);
+      az += 0.5 * (px * qy - py * qx);
+    }
+    vol += pl.w * sqrt(ax * ax + ay * ay + az * az) / 3.0;
+  }
+  volume[c] = vol;
+  float R = canonical_radius(r2);
+  radius[c] = R;
+  gen32[c] = make_float4((float)gx, (float)gy, (float)gz, R);
+}
+
+__global__ void k_particles_prep(int64_t n, const double *xyz, const double *h, float4 *x32) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  x32[i] = make_float4((float)xyz[3 * i], (float)xyz[3 * i + 1], (float)xyz[3 * i + 2], (float)h[i]);
+}
+
+}  // namespace
+
+void tess_prepare(Ctx &ctx, TessDev &t, hipStream_t s) {
+  const int64_t C = t.n_cells, F = t.n_faces, FV = t.n_fv;
+  t.face_cell = t.mem.get<int32_t>("face_cell", F);
+  t.fplane = t.mem.get<double4>("fplane", F);
+  t.fsphere = t.mem.get<double4>("fsphere", F);
+  t.fplane32 = t.mem.get<float4>("fplane32", F);
+  t.fvpos = t.mem.get<double>("fvpos", 3 * FV);
+  t.fvpos32 = t.mem.get<float4>("fvpos32", FV);
+  t.volume = t.mem.get<double>("volume", C);
+  t.radius = t.mem.get<float>("radius", C);
+  t.gen32 = t.mem.get<float4>("gen32", C);
+  t.cell_order = t.mem.get<int32_t>("cell_order", C);
+  int *bad = t.mem.get<int>("bad", 1);
+  SPH_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
+  k_face_cell<<<(unsigned)div_up(C, 256), 256, 0, s>>>(t.cell_face_off, C, t.face_cell);
+  SPH_LAUNCH_CHECK();
+  if (F > 0) {
+    k_face_prep<<<(unsigned)div_up(F, 256), 256, 0, s>>>(F, t.face_cell, t.gen, t.vert, t.face_vtx_off, t.face_vtx,
+                                                         t.fplane, t.fsphere, t.fvpos, t.fvpos32, t.fplane32, bad);
+    SPH_LAUNCH_CHECK();
+  }
+  k_cell_prep<<<(unsigned)div_up(C, 256), 256, 0, s>>>(C, t.gen, t.vert, t.cell_face_off, t.face_vtx_off,
+                                                       t.face_vtx, t.fplane, t.fsphere, t.volume, t.radius, t.gen32);
+  SPH_LAUNCH_CHECK();
+  // cells in Morton order of their sites (locality of the pair search)
+  uint64_t *keys = t.mem.get<uint64_t>("cell_keys", C);
+  morton_keys(t.gen, 3, C, t.box_lo[0], t.box_lo[1], t.box_lo[2], t.box_size, keys, t.cell_order, s);
+  radix_sort_u64(ctx.arena, keys, t.cell_order, C, 63, s);
+  int bad_h = 0;
+  SPH_HIP(hipMemcpyAsync(&bad_h, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  SPH_HIP(hipStreamSynchronize(s));
+  SPH_REQUIRE(bad_h == 0, SPHMAP_EGEOM,
+              std::to_string(bad_h) + " face(s) have the generation site on their plane (site not strictly inside)");
+}
+
+void particles_prepare(Ctx &ctx, PartDev &p, hipStream_t s) {
+  (void)ctx;
+  k_particles_prep<<<(unsigned)div_up(p.n, 256), 256, 0, s>>>(p.n, p.xyz, p.h, p.x32);
+  SPH_LAUNCH_CHECK();
+}
+
+}  // namespace sphmap

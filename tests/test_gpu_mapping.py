@@ -1,0 +1,186 @@
+"""Parity of the HIP forward and inverse mapping with the FP64 oracle.
+
+Bars: candidate-pair lists bit-exact; FP64 path weights within 1e-12
+absolute and cell masses within 1e-10 relative; mixed path cell masses
+within 1e-5 relative (max over cells with M_c > 0)."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2410_15227_amd as pkg
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pkg.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def c1(workloads):
+    return workloads.uniform_4096(seed=1)
+
+
+@pytest.fixture(scope="module")
+def c1_oracle(oracle, c1):
+    say("oracle: full pair list and weights of uniform_4096")
+    off, idx, w = oracle.pairs_weights(c1.tess, c1.pos, c1.h)
+    M = np.add.reduceat(c1.m[idx] * w, off[:-1]) if len(idx) else np.zeros(c1.tess.n_cells)
+    vol, rad = oracle.cell_info(c1.tess)
+    return off, idx, w, M, vol, rad
+
+
+def run_map(pkg, ctx, wl, precision, keep=True):
+    dt = pkg.DeviceTessellation(ctx, wl.tess)
+    res = pkg.map_particles_to_cells(ctx, dt, wl.pos, wl.h, wl.m, precision=precision, keep_pairs=keep)
+    torch.cuda.synchronize()
+    return dt, res
+
+
+def test_cell_info_matches(ctx, c1, c1_oracle):
+    import paper_2410_15227_amd as pkg
+    say("case: uniform_4096 cell info")
+    off, idx, w, M, vol, rad = c1_oracle
+    dt = pkg.DeviceTessellation(ctx, c1.tess)
+    gv, gr = dt.cell_info()
+    gv, gr = gv.cpu().numpy(), gr.cpu().numpy()
+    assert np.array_equal(gr, rad)                       # canonical radius bit-exact
+    assert np.max(np.abs(gv - vol) / vol) < 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_uniform_4096_full(ctx, c1, c1_oracle, precision):
+    import paper_2410_15227_amd as pkg
+    say(f"case: uniform_4096 full parity, precision={precision}")
+    off, idx, w, M, vol, rad = c1_oracle
+    dt, res = run_map(pkg, ctx, c1, precision)
+    goff, gidx, gw = (t.cpu().numpy() for t in res.pairs.export())
+    torch.cuda.synchronize()
+    assert np.array_equal(goff, off)                     # bit-exact CSR
+    assert np.array_equal(gidx, idx)
+    gm = res.mass.cpu().numpy()
+    rel = np.abs(gm - M) / M
+    if precision == "fp64":
+        assert np.max(np.abs(gw - w)) < 1e-12
+        assert np.max(rel) < 1e-10
+    else:
+        assert np.max(np.abs(gw - w)) < 1e-5
+        assert np.max(rel) < 1e-5
+    # exact limits: zero-overlap pairs are exactly 0 on the device
+    assert np.all(gw[w == 0.0] == 0.0)
+    np.testing.assert_allclose(res.density.cpu().numpy(), gm / vol, rtol=1e-12)
+    # coverage: sum over the particle's cells of the oracle weights
+    cov_ref = np.bincount(idx, weights=w, minlength=len(c1.pos))
+    assert np.max(np.abs(res.coverage.cpu().numpy() - cov_ref)) < (1e-11 if precision == "fp64" else 1e-5)
+
+
+def test_reverse_map(ctx, c1, c1_oracle, oracle):
+    import paper_2410_15227_amd as pkg
+    say("case: uniform_4096 inverse mapping")
+    off, idx, w, M, vol, rad = c1_oracle
+    dt, res = run_map(pkg, ctx, c1, "fp64")
+    g = c1.tess.generators
+    q = np.stack([np.sin(9 * g[:, 0]) * np.cos(5 * g[:, 1]), g[:, 2] ** 2], axis=1)
+    out = pkg.map_cells_to_particles(ctx, res.pairs, q).cpu().numpy()
+    parts = np.arange(0, len(c1.pos), 97)
+    cov, qref = oracle.particles(c1.tess, c1.pos, c1.h, parts, q)
+    assert np.max(np.abs(out[parts] - qref)) < 1e-11
+    # a constant field comes back unchanged
+    one = pkg.map_cells_to_particles(ctx, res.pairs, np.full(c1.tess.n_cells, 2.5)).cpu().numpy()
+    assert np.max(np.abs(one - 2.5)) < 1e-12
+    # sum_i m_i c_i q_i = sum_c M_c q_c
+    single = pkg.map_cells_to_particles(ctx, res.pairs, q[:, 0]).cpu().numpy()
+    lhs = np.dot(c1.m * res.coverage.cpu().numpy(), single)
+    assert abs(lhs - np.dot(res.mass.cpu().numpy(), q[:, 0])) < 1e-12
+
+
+def lattice(n):
+    from paper_2410_15227_amd.workloads import box_cells, tess_from_cells
+    a = 1.0 / n
+    gens, cells = [], []
+    for i in range(n):
+        for j in range(n):
+            for k in range(n):
+                lo = np.array([i, j, k]) * a
+                gens.append(lo + 0.5 * a)
+                cells.append(box_cells(lo, lo + a))
+    return tess_from_cells(np.array(gens), cells)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_lattice_special_positions(ctx, oracle, precision):
+    """Cubic cells with particles on faces, edges, corners, cell centres and
+    generic points; h from tiny (exact 0/1) to several cells."""
+    import paper_2410_15227_amd as pkg
+    say(f"case: lattice special positions, precision={precision}")
+    t = lattice(6)
+    a = 1.0 / 6
+    g = np.random.default_rng(4)
+    pts = [[0.5, 0.5, 0.5], [2 * a, 0.5, 0.5], [2 * a, 3 * a, 0.5], [2 * a, 3 * a, 4 * a], [a * 2.5, a * 2.5, a * 2.5],
+           [0.31, 0.47, 0.62], [1e-9, 0.5, 0.5], [0.0, 0.0, 0.0]]
+    pts += list(g.random((24, 3)))
+    pts = np.array(pts)
+    hs = np.concatenate([np.full(8, 0.9 * a), g.uniform(0.01 * a, 3 * a, 24)])
+    hs[2] = 1e-4
+    hs[3] = 2.5 * a
+    m = g.uniform(0.5, 2.0, len(pts))
+    wl = type("W", (), dict(tess=t, pos=pts, h=hs, m=m))
+    dt, res = run_map(pkg, ctx, wl, precision)
+    goff, gidx, gw = (x.cpu().numpy() for x in res.pairs.export())
+    off, idx, w = oracle.pairs_weights(t, pts, hs)
+    assert np.array_equal(goff, off) and np.array_equal(gidx, idx)
+    tol = 1e-12 if precision == "fp64" else 2e-6
+    assert np.max(np.abs(gw - w)) < tol
+    cov = res.coverage.cpu().numpy()
+    inner = np.all((pts - 2 * hs[:, None] > 0) & (pts + 2 * hs[:, None] < 1), axis=1)
+    assert np.max(np.abs(cov[inner] - 1.0)) < (1e-12 if precision == "fp64" else 2e-6)
+
+
+@pytest.fixture(scope="module")
+def c2(workloads):
+    say("building turbulent_262144 inputs")
+    return workloads.turbulent(262144, seed=2)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_turbulent_262144_sampled(ctx, c2, oracle, precision):
+    import paper_2410_15227_amd as pkg
+    say(f"case: turbulent_262144 sampled cells, precision={precision}")
+    dt, res = run_map(pkg, ctx, c2, precision)
+    goff, gidx, gw = (x.cpu().numpy() for x in res.pairs.export())
+    gm = res.mass.cpu().numpy()
+    g = np.random.default_rng(12)
+    cells = np.sort(g.choice(c2.tess.n_cells, 160, replace=False))
+    # plus the cells with the most pairs and the smallest / largest volumes
+    npairs = np.diff(goff)
+    vol = dt.cell_info()[0].cpu().numpy()
+    extra = np.concatenate([np.argsort(npairs)[-20:], np.argsort(vol)[:10], np.argsort(vol)[-10:]])
+    cells = np.unique(np.concatenate([cells, extra]))
+    off, idx, w = oracle.pairs_weights(c2.tess, c2.pos, c2.h, cells)
+    Mref = np.add.reduceat(c2.m[idx] * w, off[:-1])
+    for k, c in enumerate(cells):
+        assert np.array_equal(gidx[goff[c]:goff[c + 1]], idx[off[k]:off[k + 1]]), c
+    gws = np.concatenate([gw[goff[c]:goff[c + 1]] for c in cells])
+    rel = np.abs(gm[cells] - Mref) / Mref
+    if precision == "fp64":
+        assert np.max(np.abs(gws - w)) < 1e-12
+        assert np.max(rel) < 1e-10
+    else:
+        assert np.max(rel) < 1e-5
+    say(f"  pairs={int(goff[-1])} max_rel={np.max(rel):.3e}")
+    # whole-grid properties: mass is lost only through the walls
+    tot = gm.sum()
+    assert 0.95 < tot <= 1.0 + 1e-9
+    assert abs(tot - np.dot(c2.m, res.coverage.cpu().numpy())) < 1e-9
