@@ -106,11 +106,15 @@ typedef struct {
   double ad, p2, d2;
 } edge_t;
 
-/* integrand Psi_d(U(phi)) of one right-triangle fan */
-static double fan_integrand(const edge_t *e, double phi) {
-  double c = cos(phi);
-  double U = sqrt(e->d2 + e->p2 / (c * c));
-  return ora_Psi(e->ad, U);
+/* Integrand of one right-triangle fan written in the coordinate tau along
+   the edge (tau = |p| tan phi, dphi = |p| dtau / (p^2 + tau^2)):
+   Psi_d(U) |p| / (p^2 + tau^2) with U = sqrt(d^2 + p^2 + tau^2).  In tau the
+   integrand stays smooth when the foot point nears the edge line (p -> 0),
+   where the same integral in phi narrows to a spike next to +-pi/2. */
+static double fan_integrand(const edge_t *e, double tau) {
+  double r2 = e->p2 + tau * tau;
+  double U = sqrt(e->d2 + r2);
+  return ora_Psi(e->ad, U) * sqrt(e->p2) / r2;
 }
 
 static double gk15(const edge_t *e, double a, double b, double *err) {
@@ -135,9 +139,10 @@ static double adapt(const edge_t *e, double a, double b, double tol, int depth) 
   return adapt(e, a, m, 0.5 * tol, depth + 1) + adapt(e, m, b, 0.5 * tol, depth + 1);
 }
 
-/* int_{pa}^{pb} Psi_d(U(phi)) dphi with breakpoints at phi = 0 and where
-   U = 1 or U = 2. */
-static double fan_integral(double ad, double p, double pa, double pb) {
+/* int_{tA}^{tB} Psi_d(U) |p| dtau / (p^2 + tau^2), i.e. the fan integral
+   int Psi_d(U(phi)) dphi over the same triangle, with breakpoints at tau = 0
+   and where U = 1 or U = 2. */
+static double fan_integral_tau(double ad, double p, double pa, double pb) {
   edge_t e = {ad, p * p, ad * ad};
   double bp[8];
   int nb = 0;
@@ -146,11 +151,11 @@ static double fan_integral(double ad, double p, double pa, double pb) {
   int nc = 0;
   cand[nc++] = 0.0;
   for (int k = 1; k <= 2; ++k) {
-    double r2 = (double)(k * k) - e.d2; /* p^2 sec^2 = k^2 - d^2 */
-    if (r2 > e.p2) {
-      double ph = acos(fabs(p) / sqrt(r2));
-      cand[nc++] = ph;
-      cand[nc++] = -ph;
+    double r2 = (double)(k * k) - e.d2 - e.p2; /* tau^2 = k^2 - d^2 - p^2 */
+    if (r2 > 0.0) {
+      double t = sqrt(r2);
+      cand[nc++] = t;
+      cand[nc++] = -t;
     }
   }
   /* sort candidates ascending */
@@ -226,8 +231,7 @@ static double face_term(const double *x, double h, int nv, const double *const *
     v_sub(A, P0, ta);
     v_sub(B, P0, pb);
     double tA = v_dot(ta, e) / h, tB = v_dot(pb, e) / h;
-    double phA = atan2(tA, fabs(p)), phB = atan2(tB, fabs(p));
-    double s = fan_integral(ad, p, phA, phB);
+    double s = fan_integral_tau(ad, p, tA, tB);
     sum += (p > 0 ? 1.0 : -1.0) * s;
   }
   return (d > 0 ? 1.0 : -1.0) * sum / (4.0 * M_PI);
@@ -479,7 +483,9 @@ double ora_weight_poly(const double *x, double h, int nf, const int *fsz, const 
 
 /* Angular fan integral, exposed for unit tests:
    int_{pa}^{pb} Psi_{ad}(sqrt(ad^2 + p^2 sec^2 phi)) dphi. */
-double ora_fan_integral(double ad, double p, double pa, double pb) { return fan_integral(ad, p, pa, pb); }
+double ora_fan_integral(double ad, double p, double pa, double pb) {
+  return fan_integral_tau(ad, p, fabs(p) * tan(pa), fabs(p) * tan(pb));
+}
 
 /* ================================================= pseudo-particle builder */
 /*

@@ -62,6 +62,26 @@ def test_cube_by_cubature(oracle):
         assert abs(got - ref) < 5e-8, (a, got, ref)
 
 
+def test_continuity_near_degenerate_positions(oracle):
+    """w is an integral of a bounded kernel over a fixed cell, hence smooth in
+    the particle position: approaching a face plane whose foot point sits on a
+    face corner (edges with p -> 0), w(delta) must follow its tangent line."""
+    a, h = 1.0 / 6.0, 0.15
+    faces = box([0, 0.5, 0.5], [a, 0.5 + a, 0.5 + a])
+    w0 = oracle.weight_poly([0.0, 0.5, 0.5], h, faces)
+    slope = (oracle.weight_poly([2e-6, 0.5, 0.5], h, faces) - oracle.weight_poly([1e-6, 0.5, 0.5], h, faces)) / 1e-6
+    for dl in [1e-13, 1e-11, 1e-9, 1e-8, 1e-7]:
+        got = oracle.weight_poly([dl, 0.5, 0.5], h, faces)
+        assert abs(got - (w0 + slope * dl)) < 1e-13 + 1e-5 * dl, (dl, got - w0 - slope * dl)
+    # the same along an edge line of a generic cell face: x slides onto the
+    # plane that contains an edge and is normal to its face
+    for dl in [1e-12, 1e-9]:
+        g1 = oracle.weight_poly([0.05, 0.5 + dl, 0.6], h, faces)
+        g0 = oracle.weight_poly([0.05, 0.5, 0.6], h, faces)
+        gs = oracle.weight_poly([0.05, 0.5 + 1e-6, 0.6], h, faces)
+        assert abs(g1 - (g0 + (gs - g0) * dl / 1e-6)) < 1e-13 + 1e-5 * dl
+
+
 def test_symmetry_and_limits(oracle):
     x0 = [0.0, 0.0, 0.0]
     assert abs(oracle.weight_poly(x0, 1.0, box([-9, -9, 0], [0, 9, 9])) - 0.25) < 1e-12   # edge
