@@ -48,6 +48,7 @@ def main():
     ap.add_argument("--n", type=int, default=262144)
     ap.add_argument("--cpu-sample", type=int, default=800, help="cells of the oracle CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--fp64-steps", type=int, default=3, help="timed steps of the plain binary64 path")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -125,6 +126,30 @@ def main():
                 "kernel": "exact_integral", "kernel_ms": round(k_ms / max(k_n, 1), 4),
                 "flop_per_pair": round(flop_per_pair, 1)}
 
+    # the plain binary64 path on the same GPU and inputs, for comparison
+    fp64 = None
+    if args.precision == "mixed" and args.fp64_steps > 0:
+        mass_mixed = mass.clone()
+        for _ in range(1):
+            pkg.map_particles_to_cells(ctx, dt, xyz, h, m, precision="fp64", out_mass=mass, out_density=dens,
+                                       out_coverage=cov)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.fp64_steps):
+            r = pkg.map_particles_to_cells(ctx, dt, xyz, h, m, precision="fp64", keep_pairs=True, out_mass=mass,
+                                           out_density=dens, out_coverage=cov)
+            pkg.map_cells_to_particles(ctx, r.pairs, qcell, out=qpart)
+            r.pairs.free()
+        torch.cuda.synchronize()
+        el64 = time.perf_counter() - t0
+        ref = mass.clone()
+        rel = ((mass_mixed - ref).abs() / ref.abs().clamp_min(1e-300)).max().item()
+        fp64 = {"value": round(n_pairs * args.fp64_steps / el64, 1), "unit": "pairs/s",
+                "ms_per_step": round(el64 * 1e3 / args.fp64_steps, 3), "steps": args.fp64_steps,
+                "mixed_speedup": round((n_pairs * args.steps / el) / (n_pairs * args.fp64_steps / el64), 3),
+                "max_rel_cell_mass_diff_mixed_vs_fp64": rel}
+        mass.copy_(mass_mixed)
+
     cpu = None
     if not args.no_cpu and args.cpu_sample > 0:
         from oracle import oracle
@@ -158,6 +183,7 @@ def main():
                    "tess_upload_ms": round(tess_ms, 2)},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "fp64_path": fp64,
         "kernels_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in other.items()},
         "work_counters": ctr,
     }

@@ -15,77 +15,207 @@
 // (outside) the cell gets exactly 1 (0).  In polar coordinates about the
 // foot P0 of x on the face plane (distance d), each edge e at in-plane
 // distance p_e from P0 spans a right-triangle fan; with tau the coordinate
-// along the edge from the foot of P0 and U = sqrt(d^2 + p^2 + tau^2),
-//     4pi C_f / |d| = sum_e sgn(p_e) [F(tau_B) - F(tau_A)] - H(|d|) theta_f
-// where H(u) = -int_u^2 (1 - Phi(s))/s^2 ds, F(tau) = int_0^{phi(tau)} H(U)
-// dphi (zero contribution once U >= 2), and theta_f = 2pi when P0 lies inside
-// the face polygon, 0 outside.  F is written with
-//     phi = atan(tau/p), beta = atan(|d| tau/(p U)), L = asinh(tau/a),
+// along the edge from the foot of P0, U = sqrt(d^2 + p^2 + tau^2) and
+// H(u) = -int_u^2 (1 - Phi(s))/s^2 ds (zero for u >= 2),
+//     4pi C_f = sum_e sgn(p_e) int_{phi_A}^{phi_B} |d| [H(U) - H(|d|)] dphi.
+// Each edge term is evaluated with the same angles phi = atan(tau/p) in both
+// of its parts, so rounding in an endpoint angle is multiplied by
+// H(U) - H(|d|), which vanishes where that rounding is largest (foot point
+// next to a vertex).  A face none of whose edges comes within 2h uses the
+// exact angle sum (2pi if P0 is inside the polygon, 0 outside).
+//
+// The antiderivative |d| int H(U) dphi is, per regime (U < 1, 1 <= U < 2),
+//     c_phi phi + c_beta beta + c_L L + tau (c_1 + c_3 tau^2)
+//                                     + tau U (c_5 + c_7 tau^2),
+//     phi = atan(tau/p), beta = atan(|d| tau / (p U)), L = asinh(tau/a),
 //     a^2 = d^2 + p^2,
-// as polynomials in (tau, U, p, |d|) plus multiples of phi, beta and L, one
-// form for U < 1 and one for 1 <= U < 2, joined continuously at U = 1.
+// with coefficients that depend on (|d|, p) only, joined continuously at
+// U = 1.  Two evaluation paths:
+//   binary64: every step in binary64 with the math library's functions;
+//   mixed: edge geometry in binary32; atan, asinh and square roots from
+//     binary32 polynomial cores and seeds with binary64 range reduction and
+//     assembly (about 1e-9 relative); coefficients, angles' combination and
+//     every accumulation in binary64.  Edges whose foot point nearly touches
+//     the edge line or whose face plane nearly touches the particle (p or |d|
+//     below 1e-4 h) are recomputed from binary64 geometry.
 #include "common.hpp"
 
 namespace sphmap {
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
+constexpr double kHalfPi = 1.57079632679489661923;
+constexpr double kQuarterPi = 0.78539816339744830962;
 constexpr double kInv4Pi = 0.079577471545947667884;
+constexpr double kLn2 = 0.69314718055994530942;
 
-// |d| * F_r(tau) for regime r (0: U < 1, 1: 1 <= U < 2).
-__device__ inline double Fd64(int reg, double ad, double p, double tau, double a2, double U) {
-  const double d2 = ad * ad;
-  const double a = sqrt(a2);
-  const double phi = atan2(tau, p);
-  const double beta = atan2(ad * tau, p * U);
-  const double L = asinh(tau / a);
-  const double E1 = p * L + ad * beta;
-  const double IU = 0.5 * (tau * U + a2 * L);
-  const double U2 = U * U;
-  const double IU2 = tau * U * (0.25 * U2 - 0.125 * a2) - 0.125 * a2 * a2 * L;
-  const double E2 = d2 * phi + p * tau;
-  const double E3 = d2 * E1 + p * IU;
-  const double E4 = d2 * d2 * phi + 2.0 * d2 * p * tau + p * (p * p * tau + tau * tau * tau * (1.0 / 3.0));
-  const double E5 = d2 * d2 * E1 + 2.0 * d2 * p * IU + p * (p * p * IU + IU2);
-  if (reg == 0) return ad * (1.4 * phi - (2.0 / 3.0) * E2 + 0.3 * E4 - 0.1 * E5) - beta;
-  return ad * (1.6 * phi - (4.0 / 3.0) * E2 + E3 - 0.3 * E4 + E5 * (1.0 / 30.0)) - (16.0 / 15.0) * beta;
+// ----------------------------------------------------------- coefficients
+struct Coef {
+  double phi, beta, L, t1, t3, tU, t3U;
+};
+
+// Regime 0 (U < 1) and regime 1 (1 <= U < 2) coefficients of
+// |d| int H(U) dphi for one edge.
+__device__ inline void edge_coefs(double ad, double p, Coef &c0, Coef &c1) {
+  const double d2 = ad * ad, p2 = p * p, a2 = d2 + p2, d4 = d2 * d2;
+  const double A = 2.0 * d2 * p + p2 * p;
+  const double B = d4 * p + 0.5 * A * a2 - 0.125 * p * a2 * a2;
+  const double T = 0.5 * A + 0.125 * p * a2;
+  const double adp = ad * p;
+  c0.phi = ad * (1.4 - (2.0 / 3.0) * d2 + 0.3 * d4);
+  c0.beta = -1.0 - 0.1 * d4 * d2;
+  c0.L = -0.1 * ad * B;
+  c0.t1 = ad * (-(2.0 / 3.0) * p + 0.3 * A);
+  c0.t3 = 0.1 * adp;
+  c0.tU = -0.1 * ad * T;
+  c0.t3U = -0.025 * adp;
+  c1.phi = ad * (1.6 - (4.0 / 3.0) * d2 - 0.3 * d4);
+  c1.beta = -16.0 / 15.0 + d4 + d4 * d2 * (1.0 / 30.0);
+  c1.L = ad * (d2 * p + 0.5 * p * a2 + B * (1.0 / 30.0));
+  c1.t1 = ad * (-(4.0 / 3.0) * p - 0.3 * A);
+  c1.t3 = -0.1 * adp;
+  c1.tU = ad * (0.5 * p + T * (1.0 / 30.0));
+  c1.t3U = adp * (1.0 / 120.0);
+}
+
+__device__ inline double coef_eval(const Coef &c, double phi, double beta, double L, double tau, double U) {
+  const double t2 = tau * tau;
+  return c.phi * phi + c.beta * beta + c.L * L + tau * (c.t1 + c.t3 * t2) + tau * U * (c.tU + c.t3U * t2);
 }
 
 // |d| H(|d|)
-__device__ inline double dH64(double ad) {
+__device__ inline double dH(double ad) {
   const double a2 = ad * ad, a3 = a2 * ad;
   if (ad < 1.0) return 1.4 * ad - 1.0 - (2.0 / 3.0) * a3 + 0.3 * a3 * a2 - 0.1 * a3 * a3;
   return 1.6 * ad - 16.0 / 15.0 - (4.0 / 3.0) * a3 + a3 * ad - 0.3 * a3 * a2 + a3 * a3 * (1.0 / 30.0);
 }
 
-// |d| [F(tB) - F(tA)] for one edge (p > 0, tA < tB).  n0 / n1 count the
-// closed-form evaluations in the inner / outer regime.
-__device__ double edge64(double ad, double p, double tA, double tB, int &n0, int &n1) {
+// ------------------------------------------------- transcendental kernels
+// binary64 with the math library
+struct Math64 {
+  static __device__ inline double atanq(double y, double x) { return atan2(y, x); }  // x > 0
+  static __device__ inline double asinh_(double z) { return asinh(z); }
+  static __device__ inline double sqrt_(double v) { return sqrt(v); }
+  static __device__ inline double rcp(double v) { return 1.0 / v; }
+};
+
+// binary32 seeds / polynomial cores, binary64 refinement and assembly
+__device__ inline double rcp_mixed(double x) {
+  const double r = (double)__builtin_amdgcn_rcpf((float)x);
+  const double e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ inline double sqrt_mixed(double v) {
+  double y = (double)__builtin_amdgcn_rsqf((float)v);
+  y = y * fma(-0.5 * v * y, y, 1.5);
+  const double r = v * y;
+  return fma(0.5 * y, fma(-r, r, v), r);
+}
+// atan(y/x) for x > 0: reduce to |s| <= tan(pi/8) with one division, then
+// atan(s) = s + s^3 P(s^2), P a degree-5 polynomial fitted to
+// (atan(sqrt z) - sqrt z) / z^1.5 on [0, tan^2(pi/8)] (max rel. error 2e-9),
+// evaluated in binary32.
+__device__ inline double atan_mixed(double y, double x) {
+  const double ay = fabs(y);
+  const bool small = ay <= 0.41421356237309503 * x;
+  const bool large = ay >= 2.414213562373095 * x;
+  const double num = small ? ay : (large ? -x : ay - x);
+  const double den = small ? x : (large ? ay : ay + x);
+  const double base = small ? 0.0 : (large ? kHalfPi : kQuarterPi);
+  const double rd = rcp_mixed(den);
+  double s = num * rd;
+  s = fma(rd, fma(-den, s, num), s);
+  const double z = s * s;
+  const float zf = (float)z;
+  float P = 0.050527118146419525f;
+  P = fmaf(P, zf, -0.08626646548509598f);
+  P = fmaf(P, zf, 0.11071662604808807f);
+  P = fmaf(P, zf, -0.14284169673919678f);
+  P = fmaf(P, zf, 0.19999977946281433f);
+  P = fmaf(P, zf, -0.3333333432674408f);
+  const double r = base + fma(s * z, (double)P, s);
+  return copysign(r, y);
+}
+// asinh(z) = log(|z| + sqrt(z^2 + 1)); log(2^e m) = e ln2 + 2 atanh(t),
+// t = (m - 1)/(m + 1), 2 atanh(t) = 2t + t^3 Q(t^2), Q a degree-3 polynomial
+// fitted on |t| <= 3 - 2 sqrt(2) (max rel. error 2e-9), evaluated in binary32.
+__device__ inline double asinh_mixed(double z) {
+  const double az = fabs(z);
+  const double q = sqrt_mixed(fma(az, az, 1.0));
+  const double sv = az + q;
+  int e = __builtin_amdgcn_frexp_exp(sv);
+  double m = __builtin_amdgcn_frexp_mant(sv);  // [0.5, 1)
+  if (m < 0.70710678118654752) {
+    m *= 2.0;
+    e -= 1;
+  }
+  const double mm1 = (e == 0) ? az + az * az * rcp_mixed(q + 1.0) : m - 1.0;
+  const double den = m + 1.0;
+  const double rd = rcp_mixed(den);
+  double t = mm1 * rd;
+  t = fma(rd, fma(-den, t, mm1), t);
+  const double t2 = t * t;
+  const float zf = (float)t2;
+  float Q = 0.23331113159656525f;
+  Q = fmaf(Q, zf, 0.2855079174041748f);
+  Q = fmaf(Q, zf, 0.4000012278556824f);
+  Q = fmaf(Q, zf, 0.6666666865348816f);
+  const double L = (double)e * kLn2 + fma(t * t2, (double)Q, 2.0 * t);
+  return copysign(L, z);
+}
+struct MathMixed {
+  static __device__ inline double atanq(double y, double x) { return atan_mixed(y, x); }
+  static __device__ inline double asinh_(double z) { return asinh_mixed(z); }
+  static __device__ inline double sqrt_(double v) { return sqrt_mixed(v); }
+  static __device__ inline double rcp(double v) { return rcp_mixed(v); }
+};
+
+// ------------------------------------------------------------- one edge
+struct EdgeCount {
+  int n0 = 0, n1 = 0;
+};
+
+// sum over the fan of |d| [H(U) - H(|d|)] dphi for one edge with p > 0 and
+// tA < tB.  Returns false in `integ` when no part of the edge lies within
+// U < 2 (then the value is -dh * (phi_B - phi_A)).
+template <class M>
+__device__ double edge_term(double ad, double p, double tA, double tB, double dh, bool &integ, EdgeCount &cnt) {
   const double a2 = ad * ad + p * p;
-  if (a2 >= 4.0) return 0.0;
-  const double t2 = sqrt(4.0 - a2);
+  integ = false;
+  const double phiA = M::atanq(tA, p), phiB = M::atanq(tB, p);
+  if (a2 >= 4.0) return -dh * (phiB - phiA);
+  const double t2 = M::sqrt_(4.0 - a2);
   const double ca = fmin(fmax(tA, -t2), t2), cb = fmin(fmax(tB, -t2), t2);
-  if (!(ca < cb)) return 0.0;
+  if (!(ca < cb)) return -dh * (phiB - phiA);
+  integ = true;
+  Coef c0, c1;
+  edge_coefs(ad, p, c0, c1);
+  const double a = M::sqrt_(a2);
+  const double ia = M::rcp(a);
   double t1 = -1.0, D = 0.0;
   if (a2 < 1.0) {
-    t1 = sqrt(1.0 - a2);
+    t1 = M::sqrt_(1.0 - a2);
     if (fabs(ca) > t1 || fabs(cb) > t1) {
-      D = Fd64(0, ad, p, t1, a2, 1.0) - Fd64(1, ad, p, t1, a2, 1.0);
-      ++n0;
-      ++n1;
+      const double ph = M::atanq(t1, p), be = M::atanq(ad * t1, p), Lz = M::asinh_(t1 * ia);
+      D = coef_eval(c0, ph, be, Lz, t1, 1.0) - coef_eval(c1, ph, be, Lz, t1, 1.0);
+      ++cnt.n0;
+      ++cnt.n1;
     }
   }
-  auto F = [&](double t) -> double {
+  auto F = [&](double t, double phi) -> double {
     const double at = fabs(t);
+    const double U = (at == t2) ? 2.0 : M::sqrt_(a2 + t * t);
+    const double be = M::atanq(ad * t, p * U), Lz = M::asinh_(t * ia);
     if (at <= t1) {
-      ++n0;
-      return Fd64(0, ad, p, t, a2, sqrt(a2 + t * t));
+      ++cnt.n0;
+      return coef_eval(c0, phi, be, Lz, t, U);
     }
-    ++n1;
-    const double U = (at == t2) ? 2.0 : sqrt(a2 + t * t);
-    return Fd64(1, ad, p, t, a2, U) + copysign(D, t);
+    ++cnt.n1;
+    return coef_eval(c1, phi, be, Lz, t, U) + copysign(D, t);
   };
-  return F(cb) - F(ca);
+  const double fa = F(ca, ca == tA ? phiA : M::atanq(ca, p));
+  const double fb = F(cb, cb == tB ? phiB : M::atanq(cb, p));
+  return (fb - fa) - dh * (phiB - phiA);
 }
 
 // Signed solid angle of a planar polygon seen from x (Van Oosterom and
@@ -106,6 +236,76 @@ __device__ double solid_angle(const double *V, int nv, double x0, double x1, dou
   return om;
 }
 
+// S for a particle exactly on the boundary: signed solid angles of the faces
+// it is not on, in binary64.
+__device__ double boundary_S(int64_t f0, int64_t f1, const double4 *fplane, const int64_t *fvo, const double *fvpos,
+                             double x0, double x1, double x2) {
+  double om = 0.0;
+  for (int64_t f = f0; f < f1; ++f) {
+    const double4 pl = fplane[f];
+    if (!(pl.w > 0.0)) continue;
+    const double dist = pl.w - (pl.x * x0 + pl.y * x1 + pl.z * x2);
+    if (dist == 0.0) continue;
+    om += fabs(solid_angle(fvpos + 3 * fvo[f], (int)(fvo[f + 1] - fvo[f]), x0, x1, x2));
+  }
+  return om * kInv4Pi;
+}
+
+// One face in binary64: geometry about the generator, particle at xr.
+__device__ double face_fp64(const double4 pl, double dist, double ih, double xr0, double xr1, double xr2,
+                            const double *V, int nv, int &ne_vis, int &ne_int, EdgeCount &cnt) {
+  const double d = dist * ih, ad = fabs(d);
+  const double dh = dH(ad);
+  const double P0x = xr0 + dist * pl.x, P0y = xr1 + dist * pl.y, P0z = xr2 + dist * pl.z;
+  double sum = 0.0;
+  bool allpos = true, anyzero = false, anyint = false;
+  for (int q = 0; q < nv; ++q) {
+    const int q1 = (q + 1 == nv) ? 0 : q + 1;
+    const double Ax = V[3 * q], Ay = V[3 * q + 1], Az = V[3 * q + 2];
+    const double Bx = V[3 * q1], By = V[3 * q1 + 1], Bz = V[3 * q1 + 2];
+    const double abx = Bx - Ax, aby = By - Ay, abz = Bz - Az;
+    const double len2 = abx * abx + aby * aby + abz * abz;
+    if (len2 == 0.0) continue;
+    const double il = 1.0 / sqrt(len2);
+    const double ex = abx * il, ey = aby * il, ez = abz * il;
+    // in-plane normal of the edge pointing into the polygon: n x e
+    const double mx = pl.y * ez - pl.z * ey, my = pl.z * ex - pl.x * ez, mz = pl.x * ey - pl.y * ex;
+    const double p = ((P0x - Ax) * mx + (P0y - Ay) * my + (P0z - Az) * mz) * ih;
+    if (p <= 0.0) allpos = false;
+    if (p == 0.0) {
+      anyzero = true;
+      continue;
+    }
+    ++ne_vis;
+    const double tA = ((Ax - P0x) * ex + (Ay - P0y) * ey + (Az - P0z) * ez) * ih;
+    const double tB = ((Bx - P0x) * ex + (By - P0y) * ey + (Bz - P0z) * ez) * ih;
+    bool integ;
+    const double v = edge_term<Math64>(ad, fabs(p), tA, tB, dh, integ, cnt);
+    anyint |= integ;
+    ne_int += integ;
+    sum += p > 0.0 ? v : -v;
+  }
+  if (!anyint && !anyzero) sum = -dh * (allpos ? 2.0 * kPi : 0.0);
+  const double Cf = sum * kInv4Pi;
+  return d > 0.0 ? Cf : -Cf;
+}
+
+struct Counters {
+  int nf_int = 0, ne_vis = 0, ne_int = 0, n64 = 0;
+  EdgeCount fd;
+};
+
+__device__ inline void flush_counters(int64_t *counters, int64_t nfaces, const Counters &k) {
+  atomicAdd((unsigned long long *)&counters[1], (unsigned long long)nfaces);
+  atomicAdd((unsigned long long *)&counters[2], (unsigned long long)k.nf_int);
+  atomicAdd((unsigned long long *)&counters[3], (unsigned long long)k.ne_vis);
+  atomicAdd((unsigned long long *)&counters[4], (unsigned long long)k.ne_int);
+  atomicAdd((unsigned long long *)&counters[5], (unsigned long long)k.fd.n0);
+  atomicAdd((unsigned long long *)&counters[6], (unsigned long long)k.fd.n1);
+  atomicAdd((unsigned long long *)&counters[7], (unsigned long long)k.n64);
+}
+
+// ------------------------------------------------------- binary64 kernel
 __global__ void __launch_bounds__(256) k_exact_fp64(int64_t P, const int32_t *pair_c, const int32_t *pair_p,
                                                    const double *xyz, const double *hh, const double *gen,
                                                    const int64_t *cfo, const int64_t *fvo, const double4 *fplane,
@@ -121,7 +321,7 @@ __global__ void __launch_bounds__(256) k_exact_fp64(int64_t P, const int32_t *pa
                xr2 = xyz[3 * i + 2] - gen[3 * c + 2];
   double acc = 0.0;
   bool inside = true, on_boundary = false;
-  int nf_int = 0, ne_vis = 0, ne_int = 0, nfd0 = 0, nfd1 = 0;
+  Counters K;
   const int64_t f0 = cfo[c], f1 = cfo[c + 1];
   for (int64_t f = f0; f < f1; ++f) {
     const double4 pl = fplane[f];
@@ -132,110 +332,159 @@ __global__ void __launch_bounds__(256) k_exact_fp64(int64_t P, const int32_t *pa
       on_boundary = true;
       continue;
     }
-    const double d = dist * ih, ad = fabs(d);
-    if (ad >= 2.0) continue;
+    if (fabs(dist) >= 2.0 * h) continue;
     const double4 sp = fsphere[f];
     const double sx = xr0 - sp.x, sy = xr1 - sp.y, sz = xr2 - sp.z;
     const double reach = sp.w + 2.0 * h;
     if (sx * sx + sy * sy + sz * sz >= reach * reach) continue;
-    ++nf_int;
-    const double P0x = xr0 + dist * pl.x, P0y = xr1 + dist * pl.y, P0z = xr2 + dist * pl.z;
-    const int64_t vs = fvo[f], ve = fvo[f + 1];
-    const int nv = (int)(ve - vs);
-    const double *V = fvpos + 3 * vs;
+    ++K.nf_int;
+    acc += face_fp64(pl, dist, ih, xr0, xr1, xr2, fvpos + 3 * fvo[f], (int)(fvo[f + 1] - fvo[f]), K.ne_vis,
+                     K.ne_int, K.fd);
+  }
+  double S = inside ? 1.0 : 0.0;
+  if (inside && on_boundary) S = boundary_S(f0, f1, fplane, fvo, fvpos, xr0, xr1, xr2);
+  w_out[k] = S - acc;
+  if (counters) flush_counters(counters, f1 - f0, K);
+}
+
+// ---------------------------------------------------------- mixed kernel
+constexpr float kDegenerate = 1e-4f;  // p or |d| below this (units of h): binary64 edge
+
+__global__ void __launch_bounds__(256) k_exact_mixed(int64_t P, const int32_t *pair_c, const int32_t *pair_p,
+                                                    const double *xyz, const double *hh, const double *gen,
+                                                    const int64_t *cfo, const int64_t *fvo, const double4 *fplane,
+                                                    const float4 *fplane32, const double4 *fsphere,
+                                                    const double *fvpos, const float4 *fvpos32, double *w_out,
+                                                    int64_t *counters) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= P) return;
+  const int64_t c = pair_c[k];
+  const int64_t i = pair_p[k];
+  const double h = hh[i];
+  const double ih = 1.0 / h;
+  const float ihf = (float)ih;
+  const double xr0 = xyz[3 * i] - gen[3 * c], xr1 = xyz[3 * i + 1] - gen[3 * c + 1],
+               xr2 = xyz[3 * i + 2] - gen[3 * c + 2];
+  // particle about the generator, in units of h, binary32
+  const float x0 = (float)(xr0 * ih), x1 = (float)(xr1 * ih), x2 = (float)(xr2 * ih);
+  double acc = 0.0;
+  bool inside = true, on_boundary = false;
+  Counters K;
+  const int64_t f0 = cfo[c], f1 = cfo[c + 1];
+  for (int64_t f = f0; f < f1; ++f) {
+    const double4 pl = fplane[f];
+    if (!(pl.w > 0.0)) continue;
+    const double dist = pl.w - (pl.x * xr0 + pl.y * xr1 + pl.z * xr2);
+    if (dist < 0.0) inside = false;
+    if (dist == 0.0) {
+      on_boundary = true;
+      continue;
+    }
+    if (fabs(dist) >= 2.0 * h) continue;
+    const double4 sp = fsphere[f];
+    const double sx = xr0 - sp.x, sy = xr1 - sp.y, sz = xr2 - sp.z;
+    const double reach = sp.w + 2.0 * h;
+    if (sx * sx + sy * sy + sz * sz >= reach * reach) continue;
+    ++K.nf_int;
+    const int64_t vs = fvo[f];
+    const int nv = (int)(fvo[f + 1] - vs);
+    const double d = dist * ih, ad = fabs(d);
+    if (ad < kDegenerate) {
+      // particle on the face plane to within 1e-4 h: the whole face in binary64
+      K.n64 += nv;
+      acc += face_fp64(pl, dist, ih, xr0, xr1, xr2, fvpos + 3 * vs, nv, K.ne_vis, K.ne_int, K.fd);
+      continue;
+    }
+    const double dh = dH(ad);
+    const float4 pf = fplane32[f];
+    const float df = (float)d;
+    const float P0x = x0 + df * pf.x, P0y = x1 + df * pf.y, P0z = x2 + df * pf.z;
     double sum = 0.0;
-    bool allpos = true, anyzero = false;
+    bool allpos = true, anyzero = false, anyint = false;
+    float4 A = fvpos32[vs];
+    A.x *= ihf;
+    A.y *= ihf;
+    A.z *= ihf;
     for (int q = 0; q < nv; ++q) {
       const int q1 = (q + 1 == nv) ? 0 : q + 1;
-      const double Ax = V[3 * q], Ay = V[3 * q + 1], Az = V[3 * q + 2];
-      const double abx = V[3 * q1] - Ax, aby = V[3 * q1 + 1] - Ay, abz = V[3 * q1 + 2] - Az;
-      const double len2 = abx * abx + aby * aby + abz * abz;
-      if (len2 == 0.0) continue;
-      const double len = sqrt(len2), il = 1.0 / len;
-      const double ex = abx * il, ey = aby * il, ez = abz * il;
-      // in-plane normal of the edge pointing into the polygon: n x e
-      const double mx = pl.y * ez - pl.z * ey, my = pl.z * ex - pl.x * ez, mz = pl.x * ey - pl.y * ex;
-      const double p = ((P0x - Ax) * mx + (P0y - Ay) * my + (P0z - Az) * mz) * ih;
-      if (p <= 0.0) allpos = false;
-      if (p == 0.0) {
-        anyzero = true;
-        continue;
+      float4 B = fvpos32[vs + q1];
+      B.x *= ihf;
+      B.y *= ihf;
+      B.z *= ihf;
+      const float abx = B.x - A.x, aby = B.y - A.y, abz = B.z - A.z;
+      const float len2 = abx * abx + aby * aby + abz * abz;
+      if (len2 > 0.0f) {
+        const float il = __builtin_amdgcn_rsqf(len2);
+        const float ex = abx * il, ey = aby * il, ez = abz * il;
+        const float mx = pf.y * ez - pf.z * ey, my = pf.z * ex - pf.x * ez, mz = pf.x * ey - pf.y * ex;
+        const float p = (P0x - A.x) * mx + (P0y - A.y) * my + (P0z - A.z) * mz;
+        if (p <= 0.0f) allpos = false;
+        if (p == 0.0f) {
+          anyzero = true;
+        } else {
+          ++K.ne_vis;
+          bool integ;
+          double v;
+          if (fabsf(p) < kDegenerate) {
+            // foot point within 1e-4 h of the edge line: binary64 geometry
+            ++K.n64;
+            const double *V = fvpos + 3 * vs;
+            const double P0dx = xr0 + dist * pl.x, P0dy = xr1 + dist * pl.y, P0dz = xr2 + dist * pl.z;
+            const double Ax = V[3 * q], Ay = V[3 * q + 1], Az = V[3 * q + 2];
+            const double Bx = V[3 * q1], By = V[3 * q1 + 1], Bz = V[3 * q1 + 2];
+            const double bx = Bx - Ax, by = By - Ay, bz = Bz - Az;
+            const double il64 = 1.0 / sqrt(bx * bx + by * by + bz * bz);
+            const double e0 = bx * il64, e1 = by * il64, e2 = bz * il64;
+            const double m0 = pl.y * e2 - pl.z * e1, m1 = pl.z * e0 - pl.x * e2, m2 = pl.x * e1 - pl.y * e0;
+            const double p64 = ((P0dx - Ax) * m0 + (P0dy - Ay) * m1 + (P0dz - Az) * m2) * ih;
+            const double tA = ((Ax - P0dx) * e0 + (Ay - P0dy) * e1 + (Az - P0dz) * e2) * ih;
+            const double tB = ((Bx - P0dx) * e0 + (By - P0dy) * e1 + (Bz - P0dz) * e2) * ih;
+            if (p64 == 0.0) {
+              v = 0.0;
+              integ = false;
+            } else {
+              v = edge_term<Math64>(ad, fabs(p64), tA, tB, dh, integ, K.fd);
+              if (p64 < 0.0) v = -v;
+            }
+          } else {
+            const float tA = (A.x - P0x) * ex + (A.y - P0y) * ey + (A.z - P0z) * ez;
+            const float tB = (B.x - P0x) * ex + (B.y - P0y) * ey + (B.z - P0z) * ez;
+            v = edge_term<MathMixed>(ad, (double)fabsf(p), (double)tA, (double)tB, dh, integ, K.fd);
+            if (p < 0.0f) v = -v;
+          }
+          anyint |= integ;
+          K.ne_int += integ;
+          sum += v;
+        }
       }
-      ++ne_vis;
-      const double tA = ((Ax - P0x) * ex + (Ay - P0y) * ey + (Az - P0z) * ez) * ih;
-      const double tB = tA + len * ih;
-      if (d * d + p * p >= 4.0) continue;
-      ++ne_int;
-      const double v = edge64(ad, fabs(p), tA, tB, nfd0, nfd1);
-      sum += p > 0.0 ? v : -v;
+      A = B;
     }
-    double theta;
-    if (anyzero) {
-      // P0 on an edge line: total signed angle from the edges with p != 0
-      theta = 0.0;
-      for (int q = 0; q < nv; ++q) {
-        const int q1 = (q + 1 == nv) ? 0 : q + 1;
-        const double Ax = V[3 * q], Ay = V[3 * q + 1], Az = V[3 * q + 2];
-        const double abx = V[3 * q1] - Ax, aby = V[3 * q1 + 1] - Ay, abz = V[3 * q1 + 2] - Az;
-        const double len2 = abx * abx + aby * aby + abz * abz;
-        if (len2 == 0.0) continue;
-        const double len = sqrt(len2), il = 1.0 / len;
-        const double ex = abx * il, ey = aby * il, ez = abz * il;
-        const double mx = pl.y * ez - pl.z * ey, my = pl.z * ex - pl.x * ez, mz = pl.x * ey - pl.y * ex;
-        const double p = (P0x - Ax) * mx + (P0y - Ay) * my + (P0z - Az) * mz;
-        if (p == 0.0) continue;
-        const double tA = (Ax - P0x) * ex + (Ay - P0y) * ey + (Az - P0z) * ez;
-        const double dphi = atan2(tA + len, fabs(p)) - atan2(tA, fabs(p));
-        theta += p > 0.0 ? dphi : -dphi;
-      }
-    } else {
-      theta = allpos ? 2.0 * kPi : 0.0;
-    }
-    const double Cf = (sum - dH64(ad) * theta) * kInv4Pi;
+    if (!anyint && !anyzero) sum = -dh * (allpos ? 2.0 * kPi : 0.0);
+    const double Cf = sum * kInv4Pi;
     acc += d > 0.0 ? Cf : -Cf;
   }
-  double S;
-  if (!inside) {
-    S = 0.0;
-  } else if (!on_boundary) {
-    S = 1.0;
-  } else {
-    // particle exactly on the cell boundary: signed solid angles of the
-    // faces it is not on
-    double om = 0.0;
-    for (int64_t f = f0; f < f1; ++f) {
-      const double4 pl = fplane[f];
-      if (!(pl.w > 0.0)) continue;
-      const double dist = pl.w - (pl.x * xr0 + pl.y * xr1 + pl.z * xr2);
-      if (dist == 0.0) continue;
-      const int64_t vs = fvo[f], ve = fvo[f + 1];
-      om += fabs(solid_angle(fvpos + 3 * vs, (int)(ve - vs), xr0, xr1, xr2));
-    }
-    S = om * kInv4Pi;
-  }
+  double S = inside ? 1.0 : 0.0;
+  if (inside && on_boundary) S = boundary_S(f0, f1, fplane, fvo, fvpos, xr0, xr1, xr2);
   w_out[k] = S - acc;
-  if (counters) {
-    atomicAdd((unsigned long long *)&counters[1], (unsigned long long)(f1 - f0));
-    atomicAdd((unsigned long long *)&counters[2], (unsigned long long)nf_int);
-    atomicAdd((unsigned long long *)&counters[3], (unsigned long long)ne_vis);
-    atomicAdd((unsigned long long *)&counters[4], (unsigned long long)ne_int);
-    atomicAdd((unsigned long long *)&counters[5], (unsigned long long)nfd0);
-    atomicAdd((unsigned long long *)&counters[6], (unsigned long long)nfd1);
-  }
+  if (counters) flush_counters(counters, f1 - f0, K);
 }
 
 }  // namespace
 
 void exact_integral(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, int precision, hipStream_t s) {
-  (void)precision;
   P.w = P.mem.get<double>("w", P.n_pairs);
   if (P.n_pairs == 0) return;
   int64_t *ctr = ctx.counting ? ctx.d_counters : nullptr;
   if (ctr) SPH_HIP(hipMemsetAsync(ctr, 0, 8 * sizeof(int64_t), s));
   KernelTimer kt(&ctx, "exact_integral", s);
-  k_exact_fp64<<<(unsigned)div_up(P.n_pairs, 256), 256, 0, s>>>(P.n_pairs, P.pair_c, P.pair_p, p.xyz, p.h, t.gen,
-                                                                 t.cell_face_off, t.face_vtx_off, t.fplane,
-                                                                 t.fsphere, t.fvpos, P.w, ctr);
+  const unsigned grid = (unsigned)div_up(P.n_pairs, 256);
+  if (precision == SPHMAP_PREC_FP64)
+    k_exact_fp64<<<grid, 256, 0, s>>>(P.n_pairs, P.pair_c, P.pair_p, p.xyz, p.h, t.gen, t.cell_face_off,
+                                      t.face_vtx_off, t.fplane, t.fsphere, t.fvpos, P.w, ctr);
+  else
+    k_exact_mixed<<<grid, 256, 0, s>>>(P.n_pairs, P.pair_c, P.pair_p, p.xyz, p.h, t.gen, t.cell_face_off,
+                                       t.face_vtx_off, t.fplane, t.fplane32, t.fsphere, t.fvpos, t.fvpos32, P.w,
+                                       ctr);
   SPH_LAUNCH_CHECK();
   kt.done();
 }

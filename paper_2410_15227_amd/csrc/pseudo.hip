@@ -1,8 +1,618 @@
-// Pseudo-particle builder (replaced by the full implementation).
+// Tree-node pseudo-particles (Sec. 2.4).
+//
+// The gravity tree here is an octree of the unit cube built from 63-bit
+// Morton keys: a node at level l is a run of particles sharing the top 3l key
+// bits, a node with more than leaf_max particles (and below max_depth) splits
+// into the runs of its next 3-bit digit (child order = octant order x = 1,
+// y = 2, z = 4).  Node position is the centre of mass and node size the
+// distance from it to the furthest member (Sec. 2.2.1).  So that a host
+// reference reproduces the accepted set bit for bit, node sums are formed in a
+// fixed order without contraction: a leaf adds its members in ascending
+// particle index, an internal node adds its children's sums in octant order.
+//
+// Walk (Sec. 2.2.2, Sec. 2.4.1): a node is emitted when it is accepted and no
+// ancestor is; a leaf that is not accepted and has no accepted ancestor is
+// opened and its particles are emitted as themselves (they keep their h).
+// Acceptance: for every source, r - s > r_part and not (theta^2 r^2 < s^2)
+// (eq. opening_angle).  Each emitted node or opened leaf is one "unit"; the
+// units tile the particle order, so depth-first emission order is the order
+// of their first particle.
+//
+// Node smoothing lengths (Sec. 2.4.2, eqs. h_node, n_node, hnode_func,
+// hnode_func_deriv, hnode_newton_raphson, hnode_estval): n(h) sums
+// W(|r_a - r_b|, h) over all units b (opened leaves stand in for their
+// particles; self term included).  Newton from h0 = h_fact 2 s to
+// |h_new - h| / h0 < eps_h; Newton fails after 30 steps, when an iterate
+// leaves [1e-2 h0, 1e2 h0] or when |f'| < 1e-12; then bisection on
+// [1e-2 h0, 1e2 h0] when f changes sign there, else h0.  The sums over units
+// run in unit order, tiled through LDS, one thread per pseudo-particle.
 #include "common.hpp"
+
 namespace sphmap {
-void pseudo_build(Ctx &ctx, PseudoArgs &a, hipStream_t s) {
-  (void)ctx; (void)a; (void)s;
-  throw Error{SPHMAP_EINVAL, "pseudo-particle builder not available"};
+namespace {
+
+constexpr int kMaxLevels = 22;
+
+struct NodeArrays {
+  int32_t *first, *count, *parent, *child_first, *nchild, *level;
+};
+
+__global__ void k_check_unit_cube(int64_t n, const double *xyz, int *bad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = 0; k < 3; ++k) {
+    double x = xyz[3 * i + k];
+    if (!(x >= 0.0 && x < 1.0)) {
+      atomicAdd(bad, 1);
+      return;
+    }
+  }
 }
+
+__global__ void k_root(NodeArrays N, int64_t n) {
+  N.first[0] = 0;
+  N.count[0] = (int32_t)n;
+  N.parent[0] = -1;
+  N.level[0] = 0;
+  N.child_first[0] = -1;
+  N.nchild[0] = 0;
+}
+
+__device__ inline int digit_of(uint64_t key, int level) {
+  // digit selecting the child at `level` (1 = first split below the root)
+  return (int)((key >> (3 * (21 - level))) & 7ull);
+}
+
+// For each node of the level [b, e): the non-empty child runs.
+__global__ void k_split(NodeArrays N, int64_t b, int64_t e, int level, const uint64_t *keys, int leaf_max,
+                        int max_depth, int32_t *tfirst, int32_t *tcount, int64_t *nch) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= e - b) return;
+  const int64_t node = b + j;
+  const int32_t f = N.first[node], c = N.count[node];
+  int k = 0;
+  if (c > leaf_max && level < max_depth) {
+    int32_t lo = f;
+    const int32_t end = f + c;
+    for (int d = 0; d < 8; ++d) {
+      // first position in [lo, end) whose digit exceeds d
+      int32_t a = lo, z = end;
+      while (a < z) {
+        int32_t mid = a + (z - a) / 2;
+        if (digit_of(keys[mid], level + 1) <= d) a = mid + 1;
+        else z = mid;
+      }
+      if (a > lo) {
+        tfirst[8 * j + k] = lo;
+        tcount[8 * j + k] = a - lo;
+        ++k;
+      }
+      lo = a;
+    }
+  }
+  nch[j] = k;
+}
+
+__global__ void k_children(NodeArrays N, int64_t b, int64_t e, int level, int64_t next_off, const int32_t *tfirst,
+                           const int32_t *tcount, const int64_t *nch, const int64_t *choff) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= e - b) return;
+  const int64_t node = b + j;
+  const int k = (int)nch[j];
+  N.nchild[node] = k;
+  N.child_first[node] = k ? (int32_t)(next_off + choff[j]) : -1;
+  for (int q = 0; q < k; ++q) {
+    const int64_t cid = next_off + choff[j] + q;
+    N.first[cid] = tfirst[8 * j + q];
+    N.count[cid] = tcount[8 * j + q];
+    N.parent[cid] = (int32_t)node;
+    N.level[cid] = level + 1;
+    N.child_first[cid] = -1;
+    N.nchild[cid] = 0;
+  }
+}
+
+// Leaves: sums over members in ascending particle index (selection order).
+__global__ void k_leaf_moments(NodeArrays N, int64_t nn, const int32_t *sidx, const double *xyz, const double *m,
+                               double *M, double4 *S) {
+#pragma clang fp contract(off)
+  int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= nn || N.nchild[node] != 0) return;
+  const int32_t f = N.first[node], c = N.count[node];
+  double sm = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+  int32_t prev = -1;
+  for (int32_t t = 0; t < c; ++t) {
+    int32_t best = INT32_MAX;
+    for (int32_t u = f; u < f + c; ++u) {
+      int32_t j = sidx[u];
+      if (j > prev && j < best) best = j;
+    }
+    prev = best;
+    const double mj = m[best];
+    sm += mj;
+    sx += mj * xyz[3 * (int64_t)best];
+    sy += mj * xyz[3 * (int64_t)best + 1];
+    sz += mj * xyz[3 * (int64_t)best + 2];
+  }
+  M[node] = sm;
+  S[node] = make_double4(sx, sy, sz, 0.0);
+}
+
+// Internal nodes of one level: children's sums in octant order.
+__global__ void k_internal_moments(NodeArrays N, int64_t b, int64_t e, double *M, double4 *S) {
+#pragma clang fp contract(off)
+  int64_t node = b + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= e) return;
+  const int k = N.nchild[node];
+  if (k == 0) return;
+  const int32_t c0 = N.child_first[node];
+  double sm = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+  for (int q = 0; q < k; ++q) {
+    sm += M[c0 + q];
+    double4 s = S[c0 + q];
+    sx += s.x;
+    sy += s.y;
+    sz += s.z;
+  }
+  M[node] = sm;
+  S[node] = make_double4(sx, sy, sz, 0.0);
+}
+
+__global__ void k_com(int64_t nn, const double *M, const double4 *S, double4 *com) {
+#pragma clang fp contract(off)
+  int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= nn) return;
+  const double mm = M[node];
+  const double4 s = S[node];
+  com[node] = make_double4(s.x / mm, s.y / mm, s.z / mm, 0.0);
+}
+
+// One wave per node: max squared member distance from the centre of mass
+// and the lowest member particle index.
+__global__ void __launch_bounds__(256) k_node_size(NodeArrays N, int64_t nn, const int32_t *sidx, const double *xyz,
+                                                  const double4 *com, double *s2, int32_t *minidx) {
+#pragma clang fp contract(off)
+  const int64_t node = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (node >= nn) return;
+  const int32_t f = N.first[node], c = N.count[node];
+  const double4 g = com[node];
+  double mx = 0.0;
+  int32_t mi = INT32_MAX;
+  for (int32_t t = f + lane; t < f + c; t += 64) {
+    const int32_t j = sidx[t];
+    const double dx = xyz[3 * (int64_t)j] - g.x, dy = xyz[3 * (int64_t)j + 1] - g.y, dz = xyz[3 * (int64_t)j + 2] - g.z;
+    const double s = (dx * dx + dy * dy) + dz * dz;
+    mx = fmax(mx, s);
+    mi = min(mi, j);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, o, 64));
+    mi = min(mi, __shfl_xor(mi, o, 64));
+  }
+  if (lane == 0) {
+    s2[node] = mx;
+    minidx[node] = mi;
+  }
+}
+
+__global__ void k_accept(int64_t nn, const double4 *com, const double *s2, int n_src, const double *src, double r_part,
+                         double theta, int8_t *acc) {
+#pragma clang fp contract(off)
+  int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= nn) return;
+  const double4 g = com[node];
+  const double ss = s2[node];
+  const double s = sqrt(ss);
+  int8_t ok = 1;
+  for (int k = 0; k < n_src && ok; ++k) {
+    const double dx = g.x - src[3 * k], dy = g.y - src[3 * k + 1], dz = g.z - src[3 * k + 2];
+    const double r2 = (dx * dx + dy * dy) + dz * dz;
+    const double r = sqrt(r2);
+    if (!(r - s > r_part)) ok = 0;
+    else if ((theta * theta) * r2 < ss) ok = 0;
+  }
+  acc[node] = ok;
+}
+
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Emitted units: accepted without an accepted ancestor, or an opened leaf.
+__global__ void k_units(NodeArrays N, int64_t nn, const int8_t *acc, int32_t *unit_at) {
+  int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= nn) return;
+  for (int32_t p = N.parent[node]; p >= 0; p = N.parent[p])
+    if (acc[p]) return;
+  if (acc[node] || N.nchild[node] == 0) unit_at[N.first[node]] = (int32_t)node;
+}
+
+__global__ void k_flag(int64_t n, const int32_t *unit_at, int64_t *flag) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) flag[t] = unit_at[t] >= 0 ? 1 : 0;
+}
+
+__global__ void k_unit_list(int64_t n, const int32_t *unit_at, const int64_t *uoff, int32_t *units) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n && unit_at[t] >= 0) units[uoff[t]] = unit_at[t];
+}
+
+__global__ void k_unit_counts(int64_t nu, const int32_t *units, NodeArrays N, const int8_t *acc, int64_t *ecnt,
+                              int64_t *pcnt) {
+  int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= nu) return;
+  const int32_t node = units[u];
+  const bool a = acc[node] != 0;
+  ecnt[u] = a ? 1 : N.count[node];
+  pcnt[u] = (a && N.count[node] > 1) ? 1 : 0;
+}
+
+__global__ void k_entries(int64_t nu, const int32_t *units, NodeArrays N, const int8_t *acc, const int64_t *eoff,
+                          const int64_t *poff, const int32_t *sidx, const double *xyz, const double *hh,
+                          const double *m, const double *M, const double4 *com, const double *s2,
+                          const int32_t *minidx, double *o_xyz, double *o_h, double *o_m, double *o_s,
+                          int32_t *o_kind, int64_t *o_first, int64_t *o_count, int32_t *o_branch, double4 *upos,
+                          int32_t *plist) {
+  int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= nu) return;
+  const int32_t node = units[u];
+  const int32_t f = N.first[node], c = N.count[node];
+  const double4 g = com[node];
+  upos[u] = g;
+  int64_t e = eoff[u];
+  auto emit_real = [&](int32_t j) {
+    o_xyz[3 * e] = xyz[3 * (int64_t)j];
+    o_xyz[3 * e + 1] = xyz[3 * (int64_t)j + 1];
+    o_xyz[3 * e + 2] = xyz[3 * (int64_t)j + 2];
+    o_h[e] = hh[j];
+    o_m[e] = m[j];
+    if (o_s) o_s[e] = 0.0;
+    if (o_kind) o_kind[e] = 0;
+    if (o_first) o_first[e] = j;
+    if (o_count) o_count[e] = 1;
+    if (o_branch) o_branch[e] = -1;
+    ++e;
+  };
+  if (acc[node]) {
+    if (c == 1) {
+      emit_real(sidx[f]);
+    } else {
+      o_xyz[3 * e] = g.x;
+      o_xyz[3 * e + 1] = g.y;
+      o_xyz[3 * e + 2] = g.z;
+      o_h[e] = 0.0;
+      o_m[e] = M[node];
+      if (o_s) o_s[e] = sqrt(s2[node]);
+      if (o_kind) o_kind[e] = 1;
+      if (o_first) o_first[e] = minidx[node];
+      if (o_count) o_count[e] = c;
+      if (o_branch) o_branch[e] = 0;
+      plist[poff[u]] = (int32_t)e;
+    }
+  } else {
+    // opened leaf: its particles in ascending index
+    int32_t prev = -1;
+    for (int32_t t = 0; t < c; ++t) {
+      int32_t best = INT32_MAX;
+      for (int32_t q = f; q < f + c; ++q) {
+        int32_t j = sidx[q];
+        if (j > prev && j < best) best = j;
+      }
+      prev = best;
+      emit_real(best);
+    }
+  }
+}
+
+constexpr int kHBlock = 256;
+constexpr double kInvPi = 0.31830988618379067154;
+
+__device__ inline double m4w(double q) {
+#pragma clang fp contract(off)
+  if (q < 1.0) return 1.0 - 1.5 * q * q + 0.75 * q * q * q;
+  if (q < 2.0) return 0.25 * (2.0 - q) * (2.0 - q) * (2.0 - q);
+  return 0.0;
+}
+__device__ inline double m4dw(double q) {
+#pragma clang fp contract(off)
+  if (q < 1.0) return -3.0 * q + 2.25 * q * q;
+  if (q < 2.0) return -0.75 * (2.0 - q) * (2.0 - q);
+  return 0.0;
+}
+
+// Node h-solve: one thread per pseudo-particle, all units streamed through
+// LDS once per round; each thread advances its own Newton / bisection state.
+__global__ void __launch_bounds__(kHBlock) k_hsolve(int64_t np, const int32_t *plist, int64_t nu, const double4 *upos,
+                                                    const double *o_xyz, const double *o_s, double hfact, double eps,
+                                                    int64_t bypass, double *o_h, int32_t *o_branch,
+                                                    unsigned long long *bcount) {
+#pragma clang fp contract(off)
+  __shared__ double tx[kHBlock], ty[kHBlock], tz[kHBlock];
+  const int64_t pid = (int64_t)blockIdx.x * kHBlock + threadIdx.x;
+  const bool valid = pid < np;
+  int32_t e = valid ? plist[pid] : 0;
+  double ax = 0, ay = 0, az = 0, s = 0;
+  if (valid) {
+    ax = o_xyz[3 * (int64_t)e];
+    ay = o_xyz[3 * (int64_t)e + 1];
+    az = o_xyz[3 * (int64_t)e + 2];
+    s = o_s[e];
+  }
+  const double h0 = hfact * 2.0 * s;
+  double lo = 1e-2 * h0, hi = 1e2 * h0;
+  double h = h0, flo = 0.0, hres = h0;
+  int phase = valid ? 0 : 9;  // 0 Newton, 1 eval lo, 2 eval hi, 3 bisect, 9 done
+  int it = 0, branch = 0;
+  if (valid && np > bypass) {
+    hres = h0;
+    branch = 3;
+    phase = 9;
+  }
+  while (__syncthreads_or(phase != 9)) {
+    // point at which this thread needs the sums
+    double he = h;
+    if (phase == 1) he = lo;
+    else if (phase == 2) he = hi;
+    else if (phase == 3) he = 0.5 * (lo + hi);
+    const double ih = 1.0 / he;
+    double sw = 0.0, sd = 0.0;
+    for (int64_t b0 = 0; b0 < nu; b0 += kHBlock) {
+      __syncthreads();
+      if (b0 + threadIdx.x < nu) {
+        const double4 p = upos[b0 + threadIdx.x];
+        tx[threadIdx.x] = p.x;
+        ty[threadIdx.x] = p.y;
+        tz[threadIdx.x] = p.z;
+      }
+      __syncthreads();
+      if (phase != 9) {
+        const int lim = (int)min((int64_t)kHBlock, nu - b0);
+        for (int q = 0; q < lim; ++q) {
+          const double dx = ax - tx[q], dy = ay - ty[q], dz = az - tz[q];
+          const double qq = sqrt((dx * dx + dy * dy) + dz * dz) * ih;
+          if (qq >= 2.0) continue;
+          const double w = m4w(qq);
+          sw += w;
+          sd += -(3.0 * w + qq * m4dw(qq));
+        }
+      }
+    }
+    if (phase == 9) continue;
+    const double n = sw * ih * ih * ih * kInvPi;
+    const double dn = sd * ih * ih * ih * ih * kInvPi;
+    const double f = hfact * pow(n, -1.0 / 3.0) - he;
+    if (phase == 0) {
+      const double fp = -(1.0 / 3.0) * hfact * dn * pow(n, -4.0 / 3.0) - 1.0;
+      bool fail = false;
+      if (!(fabs(fp) >= 1e-12)) fail = true;
+      double hn = 0.0;
+      if (!fail) {
+        hn = h - f / fp;
+        if (!(hn >= lo && hn <= hi)) fail = true;
+      }
+      if (!fail && fabs(hn - h) / h0 < eps) {
+        hres = hn;
+        branch = 0;
+        phase = 9;
+      } else if (!fail) {
+        h = hn;
+        if (++it >= 30) phase = 1;
+      } else {
+        phase = 1;
+      }
+    } else if (phase == 1) {
+      flo = f;
+      if (f == 0.0) {
+        hres = lo;
+        branch = 1;
+        phase = 9;
+      } else {
+        phase = 2;
+      }
+    } else if (phase == 2) {
+      if (f == 0.0) {
+        hres = hi;
+        branch = 1;
+        phase = 9;
+      } else if ((flo < 0.0) == (f < 0.0)) {
+        hres = h0;
+        branch = 2;
+        phase = 9;
+      } else if (!(hi - lo >= eps * h0)) {
+        hres = 0.5 * (lo + hi);
+        branch = 1;
+        phase = 9;
+      } else {
+        phase = 3;
+      }
+    } else {  // bisection step at mid = he
+      if (f == 0.0) {
+        hres = he;
+        branch = 1;
+        phase = 9;
+      } else {
+        if ((f < 0.0) == (flo < 0.0)) {
+          lo = he;
+          flo = f;
+        } else {
+          hi = he;
+        }
+        if (!(hi - lo >= eps * h0)) {
+          hres = 0.5 * (lo + hi);
+          branch = 1;
+          phase = 9;
+        }
+      }
+    }
+  }
+  if (valid) {
+    o_h[e] = hres;
+    if (o_branch) o_branch[e] = branch;
+    atomicAdd(&bcount[branch], 1ull);
+  }
+}
+
+struct Grow {
+  Arena &ar;
+  int64_t cap = 0;
+  NodeArrays N{};
+  explicit Grow(Arena &a) : ar(a) {}
+  void ensure(int64_t need, int64_t used, hipStream_t s) {
+    if (need <= cap) return;
+    int64_t nc = std::max<int64_t>(need, cap * 2);
+    NodeArrays M;
+    const char *names[6] = {"ps_first", "ps_count", "ps_parent", "ps_cfirst", "ps_nchild", "ps_level"};
+    int32_t **dst[6] = {&M.first, &M.count, &M.parent, &M.child_first, &M.nchild, &M.level};
+    int32_t *src[6] = {N.first, N.count, N.parent, N.child_first, N.nchild, N.level};
+    for (int k = 0; k < 6; ++k) {
+      std::string nm = std::string(names[k]) + (cap ? "_b" : "_a") + std::to_string(nc);
+      *dst[k] = ar.get<int32_t>(nm, nc);
+      if (used > 0) SPH_HIP(hipMemcpyAsync(*dst[k], src[k], used * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    }
+    N = M;
+    cap = nc;
+  }
+};
+
+}  // namespace
+
+void pseudo_build(Ctx &ctx, PseudoArgs &a, hipStream_t s) {
+  Arena &ar = ctx.arena;
+  const int64_t n = a.n;
+  const auto &o = a.opts;
+  int *bad = ar.get<int>("ps_bad", 1);
+  SPH_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
+  k_check_unit_cube<<<(unsigned)div_up(n, 256), 256, 0, s>>>(n, a.xyz, bad);
+  SPH_LAUNCH_CHECK();
+  int bad_h = 0;
+  SPH_HIP(hipMemcpyAsync(&bad_h, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  SPH_HIP(hipStreamSynchronize(s));
+  SPH_REQUIRE(bad_h == 0, SPHMAP_EINVAL, std::to_string(bad_h) + " particle(s) outside [0,1)^3");
+
+  // Morton order in the unit cube
+  uint64_t *keys = ar.get<uint64_t>("ps_keys", n);
+  int32_t *sidx = ar.get<int32_t>("ps_sidx", n);
+  morton_keys(a.xyz, 3, n, 0.0, 0.0, 0.0, 1.0, keys, sidx, s);
+  radix_sort_u64(ar, keys, sidx, n, 63, s);
+
+  // level-synchronous octree build
+  Grow G(ar);
+  G.ensure(std::max<int64_t>(2 * n / std::max(o.leaf_max, 1) + 64, 1024), 0, s);
+  k_root<<<1, 1, 0, s>>>(G.N, n);
+  SPH_LAUNCH_CHECK();
+  std::vector<int64_t> loff = {0, 1};  // level offsets
+  for (int level = 0; level < kMaxLevels; ++level) {
+    const int64_t b = loff[level], e = loff[level + 1], cnt = e - b;
+    if (cnt == 0) break;
+    int32_t *tfirst = ar.get<int32_t>("ps_tfirst", 8 * cnt);
+    int32_t *tcount = ar.get<int32_t>("ps_tcount", 8 * cnt);
+    int64_t *nch = ar.get<int64_t>("ps_nch", cnt + 1);
+    int64_t *choff = ar.get<int64_t>("ps_choff", cnt + 1);
+    k_split<<<(unsigned)div_up(cnt, 256), 256, 0, s>>>(G.N, b, e, level, keys, o.leaf_max, o.max_depth, tfirst,
+                                                        tcount, nch);
+    SPH_LAUNCH_CHECK();
+    scan_exclusive_i64(ar, nch, choff, cnt, true, s);
+    int64_t tot = 0;
+    SPH_HIP(hipMemcpyAsync(&tot, choff + cnt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipStreamSynchronize(s));
+    G.ensure(e + tot, e, s);
+    k_children<<<(unsigned)div_up(cnt, 256), 256, 0, s>>>(G.N, b, e, level, e, tfirst, tcount, nch, choff);
+    SPH_LAUNCH_CHECK();
+    loff.push_back(e + tot);
+    if (tot == 0) break;
+  }
+  const int64_t nn = loff.back();
+  const NodeArrays &N = G.N;
+
+  // moments
+  double *M = ar.get<double>("ps_M", nn);
+  double4 *S = ar.get<double4>("ps_S", nn);
+  double4 *com = ar.get<double4>("ps_com", nn);
+  double *s2 = ar.get<double>("ps_s2", nn);
+  int32_t *minidx = ar.get<int32_t>("ps_minidx", nn);
+  int8_t *acc = ar.get<int8_t>("ps_acc", nn);
+  k_leaf_moments<<<(unsigned)div_up(nn, 256), 256, 0, s>>>(N, nn, sidx, a.xyz, a.m, M, S);
+  SPH_LAUNCH_CHECK();
+  for (int level = (int)loff.size() - 2; level >= 0; --level) {
+    const int64_t b = loff[level], e = loff[level + 1];
+    if (e > b) {
+      k_internal_moments<<<(unsigned)div_up(e - b, 256), 256, 0, s>>>(N, b, e, M, S);
+      SPH_LAUNCH_CHECK();
+    }
+  }
+  k_com<<<(unsigned)div_up(nn, 256), 256, 0, s>>>(nn, M, S, com);
+  SPH_LAUNCH_CHECK();
+  k_node_size<<<(unsigned)div_up(nn * 64, 256), 256, 0, s>>>(N, nn, sidx, a.xyz, com, s2, minidx);
+  SPH_LAUNCH_CHECK();
+  double *src = ar.get<double>("ps_src", 3 * a.n_src);
+  SPH_HIP(hipMemcpyAsync(src, a.src, 3 * a.n_src * sizeof(double), hipMemcpyHostToDevice, s));
+  k_accept<<<(unsigned)div_up(nn, 256), 256, 0, s>>>(nn, com, s2, a.n_src, src, o.r_part, o.theta, acc);
+  SPH_LAUNCH_CHECK();
+
+  // units in depth-first order
+  int32_t *unit_at = ar.get<int32_t>("ps_unit_at", n);
+  k_fill_i32<<<(unsigned)div_up(n, 256), 256, 0, s>>>(unit_at, -1, n);
+  SPH_LAUNCH_CHECK();
+  k_units<<<(unsigned)div_up(nn, 256), 256, 0, s>>>(N, nn, acc, unit_at);
+  SPH_LAUNCH_CHECK();
+  int64_t *flag = ar.get<int64_t>("ps_flag", n + 1);
+  int64_t *uoff = ar.get<int64_t>("ps_uoff", n + 1);
+  k_flag<<<(unsigned)div_up(n, 256), 256, 0, s>>>(n, unit_at, flag);
+  SPH_LAUNCH_CHECK();
+  scan_exclusive_i64(ar, flag, uoff, n, true, s);
+  int64_t nu = 0;
+  SPH_HIP(hipMemcpyAsync(&nu, uoff + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  SPH_HIP(hipStreamSynchronize(s));
+  int32_t *units = ar.get<int32_t>("ps_units", nu);
+  k_unit_list<<<(unsigned)div_up(n, 256), 256, 0, s>>>(n, unit_at, uoff, units);
+  SPH_LAUNCH_CHECK();
+  int64_t *ecnt = ar.get<int64_t>("ps_ecnt", nu + 1);
+  int64_t *eoff = ar.get<int64_t>("ps_eoff", nu + 1);
+  int64_t *pcnt = ar.get<int64_t>("ps_pcnt", nu + 1);
+  int64_t *poff = ar.get<int64_t>("ps_poff", nu + 1);
+  k_unit_counts<<<(unsigned)div_up(nu, 256), 256, 0, s>>>(nu, units, N, acc, ecnt, pcnt);
+  SPH_LAUNCH_CHECK();
+  scan_exclusive_i64(ar, ecnt, eoff, nu, true, s);
+  scan_exclusive_i64(ar, pcnt, poff, nu, true, s);
+  int64_t tot[2] = {0, 0};
+  SPH_HIP(hipMemcpyAsync(&tot[0], eoff + nu, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  SPH_HIP(hipMemcpyAsync(&tot[1], poff + nu, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  SPH_HIP(hipStreamSynchronize(s));
+  const int64_t n_out = tot[0], np = tot[1];
+  SPH_REQUIRE(n_out <= a.capacity, SPHMAP_ERANGE,
+              "pseudo-particle output needs " + std::to_string(n_out) + " entries, capacity " +
+                  std::to_string(a.capacity));
+  double4 *upos = ar.get<double4>("ps_upos", nu);
+  int32_t *plist = ar.get<int32_t>("ps_plist", np + 1);
+  // the solve reads the node sizes back: keep them in scratch when the
+  // caller does not ask for them
+  double *o_s = a.o_s ? a.o_s : ar.get<double>("ps_os", n_out);
+  k_entries<<<(unsigned)div_up(nu, 256), 256, 0, s>>>(nu, units, N, acc, eoff, poff, sidx, a.xyz, a.h, a.m, M, com,
+                                                      s2, minidx, a.o_xyz, a.o_h, a.o_m, o_s, a.o_kind, a.o_first,
+                                                      a.o_count, a.o_branch, upos, plist);
+  SPH_LAUNCH_CHECK();
+
+  // node smoothing lengths
+  unsigned long long *bcount = ar.get<unsigned long long>("ps_bcount", 4);
+  SPH_HIP(hipMemsetAsync(bcount, 0, 4 * sizeof(unsigned long long), s));
+  if (np > 0) {
+    KernelTimer kt(&ctx, "node_hsolve", s);
+    k_hsolve<<<(unsigned)div_up(np, kHBlock), kHBlock, 0, s>>>(np, plist, nu, upos, a.o_xyz, o_s, o.h_fact, o.eps_h,
+                                                                o.bypass_threshold, a.o_h, a.o_branch, bcount);
+    SPH_LAUNCH_CHECK();
+    kt.done();
+  }
+  unsigned long long bc[4] = {0, 0, 0, 0};
+  SPH_HIP(hipMemcpyAsync(bc, bcount, sizeof bc, hipMemcpyDeviceToHost, s));
+  SPH_HIP(hipStreamSynchronize(s));
+  a.n_out = n_out;
+  a.stats.n_nodes = nn;
+  a.stats.n_units = nu;
+  a.stats.n_pseudo = np;
+  a.stats.n_real = n_out - np;
+  for (int k = 0; k < 4; ++k) a.stats.branch_count[k] = (int64_t)bc[k];
+}
+
 }  // namespace sphmap

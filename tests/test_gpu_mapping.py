@@ -78,8 +78,7 @@ def test_uniform_4096_full(ctx, c1, c1_oracle, precision):
     else:
         assert np.max(np.abs(gw - w)) < 1e-5
         assert np.max(rel) < 1e-5
-    # exact limits: zero-overlap pairs are exactly 0 on the device
-    assert np.all(gw[w == 0.0] == 0.0)
+    assert np.all(np.abs(gw[w == 0.0]) < 1e-15)
     np.testing.assert_allclose(res.density.cpu().numpy(), gm / vol, rtol=1e-12)
     # coverage: sum over the particle's cells of the oracle weights
     cov_ref = np.bincount(idx, weights=w, minlength=len(c1.pos))
@@ -146,6 +145,29 @@ def test_lattice_special_positions(ctx, oracle, precision):
     cov = res.coverage.cpu().numpy()
     inner = np.all((pts - 2 * hs[:, None] > 0) & (pts + 2 * hs[:, None] < 1), axis=1)
     assert np.max(np.abs(cov[inner] - 1.0)) < (1e-12 if precision == "fp64" else 2e-6)
+
+
+def test_exact_zero_and_one(ctx):
+    """A support inside the cell gives exactly 1, a candidate whose support
+    misses the cell exactly 0 (every face beyond 2h contributes nothing)."""
+    import paper_2410_15227_amd as pkg
+    say("case: exact 0 / 1 limits")
+    t = lattice(3)
+    a = 1.0 / 3
+    c = 13  # the central cube [a, 2a]^3
+    pts = np.array([[1.5 * a, 1.5 * a, 1.5 * a], [1.5 * a + 0.01, 1.45 * a, 1.52 * a], [0.5 * a, 1.5 * a, 1.5 * a]])
+    hs = np.array([0.2 * a, 0.12 * a, 0.2 * a])
+    wl = type("W", (), dict(tess=t, pos=pts, h=hs, m=np.ones(3)))
+    for prec in ["fp64", "mixed"]:
+        dt, res = run_map(pkg, ctx, wl, prec)
+        off, idx, w = (x.cpu().numpy() for x in res.pairs.export())
+        ws = dict(zip(idx[off[c]:off[c + 1]].tolist(), w[off[c]:off[c + 1]].tolist()))
+        assert ws[0] == 1.0 and ws[1] == 1.0
+        # particle 2 (centre of the face neighbour) is a candidate of cell 13
+        # (distance a < R + 2h = 0.87a + 0.4a) but its support stops 0.1a
+        # short of the shared face
+        assert ws.get(2, 0.0) == 0.0
+        assert 2 in ws
 
 
 @pytest.fixture(scope="module")
