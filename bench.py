@@ -111,7 +111,7 @@ def main():
     ctx.set_timing(False)
     k_ms, k_n = ctx.kernel_time("exact_integral")
     other = {name: ctx.kernel_time(name) for name in ["pair_count", "pair_fill", "transpose", "cell_reduce",
-                                                     "reverse"]}
+                                                     "reverse", "exact_redo", "flat_reset"]}
     ms_step = el * 1e3 / args.steps
     value = n_pairs * args.steps / el
 

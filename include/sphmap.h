@@ -82,7 +82,8 @@ const char *sphmap_last_error(const sphmap_ctx *ctx);
  *                                   cyclic convex polygon in EITHER
  *                                   orientation (oriented internally so its
  *                                   normal points away from the generator)
- * Faces of zero area are accepted and contribute nothing.  All arrays are
+ * Faces of zero area are accepted and contribute nothing; a face may have at
+ * most 128 vertices.  All arrays are
  * copied; the host memory may be reused after return.  The preprocessing
  * (face planes, volumes, bounding radii) is enqueued on `stream`.
  * Errors: EINVAL for inconsistent offsets or out-of-range indices.

@@ -99,8 +99,10 @@ int sphmap_tess_upload(sphmap_ctx *ctx, int64_t n_cells, int64_t n_faces, int64_
     for (int64_t c = 0; c < n_cells; ++c)
       SPH_REQUIRE(h_cell_face_off[c + 1] >= h_cell_face_off[c], SPHMAP_EINVAL, "cell_face_off not non-decreasing");
     SPH_REQUIRE(h_face_vtx_off[0] == 0, SPHMAP_EINVAL, "face_vtx_off must start at 0");
-    for (int64_t f = 0; f < n_faces; ++f)
+    for (int64_t f = 0; f < n_faces; ++f) {
       SPH_REQUIRE(h_face_vtx_off[f + 1] >= h_face_vtx_off[f], SPHMAP_EINVAL, "face_vtx_off not non-decreasing");
+      SPH_REQUIRE(h_face_vtx_off[f + 1] - h_face_vtx_off[f] <= 128, SPHMAP_EINVAL, "a face has more than 128 vertices");
+    }
     const int64_t FV = h_face_vtx_off[n_faces];
     for (int64_t k = 0; k < FV; ++k)
       SPH_REQUIRE(h_face_vtx[k] >= 0 && h_face_vtx[k] < n_vertices, SPHMAP_EINVAL, "face vertex index out of range");

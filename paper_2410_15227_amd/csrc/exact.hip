@@ -38,6 +38,10 @@
 //     every accumulation in binary64.  Edges whose foot point nearly touches
 //     the edge line or whose face plane nearly touches the particle (p or |d|
 //     below 1e-4 h) are recomputed from binary64 geometry.
+#include <algorithm>
+#include <cstdlib>
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace sphmap {
@@ -94,6 +98,10 @@ __device__ inline double dH(double ad) {
 // binary64 with the math library
 struct Math64 {
   static __device__ inline double atanq(double y, double x) { return atan2(y, x); }  // x > 0
+  // angle subtended at the foot point by the edge [tA, tB] at distance p > 0
+  static __device__ inline double span(double p, double tA, double tB) {
+    return atan2(p * (tB - tA), fma(tA, tB, p * p));
+  }
   static __device__ inline double asinh_(double z) { return asinh(z); }
   static __device__ inline double sqrt_(double v) { return sqrt(v); }
   static __device__ inline double rcp(double v) { return 1.0 / v; }
@@ -165,6 +173,10 @@ __device__ inline double asinh_mixed(double z) {
 }
 struct MathMixed {
   static __device__ inline double atanq(double y, double x) { return atan_mixed(y, x); }
+  static __device__ inline double span(double p, double tA, double tB) {
+    const double y = p * (tB - tA), x = fma(tA, tB, p * p);  // y > 0
+    return x > 0.0 ? atan_mixed(y, x) : (x < 0.0 ? kPi - atan_mixed(y, -x) : kHalfPi);
+  }
   static __device__ inline double asinh_(double z) { return asinh_mixed(z); }
   static __device__ inline double sqrt_(double v) { return sqrt_mixed(v); }
   static __device__ inline double rcp(double v) { return rcp_mixed(v); }
@@ -181,13 +193,16 @@ struct EdgeCount {
 template <class M>
 __device__ double edge_term(double ad, double p, double tA, double tB, double dh, bool &integ, EdgeCount &cnt) {
   const double a2 = ad * ad + p * p;
-  integ = false;
+  const double r2 = 4.0 - a2;
+  integ = r2 > 0.0 && (tA < 0.0 || tA * tA < r2) && (tB > 0.0 || tB * tB < r2);
   const double phiA = M::atanq(tA, p), phiB = M::atanq(tB, p);
-  if (a2 >= 4.0) return -dh * (phiB - phiA);
-  const double t2 = M::sqrt_(4.0 - a2);
+  if (!integ) return -dh * (phiB - phiA);
+  const double t2 = M::sqrt_(r2);
   const double ca = fmin(fmax(tA, -t2), t2), cb = fmin(fmax(tB, -t2), t2);
-  if (!(ca < cb)) return -dh * (phiB - phiA);
-  integ = true;
+  if (!(ca < cb)) {
+    integ = false;
+    return -dh * (phiB - phiA);
+  }
   Coef c0, c1;
   edge_coefs(ad, p, c0, c1);
   const double a = M::sqrt_(a2);
@@ -350,14 +365,10 @@ __global__ void __launch_bounds__(256) k_exact_fp64(int64_t P, const int32_t *pa
 // ---------------------------------------------------------- mixed kernel
 constexpr float kDegenerate = 1e-4f;  // p or |d| below this (units of h): binary64 edge
 
-__global__ void __launch_bounds__(256) k_exact_mixed(int64_t P, const int32_t *pair_c, const int32_t *pair_p,
-                                                    const double *xyz, const double *hh, const double *gen,
-                                                    const int64_t *cfo, const int64_t *fvo, const double4 *fplane,
-                                                    const float4 *fplane32, const double4 *fsphere,
-                                                    const double *fvpos, const float4 *fvpos32, double *w_out,
-                                                    int64_t *counters) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= P) return;
+__device__ inline void pair_mixed(int64_t k, const int32_t *pair_c, const int32_t *pair_p, const double *xyz,
+                                  const double *hh, const double *gen, const int64_t *cfo, const int64_t *fvo,
+                                  const double4 *fplane, const float4 *fplane32, const double4 *fsphere,
+                                  const double *fvpos, const float4 *fvpos32, double *w_out, int64_t *counters) {
   const int64_t c = pair_c[k];
   const int64_t i = pair_p[k];
   const double h = hh[i];
@@ -469,6 +480,324 @@ __global__ void __launch_bounds__(256) k_exact_mixed(int64_t P, const int32_t *p
   if (counters) flush_counters(counters, f1 - f0, K);
 }
 
+__global__ void __launch_bounds__(256) k_exact_mixed(int64_t P, const int32_t *pair_c, const int32_t *pair_p,
+                                                    const double *xyz, const double *hh, const double *gen,
+                                                    const int64_t *cfo, const int64_t *fvo, const double4 *fplane,
+                                                    const float4 *fplane32, const double4 *fsphere,
+                                                    const double *fvpos, const float4 *fvpos32, double *w_out,
+                                                    int64_t *counters) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < P)
+    pair_mixed(k, pair_c, pair_p, xyz, hh, gen, cfo, fvo, fplane, fplane32, fsphere, fvpos, fvpos32, w_out, counters);
+}
+
+// the same over a device-side list of pairs (its length read on the device)
+__global__ void __launch_bounds__(256) k_exact_mixed_list(const int32_t *list, const int32_t *n_list,
+                                                         const int32_t *pair_c, const int32_t *pair_p,
+                                                         const double *xyz, const double *hh, const double *gen,
+                                                         const int64_t *cfo, const int64_t *fvo,
+                                                         const double4 *fplane, const float4 *fplane32,
+                                                         const double4 *fsphere, const double *fvpos,
+                                                         const float4 *fvpos32, double *w_out, int64_t *counters) {
+  const int n = *n_list;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
+    pair_mixed(list[t], pair_c, pair_p, xyz, hh, gen, cfo, fvo, fplane, fplane32, fsphere, fvpos, fvpos32, w_out,
+               counters);
+}
+
+// ------------------------------------------------------- wave helpers
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline int wave_scan_excl(int v, int lane) {
+  int x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  return x - v;
+}
+
+// binary64 geometry of edge (e, e1) of a face about the generator, particle at xr
+__device__ inline bool edge_geo64(const double4 pl, double dist, double ih, double xr0, double xr1, double xr2,
+                                  const double *V, int e, int e1, double &p, double &tA, double &tB) {
+  const double P0x = xr0 + dist * pl.x, P0y = xr1 + dist * pl.y, P0z = xr2 + dist * pl.z;
+  const double Ax = V[3 * e], Ay = V[3 * e + 1], Az = V[3 * e + 2];
+  const double Bx = V[3 * e1], By = V[3 * e1 + 1], Bz = V[3 * e1 + 2];
+  const double bx = Bx - Ax, by = By - Ay, bz = Bz - Az;
+  const double len2 = bx * bx + by * by + bz * bz;
+  if (!(len2 > 0.0)) return false;
+  const double il = 1.0 / sqrt(len2);
+  const double ex = bx * il, ey = by * il, ez = bz * il;
+  const double mx = pl.y * ez - pl.z * ey, my = pl.z * ex - pl.x * ez, mz = pl.x * ey - pl.y * ex;
+  p = ((P0x - Ax) * mx + (P0y - Ay) * my + (P0z - Az) * mz) * ih;
+  tA = ((Ax - P0x) * ex + (Ay - P0y) * ey + (Az - P0z) * ez) * ih;
+  tB = ((Bx - P0x) * ex + (By - P0y) * ey + (Bz - P0z) * ez) * ih;
+  return true;
+}
+
+// ------------------------------------------ two-phase wave kernel (mixed)
+// The closed form of an edge within 2h is most of the work, and in a
+// one-pair-per-lane loop the lanes of a wave reach it on different faces and
+// edges.  Here a wavefront takes 64 consecutive pairs (one per lane) from a
+// work counter and runs two phases over a private scratch region:
+//   A: each lane walks its pair's faces and edges, adds the angle terms
+//      -dh * (phi_B - phi_A) of every edge, and stores each edge within 2h
+//      as a float4 item (signed |d|, signed p, tau_A, tau_B) in its own slice
+//      of the region: edges whose clipped range crosses U = 1 from the front,
+//      the others from the back;
+//   B: the wave evaluates the items of all 64 slices 64 at a time, crossing
+//      edges first, so that the lanes of a pass run the same code, and
+//      writes each result over its item.
+// A lane pauses before a face whose edges might overflow its slice; the
+// wave then runs phase B and the paused lanes resume (a round).  Each lane
+// adds its own results in its own slice order, round after round, so a
+// weight depends on its pair alone, never on the pairs sharing the wave.
+// Pairs that need binary64 geometry are listed and left to the
+// one-pair-per-lane kernel.
+constexpr int kFlatWaves = 4;  // wavefronts per workgroup
+constexpr int kFlatCap = 64;   // items per lane slice
+
+__global__ void k_zero_i32(int32_t *p, int n) {
+  const int t = threadIdx.x;
+  if (t < n) p[t] = 0;
+}
+
+// F(cb) - F(ca) of one edge within 2h (p > 0, tA < tB): the part of the fan
+// integral that is not the angle term.
+template <class M>
+__device__ inline double edge_fan(double ad, double p, double tA, double tB, EdgeCount &cnt) {
+  const double a2 = ad * ad + p * p;
+  const double t2 = M::sqrt_(4.0 - a2);
+  const double ca = fmin(fmax(tA, -t2), t2), cb = fmin(fmax(tB, -t2), t2);
+  Coef c0, c1;
+  edge_coefs(ad, p, c0, c1);
+  const double a = M::sqrt_(a2);
+  const double ia = M::rcp(a);
+  double t1 = -1.0, D = 0.0;
+  if (a2 < 1.0) {
+    t1 = M::sqrt_(1.0 - a2);
+    // the join constant cancels unless [ca, cb] crosses t = -t1 or t = t1
+    if ((ca < -t1 && cb > -t1) || (ca < t1 && cb > t1)) {
+      const double ph = M::atanq(t1, p), be = M::atanq(ad * t1, p), Lz = M::asinh_(t1 * ia);
+      D = coef_eval(c0, ph, be, Lz, t1, 1.0) - coef_eval(c1, ph, be, Lz, t1, 1.0);
+      ++cnt.n0;
+      ++cnt.n1;
+    }
+  }
+  auto F = [&](double t) -> double {
+    const double at = fabs(t);
+    const double U = (at == t2) ? 2.0 : M::sqrt_(a2 + t * t);
+    const double phi = M::atanq(t, p), be = M::atanq(ad * t, p * U), Lz = M::asinh_(t * ia);
+    if (at <= t1) {
+      ++cnt.n0;
+      return coef_eval(c0, phi, be, Lz, t, U);
+    }
+    ++cnt.n1;
+    return coef_eval(c1, phi, be, Lz, t, U) + copysign(D, t);
+  };
+  return F(cb) - F(ca);
+}
+
+__device__ inline double item_value(const float4 it, EdgeCount &cnt) {
+  const double v = edge_fan<MathMixed>((double)fabsf(it.x), (double)fabsf(it.y), (double)it.z, (double)it.w, cnt);
+  return ((it.x < 0.0f) != (it.y < 0.0f)) ? -v : v;
+}
+
+__device__ inline void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+template <bool kCount>
+__global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_flat(
+    int64_t P, const int32_t *pair_c, const int32_t *pair_p, const double *xyz, const double *hh, const double *gen,
+    const int64_t *cfo, const int64_t *fvo, const double4 *fplane, const float4 *fplane32, const double4 *fsphere,
+    const float4 *fvpos32, double *w_out, int64_t *counters, float4 *scratch, int cap, int32_t *next_chunk,
+    int32_t *redo, int32_t *n_redo) {
+  __shared__ int s_incl[kFlatWaves][64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  float4 *const region = scratch + ((int64_t)blockIdx.x * kFlatWaves + wid) * 64 * cap;
+  float4 *const mine = region + (int64_t)lane * cap;
+  const int64_t n_chunks = (P + 63) >> 6;
+  Counters K;
+  int64_t nfaces = 0;
+  while (true) {
+    int chunk = 0;
+    if (lane == 0) chunk = atomicAdd(next_chunk, 1);
+    chunk = __shfl(chunk, 0, 64);
+    if (chunk >= n_chunks) break;
+    const int64_t k = (int64_t)chunk * 64 + lane;
+    // per pair, kept across rounds
+    int64_t f = 0, f1 = 0;
+    double light = 0.0, heavy = 0.0;
+    bool inside = true, on_boundary = false, again = false, done = true;
+    if (k < P) {
+      const int64_t c = pair_c[k];
+      f = cfo[c];
+      f1 = cfo[c + 1];
+      nfaces += f1 - f;
+      done = false;
+    }
+    // Rounds: phase A until every lane has finished its faces or paused
+    // before a face whose edges might not fit in its slice, then phase B.
+    while (true) {
+      int nD = 0, nN = 0;
+      if (!done) {
+        const int64_t c = pair_c[k];
+        const int64_t i = pair_p[k];
+        const double h = hh[i];
+        const double ih = 1.0 / h;
+        const float ihf = (float)ih;
+        const double xr0 = xyz[3 * i] - gen[3 * c], xr1 = xyz[3 * i + 1] - gen[3 * c + 1],
+                     xr2 = xyz[3 * i + 2] - gen[3 * c + 2];
+        const float x0 = (float)(xr0 * ih), x1 = (float)(xr1 * ih), x2 = (float)(xr2 * ih);
+        for (; f < f1; ++f) {
+          const double4 pl = fplane[f];
+          if (!(pl.w > 0.0)) continue;
+          const double dist = pl.w - (pl.x * xr0 + pl.y * xr1 + pl.z * xr2);
+          if (dist < 0.0) inside = false;
+          if (dist == 0.0) {
+            on_boundary = true;
+            continue;
+          }
+          if (fabs(dist) >= 2.0 * h) continue;
+          const double4 sp = fsphere[f];
+          const double sx = xr0 - sp.x, sy = xr1 - sp.y, sz = xr2 - sp.z;
+          const double reach = sp.w + 2.0 * h;
+          if (sx * sx + sy * sy + sz * sz >= reach * reach) continue;
+          const int64_t vs = fvo[f];
+          const int nv = (int)(fvo[f + 1] - vs);
+          const double d = dist * ih;
+          if (fabs(d) < kDegenerate || nv > cap) {
+            K.n64 += fabs(d) < kDegenerate ? nv : 0;
+            again = true;
+            break;
+          }
+          if (nD + nN + nv > cap) break;  // pause: flush the slice first
+          ++K.nf_int;
+          // |d| rounded to binary32, like the rest of the face's geometry
+          const float df = (float)d;
+          const double ad = (double)fabsf(df);
+          const double dh = dH(ad);
+          const float4 pf = fplane32[f];
+          const float P0x = x0 + df * pf.x, P0y = x1 + df * pf.y, P0z = x2 + df * pf.z;
+          double sum = 0.0;
+          bool allpos = true, anyzero = false, anyint = false;
+          float4 A = fvpos32[vs];
+          A.x *= ihf;
+          A.y *= ihf;
+          A.z *= ihf;
+          for (int q = 0; q < nv; ++q) {
+            const int q1 = (q + 1 == nv) ? 0 : q + 1;
+            float4 B = fvpos32[vs + q1];
+            B.x *= ihf;
+            B.y *= ihf;
+            B.z *= ihf;
+            const float abx = B.x - A.x, aby = B.y - A.y, abz = B.z - A.z;
+            const float len2 = abx * abx + aby * aby + abz * abz;
+            if (len2 > 0.0f) {
+              const float il = __builtin_amdgcn_rsqf(len2);
+              const float ex = abx * il, ey = aby * il, ez = abz * il;
+              const float mx = pf.y * ez - pf.z * ey, my = pf.z * ex - pf.x * ez, mz = pf.x * ey - pf.y * ex;
+              const float p = (P0x - A.x) * mx + (P0y - A.y) * my + (P0z - A.z) * mz;
+              if (p <= 0.0f) allpos = false;
+              if (p == 0.0f) {
+                anyzero = true;
+              } else if (fabsf(p) < kDegenerate) {
+                ++K.n64;
+                again = true;
+                break;
+              } else {
+                ++K.ne_vis;
+                const float tA = (A.x - P0x) * ex + (A.y - P0y) * ey + (A.z - P0z) * ez;
+                const float tB = (B.x - P0x) * ex + (B.y - P0y) * ey + (B.z - P0z) * ez;
+                const double ap = (double)fabsf(p), dA = (double)tA, dB = (double)tB;
+                const double ang = -dh * MathMixed::span(ap, dA, dB);
+                sum += p > 0.0f ? ang : -ang;
+                const double a2 = ad * ad + ap * ap;
+                const double r2 = 4.0 - a2;
+                bool integ = r2 > 0.0 && (dA < 0.0 || dA * dA < r2) && (dB > 0.0 || dB * dB < r2);
+                if (integ) {
+                  const double t2 = sqrt_mixed(r2);
+                  const double ca = fmin(fmax(dA, -t2), t2), cb = fmin(fmax(dB, -t2), t2);
+                  integ = ca < cb;
+                  if (integ) {
+                    bool cross = false;
+                    if (a2 < 1.0) {
+                      const double t1 = sqrt_mixed(1.0 - a2);
+                      cross = (ca < -t1 && cb > -t1) || (ca < t1 && cb > t1);
+                    }
+                    const float4 it = make_float4(df, p, tA, tB);
+                    if (cross) mine[nD++] = it;
+                    else mine[cap - 1 - nN++] = it;
+                  }
+                }
+                anyint |= integ;
+                K.ne_int += integ;
+              }
+            }
+            A = B;
+          }
+          if (again) break;
+          if (!anyint && !anyzero) sum = -dh * (allpos ? 2.0 * kPi : 0.0);
+          light += d > 0.0 ? sum : -sum;
+        }
+        if (f == f1) {
+          done = true;
+          again |= inside && on_boundary;
+        }
+        if (again) {
+          // binary64 geometry (particle within 1e-4 h of a face plane or its
+          // foot point of an edge line, or exactly on the boundary) or a face
+          // larger than a slice: the pair goes to the one-pair-per-lane kernel
+          done = true;
+          nD = nN = 0;
+          redo[atomicAdd(n_redo, 1)] = (int32_t)k;
+        }
+      }
+      wave_fence();
+      // ---------------- phase B: crossing items, then the others
+#pragma unroll 1
+      for (int pass = 0; pass < 2; ++pass) {
+        const int n = pass == 0 ? nD : nN;
+        const int incl = wave_scan_excl(n, lane) + n;
+        const int total = __shfl(incl, 63, 64);
+        s_incl[wid][lane] = incl;
+        wave_sync();
+        for (int base = 0; base < total; base += 64) {
+          const int j = base + lane;
+          if (j < total) {
+            int lo = 0, hi = 63;  // first slice whose inclusive count exceeds j
+            while (lo < hi) {
+              const int mid = (lo + hi) >> 1;
+              if (s_incl[wid][mid] > j) hi = mid;
+              else lo = mid + 1;
+            }
+            const int r = j - (lo ? s_incl[wid][lo - 1] : 0);
+            float4 *slot = region + (int64_t)lo * cap + (pass == 0 ? r : cap - 1 - r);
+            const double v = item_value(*slot, K.fd);
+            *reinterpret_cast<double *>(slot) = v;
+          }
+        }
+        wave_sync();
+      }
+      wave_fence();
+      for (int r = 0; r < nD; ++r) heavy += *reinterpret_cast<const double *>(mine + r);
+      for (int r = 0; r < nN; ++r) heavy += *reinterpret_cast<const double *>(mine + cap - 1 - r);
+      wave_fence();
+      if (__all(done)) break;
+    }
+    if (k < P && !again) w_out[k] = (inside ? 1.0 : 0.0) - kInv4Pi * (light + heavy);
+  }
+  if (kCount) flush_counters(counters, nfaces, K);
+}
+
 }  // namespace
 
 void exact_integral(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, int precision, hipStream_t s) {
@@ -476,17 +805,52 @@ void exact_integral(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, i
   if (P.n_pairs == 0) return;
   int64_t *ctr = ctx.counting ? ctx.d_counters : nullptr;
   if (ctr) SPH_HIP(hipMemsetAsync(ctr, 0, 8 * sizeof(int64_t), s));
+  static const char *variant = getenv("SPHMAP_EXACT_VARIANT");
+  const bool per_pair = precision == SPHMAP_PREC_FP64 || (variant && variant[0] == 'u');
+  if (per_pair) {
+    KernelTimer kt(&ctx, "exact_integral", s);
+    const unsigned grid = (unsigned)div_up(P.n_pairs, 256);
+    if (precision == SPHMAP_PREC_FP64)
+      k_exact_fp64<<<grid, 256, 0, s>>>(P.n_pairs, P.pair_c, P.pair_p, p.xyz, p.h, t.gen, t.cell_face_off,
+                                        t.face_vtx_off, t.fplane, t.fsphere, t.fvpos, P.w, ctr);
+    else
+      k_exact_mixed<<<grid, 256, 0, s>>>(P.n_pairs, P.pair_c, P.pair_p, p.xyz, p.h, t.gen, t.cell_face_off,
+                                         t.face_vtx_off, t.fplane, t.fplane32, t.fsphere, t.fvpos, t.fvpos32, P.w,
+                                         ctr);
+    SPH_LAUNCH_CHECK();
+    kt.done();
+    return;
+  }
+  // persistent two-phase kernel: as many workgroups as stay resident at once
+  static int n_cu = 0, per_cu = 0;
+  if (n_cu == 0) {
+    SPH_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx.device));
+    SPH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_exact_flat<false>, 64 * kFlatWaves, 0));
+    per_cu = std::max(per_cu, 1);
+  }
+  static const char *cap_env = getenv("SPHMAP_FLAT_CAP");
+  const int cap = cap_env ? std::max(8, atoi(cap_env)) : kFlatCap;
+  const int64_t n_chunks = div_up(P.n_pairs, 64);
+  const int64_t grid = std::min<int64_t>((int64_t)n_cu * per_cu, div_up(n_chunks, kFlatWaves));
+  float4 *scratch = ctx.arena.get<float4>("flat_items", grid * kFlatWaves * 64 * cap);
+  int32_t *next = ctx.arena.get<int32_t>("flat_next", 2);  // work counter, redo count
+  int32_t *redo = ctx.arena.get<int32_t>("flat_redo", P.n_pairs);
+  KernelTimer kz(&ctx, "flat_reset", s);
+  k_zero_i32<<<1, 64, 0, s>>>(next, 2);
+  SPH_LAUNCH_CHECK();
+  kz.done();
   KernelTimer kt(&ctx, "exact_integral", s);
-  const unsigned grid = (unsigned)div_up(P.n_pairs, 256);
-  if (precision == SPHMAP_PREC_FP64)
-    k_exact_fp64<<<grid, 256, 0, s>>>(P.n_pairs, P.pair_c, P.pair_p, p.xyz, p.h, t.gen, t.cell_face_off,
-                                      t.face_vtx_off, t.fplane, t.fsphere, t.fvpos, P.w, ctr);
-  else
-    k_exact_mixed<<<grid, 256, 0, s>>>(P.n_pairs, P.pair_c, P.pair_p, p.xyz, p.h, t.gen, t.cell_face_off,
-                                       t.face_vtx_off, t.fplane, t.fplane32, t.fsphere, t.fvpos, t.fvpos32, P.w,
-                                       ctr);
+  (ctr ? k_exact_flat<true> : k_exact_flat<false>)<<<(unsigned)grid, 64 * kFlatWaves, 0, s>>>(
+      P.n_pairs, P.pair_c, P.pair_p, p.xyz, p.h, t.gen, t.cell_face_off, t.face_vtx_off, t.fplane, t.fplane32,
+      t.fsphere, t.fvpos32, P.w, ctr, scratch, cap, next, redo, next + 1);
   SPH_LAUNCH_CHECK();
   kt.done();
+  KernelTimer kr(&ctx, "exact_redo", s);
+  k_exact_mixed_list<<<(unsigned)(n_cu * 4), 256, 0, s>>>(redo, next + 1, P.pair_c, P.pair_p, p.xyz, p.h, t.gen,
+                                                          t.cell_face_off, t.face_vtx_off, t.fplane, t.fplane32,
+                                                          t.fsphere, t.fvpos, t.fvpos32, P.w, ctr);
+  SPH_LAUNCH_CHECK();
+  kr.done();
 }
 
 }  // namespace sphmap

@@ -78,7 +78,7 @@ def test_uniform_4096_full(ctx, c1, c1_oracle, precision):
     else:
         assert np.max(np.abs(gw - w)) < 1e-5
         assert np.max(rel) < 1e-5
-    assert np.all(np.abs(gw[w == 0.0]) < 1e-15)
+    assert np.all(np.abs(gw[w == 0.0]) < (1e-15 if precision == "fp64" else 1e-8))
     np.testing.assert_allclose(res.density.cpu().numpy(), gm / vol, rtol=1e-12)
     # coverage: sum over the particle's cells of the oracle weights
     cov_ref = np.bincount(idx, weights=w, minlength=len(c1.pos))
