@@ -16,6 +16,7 @@ Prints ONE JSON line.  Metric: particle-cell pair integrals per second.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,15 +25,43 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Per-item arithmetic of the exact-integral kernel (FLOPs; square roots,
-# divisions, reciprocals, atan2 and asinh counted as one each), multiplied by
-# the device work counters of the same workload:
+# Per-item arithmetic of the Exact integral (FLOPs; a square root, division,
+# reciprocal, atan or log counted as one), multiplied by the device work
+# counters of the same workload:
 FLOP_FACE_TEST = 6        # plane distance of the particle
-FLOP_FACE_INT = 32        # scaled distance, sphere cull, foot point, C_f, accumulation
-FLOP_EDGE_VISIT = 46      # edge direction, in-plane normal, p, tau_A, tau_B, a^2
-FLOP_EDGE_INT = 10        # clip to U < 2, regime split
-FLOP_FD = 60              # one evaluation of |d| F (3 transcendentals + polynomials)
-PEAK = {"mixed": 157.3, "fp64": 78.6}  # MI355X vector FP32 (packed) / FP64, TFLOP/s
+FLOP_FACE_INT = 32        # scaled distance, sphere cull, foot point, |d| H(|d|), accumulation
+FLOP_EDGE_VISIT = 46      # edge direction, in-plane normal, p, tau_A, tau_B, angle term
+FLOP_EDGE_INT = 14        # clip to U < 2, regime split
+FLOP_PIECE = 93           # mixed path: one single-regime piece (coefficients, 3 differences, polynomials)
+FLOP_FD = 60              # binary64 path: one antiderivative evaluation (3 transcendentals + polynomials)
+# Vector FMA peak of MI355X for the arithmetic these kernels issue: 256 CUs x
+# 4 SIMDs x 16 lanes x 2 FLOP x 2.4 GHz = 78.6 TFLOP/s, the same for binary64
+# and for unpacked binary32 (the library is built without packed-FP32 code).
+PEAK_TFLOPS = 78.6
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "exact_integral_turbulent_262144_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2410_15227_amd", "csrc", f) for f in ("exact.hip", "common.hpp")]
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(precision, workload):
+    """HBM bytes per launch of the Exact-integral kernels from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs, or None once the kernel sources
+    differ from the ones those counters were taken on."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        d = json.load(fh)
+    if d.get("source_sha256") != kernel_source_sha() or d.get("precision") != precision \
+            or d.get("workload") != workload:
+        return None
+    return int(d["hbm_bytes_per_launch"])
 
 
 def log(*a):
@@ -46,9 +75,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--n", type=int, default=262144)
-    ap.add_argument("--cpu-sample", type=int, default=800, help="cells of the oracle CPU baseline")
+    ap.add_argument("--cpu-sample", type=int, default=30000, help="cells of the oracle CPU baseline (about 10-15 s)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=3, help="timed steps of the plain binary64 path")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -115,16 +146,21 @@ def main():
     ms_step = el * 1e3 / args.steps
     value = n_pairs * args.steps / el
 
+    per_eval = FLOP_PIECE if args.precision == "mixed" else FLOP_FD
     flop = (FLOP_FACE_TEST * ctr[1] + FLOP_FACE_INT * ctr[2] + FLOP_EDGE_VISIT * ctr[3] + FLOP_EDGE_INT * ctr[4]
-            + FLOP_FD * (ctr[5] + ctr[6]))
+            + per_eval * (ctr[5] + ctr[6]))
     flop_per_pair = flop / max(n_pairs, 1)
-    k_avg_s = k_ms / max(k_n, 1) / 1e3
+    # the integral is one launch of the main kernel plus, on the mixed path,
+    # one launch over the pairs left to binary64 geometry
+    redo_ms, redo_n = ctx.kernel_time("exact_redo")
+    k_avg_s = (k_ms / max(k_n, 1) + redo_ms / max(redo_n, 1)) / 1e3
     achieved = flop / k_avg_s / 1e12 if k_avg_s > 0 else 0.0
-    peak = PEAK[args.precision]
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None,
-                "kernel": "exact_integral", "kernel_ms": round(k_ms / max(k_n, 1), 4),
-                "flop_per_pair": round(flop_per_pair, 1)}
+    workload = f"turbulent_{args.n}"
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_TFLOPS, 4), "traffic": measured_traffic(args.precision, workload),
+                "kernel": "exact_integral" + (" (k_exact_flat + k_exact_mixed_list)" if args.precision == "mixed"
+                                              else " (k_exact_fp64)"),
+                "kernel_ms": round(k_avg_s * 1e3, 4), "flop_per_pair": round(flop_per_pair, 1)}
 
     # the plain binary64 path on the same GPU and inputs, for comparison
     fp64 = None
@@ -149,6 +185,14 @@ def main():
                 "mixed_speedup": round((n_pairs * args.steps / el) / (n_pairs * args.fp64_steps / el64), 3),
                 "max_rel_cell_mass_diff_mixed_vs_fp64": rel}
         mass.copy_(mass_mixed)
+
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     cpu = None
     if not args.no_cpu and args.cpu_sample > 0:
@@ -178,7 +222,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if args.precision == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"turbulent_{args.n}", "n_particles": args.n, "n_cells": C,
+        "config": {"workload": workload, "n_particles": args.n, "n_cells": C,
                    "n_pairs": int(n_pairs), "precision": args.precision, "sigma_lnrho": 1.5,
                    "tess_upload_ms": round(tess_ms, 2)},
         "roofline": roofline,

@@ -205,8 +205,9 @@ int build_pseudo_particles(sphmap_ctx *ctx, int64_t n, const double *d_xyz, cons
 
 /* ------------------------------------------------------------------------
  * Kernel timing: when enabled, HIP events are recorded on the launch stream
- * around each launch of the named kernels ("exact_integral", "pair_fill",
- * "pair_count", "cell_reduce", "reverse", "transpose", "node_hsolve").
+ * around each launch of the named kernels ("exact_integral", "exact_redo",
+ * "pair_fill", "pair_count", "cell_reduce", "reverse", "transpose",
+ * "node_hsolve").
  * sphmap_kernel_time synchronises on the recorded events and returns the
  * summed milliseconds and the number of launches since the last reset.
  * ---------------------------------------------------------------------- */
@@ -216,10 +217,15 @@ int sphmap_reset_timing(sphmap_ctx *ctx);
 
 /* Work counters of the last forward mapping (host, 8 values): [0] pairs,
    [1] faces tested, [2] faces integrated (within 2h), [3] edges visited,
-   [4] edges integrated (edge line within 2h), [5] closed-form evaluations in
-   the inner regime (U < 1), [6] in the outer regime (1 <= U < 2), [7] edges
-   the mixed path evaluated in binary64.  Counting costs time; it is only
-   done when enabled (sphmap_set_counting). */
+   [4] edges integrated (edge line within 2h).  [5] and [6]: closed-form
+   evaluations -- binary64 path: antiderivative evaluations in the inner
+   (U < 1) and outer (1 <= U < 2) regime; mixed path: single-regime pieces
+   (one per integrated edge, two when its range crosses U = 1) with inner /
+   outer coefficients (a piece with twice their difference counts as
+   inner).  [7] edges or faces
+   evaluated from binary64 geometry (mixed path: the pairs holding them are
+   recomputed one pair per lane).  Counting costs time; it is only done when
+   enabled (sphmap_set_counting). */
 int sphmap_set_counting(sphmap_ctx *ctx, int32_t enabled);
 int sphmap_work_counters(sphmap_ctx *ctx, int64_t *out8);
 

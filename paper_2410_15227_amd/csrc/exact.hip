@@ -175,7 +175,8 @@ struct MathMixed {
   static __device__ inline double atanq(double y, double x) { return atan_mixed(y, x); }
   static __device__ inline double span(double p, double tA, double tB) {
     const double y = p * (tB - tA), x = fma(tA, tB, p * p);  // y > 0
-    return x > 0.0 ? atan_mixed(y, x) : (x < 0.0 ? kPi - atan_mixed(y, -x) : kHalfPi);
+    const double r = atan_mixed(y, fabs(x));  // pi/2 for x = 0
+    return x < 0.0 ? kPi - r : r;
   }
   static __device__ inline double asinh_(double z) { return asinh_mixed(z); }
   static __device__ inline double sqrt_(double v) { return sqrt_mixed(v); }
@@ -480,18 +481,8 @@ __device__ inline void pair_mixed(int64_t k, const int32_t *pair_c, const int32_
   if (counters) flush_counters(counters, f1 - f0, K);
 }
 
-__global__ void __launch_bounds__(256) k_exact_mixed(int64_t P, const int32_t *pair_c, const int32_t *pair_p,
-                                                    const double *xyz, const double *hh, const double *gen,
-                                                    const int64_t *cfo, const int64_t *fvo, const double4 *fplane,
-                                                    const float4 *fplane32, const double4 *fsphere,
-                                                    const double *fvpos, const float4 *fvpos32, double *w_out,
-                                                    int64_t *counters) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < P)
-    pair_mixed(k, pair_c, pair_p, xyz, hh, gen, cfo, fvo, fplane, fplane32, fsphere, fvpos, fvpos32, w_out, counters);
-}
-
-// the same over a device-side list of pairs (its length read on the device)
+// one pair per lane over a device-side list of pairs (its length read on the
+// device): the pairs the two-phase kernel leaves to binary64 geometry
 __global__ void __launch_bounds__(256) k_exact_mixed_list(const int32_t *list, const int32_t *n_list,
                                                          const int32_t *pair_c, const int32_t *pair_p,
                                                          const double *xyz, const double *hh, const double *gen,
@@ -560,51 +551,141 @@ __device__ inline bool edge_geo64(const double4 pl, double dist, double ih, doub
 // Pairs that need binary64 geometry are listed and left to the
 // one-pair-per-lane kernel.
 constexpr int kFlatWaves = 4;  // wavefronts per workgroup
-constexpr int kFlatCap = 64;   // items per lane slice
+constexpr int kFlatCap = 128;  // items per lane slice (a face has at most 128 edges)
 
 __global__ void k_zero_i32(int32_t *p, int n) {
   const int t = threadIdx.x;
   if (t < n) p[t] = 0;
 }
 
-// F(cb) - F(ca) of one edge within 2h (p > 0, tA < tB): the part of the fan
-// integral that is not the angle term.
-template <class M>
-__device__ inline double edge_fan(double ad, double p, double tA, double tB, EdgeCount &cnt) {
-  const double a2 = ad * ad + p * p;
-  const double t2 = M::sqrt_(4.0 - a2);
-  const double ca = fmin(fmax(tA, -t2), t2), cb = fmin(fmax(tB, -t2), t2);
-  Coef c0, c1;
-  edge_coefs(ad, p, c0, c1);
-  const double a = M::sqrt_(a2);
-  const double ia = M::rcp(a);
-  double t1 = -1.0, D = 0.0;
-  if (a2 < 1.0) {
-    t1 = M::sqrt_(1.0 - a2);
-    // the join constant cancels unless [ca, cb] crosses t = -t1 or t = t1
-    if ((ca < -t1 && cb > -t1) || (ca < t1 && cb > t1)) {
-      const double ph = M::atanq(t1, p), be = M::atanq(ad * t1, p), Lz = M::asinh_(t1 * ia);
-      D = coef_eval(c0, ph, be, Lz, t1, 1.0) - coef_eval(c1, ph, be, Lz, t1, 1.0);
-      ++cnt.n0;
-      ++cnt.n1;
-    }
-  }
-  auto F = [&](double t) -> double {
-    const double at = fabs(t);
-    const double U = (at == t2) ? 2.0 : M::sqrt_(a2 + t * t);
-    const double phi = M::atanq(t, p), be = M::atanq(ad * t, p * U), Lz = M::asinh_(t * ia);
-    if (at <= t1) {
-      ++cnt.n0;
-      return coef_eval(c0, phi, be, Lz, t, U);
-    }
-    ++cnt.n1;
-    return coef_eval(c1, phi, be, Lz, t, U) + copysign(D, t);
-  };
-  return F(cb) - F(ca);
+// atan2(y, x) for any x, from the binary32-core atan
+__device__ inline double atan2_mixed(double y, double x) {
+  const double r = atan_mixed(y, fabs(x));  // copysign(pi/2, y) for x = 0
+  return x < 0.0 ? copysign(kPi, y) - r : r;
 }
 
-__device__ inline double item_value(const float4 it, EdgeCount &cnt) {
-  const double v = edge_fan<MathMixed>((double)fabsf(it.x), (double)fabsf(it.y), (double)it.z, (double)it.w, cnt);
+// log(num / den) for num, den > 0 with one division: the exponents are split
+// off both, the mantissa ratio brought into [1/sqrt2, sqrt2] and
+// log(m) = 2 atanh((m_n - m_d) / (m_n + m_d)) from the binary32 core.
+__device__ inline double log_ratio_mixed(double num, double den) {
+  int e = __builtin_amdgcn_frexp_exp(num) - __builtin_amdgcn_frexp_exp(den);
+  double mn = __builtin_amdgcn_frexp_mant(num);  // [0.5, 1)
+  const double md = __builtin_amdgcn_frexp_mant(den);
+  if (mn < 0.70710678118654752 * md) {
+    mn *= 2.0;
+    e -= 1;
+  } else if (mn > 1.4142135623730950 * md) {
+    mn *= 0.5;
+    e += 1;
+  }
+  const double nm = mn - md, dn = mn + md;
+  const double rd = rcp_mixed(dn);
+  double t = nm * rd;
+  t = fma(rd, fma(-dn, t, nm), t);
+  const double t2 = t * t;
+  const float zf = (float)t2;
+  float Q = 0.23331113159656525f;
+  Q = fmaf(Q, zf, 0.2855079174041748f);
+  Q = fmaf(Q, zf, 0.4000012278556824f);
+  Q = fmaf(Q, zf, 0.6666666865348816f);
+  return (double)e * kLn2 + fma(t * t2, (double)Q, 2.0 * t);
+}
+
+// F(v) - F(u) over [u, v] inside one regime with coefficients c, from
+// differences: phi(v) - phi(u) and beta(v) - beta(u) as one angle each
+// (atan2 of the tangent-difference numerator and denominator, scaled by
+// positive factors), L(v) - L(u) = log(N(v) / N(u)) with N(t) = t + U(t),
+// written a^2 / (U - t) for t < 0 to avoid cancellation.
+__device__ inline double piece(const Coef &c, double ad, double p, double a2, double u, double Uu, double v,
+                               double Uv) {
+  const double dphi = atan2_mixed(p * (v - u), fma(u, v, p * p));
+  const double dbeta = atan2_mixed(ad * p * (v * Uu - u * Uv), p * p * Uu * Uv + ad * ad * u * v);
+  const bool un = u < 0.0, vn = v < 0.0;
+  const double Nv = vn ? Uu - u : v + Uv;
+  const double Nu = un ? (vn ? Uv - v : a2) : u + Uu;
+  const double num = (un && !vn) ? Nv * (Uu - u) : Nv;
+  const double dL = log_ratio_mixed(num, Nu);
+  const double u2 = u * u, v2 = v * v;
+  const double poly = (v * fma(c.t3, v2, c.t1) - u * fma(c.t3, u2, c.t1)) +
+                      (v * Uv * fma(c.t3U, v2, c.tU) - u * Uu * fma(c.t3U, u2, c.tU));
+  return c.phi * dphi + c.beta * dbeta + c.L * dL + poly;
+}
+
+// w0 * (inner coefficients) + w1 * (outer coefficients) of one edge, formed
+// directly so that only one set is live: (1, 0) inner, (0, 1) outer,
+// (2, -2) twice their difference.
+__device__ inline Coef coef_mix(double ad, double p, double w0, double w1) {
+  const double d2 = ad * ad, p2 = p * p, a2 = d2 + p2, d4 = d2 * d2;
+  const double A = 2.0 * d2 * p + p2 * p;
+  const double B = d4 * p + 0.5 * A * a2 - 0.125 * p * a2 * a2;
+  const double T = 0.5 * A + 0.125 * p * a2;
+  const double adp = ad * p;
+  const double kA = -(2.0 / 3.0) * w0 - (4.0 / 3.0) * w1;
+  const double kB = 0.3 * (w0 - w1);
+  const double kC = -0.1 * w0 + w1 * (1.0 / 30.0);
+  Coef c;
+  c.phi = ad * ((1.4 * w0 + 1.6 * w1) + kA * d2 + kB * d4);
+  c.beta = (-w0 - (16.0 / 15.0) * w1) + w1 * d4 + kC * d4 * d2;
+  c.L = ad * (w1 * (d2 * p + 0.5 * p * a2) + kC * B);
+  c.t1 = ad * (kA * p + kB * A);
+  c.t3 = 0.1 * (w0 - w1) * adp;
+  c.tU = ad * (0.5 * w1 * p + kC * T);
+  c.t3U = (-0.025 * w0 + w1 * (1.0 / 120.0)) * adp;
+  return c;
+}
+
+// F(cb) - F(ca) of one edge within 2h (p > 0, tA < tB) whose clipped range
+// stays in one regime: one piece.
+__device__ inline double fan_one(double ad, double p, double tA, double tB, EdgeCount &cnt) {
+  const double a2 = ad * ad + p * p;
+  const double t2 = sqrt_mixed(4.0 - a2);
+  const double ca = fmin(fmax(tA, -t2), t2), cb = fmin(fmax(tB, -t2), t2);
+  const double Ua = (fabs(ca) == t2) ? 2.0 : sqrt_mixed(fma(ca, ca, a2));
+  const double Ub = (fabs(cb) == t2) ? 2.0 : sqrt_mixed(fma(cb, cb, a2));
+  const double mid = 0.5 * (ca + cb);
+  const bool outer = !(mid * mid < 1.0 - a2);
+  cnt.n0 += !outer;
+  cnt.n1 += outer;
+  return piece(coef_mix(ad, p, outer ? 0.0 : 1.0, outer ? 1.0 : 0.0), ad, p, a2, ca, Ua, cb, Ub);
+}
+
+// The same for a clipped range that crosses t = -t1 or t = +t1 (U = 1):
+// two pieces split at the crossing; across both, the outer coefficients
+// over the whole range plus 2 (F_inner - F_outer) over [0, t1] (odd in t).
+__device__ inline double fan_two(double ad, double p, double tA, double tB, EdgeCount &cnt) {
+  const double a2 = ad * ad + p * p;
+  const double t2 = sqrt_mixed(4.0 - a2);
+  const double ca = fmin(fmax(tA, -t2), t2), cb = fmin(fmax(tB, -t2), t2);
+  const double Ua = (fabs(ca) == t2) ? 2.0 : sqrt_mixed(fma(ca, ca, a2));
+  const double Ub = (fabs(cb) == t2) ? 2.0 : sqrt_mixed(fma(cb, cb, a2));
+  const bool in = a2 < 1.0;  // an inner regime exists
+  const double t1 = in ? sqrt_mixed(1.0 - a2) : 0.0;
+  const bool lo = in && ca < -t1 && cb > -t1, hi = in && ca < t1 && cb > t1;
+  const bool both = lo && hi;
+  // first piece: [ca, s] (or [ca, cb] when both crossings are inside)
+  const double s = lo ? -t1 : t1;
+  const bool one = !lo && !hi;  // no crossing after all (rounding at the join)
+  const double mid = 0.5 * (ca + cb);
+  const bool outer1 = both || lo || (one && !(mid * mid < 1.0 - a2));
+  const double v1 = (both || one) ? cb : s, V1 = (both || one) ? Ub : 1.0;
+  double r = piece(coef_mix(ad, p, outer1 ? 0.0 : 1.0, outer1 ? 1.0 : 0.0), ad, p, a2, ca, Ua, v1, V1);
+  // second piece: [s, cb], or [0, t1] with 2 (inner - outer)
+  if (!one) {
+    const double w0 = both ? 2.0 : (lo ? 1.0 : 0.0), w1 = both ? -2.0 : (lo ? 0.0 : 1.0);
+    const double u2 = both ? 0.0 : s, W2 = both ? sqrt_mixed(a2) : 1.0;
+    const double v2 = both ? t1 : cb, V2 = both ? 1.0 : Ub;
+    r += piece(coef_mix(ad, p, w0, w1), ad, p, a2, u2, W2, v2, V2);
+    cnt.n0 += w0 != 0.0;
+    cnt.n1 += w0 == 0.0;
+  }
+  cnt.n0 += !outer1;
+  cnt.n1 += outer1;
+  return r;
+}
+
+__device__ inline double item_value(const float4 it, bool two, EdgeCount &cnt) {
+  const double ad = (double)fabsf(it.x), p = (double)fabsf(it.y), tA = (double)it.z, tB = (double)it.w;
+  const double v = two ? fan_two(ad, p, tA, tB, cnt) : fan_one(ad, p, tA, tB, cnt);
   return ((it.x < 0.0f) != (it.y < 0.0f)) ? -v : v;
 }
 
@@ -781,7 +862,7 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_flat(
             }
             const int r = j - (lo ? s_incl[wid][lo - 1] : 0);
             float4 *slot = region + (int64_t)lo * cap + (pass == 0 ? r : cap - 1 - r);
-            const double v = item_value(*slot, K.fd);
+            const double v = item_value(*slot, pass == 0, K.fd);
             *reinterpret_cast<double *>(slot) = v;
           }
         }
@@ -805,18 +886,11 @@ void exact_integral(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, i
   if (P.n_pairs == 0) return;
   int64_t *ctr = ctx.counting ? ctx.d_counters : nullptr;
   if (ctr) SPH_HIP(hipMemsetAsync(ctr, 0, 8 * sizeof(int64_t), s));
-  static const char *variant = getenv("SPHMAP_EXACT_VARIANT");
-  const bool per_pair = precision == SPHMAP_PREC_FP64 || (variant && variant[0] == 'u');
-  if (per_pair) {
+  if (precision == SPHMAP_PREC_FP64) {
     KernelTimer kt(&ctx, "exact_integral", s);
-    const unsigned grid = (unsigned)div_up(P.n_pairs, 256);
-    if (precision == SPHMAP_PREC_FP64)
-      k_exact_fp64<<<grid, 256, 0, s>>>(P.n_pairs, P.pair_c, P.pair_p, p.xyz, p.h, t.gen, t.cell_face_off,
-                                        t.face_vtx_off, t.fplane, t.fsphere, t.fvpos, P.w, ctr);
-    else
-      k_exact_mixed<<<grid, 256, 0, s>>>(P.n_pairs, P.pair_c, P.pair_p, p.xyz, p.h, t.gen, t.cell_face_off,
-                                         t.face_vtx_off, t.fplane, t.fplane32, t.fsphere, t.fvpos, t.fvpos32, P.w,
-                                         ctr);
+    k_exact_fp64<<<(unsigned)div_up(P.n_pairs, 256), 256, 0, s>>>(P.n_pairs, P.pair_c, P.pair_p, p.xyz, p.h, t.gen,
+                                                                  t.cell_face_off, t.face_vtx_off, t.fplane,
+                                                                  t.fsphere, t.fvpos, P.w, ctr);
     SPH_LAUNCH_CHECK();
     kt.done();
     return;
@@ -828,8 +902,7 @@ void exact_integral(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, i
     SPH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_exact_flat<false>, 64 * kFlatWaves, 0));
     per_cu = std::max(per_cu, 1);
   }
-  static const char *cap_env = getenv("SPHMAP_FLAT_CAP");
-  const int cap = cap_env ? std::max(8, atoi(cap_env)) : kFlatCap;
+  const int cap = kFlatCap;
   const int64_t n_chunks = div_up(P.n_pairs, 64);
   const int64_t grid = std::min<int64_t>((int64_t)n_cu * per_cu, div_up(n_chunks, kFlatWaves));
   float4 *scratch = ctx.arena.get<float4>("flat_items", grid * kFlatWaves * 64 * cap);
