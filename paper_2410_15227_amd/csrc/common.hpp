@@ -121,6 +121,12 @@ struct TessDev {
   double *fvpos = nullptr;        // [FV][3] oriented vertex positions about g
   float4 *fvpos32 = nullptr;      // [FV] binary32 copies (w unused)
   float4 *fplane32 = nullptr;     // binary32 copies of fplane
+  // per face-vertex slot k, the edge from slot k to the next slot of its face
+  // (binary32): start vertex about g and length; unit direction; in-plane
+  // normal n x e (pointing into the polygon)
+  float4 *edgeA = nullptr;        // [FV] A.xyz, |B - A|
+  float4 *edgeE = nullptr;        // [FV] e.xyz, 0
+  float4 *edgeM = nullptr;        // [FV] m.xyz, 0
   double *volume = nullptr;       // [C]
   float *radius = nullptr;        // [C]
   float4 *gen32 = nullptr;        // [C] fl(g), R_c in w

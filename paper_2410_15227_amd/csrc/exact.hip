@@ -531,27 +531,8 @@ __device__ inline bool edge_geo64(const double4 pl, double dist, double ih, doub
   return true;
 }
 
-// ------------------------------------------ two-phase wave kernel (mixed)
-// The closed form of an edge within 2h is most of the work, and in a
-// one-pair-per-lane loop the lanes of a wave reach it on different faces and
-// edges.  Here a wavefront takes 64 consecutive pairs (one per lane) from a
-// work counter and runs two phases over a private scratch region:
-//   A: each lane walks its pair's faces and edges, adds the angle terms
-//      -dh * (phi_B - phi_A) of every edge, and stores each edge within 2h
-//      as a float4 item (signed |d|, signed p, tau_A, tau_B) in its own slice
-//      of the region: edges whose clipped range crosses U = 1 from the front,
-//      the others from the back;
-//   B: the wave evaluates the items of all 64 slices 64 at a time, crossing
-//      edges first, so that the lanes of a pass run the same code, and
-//      writes each result over its item.
-// A lane pauses before a face whose edges might overflow its slice; the
-// wave then runs phase B and the paused lanes resume (a round).  Each lane
-// adds its own results in its own slice order, round after round, so a
-// weight depends on its pair alone, never on the pairs sharing the wave.
-// Pairs that need binary64 geometry are listed and left to the
-// one-pair-per-lane kernel.
+// ------------------------------------------------- persistent kernels
 constexpr int kFlatWaves = 4;  // wavefronts per workgroup
-constexpr int kFlatCap = 128;  // items per lane slice (a face has at most 128 edges)
 
 __global__ void k_zero_i32(int32_t *p, int n) {
   const int t = threadIdx.x;
@@ -695,16 +676,97 @@ __device__ inline void wave_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// ------------------------------------ edge-parallel wave kernel (mixed)
+// A wavefront takes 64 consecutive pairs (one per lane) from a work counter.
+//   A1 (lane = pair): the cull over the cell's faces (plane distance, face
+//      sphere against the 2h sphere), kept as a bit mask; the faces within
+//      reach are listed pair-major with their foot point, |d| and
+//      |d| H(|d|), and every edge of the chunk is tagged with its face;
+//   A2 (lane = edge): the wave walks those edges 64 at a time; each lane
+//      forms its edge's in-plane geometry from the precomputed edge frame,
+//      adds the angle term -dh (phi_B - phi_A) to its pair, and queues the
+//      edge in LDS when it comes within 2h (one queue for ranges crossing
+//      U = 1, one for the others);
+//   B  (lane = item): whenever a queue holds 64 items the wave evaluates
+//      them together, so every lane runs the same closed form.
+// Each pair's terms are added as 64-bit fixed-point integers (2^-50) with
+// LDS atomics: integer sums do not depend on order, so a weight is a
+// function of its own pair alone and repeats bit for bit.  Pairs with more
+// than 64 faces, more candidate edges than a chunk slot holds, or that need
+// binary64 geometry are listed for the one-pair-per-lane kernel.
+constexpr int kMaxFaces = 64;              // faces per cell handled here
+constexpr int kEntryCap = 64 * kMaxFaces;  // face entries per chunk
+constexpr int kEdgeCap = 128;              // candidate edges per pair handled here
+constexpr int kQueue = 128;                // items per LDS queue
+
+struct __align__(16) FaceEntry {
+  float ihf;      // 1/h of the owner (binary32)
+  int32_t vs;     // first vertex slot of the face
+  int32_t start;  // first edge of the face in the chunk's edge space
+  int32_t owner;  // lane of the pair
+};
+
+struct EdgeWave {  // per-wavefront LDS
+  unsigned long long acc[64];
+  float4 qD[kQueue], qN[kQueue];
+  unsigned char oD[kQueue], oN[kQueue];
+  int redo[64];
+};
+
+__device__ inline uint64_t lanes_in(int lo, int hi) {  // bits [lo, hi), 0 <= lo <= hi <= 64
+  const uint64_t a = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
+  const uint64_t b = lo >= 64 ? ~0ull : ((1ull << lo) - 1ull);
+  return a & ~b;
+}
+
+// v in units of 2^-50, rounded down, as a two's-complement 64-bit integer
+// (|v| < 2^13).
+__device__ inline unsigned long long to_fixed(double v) {
+  const double t = v * 0x1p50;
+  const double hi = floor(t * 0x1p-32);
+  const double lo = t - hi * 0x1p32;  // [0, 2^32)
+  return ((unsigned long long)(unsigned)(int)hi << 32) + (unsigned long long)(unsigned)lo;
+}
+
+__device__ inline double from_fixed(unsigned long long a) {
+  const int hi = (int)(a >> 32);
+  const unsigned lo = (unsigned)a;
+  return ((double)hi * 0x1p32 + (double)lo) * 0x1p-50;
+}
+
+// Evaluate the first n (<= 64) items of a queue and add them to their pairs;
+// move the rest to the front.  Returns the new length.
+__device__ inline int drain(EdgeWave &L, float4 *q, unsigned char *o, int len, int n, bool two, int lane,
+                            EdgeCount &cnt) {
+  if (lane < n) {
+    const double r = item_value(q[lane], two, cnt);
+    atomicAdd(&L.acc[o[lane]], to_fixed(r));
+  }
+  const int rest = len - n;
+  if (lane < rest) {
+    const float4 it = q[n + lane];
+    const unsigned char ow = o[n + lane];
+    q[lane] = it;
+    o[lane] = ow;
+  }
+  wave_sync();
+  return rest;
+}
+
 template <bool kCount>
-__global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_flat(
+__global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
     int64_t P, const int32_t *pair_c, const int32_t *pair_p, const double *xyz, const double *hh, const double *gen,
-    const int64_t *cfo, const int64_t *fvo, const double4 *fplane, const float4 *fplane32, const double4 *fsphere,
-    const float4 *fvpos32, double *w_out, int64_t *counters, float4 *scratch, int cap, int32_t *next_chunk,
-    int32_t *redo, int32_t *n_redo) {
-  __shared__ int s_incl[kFlatWaves][64];
+    const int64_t *cfo, const int64_t *fvo, const double4 *fplane, const double4 *fsphere, const float4 *edgeA,
+    const float4 *edgeE, const float4 *edgeM, double *w_out, int64_t *counters, FaceEntry *entries, float4 *egeo,
+    double *edh, int32_t *eface, int32_t *next_chunk, int32_t *redo, int32_t *n_redo) {
+  __shared__ EdgeWave lds[kFlatWaves];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  float4 *const region = scratch + ((int64_t)blockIdx.x * kFlatWaves + wid) * 64 * cap;
-  float4 *const mine = region + (int64_t)lane * cap;
+  EdgeWave &L = lds[wid];
+  const int64_t wave = (int64_t)blockIdx.x * kFlatWaves + wid;
+  FaceEntry *const ent = entries + wave * kEntryCap;
+  float4 *const eg = egeo + wave * kEntryCap;
+  double *const ed = edh + wave * kEntryCap;
+  int32_t *const ef = eface + wave * 64 * kEdgeCap;
   const int64_t n_chunks = (P + 63) >> 6;
   Counters K;
   int64_t nfaces = 0;
@@ -714,167 +776,162 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_flat(
     chunk = __shfl(chunk, 0, 64);
     if (chunk >= n_chunks) break;
     const int64_t k = (int64_t)chunk * 64 + lane;
-    // per pair, kept across rounds
-    int64_t f = 0, f1 = 0;
-    double light = 0.0, heavy = 0.0;
-    bool inside = true, on_boundary = false, again = false, done = true;
-    if (k < P) {
+    const bool valid = k < P;
+    // ---------------- A1: cull
+    uint64_t mask = 0;
+    int nsurv = 0, nedge = 0;
+    bool inside = true, on_boundary = false, again = false;
+    int64_t f0 = 0;
+    double xr0 = 0.0, xr1 = 0.0, xr2 = 0.0, ih = 0.0, h = 0.0;
+    if (valid) {
       const int64_t c = pair_c[k];
-      f = cfo[c];
-      f1 = cfo[c + 1];
-      nfaces += f1 - f;
-      done = false;
+      const int64_t i = pair_p[k];
+      h = hh[i];
+      ih = 1.0 / h;
+      xr0 = xyz[3 * i] - gen[3 * c];
+      xr1 = xyz[3 * i + 1] - gen[3 * c + 1];
+      xr2 = xyz[3 * i + 2] - gen[3 * c + 2];
+      f0 = cfo[c];
+      const int nf = (int)(cfo[c + 1] - f0);
+      nfaces += nf;
+      if (nf > kMaxFaces) again = true;
+      for (int j = 0; j < nf && !again; ++j) {
+        const int64_t f = f0 + j;
+        const double4 pl = fplane[f];
+        if (!(pl.w > 0.0)) continue;
+        const double dist = pl.w - (pl.x * xr0 + pl.y * xr1 + pl.z * xr2);
+        if (dist < 0.0) inside = false;
+        if (dist == 0.0) {
+          on_boundary = true;
+          continue;
+        }
+        if (fabs(dist) >= 2.0 * h) continue;
+        const double4 sp = fsphere[f];
+        const double sx = xr0 - sp.x, sy = xr1 - sp.y, sz = xr2 - sp.z;
+        const double reach = sp.w + 2.0 * h;
+        if (sx * sx + sy * sy + sz * sz >= reach * reach) continue;
+        if (fabs(dist * ih) < kDegenerate) {
+          ++K.n64;
+          again = true;
+          break;
+        }
+        mask |= 1ull << j;
+        ++nsurv;
+        nedge += (int)(fvo[f + 1] - fvo[f]);
+      }
+      again |= nedge > kEdgeCap || (inside && on_boundary);
+      if (again) {
+        mask = 0;
+        nsurv = nedge = 0;
+      }
     }
-    // Rounds: phase A until every lane has finished its faces or paused
-    // before a face whose edges might not fit in its slice, then phase B.
-    while (true) {
-      int nD = 0, nN = 0;
-      if (!done) {
-        const int64_t c = pair_c[k];
-        const int64_t i = pair_p[k];
-        const double h = hh[i];
-        const double ih = 1.0 / h;
-        const float ihf = (float)ih;
-        const double xr0 = xyz[3 * i] - gen[3 * c], xr1 = xyz[3 * i + 1] - gen[3 * c + 1],
-                     xr2 = xyz[3 * i + 2] - gen[3 * c + 2];
-        const float x0 = (float)(xr0 * ih), x1 = (float)(xr1 * ih), x2 = (float)(xr2 * ih);
-        for (; f < f1; ++f) {
-          const double4 pl = fplane[f];
-          if (!(pl.w > 0.0)) continue;
-          const double dist = pl.w - (pl.x * xr0 + pl.y * xr1 + pl.z * xr2);
-          if (dist < 0.0) inside = false;
-          if (dist == 0.0) {
-            on_boundary = true;
-            continue;
-          }
-          if (fabs(dist) >= 2.0 * h) continue;
-          const double4 sp = fsphere[f];
-          const double sx = xr0 - sp.x, sy = xr1 - sp.y, sz = xr2 - sp.z;
-          const double reach = sp.w + 2.0 * h;
-          if (sx * sx + sy * sy + sz * sz >= reach * reach) continue;
-          const int64_t vs = fvo[f];
-          const int nv = (int)(fvo[f + 1] - vs);
-          const double d = dist * ih;
-          if (fabs(d) < kDegenerate || nv > cap) {
-            K.n64 += fabs(d) < kDegenerate ? nv : 0;
-            again = true;
-            break;
-          }
-          if (nD + nN + nv > cap) break;  // pause: flush the slice first
-          ++K.nf_int;
-          // |d| rounded to binary32, like the rest of the face's geometry
-          const float df = (float)d;
-          const double ad = (double)fabsf(df);
-          const double dh = dH(ad);
-          const float4 pf = fplane32[f];
-          const float P0x = x0 + df * pf.x, P0y = x1 + df * pf.y, P0z = x2 + df * pf.z;
-          double sum = 0.0;
-          bool allpos = true, anyzero = false, anyint = false;
-          float4 A = fvpos32[vs];
-          A.x *= ihf;
-          A.y *= ihf;
-          A.z *= ihf;
-          for (int q = 0; q < nv; ++q) {
-            const int q1 = (q + 1 == nv) ? 0 : q + 1;
-            float4 B = fvpos32[vs + q1];
-            B.x *= ihf;
-            B.y *= ihf;
-            B.z *= ihf;
-            const float abx = B.x - A.x, aby = B.y - A.y, abz = B.z - A.z;
-            const float len2 = abx * abx + aby * aby + abz * abz;
-            if (len2 > 0.0f) {
-              const float il = __builtin_amdgcn_rsqf(len2);
-              const float ex = abx * il, ey = aby * il, ez = abz * il;
-              const float mx = pf.y * ez - pf.z * ey, my = pf.z * ex - pf.x * ez, mz = pf.x * ey - pf.y * ex;
-              const float p = (P0x - A.x) * mx + (P0y - A.y) * my + (P0z - A.z) * mz;
-              if (p <= 0.0f) allpos = false;
-              if (p == 0.0f) {
-                anyzero = true;
-              } else if (fabsf(p) < kDegenerate) {
-                ++K.n64;
-                again = true;
-                break;
-              } else {
-                ++K.ne_vis;
-                const float tA = (A.x - P0x) * ex + (A.y - P0y) * ey + (A.z - P0z) * ez;
-                const float tB = (B.x - P0x) * ex + (B.y - P0y) * ey + (B.z - P0z) * ez;
-                const double ap = (double)fabsf(p), dA = (double)tA, dB = (double)tB;
-                const double ang = -dh * MathMixed::span(ap, dA, dB);
-                sum += p > 0.0f ? ang : -ang;
-                const double a2 = ad * ad + ap * ap;
-                const double r2 = 4.0 - a2;
-                bool integ = r2 > 0.0 && (dA < 0.0 || dA * dA < r2) && (dB > 0.0 || dB * dB < r2);
-                if (integ) {
-                  const double t2 = sqrt_mixed(r2);
-                  const double ca = fmin(fmax(dA, -t2), t2), cb = fmin(fmax(dB, -t2), t2);
-                  integ = ca < cb;
-                  if (integ) {
-                    bool cross = false;
-                    if (a2 < 1.0) {
-                      const double t1 = sqrt_mixed(1.0 - a2);
-                      cross = (ca < -t1 && cb > -t1) || (ca < t1 && cb > t1);
-                    }
-                    const float4 it = make_float4(df, p, tA, tB);
-                    if (cross) mine[nD++] = it;
-                    else mine[cap - 1 - nN++] = it;
-                  }
-                }
-                anyint |= integ;
-                K.ne_int += integ;
+    const int e_off = wave_scan_excl(nsurv, lane);
+    const int x_off = wave_scan_excl(nedge, lane);
+    const int n_edge = __shfl(x_off + nedge, 63, 64);
+    L.acc[lane] = 0ull;
+    L.redo[lane] = again ? 1 : 0;
+    if (kCount) K.nf_int += nsurv;
+    // ---------------- A1b: the face list, pair-major, and each edge's face
+    if (valid && !again) {
+      int e = e_off, start = x_off;
+      uint64_t m = mask;
+      while (m) {
+        const int j = __builtin_ctzll(m);
+        m &= m - 1;
+        const int64_t f = f0 + j;
+        const double4 pl = fplane[f];
+        const double dist = pl.w - (pl.x * xr0 + pl.y * xr1 + pl.z * xr2);
+        const int64_t vs = fvo[f];
+        const int nv = (int)(fvo[f + 1] - vs);
+        // |d| rounded to binary32, like the rest of the face's geometry
+        const float df = (float)(dist * ih);
+        FaceEntry fe;
+        fe.ihf = (float)ih;
+        fe.vs = (int32_t)vs;
+        fe.start = start;
+        fe.owner = lane;
+        ent[e] = fe;
+        eg[e] = make_float4((float)(xr0 + dist * pl.x), (float)(xr1 + dist * pl.y), (float)(xr2 + dist * pl.z), df);
+        ed[e] = dH((double)fabsf(df));
+        for (int q = 0; q < nv; ++q) ef[start + q] = e;
+        ++e;
+        start += nv;
+      }
+    }
+    wave_fence();
+    // ---------------- A2: one edge per lane; B whenever a queue fills
+    int qD = 0, qN = 0;
+    for (int b = 0; b < n_edge; b += 64) {
+      const int g = b + lane;
+      const bool live = g < n_edge;
+      int owner = 0;
+      bool integ = false, cross = false;
+      float4 it = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (live) {
+        const int e = ef[g];
+        const FaceEntry fe = ent[e];
+        owner = fe.owner;
+        const int64_t slot = fe.vs + (g - fe.start);
+        const float4 EA = edgeA[slot];
+        if (EA.w > 0.0f) {
+          const float4 geo = eg[e];  // foot point about g (absolute), signed |d|/h
+          const float4 EE = edgeE[slot], EM = edgeM[slot];
+          const float dx = geo.x - EA.x, dy = geo.y - EA.y, dz = geo.z - EA.z;
+          const float p = (dx * EM.x + dy * EM.y + dz * EM.z) * fe.ihf;
+          if (p != 0.0f) {
+            if (fabsf(p) < kDegenerate) {
+              ++K.n64;
+              L.redo[owner] = 1;  // binary64 geometry for this pair
+            } else {
+              ++K.ne_vis;
+              const float tA = -(dx * EE.x + dy * EE.y + dz * EE.z) * fe.ihf;
+              const float tB = fmaf(EA.w, fe.ihf, tA);
+              const double ap = (double)fabsf(p), dA = (double)tA, dB = (double)tB;
+              const double ad = (double)fabsf(geo.w);
+              const double ang = -ed[e] * MathMixed::span(ap, dA, dB);
+              atomicAdd(&L.acc[owner], to_fixed(((p > 0.0f) == (geo.w > 0.0f)) ? ang : -ang));
+              // within 2h somewhere on [tA, tB], and crossing U = 1 (squares, no roots)
+              const double a2 = ad * ad + ap * ap;
+              const double r2 = 4.0 - a2, s1 = 1.0 - a2;
+              integ = r2 > 0.0 && dA < dB && (dA < 0.0 || dA * dA < r2) && (dB > 0.0 || dB * dB < r2);
+              if (integ && s1 > 0.0) {
+                const bool lo = (dA < 0.0 && dA * dA > s1) && (dB >= 0.0 || dB * dB < s1);
+                const bool hi = (dA < 0.0 || dA * dA < s1) && (dB > 0.0 && dB * dB > s1);
+                cross = lo || hi;
               }
+              K.ne_int += integ;
+              it = make_float4(geo.w, p, tA, tB);
             }
-            A = B;
-          }
-          if (again) break;
-          if (!anyint && !anyzero) sum = -dh * (allpos ? 2.0 * kPi : 0.0);
-          light += d > 0.0 ? sum : -sum;
-        }
-        if (f == f1) {
-          done = true;
-          again |= inside && on_boundary;
-        }
-        if (again) {
-          // binary64 geometry (particle within 1e-4 h of a face plane or its
-          // foot point of an edge line, or exactly on the boundary) or a face
-          // larger than a slice: the pair goes to the one-pair-per-lane kernel
-          done = true;
-          nD = nN = 0;
-          redo[atomicAdd(n_redo, 1)] = (int32_t)k;
-        }
-      }
-      wave_fence();
-      // ---------------- phase B: crossing items, then the others
-#pragma unroll 1
-      for (int pass = 0; pass < 2; ++pass) {
-        const int n = pass == 0 ? nD : nN;
-        const int incl = wave_scan_excl(n, lane) + n;
-        const int total = __shfl(incl, 63, 64);
-        s_incl[wid][lane] = incl;
-        wave_sync();
-        for (int base = 0; base < total; base += 64) {
-          const int j = base + lane;
-          if (j < total) {
-            int lo = 0, hi = 63;  // first slice whose inclusive count exceeds j
-            while (lo < hi) {
-              const int mid = (lo + hi) >> 1;
-              if (s_incl[wid][mid] > j) hi = mid;
-              else lo = mid + 1;
-            }
-            const int r = j - (lo ? s_incl[wid][lo - 1] : 0);
-            float4 *slot = region + (int64_t)lo * cap + (pass == 0 ? r : cap - 1 - r);
-            const double v = item_value(*slot, pass == 0, K.fd);
-            *reinterpret_cast<double *>(slot) = v;
           }
         }
-        wave_sync();
       }
-      wave_fence();
-      for (int r = 0; r < nD; ++r) heavy += *reinterpret_cast<const double *>(mine + r);
-      for (int r = 0; r < nN; ++r) heavy += *reinterpret_cast<const double *>(mine + cap - 1 - r);
-      wave_fence();
-      if (__all(done)) break;
+      const uint64_t mD = __ballot(integ && cross), mN = __ballot(integ && !cross);
+      const uint64_t below = lanes_in(0, lane);
+      if (integ) {
+        const int pos = cross ? qD + __popcll(mD & below) : qN + __popcll(mN & below);
+        if (cross) {
+          L.qD[pos] = it;
+          L.oD[pos] = (unsigned char)owner;
+        } else {
+          L.qN[pos] = it;
+          L.oN[pos] = (unsigned char)owner;
+        }
+      }
+      qD += __popcll(mD);
+      qN += __popcll(mN);
+      wave_sync();
+      if (qD >= 64) qD = drain(L, L.qD, L.oD, qD, 64, true, lane, K.fd);
+      if (qN >= 64) qN = drain(L, L.qN, L.oN, qN, 64, false, lane, K.fd);
     }
-    if (k < P && !again) w_out[k] = (inside ? 1.0 : 0.0) - kInv4Pi * (light + heavy);
+    if (qD > 0) drain(L, L.qD, L.oD, qD, qD, true, lane, K.fd);
+    if (qN > 0) drain(L, L.qN, L.oN, qN, qN, false, lane, K.fd);
+    wave_sync();
+    if (valid && !again && L.redo[lane] == 0) {
+      w_out[k] = (inside ? 1.0 : 0.0) - kInv4Pi * from_fixed(L.acc[lane]);
+    } else if (valid) {
+      redo[atomicAdd(n_redo, 1)] = (int32_t)k;
+    }
+    wave_fence();
   }
   if (kCount) flush_counters(counters, nfaces, K);
 }
@@ -895,17 +952,20 @@ void exact_integral(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, i
     kt.done();
     return;
   }
-  // persistent two-phase kernel: as many workgroups as stay resident at once
+  // persistent kernel: as many workgroups as stay resident at once
   static int n_cu = 0, per_cu = 0;
   if (n_cu == 0) {
     SPH_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx.device));
-    SPH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_exact_flat<false>, 64 * kFlatWaves, 0));
+    SPH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_exact_edges<false>, 64 * kFlatWaves, 0));
     per_cu = std::max(per_cu, 1);
   }
-  const int cap = kFlatCap;
   const int64_t n_chunks = div_up(P.n_pairs, 64);
   const int64_t grid = std::min<int64_t>((int64_t)n_cu * per_cu, div_up(n_chunks, kFlatWaves));
-  float4 *scratch = ctx.arena.get<float4>("flat_items", grid * kFlatWaves * 64 * cap);
+  const int64_t waves = grid * kFlatWaves;
+  FaceEntry *entries = ctx.arena.get<FaceEntry>("flat_entries", waves * kEntryCap);
+  float4 *egeo = ctx.arena.get<float4>("flat_egeo", waves * kEntryCap);
+  double *edh = ctx.arena.get<double>("flat_edh", waves * kEntryCap);
+  int32_t *eface = ctx.arena.get<int32_t>("flat_eface", waves * 64 * kEdgeCap);
   int32_t *next = ctx.arena.get<int32_t>("flat_next", 2);  // work counter, redo count
   int32_t *redo = ctx.arena.get<int32_t>("flat_redo", P.n_pairs);
   KernelTimer kz(&ctx, "flat_reset", s);
@@ -913,9 +973,9 @@ void exact_integral(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, i
   SPH_LAUNCH_CHECK();
   kz.done();
   KernelTimer kt(&ctx, "exact_integral", s);
-  (ctr ? k_exact_flat<true> : k_exact_flat<false>)<<<(unsigned)grid, 64 * kFlatWaves, 0, s>>>(
-      P.n_pairs, P.pair_c, P.pair_p, p.xyz, p.h, t.gen, t.cell_face_off, t.face_vtx_off, t.fplane, t.fplane32,
-      t.fsphere, t.fvpos32, P.w, ctr, scratch, cap, next, redo, next + 1);
+  (ctr ? k_exact_edges<true> : k_exact_edges<false>)<<<(unsigned)grid, 64 * kFlatWaves, 0, s>>>(
+      P.n_pairs, P.pair_c, P.pair_p, p.xyz, p.h, t.gen, t.cell_face_off, t.face_vtx_off, t.fplane, t.fsphere,
+      t.edgeA, t.edgeE, t.edgeM, P.w, ctr, entries, egeo, edh, eface, next, redo, next + 1);
   SPH_LAUNCH_CHECK();
   kt.done();
   KernelTimer kr(&ctx, "exact_redo", s);

@@ -21,7 +21,8 @@ __global__ void k_face_cell(const int64_t *cfo, int64_t C, int32_t *face_cell) {
 
 __global__ void k_face_prep(int64_t F, const int32_t *face_cell, const double *gen, const double *vert,
                             const int64_t *fvo, const int32_t *fv, double4 *fplane, double4 *fsphere,
-                            double *fvpos, float4 *fvpos32, float4 *fplane32, int *bad) {
+                            double *fvpos, float4 *fvpos32, float4 *fplane32, float4 *edgeA, float4 *edgeE,
+                            float4 *edgeM, int *bad) {
   int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= F) return;
   const int64_t c = face_cell[f];
@@ -82,6 +83,23 @@ __global__ void k_face_prep(int64_t F, const int32_t *face_cell, const double *g
     fvpos[3 * (s + k) + 1] = py;
     fvpos[3 * (s + k) + 2] = pz;
     fvpos32[s + k] = make_float4((float)px, (float)py, (float)pz, 0.0f);
+  }
+  // edges of the oriented polygon, from binary64 vertices
+  for (int k = 0; k < nv; ++k) {
+    const double *A = fvpos + 3 * (s + k);
+    const double *B = fvpos + 3 * (s + (k + 1 == nv ? 0 : k + 1));
+    const double bx = B[0] - A[0], by = B[1] - A[1], bz = B[2] - A[2];
+    const double len = sqrt(bx * bx + by * by + bz * bz);
+    double ex = 0.0, ey = 0.0, ez = 0.0;
+    if (len > 0.0) {
+      ex = bx / len;
+      ey = by / len;
+      ez = bz / len;
+    }
+    const double mx = ny * ez - nz * ey, my = nz * ex - nx * ez, mz = nx * ey - ny * ex;
+    edgeA[s + k] = make_float4((float)A[0], (float)A[1], (float)A[2], (float)len);
+    edgeE[s + k] = make_float4((float)ex, (float)ey, (float)ez, 0.0f);
+    edgeM[s + k] = make_float4((float)mx, (float)my, (float)mz, 0.0f);
   }
 }
 
@@ -156,6 +174,9 @@ void tess_prepare(Ctx &ctx, TessDev &t, hipStream_t s) {
   t.fplane32 = t.mem.get<float4>("fplane32", F);
   t.fvpos = t.mem.get<double>("fvpos", 3 * FV);
   t.fvpos32 = t.mem.get<float4>("fvpos32", FV);
+  t.edgeA = t.mem.get<float4>("edgeA", FV);
+  t.edgeE = t.mem.get<float4>("edgeE", FV);
+  t.edgeM = t.mem.get<float4>("edgeM", FV);
   t.volume = t.mem.get<double>("volume", C);
   t.radius = t.mem.get<float>("radius", C);
   t.gen32 = t.mem.get<float4>("gen32", C);
@@ -166,7 +187,8 @@ void tess_prepare(Ctx &ctx, TessDev &t, hipStream_t s) {
   SPH_LAUNCH_CHECK();
   if (F > 0) {
     k_face_prep<<<(unsigned)div_up(F, 256), 256, 0, s>>>(F, t.face_cell, t.gen, t.vert, t.face_vtx_off, t.face_vtx,
-                                                         t.fplane, t.fsphere, t.fvpos, t.fvpos32, t.fplane32, bad);
+                                                         t.fplane, t.fsphere, t.fvpos, t.fvpos32, t.fplane32,
+                                                         t.edgeA, t.edgeE, t.edgeM, bad);
     SPH_LAUNCH_CHECK();
   }
   k_cell_prep<<<(unsigned)div_up(C, 256), 256, 0, s>>>(C, t.gen, t.vert, t.cell_face_off, t.face_vtx_off,
