@@ -681,7 +681,8 @@ __device__ inline void wave_fence() {
 //   A1 (lane = pair): the cull over the cell's faces (plane distance, face
 //      sphere against the 2h sphere), kept as a bit mask; the faces within
 //      reach are listed pair-major with their foot point, |d| and
-//      |d| H(|d|), and every edge of the chunk is tagged with its face;
+//      |d| H(|d|), and every edge of the chunk gets a record (vertex slot,
+//      face);
 //   A2 (lane = edge): the wave walks those edges 64 at a time; each lane
 //      forms its edge's in-plane geometry from the precomputed edge frame,
 //      adds the angle term -dh (phi_B - phi_A) to its pair, and queues the
@@ -699,14 +700,17 @@ constexpr int kEntryCap = 64 * kMaxFaces;  // face entries per chunk
 constexpr int kEdgeCap = 128;              // candidate edges per pair handled here
 constexpr int kQueue = 128;                // items per LDS queue
 
-struct __align__(16) FaceEntry {
-  float ihf;      // 1/h of the owner (binary32)
-  int32_t vs;     // first vertex slot of the face
-  int32_t start;  // first edge of the face in the chunk's edge space
-  int32_t owner;  // lane of the pair
+struct __align__(16) FaceRec {  // a face within reach of a pair
+  float px, py, pz;  // foot point about the generator (absolute units)
+  float df;          // signed |d| / h, binary32
+  double dh;         // |d| H(|d|)
+  float ihf;         // 1/h of the pair (binary32)
+  int32_t owner;     // lane of the pair
 };
 
 struct EdgeWave {  // per-wavefront LDS
+  double4 wpl[64], wsp[64];  // window of the chunk's faces: plane, bounding sphere
+  int wvs[64], wnv[64];      // first vertex slot, vertex count
   unsigned long long acc[64];
   float4 qD[kQueue], qN[kQueue];
   unsigned char oD[kQueue], oN[kQueue];
@@ -757,16 +761,14 @@ template <bool kCount>
 __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
     int64_t P, const int32_t *pair_c, const int32_t *pair_p, const double *xyz, const double *hh, const double *gen,
     const int64_t *cfo, const int64_t *fvo, const double4 *fplane, const double4 *fsphere, const float4 *edgeA,
-    const float4 *edgeE, const float4 *edgeM, double *w_out, int64_t *counters, FaceEntry *entries, float4 *egeo,
-    double *edh, int32_t *eface, int32_t *next_chunk, int32_t *redo, int32_t *n_redo) {
+    const float4 *edgeE, const float4 *edgeM, double *w_out, int64_t *counters, FaceRec *faces, int2 *edges,
+    int32_t *next_chunk, int32_t *redo, int32_t *n_redo) {
   __shared__ EdgeWave lds[kFlatWaves];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   EdgeWave &L = lds[wid];
   const int64_t wave = (int64_t)blockIdx.x * kFlatWaves + wid;
-  FaceEntry *const ent = entries + wave * kEntryCap;
-  float4 *const eg = egeo + wave * kEntryCap;
-  double *const ed = edh + wave * kEntryCap;
-  int32_t *const ef = eface + wave * 64 * kEdgeCap;
+  FaceRec *const fr = faces + wave * kEntryCap;
+  int2 *const er = edges + wave * 64 * kEdgeCap;  // per edge of the chunk: vertex slot, face record
   const int64_t n_chunks = (P + 63) >> 6;
   Counters K;
   int64_t nfaces = 0;
@@ -778,10 +780,14 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
     const int64_t k = (int64_t)chunk * 64 + lane;
     const bool valid = k < P;
     // ---------------- A1: cull
+    // The chunk's pairs are sorted by cell, so their faces are one range
+    // [F0, F1); it is staged through LDS 64 faces at a time.
+    const int64_t k_last = min((int64_t)chunk * 64 + 63, P - 1);
+    const int64_t F0 = cfo[pair_c[(int64_t)chunk * 64]], F1 = cfo[pair_c[k_last] + 1];
     uint64_t mask = 0;
     int nsurv = 0, nedge = 0;
     bool inside = true, on_boundary = false, again = false;
-    int64_t f0 = 0;
+    int64_t f0 = 0, f1 = 0;
     double xr0 = 0.0, xr1 = 0.0, xr2 = 0.0, ih = 0.0, h = 0.0;
     if (valid) {
       const int64_t c = pair_c[k];
@@ -792,33 +798,50 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
       xr1 = xyz[3 * i + 1] - gen[3 * c + 1];
       xr2 = xyz[3 * i + 2] - gen[3 * c + 2];
       f0 = cfo[c];
-      const int nf = (int)(cfo[c + 1] - f0);
-      nfaces += nf;
-      if (nf > kMaxFaces) again = true;
-      for (int j = 0; j < nf && !again; ++j) {
-        const int64_t f = f0 + j;
-        const double4 pl = fplane[f];
-        if (!(pl.w > 0.0)) continue;
-        const double dist = pl.w - (pl.x * xr0 + pl.y * xr1 + pl.z * xr2);
-        if (dist < 0.0) inside = false;
-        if (dist == 0.0) {
-          on_boundary = true;
-          continue;
+      f1 = cfo[c + 1];
+      nfaces += f1 - f0;
+      if (f1 - f0 > kMaxFaces) again = true;
+    }
+    for (int64_t wb = F0; wb < F1; wb += 64) {
+      {
+        const int64_t f = wb + lane;
+        if (f < F1) {
+          L.wpl[lane] = fplane[f];
+          L.wsp[lane] = fsphere[f];
+          const int64_t vs = fvo[f];
+          L.wvs[lane] = (int)vs;
+          L.wnv[lane] = (int)(fvo[f + 1] - vs);
         }
-        if (fabs(dist) >= 2.0 * h) continue;
-        const double4 sp = fsphere[f];
-        const double sx = xr0 - sp.x, sy = xr1 - sp.y, sz = xr2 - sp.z;
-        const double reach = sp.w + 2.0 * h;
-        if (sx * sx + sy * sy + sz * sz >= reach * reach) continue;
-        if (fabs(dist * ih) < kDegenerate) {
-          ++K.n64;
-          again = true;
-          break;
-        }
-        mask |= 1ull << j;
-        ++nsurv;
-        nedge += (int)(fvo[f + 1] - fvo[f]);
       }
+      wave_sync();
+      if (valid && !again) {
+        const int64_t ja = max(f0, wb) - wb, jb = min(f1, wb + 64) - wb;
+        for (int64_t j = ja; j < jb; ++j) {
+          const double4 pl = L.wpl[j];
+          if (!(pl.w > 0.0)) continue;
+          const double dist = pl.w - (pl.x * xr0 + pl.y * xr1 + pl.z * xr2);
+          if (dist < 0.0) inside = false;
+          if (dist == 0.0) {
+            on_boundary = true;
+            continue;
+          }
+          const double4 sp = L.wsp[j];
+          const double sx = xr0 - sp.x, sy = xr1 - sp.y, sz = xr2 - sp.z;
+          const double reach = sp.w + 2.0 * h;
+          if (fabs(dist) >= 2.0 * h || sx * sx + sy * sy + sz * sz >= reach * reach) continue;
+          if (fabs(dist * ih) < kDegenerate) {
+            ++K.n64;
+            again = true;
+            break;
+          }
+          mask |= 1ull << (wb + j - f0);
+          ++nsurv;
+          nedge += L.wnv[j];
+        }
+      }
+      wave_sync();
+    }
+    if (valid) {
       again |= nedge > kEdgeCap || (inside && on_boundary);
       if (again) {
         mask = 0;
@@ -831,65 +854,80 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
     L.acc[lane] = 0ull;
     L.redo[lane] = again ? 1 : 0;
     if (kCount) K.nf_int += nsurv;
-    // ---------------- A1b: the face list, pair-major, and each edge's face
-    if (valid && !again) {
+    // ---------------- A1b: the face list, pair-major, and each edge's record
+    {
       int e = e_off, start = x_off;
-      uint64_t m = mask;
-      while (m) {
-        const int j = __builtin_ctzll(m);
-        m &= m - 1;
-        const int64_t f = f0 + j;
-        const double4 pl = fplane[f];
-        const double dist = pl.w - (pl.x * xr0 + pl.y * xr1 + pl.z * xr2);
-        const int64_t vs = fvo[f];
-        const int nv = (int)(fvo[f + 1] - vs);
-        // |d| rounded to binary32, like the rest of the face's geometry
-        const float df = (float)(dist * ih);
-        FaceEntry fe;
-        fe.ihf = (float)ih;
-        fe.vs = (int32_t)vs;
-        fe.start = start;
-        fe.owner = lane;
-        ent[e] = fe;
-        eg[e] = make_float4((float)(xr0 + dist * pl.x), (float)(xr1 + dist * pl.y), (float)(xr2 + dist * pl.z), df);
-        ed[e] = dH((double)fabsf(df));
-        for (int q = 0; q < nv; ++q) ef[start + q] = e;
-        ++e;
-        start += nv;
+      for (int64_t wb = F0; wb < F1; wb += 64) {
+        if (F1 - F0 > 64) {  // a single window is still staged from the cull
+          const int64_t f = wb + lane;
+          if (f < F1) {
+            L.wpl[lane] = fplane[f];
+            const int64_t vs = fvo[f];
+            L.wvs[lane] = (int)vs;
+            L.wnv[lane] = (int)(fvo[f + 1] - vs);
+          }
+        }
+        wave_sync();
+        const int64_t ja = max(f0, wb) - wb, jb = min(f1, wb + 64) - wb;
+        if (mask && ja < jb) {
+          uint64_t m = mask & lanes_in((int)(wb + ja - f0), (int)(wb + jb - f0));
+          while (m) {
+            const int j = (int)(__builtin_ctzll(m) - (wb - f0));
+            m &= m - 1;
+            const double4 pl = L.wpl[j];
+            const double dist = pl.w - (pl.x * xr0 + pl.y * xr1 + pl.z * xr2);
+            const int vs = L.wvs[j], nv = L.wnv[j];
+            // |d| rounded to binary32, like the rest of the face's geometry
+            const float df = (float)(dist * ih);
+            FaceRec rec;
+            rec.px = (float)(xr0 + dist * pl.x);
+            rec.py = (float)(xr1 + dist * pl.y);
+            rec.pz = (float)(xr2 + dist * pl.z);
+            rec.df = df;
+            rec.dh = dH((double)fabsf(df));
+            rec.ihf = (float)ih;
+            rec.owner = lane;
+            fr[e] = rec;
+            for (int q = 0; q < nv; ++q) er[start + q] = make_int2(vs + q, e);
+            ++e;
+            start += nv;
+          }
+        }
+        wave_sync();
       }
     }
     wave_fence();
     // ---------------- A2: one edge per lane; B whenever a queue fills
     int qD = 0, qN = 0;
+    int2 rec_next = lane < n_edge ? er[lane] : make_int2(0, 0);
     for (int b = 0; b < n_edge; b += 64) {
       const int g = b + lane;
       const bool live = g < n_edge;
+      const int2 rec = rec_next;
+      if (g + 64 < n_edge) rec_next = er[g + 64];  // next batch, in flight meanwhile
       int owner = 0;
       bool integ = false, cross = false;
       float4 it = make_float4(0.f, 0.f, 0.f, 0.f);
       if (live) {
-        const int e = ef[g];
-        const FaceEntry fe = ent[e];
-        owner = fe.owner;
-        const int64_t slot = fe.vs + (g - fe.start);
-        const float4 EA = edgeA[slot];
+        const FaceRec fc = fr[rec.y];
+        owner = fc.owner;
+        const float4 EA = edgeA[rec.x];
         if (EA.w > 0.0f) {
-          const float4 geo = eg[e];  // foot point about g (absolute), signed |d|/h
-          const float4 EE = edgeE[slot], EM = edgeM[slot];
-          const float dx = geo.x - EA.x, dy = geo.y - EA.y, dz = geo.z - EA.z;
-          const float p = (dx * EM.x + dy * EM.y + dz * EM.z) * fe.ihf;
+          const float4 EE = edgeE[rec.x], EM = edgeM[rec.x];
+          const float dx = fc.px - EA.x, dy = fc.py - EA.y, dz = fc.pz - EA.z;
+          const float p = (dx * EM.x + dy * EM.y + dz * EM.z) * fc.ihf;
           if (p != 0.0f) {
             if (fabsf(p) < kDegenerate) {
               ++K.n64;
               L.redo[owner] = 1;  // binary64 geometry for this pair
             } else {
               ++K.ne_vis;
-              const float tA = -(dx * EE.x + dy * EE.y + dz * EE.z) * fe.ihf;
-              const float tB = fmaf(EA.w, fe.ihf, tA);
+              const float tA = -(dx * EE.x + dy * EE.y + dz * EE.z) * fc.ihf;
+              const float tB = fmaf(EA.w, fc.ihf, tA);
               const double ap = (double)fabsf(p), dA = (double)tA, dB = (double)tB;
-              const double ad = (double)fabsf(geo.w);
-              const double ang = -ed[e] * MathMixed::span(ap, dA, dB);
-              atomicAdd(&L.acc[owner], to_fixed(((p > 0.0f) == (geo.w > 0.0f)) ? ang : -ang));
+              const double ad = (double)fabsf(fc.df);
+              const double ang = -fc.dh * MathMixed::span(ap, dA, dB);
+              atomicAdd(&L.acc[owner], to_fixed(((p > 0.0f) == (fc.df > 0.0f)) ? ang : -ang));
               // within 2h somewhere on [tA, tB], and crossing U = 1 (squares, no roots)
               const double a2 = ad * ad + ap * ap;
               const double r2 = 4.0 - a2, s1 = 1.0 - a2;
@@ -900,7 +938,7 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
                 cross = lo || hi;
               }
               K.ne_int += integ;
-              it = make_float4(geo.w, p, tA, tB);
+              it = make_float4(fc.df, p, tA, tB);
             }
           }
         }
@@ -962,10 +1000,8 @@ void exact_integral(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, i
   const int64_t n_chunks = div_up(P.n_pairs, 64);
   const int64_t grid = std::min<int64_t>((int64_t)n_cu * per_cu, div_up(n_chunks, kFlatWaves));
   const int64_t waves = grid * kFlatWaves;
-  FaceEntry *entries = ctx.arena.get<FaceEntry>("flat_entries", waves * kEntryCap);
-  float4 *egeo = ctx.arena.get<float4>("flat_egeo", waves * kEntryCap);
-  double *edh = ctx.arena.get<double>("flat_edh", waves * kEntryCap);
-  int32_t *eface = ctx.arena.get<int32_t>("flat_eface", waves * 64 * kEdgeCap);
+  FaceRec *faces = ctx.arena.get<FaceRec>("flat_faces", waves * kEntryCap);
+  int2 *edges = ctx.arena.get<int2>("flat_edges", waves * 64 * kEdgeCap);
   int32_t *next = ctx.arena.get<int32_t>("flat_next", 2);  // work counter, redo count
   int32_t *redo = ctx.arena.get<int32_t>("flat_redo", P.n_pairs);
   KernelTimer kz(&ctx, "flat_reset", s);
@@ -975,7 +1011,7 @@ void exact_integral(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, i
   KernelTimer kt(&ctx, "exact_integral", s);
   (ctr ? k_exact_edges<true> : k_exact_edges<false>)<<<(unsigned)grid, 64 * kFlatWaves, 0, s>>>(
       P.n_pairs, P.pair_c, P.pair_p, p.xyz, p.h, t.gen, t.cell_face_off, t.face_vtx_off, t.fplane, t.fsphere,
-      t.edgeA, t.edgeE, t.edgeM, P.w, ctr, entries, egeo, edh, eface, next, redo, next + 1);
+      t.edgeA, t.edgeE, t.edgeM, P.w, ctr, faces, edges, next, redo, next + 1);
   SPH_LAUNCH_CHECK();
   kt.done();
   KernelTimer kr(&ctx, "exact_redo", s);
