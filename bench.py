@@ -158,7 +158,7 @@ def main():
     workload = f"turbulent_{args.n}"
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_TFLOPS, 4), "traffic": measured_traffic(args.precision, workload),
-                "kernel": "exact_integral" + (" (k_exact_flat + k_exact_mixed_list)" if args.precision == "mixed"
+                "kernel": "exact_integral" + (" (k_exact_edges + k_exact_mixed_list)" if args.precision == "mixed"
                                               else " (k_exact_fp64)"),
                 "kernel_ms": round(k_avg_s * 1e3, 4), "flop_per_pair": round(flop_per_pair, 1)}
 
