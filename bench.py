@@ -78,6 +78,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=30000, help="cells of the oracle CPU baseline (about 10-15 s)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=3, help="timed steps of the plain binary64 path")
+    ap.add_argument("--workload", default="turbulent", choices=["turbulent", "pseudo"],
+                    help="turbulent: the 262,144-particle cloud (default); pseudo: 1,048,576 particles collapsed "
+                         "to tree-node pseudo-particles around the densest particle, mapped on the mixed set's grid")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -85,6 +88,8 @@ def main():
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is a design in DESIGN.md, not a measured path", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "pseudo":
+        return run_pseudo(args)
 
     import numpy as np
     import torch
@@ -233,6 +238,112 @@ def main():
     }
     print(json.dumps(out), flush=True)
     dt.free()
+    ctx.close()
+
+
+def run_pseudo(args):
+    """Tree-based pseudo-particles (Sec. 2.4) on a 1,048,576-particle
+    turbulent cloud (seed 3) with one source at its densest particle:
+    r_part = 0.2, theta = 0.5, h_fact = 1.2, eps_h = 1e-2.  The mixed set
+    (pseudo-particles + real particles near the source) is mapped onto the
+    Voronoi grid of its own positions; the same mapping of all particles on
+    their own grid is timed beside it.  One timed step = the pseudo-particle
+    build + the forward and inverse mapping of the mixed set."""
+    import numpy as np
+    import torch
+
+    import paper_2410_15227_amd as pkg
+    from paper_2410_15227_amd import workloads
+
+    n_all = 1 << 20
+    t0 = time.time()
+    pos, m, h, rho = workloads.make_cloud("turbulent", n_all, 3)
+    src = pos[workloads.densest_particle(rho)]
+    log(f"inputs: turbulent_{n_all} (seed 3) in {time.time() - t0:.1f}s; source {src}")
+    ctx = pkg.Context(0)
+    dev = ctx.device
+    xyz = torch.tensor(pos, dtype=torch.float64, device=dev)
+    hd = torch.tensor(h, dtype=torch.float64, device=dev)
+    md = torch.tensor(m, dtype=torch.float64, device=dev)
+    opts = dict(r_part=0.2, theta=0.5, h_fact=1.2, eps_h=1e-2)
+
+    def build():
+        return pkg.build_pseudo_particles(ctx, xyz, hd, md, [src], **opts)
+
+    ps = build()
+    torch.cuda.synchronize()
+    mix_pos = ps["xyz"].cpu().numpy()
+    mix_h = ps["h"].cpu().numpy()
+    mix_m = ps["m"].cpu().numpy()
+    n_mix = len(mix_m)
+    if len(np.unique(mix_pos, axis=0)) != n_mix:
+        raise RuntimeError("coincident positions in the mixed set: its Voronoi grid is undefined")
+    t0 = time.time()
+    tess_mix = workloads.voronoi(mix_pos)
+    vor_mix_s = time.time() - t0
+    t0 = time.time()
+    tess_all = workloads.voronoi(pos)
+    vor_all_s = time.time() - t0
+    log(f"mixed set {n_mix} ({ps['stats']}); Voronoi {vor_mix_s:.1f}s (mixed), {vor_all_s:.1f}s (all)")
+
+    mix_xyz = torch.tensor(mix_pos, dtype=torch.float64, device=dev)
+    mix_hd = torch.tensor(mix_h, dtype=torch.float64, device=dev)
+    mix_md = torch.tensor(mix_m, dtype=torch.float64, device=dev)
+    dt_mix = ctx.upload(tess_mix)
+    dt_all = ctx.upload(tess_all)
+
+    def mapping(dt, x, hh, mm, n_cells):
+        res = pkg.map_particles_to_cells(ctx, dt, x, hh, mm, precision=args.precision, keep_pairs=True)
+        q = torch.ones(n_cells, dtype=torch.float64, device=dev)
+        pkg.map_cells_to_particles(ctx, res.pairs, q)
+        return res
+
+    def timed(fn, steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = None
+        for _ in range(steps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, out
+
+    build_s, _ = timed(build, args.steps)
+    mix_s, res_mix = timed(lambda: mapping(dt_mix, mix_xyz, mix_hd, mix_md, tess_mix.n_cells), args.steps)
+    all_s, res_all = timed(lambda: mapping(dt_all, xyz, hd, md, tess_all.n_cells), max(1, args.steps // 2))
+    pairs_mix, pairs_all = res_mix.pairs.n_pairs, res_all.pairs.n_pairs
+    tot_mix = float(res_mix.mass.sum().item())
+    tot_all = float(res_all.mass.sum().item())
+    step_s = build_s + mix_s
+    out = {
+        "metric": "particle-cell pair integrals/s",
+        "value": round(pairs_mix / mix_s, 1),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_s * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"pseudo_{n_all}", "n_particles": n_all, "precision": args.precision,
+                   "sigma_lnrho": 1.5, "r_part": 0.2, "theta": 0.5, "h_fact": 1.2, "eps_h": 1e-2},
+        "pseudo": {"n_mixed": n_mix, "n_pseudo": ps["stats"]["n_pseudo"], "n_real": ps["stats"]["n_real"],
+                   "n_nodes": ps["stats"]["n_nodes"], "h_branches": ps["stats"]["branch_count"],
+                   "pairs_all": int(pairs_all), "pairs_mixed": int(pairs_mix),
+                   "pair_reduction": round(pairs_all / max(pairs_mix, 1), 3),
+                   "build_ms": round(build_s * 1e3, 3), "map_mixed_ms": round(mix_s * 1e3, 3),
+                   "map_all_ms": round(all_s * 1e3, 3),
+                   "speedup_vs_all_particles": round(all_s / step_s, 3),
+                   "mass_mixed_grid": tot_mix, "mass_all_grid": tot_all,
+                   "host_voronoi_s": {"mixed": round(vor_mix_s, 2), "all": round(vor_all_s, 2)}},
+    }
+    print(json.dumps(out), flush=True)
+    dt_mix.free()
+    dt_all.free()
     ctx.close()
 
 

@@ -167,8 +167,10 @@ __global__ void k_com(int64_t nn, const double *M, const double4 *S, double4 *co
   com[node] = make_double4(s.x / mm, s.y / mm, s.z / mm, 0.0);
 }
 
-// One wave per node: max squared member distance from the centre of mass
-// and the lowest member particle index.
+constexpr int kBigNode = 4096;  // members above which a node's size takes a whole workgroup
+
+// One wave per node of at most kBigNode members: max squared member
+// distance from the centre of mass and the lowest member particle index.
 __global__ void __launch_bounds__(256) k_node_size(NodeArrays N, int64_t nn, const int32_t *sidx, const double *xyz,
                                                   const double4 *com, double *s2, int32_t *minidx) {
 #pragma clang fp contract(off)
@@ -176,6 +178,7 @@ __global__ void __launch_bounds__(256) k_node_size(NodeArrays N, int64_t nn, con
   const int lane = threadIdx.x & 63;
   if (node >= nn) return;
   const int32_t f = N.first[node], c = N.count[node];
+  if (c > kBigNode) return;
   const double4 g = com[node];
   double mx = 0.0;
   int32_t mi = INT32_MAX;
@@ -193,6 +196,62 @@ __global__ void __launch_bounds__(256) k_node_size(NodeArrays N, int64_t nn, con
   if (lane == 0) {
     s2[node] = mx;
     minidx[node] = mi;
+  }
+}
+
+__global__ void k_flag_big(NodeArrays N, int64_t nn, int64_t *flag) {
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node < nn) flag[node] = N.count[node] > kBigNode ? 1 : 0;
+}
+
+__global__ void k_list_big(NodeArrays N, int64_t nn, const int64_t *off, int32_t *list) {
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node < nn && N.count[node] > kBigNode) list[off[node]] = (int32_t)node;
+}
+
+// The same for the nodes above kBigNode members, one workgroup per node
+// (grid-stride over the device-side list; max and min do not depend on the
+// order in which the waves finish).
+__global__ void __launch_bounds__(1024) k_node_size_big(NodeArrays N, const int32_t *list, const int64_t *n_list,
+                                                       const int32_t *sidx, const double *xyz, const double4 *com,
+                                                       double *s2, int32_t *minidx) {
+#pragma clang fp contract(off)
+  __shared__ double smx[16];
+  __shared__ int32_t smi[16];
+  const int64_t nb = *n_list;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int32_t node = list[b];
+    const int32_t f = N.first[node], c = N.count[node];
+    const double4 g = com[node];
+    double mx = 0.0;
+    int32_t mi = INT32_MAX;
+    for (int32_t t = f + (int32_t)threadIdx.x; t < f + c; t += (int32_t)blockDim.x) {
+      const int32_t j = sidx[t];
+      const double dx = xyz[3 * (int64_t)j] - g.x, dy = xyz[3 * (int64_t)j + 1] - g.y,
+                   dz = xyz[3 * (int64_t)j + 2] - g.z;
+      const double s = (dx * dx + dy * dy) + dz * dz;
+      mx = fmax(mx, s);
+      mi = min(mi, j);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      mx = fmax(mx, __shfl_xor(mx, o, 64));
+      mi = min(mi, __shfl_xor(mi, o, 64));
+    }
+    if (lane == 0) {
+      smx[wid] = mx;
+      smi[wid] = mi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+        mx = fmax(mx, smx[w]);
+        mi = min(mi, smi[w]);
+      }
+      s2[node] = mx;
+      minidx[node] = mi;
+    }
+    __syncthreads();
   }
 }
 
@@ -306,7 +365,6 @@ __global__ void k_entries(int64_t nu, const int32_t *units, NodeArrays N, const 
   }
 }
 
-constexpr int kHBlock = 256;
 constexpr double kInvPi = 0.31830988618379067154;
 
 __device__ inline double m4w(double q) {
@@ -322,64 +380,70 @@ __device__ inline double m4dw(double q) {
   return 0.0;
 }
 
-// Node h-solve: one thread per pseudo-particle, all units streamed through
-// LDS once per round; each thread advances its own Newton / bisection state.
-__global__ void __launch_bounds__(kHBlock) k_hsolve(int64_t np, const int32_t *plist, int64_t nu, const double4 *upos,
-                                                    const double *o_xyz, const double *o_s, double hfact, double eps,
-                                                    int64_t bypass, double *o_h, int32_t *o_branch,
-                                                    unsigned long long *bcount) {
+__device__ inline double readlane_d(double v, int j) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, j);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), j);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+constexpr int kHWaves = 4;  // pseudo-particles per workgroup
+
+// Node h-solve: one wavefront per pseudo-particle.  Each Newton or
+// bisection step needs the sums over all units within 2h; the 64 lanes
+// evaluate 64 consecutive units at a time and the terms that are not zero
+// are added in unit order, so the sums are those of a plain sequential loop.
+__global__ void __launch_bounds__(64 * kHWaves) k_hsolve(int64_t np, const int32_t *plist, int64_t nu,
+                                                        const double4 *upos, const double *o_xyz, const double *o_s,
+                                                        double hfact, double eps, int64_t bypass, double *o_h,
+                                                        int32_t *o_branch, unsigned long long *bcount) {
 #pragma clang fp contract(off)
-  __shared__ double tx[kHBlock], ty[kHBlock], tz[kHBlock];
-  const int64_t pid = (int64_t)blockIdx.x * kHBlock + threadIdx.x;
-  const bool valid = pid < np;
-  int32_t e = valid ? plist[pid] : 0;
-  double ax = 0, ay = 0, az = 0, s = 0;
-  if (valid) {
-    ax = o_xyz[3 * (int64_t)e];
-    ay = o_xyz[3 * (int64_t)e + 1];
-    az = o_xyz[3 * (int64_t)e + 2];
-    s = o_s[e];
-  }
+  const int64_t pid = (int64_t)blockIdx.x * kHWaves + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (pid >= np) return;  // the whole wavefront
+  const int32_t e = plist[pid];
+  const double ax = o_xyz[3 * (int64_t)e], ay = o_xyz[3 * (int64_t)e + 1], az = o_xyz[3 * (int64_t)e + 2];
+  const double s = o_s[e];
   const double h0 = hfact * 2.0 * s;
   double lo = 1e-2 * h0, hi = 1e2 * h0;
   double h = h0, flo = 0.0, hres = h0;
-  int phase = valid ? 0 : 9;  // 0 Newton, 1 eval lo, 2 eval hi, 3 bisect, 9 done
+  int phase = 0;  // 0 Newton, 1 eval lo, 2 eval hi, 3 bisect, 9 done
   int it = 0, branch = 0;
-  if (valid && np > bypass) {
+  if (np > bypass) {
     hres = h0;
     branch = 3;
     phase = 9;
   }
-  while (__syncthreads_or(phase != 9)) {
-    // point at which this thread needs the sums
+  while (phase != 9) {
+    // point at which the sums are needed
     double he = h;
     if (phase == 1) he = lo;
     else if (phase == 2) he = hi;
     else if (phase == 3) he = 0.5 * (lo + hi);
     const double ih = 1.0 / he;
     double sw = 0.0, sd = 0.0;
-    for (int64_t b0 = 0; b0 < nu; b0 += kHBlock) {
-      __syncthreads();
-      if (b0 + threadIdx.x < nu) {
-        const double4 p = upos[b0 + threadIdx.x];
-        tx[threadIdx.x] = p.x;
-        ty[threadIdx.x] = p.y;
-        tz[threadIdx.x] = p.z;
-      }
-      __syncthreads();
-      if (phase != 9) {
-        const int lim = (int)min((int64_t)kHBlock, nu - b0);
-        for (int q = 0; q < lim; ++q) {
-          const double dx = ax - tx[q], dy = ay - ty[q], dz = az - tz[q];
-          const double qq = sqrt((dx * dx + dy * dy) + dz * dz) * ih;
-          if (qq >= 2.0) continue;
-          const double w = m4w(qq);
-          sw += w;
-          sd += -(3.0 * w + qq * m4dw(qq));
+    for (int64_t b0 = 0; b0 < nu; b0 += 64) {
+      const int64_t u = b0 + lane;
+      double w = 0.0, dt = 0.0;
+      bool hit = false;
+      if (u < nu) {
+        const double4 p = upos[u];
+        const double dx = ax - p.x, dy = ay - p.y, dz = az - p.z;
+        const double qq = sqrt((dx * dx + dy * dy) + dz * dz) * ih;
+        if (qq < 2.0) {
+          hit = true;
+          w = m4w(qq);
+          dt = -(3.0 * w + qq * m4dw(qq));
         }
       }
+      uint64_t mask = __ballot(hit);
+      while (mask) {
+        const int j = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        sw += readlane_d(w, j);
+        sd += readlane_d(dt, j);
+      }
     }
-    if (phase == 9) continue;
     const double n = sw * ih * ih * ih * kInvPi;
     const double dn = sd * ih * ih * ih * ih * kInvPi;
     const double f = hfact * pow(n, -1.0 / 3.0) - he;
@@ -447,7 +511,7 @@ __global__ void __launch_bounds__(kHBlock) k_hsolve(int64_t np, const int32_t *p
       }
     }
   }
-  if (valid) {
+  if (lane == 0) {
     o_h[e] = hres;
     if (o_branch) o_branch[e] = branch;
     atomicAdd(&bcount[branch], 1ull);
@@ -546,6 +610,21 @@ void pseudo_build(Ctx &ctx, PseudoArgs &a, hipStream_t s) {
   SPH_LAUNCH_CHECK();
   k_node_size<<<(unsigned)div_up(nn * 64, 256), 256, 0, s>>>(N, nn, sidx, a.xyz, com, s2, minidx);
   SPH_LAUNCH_CHECK();
+  {
+    int64_t *bflag = ar.get<int64_t>("ps_bflag", nn + 1);
+    int64_t *boff = ar.get<int64_t>("ps_boff", nn + 1);
+    int32_t *blist = ar.get<int32_t>("ps_blist", std::max<int64_t>(nn, 1));
+    k_flag_big<<<(unsigned)div_up(nn, 256), 256, 0, s>>>(N, nn, bflag);
+    SPH_LAUNCH_CHECK();
+    scan_exclusive_i64(ar, bflag, boff, nn, true, s);
+    k_list_big<<<(unsigned)div_up(nn, 256), 256, 0, s>>>(N, nn, boff, blist);
+    SPH_LAUNCH_CHECK();
+    // at most n / kBigNode big nodes per level
+    const int64_t bound = std::max<int64_t>(1, (int64_t)(loff.size() - 1) * (n / kBigNode + 1));
+    k_node_size_big<<<(unsigned)std::min<int64_t>(bound, 2048), 1024, 0, s>>>(N, blist, boff + nn, sidx, a.xyz, com,
+                                                                              s2, minidx);
+    SPH_LAUNCH_CHECK();
+  }
   double *src = ar.get<double>("ps_src", 3 * a.n_src);
   SPH_HIP(hipMemcpyAsync(src, a.src, 3 * a.n_src * sizeof(double), hipMemcpyHostToDevice, s));
   k_accept<<<(unsigned)div_up(nn, 256), 256, 0, s>>>(nn, com, s2, a.n_src, src, o.r_part, o.theta, acc);
@@ -599,7 +678,7 @@ void pseudo_build(Ctx &ctx, PseudoArgs &a, hipStream_t s) {
   SPH_HIP(hipMemsetAsync(bcount, 0, 4 * sizeof(unsigned long long), s));
   if (np > 0) {
     KernelTimer kt(&ctx, "node_hsolve", s);
-    k_hsolve<<<(unsigned)div_up(np, kHBlock), kHBlock, 0, s>>>(np, plist, nu, upos, a.o_xyz, o_s, o.h_fact, o.eps_h,
+    k_hsolve<<<(unsigned)div_up(np, kHWaves), 64 * kHWaves, 0, s>>>(np, plist, nu, upos, a.o_xyz, o_s, o.h_fact, o.eps_h,
                                                                 o.bypass_threshold, a.o_h, a.o_branch, bcount);
     SPH_LAUNCH_CHECK();
     kt.done();
