@@ -127,6 +127,27 @@ int map_particles_to_cells(sphmap_ctx *ctx, const sphmap_tess *tess, int64_t n, 
                            double *d_cell_mass, double *d_cell_density, double *d_coverage, void *stream,
                            sphmap_pairs **pairs_out);
 
+/* ------------------------------------------------------------------------
+ * Batched forward mapping: n_inst independent instances (the forward map
+ * above, each with its own tessellation and particles) in one call.  The
+ * candidate pairs are found per instance; the Exact integral of all
+ * instances runs as one persistent launch, each 64-pair chunk of work
+ * belonging to one instance; the reductions run per instance.  A weight
+ * depends on its own pair only, so every instance's results equal those of
+ * map_particles_to_cells on that instance alone, bit for bit.
+ *   tess[k], n[k], d_xyz[k], d_h[k], d_m[k], d_cell_mass[k]: as in the
+ *   single call (host arrays of n_inst entries holding device pointers);
+ *   d_cell_density, d_coverage: NULL, or host arrays whose entries may be
+ *   NULL; pairs_out: NULL, or a host array receiving n_inst retained lists.
+ * Errors: as the single call, per instance; EINVAL for n_inst < 1.  On an
+ * error no list is returned.
+ * ---------------------------------------------------------------------- */
+int map_particles_to_cells_batch(sphmap_ctx *ctx, int32_t n_inst, const sphmap_tess *const *tess, const int64_t *n,
+                                 const double *const *d_xyz, const double *const *d_h, const double *const *d_m,
+                                 int32_t precision, int32_t normalize, double *const *d_cell_mass,
+                                 double *const *d_cell_density, double *const *d_coverage, void *stream,
+                                 sphmap_pairs **pairs_out);
+
 /* Number of candidate pairs, cells and particles of a retained pair list. */
 int sphmap_pairs_info(const sphmap_pairs *pairs, int64_t *n_pairs, int64_t *n_cells, int64_t *n_particles);
 /* Copy the retained list into caller device buffers (any may be NULL):

@@ -211,6 +211,43 @@ def map_particles_to_cells(ctx: Context, tess: DeviceTessellation, xyz, h, m, pr
     return MapResult(mass, dens, cov, pairs)
 
 
+def map_particles_to_cells_batch(ctx: Context, tess, xyz, h, m, precision: str | int = "mixed",
+                                 normalize: bool = False, keep_pairs: bool = False, with_coverage: bool = True,
+                                 stream=None) -> list:
+    """Forward mapping of several independent instances in one call (lists
+    of tessellations and per-instance particle arrays); returns one
+    MapResult per instance."""
+    torch = _torch()
+    dev = ctx.device
+    k = len(tess)
+    if not (len(xyz) == len(h) == len(m) == k) or k < 1:
+        raise ValueError("tess, xyz, h and m must be lists of the same non-zero length")
+    xs = [_dev_f64(a, dev, 3) for a in xyz]
+    hs = [_dev_f64(a, dev) for a in h]
+    ms = [_dev_f64(a, dev) for a in m]
+    ns = [a.shape[0] for a in xs]
+    for x, hh, mm, n in zip(xs, hs, ms, ns):
+        if hh.shape != (n,) or mm.shape != (n,):
+            raise ValueError("h and m must have shape [n] per instance")
+    prec = {"fp64": PREC_FP64, "mixed": PREC_MIXED}.get(precision, precision)
+    mass = [torch.empty(t.n_cells, dtype=torch.float64, device=dev) for t in tess]
+    dens = [torch.empty(t.n_cells, dtype=torch.float64, device=dev) for t in tess]
+    cov = [torch.empty(n, dtype=torch.float64, device=dev) for n in ns] if with_coverage else None
+    P = ctypes.c_void_p * k
+    arr = lambda ts: P(*[_ptr(t) for t in ts])
+    th = P(*[t.handle for t in tess])
+    nn = (ctypes.c_int64 * k)(*ns)
+    ph = P()
+    ctx.check(_native.lib().map_particles_to_cells_batch(
+        ctx.handle, k, th, nn, arr(xs), arr(hs), arr(ms), int(prec), 1 if normalize else 0, arr(mass), arr(dens),
+        arr(cov) if cov is not None else None, _stream_handle(stream), ph if keep_pairs else None))
+    out = []
+    for j in range(k):
+        pairs = Pairs(ctx, ctypes.c_void_p(ph[j])) if keep_pairs else None
+        out.append(MapResult(mass[j], dens[j], cov[j] if cov is not None else None, pairs))
+    return out
+
+
 def map_cells_to_particles(ctx: Context, pairs: Pairs, cell_values, out=None, stream=None):
     """Inverse mapping q_i = sum_c w_ic q_c / c_i ([C] or [C,k] -> [n] or [n,k])."""
     torch = _torch()

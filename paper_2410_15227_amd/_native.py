@@ -18,7 +18,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 EXPORTS = [
     "sphmap_version", "sphmap_create", "sphmap_destroy", "sphmap_last_error",
     "sphmap_tess_upload", "sphmap_tess_free", "sphmap_tess_cell_info",
-    "map_particles_to_cells", "sphmap_pairs_info", "sphmap_pairs_export", "sphmap_pairs_free",
+    "map_particles_to_cells", "map_particles_to_cells_batch", "sphmap_pairs_info", "sphmap_pairs_export", "sphmap_pairs_free",
     "map_cells_to_particles", "build_pseudo_particles",
     "sphmap_set_timing", "sphmap_kernel_time", "sphmap_reset_timing",
     "sphmap_set_counting", "sphmap_work_counters",
@@ -70,6 +70,8 @@ def lib():
         L.sphmap_tess_cell_info.argtypes = [vp, vp, vp, vp, vp]
         L.map_particles_to_cells.restype = ctypes.c_int
         L.map_particles_to_cells.argtypes = [vp, vp, i64, vp, vp, vp, i32, i32, vp, vp, vp, vp, pp]
+        L.map_particles_to_cells_batch.restype = ctypes.c_int
+        L.map_particles_to_cells_batch.argtypes = [vp, i32, vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp]
         L.sphmap_pairs_info.restype = ctypes.c_int
         L.sphmap_pairs_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.sphmap_pairs_export.restype = ctypes.c_int

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <vector>
 
 #include "common.hpp"
 
@@ -76,6 +77,10 @@ int sphmap_destroy(sphmap_ctx *ctx) {
     }
   delete ctx->c.scratch_pairs;
   ctx->c.scratch_pairs = nullptr;
+  for (auto *P : ctx->c.scratch_batch) delete P;
+  ctx->c.scratch_batch.clear();
+  if (ctx->c.pinned) (void)hipHostFree(ctx->c.pinned);
+  ctx->c.pinned = nullptr;
   delete ctx;
   return SPHMAP_OK;
 }
@@ -209,6 +214,71 @@ int map_particles_to_cells(sphmap_ctx *ctx, const sphmap_tess *tess, int64_t n, 
     }
   });
   if (rc == SPHMAP_OK && pairs_out) *pairs_out = owned.release();
+  return rc;
+}
+
+int map_particles_to_cells_batch(sphmap_ctx *ctx, int32_t n_inst, const sphmap_tess *const *tess, const int64_t *n,
+                                 const double *const *d_xyz, const double *const *d_h, const double *const *d_m,
+                                 int32_t precision, int32_t normalize, double *const *d_cell_mass,
+                                 double *const *d_cell_density, double *const *d_coverage, void *stream,
+                                 sphmap_pairs **pairs_out) {
+  if (!ctx) return SPHMAP_EINVAL;
+  std::vector<std::unique_ptr<sphmap_pairs>> owned;
+  int rc = guarded(ctx, [&] {
+    SPH_REQUIRE(n_inst >= 1, SPHMAP_EINVAL, "n_inst < 1");
+    SPH_REQUIRE(tess && n && d_xyz && d_h && d_m && d_cell_mass, SPHMAP_EINVAL, "null required array");
+    SPH_REQUIRE(precision == SPHMAP_PREC_FP64 || precision == SPHMAP_PREC_MIXED, SPHMAP_EINVAL, "bad precision");
+    SPH_REQUIRE(normalize == 0 || normalize == 1, SPHMAP_EINVAL, "normalize must be 0 or 1");
+    int64_t n_max = 0;
+    for (int k = 0; k < n_inst; ++k) {
+      SPH_REQUIRE(tess[k], SPHMAP_EINVAL, "null tessellation of instance " + std::to_string(k));
+      SPH_REQUIRE(n[k] >= 1 && n[k] < ((int64_t)1 << 31), SPHMAP_EINVAL,
+                  "n out of range [1, 2^31) for instance " + std::to_string(k));
+      SPH_REQUIRE(d_xyz[k] && d_h[k] && d_m[k] && d_cell_mass[k], SPHMAP_EINVAL,
+                  "null required pointer of instance " + std::to_string(k));
+      SPH_REQUIRE(tess[k]->t.device == ctx->c.device, SPHMAP_EINVAL, "tessellation belongs to another device");
+      n_max = std::max(n_max, n[k]);
+    }
+    hipStream_t s = as_stream(stream);
+    sphmap::Ctx &C = ctx->c;
+    std::vector<sphmap::PairsDev *> P(n_inst);
+    if (pairs_out) {
+      for (int k = 0; k < n_inst; ++k) {
+        owned.emplace_back(new sphmap_pairs);
+        P[k] = &owned.back()->p;
+      }
+    } else {
+      while ((int)C.scratch_batch.size() < n_inst) C.scratch_batch.push_back(new sphmap::PairsDev);
+      for (int k = 0; k < n_inst; ++k) P[k] = C.scratch_batch[k];
+    }
+    float4 *x32 = C.arena.get<float4>("x32", n_max);
+    std::vector<sphmap::PartDev> pd(n_inst);
+    std::vector<sphmap::ExactJob> jobs(n_inst);
+    int64_t total = 0;
+    for (int k = 0; k < n_inst; ++k) {
+      P[k]->device = C.device;
+      pd[k] = sphmap::PartDev{n[k], d_xyz[k], d_h[k], d_m[k], x32};
+      sphmap::particles_prepare(C, pd[k], s);
+      sphmap::find_pairs(C, tess[k]->t, pd[k], *P[k], s);
+      jobs[k] = sphmap::ExactJob{&tess[k]->t, &pd[k], P[k]};
+      total += P[k]->n_pairs;
+    }
+    sphmap::exact_integral_batch(C, jobs, precision, s);
+    for (int k = 0; k < n_inst; ++k) {
+      sphmap::particle_major(C, *P[k], s);
+      sphmap::cell_reduce(C, tess[k]->t, pd[k], *P[k], normalize != 0, d_cell_mass[k],
+                          d_cell_density ? d_cell_density[k] : nullptr, s);
+      if (d_coverage && d_coverage[k])
+        SPH_HIP(hipMemcpyAsync(d_coverage[k], P[k]->coverage, n[k] * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    if (C.counting) {
+      SPH_HIP(hipMemcpyAsync(C.counters, C.d_counters, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      SPH_HIP(hipStreamSynchronize(s));
+      C.counters[0] = total;
+    }
+  });
+  if (rc == SPHMAP_OK && pairs_out)
+    for (int k = 0; k < n_inst; ++k) pairs_out[k] = owned[k].release();
   return rc;
 }
 

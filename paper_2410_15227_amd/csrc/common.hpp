@@ -70,7 +70,25 @@ struct Ctx {
   int64_t counters[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int64_t *d_counters = nullptr;  // device copy of the work counters
   int *d_status = nullptr;        // device status word (non-finite results)
-  void *pinned = nullptr;         // small pinned host scratch
+  void *pinned = nullptr;         // pinned host staging for small tables
+  size_t pinned_bytes = 0;
+  std::vector<PairsDev *> scratch_batch;  // pair lists of batched calls that do not keep them
+  // Pinned host staging of at least `bytes`.  Its previous contents must no
+  // longer be needed by queued copies (every forward call synchronises its
+  // stream once, for the pair count, before it stages a table).
+  void *pinned_get(size_t bytes) {
+    if (pinned_bytes < bytes) {
+      if (pinned) {
+        SPH_HIP(hipDeviceSynchronize());
+        SPH_HIP(hipHostFree(pinned));
+        pinned = nullptr;
+        pinned_bytes = 0;
+      }
+      SPH_HIP(hipHostMalloc(&pinned, bytes + 4096, hipHostMallocDefault));
+      pinned_bytes = bytes + 4096;
+    }
+    return pinned;
+  }
 };
 
 // RAII scope that records events around one launch when timing is on.
@@ -178,6 +196,13 @@ void particles_prepare(Ctx &ctx, PartDev &p, hipStream_t s);
 void find_pairs(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, hipStream_t s);
 // weights
 void exact_integral(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, int precision, hipStream_t s);
+// several independent instances in one persistent launch
+struct ExactJob {
+  const TessDev *t;
+  const PartDev *p;
+  PairsDev *P;
+};
+void exact_integral_batch(Ctx &ctx, const std::vector<ExactJob> &jobs, int precision, hipStream_t s);
 // transpose + coverage
 void particle_major(Ctx &ctx, PairsDev &P, hipStream_t s);
 // M_c and rho_c (scale: optional per-particle mass factor 1/c_i)

@@ -39,6 +39,7 @@
 //     the edge line or whose face plane nearly touches the particle (p or |d|
 //     below 1e-4 h) are recomputed from binary64 geometry.
 #include <algorithm>
+#include <vector>
 #include <cstdlib>
 #include <type_traits>
 
@@ -306,6 +307,30 @@ __device__ double face_fp64(const double4 pl, double dist, double ih, double xr0
   return d > 0.0 ? Cf : -Cf;
 }
 
+// One mapping instance as the persistent kernels see it (device-side table).
+struct ExactInst {
+  const int32_t *pair_c, *pair_p;
+  const double *xyz, *hh, *gen;
+  const int64_t *cfo, *fvo;
+  const double4 *fplane, *fsphere;
+  const float4 *fplane32, *fvpos32, *edgeA, *edgeE, *edgeM;
+  const double *fvpos;
+  double *w;
+  int64_t P;
+};
+
+// instance holding global chunk `chunk` (chunk0: first chunk of each
+// instance, ascending, n_inst + 1 entries)
+__device__ inline int inst_of(const int64_t *chunk0, int n_inst, int64_t chunk) {
+  int lo = 0, hi = n_inst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (chunk0[mid] <= chunk) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 struct Counters {
   int nf_int = 0, ne_vis = 0, ne_int = 0, n64 = 0;
   EdgeCount fd;
@@ -483,17 +508,17 @@ __device__ inline void pair_mixed(int64_t k, const int32_t *pair_c, const int32_
 
 // one pair per lane over a device-side list of pairs (its length read on the
 // device): the pairs the two-phase kernel leaves to binary64 geometry
-__global__ void __launch_bounds__(256) k_exact_mixed_list(const int32_t *list, const int32_t *n_list,
-                                                         const int32_t *pair_c, const int32_t *pair_p,
-                                                         const double *xyz, const double *hh, const double *gen,
-                                                         const int64_t *cfo, const int64_t *fvo,
-                                                         const double4 *fplane, const float4 *fplane32,
-                                                         const double4 *fsphere, const double *fvpos,
-                                                         const float4 *fvpos32, double *w_out, int64_t *counters) {
+__global__ void __launch_bounds__(256) k_exact_mixed_list(const int64_t *list, const int32_t *n_list,
+                                                         const ExactInst *insts, const int64_t *chunk0, int n_inst,
+                                                         int64_t *counters) {
   const int n = *n_list;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
-    pair_mixed(list[t], pair_c, pair_p, xyz, hh, gen, cfo, fvo, fplane, fplane32, fsphere, fvpos, fvpos32, w_out,
-               counters);
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    const int64_t gid = list[t];
+    const int ins = inst_of(chunk0, n_inst, gid >> 6);
+    const ExactInst &I = insts[ins];
+    pair_mixed(gid - chunk0[ins] * 64, I.pair_c, I.pair_p, I.xyz, I.hh, I.gen, I.cfo, I.fvo, I.fplane, I.fplane32,
+               I.fsphere, I.fvpos, I.fvpos32, I.w, counters);
+  }
 }
 
 // ------------------------------------------------------- wave helpers
@@ -759,31 +784,38 @@ __device__ inline int drain(EdgeWave &L, float4 *q, unsigned char *o, int len, i
 
 template <bool kCount>
 __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
-    int64_t P, const int32_t *pair_c, const int32_t *pair_p, const double *xyz, const double *hh, const double *gen,
-    const int64_t *cfo, const int64_t *fvo, const double4 *fplane, const double4 *fsphere, const float4 *edgeA,
-    const float4 *edgeE, const float4 *edgeM, double *w_out, int64_t *counters, FaceRec *faces, int2 *edges,
-    int32_t *next_chunk, int32_t *redo, int32_t *n_redo) {
+    const ExactInst *insts, const int64_t *chunk0, int n_inst, int64_t *counters, FaceRec *faces, int2 *edges,
+    int32_t *next_chunk, int64_t *redo, int32_t *n_redo) {
   __shared__ EdgeWave lds[kFlatWaves];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   EdgeWave &L = lds[wid];
   const int64_t wave = (int64_t)blockIdx.x * kFlatWaves + wid;
   FaceRec *const fr = faces + wave * kEntryCap;
   int2 *const er = edges + wave * 64 * kEdgeCap;  // per edge of the chunk: vertex slot, face record
-  const int64_t n_chunks = (P + 63) >> 6;
+  const int64_t n_chunks = chunk0[n_inst];
   Counters K;
   int64_t nfaces = 0;
   while (true) {
-    int chunk = 0;
-    if (lane == 0) chunk = atomicAdd(next_chunk, 1);
-    chunk = __shfl(chunk, 0, 64);
-    if (chunk >= n_chunks) break;
-    const int64_t k = (int64_t)chunk * 64 + lane;
+    int gchunk = 0;
+    if (lane == 0) gchunk = atomicAdd(next_chunk, 1);
+    gchunk = __shfl(gchunk, 0, 64);
+    if (gchunk >= n_chunks) break;
+    const int ins = inst_of(chunk0, n_inst, gchunk);
+    const ExactInst &I = insts[ins];
+    const int32_t *const pair_c = I.pair_c, *const pair_p = I.pair_p;
+    const double *const xyz = I.xyz, *const hh = I.hh, *const gen = I.gen;
+    const int64_t *const cfo = I.cfo, *const fvo = I.fvo;
+    const double4 *const fplane = I.fplane, *const fsphere = I.fsphere;
+    const float4 *const edgeA = I.edgeA, *const edgeE = I.edgeE, *const edgeM = I.edgeM;
+    const int64_t P = I.P;
+    const int64_t chunk = gchunk - chunk0[ins];
+    const int64_t k = chunk * 64 + lane;
     const bool valid = k < P;
     // ---------------- A1: cull
     // The chunk's pairs are sorted by cell, so their faces are one range
     // [F0, F1); it is staged through LDS 64 faces at a time.
-    const int64_t k_last = min((int64_t)chunk * 64 + 63, P - 1);
-    const int64_t F0 = cfo[pair_c[(int64_t)chunk * 64]], F1 = cfo[pair_c[k_last] + 1];
+    const int64_t k_last = min(chunk * 64 + 63, P - 1);
+    const int64_t F0 = cfo[pair_c[chunk * 64]], F1 = cfo[pair_c[k_last] + 1];
     uint64_t mask = 0;
     int nsurv = 0, nedge = 0;
     bool inside = true, on_boundary = false, again = false;
@@ -965,9 +997,9 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
     if (qN > 0) drain(L, L.qN, L.oN, qN, qN, false, lane, K.fd);
     wave_sync();
     if (valid && !again && L.redo[lane] == 0) {
-      w_out[k] = (inside ? 1.0 : 0.0) - kInv4Pi * from_fixed(L.acc[lane]);
+      I.w[k] = (inside ? 1.0 : 0.0) - kInv4Pi * from_fixed(L.acc[lane]);
     } else if (valid) {
-      redo[atomicAdd(n_redo, 1)] = (int32_t)k;
+      redo[atomicAdd(n_redo, 1)] = (int64_t)gchunk * 64 + lane;
     }
     wave_fence();
   }
@@ -976,20 +1008,48 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
 
 }  // namespace
 
-void exact_integral(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, int precision, hipStream_t s) {
-  P.w = P.mem.get<double>("w", P.n_pairs);
-  if (P.n_pairs == 0) return;
+void exact_integral_batch(Ctx &ctx, const std::vector<ExactJob> &jobs, int precision, hipStream_t s) {
+  int64_t total = 0;
+  for (const auto &j : jobs) {
+    j.P->w = j.P->mem.get<double>("w", j.P->n_pairs);
+    total += j.P->n_pairs;
+  }
   int64_t *ctr = ctx.counting ? ctx.d_counters : nullptr;
   if (ctr) SPH_HIP(hipMemsetAsync(ctr, 0, 8 * sizeof(int64_t), s));
+  if (total == 0) return;
   if (precision == SPHMAP_PREC_FP64) {
     KernelTimer kt(&ctx, "exact_integral", s);
-    k_exact_fp64<<<(unsigned)div_up(P.n_pairs, 256), 256, 0, s>>>(P.n_pairs, P.pair_c, P.pair_p, p.xyz, p.h, t.gen,
-                                                                  t.cell_face_off, t.face_vtx_off, t.fplane,
-                                                                  t.fsphere, t.fvpos, P.w, ctr);
-    SPH_LAUNCH_CHECK();
+    for (const auto &j : jobs) {
+      const TessDev &t = *j.t;
+      const PartDev &p = *j.p;
+      PairsDev &P = *j.P;
+      if (P.n_pairs == 0) continue;
+      k_exact_fp64<<<(unsigned)div_up(P.n_pairs, 256), 256, 0, s>>>(P.n_pairs, P.pair_c, P.pair_p, p.xyz, p.h, t.gen,
+                                                                    t.cell_face_off, t.face_vtx_off, t.fplane,
+                                                                    t.fsphere, t.fvpos, P.w, ctr);
+      SPH_LAUNCH_CHECK();
+    }
     kt.done();
     return;
   }
+  // instance table: each instance's pairs start at a fresh 64-pair chunk
+  const int n_inst = (int)jobs.size();
+  char *stage = (char *)ctx.pinned_get(n_inst * sizeof(ExactInst) + (n_inst + 1) * sizeof(int64_t) + 64);
+  ExactInst *host = (ExactInst *)stage;
+  int64_t *c0 = (int64_t *)(stage + ((n_inst * sizeof(ExactInst) + 63) & ~(size_t)63));
+  c0[0] = 0;
+  for (int k = 0; k < n_inst; ++k) {
+    const TessDev &t = *jobs[k].t;
+    const PartDev &p = *jobs[k].p;
+    const PairsDev &P = *jobs[k].P;
+    host[k] = ExactInst{P.pair_c, P.pair_p, p.xyz, p.h, t.gen, t.cell_face_off, t.face_vtx_off, t.fplane, t.fsphere,
+                        t.fplane32, t.fvpos32, t.edgeA, t.edgeE, t.edgeM, t.fvpos, P.w, P.n_pairs};
+    c0[k + 1] = c0[k] + div_up(P.n_pairs, 64);
+  }
+  ExactInst *d_inst = ctx.arena.get<ExactInst>("flat_insts", n_inst);
+  int64_t *d_c0 = ctx.arena.get<int64_t>("flat_chunk0", n_inst + 1);
+  SPH_HIP(hipMemcpyAsync(d_inst, host, n_inst * sizeof(ExactInst), hipMemcpyHostToDevice, s));
+  SPH_HIP(hipMemcpyAsync(d_c0, c0, (n_inst + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
   // persistent kernel: as many workgroups as stay resident at once
   static int n_cu = 0, per_cu = 0;
   if (n_cu == 0) {
@@ -997,29 +1057,30 @@ void exact_integral(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, i
     SPH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_exact_edges<false>, 64 * kFlatWaves, 0));
     per_cu = std::max(per_cu, 1);
   }
-  const int64_t n_chunks = div_up(P.n_pairs, 64);
+  const int64_t n_chunks = c0[n_inst];
   const int64_t grid = std::min<int64_t>((int64_t)n_cu * per_cu, div_up(n_chunks, kFlatWaves));
   const int64_t waves = grid * kFlatWaves;
   FaceRec *faces = ctx.arena.get<FaceRec>("flat_faces", waves * kEntryCap);
   int2 *edges = ctx.arena.get<int2>("flat_edges", waves * 64 * kEdgeCap);
   int32_t *next = ctx.arena.get<int32_t>("flat_next", 2);  // work counter, redo count
-  int32_t *redo = ctx.arena.get<int32_t>("flat_redo", P.n_pairs);
+  int64_t *redo = ctx.arena.get<int64_t>("flat_redo", total);
   KernelTimer kz(&ctx, "flat_reset", s);
   k_zero_i32<<<1, 64, 0, s>>>(next, 2);
   SPH_LAUNCH_CHECK();
   kz.done();
   KernelTimer kt(&ctx, "exact_integral", s);
   (ctr ? k_exact_edges<true> : k_exact_edges<false>)<<<(unsigned)grid, 64 * kFlatWaves, 0, s>>>(
-      P.n_pairs, P.pair_c, P.pair_p, p.xyz, p.h, t.gen, t.cell_face_off, t.face_vtx_off, t.fplane, t.fsphere,
-      t.edgeA, t.edgeE, t.edgeM, P.w, ctr, faces, edges, next, redo, next + 1);
+      d_inst, d_c0, n_inst, ctr, faces, edges, next, redo, next + 1);
   SPH_LAUNCH_CHECK();
   kt.done();
   KernelTimer kr(&ctx, "exact_redo", s);
-  k_exact_mixed_list<<<(unsigned)(n_cu * 4), 256, 0, s>>>(redo, next + 1, P.pair_c, P.pair_p, p.xyz, p.h, t.gen,
-                                                          t.cell_face_off, t.face_vtx_off, t.fplane, t.fplane32,
-                                                          t.fsphere, t.fvpos, t.fvpos32, P.w, ctr);
+  k_exact_mixed_list<<<(unsigned)(n_cu * 4), 256, 0, s>>>(redo, next + 1, d_inst, d_c0, n_inst, ctr);
   SPH_LAUNCH_CHECK();
   kr.done();
+}
+
+void exact_integral(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, int precision, hipStream_t s) {
+  exact_integral_batch(ctx, {ExactJob{&t, &p, &P}}, precision, s);
 }
 
 }  // namespace sphmap

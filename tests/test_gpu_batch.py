@@ -1,0 +1,75 @@
+"""Batched forward mapping: several independent instances in one call give,
+instance by instance, the same cell masses, coverages and weights as the
+single-instance call, bit for bit (each weight depends on its own pair
+only), for both precisions."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2410_15227_amd as pkg
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pkg.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def instances(workloads):
+    out = []
+    for n, kind, seed in [(1500, "uniform", 40), (6000, "turbulent", 41), (300, "uniform", 42),
+                          (12000, "turbulent", 43), (2500, "uniform", 44)]:
+        pos, m, h, rho = workloads.make_cloud(kind, n, seed)
+        out.append((pos, h, m, workloads.voronoi(pos)))
+    return out
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_batch_equals_single(ctx, instances, precision):
+    import paper_2410_15227_amd as pkg
+    say(f"case: batch of {len(instances)} instances, precision={precision}")
+    dts = [pkg.DeviceTessellation(ctx, t) for (_, _, _, t) in instances]
+    singles = []
+    for (pos, h, m, _), dt in zip(instances, dts):
+        r = pkg.map_particles_to_cells(ctx, dt, pos, h, m, precision=precision, keep_pairs=True)
+        singles.append((r.mass.cpu().numpy(), r.coverage.cpu().numpy(), [x.cpu().numpy() for x in r.pairs.export()]))
+        r.pairs.free()
+    batch = pkg.map_particles_to_cells_batch(ctx, dts, [i[0] for i in instances], [i[1] for i in instances],
+                                             [i[2] for i in instances], precision=precision, keep_pairs=True)
+    torch.cuda.synchronize()
+    for k, (res, (M, cov, (off, idx, w))) in enumerate(zip(batch, singles)):
+        goff, gidx, gw = (x.cpu().numpy() for x in res.pairs.export())
+        assert np.array_equal(goff, off) and np.array_equal(gidx, idx), k
+        assert np.array_equal(gw, w), k                      # weights bit for bit
+        assert np.array_equal(res.mass.cpu().numpy(), M), k
+        assert np.array_equal(res.coverage.cpu().numpy(), cov), k
+        res.pairs.free()
+    # the batch again without keeping the lists (scratch lists reused)
+    again = pkg.map_particles_to_cells_batch(ctx, dts, [i[0] for i in instances], [i[1] for i in instances],
+                                             [i[2] for i in instances], precision=precision)
+    for res, (M, _, _) in zip(again, singles):
+        assert np.array_equal(res.mass.cpu().numpy(), M)
+    for dt in dts:
+        dt.free()
+
+
+def test_batch_rejects_bad_input(ctx, instances):
+    import paper_2410_15227_amd as pkg
+    pos, h, m, t = instances[0]
+    dt = pkg.DeviceTessellation(ctx, t)
+    with pytest.raises(Exception):
+        pkg.map_particles_to_cells_batch(ctx, [dt], [pos], [h[:-1]], [m])
+    dt.free()
