@@ -78,9 +78,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=30000, help="cells of the oracle CPU baseline (about 10-15 s)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=3, help="timed steps of the plain binary64 path")
-    ap.add_argument("--workload", default="turbulent", choices=["turbulent", "pseudo"],
+    ap.add_argument("--workload", default="turbulent", choices=["turbulent", "pseudo", "batch"],
                     help="turbulent: the 262,144-particle cloud (default); pseudo: 1,048,576 particles collapsed "
-                         "to tree-node pseudo-particles around the densest particle, mapped on the mixed set's grid")
+                         "to tree-node pseudo-particles around the densest particle, mapped on the mixed set's grid; "
+                         "batch: 64 independent instances of 2^12..2^18 particles in one batched call")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -90,6 +91,8 @@ def main():
         sys.exit(2)
     if args.workload == "pseudo":
         return run_pseudo(args)
+    if args.workload == "batch":
+        return run_batch(args)
 
     import numpy as np
     import torch
@@ -344,6 +347,124 @@ def run_pseudo(args):
     print(json.dumps(out), flush=True)
     dt_mix.free()
     dt_all.free()
+    ctx.close()
+
+
+def run_batch(args):
+    """64 independent mapping instances (sizes round(2^U(12,18)), uniform or
+    turbulent clouds with probability 1/2, seeds 4000 + k), each with its own
+    Voronoi grid.  One timed step = the batched forward mapping of all
+    instances (one persistent Exact launch, launch shape autotuned during the
+    warm-up) + the inverse mapping of one cell field per instance.  The same
+    work as 64 single calls, and the batch in plain binary64, are timed
+    beside it."""
+    import numpy as np
+    import torch
+
+    import paper_2410_15227_amd as pkg
+    from paper_2410_15227_amd import workloads
+
+    mix = workloads.batch_mix(64, 4000, 12, 18)
+    t0 = time.time()
+    inst = []
+    for n, kind, seed in mix:
+        pos, m, h, rho = workloads.make_cloud(kind, n, seed)
+        inst.append((pos, h, m, workloads.voronoi(pos)))
+    host_s = time.time() - t0
+    n_tot = sum(n for n, _, _ in mix)
+    log(f"inputs: {len(mix)} instances, {n_tot} particles, built in {host_s:.1f}s")
+    ctx = pkg.Context(0)
+    dev = ctx.device
+    dts = [ctx.upload(t) for (_, _, _, t) in inst]
+    xs = [torch.tensor(p, dtype=torch.float64, device=dev) for (p, _, _, _) in inst]
+    hs = [torch.tensor(h, dtype=torch.float64, device=dev) for (_, h, _, _) in inst]
+    ms = [torch.tensor(m, dtype=torch.float64, device=dev) for (_, _, m, _) in inst]
+    qs = [torch.ones(t.n_cells, dtype=torch.float64, device=dev) for (_, _, _, t) in inst]
+
+    def batched(precision=args.precision):
+        res = pkg.map_particles_to_cells_batch(ctx, dts, xs, hs, ms, precision=precision, keep_pairs=True)
+        for r, q in zip(res, qs):
+            pkg.map_cells_to_particles(ctx, r.pairs, q)
+        return res
+
+    def singles():
+        out = []
+        for dt, x, h, m, q in zip(dts, xs, hs, ms, qs):
+            r = pkg.map_particles_to_cells(ctx, dt, x, h, m, precision=args.precision, keep_pairs=True)
+            pkg.map_cells_to_particles(ctx, r.pairs, q)
+            out.append(r)
+        return out
+
+    def free(res):
+        for r in res:
+            r.pairs.free()
+
+    ctx.set_autotune(True)
+    for _ in range(max(1, args.warmup)):
+        free(batched())
+    ctx.set_autotune(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = batched()
+        if _ != args.steps - 1:
+            free(res)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    n_pairs = sum(r.pairs.n_pairs for r in res)
+    mass_b = [r.mass.clone() for r in res]
+    free(res)
+    shape = ctx.tuned_shape(n_pairs)
+    free(singles())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, args.steps // 2)):
+        res1 = singles()
+        free(res1)
+    torch.cuda.synchronize()
+    el1 = (time.perf_counter() - t0) / max(1, args.steps // 2)
+    same = all(bool(torch.equal(a.mass, b)) for a, b in zip(res1, mass_b))
+    fp64 = None
+    if args.fp64_steps > 0 and args.precision == "mixed":
+        free(batched("fp64"))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.fp64_steps):
+            r64 = batched("fp64")
+            if _ != args.fp64_steps - 1:
+                free(r64)
+        torch.cuda.synchronize()
+        el64 = (time.perf_counter() - t0) / args.fp64_steps
+        rel = max(float(((a - r.mass).abs() / r.mass.abs().clamp_min(1e-300)).max().item())
+                  for a, r in zip(mass_b, r64))
+        free(r64)
+        fp64 = {"value": round(n_pairs / el64, 1), "unit": "pairs/s", "ms_per_step": round(el64 * 1e3, 3),
+                "mixed_speedup": round(el64 / el, 3), "max_rel_cell_mass_diff_mixed_vs_fp64": rel}
+    out = {
+        "metric": "particle-cell pair integrals/s",
+        "value": round(n_pairs / el, 1),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(el * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "batch_64", "instances": len(mix), "n_particles": n_tot, "n_pairs": int(n_pairs),
+                   "sizes": "round(2^U(12,18))", "precision": args.precision},
+        "batch": {"singles_ms_per_step": round(el1 * 1e3, 3), "batch_speedup_vs_singles": round(el1 / el, 3),
+                  "same_masses_as_singles": same,
+                  "tuned_shape": None if shape is None else {"blocks_per_cu": shape[0], "chunks_per_fetch": shape[1],
+                                                              "ms": round(shape[2], 3)},
+                  "host_inputs_s": round(host_s, 1)},
+        "fp64_path": fp64,
+    }
+    print(json.dumps(out), flush=True)
+    for dt in dts:
+        dt.free()
     ctx.close()
 
 

@@ -248,6 +248,18 @@ int sphmap_reset_timing(sphmap_ctx *ctx);
    recomputed one pair per lane).  Counting costs time; it is only done when
    enabled (sphmap_set_counting). */
 int sphmap_set_counting(sphmap_ctx *ctx, int32_t enabled);
+
+/* Launch-shape autotuning of the mixed-path Exact integral (the persistent
+   kernel's workgroups per compute unit and 64-pair chunks taken per work
+   fetch).  When enabled, the first forward call whose pair total falls in
+   a new power-of-two class times every candidate shape -- all compute the
+   same weights -- and keeps the fastest for later calls of that class
+   (enabled or not).  Counting calls are never tuned.
+   sphmap_tuned_shape reports the shape kept for the class of n_pairs:
+   blocks_per_cu = 0 when none is kept (the default shape is then used). */
+int sphmap_set_autotune(sphmap_ctx *ctx, int32_t enabled);
+int sphmap_tuned_shape(sphmap_ctx *ctx, int64_t n_pairs, int32_t *blocks_per_cu, int32_t *chunks_per_fetch,
+                       double *ms);
 int sphmap_work_counters(sphmap_ctx *ctx, int64_t *out8);
 
 #ifdef __cplusplus

@@ -94,6 +94,17 @@ class Context:
     def set_counting(self, on: bool = True):
         self.check(_native.lib().sphmap_set_counting(self.handle, 1 if on else 0))
 
+    def set_autotune(self, on: bool = True):
+        """Autotune the Exact launch shape per power-of-two pair-count class."""
+        self.check(_native.lib().sphmap_set_autotune(self.handle, 1 if on else 0))
+
+    def tuned_shape(self, n_pairs: int):
+        """(workgroups per CU, chunks per fetch, ms) kept for the class of n_pairs, or None."""
+        b, f, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        self.check(_native.lib().sphmap_tuned_shape(self.handle, int(n_pairs), ctypes.byref(b), ctypes.byref(f),
+                                                    ctypes.byref(ms)))
+        return None if b.value == 0 else (b.value, f.value, ms.value)
+
     def work_counters(self):
         arr = (ctypes.c_int64 * 8)()
         self.check(_native.lib().sphmap_work_counters(self.handle, arr))

@@ -21,7 +21,7 @@ EXPORTS = [
     "map_particles_to_cells", "map_particles_to_cells_batch", "sphmap_pairs_info", "sphmap_pairs_export", "sphmap_pairs_free",
     "map_cells_to_particles", "build_pseudo_particles",
     "sphmap_set_timing", "sphmap_kernel_time", "sphmap_reset_timing",
-    "sphmap_set_counting", "sphmap_work_counters",
+    "sphmap_set_counting", "sphmap_work_counters", "sphmap_set_autotune", "sphmap_tuned_shape",
 ]
 
 
@@ -72,6 +72,11 @@ def lib():
         L.map_particles_to_cells.argtypes = [vp, vp, i64, vp, vp, vp, i32, i32, vp, vp, vp, vp, pp]
         L.map_particles_to_cells_batch.restype = ctypes.c_int
         L.map_particles_to_cells_batch.argtypes = [vp, i32, vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp]
+        L.sphmap_set_autotune.restype = ctypes.c_int
+        L.sphmap_set_autotune.argtypes = [vp, i32]
+        L.sphmap_tuned_shape.restype = ctypes.c_int
+        L.sphmap_tuned_shape.argtypes = [vp, i64, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                         ctypes.POINTER(ctypes.c_double)]
         L.sphmap_pairs_info.restype = ctypes.c_int
         L.sphmap_pairs_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.sphmap_pairs_export.restype = ctypes.c_int

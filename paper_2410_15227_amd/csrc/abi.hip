@@ -409,6 +409,23 @@ int sphmap_set_counting(sphmap_ctx *ctx, int32_t enabled) {
   return SPHMAP_OK;
 }
 
+int sphmap_set_autotune(sphmap_ctx *ctx, int32_t enabled) {
+  if (!ctx) return SPHMAP_EINVAL;
+  ctx->c.autotune = enabled != 0;
+  return SPHMAP_OK;
+}
+
+int sphmap_tuned_shape(sphmap_ctx *ctx, int64_t n_pairs, int32_t *blocks_per_cu, int32_t *chunks_per_fetch,
+                       double *ms) {
+  if (!ctx || n_pairs < 1 || !blocks_per_cu || !chunks_per_fetch) return SPHMAP_EINVAL;
+  const int bucket = 63 - __builtin_clzll((unsigned long long)n_pairs);
+  auto it = ctx->c.tuned.find(bucket);
+  *blocks_per_cu = it == ctx->c.tuned.end() ? 0 : it->second.blocks_per_cu;
+  *chunks_per_fetch = it == ctx->c.tuned.end() ? 0 : it->second.per_fetch;
+  if (ms) *ms = it == ctx->c.tuned.end() ? 0.0 : it->second.ms;
+  return SPHMAP_OK;
+}
+
 int sphmap_work_counters(sphmap_ctx *ctx, int64_t *out8) {
   if (!ctx || !out8) return SPHMAP_EINVAL;
   for (int k = 0; k < 8; ++k) out8[k] = ctx->c.counters[k];

@@ -59,6 +59,13 @@ struct TimerRecord {
 
 struct PairsDev;
 
+// a launch shape chosen by the autotuner
+struct TuneChoice {
+  int blocks_per_cu;
+  int per_fetch;
+  double ms;
+};
+
 struct Ctx {
   int device = 0;
   PairsDev *scratch_pairs = nullptr;  // pair list of calls that do not keep one
@@ -73,6 +80,8 @@ struct Ctx {
   void *pinned = nullptr;         // pinned host staging for small tables
   size_t pinned_bytes = 0;
   std::vector<PairsDev *> scratch_batch;  // pair lists of batched calls that do not keep them
+  bool autotune = false;
+  std::map<int, TuneChoice> tuned;  // by floor(log2(pairs)) of the Exact launch
   // Pinned host staging of at least `bytes`.  Its previous contents must no
   // longer be needed by queued copies (every forward call synchronises its
   // stream once, for the pair count, before it stages a table).

@@ -784,8 +784,8 @@ __device__ inline int drain(EdgeWave &L, float4 *q, unsigned char *o, int len, i
 
 template <bool kCount>
 __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
-    const ExactInst *insts, const int64_t *chunk0, int n_inst, int64_t *counters, FaceRec *faces, int2 *edges,
-    int32_t *next_chunk, int64_t *redo, int32_t *n_redo) {
+    const ExactInst *insts, const int64_t *chunk0, int n_inst, int per_fetch, int64_t *counters, FaceRec *faces,
+    int2 *edges, int32_t *next_chunk, int64_t *redo, int32_t *n_redo) {
   __shared__ EdgeWave lds[kFlatWaves];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   EdgeWave &L = lds[wid];
@@ -796,10 +796,12 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
   Counters K;
   int64_t nfaces = 0;
   while (true) {
-    int gchunk = 0;
-    if (lane == 0) gchunk = atomicAdd(next_chunk, 1);
-    gchunk = __shfl(gchunk, 0, 64);
-    if (gchunk >= n_chunks) break;
+    int gbase = 0;
+    if (lane == 0) gbase = atomicAdd(next_chunk, per_fetch);
+    gbase = __shfl(gbase, 0, 64);
+    if (gbase >= n_chunks) break;
+    const int64_t gend = min((int64_t)gbase + per_fetch, n_chunks);
+    for (int64_t gchunk = gbase; gchunk < gend; ++gchunk) {
     const int ins = inst_of(chunk0, n_inst, gchunk);
     const ExactInst &I = insts[ins];
     const int32_t *const pair_c = I.pair_c, *const pair_p = I.pair_p;
@@ -999,9 +1001,10 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
     if (valid && !again && L.redo[lane] == 0) {
       I.w[k] = (inside ? 1.0 : 0.0) - kInv4Pi * from_fixed(L.acc[lane]);
     } else if (valid) {
-      redo[atomicAdd(n_redo, 1)] = (int64_t)gchunk * 64 + lane;
+      redo[atomicAdd(n_redo, 1)] = gchunk * 64 + lane;
     }
     wave_fence();
+    }  // chunks of this fetch
   }
   if (kCount) flush_counters(counters, nfaces, K);
 }
@@ -1058,21 +1061,52 @@ void exact_integral_batch(Ctx &ctx, const std::vector<ExactJob> &jobs, int preci
     per_cu = std::max(per_cu, 1);
   }
   const int64_t n_chunks = c0[n_inst];
-  const int64_t grid = std::min<int64_t>((int64_t)n_cu * per_cu, div_up(n_chunks, kFlatWaves));
-  const int64_t waves = grid * kFlatWaves;
-  FaceRec *faces = ctx.arena.get<FaceRec>("flat_faces", waves * kEntryCap);
-  int2 *edges = ctx.arena.get<int2>("flat_edges", waves * 64 * kEdgeCap);
   int32_t *next = ctx.arena.get<int32_t>("flat_next", 2);  // work counter, redo count
   int64_t *redo = ctx.arena.get<int64_t>("flat_redo", total);
-  KernelTimer kz(&ctx, "flat_reset", s);
-  k_zero_i32<<<1, 64, 0, s>>>(next, 2);
-  SPH_LAUNCH_CHECK();
-  kz.done();
-  KernelTimer kt(&ctx, "exact_integral", s);
-  (ctr ? k_exact_edges<true> : k_exact_edges<false>)<<<(unsigned)grid, 64 * kFlatWaves, 0, s>>>(
-      d_inst, d_c0, n_inst, ctr, faces, edges, next, redo, next + 1);
-  SPH_LAUNCH_CHECK();
-  kt.done();
+  auto launch = [&](int blocks_per_cu, int per_fetch) {
+    const int64_t grid = std::min<int64_t>((int64_t)n_cu * std::min(blocks_per_cu, per_cu), div_up(n_chunks, kFlatWaves));
+    const int64_t waves = grid * kFlatWaves;
+    FaceRec *faces = ctx.arena.get<FaceRec>("flat_faces", waves * kEntryCap);
+    int2 *edges = ctx.arena.get<int2>("flat_edges", waves * 64 * kEdgeCap);
+    KernelTimer kz(&ctx, "flat_reset", s);
+    k_zero_i32<<<1, 64, 0, s>>>(next, 2);
+    SPH_LAUNCH_CHECK();
+    kz.done();
+    KernelTimer kt(&ctx, "exact_integral", s);
+    (ctr ? k_exact_edges<true> : k_exact_edges<false>)<<<(unsigned)grid, 64 * kFlatWaves, 0, s>>>(
+        d_inst, d_c0, n_inst, per_fetch, ctr, faces, edges, next, redo, next + 1);
+    SPH_LAUNCH_CHECK();
+    kt.done();
+  };
+  // Launch shape: workgroups per CU and 64-pair chunks per work fetch.  With
+  // autotuning on, the first call in a size class (power of two of the pair
+  // count) times every candidate -- each computes the same weights -- and
+  // keeps the fastest for later calls of that class.
+  const int bucket = 63 - __builtin_clzll((unsigned long long)total);
+  auto it = ctx.tuned.find(bucket);
+  if (it != ctx.tuned.end()) {
+    launch(it->second.blocks_per_cu, it->second.per_fetch);
+  } else if (ctx.autotune && !ctr) {
+    TuneChoice best{per_cu, 1, 0.0};
+    hipEvent_t a, b;
+    SPH_HIP(hipEventCreate(&a));
+    SPH_HIP(hipEventCreate(&b));
+    for (int bpc = per_cu; bpc >= 1; --bpc)
+      for (int pf : {1, 2, 4}) {
+        SPH_HIP(hipEventRecord(a, s));
+        launch(bpc, pf);
+        SPH_HIP(hipEventRecord(b, s));
+        SPH_HIP(hipEventSynchronize(b));
+        float ms = 0.f;
+        SPH_HIP(hipEventElapsedTime(&ms, a, b));
+        if (best.ms == 0.0 || ms < best.ms) best = TuneChoice{bpc, pf, (double)ms};
+      }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    ctx.tuned[bucket] = best;
+  } else {
+    launch(per_cu, 1);
+  }
   KernelTimer kr(&ctx, "exact_redo", s);
   k_exact_mixed_list<<<(unsigned)(n_cu * 4), 256, 0, s>>>(redo, next + 1, d_inst, d_c0, n_inst, ctr);
   SPH_LAUNCH_CHECK();
