@@ -1054,12 +1054,12 @@ void exact_integral_batch(Ctx &ctx, const std::vector<ExactJob> &jobs, int preci
   SPH_HIP(hipMemcpyAsync(d_inst, host, n_inst * sizeof(ExactInst), hipMemcpyHostToDevice, s));
   SPH_HIP(hipMemcpyAsync(d_c0, c0, (n_inst + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
   // persistent kernel: as many workgroups as stay resident at once
-  static int n_cu = 0, per_cu = 0;
-  if (n_cu == 0) {
-    SPH_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx.device));
-    SPH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_exact_edges<false>, 64 * kFlatWaves, 0));
-    per_cu = std::max(per_cu, 1);
+  if (ctx.n_cu == 0) {  // per context: contexts may live on different threads
+    SPH_HIP(hipDeviceGetAttribute(&ctx.n_cu, hipDeviceAttributeMultiprocessorCount, ctx.device));
+    SPH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&ctx.exact_per_cu, k_exact_edges<false>, 64 * kFlatWaves, 0));
+    ctx.exact_per_cu = std::max(ctx.exact_per_cu, 1);
   }
+  const int n_cu = ctx.n_cu, per_cu = ctx.exact_per_cu;
   const int64_t n_chunks = c0[n_inst];
   int32_t *next = ctx.arena.get<int32_t>("flat_next", 2);  // work counter, redo count
   int64_t *redo = ctx.arena.get<int64_t>("flat_redo", total);
