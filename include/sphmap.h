@@ -206,6 +206,7 @@ typedef struct {
   int64_t n_pseudo;          /* pseudo-particles                               */
   int64_t n_real;            /* particles emitted as themselves                */
   int64_t branch_count[4];   /* h-solve branch: Newton, bisection, h0, bypass  */
+  double s_root;             /* size of the root node (Sec. 2.4.1, eq. resol_param) */
 } sphmap_pseudo_stats;
 
 /* Inputs d_xyz [n][3], d_h [n], d_m [n] (device); h_sources [n_src][3] (host).
@@ -223,6 +224,36 @@ int build_pseudo_particles(sphmap_ctx *ctx, int64_t n, const double *d_xyz, cons
                            int64_t capacity, double *d_out_xyz, double *d_out_h, double *d_out_m, double *d_out_s,
                            int32_t *d_out_kind, int64_t *d_out_first, int64_t *d_out_count,
                            int32_t *d_out_branch, int64_t *n_out, sphmap_pseudo_stats *stats, void *stream);
+
+/* The same with the nodes to open named (Sec. 2.4.1: nodes that failed the
+ * resolution check of an earlier walk are opened in the next one).
+ *   d_open_labels [n_open] (device, any order; NULL when n_open = 0): node
+ *     labels; a labelled node is opened whatever the walk criterion says
+ *     (an opened leaf emits its particles with their own h).  Labels that
+ *     name no node are ignored.
+ *   d_out_label [capacity] (device, may be NULL): the label of each entry's
+ *     unit (the accepted node, or the opened leaf holding the particle).
+ * A node label is a 1 followed by the node's octant digits (x + 2y + 4z,
+ * 3 bits per level) from the root down; the root is 1. */
+int build_pseudo_particles_open(sphmap_ctx *ctx, int64_t n, const double *d_xyz, const double *d_h,
+                                const double *d_m, int32_t n_src, const double *h_sources,
+                                const sphmap_pseudo_opts *opts, int64_t n_open, const uint64_t *d_open_labels,
+                                int64_t capacity, double *d_out_xyz, double *d_out_h, double *d_out_m,
+                                double *d_out_s, int32_t *d_out_kind, int64_t *d_out_first, int64_t *d_out_count,
+                                int32_t *d_out_branch, uint64_t *d_out_label, int64_t *n_out,
+                                sphmap_pseudo_stats *stats, void *stream);
+
+/* Resolution check of the adaptive walk (eq. resol_param, Sec. 2.4.1): a
+ * pseudo-particle (kind 1) of size s whose neutral fraction f is below
+ * f_neu,limit = (1/K) (K - 1 / (s / s_root)) is under-resolved.  Inputs are
+ * the builder's outputs for n entries (device) and the neutral fraction of
+ * each entry d_fneu [n] (device, e.g. from map_cells_to_particles of a cell
+ * field).  Writes the labels of the under-resolved entries, in entry order,
+ * to d_out_labels [n] (device) and their number to *n_found (host).
+ * Errors: EINVAL (null pointers, s_root <= 0, K <= 1). */
+int select_underresolved(sphmap_ctx *ctx, int64_t n, const int32_t *d_kind, const uint64_t *d_label,
+                         const double *d_s, const double *d_fneu, double s_root, double K, uint64_t *d_out_labels,
+                         int64_t *n_found, void *stream);
 
 /* ------------------------------------------------------------------------
  * Kernel timing: when enabled, HIP events are recorded on the launch stream

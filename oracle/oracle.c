@@ -517,6 +517,7 @@ double ora_fan_integral(double ad, double p, double pa, double pb) {
 typedef struct {
   int64_t first;   /* first member in the tree's particle order */
   int64_t count;
+  uint64_t label;  /* 1 followed by the node's octant digits, root first */
   int32_t child[8];
   int32_t is_leaf;
   double M, S[3];  /* mass and sum of m x */
@@ -539,7 +540,7 @@ static int cmp_i64(const void *a, const void *b) {
 }
 
 static int32_t otree_build(otree_t *T, int64_t first, int64_t count, const double lo[3], double size,
-                           int depth) {
+                           int depth, uint64_t label) {
   if (T->n_nodes == T->cap) {
     T->cap = T->cap * 2 + 64;
     T->nodes = (onode_t *)realloc(T->nodes, sizeof(onode_t) * T->cap);
@@ -549,6 +550,7 @@ static int32_t otree_build(otree_t *T, int64_t first, int64_t count, const doubl
   memset(&nd, 0, sizeof nd);
   nd.first = first;
   nd.count = count;
+  nd.label = label;
   for (int k = 0; k < 8; ++k) nd.child[k] = -1;
   int64_t *ord = T->order + first;
   if (count <= T->leaf_max || depth >= T->max_depth) {
@@ -584,7 +586,7 @@ static int32_t otree_build(otree_t *T, int64_t first, int64_t count, const doubl
     for (int o = 0; o < 8; ++o) {
       if (!cnt[o]) continue;
       double clo[3] = {(o & 1) ? mid[0] : lo[0], (o & 2) ? mid[1] : lo[1], (o & 4) ? mid[2] : lo[2]};
-      int32_t c = otree_build(T, first + off[o], cnt[o], clo, half, depth + 1);
+      int32_t c = otree_build(T, first + off[o], cnt[o], clo, half, depth + 1, (label << 3) | (uint64_t)o);
       nd.child[o] = c;
       nd.M += T->nodes[c].M;
       for (int k = 0; k < 3; ++k) nd.S[k] += T->nodes[c].S[k];
@@ -602,6 +604,17 @@ static int32_t otree_build(otree_t *T, int64_t first, int64_t count, const doubl
   return id;
 }
 
+static int cmp_u64(const void *a, const void *b) {
+  uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+  return (x > y) - (x < y);
+}
+
+/* label in the sorted list of nodes to open (Sec. 2.4.1: nodes that failed
+   the resolution check are opened in the next walk) */
+static int forced_open(uint64_t label, int64_t n_open, const uint64_t *open_sorted) {
+  return n_open > 0 && bsearch(&label, open_sorted, (size_t)n_open, sizeof(uint64_t), cmp_u64) != NULL;
+}
+
 static int accepted(const onode_t *nd, int n_src, const double *src, double r_part, double theta) {
   double s = sqrt(nd->s2);
   for (int k = 0; k < n_src; ++k) {
@@ -616,6 +629,9 @@ static int accepted(const onode_t *nd, int n_src, const double *src, double r_pa
 
 typedef struct {
   int64_t n;
+  int64_t n_open;
+  const uint64_t *open;  /* sorted labels of nodes to open */
+  uint64_t *label;  /* node label of the entry's unit */
   int32_t *kind;    /* 0 real particle, 1 pseudo-particle */
   int64_t *first;   /* lowest member particle index */
   int64_t *count;   /* members */
@@ -630,11 +646,12 @@ typedef struct {
 static void walk(const otree_t *T, int32_t id, int n_src, const double *src, double r_part, double theta,
                  const double *hp, emit_t *E) {
   const onode_t *nd = &T->nodes[id];
-  if (accepted(nd, n_src, src, r_part, theta)) {
+  if (accepted(nd, n_src, src, r_part, theta) && !forced_open(nd->label, E->n_open, E->open)) {
     int64_t u = E->n_units++;
     for (int k = 0; k < 3; ++k) E->upos[3 * u + k] = nd->com[k];
     int64_t e = E->n++;
     E->unit[e] = (int32_t)u;
+    E->label[e] = nd->label;
     E->count[e] = nd->count;
     if (nd->count == 1) {
       int64_t j = T->order[nd->first];
@@ -664,6 +681,7 @@ static void walk(const otree_t *T, int32_t id, int n_src, const double *src, dou
       int64_t j = T->order[nd->first + t];
       int64_t e = E->n++;
       E->unit[e] = (int32_t)u;
+      E->label[e] = nd->label;
       E->kind[e] = 0;
       E->first[e] = j;
       E->count[e] = 1;
@@ -755,14 +773,19 @@ int ora_node_h(const double *a, double s, int64_t nu, const double *upos, double
 
 /* Full builder.  Outputs (capacity n entries each; pos [n][3]):
    kind, first (lowest member index), count, pos, mass, h, s (node size),
-   branch (-1 for real particles), unit (h-solve unit of the entry).
-   Returns the number of emitted entries; *n_units_out = number of units,
-   upos_out (capacity n*3) their positions; *n_nodes_out = tree size. */
+   branch (-1 for real particles), unit (h-solve unit of the entry), label
+   (node label of the entry's unit: a 1 followed by the octant digits from
+   the root down, 3 bits per level).  Nodes whose labels are among the
+   n_open labels in open (any order) are opened whatever the walk criterion
+   says.  Returns the number of emitted entries; *n_units_out = number of
+   units, upos_out (capacity n*3) their positions; *n_nodes_out = tree size;
+   *s_root_out = size of the root node. */
 int64_t ora_pseudo_build(int64_t n, const double *x, const double *m, const double *hp, int32_t n_src,
                          const double *src, double r_part, double theta, double hfact, double eps,
-                         int32_t leaf_max, int32_t max_depth, int64_t bypass, int32_t *kind, int64_t *first,
-                         int64_t *count, double *pos, double *mass, double *h, double *s, int32_t *branch,
-                         int32_t *unit, int64_t *n_units_out, double *upos_out, int64_t *n_nodes_out) {
+                         int32_t leaf_max, int32_t max_depth, int64_t bypass, int64_t n_open, const uint64_t *open,
+                         int32_t *kind, int64_t *first, int64_t *count, double *pos, double *mass, double *h,
+                         double *s, int32_t *branch, int32_t *unit, uint64_t *label, int64_t *n_units_out,
+                         double *upos_out, int64_t *n_nodes_out, double *s_root_out) {
   otree_t T;
   T.x = x;
   T.m = m;
@@ -773,9 +796,15 @@ int64_t ora_pseudo_build(int64_t n, const double *x, const double *m, const doub
   T.nodes = NULL;
   T.n_nodes = T.cap = 0;
   double lo[3] = {0.0, 0.0, 0.0};
-  otree_build(&T, 0, n, lo, 1.0, 0);
+  otree_build(&T, 0, n, lo, 1.0, 0, 1);
+  uint64_t *open_sorted = (uint64_t *)malloc(sizeof(uint64_t) * (n_open > 0 ? n_open : 1));
+  if (n_open > 0) memcpy(open_sorted, open, sizeof(uint64_t) * n_open);
+  qsort(open_sorted, (size_t)n_open, sizeof(uint64_t), cmp_u64);
   emit_t E;
   E.n = 0;
+  E.n_open = n_open;
+  E.open = open_sorted;
+  E.label = label;
   E.kind = kind;
   E.first = first;
   E.count = count;
@@ -804,7 +833,24 @@ int64_t ora_pseudo_build(int64_t n, const double *x, const double *m, const doub
   }
   *n_units_out = E.n_units;
   *n_nodes_out = T.n_nodes;
+  *s_root_out = n > 0 ? sqrt(T.nodes[0].s2) : 0.0;
+  free(open_sorted);
   free(T.order);
   free(T.nodes);
   return E.n;
+}
+
+/* Resolution parameter (eq. resol_param): the neutral-fraction threshold of a
+   node of size s_node, f_neu,limit = (1/K) (K - 1 / (s_node / s_root)). */
+double ora_fneu_limit(double s_ratio, double K) { return (K - 1.0 / s_ratio) / K; }
+
+/* Pseudo-particles whose neutral fraction is below the threshold of their
+   size (under-resolved, Sec. 2.4.1): their labels, in entry order.  Real
+   particles are never checked.  Returns the count. */
+int64_t ora_underresolved(int64_t n, const int32_t *kind, const uint64_t *label, const double *s,
+                          const double *fneu, double s_root, double K, uint64_t *out) {
+  int64_t k = 0;
+  for (int64_t e = 0; e < n; ++e)
+    if (kind[e] == 1 && fneu[e] < ora_fneu_limit(s[e] / s_root, K)) out[k++] = label[e];
+  return k;
 }

@@ -61,7 +61,11 @@ def _lib():
         L.ora_node_h.restype = ctypes.c_int
         L.ora_node_h.argtypes = [vp, dbl, i64, vp, dbl, dbl, vp, vp]
         L.ora_pseudo_build.restype = i64
-        L.ora_pseudo_build.argtypes = [i64, vp, vp, vp, i32, vp, dbl, dbl, dbl, dbl, i32, i32, i64] + [vp] * 12
+        L.ora_pseudo_build.argtypes = [i64, vp, vp, vp, i32, vp, dbl, dbl, dbl, dbl, i32, i32, i64, i64, vp] + [vp] * 14
+        L.ora_fneu_limit.restype = dbl
+        L.ora_fneu_limit.argtypes = [dbl, dbl]
+        L.ora_underresolved.restype = i64
+        L.ora_underresolved.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, vp]
         _L = L
     return _L
 
@@ -197,9 +201,10 @@ def node_h(a, s, upos, hfact=1.2, eps=1e-2):
 
 
 def pseudo_build(pos, m, h, sources, r_part=0.2, theta=0.5, hfact=1.2, eps=1e-2, leaf_max=8, max_depth=21,
-                 bypass=1_000_000):
+                 bypass=1_000_000, open_labels=None):
     """Tree-walk pseudo-particles and node smoothing lengths.  Returns a dict
-    of arrays in emission order."""
+    of arrays in emission order.  open_labels: node labels to open whatever
+    the walk criterion says (the failed nodes of an earlier walk)."""
     pos, m, h = _c(pos, np.float64), _c(m, np.float64), _c(h, np.float64)
     src = _c(np.asarray(sources, float).reshape(-1, 3), np.float64)
     n = pos.shape[0]
@@ -212,12 +217,33 @@ def pseudo_build(pos, m, h, sources, r_part=0.2, theta=0.5, hfact=1.2, eps=1e-2,
     s = np.empty(n)
     branch = np.empty(n, dtype=np.int32)
     unit = np.empty(n, dtype=np.int32)
+    label = np.empty(n, dtype=np.uint64)
     nu = np.zeros(1, dtype=np.int64)
     upos = np.empty((n, 3))
     nn = np.zeros(1, dtype=np.int64)
+    sroot = np.zeros(1)
+    op = np.ascontiguousarray(np.asarray(open_labels if open_labels is not None else [], dtype=np.uint64))
     k = _lib().ora_pseudo_build(n, _p(pos), _p(m), _p(h), src.shape[0], _p(src), r_part, theta, hfact, eps,
-                                leaf_max, max_depth, bypass, _p(kind), _p(first), _p(count), _p(opos), _p(mass),
-                                _p(oh), _p(s), _p(branch), _p(unit), _p(nu), _p(upos), _p(nn))
+                                leaf_max, max_depth, bypass, len(op), _p(op), _p(kind), _p(first), _p(count),
+                                _p(opos), _p(mass), _p(oh), _p(s), _p(branch), _p(unit), _p(label), _p(nu),
+                                _p(upos), _p(nn), _p(sroot))
     k = int(k)
     return dict(kind=kind[:k], first=first[:k], count=count[:k], pos=opos[:k], mass=mass[:k], h=oh[:k], s=s[:k],
-                branch=branch[:k], unit=unit[:k], upos=upos[:int(nu[0])], n_nodes=int(nn[0]))
+                branch=branch[:k], unit=unit[:k], label=label[:k], upos=upos[:int(nu[0])], n_nodes=int(nn[0]),
+                s_root=float(sroot[0]))
+
+
+def fneu_limit(s_ratio: float, K: float) -> float:
+    """eq. resol_param: neutral-fraction threshold of a node of relative size s_ratio."""
+    return float(_lib().ora_fneu_limit(float(s_ratio), float(K)))
+
+
+def underresolved(kind, label, s, fneu, s_root: float, K: float):
+    """Labels of the pseudo-particles below their threshold, in entry order."""
+    kind = np.ascontiguousarray(kind, dtype=np.int32)
+    label = np.ascontiguousarray(label, dtype=np.uint64)
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    fneu = np.ascontiguousarray(fneu, dtype=np.float64)
+    out = np.empty(len(kind), dtype=np.uint64)
+    k = _lib().ora_underresolved(len(kind), _p(kind), _p(label), _p(s), _p(fneu), float(s_root), float(K), _p(out))
+    return out[:int(k)]

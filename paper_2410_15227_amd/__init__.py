@@ -276,9 +276,11 @@ def map_cells_to_particles(ctx: Context, pairs: Pairs, cell_values, out=None, st
 
 def build_pseudo_particles(ctx: Context, xyz, h, m, sources, r_part: float = 0.2, theta: float = 0.5,
                            h_fact: float = 1.2, eps_h: float = 1e-2, leaf_max: int = 8, max_depth: int = 21,
-                           bypass_threshold: int = 1_000_000, stream=None) -> dict:
+                           bypass_threshold: int = 1_000_000, open_labels=None, stream=None) -> dict:
     """Tree-node pseudo-particles and their smoothing lengths (Sec. 2.4).
-    Returns a dict of device tensors in emission order plus 'stats'."""
+    open_labels: node labels to open whatever the walk criterion says (the
+    failed nodes of an earlier walk).  Returns a dict of device tensors in
+    emission order (with each entry's node 'label') plus 'stats'."""
     import numpy as np
     torch = _torch()
     dev = ctx.device
@@ -296,16 +298,73 @@ def build_pseudo_particles(ctx: Context, xyz, h, m, sources, r_part: float = 0.2
              kind=torch.empty(cap, dtype=torch.int32, device=dev),
              first=torch.empty(cap, dtype=torch.int64, device=dev),
              count=torch.empty(cap, dtype=torch.int64, device=dev),
-             branch=torch.empty(cap, dtype=torch.int32, device=dev))
+             branch=torch.empty(cap, dtype=torch.int32, device=dev),
+             label=torch.empty(cap, dtype=torch.int64, device=dev))  # uint64 bit patterns
+    if open_labels is not None and len(open_labels) > 0:
+        ol = torch.as_tensor(np.asarray(open_labels, dtype=np.uint64).view(np.int64), device=dev).contiguous()
+    else:
+        ol = None
     n_out = ctypes.c_int64()
     st = _native.PseudoStats()
-    ctx.check(_native.lib().build_pseudo_particles(
+    ctx.check(_native.lib().build_pseudo_particles_open(
         ctx.handle, n, _ptr(xyz), _ptr(h), _ptr(m), src.shape[0], src.ctypes.data_as(ctypes.c_void_p),
-        ctypes.byref(opts), cap, _ptr(o["xyz"]), _ptr(o["h"]), _ptr(o["m"]), _ptr(o["s"]), _ptr(o["kind"]),
-        _ptr(o["first"]), _ptr(o["count"]), _ptr(o["branch"]), ctypes.byref(n_out), ctypes.byref(st),
-        _stream_handle(stream)))
+        ctypes.byref(opts), 0 if ol is None else ol.shape[0], _ptr(ol), cap, _ptr(o["xyz"]), _ptr(o["h"]),
+        _ptr(o["m"]), _ptr(o["s"]), _ptr(o["kind"]), _ptr(o["first"]), _ptr(o["count"]), _ptr(o["branch"]),
+        _ptr(o["label"]), ctypes.byref(n_out), ctypes.byref(st), _stream_handle(stream)))
     k = n_out.value
     res = {key: val[:k] for key, val in o.items()}
     res["stats"] = dict(n_nodes=st.n_nodes, n_units=st.n_units, n_pseudo=st.n_pseudo, n_real=st.n_real,
-                        branch_count=list(st.branch_count))
+                        branch_count=list(st.branch_count), s_root=st.s_root)
     return res
+
+
+def select_underresolved(ctx: Context, ps: dict, fneu, K: float, stream=None):
+    """Labels (uint64, host) of the pseudo-particles of `ps` whose neutral
+    fraction `fneu` (one value per entry) is below f_neu,limit of their size
+    (eq. resol_param), in entry order."""
+    import numpy as np
+    torch = _torch()
+    fneu = _dev_f64(fneu, ctx.device)
+    n = ps["kind"].shape[0]
+    out = torch.empty(max(n, 1), dtype=torch.int64, device=ctx.device)
+    cnt = ctypes.c_int64()
+    ctx.check(_native.lib().select_underresolved(ctx.handle, n, _ptr(ps["kind"]), _ptr(ps["label"]), _ptr(ps["s"]),
+                                                 _ptr(fneu), float(ps["stats"]["s_root"]), float(K), _ptr(out),
+                                                 ctypes.byref(cnt), _stream_handle(stream)))
+    return out[:cnt.value].cpu().numpy().view(np.uint64)
+
+
+def adaptive_pseudo_particles(ctx: Context, xyz, h, m, sources, cell_fneu, K: float, max_iter: int = 16,
+                              precision: str = "mixed", **walk) -> tuple:
+    """The adaptive tree walk of Sec. 2.4.1.  Each iteration builds the
+    pseudo-particles with every node that has failed so far opened, builds the
+    Voronoi grid of the mixed set (host), asks `cell_fneu(generators)` for the
+    neutral fraction of every cell (the radiative transfer's output; here any
+    cell field), maps it back onto the entries (map_cells_to_particles of the
+    forward mapping's weights) and checks eq. resol_param; it stops when no
+    pseudo-particle is under-resolved.  Returns (final build, history); the
+    build also holds the entries' 'fneu' and the labels it 'opened'."""
+    import numpy as np
+
+    from . import workloads
+    opened = np.zeros(0, dtype=np.uint64)
+    history = []
+    for it in range(max_iter):
+        ps = build_pseudo_particles(ctx, xyz, h, m, sources, open_labels=opened, **walk)
+        pos = ps["xyz"].cpu().numpy()
+        tess = workloads.voronoi(pos)
+        dt = DeviceTessellation(ctx, tess)
+        res = map_particles_to_cells(ctx, dt, ps["xyz"], ps["h"], ps["m"], precision=precision, keep_pairs=True)
+        f_cells = np.asarray(cell_fneu(tess.generators), dtype=np.float64)
+        fneu = map_cells_to_particles(ctx, res.pairs, f_cells)
+        bad = select_underresolved(ctx, ps, fneu, K)
+        history.append(dict(iteration=it, n_entries=int(ps["kind"].shape[0]), n_pseudo=ps["stats"]["n_pseudo"],
+                            n_pairs=res.pairs.n_pairs, n_failed=int(len(bad))))
+        res.pairs.free()
+        dt.free()
+        ps["fneu"] = fneu
+        ps["opened"] = opened
+        if len(bad) == 0:
+            return ps, history
+        opened = np.union1d(opened, bad)
+    return ps, history

@@ -325,11 +325,13 @@ int map_cells_to_particles(sphmap_ctx *ctx, const sphmap_pairs *pairs, const dou
   });
 }
 
-int build_pseudo_particles(sphmap_ctx *ctx, int64_t n, const double *d_xyz, const double *d_h, const double *d_m,
-                           int32_t n_src, const double *h_sources, const sphmap_pseudo_opts *opts, int64_t capacity,
-                           double *d_out_xyz, double *d_out_h, double *d_out_m, double *d_out_s, int32_t *d_out_kind,
-                           int64_t *d_out_first, int64_t *d_out_count, int32_t *d_out_branch, int64_t *n_out,
-                           sphmap_pseudo_stats *stats, void *stream) {
+int build_pseudo_particles_open(sphmap_ctx *ctx, int64_t n, const double *d_xyz, const double *d_h,
+                                const double *d_m, int32_t n_src, const double *h_sources,
+                                const sphmap_pseudo_opts *opts, int64_t n_open, const uint64_t *d_open_labels,
+                                int64_t capacity, double *d_out_xyz, double *d_out_h, double *d_out_m,
+                                double *d_out_s, int32_t *d_out_kind, int64_t *d_out_first, int64_t *d_out_count,
+                                int32_t *d_out_branch, uint64_t *d_out_label, int64_t *n_out,
+                                sphmap_pseudo_stats *stats, void *stream) {
   if (!ctx) return SPHMAP_EINVAL;
   return guarded(ctx, [&] {
     SPH_REQUIRE(n >= 1 && n < ((int64_t)1 << 31), SPHMAP_EINVAL, "n out of range [1, 2^31)");
@@ -340,6 +342,7 @@ int build_pseudo_particles(sphmap_ctx *ctx, int64_t n, const double *d_xyz, cons
     SPH_REQUIRE(opts->max_depth >= 1 && opts->max_depth <= 21, SPHMAP_EINVAL, "max_depth must be in [1, 21]");
     SPH_REQUIRE(opts->theta >= 0 && opts->h_fact > 0 && opts->eps_h > 0, SPHMAP_EINVAL, "bad option value");
     SPH_REQUIRE(d_out_xyz && d_out_h && d_out_m && n_out, SPHMAP_EINVAL, "null required output");
+    SPH_REQUIRE(n_open >= 0 && (n_open == 0 || d_open_labels), SPHMAP_EINVAL, "null open-label list");
     sphmap::PseudoArgs a;
     a.n = n;
     a.xyz = d_xyz;
@@ -357,11 +360,37 @@ int build_pseudo_particles(sphmap_ctx *ctx, int64_t n, const double *d_xyz, cons
     a.o_first = d_out_first;
     a.o_count = d_out_count;
     a.o_branch = d_out_branch;
+    a.o_label = d_out_label;
+    a.n_open = n_open;
+    a.open_labels = d_open_labels;
     a.n_out = 0;
     std::memset(&a.stats, 0, sizeof a.stats);
     sphmap::pseudo_build(ctx->c, a, as_stream(stream));
     *n_out = a.n_out;
     if (stats) *stats = a.stats;
+  });
+}
+
+int build_pseudo_particles(sphmap_ctx *ctx, int64_t n, const double *d_xyz, const double *d_h, const double *d_m,
+                           int32_t n_src, const double *h_sources, const sphmap_pseudo_opts *opts, int64_t capacity,
+                           double *d_out_xyz, double *d_out_h, double *d_out_m, double *d_out_s, int32_t *d_out_kind,
+                           int64_t *d_out_first, int64_t *d_out_count, int32_t *d_out_branch, int64_t *n_out,
+                           sphmap_pseudo_stats *stats, void *stream) {
+  return build_pseudo_particles_open(ctx, n, d_xyz, d_h, d_m, n_src, h_sources, opts, 0, nullptr, capacity,
+                                     d_out_xyz, d_out_h, d_out_m, d_out_s, d_out_kind, d_out_first, d_out_count,
+                                     d_out_branch, nullptr, n_out, stats, stream);
+}
+
+int select_underresolved(sphmap_ctx *ctx, int64_t n, const int32_t *d_kind, const uint64_t *d_label,
+                         const double *d_s, const double *d_fneu, double s_root, double K, uint64_t *d_out_labels,
+                         int64_t *n_found, void *stream) {
+  if (!ctx) return SPHMAP_EINVAL;
+  return guarded(ctx, [&] {
+    SPH_REQUIRE(n >= 0 && n_found, SPHMAP_EINVAL, "bad count or null output count");
+    SPH_REQUIRE(n == 0 || (d_kind && d_label && d_s && d_fneu && d_out_labels), SPHMAP_EINVAL, "null array");
+    SPH_REQUIRE(s_root > 0.0 && K > 1.0, SPHMAP_EINVAL, "need s_root > 0 and K > 1");
+    *n_found = sphmap::select_underresolved(ctx->c, n, d_kind, d_label, d_s, d_fneu, s_root, K, d_out_labels,
+                                            as_stream(stream));
   });
 }
 

@@ -231,10 +231,16 @@ struct PseudoArgs {
   int32_t *o_kind;
   int64_t *o_first, *o_count;
   int32_t *o_branch;
+  uint64_t *o_label = nullptr;            // node label of each entry's unit
+  int64_t n_open = 0;                     // labels of nodes to open (device)
+  const uint64_t *open_labels = nullptr;
   int64_t n_out;
   sphmap_pseudo_stats stats;
 };
 void pseudo_build(Ctx &ctx, PseudoArgs &a, hipStream_t s);
+// labels of under-resolved pseudo-particles (eq. resol_param), entry order
+int64_t select_underresolved(Ctx &ctx, int64_t n, const int32_t *kind, const uint64_t *label, const double *s_node,
+                             const double *fneu, double s_root, double K, uint64_t *out, hipStream_t s);
 
 inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

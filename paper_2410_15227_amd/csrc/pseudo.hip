@@ -255,6 +255,31 @@ __global__ void __launch_bounds__(1024) k_node_size_big(NodeArrays N, const int3
   }
 }
 
+// Node label: a 1 followed by the octant digits from the root down (3 bits
+// per level), read off the Morton key of the node's first member.
+__global__ void k_label(NodeArrays N, int64_t nn, const uint64_t *keys, uint64_t *label) {
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= nn) return;
+  const int l = N.level[node];
+  const uint64_t key = keys[N.first[node]];
+  label[node] = (1ull << (3 * l)) | (l == 0 ? 0ull : key >> (3 * (21 - l)));
+}
+
+// Nodes whose labels are in the sorted list are opened (Sec. 2.4.1: the
+// nodes that failed the resolution check).
+__global__ void k_force_open(int64_t nn, const uint64_t *label, int64_t n_open, const uint64_t *open, int8_t *acc) {
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= nn || !acc[node]) return;
+  const uint64_t l = label[node];
+  int64_t lo = 0, hi = n_open;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (open[mid] < l) lo = mid + 1;
+    else hi = mid;
+  }
+  if (lo < n_open && open[lo] == l) acc[node] = 0;
+}
+
 __global__ void k_accept(int64_t nn, const double4 *com, const double *s2, int n_src, const double *src, double r_part,
                          double theta, int8_t *acc) {
 #pragma clang fp contract(off)
@@ -313,7 +338,7 @@ __global__ void k_entries(int64_t nu, const int32_t *units, NodeArrays N, const 
                           const double *m, const double *M, const double4 *com, const double *s2,
                           const int32_t *minidx, double *o_xyz, double *o_h, double *o_m, double *o_s,
                           int32_t *o_kind, int64_t *o_first, int64_t *o_count, int32_t *o_branch, double4 *upos,
-                          int32_t *plist) {
+                          int32_t *plist, const uint64_t *label, uint64_t *o_label) {
   int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= nu) return;
   const int32_t node = units[u];
@@ -332,6 +357,7 @@ __global__ void k_entries(int64_t nu, const int32_t *units, NodeArrays N, const 
     if (o_first) o_first[e] = j;
     if (o_count) o_count[e] = 1;
     if (o_branch) o_branch[e] = -1;
+    if (o_label) o_label[e] = label[node];
     ++e;
   };
   if (acc[node]) {
@@ -348,6 +374,7 @@ __global__ void k_entries(int64_t nu, const int32_t *units, NodeArrays N, const 
       if (o_first) o_first[e] = minidx[node];
       if (o_count) o_count[e] = c;
       if (o_branch) o_branch[e] = 0;
+      if (o_label) o_label[e] = label[node];
       plist[poff[u]] = (int32_t)e;
     }
   } else {
@@ -629,6 +656,18 @@ void pseudo_build(Ctx &ctx, PseudoArgs &a, hipStream_t s) {
   SPH_HIP(hipMemcpyAsync(src, a.src, 3 * a.n_src * sizeof(double), hipMemcpyHostToDevice, s));
   k_accept<<<(unsigned)div_up(nn, 256), 256, 0, s>>>(nn, com, s2, a.n_src, src, o.r_part, o.theta, acc);
   SPH_LAUNCH_CHECK();
+  uint64_t *label = ar.get<uint64_t>("ps_label", nn);
+  k_label<<<(unsigned)div_up(nn, 256), 256, 0, s>>>(N, nn, keys, label);
+  SPH_LAUNCH_CHECK();
+  if (a.n_open > 0) {
+    uint64_t *op = ar.get<uint64_t>("ps_open", a.n_open);
+    int32_t *dummy = ar.get<int32_t>("ps_open_idx", a.n_open);
+    SPH_HIP(hipMemcpyAsync(op, a.open_labels, a.n_open * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+    iota_i32(dummy, a.n_open, s);
+    radix_sort_u64(ar, op, dummy, a.n_open, 64, s);
+    k_force_open<<<(unsigned)div_up(nn, 256), 256, 0, s>>>(nn, label, a.n_open, op, acc);
+    SPH_LAUNCH_CHECK();
+  }
 
   // units in depth-first order
   int32_t *unit_at = ar.get<int32_t>("ps_unit_at", n);
@@ -670,7 +709,7 @@ void pseudo_build(Ctx &ctx, PseudoArgs &a, hipStream_t s) {
   double *o_s = a.o_s ? a.o_s : ar.get<double>("ps_os", n_out);
   k_entries<<<(unsigned)div_up(nu, 256), 256, 0, s>>>(nu, units, N, acc, eoff, poff, sidx, a.xyz, a.h, a.m, M, com,
                                                       s2, minidx, a.o_xyz, a.o_h, a.o_m, o_s, a.o_kind, a.o_first,
-                                                      a.o_count, a.o_branch, upos, plist);
+                                                      a.o_count, a.o_branch, upos, plist, label, a.o_label);
   SPH_LAUNCH_CHECK();
 
   // node smoothing lengths
@@ -691,7 +730,43 @@ void pseudo_build(Ctx &ctx, PseudoArgs &a, hipStream_t s) {
   a.stats.n_units = nu;
   a.stats.n_pseudo = np;
   a.stats.n_real = n_out - np;
+  {
+    double r2 = 0.0;
+    SPH_HIP(hipMemcpyAsync(&r2, s2, sizeof(double), hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipStreamSynchronize(s));
+    a.stats.s_root = sqrt(r2);
+  }
   for (int k = 0; k < 4; ++k) a.stats.branch_count[k] = (int64_t)bc[k];
+}
+
+__global__ void k_underresolved_flag(int64_t n, const int32_t *kind, const double *s_node, const double *fneu,
+                                     double s_root, double K, int64_t *flag) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  // eq. resol_param: f_neu,limit = (1/K) (K - 1 / (s_node / s_root))
+  flag[e] = (kind[e] == 1 && fneu[e] < (K - 1.0 / (s_node[e] / s_root)) / K) ? 1 : 0;
+}
+
+__global__ void k_underresolved_list(int64_t n, const int64_t *flag, const int64_t *off, const uint64_t *label,
+                                     uint64_t *out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n && flag[e]) out[off[e]] = label[e];
+}
+
+int64_t select_underresolved(Ctx &ctx, int64_t n, const int32_t *kind, const uint64_t *label, const double *s_node,
+                             const double *fneu, double s_root, double K, uint64_t *out, hipStream_t s) {
+  if (n <= 0) return 0;
+  int64_t *flag = ctx.arena.get<int64_t>("ur_flag", n + 1);
+  int64_t *off = ctx.arena.get<int64_t>("ur_off", n + 1);
+  k_underresolved_flag<<<(unsigned)div_up(n, 256), 256, 0, s>>>(n, kind, s_node, fneu, s_root, K, flag);
+  SPH_LAUNCH_CHECK();
+  scan_exclusive_i64(ctx.arena, flag, off, n, true, s);
+  k_underresolved_list<<<(unsigned)div_up(n, 256), 256, 0, s>>>(n, flag, off, label, out);
+  SPH_LAUNCH_CHECK();
+  int64_t cnt = 0;
+  SPH_HIP(hipMemcpyAsync(&cnt, off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  SPH_HIP(hipStreamSynchronize(s));
+  return cnt;
 }
 
 }  // namespace sphmap

@@ -93,7 +93,7 @@ def turbulent_cloud(n: int, seed: int, grid: int | None = None, sigma_lnrho: flo
     nz = k2 > 0
     amp[nz] = 1.0 / k2[nz]  # |k|^-2 amplitude -> P(k) ~ k^-4
     fk *= amp
-    delta = np.fft.irfftn(fk, s=(grid, grid, grid))
+    delta = np.fft.irfftn(fk, s=(grid, grid, grid), axes=(0, 1, 2))
     delta -= delta.mean()
     delta /= delta.std()
     rho = np.exp(sigma_lnrho * delta - 0.5 * sigma_lnrho**2).ravel()

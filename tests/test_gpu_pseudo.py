@@ -32,8 +32,7 @@ def compare(ctx, oracle, pos, m, h, src, **kw):
     import paper_2410_15227_amd as pkg
     ref = oracle.pseudo_build(pos, m, h, src, **{k: v for k, v in kw.items() if k != "bypass_threshold"},
                               **({"bypass": kw["bypass_threshold"]} if "bypass_threshold" in kw else {}))
-    got = pkg.build_pseudo_particles(ctx, pos, m=m, h=h, xyz=None, sources=src, **kw) if False else \
-        pkg.build_pseudo_particles(ctx, pos, h, m, src, **kw)
+    got = pkg.build_pseudo_particles(ctx, pos, h, m, src, **kw)
     torch.cuda.synchronize()
     g = {k: v.cpu().numpy() for k, v in got.items() if k != "stats"}
     n = len(ref["kind"])
@@ -45,6 +44,7 @@ def compare(ctx, oracle, pos, m, h, src, **kw):
     assert np.array_equal(g["m"], ref["mass"])
     assert np.array_equal(g["s"], ref["s"])
     assert np.array_equal(g["branch"], ref["branch"])
+    assert np.array_equal(g["label"].view(np.uint64), ref["label"])
     ps = ref["kind"] == 1
     real = ~ps
     assert np.array_equal(g["h"][real], ref["h"][real])
@@ -54,6 +54,7 @@ def compare(ctx, oracle, pos, m, h, src, **kw):
     st = got["stats"]
     assert st["n_pseudo"] == int(ps.sum()) and st["n_units"] == len(ref["upos"])
     assert st["n_nodes"] == ref["n_nodes"]
+    assert st["s_root"] == ref["s_root"]
     return ref, g, st
 
 
@@ -96,3 +97,77 @@ def test_turbulent_1m_densest_source(ctx, oracle, workloads):
     ref, g, st = compare(ctx, oracle, pos, m, h, src, r_part=0.2, theta=0.5)
     say(f"  entries={len(g['m'])} pseudo={st['n_pseudo']} real={st['n_real']} nodes={st['n_nodes']} "
         f"branches={st['branch_count']}")
+
+
+def test_forced_open_labels(ctx, oracle, workloads):
+    """Nodes named by label are opened whatever the walk criterion says
+    (Sec. 2.4.1): every third pseudo-particle, the smallest one (a leaf, whose
+    members come back as real particles) and labels that name no node."""
+    say("case: pseudo turbulent 40000, forced opening")
+    pos, m, h, rho = workloads.make_cloud("turbulent", 40000, seed=41)
+    src = pos[workloads.densest_particle(rho)][None, :]
+    ref, g, st = compare(ctx, oracle, pos, m, h, src, r_part=0.2, theta=0.5)
+    ps = ref["kind"] == 1
+    lab = ref["label"][ps]
+    leaf = lab[np.argmin(ref["count"][ps])]
+    assert ref["count"][ps].min() <= 8
+    bogus = np.array([2, 1 << 63, (1 << 60) | 12345], dtype=np.uint64)
+    open_labels = np.concatenate([lab[::3], [leaf], bogus])
+    ref2, g2, st2 = compare(ctx, oracle, pos, m, h, src, r_part=0.2, theta=0.5, open_labels=open_labels)
+    assert not np.isin(ref2["label"][ref2["kind"] == 1], open_labels).any()
+    assert st2["n_pseudo"] != st["n_pseudo"] or len(g2["kind"]) > len(g["kind"])
+    assert abs(g2["m"].sum() - m.sum()) < 1e-11 * m.sum()
+    say(f"  opened={len(open_labels)} entries {len(g['kind'])} -> {len(g2['kind'])}")
+
+
+def test_select_underresolved(ctx, oracle, workloads):
+    """The resolution check of eq. resol_param on the device against the
+    oracle's on the same entries and neutral fractions, including values on
+    the threshold itself."""
+    import paper_2410_15227_amd as pkg
+    say("case: underresolved selection, turbulent 40000")
+    pos, m, h, rho = workloads.make_cloud("turbulent", 40000, seed=42)
+    src = pos[workloads.densest_particle(rho)][None, :]
+    got = pkg.build_pseudo_particles(ctx, pos, h, m, src, r_part=0.2, theta=0.5)
+    kind = got["kind"].cpu().numpy()
+    label = got["label"].cpu().numpy().view(np.uint64)
+    s = got["s"].cpu().numpy()
+    s_root = got["stats"]["s_root"]
+    rng = np.random.default_rng(7)
+    for K in [2.0, 30.0, 300.0]:
+        f = rng.random(len(kind))
+        on = rng.random(len(kind)) < 0.2  # exactly at the threshold: not under-resolved
+        f[on] = np.array([oracle.fneu_limit(x / s_root, K) for x in s[on]])
+        want = oracle.underresolved(kind, label, s, f, s_root, K)
+        have = pkg.select_underresolved(ctx, got, f, K)
+        assert np.array_equal(have, want)
+        say(f"  K={K}: {len(want)} of {int((kind == 1).sum())} flagged")
+    assert len(pkg.select_underresolved(ctx, got, np.ones(len(kind)), 30.0)) == 0
+
+
+def test_adaptive_walk_converges(ctx, oracle, workloads):
+    """The adaptive walk of Sec. 2.4.1 on a clumpy cloud around one source
+    whose cells are ionised inside a sphere and neutral outside: it ends with
+    no under-resolved pseudo-particle, the final set is the oracle's walk with
+    the same nodes opened, and mass is conserved."""
+    import paper_2410_15227_amd as pkg
+    say("case: adaptive walk, turbulent 20000, Stromgren-like field")
+    pos, m, h, rho = workloads.make_cloud("turbulent", 20000, seed=43)
+    c = pos[workloads.densest_particle(rho)]
+    R = 0.25
+
+    def cell_fneu(gen):
+        r = np.linalg.norm(gen - c, axis=1)
+        return 0.5 * (1.0 + np.tanh((r - R) / 0.02))
+
+    K = 30.0
+    ps, hist = pkg.adaptive_pseudo_particles(ctx, pos, h, m, c[None, :], cell_fneu, K, max_iter=24,
+                                             r_part=0.1, theta=0.5)
+    for row in hist:
+        say(f"  {row}")
+    assert hist[-1]["n_failed"] == 0 and len(hist) >= 2
+    assert hist[0]["n_failed"] > 0
+    ref, g, st = compare(ctx, oracle, pos, m, h, c[None, :], r_part=0.1, theta=0.5, open_labels=ps["opened"])
+    f = ps["fneu"].cpu().numpy()
+    assert len(oracle.underresolved(ref["kind"], ref["label"], ref["s"], f, ref["s_root"], K)) == 0
+    assert abs(g["m"].sum() - m.sum()) < 1e-11 * m.sum()

@@ -1,0 +1,90 @@
+"""Pins of the adaptive tree walk's pieces (Sec. 2.4.1): the resolution
+parameter eq. resol_param against the worked example of App. A and its
+closed-form limits, the resolution check, node labels and the opening of
+named nodes."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "resol_param_appendix_a.json")
+
+
+def test_appendix_a_worked_example(oracle):
+    ex = json.load(open(GOLDEN))
+    lim = oracle.fneu_limit(ex["s_ratio"], ex["K"])
+    assert round(lim, ex["printed_decimals"]) == ex["f_neu_limit_printed"]
+    assert (ex["f_neu"] < lim) == ex["under_resolved"]
+
+
+@pytest.mark.parametrize("K", [1.01, 10.0, 30.0, 100.0, 500.0])
+def test_resol_param_limits(oracle, K):
+    # a node as large as the root needs f >= 1 - 1/K; a node of size s_root/K
+    # has threshold 0 (never under-resolved at or below that size); the
+    # threshold rises with the node size and with K
+    assert abs(oracle.fneu_limit(1.0, K) - (1.0 - 1.0 / K)) < 1e-15
+    assert abs(oracle.fneu_limit(1.0 / K, K)) < 1e-12
+    r = np.linspace(0.01, 1.0, 50)
+    v = np.array([oracle.fneu_limit(x, K) for x in r])
+    assert np.all(np.diff(v) > 0)
+    if K < 500:
+        assert oracle.fneu_limit(0.4, K * 2) > oracle.fneu_limit(0.4, K)
+
+
+def test_check_selects_in_entry_order(oracle):
+    kind = np.array([1, 0, 1, 1, 1], dtype=np.int32)
+    label = np.array([9, 10, 11, 12, 13], dtype=np.uint64)
+    s = np.array([0.4, 0.4, 0.4, 0.01, 0.4])
+    f = np.array([0.8, 0.0, 0.95, 0.0, 0.9])  # K = 30: limit 0.91667 at s/s_root = 0.4
+    got = oracle.underresolved(kind, label, s, f, 1.0, 30.0)
+    assert list(got) == [9, 13]  # real entries and small nodes are never flagged
+
+
+def decode(label):
+    label = int(label)
+    d = (label.bit_length() - 1) // 3
+    ix = iy = iz = 0
+    for lvl in range(d):
+        o = (label >> (3 * (d - 1 - lvl))) & 7
+        ix = 2 * ix + (o & 1)
+        iy = 2 * iy + ((o >> 1) & 1)
+        iz = 2 * iz + ((o >> 2) & 1)
+    return d, ix, iy, iz
+
+
+def test_labels_name_the_cubes(oracle, workloads):
+    pos, m, h, rho = workloads.make_cloud("uniform", 4000, 61)
+    b = oracle.pseudo_build(pos, m, h, [[0.3, 0.6, 0.5]], r_part=0.2, theta=0.5)
+    for e in range(len(b["kind"])):
+        d, ix, iy, iz = decode(b["label"][e])
+        if b["kind"][e] == 0:  # a real particle lies in its unit's cube
+            x = pos[b["first"][e]] * 2.0**d
+            assert (int(x[0]), int(x[1]), int(x[2])) == (ix, iy, iz)
+        assert (int(b["label"][e]).bit_length() - 1) % 3 == 0
+
+
+def test_opening_named_nodes(oracle, workloads):
+    pos, m, h, rho = workloads.make_cloud("turbulent", 8000, 62)
+    src = [pos[workloads.densest_particle(rho)]]
+    a = oracle.pseudo_build(pos, m, h, src, r_part=0.2, theta=0.5)
+    ps = a["kind"] == 1
+    lab = a["label"][ps]
+    # opening every pseudo-particle refines all of them: none of the old labels survives
+    b = oracle.pseudo_build(pos, m, h, src, r_part=0.2, theta=0.5, open_labels=lab)
+    assert not np.isin(b["label"][b["kind"] == 1], lab).any()
+    assert (b["kind"] == 1).sum() >= ps.sum() and len(b["kind"]) > len(a["kind"])
+    assert abs(b["mass"].sum() - m.sum()) < 1e-12
+    real = b["first"][b["kind"] == 0]
+    assert len(np.unique(real)) == len(real)
+    # every particle is covered exactly once: by itself or by one pseudo-particle
+    assert b["count"].sum() == len(m)
+    # a forced-open leaf gives its members back as real particles under its label
+    leaf = a["label"][ps][np.argmin(a["count"][ps])]
+    d = oracle.pseudo_build(pos, m, h, src, r_part=0.2, theta=0.5, open_labels=np.array([leaf], np.uint64))
+    sel = d["label"] == leaf
+    assert a["count"][ps].min() <= 8  # the smallest pseudo-particle is a leaf here
+    assert (d["kind"][sel] == 0).all() and sel.sum() == a["count"][ps].min()
+    # labels that name no node change nothing
+    c = oracle.pseudo_build(pos, m, h, src, r_part=0.2, theta=0.5, open_labels=np.array([3, 2**62 + 5], np.uint64))
+    assert np.array_equal(c["pos"], a["pos"]) and np.array_equal(c["label"], a["label"])
