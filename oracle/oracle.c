@@ -638,6 +638,7 @@ typedef struct {
   double *pos;      /* [][3] */
   double *mass, *h, *s;
   int32_t *unit;    /* h-solve unit of the entry */
+  int64_t *owner;   /* [n particles] entry that holds the particle */
   /* h-solve units: accepted nodes and opened leaves */
   int64_t n_units;
   double *upos;     /* [][3] */
@@ -653,6 +654,7 @@ static void walk(const otree_t *T, int32_t id, int n_src, const double *src, dou
     E->unit[e] = (int32_t)u;
     E->label[e] = nd->label;
     E->count[e] = nd->count;
+    for (int64_t t = 0; t < nd->count; ++t) E->owner[T->order[nd->first + t]] = e;
     if (nd->count == 1) {
       int64_t j = T->order[nd->first];
       E->kind[e] = 0;
@@ -682,6 +684,7 @@ static void walk(const otree_t *T, int32_t id, int n_src, const double *src, dou
       int64_t e = E->n++;
       E->unit[e] = (int32_t)u;
       E->label[e] = nd->label;
+      E->owner[j] = e;
       E->kind[e] = 0;
       E->first[e] = j;
       E->count[e] = 1;
@@ -775,7 +778,8 @@ int ora_node_h(const double *a, double s, int64_t nu, const double *upos, double
    kind, first (lowest member index), count, pos, mass, h, s (node size),
    branch (-1 for real particles), unit (h-solve unit of the entry), label
    (node label of the entry's unit: a 1 followed by the octant digits from
-   the root down, 3 bits per level).  Nodes whose labels are among the
+   the root down, 3 bits per level), owner ([n]: the entry that holds each
+   particle, itself or its pseudo-particle).  Nodes whose labels are among the
    n_open labels in open (any order) are opened whatever the walk criterion
    says.  Returns the number of emitted entries; *n_units_out = number of
    units, upos_out (capacity n*3) their positions; *n_nodes_out = tree size;
@@ -784,8 +788,8 @@ int64_t ora_pseudo_build(int64_t n, const double *x, const double *m, const doub
                          const double *src, double r_part, double theta, double hfact, double eps,
                          int32_t leaf_max, int32_t max_depth, int64_t bypass, int64_t n_open, const uint64_t *open,
                          int32_t *kind, int64_t *first, int64_t *count, double *pos, double *mass, double *h,
-                         double *s, int32_t *branch, int32_t *unit, uint64_t *label, int64_t *n_units_out,
-                         double *upos_out, int64_t *n_nodes_out, double *s_root_out) {
+                         double *s, int32_t *branch, int32_t *unit, uint64_t *label, int64_t *owner,
+                         int64_t *n_units_out, double *upos_out, int64_t *n_nodes_out, double *s_root_out) {
   otree_t T;
   T.x = x;
   T.m = m;
@@ -813,6 +817,7 @@ int64_t ora_pseudo_build(int64_t n, const double *x, const double *m, const doub
   E.h = h;
   E.s = s;
   E.unit = unit;
+  E.owner = owner;
   E.n_units = 0;
   E.upos = upos_out;
   walk(&T, 0, n_src, src, r_part, theta, hp, &E);
@@ -853,4 +858,40 @@ int64_t ora_underresolved(int64_t n, const int32_t *kind, const uint64_t *label,
   for (int64_t e = 0; e < n; ++e)
     if (kind[e] == 1 && fneu[e] < ora_fneu_limit(s[e] / s_root, K)) out[k++] = label[e];
   return k;
+}
+
+/* Per-particle values from the mixed set (Sec. 3.3: the paper proposes
+   interpolating each SPH particle's ionic fraction from the pseudo-particles
+   whose smoothing spheres reach it, instead of giving every member its node's
+   value).  Reading: a particle that is an entry itself keeps that entry's
+   value; any other particle i takes the kernel-weighted mean over all entries
+   j with |x_i - x_j| < 2 h_j,
+     q_i = sum_j W(|x_i - x_j|, h_j) q_j / sum_j W(|x_i - x_j|, h_j),
+   with W the M4 kernel of the entry's own h (Shepard normalisation), and its
+   owner's value when no entry reaches it.  Plain O(n E) loop, entries in
+   index order.  values and out are [][ncomp]. */
+void ora_interpolate(int64_t n, const double *x, const int64_t *owner, int64_t ne, const double *ex,
+                     const double *eh, const int32_t *ekind, const double *val, int32_t ncomp, double *out) {
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t o = owner[i];
+    double *oi = out + (int64_t)ncomp * i;
+    if (ekind[o] == 0) {
+      for (int k = 0; k < ncomp; ++k) oi[k] = val[(int64_t)ncomp * o + k];
+      continue;
+    }
+    double den = 0.0;
+    double num[16];
+    for (int k = 0; k < ncomp; ++k) num[k] = 0.0;
+    for (int64_t j = 0; j < ne; ++j) {
+      const double dx = x[3 * i] - ex[3 * j], dy = x[3 * i + 1] - ex[3 * j + 1], dz = x[3 * i + 2] - ex[3 * j + 2];
+      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      const double hj = eh[j];
+      if (!(r < 2.0 * hj)) continue;
+      const double W = ora_w(r / hj) / (M_PI * hj * hj * hj);
+      den += W;
+      for (int k = 0; k < ncomp; ++k) num[k] += W * val[(int64_t)ncomp * j + k];
+    }
+    for (int k = 0; k < ncomp; ++k) oi[k] = den > 0.0 ? num[k] / den : val[(int64_t)ncomp * o + k];
+  }
 }

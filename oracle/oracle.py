@@ -61,11 +61,13 @@ def _lib():
         L.ora_node_h.restype = ctypes.c_int
         L.ora_node_h.argtypes = [vp, dbl, i64, vp, dbl, dbl, vp, vp]
         L.ora_pseudo_build.restype = i64
-        L.ora_pseudo_build.argtypes = [i64, vp, vp, vp, i32, vp, dbl, dbl, dbl, dbl, i32, i32, i64, i64, vp] + [vp] * 14
+        L.ora_pseudo_build.argtypes = [i64, vp, vp, vp, i32, vp, dbl, dbl, dbl, dbl, i32, i32, i64, i64, vp] + [vp] * 15
         L.ora_fneu_limit.restype = dbl
         L.ora_fneu_limit.argtypes = [dbl, dbl]
         L.ora_underresolved.restype = i64
         L.ora_underresolved.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, vp]
+        L.ora_interpolate.restype = None
+        L.ora_interpolate.argtypes = [i64, vp, vp, i64, vp, vp, vp, vp, i32, vp]
         _L = L
     return _L
 
@@ -204,7 +206,8 @@ def pseudo_build(pos, m, h, sources, r_part=0.2, theta=0.5, hfact=1.2, eps=1e-2,
                  bypass=1_000_000, open_labels=None):
     """Tree-walk pseudo-particles and node smoothing lengths.  Returns a dict
     of arrays in emission order.  open_labels: node labels to open whatever
-    the walk criterion says (the failed nodes of an earlier walk)."""
+    the walk criterion says (the failed nodes of an earlier walk).  'owner'
+    gives, for every particle, the entry that holds it."""
     pos, m, h = _c(pos, np.float64), _c(m, np.float64), _c(h, np.float64)
     src = _c(np.asarray(sources, float).reshape(-1, 3), np.float64)
     n = pos.shape[0]
@@ -218,6 +221,7 @@ def pseudo_build(pos, m, h, sources, r_part=0.2, theta=0.5, hfact=1.2, eps=1e-2,
     branch = np.empty(n, dtype=np.int32)
     unit = np.empty(n, dtype=np.int32)
     label = np.empty(n, dtype=np.uint64)
+    owner = np.empty(n, dtype=np.int64)
     nu = np.zeros(1, dtype=np.int64)
     upos = np.empty((n, 3))
     nn = np.zeros(1, dtype=np.int64)
@@ -225,11 +229,11 @@ def pseudo_build(pos, m, h, sources, r_part=0.2, theta=0.5, hfact=1.2, eps=1e-2,
     op = np.ascontiguousarray(np.asarray(open_labels if open_labels is not None else [], dtype=np.uint64))
     k = _lib().ora_pseudo_build(n, _p(pos), _p(m), _p(h), src.shape[0], _p(src), r_part, theta, hfact, eps,
                                 leaf_max, max_depth, bypass, len(op), _p(op), _p(kind), _p(first), _p(count),
-                                _p(opos), _p(mass), _p(oh), _p(s), _p(branch), _p(unit), _p(label), _p(nu),
+                                _p(opos), _p(mass), _p(oh), _p(s), _p(branch), _p(unit), _p(label), _p(owner), _p(nu),
                                 _p(upos), _p(nn), _p(sroot))
     k = int(k)
     return dict(kind=kind[:k], first=first[:k], count=count[:k], pos=opos[:k], mass=mass[:k], h=oh[:k], s=s[:k],
-                branch=branch[:k], unit=unit[:k], label=label[:k], upos=upos[:int(nu[0])], n_nodes=int(nn[0]),
+                branch=branch[:k], unit=unit[:k], label=label[:k], owner=owner, upos=upos[:int(nu[0])], n_nodes=int(nn[0]),
                 s_root=float(sroot[0]))
 
 
@@ -247,3 +251,22 @@ def underresolved(kind, label, s, fneu, s_root: float, K: float):
     out = np.empty(len(kind), dtype=np.uint64)
     k = _lib().ora_underresolved(len(kind), _p(kind), _p(label), _p(s), _p(fneu), float(s_root), float(K), _p(out))
     return out[:int(k)]
+
+
+def interpolate(pos, owner, entry_pos, entry_h, entry_kind, values):
+    """Per-particle values from the mixed set (Sec. 3.3): a particle that is
+    an entry keeps its value, any other takes the Shepard-normalised M4
+    average over the entries whose 2h spheres reach it (its owner's value when
+    none does).  values: [E] or [E][k]."""
+    pos = _c(pos, np.float64)
+    owner = _c(owner, np.int64)
+    ex = _c(entry_pos, np.float64)
+    eh = _c(entry_h, np.float64)
+    ek = _c(entry_kind, np.int32)
+    v = np.asarray(values, dtype=np.float64)
+    k = 1 if v.ndim == 1 else v.shape[1]
+    assert k <= 16
+    v = np.ascontiguousarray(v.reshape(len(eh), k))
+    out = np.empty((pos.shape[0], k))
+    _lib().ora_interpolate(pos.shape[0], _p(pos), _p(owner), len(eh), _p(ex), _p(eh), _p(ek), _p(v), k, _p(out))
+    return out[:, 0] if np.asarray(values).ndim == 1 else out
