@@ -863,13 +863,16 @@ int64_t ora_underresolved(int64_t n, const int32_t *kind, const uint64_t *label,
 /* Per-particle values from the mixed set (Sec. 3.3: the paper proposes
    interpolating each SPH particle's ionic fraction from the pseudo-particles
    whose smoothing spheres reach it, instead of giving every member its node's
-   value).  Reading: a particle that is an entry itself keeps that entry's
-   value; any other particle i takes the kernel-weighted mean over all entries
-   j with |x_i - x_j| < 2 h_j,
-     q_i = sum_j W(|x_i - x_j|, h_j) q_j / sum_j W(|x_i - x_j|, h_j),
-   with W the M4 kernel of the entry's own h (Shepard normalisation), and its
-   owner's value when no entry reaches it.  Plain O(n E) loop, entries in
-   index order.  values and out are [][ncomp]. */
+   value).  Reading: the SPH interpolant over the entries, each entry j with
+   the volume its smoothing length stands for, V_j = (h_j / h_fact)^3 (the
+   h-density relation of eq. h_node for pseudo-particles, and of the SPH
+   particles themselves), normalised by the same sum (Shepard):
+     q_i = sum_j V_j W(|x_i - x_j|, h_j) q_j / sum_j V_j W(|x_i - x_j|, h_j)
+         = sum_j w(r_ij / h_j) q_j / sum_j w(r_ij / h_j)
+   over the entries with |x_i - x_j| < 2 h_j (the h^3 and h_fact cancel; w
+   is the dimensionless M4 kernel).  A particle that is an entry itself keeps
+   that entry's value, one that no sphere reaches its owner's value.  Plain
+   O(n E) loop, entries in index order.  values and out are [][ncomp]. */
 void ora_interpolate(int64_t n, const double *x, const int64_t *owner, int64_t ne, const double *ex,
                      const double *eh, const int32_t *ekind, const double *val, int32_t ncomp, double *out) {
 #pragma omp parallel for schedule(dynamic, 64)
@@ -888,7 +891,7 @@ void ora_interpolate(int64_t n, const double *x, const int64_t *owner, int64_t n
       const double r = sqrt(dx * dx + dy * dy + dz * dz);
       const double hj = eh[j];
       if (!(r < 2.0 * hj)) continue;
-      const double W = ora_w(r / hj) / (M_PI * hj * hj * hj);
+      const double W = ora_w(r / hj);
       den += W;
       for (int k = 0; k < ncomp; ++k) num[k] += W * val[(int64_t)ncomp * j + k];
     }

@@ -255,9 +255,10 @@ def underresolved(kind, label, s, fneu, s_root: float, K: float):
 
 def interpolate(pos, owner, entry_pos, entry_h, entry_kind, values):
     """Per-particle values from the mixed set (Sec. 3.3): a particle that is
-    an entry keeps its value, any other takes the Shepard-normalised M4
-    average over the entries whose 2h spheres reach it (its owner's value when
-    none does).  values: [E] or [E][k]."""
+    an entry keeps its value, any other takes the Shepard-normalised SPH
+    interpolant over the entries whose 2h spheres reach it, each weighted by
+    w(r / h_j) (volume (h_j / h_fact)^3 times W; its owner's value when none
+    reaches it).  values: [E] or [E][k]."""
     pos = _c(pos, np.float64)
     owner = _c(owner, np.int64)
     ex = _c(entry_pos, np.float64)

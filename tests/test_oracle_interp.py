@@ -1,8 +1,9 @@
 """Pins of the per-particle interpolation from the mixed set (Sec. 3.3: each
 SPH particle's value taken from the entries whose smoothing spheres reach it,
 the refinement the paper proposes over giving every member its node's value).
-Closed forms use the M4 kernel's textbook values w(0) = 1, w(1) = 1/4,
-w(3/2) = 1/32 with W = w(r/h) / (pi h^3)."""
+The SPH interpolant with entry volumes (h/h_fact)^3 (eq. h_node) weights each
+entry by the dimensionless kernel w(r/h) alone; closed forms use the M4
+kernel's textbook values w(0) = 1, w(1) = 1/4, w(3/2) = 1/32."""
 import numpy as np
 import pytest
 
@@ -16,8 +17,10 @@ def test_closed_forms(oracle):
     # a member of pseudo-particle A at A's centre; B is another entry
     # same h: weights 1 and 1/4 -> (0 * 1 + 1 * 1/4) / (5/4)
     assert abs(one(oracle, [0, 0, 0], [[0, 0, 0], [1, 0, 0]], [1, 1], [1, 0], [0, 1]) - 0.2) < 1e-15
-    # h_B = 1/2 at r = 1/2 (q = 1): W_B = (1/4) 8 / pi = 2 / pi against W_A = 1 / pi
-    assert abs(one(oracle, [0, 0, 0], [[0, 0, 0], [0, 0.5, 0]], [1, 0.5], [1, 1], [0, 1]) - 2.0 / 3.0) < 1e-15
+    # h_B = 1/2 at r = 1/2: the same q = 1, so the same weight 1/4 whatever h is
+    assert abs(one(oracle, [0, 0, 0], [[0, 0, 0], [0, 0.5, 0]], [1, 0.5], [1, 1], [0, 1]) - 0.2) < 1e-15
+    # h_A = 3 at r = 0 and h_B = 0.4 at r = 0.6 (q = 3/2): weights 1 and 1/32
+    assert abs(one(oracle, [0, 0, 0], [[0, 0, 0], [0.6, 0, 0]], [3, 0.4], [1, 1], [0, 1]) - 1.0 / 33.0) < 1e-15
     # q = 3/2: weights 1 and 1/32
     assert abs(one(oracle, [0, 0, 0], [[0, 0, 0], [0, 0, 1.5]], [1, 1], [1, 1], [0, 1]) - 1.0 / 33.0) < 1e-15
     # at exactly r = 2h an entry adds nothing
