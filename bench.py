@@ -257,7 +257,10 @@ def run_pseudo(args):
     (pseudo-particles + real particles near the source) is mapped onto the
     Voronoi grid of its own positions; the same mapping of all particles on
     their own grid is timed beside it.  One timed step = the pseudo-particle
-    build + the forward and inverse mapping of the mixed set."""
+    build + the forward and inverse mapping of the mixed set + the
+    interpolation of the inverse-mapped values onto all particles (Sec. 3.3).
+    The cell field is a Stromgren-like sphere around the source,
+    f = (1 + tanh((r - 0.25) / 0.02)) / 2."""
     import numpy as np
     import torch
 
@@ -301,12 +304,6 @@ def run_pseudo(args):
     dt_mix = ctx.upload(tess_mix)
     dt_all = ctx.upload(tess_all)
 
-    def mapping(dt, x, hh, mm, n_cells):
-        res = pkg.map_particles_to_cells(ctx, dt, x, hh, mm, precision=args.precision, keep_pairs=True)
-        q = torch.ones(n_cells, dtype=torch.float64, device=dev)
-        pkg.map_cells_to_particles(ctx, res.pairs, q)
-        return res
-
     def timed(fn, steps):
         for _ in range(args.warmup):
             fn()
@@ -318,13 +315,41 @@ def run_pseudo(args):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps, out
 
+    def field(gen):
+        r = np.linalg.norm(np.asarray(gen) - src, axis=1)
+        return torch.tensor(0.5 * (1.0 + np.tanh((r - 0.25) / 0.02)), dtype=torch.float64, device=dev)
+
+    f_mix = field(tess_mix.generators)
+    f_all = field(tess_all.generators)
+    fe = {}
+
+    def mapping(dt, x, hh, mm, f_cells):
+        res = pkg.map_particles_to_cells(ctx, dt, x, hh, mm, precision=args.precision, keep_pairs=True)
+        fe["v"] = pkg.map_cells_to_particles(ctx, res.pairs, f_cells)
+        return res
+
+    def interp():
+        return pkg.interpolate_to_particles(ctx, xyz, ps, fe["v"])
+
     build_s, _ = timed(build, args.steps)
-    mix_s, res_mix = timed(lambda: mapping(dt_mix, mix_xyz, mix_hd, mix_md, tess_mix.n_cells), args.steps)
-    all_s, res_all = timed(lambda: mapping(dt_all, xyz, hd, md, tess_all.n_cells), max(1, args.steps // 2))
+    mix_s, res_mix = timed(lambda: mapping(dt_mix, mix_xyz, mix_hd, mix_md, f_mix), args.steps)
+    ctx.reset_timing()
+    ctx.set_timing(True)
+    interp_s, f_interp = timed(interp, args.steps)
+    ms, launches = ctx.kernel_time("interp")
+    interp_kernel_ms = ms / max(1, launches)
+    ctx.set_timing(False)
+    f_mix_entries = fe["v"]
+    f_owner = f_mix_entries[ps["owner"]]
+    all_s, res_all = timed(lambda: mapping(dt_all, xyz, hd, md, f_all), max(1, args.steps // 2))
+    f_direct = fe["v"]
+    # how far each per-particle field is from the all-particle mapping's
+    gap_owner = float((f_owner - f_direct).abs().mean().item())
+    gap_interp = float((f_interp - f_direct).abs().mean().item())
     pairs_mix, pairs_all = res_mix.pairs.n_pairs, res_all.pairs.n_pairs
     tot_mix = float(res_mix.mass.sum().item())
     tot_all = float(res_all.mass.sum().item())
-    step_s = build_s + mix_s
+    step_s = build_s + mix_s + interp_s
     out = {
         "metric": "particle-cell pair integrals/s",
         "value": round(pairs_mix / mix_s, 1),
@@ -345,7 +370,11 @@ def run_pseudo(args):
                    "pairs_all": int(pairs_all), "pairs_mixed": int(pairs_mix),
                    "pair_reduction": round(pairs_all / max(pairs_mix, 1), 3),
                    "build_ms": round(build_s * 1e3, 3), "map_mixed_ms": round(mix_s * 1e3, 3),
-                   "map_all_ms": round(all_s * 1e3, 3),
+                   "map_all_ms": round(all_s * 1e3, 3), "interp_ms": round(interp_s * 1e3, 3),
+                   "interp_kernel_ms": round(interp_kernel_ms, 3),
+                   "interp_particles_per_s": round(n_all / interp_s, 1),
+                   "mean_abs_gap_to_all_particle_map": {"owner_value": round(gap_owner, 6),
+                                                       "interpolated": round(gap_interp, 6)},
                    "speedup_vs_all_particles": round(all_s / step_s, 3),
                    "mass_mixed_grid": tot_mix, "mass_all_grid": tot_all,
                    "host_voronoi_s": {"mixed": round(vor_mix_s, 2), "all": round(vor_all_s, 2)}},

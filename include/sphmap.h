@@ -233,6 +233,9 @@ int build_pseudo_particles(sphmap_ctx *ctx, int64_t n, const double *d_xyz, cons
  *     name no node are ignored.
  *   d_out_label [capacity] (device, may be NULL): the label of each entry's
  *     unit (the accepted node, or the opened leaf holding the particle).
+ *   d_out_owner [n] (device, may be NULL): for every input particle, the
+ *     index of the entry that holds it (itself when emitted as a real
+ *     particle, else its pseudo-particle).
  * A node label is a 1 followed by the node's octant digits (x + 2y + 4z,
  * 3 bits per level) from the root down; the root is 1. */
 int build_pseudo_particles_open(sphmap_ctx *ctx, int64_t n, const double *d_xyz, const double *d_h,
@@ -240,8 +243,8 @@ int build_pseudo_particles_open(sphmap_ctx *ctx, int64_t n, const double *d_xyz,
                                 const sphmap_pseudo_opts *opts, int64_t n_open, const uint64_t *d_open_labels,
                                 int64_t capacity, double *d_out_xyz, double *d_out_h, double *d_out_m,
                                 double *d_out_s, int32_t *d_out_kind, int64_t *d_out_first, int64_t *d_out_count,
-                                int32_t *d_out_branch, uint64_t *d_out_label, int64_t *n_out,
-                                sphmap_pseudo_stats *stats, void *stream);
+                                int32_t *d_out_branch, uint64_t *d_out_label, int64_t *d_out_owner,
+                                int64_t *n_out, sphmap_pseudo_stats *stats, void *stream);
 
 /* Resolution check of the adaptive walk (eq. resol_param, Sec. 2.4.1): a
  * pseudo-particle (kind 1) of size s whose neutral fraction f is below
@@ -255,11 +258,34 @@ int select_underresolved(sphmap_ctx *ctx, int64_t n, const int32_t *d_kind, cons
                          const double *d_s, const double *d_fneu, double s_root, double K, uint64_t *d_out_labels,
                          int64_t *n_found, void *stream);
 
+/* Per-particle values from the mixed set (Sec. 3.3: the refinement the paper
+ * proposes over giving every member of a pseudo-particle its node's value).
+ * A particle whose owner is a real entry (kind 0) takes that entry's values;
+ * any other particle i takes the Shepard-normalised SPH interpolant
+ *   q_i = sum_j w(r_ij / h_j) q_j / sum_j w(r_ij / h_j)
+ * over all entries j with r_ij = |x_i - x_j| < 2 h_j (each entry weighted by
+ * its volume (h_j / h_fact)^3 of eq. h_node times W(r_ij, h_j), which leaves
+ * the dimensionless M4 kernel w), or its owner's values when no entry
+ * reaches it.
+ *   d_xyz [n][3]: particle positions; d_owner [n]: entry holding each particle
+ *     (build_pseudo_particles_open's d_out_owner).
+ *   d_entry_xyz [n_entries][3], d_entry_h, d_entry_kind: the mixed set.
+ *   d_values [n_entries][ncomp]: entry values (e.g. the inverse map of the
+ *     cell ionic fractions); d_out [n][ncomp].
+ * All arrays device-resident, owned by the caller.  Positions must lie in
+ * [0,1)^3 and owners in [0, n_entries): EINVAL otherwise, nothing written.
+ * Each value is summed by one thread in a fixed order: results repeat bit
+ * for bit. */
+int interpolate_to_particles(sphmap_ctx *ctx, int64_t n, const double *d_xyz, const int64_t *d_owner,
+                             int64_t n_entries, const double *d_entry_xyz, const double *d_entry_h,
+                             const int32_t *d_entry_kind, const double *d_values, int32_t ncomp, double *d_out,
+                             void *stream);
+
 /* ------------------------------------------------------------------------
  * Kernel timing: when enabled, HIP events are recorded on the launch stream
  * around each launch of the named kernels ("exact_integral", "exact_redo",
  * "pair_fill", "pair_count", "cell_reduce", "reverse", "transpose",
- * "node_hsolve").
+ * "node_hsolve", "interp").
  * sphmap_kernel_time synchronises on the recorded events and returns the
  * summed milliseconds and the number of launches since the last reset.
  * ---------------------------------------------------------------------- */

@@ -280,7 +280,8 @@ def build_pseudo_particles(ctx: Context, xyz, h, m, sources, r_part: float = 0.2
     """Tree-node pseudo-particles and their smoothing lengths (Sec. 2.4).
     open_labels: node labels to open whatever the walk criterion says (the
     failed nodes of an earlier walk).  Returns a dict of device tensors in
-    emission order (with each entry's node 'label') plus 'stats'."""
+    emission order (with each entry's node 'label'), 'owner' (for every
+    input particle, the entry that holds it) and 'stats'."""
     import numpy as np
     torch = _torch()
     dev = ctx.device
@@ -300,6 +301,7 @@ def build_pseudo_particles(ctx: Context, xyz, h, m, sources, r_part: float = 0.2
              count=torch.empty(cap, dtype=torch.int64, device=dev),
              branch=torch.empty(cap, dtype=torch.int32, device=dev),
              label=torch.empty(cap, dtype=torch.int64, device=dev))  # uint64 bit patterns
+    owner = torch.empty(n, dtype=torch.int64, device=dev)
     if open_labels is not None and len(open_labels) > 0:
         ol = torch.as_tensor(np.asarray(open_labels, dtype=np.uint64).view(np.int64), device=dev).contiguous()
     else:
@@ -310,9 +312,10 @@ def build_pseudo_particles(ctx: Context, xyz, h, m, sources, r_part: float = 0.2
         ctx.handle, n, _ptr(xyz), _ptr(h), _ptr(m), src.shape[0], src.ctypes.data_as(ctypes.c_void_p),
         ctypes.byref(opts), 0 if ol is None else ol.shape[0], _ptr(ol), cap, _ptr(o["xyz"]), _ptr(o["h"]),
         _ptr(o["m"]), _ptr(o["s"]), _ptr(o["kind"]), _ptr(o["first"]), _ptr(o["count"]), _ptr(o["branch"]),
-        _ptr(o["label"]), ctypes.byref(n_out), ctypes.byref(st), _stream_handle(stream)))
+        _ptr(o["label"]), _ptr(owner), ctypes.byref(n_out), ctypes.byref(st), _stream_handle(stream)))
     k = n_out.value
     res = {key: val[:k] for key, val in o.items()}
+    res["owner"] = owner
     res["stats"] = dict(n_nodes=st.n_nodes, n_units=st.n_units, n_pseudo=st.n_pseudo, n_real=st.n_real,
                         branch_count=list(st.branch_count), s_root=st.s_root)
     return res
@@ -332,6 +335,31 @@ def select_underresolved(ctx: Context, ps: dict, fneu, K: float, stream=None):
                                                  _ptr(fneu), float(ps["stats"]["s_root"]), float(K), _ptr(out),
                                                  ctypes.byref(cnt), _stream_handle(stream)))
     return out[:cnt.value].cpu().numpy().view(np.uint64)
+
+
+def interpolate_to_particles(ctx: Context, xyz, ps: dict, values, stream=None):
+    """Per-particle values from the mixed set `ps` (Sec. 3.3): a particle
+    emitted as itself keeps its entry's value; a member of a pseudo-particle
+    takes the Shepard-normalised SPH interpolant over the entries whose 2h
+    spheres reach it, entry j weighted by w(r / h_j) (its volume
+    (h_j / h_fact)^3 times W).  values: [E] or [E][k] per entry; returns [n] or
+    [n][k] on the device."""
+    torch = _torch()
+    dev = ctx.device
+    xyz = _dev_f64(xyz, dev, 3)
+    v = _dev_f64(values, dev)
+    if v.dim() not in (1, 2):
+        raise ValueError("values must be [E] or [E][k]")
+    ne = ps["kind"].shape[0]
+    k = 1 if v.dim() == 1 else v.shape[1]
+    if v.shape[0] != ne:
+        raise ValueError(f"values has {v.shape[0]} rows for {ne} entries")
+    n = xyz.shape[0]
+    out = torch.empty((n, k) if v.dim() == 2 else n, dtype=torch.float64, device=dev)
+    ctx.check(_native.lib().interpolate_to_particles(
+        ctx.handle, n, _ptr(xyz), _ptr(ps["owner"]), ne, _ptr(ps["xyz"]), _ptr(ps["h"]), _ptr(ps["kind"]),
+        _ptr(v), k, _ptr(out), _stream_handle(stream)))
+    return out
 
 
 def adaptive_pseudo_particles(ctx: Context, xyz, h, m, sources, cell_fneu, K: float, max_iter: int = 16,

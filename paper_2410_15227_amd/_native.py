@@ -20,6 +20,7 @@ EXPORTS = [
     "sphmap_tess_upload", "sphmap_tess_free", "sphmap_tess_cell_info",
     "map_particles_to_cells", "map_particles_to_cells_batch", "sphmap_pairs_info", "sphmap_pairs_export", "sphmap_pairs_free",
     "map_cells_to_particles", "build_pseudo_particles", "build_pseudo_particles_open", "select_underresolved",
+    "interpolate_to_particles",
     "sphmap_set_timing", "sphmap_kernel_time", "sphmap_reset_timing",
     "sphmap_set_counting", "sphmap_work_counters", "sphmap_set_autotune", "sphmap_tuned_shape",
 ]
@@ -87,11 +88,13 @@ def lib():
         L.map_cells_to_particles.argtypes = [vp, vp, vp, i32, vp, vp]
         L.build_pseudo_particles_open.restype = ctypes.c_int
         L.build_pseudo_particles_open.argtypes = [vp, i64, vp, vp, vp, i32, vp, ctypes.POINTER(PseudoOpts), i64, vp,
-                                                  i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i64),
+                                                  i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i64),
                                                   ctypes.POINTER(PseudoStats), vp]
         L.select_underresolved.restype = ctypes.c_int
         L.select_underresolved.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.c_double, ctypes.c_double, vp,
                                            ctypes.POINTER(i64), vp]
+        L.interpolate_to_particles.restype = ctypes.c_int
+        L.interpolate_to_particles.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp, i32, vp, vp]
         L.build_pseudo_particles.restype = ctypes.c_int
         L.build_pseudo_particles.argtypes = [vp, i64, vp, vp, vp, i32, vp, ctypes.POINTER(PseudoOpts), i64,
                                              vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i64),

@@ -330,8 +330,8 @@ int build_pseudo_particles_open(sphmap_ctx *ctx, int64_t n, const double *d_xyz,
                                 const sphmap_pseudo_opts *opts, int64_t n_open, const uint64_t *d_open_labels,
                                 int64_t capacity, double *d_out_xyz, double *d_out_h, double *d_out_m,
                                 double *d_out_s, int32_t *d_out_kind, int64_t *d_out_first, int64_t *d_out_count,
-                                int32_t *d_out_branch, uint64_t *d_out_label, int64_t *n_out,
-                                sphmap_pseudo_stats *stats, void *stream) {
+                                int32_t *d_out_branch, uint64_t *d_out_label, int64_t *d_out_owner,
+                                int64_t *n_out, sphmap_pseudo_stats *stats, void *stream) {
   if (!ctx) return SPHMAP_EINVAL;
   return guarded(ctx, [&] {
     SPH_REQUIRE(n >= 1 && n < ((int64_t)1 << 31), SPHMAP_EINVAL, "n out of range [1, 2^31)");
@@ -361,6 +361,7 @@ int build_pseudo_particles_open(sphmap_ctx *ctx, int64_t n, const double *d_xyz,
     a.o_count = d_out_count;
     a.o_branch = d_out_branch;
     a.o_label = d_out_label;
+    a.o_owner = d_out_owner;
     a.n_open = n_open;
     a.open_labels = d_open_labels;
     a.n_out = 0;
@@ -378,7 +379,7 @@ int build_pseudo_particles(sphmap_ctx *ctx, int64_t n, const double *d_xyz, cons
                            sphmap_pseudo_stats *stats, void *stream) {
   return build_pseudo_particles_open(ctx, n, d_xyz, d_h, d_m, n_src, h_sources, opts, 0, nullptr, capacity,
                                      d_out_xyz, d_out_h, d_out_m, d_out_s, d_out_kind, d_out_first, d_out_count,
-                                     d_out_branch, nullptr, n_out, stats, stream);
+                                     d_out_branch, nullptr, nullptr, n_out, stats, stream);
 }
 
 int select_underresolved(sphmap_ctx *ctx, int64_t n, const int32_t *d_kind, const uint64_t *d_label,
@@ -391,6 +392,23 @@ int select_underresolved(sphmap_ctx *ctx, int64_t n, const int32_t *d_kind, cons
     SPH_REQUIRE(s_root > 0.0 && K > 1.0, SPHMAP_EINVAL, "need s_root > 0 and K > 1");
     *n_found = sphmap::select_underresolved(ctx->c, n, d_kind, d_label, d_s, d_fneu, s_root, K, d_out_labels,
                                             as_stream(stream));
+  });
+}
+
+int interpolate_to_particles(sphmap_ctx *ctx, int64_t n, const double *d_xyz, const int64_t *d_owner,
+                             int64_t n_entries, const double *d_entry_xyz, const double *d_entry_h,
+                             const int32_t *d_entry_kind, const double *d_values, int32_t ncomp, double *d_out,
+                             void *stream) {
+  if (!ctx) return SPHMAP_EINVAL;
+  return guarded(ctx, [&] {
+    SPH_REQUIRE(n >= 0 && n < ((int64_t)1 << 31), SPHMAP_EINVAL, "n out of range [0, 2^31)");
+    SPH_REQUIRE(n_entries >= 1 && n_entries < ((int64_t)1 << 31), SPHMAP_EINVAL,
+                "n_entries out of range [1, 2^31)");
+    SPH_REQUIRE(ncomp >= 1, SPHMAP_EINVAL, "ncomp must be at least 1");
+    SPH_REQUIRE(n == 0 || (d_xyz && d_owner && d_out), SPHMAP_EINVAL, "null particle array");
+    SPH_REQUIRE(d_entry_xyz && d_entry_h && d_entry_kind && d_values, SPHMAP_EINVAL, "null entry array");
+    sphmap::interpolate_particles(ctx->c, n, d_xyz, d_owner, n_entries, d_entry_xyz, d_entry_h, d_entry_kind,
+                                  d_values, ncomp, d_out, as_stream(stream));
   });
 }
 

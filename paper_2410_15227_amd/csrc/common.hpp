@@ -232,6 +232,7 @@ struct PseudoArgs {
   int64_t *o_first, *o_count;
   int32_t *o_branch;
   uint64_t *o_label = nullptr;            // node label of each entry's unit
+  int64_t *o_owner = nullptr;             // [n] entry that holds each particle
   int64_t n_open = 0;                     // labels of nodes to open (device)
   const uint64_t *open_labels = nullptr;
   int64_t n_out;
@@ -241,6 +242,11 @@ void pseudo_build(Ctx &ctx, PseudoArgs &a, hipStream_t s);
 // labels of under-resolved pseudo-particles (eq. resol_param), entry order
 int64_t select_underresolved(Ctx &ctx, int64_t n, const int32_t *kind, const uint64_t *label, const double *s_node,
                              const double *fneu, double s_root, double K, uint64_t *out, hipStream_t s);
+
+// per-particle values from the mixed set (Sec. 3.3)
+void interpolate_particles(Ctx &ctx, int64_t n, const double *xyz, const int64_t *owner, int64_t ne,
+                           const double *exyz, const double *eh, const int32_t *ekind, const double *val, int ncomp,
+                           double *out, hipStream_t s);
 
 inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

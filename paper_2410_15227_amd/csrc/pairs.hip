@@ -17,23 +17,10 @@
 // Morton order of their sites so that a wave's walks stay coherent.  A count
 // pass sizes the CSR, a fill pass writes it, and each cell's list is then
 // sorted by particle index.
-#include "common.hpp"
+#include "ballsearch.hpp"
 
 namespace sphmap {
 namespace {
-
-constexpr int kFan = 16;        // children per hierarchy node
-constexpr int kMaxLevels = 10;  // 16^10 > 2^31 particles
-
-struct Hier {
-  int levels;                 // number of box levels (level 1 = groups of particles)
-  int64_t n[kMaxLevels + 1];  // nodes per level (n[0] = particles)
-  float4 *lo[kMaxLevels + 1];
-  float4 *hi[kMaxLevels + 1];
-  const float4 *sx;           // sorted particles: fl(x), fl(y), fl(z), fl(h)
-  const int32_t *sidx;        // sorted -> original particle index
-  float margin_abs;           // absolute slack of the box test
-};
 
 __global__ void k_gather_sorted(int64_t n, const int32_t *sidx, const float4 *x32, float4 *sx) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -75,13 +62,6 @@ __global__ void k_up_boxes(int64_t nc, const float4 *clo, const float4 *chi, int
   }
   lo[b] = l;
   hi[b] = h;
-}
-
-__device__ inline bool box_hit(const float4 &lo, const float4 &hi, const float4 &g, float r2) {
-  float dx = fmaxf(fmaxf(lo.x - g.x, g.x - hi.x), 0.0f);
-  float dy = fmaxf(fmaxf(lo.y - g.y, g.y - hi.y), 0.0f);
-  float dz = fmaxf(fmaxf(lo.z - g.z, g.z - hi.z), 0.0f);
-  return dx * dx + dy * dy + dz * dz <= r2;
 }
 
 // The canonical binary32 test, evaluated without contraction.
@@ -206,6 +186,29 @@ __global__ void __launch_bounds__(256) k_sort_segments(int64_t C, const int64_t 
 
 }  // namespace
 
+void build_hier(Arena &ar, const float4 *sx, int64_t n, float slack, const std::string &tag, Hier &H, hipStream_t s) {
+  H.n[0] = n;
+  H.lo[0] = H.hi[0] = nullptr;
+  H.margin_abs = 2.0f * slack;
+  int l = 0;
+  int64_t cnt = n;
+  do {
+    ++l;
+    SPH_REQUIRE(l <= kMaxLevels, SPHMAP_EINVAL, "too many balls for the search hierarchy");
+    int64_t nb = div_up(cnt, kFan);
+    H.n[l] = nb;
+    H.lo[l] = ar.get<float4>(tag + "_lo" + std::to_string(l), nb);
+    H.hi[l] = ar.get<float4>(tag + "_hi" + std::to_string(l), nb);
+    if (l == 1)
+      k_leaf_boxes<<<(unsigned)div_up(nb, 256), 256, 0, s>>>(n, sx, nb, H.lo[1], H.hi[1], slack);
+    else
+      k_up_boxes<<<(unsigned)div_up(nb, 256), 256, 0, s>>>(cnt, H.lo[l - 1], H.hi[l - 1], nb, H.lo[l], H.hi[l]);
+    SPH_LAUNCH_CHECK();
+    cnt = nb;
+  } while (cnt > kFan);
+  H.levels = l;
+}
+
 void find_pairs(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, hipStream_t s) {
   Arena &ar = ctx.arena;
   const int64_t N = p.n, C = t.n_cells;
@@ -220,27 +223,8 @@ void find_pairs(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, hipSt
   Hier H;
   H.sx = sx;
   H.sidx = sidx;
-  H.n[0] = N;
-  H.lo[0] = H.hi[0] = nullptr;
   const float slack = (float)(1e-6 * t.box_size);
-  H.margin_abs = 2.0f * slack;
-  int l = 0;
-  int64_t cnt = N;
-  do {
-    ++l;
-    SPH_REQUIRE(l <= kMaxLevels, SPHMAP_EINVAL, "too many particles for the search hierarchy");
-    int64_t nb = div_up(cnt, kFan);
-    H.n[l] = nb;
-    H.lo[l] = ar.get<float4>("pp_lo" + std::to_string(l), nb);
-    H.hi[l] = ar.get<float4>("pp_hi" + std::to_string(l), nb);
-    if (l == 1)
-      k_leaf_boxes<<<(unsigned)div_up(nb, 256), 256, 0, s>>>(N, sx, nb, H.lo[1], H.hi[1], slack);
-    else
-      k_up_boxes<<<(unsigned)div_up(nb, 256), 256, 0, s>>>(cnt, H.lo[l - 1], H.hi[l - 1], nb, H.lo[l], H.hi[l]);
-    SPH_LAUNCH_CHECK();
-    cnt = nb;
-  } while (cnt > kFan);
-  H.levels = l;
+  build_hier(ar, sx, N, slack, "pp", H, s);
 
   P.n_cells = C;
   P.n_particles = N;

@@ -392,6 +392,24 @@ __global__ void k_entries(int64_t nu, const int32_t *units, NodeArrays N, const 
   }
 }
 
+// Entry that holds each particle: the sorted position's unit is the last unit
+// starting at or before it; an opened leaf's particles are its entries in
+// ascending index, so a particle's entry is offset by its rank among them.
+__global__ void k_owner(int64_t n, const int64_t *flag, const int64_t *uoff, const int32_t *units, NodeArrays N,
+                        const int8_t *acc, const int64_t *eoff, const int32_t *sidx, int64_t *owner) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const int64_t u = uoff[q] + flag[q] - 1;
+  const int32_t node = units[u];
+  const int32_t j = sidx[q];
+  int64_t e = eoff[u];
+  if (!acc[node]) {
+    const int32_t f = N.first[node], c = N.count[node];
+    for (int32_t t = f; t < f + c; ++t) e += sidx[t] < j;
+  }
+  owner[j] = e;
+}
+
 constexpr double kInvPi = 0.31830988618379067154;
 
 __device__ inline double m4w(double q) {
@@ -711,6 +729,10 @@ void pseudo_build(Ctx &ctx, PseudoArgs &a, hipStream_t s) {
                                                       s2, minidx, a.o_xyz, a.o_h, a.o_m, o_s, a.o_kind, a.o_first,
                                                       a.o_count, a.o_branch, upos, plist, label, a.o_label);
   SPH_LAUNCH_CHECK();
+  if (a.o_owner && n > 0) {
+    k_owner<<<(unsigned)div_up(n, 256), 256, 0, s>>>(n, flag, uoff, units, N, acc, eoff, sidx, a.o_owner);
+    SPH_LAUNCH_CHECK();
+  }
 
   // node smoothing lengths
   unsigned long long *bcount = ar.get<unsigned long long>("ps_bcount", 4);
