@@ -46,6 +46,13 @@ extern "C" {
 #define SPHMAP_EHIP (-4)   /* HIP runtime error                             */
 #define SPHMAP_ERANGE (-5) /* output capacity too small                     */
 
+/* Bits of the device status word (sphmap_sync_status). */
+#define SPHMAP_STATUS_NONFINITE_MASS 1  /* a cell mass M_c was not finite      */
+#define SPHMAP_STATUS_ZERO_COVERAGE 2   /* inverse map: a particle with c_i = 0
+                                           (no cell overlaps it) got q_i = 0  */
+#define SPHMAP_STATUS_NONFINITE_VALUE 4 /* inverse map or interpolation wrote a
+                                           value that was not finite          */
+
 #define SPHMAP_PREC_FP64 0  /* every step of the integral in binary64        */
 #define SPHMAP_PREC_MIXED 1 /* binary32 closed form, binary64 for degenerate
                                pieces and for every accumulation            */
@@ -65,6 +72,32 @@ int sphmap_destroy(sphmap_ctx *ctx);
 /* Message of the last failing call on ctx ("" if none); valid until the
    next call on ctx. */
 const char *sphmap_last_error(const sphmap_ctx *ctx);
+
+/* Device-side anomalies do not stop a call: the kernels that meet them set
+   bits (SPHMAP_STATUS_*) in a status word of the context.  This waits for
+   `stream`, stores the word in *status (host) and, if clear != 0, resets it
+   to 0.  The word collects every call on ctx since it was last cleared. */
+int sphmap_sync_status(sphmap_ctx *ctx, void *stream, int32_t clear, int32_t *status);
+
+/* Device memory a mapping needs, by owner (upper bounds, in bytes):
+     workspace     the context's scratch for one forward mapping of
+                   n_particles on the grid followed by an inverse mapping
+                   (pair search, Exact integral work queues, transpose);
+                   the context keeps it between calls
+     pairs         the retained pair list with its weights and particle-major
+                   copy (freed with sphmap_pairs_free)
+     tessellation  the uploaded grid (freed with sphmap_tess_free)
+   n_pairs: the candidate-pair count when known (an earlier step on the same
+   grid), else 0 for an estimate of 200 per particle.  Each named device
+   buffer is counted as at least one 2 MiB allocation granule.  Caller
+   buffers are not included.  Errors: EINVAL for negative sizes. */
+typedef struct {
+  size_t workspace;
+  size_t pairs;
+  size_t tessellation;
+} sphmap_footprint;
+int sphmap_estimate_footprint(sphmap_ctx *ctx, int64_t n_particles, int64_t n_pairs, int64_t n_cells,
+                              int64_t n_faces, int64_t n_face_vertices, int64_t n_vertices, sphmap_footprint *out);
 
 /* ------------------------------------------------------------------------
  * Tessellation upload (Sec. 2.3: the grid code receives the generation sites

@@ -23,6 +23,11 @@ __all__ = ["Context", "DeviceTessellation", "Pairs", "MapResult", "map_particles
            "map_cells_to_particles", "build_pseudo_particles", "SphmapError", "PREC_FP64", "PREC_MIXED"]
 
 
+STATUS_NONFINITE_MASS = 1   # a cell mass was not finite
+STATUS_ZERO_COVERAGE = 2    # inverse map: a particle no cell overlaps got 0
+STATUS_NONFINITE_VALUE = 4  # inverse map or interpolation wrote a non-finite value
+
+
 def _torch():
     import torch
     return torch
@@ -79,6 +84,25 @@ class Context:
         return DeviceTessellation(self, tess, stream)
 
     # timing / counters -------------------------------------------------
+    def sync_status(self, stream=None, clear: bool = True) -> int:
+        """Wait for `stream` and return the device status word (bits
+        STATUS_*), clearing it unless clear is False."""
+        v = ctypes.c_int32()
+        self.check(_native.lib().sphmap_sync_status(self.handle, _stream_handle(stream), 1 if clear else 0,
+                                                    ctypes.byref(v)))
+        return v.value
+
+    def estimate_footprint(self, n_particles: int, tess, n_pairs: int = 0) -> dict:
+        """Device bytes of one forward + inverse mapping of n_particles on
+        `tess` (host Tessellation or DeviceTessellation's source): the
+        context workspace, the retained pair list and the uploaded grid.
+        n_pairs: the candidate-pair count if known, else 0 (estimated)."""
+        f = _native.Footprint()
+        self.check(_native.lib().sphmap_estimate_footprint(
+            self.handle, int(n_particles), int(n_pairs), int(tess.n_cells), len(tess.face_vtx_off) - 1,
+            len(tess.face_vtx), len(tess.vertices), ctypes.byref(f)))
+        return dict(workspace=f.workspace, pairs=f.pairs, tessellation=f.tessellation)
+
     def set_timing(self, on: bool = True):
         self.check(_native.lib().sphmap_set_timing(self.handle, 1 if on else 0))
 

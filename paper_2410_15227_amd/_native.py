@@ -20,7 +20,7 @@ EXPORTS = [
     "sphmap_tess_upload", "sphmap_tess_free", "sphmap_tess_cell_info",
     "map_particles_to_cells", "map_particles_to_cells_batch", "sphmap_pairs_info", "sphmap_pairs_export", "sphmap_pairs_free",
     "map_cells_to_particles", "build_pseudo_particles", "build_pseudo_particles_open", "select_underresolved",
-    "interpolate_to_particles",
+    "interpolate_to_particles", "sphmap_sync_status", "sphmap_estimate_footprint",
     "sphmap_set_timing", "sphmap_kernel_time", "sphmap_reset_timing",
     "sphmap_set_counting", "sphmap_work_counters", "sphmap_set_autotune", "sphmap_tuned_shape",
 ]
@@ -35,6 +35,10 @@ class PseudoOpts(ctypes.Structure):
 class PseudoStats(ctypes.Structure):
     _fields_ = [("n_nodes", ctypes.c_int64), ("n_units", ctypes.c_int64), ("n_pseudo", ctypes.c_int64),
                 ("n_real", ctypes.c_int64), ("branch_count", ctypes.c_int64 * 4), ("s_root", ctypes.c_double)]
+
+
+class Footprint(ctypes.Structure):
+    _fields_ = [("workspace", ctypes.c_size_t), ("pairs", ctypes.c_size_t), ("tessellation", ctypes.c_size_t)]
 
 
 class SphmapError(RuntimeError):
@@ -93,6 +97,10 @@ def lib():
         L.select_underresolved.restype = ctypes.c_int
         L.select_underresolved.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.c_double, ctypes.c_double, vp,
                                            ctypes.POINTER(i64), vp]
+        L.sphmap_sync_status.restype = ctypes.c_int
+        L.sphmap_sync_status.argtypes = [vp, vp, i32, ctypes.POINTER(i32)]
+        L.sphmap_estimate_footprint.restype = ctypes.c_int
+        L.sphmap_estimate_footprint.argtypes = [vp, i64, i64, i64, i64, i64, i64, ctypes.POINTER(Footprint)]
         L.interpolate_to_particles.restype = ctypes.c_int
         L.interpolate_to_particles.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp, i32, vp, vp]
         L.build_pseudo_particles.restype = ctypes.c_int

@@ -412,6 +412,46 @@ int interpolate_to_particles(sphmap_ctx *ctx, int64_t n, const double *d_xyz, co
   });
 }
 
+int sphmap_sync_status(sphmap_ctx *ctx, void *stream, int32_t clear, int32_t *status) {
+  if (!ctx || !status) return SPHMAP_EINVAL;
+  return guarded(ctx, [&] {
+    int v = 0;
+    hipStream_t s = as_stream(stream);
+    SPH_HIP(hipMemcpyAsync(&v, ctx->c.d_status, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (clear) SPH_HIP(hipMemsetAsync(ctx->c.d_status, 0, sizeof(int), s));
+    SPH_HIP(hipStreamSynchronize(s));
+    *status = v;
+  });
+}
+
+int sphmap_estimate_footprint(sphmap_ctx *ctx, int64_t n_particles, int64_t n_pairs, int64_t n_cells,
+                              int64_t n_faces, int64_t n_face_vertices, int64_t n_vertices, sphmap_footprint *out) {
+  if (!ctx || !out) return SPHMAP_EINVAL;
+  return guarded(ctx, [&] {
+    SPH_REQUIRE(n_particles >= 0 && n_pairs >= 0 && n_cells >= 0 && n_faces >= 0 && n_face_vertices >= 0 &&
+                    n_vertices >= 0,
+                SPHMAP_EINVAL, "negative size");
+    const int64_t N = n_particles, C = n_cells, P = n_pairs > 0 ? n_pairs : 200 * n_particles;
+    // arena buffers grow to 9/8 of the request; the device allocator hands
+    // out whole 2 MiB granules, once per named buffer
+    auto grown = [](double b, int n_buffers) { return (size_t)(b * 1.125 + 2097152.0 * n_buffers); };
+    // per particle: staged float4, Morton key + index, sorted copy, radix
+    // temporaries, search boxes, transpose counts; per pair: transpose keys,
+    // permutation and radix temporaries; per cell: pair counts
+    const double ws = 16.0 * N + 12.0 * N + 16.0 * N + 12.0 * N + 3.0 * N + 8.0 * N + 16.0 * P + 8.0 * C +
+                      (double)sphmap::exact_workspace_bytes(ctx->c, P);
+    // retained list: cell offsets, pair indices, weights, particle-major
+    // copy, particle offsets and coverage
+    const double pr = 8.0 * C + (4.0 + 4.0 + 8.0 + 4.0 + 8.0) * P + 16.0 * N;
+    // grid: generators, offsets, orders and volumes per cell; planes, spheres
+    // and cell per face; oriented vertices and edge frames per face vertex
+    const double tb = 96.0 * C + 96.0 * n_faces + 96.0 * n_face_vertices + 24.0 * n_vertices;
+    out->workspace = grown(ws, 48);
+    out->pairs = grown(pr, 8);
+    out->tessellation = grown(tb, 24);
+  });
+}
+
 int sphmap_set_timing(sphmap_ctx *ctx, int32_t enabled) {
   if (!ctx) return SPHMAP_EINVAL;
   ctx->c.timing = enabled != 0;

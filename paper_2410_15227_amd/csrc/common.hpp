@@ -213,6 +213,8 @@ struct ExactJob {
   PairsDev *P;
 };
 void exact_integral_batch(Ctx &ctx, const std::vector<ExactJob> &jobs, int precision, hipStream_t s);
+// upper bound of the context scratch the Exact integral of n_pairs pairs takes
+size_t exact_workspace_bytes(Ctx &ctx, int64_t n_pairs);
 // transpose + coverage
 void particle_major(Ctx &ctx, PairsDev &P, hipStream_t s);
 // M_c and rho_c (scale: optional per-particle mass factor 1/c_i)

@@ -1011,6 +1011,15 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
 
 }  // namespace
 
+// Compute units and resident Exact workgroups per CU, queried once per
+// context (contexts may live on different threads).
+static void exact_occupancy(Ctx &ctx) {
+  if (ctx.n_cu != 0) return;
+  SPH_HIP(hipDeviceGetAttribute(&ctx.n_cu, hipDeviceAttributeMultiprocessorCount, ctx.device));
+  SPH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&ctx.exact_per_cu, k_exact_edges<false>, 64 * kFlatWaves, 0));
+  ctx.exact_per_cu = std::max(ctx.exact_per_cu, 1);
+}
+
 void exact_integral_batch(Ctx &ctx, const std::vector<ExactJob> &jobs, int precision, hipStream_t s) {
   int64_t total = 0;
   for (const auto &j : jobs) {
@@ -1054,11 +1063,7 @@ void exact_integral_batch(Ctx &ctx, const std::vector<ExactJob> &jobs, int preci
   SPH_HIP(hipMemcpyAsync(d_inst, host, n_inst * sizeof(ExactInst), hipMemcpyHostToDevice, s));
   SPH_HIP(hipMemcpyAsync(d_c0, c0, (n_inst + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
   // persistent kernel: as many workgroups as stay resident at once
-  if (ctx.n_cu == 0) {  // per context: contexts may live on different threads
-    SPH_HIP(hipDeviceGetAttribute(&ctx.n_cu, hipDeviceAttributeMultiprocessorCount, ctx.device));
-    SPH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&ctx.exact_per_cu, k_exact_edges<false>, 64 * kFlatWaves, 0));
-    ctx.exact_per_cu = std::max(ctx.exact_per_cu, 1);
-  }
+  exact_occupancy(ctx);
   const int n_cu = ctx.n_cu, per_cu = ctx.exact_per_cu;
   const int64_t n_chunks = c0[n_inst];
   int32_t *next = ctx.arena.get<int32_t>("flat_next", 2);  // work counter, redo count
@@ -1111,6 +1116,13 @@ void exact_integral_batch(Ctx &ctx, const std::vector<ExactJob> &jobs, int preci
   k_exact_mixed_list<<<(unsigned)(n_cu * 4), 256, 0, s>>>(redo, next + 1, d_inst, d_c0, n_inst, ctr);
   SPH_LAUNCH_CHECK();
   kr.done();
+}
+
+size_t exact_workspace_bytes(Ctx &ctx, int64_t n_pairs) {
+  exact_occupancy(ctx);
+  const int64_t grid = std::min<int64_t>((int64_t)ctx.n_cu * ctx.exact_per_cu, div_up(div_up(n_pairs, 64), kFlatWaves));
+  const int64_t waves = std::max<int64_t>(grid, 1) * kFlatWaves;
+  return (size_t)(waves * (kEntryCap * sizeof(FaceRec) + 64 * kEdgeCap * sizeof(int2)) + n_pairs * sizeof(int64_t));
 }
 
 void exact_integral(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, int precision, hipStream_t s) {

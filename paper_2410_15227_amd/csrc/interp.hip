@@ -71,7 +71,8 @@ __global__ void k_owner_keys(int64_t n, const int64_t *owner, uint32_t *key, int
 // One thread per particle, components [c0, c0 + kCompPass) of ncomp.
 __global__ void __launch_bounds__(256) k_interp(Hier H, const double4 *sd, int64_t n, const int32_t *qidx,
                                                 const double *xyz, const int64_t *owner, const int32_t *ekind,
-                                                const double *val, int ncomp, int c0, double *out) {
+                                                const double *val, int ncomp, int c0, double *out,
+                                                int *status) {
 #pragma clang fp contract(off)
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
@@ -81,7 +82,12 @@ __global__ void __launch_bounds__(256) k_interp(Hier H, const double4 *sd, int64
   double *oi = out + (int64_t)ncomp * i + c0;
   const double *vo = val + (int64_t)ncomp * o + c0;
   if (ekind[o] == 0) {
-    for (int k = 0; k < nc; ++k) oi[k] = vo[k];
+    int bad = 0;
+    for (int k = 0; k < nc; ++k) {
+      oi[k] = vo[k];
+      if (!isfinite(vo[k])) bad = SPHMAP_STATUS_NONFINITE_VALUE;
+    }
+    if (bad) atomicOr(status, bad);
     return;
   }
   const double px = xyz[3 * i], py = xyz[3 * i + 1], pz = xyz[3 * i + 2];
@@ -130,7 +136,13 @@ __global__ void __launch_bounds__(256) k_interp(Hier H, const double4 *sd, int64
         }
     }
   }
-  for (int c = 0; c < nc; ++c) oi[c] = den > 0.0 ? num[c] / den : vo[c];
+  int bad = 0;
+  for (int c = 0; c < nc; ++c) {
+    const double v = den > 0.0 ? num[c] / den : vo[c];
+    oi[c] = v;
+    if (!isfinite(v)) bad = SPHMAP_STATUS_NONFINITE_VALUE;
+  }
+  if (bad) atomicOr(status, bad);
 }
 
 }  // namespace
@@ -178,7 +190,8 @@ void interpolate_particles(Ctx &ctx, int64_t n, const double *xyz, const int64_t
 
   KernelTimer kt(&ctx, "interp", s);
   for (int c0 = 0; c0 < ncomp; c0 += kCompPass) {
-    k_interp<<<(unsigned)div_up(n, 256), 256, 0, s>>>(H, sd, n, qidx, xyz, owner, ekind, val, ncomp, c0, out);
+    k_interp<<<(unsigned)div_up(n, 256), 256, 0, s>>>(H, sd, n, qidx, xyz, owner, ekind, val, ncomp, c0, out,
+                                                       ctx.d_status);
     SPH_LAUNCH_CHECK();
   }
   kt.done();

@@ -21,7 +21,7 @@ __device__ inline double wave_sum(double v) {
 
 __global__ void __launch_bounds__(256) k_cell_mass(int64_t C, const int64_t *off, const int32_t *pair_p,
                                                   const double *w, const double *m, const double *cov,
-                                                  const double *vol, double *mass, double *rho) {
+                                                  const double *vol, double *mass, double *rho, int *status) {
   const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (c >= C) return;
@@ -37,6 +37,7 @@ __global__ void __launch_bounds__(256) k_cell_mass(int64_t C, const int64_t *off
   if (lane == 0) {
     mass[c] = acc;
     if (rho) rho[c] = acc / vol[c];
+    if (!isfinite(acc)) atomicOr(status, SPHMAP_STATUS_NONFINITE_MASS);
   }
 }
 
@@ -73,7 +74,7 @@ __global__ void __launch_bounds__(256) k_coverage(int64_t N, const int64_t *poff
 template <int kComp>
 __global__ void __launch_bounds__(256) k_reverse(int64_t N, int ncomp, const int64_t *poff, const int32_t *pm_cell,
                                                 const double *pm_w, const double *cov, const double *q,
-                                                double *out) {
+                                                double *out, int *status) {
   const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
   const int lane = threadIdx.x & 15;  // 16 lanes per particle
   if (i >= N) return;
@@ -97,17 +98,27 @@ __global__ void __launch_bounds__(256) k_reverse(int64_t N, int ncomp, const int
     }
     if (lane == 0) {
       const double ci = cov[i];
-      for (int r = 0; r < kComp; ++r) out[i * kComp + r] = ci > 0.0 ? acc[r] / ci : 0.0;
+      int bad = ci > 0.0 ? 0 : SPHMAP_STATUS_ZERO_COVERAGE;
+      for (int r = 0; r < kComp; ++r) {
+        const double v = ci > 0.0 ? acc[r] / ci : 0.0;
+        out[i * kComp + r] = v;
+        if (!isfinite(v)) bad |= SPHMAP_STATUS_NONFINITE_VALUE;
+      }
+      if (bad) atomicOr(status, bad);
     }
   } else {
     const double ci = cov[i];
+    int bad = ci > 0.0 ? 0 : SPHMAP_STATUS_ZERO_COVERAGE;
     for (int r = 0; r < nc; ++r) {
       double v = 0.0;
       for (int64_t j = s + lane; j < e; j += 16) v += pm_w[j] * q[(int64_t)pm_cell[j] * nc + r];
 #pragma unroll
       for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
-      if (lane == 0) out[i * nc + r] = ci > 0.0 ? v / ci : 0.0;
+      v = ci > 0.0 ? v / ci : 0.0;
+      if (lane == 0) out[i * nc + r] = v;
+      if (!isfinite(v)) bad |= SPHMAP_STATUS_NONFINITE_VALUE;
     }
+    if (lane == 0 && bad) atomicOr(status, bad);
   }
 }
 
@@ -119,7 +130,8 @@ void cell_reduce(Ctx &ctx, const TessDev &t, const PartDev &p, const PairsDev &P
   if (C == 0) return;
   KernelTimer kt(&ctx, "cell_reduce", s);
   k_cell_mass<<<(unsigned)div_up(C * 64, 256), 256, 0, s>>>(C, P.cell_off, P.pair_p, P.w, p.m,
-                                                            normalize ? P.coverage : nullptr, t.volume, mass, rho);
+                                                            normalize ? P.coverage : nullptr, t.volume, mass, rho,
+                                                            ctx.d_status);
   SPH_LAUNCH_CHECK();
   kt.done();
 }
@@ -163,13 +175,14 @@ void reverse_map(Ctx &ctx, const PairsDev &P, const double *q, int ncomp, double
   KernelTimer kt(&ctx, "reverse", s);
   const unsigned grid = (unsigned)div_up(N * 16, 256);
   if (ncomp == 1)
-    k_reverse<1><<<grid, 256, 0, s>>>(N, 1, P.part_off, P.pm_cell, P.pm_w, P.coverage, q, out);
+    k_reverse<1><<<grid, 256, 0, s>>>(N, 1, P.part_off, P.pm_cell, P.pm_w, P.coverage, q, out, ctx.d_status);
   else if (ncomp == 2)
-    k_reverse<2><<<grid, 256, 0, s>>>(N, 2, P.part_off, P.pm_cell, P.pm_w, P.coverage, q, out);
+    k_reverse<2><<<grid, 256, 0, s>>>(N, 2, P.part_off, P.pm_cell, P.pm_w, P.coverage, q, out, ctx.d_status);
   else if (ncomp == 4)
-    k_reverse<4><<<grid, 256, 0, s>>>(N, 4, P.part_off, P.pm_cell, P.pm_w, P.coverage, q, out);
+    k_reverse<4><<<grid, 256, 0, s>>>(N, 4, P.part_off, P.pm_cell, P.pm_w, P.coverage, q, out, ctx.d_status);
   else
-    k_reverse<0><<<grid, 256, 0, s>>>(N, ncomp, P.part_off, P.pm_cell, P.pm_w, P.coverage, q, out);
+    k_reverse<0><<<grid, 256, 0, s>>>(N, ncomp, P.part_off, P.pm_cell, P.pm_w, P.coverage, q, out,
+                                      ctx.d_status);
   SPH_LAUNCH_CHECK();
   kt.done();
 }

@@ -22,29 +22,6 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-# Device bytes per unit of a forward + inverse mapping with a retained pair
-# list (pair indices, weights, particle-major copy and sort temporaries per
-# pair; staged coordinates, coverage and offsets per particle; offsets and
-# outputs per cell), and per tessellation (face planes, spheres, oriented
-# vertices and per-edge frames per face-vertex slot).
-BYTES_PER_PAIR = 48
-BYTES_PER_PARTICLE = 96
-BYTES_PER_CELL = 64
-BYTES_PER_FACE = 96
-BYTES_PER_FACE_VERTEX = 96
-PAIRS_PER_PARTICLE = 200  # candidate pairs per particle assumed before the count is known
-
-
-def tess_bytes(tess) -> int:
-    return int(BYTES_PER_CELL * tess.n_cells + BYTES_PER_FACE * tess.n_faces
-               + BYTES_PER_FACE_VERTEX * len(tess.face_vtx))
-
-
-def job_bytes(n_particles: int, n_cells: int) -> int:
-    return int(BYTES_PER_PARTICLE * n_particles + BYTES_PER_CELL * n_cells
-               + BYTES_PER_PAIR * PAIRS_PER_PARTICLE * n_particles)
-
-
 @dataclass
 class Job:
     key: str                 # identity of the tessellation
@@ -77,11 +54,13 @@ class MappingServer:
         self.k = inverse_components
         self.budget = int(hbm_budget)
         self._slots = [(pkg.Context(device), torch.cuda.Stream(device=device)) for _ in range(slots)]
+        self._est_ctx = pkg.Context(device)  # footprint queries, under the lock only
         self._cv = threading.Condition()
         self._queue: collections.deque[Job] = collections.deque()
         self._running_bytes = 0
         self._resident: collections.OrderedDict[str, tuple] = collections.OrderedDict()  # key -> (dt, bytes, users)
         self._resident_bytes = 0
+        self._pairs_seen: dict[str, int] = {}
         self._stop = False
         self.completed: list[Job] = []
         self._threads = [threading.Thread(target=self._worker, args=(i,), daemon=True) for i in range(slots)]
@@ -95,6 +74,13 @@ class MappingServer:
             self._queue.append(job)
             self._cv.notify_all()
         return job
+
+    def footprint_bytes(self, job: Job, resident: bool = False) -> int:
+        """Device bytes admission reserves for `job` (its grid counted
+        unless resident)."""
+        with self._cv:
+            fp = self._footprint(job)
+        return fp["workspace"] + fp["pairs"] + (0 if resident else fp["tessellation"])
 
     def resident_keys(self) -> list[str]:
         with self._cv:
@@ -119,12 +105,18 @@ class MappingServer:
             self._resident.clear()
         for ctx, _ in self._slots:
             ctx.close()
+        self._est_ctx.close()
 
     # ----------------------------------------------------------- scheduling
+    def _footprint(self, job: Job) -> dict:
+        # the library's model; a grid seen before lends its last pair count
+        return self._est_ctx.estimate_footprint(len(job.m), job.tess, self._pairs_seen.get(job.key, 0))
+
     def _need(self, job: Job) -> int:
-        need = job_bytes(len(job.m), job.tess.n_cells)
+        fp = self._footprint(job)
+        need = fp["workspace"] + fp["pairs"]
         if job.key not in self._resident:
-            need += tess_bytes(job.tess)
+            need += fp["tessellation"]
         return need
 
     def _evict_for(self, need: int) -> bool:
@@ -158,10 +150,11 @@ class MappingServer:
                             break
                     self._cv.wait()
                 job.resident_hit = job.key in self._resident
+                fp = self._footprint(job)
                 if job.resident_hit:
                     dt, b, users = self._resident.pop(job.key)
                     self._resident[job.key] = (dt, b, users + 1)  # most recently used
-                    run_bytes = job_bytes(len(job.m), job.tess.n_cells)
+                    run_bytes = fp["workspace"] + fp["pairs"]
                 else:
                     dt = None
                     run_bytes = need
@@ -179,7 +172,7 @@ class MappingServer:
                                 stream.synchronize()
                                 mine.free()
                             else:
-                                tb = tess_bytes(job.tess)
+                                tb = fp["tessellation"]
                                 self._resident[job.key] = (dt, tb, 1)
                                 self._resident_bytes += tb
                                 self._running_bytes -= tb
@@ -202,6 +195,8 @@ class MappingServer:
             job.end = time.perf_counter()
             with self._cv:
                 self._running_bytes -= run_bytes
+                if job.n_pairs:
+                    self._pairs_seen[job.key] = job.n_pairs
                 dt_entry = self._resident.get(job.key)
                 if dt_entry is not None:
                     d, b, users = dt_entry

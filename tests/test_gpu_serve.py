@@ -61,7 +61,11 @@ def test_budget_of_one_job(pool, workloads):
         pytest.skip("no GPU")
     say("case: budget below two jobs")
     g = pool[1]
-    one = serve.job_bytes(len(g["m"]), g["tess"].n_cells) + serve.tess_bytes(g["tess"])
+    import paper_2410_15227_amd as pkg
+    c = pkg.Context(0)
+    fp = c.estimate_footprint(len(g["m"]), g["tess"])
+    c.close()
+    one = fp["workspace"] + fp["pairs"] + fp["tessellation"]
     srv = serve.MappingServer(0, slots=3, hbm_budget=one)
     mix = [srv.submit(serve.Job(g["key"], g["tess"], workloads.jitter(g["pos"], g["m"], g["rho"], seed=50 + i),
                                 g["h"], g["m"])) for i in range(6)]

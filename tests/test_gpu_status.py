@@ -1,0 +1,115 @@
+"""The device status word and the footprint model of the boundary.
+
+Status: non-finite cell masses, particles no cell overlaps (q_i = 0 in the
+inverse map) and non-finite mapped or interpolated values set their bits;
+clean calls leave the word at 0; reading it clears it.
+Footprint: the device memory a fresh context, a retained pair list and an
+uploaded grid actually take stays below the estimate."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def grid(workloads):
+    pos, m, h, rho = workloads.make_cloud("uniform", 4096, seed=1)
+    return pos, m, h, workloads.voronoi(pos)
+
+
+def test_status_bits(grid):
+    import paper_2410_15227_amd as pkg
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    say("case: status word, uniform 4096")
+    pos, m, h, tess = grid
+    ctx = pkg.Context(0)
+    dt = ctx.upload(tess)
+    res = pkg.map_particles_to_cells(ctx, dt, pos, h, m, keep_pairs=True)
+    pkg.map_cells_to_particles(ctx, res.pairs, torch.ones(tess.n_cells, dtype=torch.float64, device="cuda"))
+    assert ctx.sync_status() == 0
+    # a NaN mass reaches every cell the particle overlaps
+    m2 = m.copy()
+    m2[7] = np.nan
+    pkg.map_particles_to_cells(ctx, dt, pos, h, m2)
+    assert ctx.sync_status(clear=False) == pkg.STATUS_NONFINITE_MASS
+    assert ctx.sync_status() == pkg.STATUS_NONFINITE_MASS  # read again, then cleared
+    assert ctx.sync_status() == 0
+    # a non-finite cell value in the inverse map
+    q = torch.ones(tess.n_cells, dtype=torch.float64, device="cuda")
+    q[3] = float("inf")
+    pkg.map_cells_to_particles(ctx, res.pairs, q)
+    assert ctx.sync_status() == pkg.STATUS_NONFINITE_VALUE
+    # a particle outside the grid's box overlaps no cell
+    pos3 = pos.copy()
+    pos3[11] = [5.0, 5.0, 5.0]
+    r3 = pkg.map_particles_to_cells(ctx, dt, pos3, h, m, keep_pairs=True)
+    v = pkg.map_cells_to_particles(ctx, r3.pairs, torch.ones(tess.n_cells, dtype=torch.float64, device="cuda"))
+    assert ctx.sync_status() == pkg.STATUS_ZERO_COVERAGE
+    assert float(v[11]) == 0.0
+    r3.pairs.free()
+    res.pairs.free()
+    dt.free()
+    ctx.close()
+
+
+def test_status_interpolation(workloads, oracle):
+    import paper_2410_15227_amd as pkg
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    say("case: status word, interpolation")
+    pos, m, h, rho = workloads.make_cloud("uniform", 3000, seed=2)
+    ref = oracle.pseudo_build(pos, m, h, [[0.5, 0.5, 0.5]], r_part=0.1, theta=0.6)
+    ms = dict(xyz=torch.tensor(ref["pos"], device="cuda"), h=torch.tensor(ref["h"], device="cuda"),
+              kind=torch.tensor(ref["kind"], device="cuda"), owner=torch.tensor(ref["owner"], device="cuda"))
+    ctx = pkg.Context(0)
+    v = np.random.default_rng(1).random(len(ref["kind"]))
+    pkg.interpolate_to_particles(ctx, pos, ms, v)
+    assert ctx.sync_status() == 0
+    v[np.flatnonzero(ref["kind"] == 1)[0]] = np.nan
+    pkg.interpolate_to_particles(ctx, pos, ms, v)
+    assert ctx.sync_status() == pkg.STATUS_NONFINITE_VALUE
+    ctx.close()
+
+
+def test_footprint_bounds_use(grid):
+    import paper_2410_15227_amd as pkg
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    say("case: footprint estimate vs device memory, uniform 4096")
+    pos, m, h, tess = grid
+    xyz = torch.tensor(pos, device="cuda")
+    hd = torch.tensor(h, device="cuda")
+    md = torch.tensor(m, device="cuda")
+    q = torch.ones(tess.n_cells, dtype=torch.float64, device="cuda")
+    out = torch.empty(len(m), dtype=torch.float64, device="cuda")
+    mass = torch.empty(tess.n_cells, dtype=torch.float64, device="cuda")
+    dens = torch.empty(tess.n_cells, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    ctx = pkg.Context(0)
+    est = ctx.estimate_footprint(len(m), tess)
+    free0 = torch.cuda.mem_get_info()[0]
+    dt = ctx.upload(tess)
+    res = pkg.map_particles_to_cells(ctx, dt, xyz, hd, md, keep_pairs=True, out_mass=mass, out_density=dens)
+    pkg.map_cells_to_particles(ctx, res.pairs, q, out=out)
+    torch.cuda.synchronize()
+    used = free0 - torch.cuda.mem_get_info()[0]
+    total = est["workspace"] + est["pairs"] + est["tessellation"]
+    exact = ctx.estimate_footprint(len(m), tess, n_pairs=res.pairs.n_pairs)
+    say(f"  used {used / 2**20:.1f} MiB, estimate {total / 2**20:.1f} MiB, with the pair count "
+        f"{sum(exact.values()) / 2**20:.1f} MiB ({res.pairs.n_pairs} pairs)")
+    # the library's code object is loaded on the first launch: allow 16 MiB
+    assert used <= sum(exact.values()) + (16 << 20)
+    assert used <= total + (16 << 20)
+    assert total <= 2 * used
+    res.pairs.free()
+    dt.free()
+    ctx.close()
