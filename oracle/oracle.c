@@ -898,3 +898,279 @@ void ora_interpolate(int64_t n, const double *x, const int64_t *owner, int64_t n
     for (int k = 0; k < ncomp; ++k) oi[k] = den > 0.0 ? num[k] / den : val[(int64_t)ncomp * o + k];
   }
 }
+
+/* ------------------------------------------------------------------ Voronoi
+   The grid the mapping runs on (Sec. 2.3): the Voronoi cell of generator c
+   inside the box [lo, hi] is the set of box points at least as close to g_c
+   as to any other generator.  Built the textbook way: start from the box as
+   six square faces and cut it by the bisector half-space of every other
+   generator in turn (n.x <= d with n = g_j - g_c, d = (|g_j|^2 - |g_c|^2) / 2),
+   clipping each face polygon against the plane and closing the cut with a
+   cap face whose points are ordered by angle about their mean.  Face ids:
+   the neighbouring generator, or -1..-6 for the box planes x-, x+, y-, y+,
+   z-, z+.  Volume and centroid by the fan of tetrahedra (g_c, v0, v_i,
+   v_i+1) over each face. */
+
+typedef struct {
+  int nv, cap;
+  double *v; /* [cap][3] */
+  int64_t id;
+} opoly_t;
+
+typedef struct {
+  int nf, cap;
+  opoly_t *f;
+} ocell_t;
+
+static void opoly_push(opoly_t *p, const double *x) {
+  if (p->nv == p->cap) {
+    p->cap = p->cap ? 2 * p->cap : 8;
+    p->v = (double *)realloc(p->v, sizeof(double) * 3 * p->cap);
+  }
+  memcpy(p->v + 3 * p->nv, x, sizeof(double) * 3);
+  p->nv++;
+}
+
+static opoly_t *ocell_add(ocell_t *C, int64_t id) {
+  if (C->nf == C->cap) {
+    C->cap = C->cap ? 2 * C->cap : 16;
+    C->f = (opoly_t *)realloc(C->f, sizeof(opoly_t) * C->cap);
+  }
+  opoly_t *p = &C->f[C->nf++];
+  p->nv = p->cap = 0;
+  p->v = NULL;
+  p->id = id;
+  return p;
+}
+
+static void ocell_free(ocell_t *C) {
+  for (int k = 0; k < C->nf; ++k) free(C->f[k].v);
+  free(C->f);
+  C->f = NULL;
+  C->nf = C->cap = 0;
+}
+
+static void ocell_box(ocell_t *C, const double *lo, const double *hi) {
+  /* corner (i, j, k) with bits x = 1, y = 2, z = 4 */
+  static const int quad[6][4] = {{0, 4, 6, 2}, {1, 3, 7, 5}, {0, 1, 5, 4}, {2, 6, 7, 3}, {0, 2, 3, 1}, {4, 5, 7, 6}};
+  C->nf = C->cap = 0;
+  C->f = NULL;
+  for (int s = 0; s < 6; ++s) {
+    opoly_t *p = ocell_add(C, -1 - s);
+    for (int q = 0; q < 4; ++q) {
+      const int b = quad[s][q];
+      double x[3] = {(b & 1) ? hi[0] : lo[0], (b & 2) ? hi[1] : lo[1], (b & 4) ? hi[2] : lo[2]};
+      opoly_push(p, x);
+    }
+  }
+}
+
+/* keep n.x <= d (n unit); returns 1 when a vertex lay beyond eps */
+static int ocell_clip(ocell_t *C, const double *n, double d, int64_t id, double eps) {
+  opoly_t cap = {0, 0, NULL, id};
+  int cut = 0;
+  for (int k = 0; k < C->nf; ++k)
+    for (int i = 0; i < C->f[k].nv; ++i)
+      if (v_dot(n, C->f[k].v + 3 * i) - d > eps) cut = 1;
+  if (!cut) return 0;
+  int w = 0;
+  for (int k = 0; k < C->nf; ++k) {
+    opoly_t *f = &C->f[k];
+    opoly_t out = {0, 0, NULL, f->id};
+    for (int i = 0; i < f->nv; ++i) {
+      const double *a = f->v + 3 * i, *b = f->v + 3 * ((i + 1) % f->nv);
+      const double sa = v_dot(n, a) - d, sb = v_dot(n, b) - d;
+      if (sa <= eps) {
+        opoly_push(&out, a);
+        if (sa >= -eps) opoly_push(&cap, a);
+      }
+      if ((sa < -eps && sb > eps) || (sa > eps && sb < -eps)) {
+        const double t = sa / (sa - sb);
+        double x[3] = {a[0] + t * (b[0] - a[0]), a[1] + t * (b[1] - a[1]), a[2] + t * (b[2] - a[2])};
+        opoly_push(&out, x);
+        opoly_push(&cap, x);
+      }
+    }
+    free(f->v);
+    if (out.nv >= 3)
+      C->f[w++] = out;
+    else
+      free(out.v);
+  }
+  C->nf = w;
+  /* cap: distinct points ordered by angle about their mean */
+  opoly_t uq = {0, 0, NULL, id};
+  for (int i = 0; i < cap.nv; ++i) {
+    int dup = 0;
+    for (int j = 0; j < uq.nv && !dup; ++j) {
+      double e[3];
+      v_sub(cap.v + 3 * i, uq.v + 3 * j, e);
+      dup = v_dot(e, e) <= 100.0 * eps * eps;
+    }
+    if (!dup) opoly_push(&uq, cap.v + 3 * i);
+  }
+  free(cap.v);
+  if (uq.nv >= 3) {
+    double m[3] = {0, 0, 0}, u[3], t[3], ww[3];
+    for (int i = 0; i < uq.nv; ++i)
+      for (int q = 0; q < 3; ++q) m[q] += uq.v[3 * i + q] / uq.nv;
+    t[0] = fabs(n[0]) < 0.9 ? 1.0 : 0.0;
+    t[1] = fabs(n[0]) < 0.9 ? 0.0 : 1.0;
+    t[2] = 0.0;
+    v_cross(n, t, u);
+    const double lu = sqrt(v_dot(u, u));
+    for (int q = 0; q < 3; ++q) u[q] /= lu;
+    v_cross(n, u, ww);
+    double *ang = (double *)malloc(sizeof(double) * uq.nv);
+    for (int i = 0; i < uq.nv; ++i) {
+      double e[3];
+      v_sub(uq.v + 3 * i, m, e);
+      ang[i] = atan2(v_dot(e, ww), v_dot(e, u));
+    }
+    for (int i = 1; i < uq.nv; ++i) /* insertion sort by angle */
+      for (int j = i; j > 0 && ang[j] < ang[j - 1]; --j) {
+        double ta = ang[j];
+        ang[j] = ang[j - 1];
+        ang[j - 1] = ta;
+        double tv[3];
+        memcpy(tv, uq.v + 3 * j, sizeof tv);
+        memcpy(uq.v + 3 * j, uq.v + 3 * (j - 1), sizeof tv);
+        memcpy(uq.v + 3 * (j - 1), tv, sizeof tv);
+      }
+    free(ang);
+    opoly_t *p = ocell_add(C, id);
+    *p = uq;
+  } else {
+    free(uq.v);
+  }
+  return 1;
+}
+
+static void ocell_build(int64_t n, const double *g, int64_t c, const double *lo, const double *hi, ocell_t *C) {
+  ocell_box(C, lo, hi);
+  const double L = fmax(hi[0] - lo[0], fmax(hi[1] - lo[1], hi[2] - lo[2]));
+  const double eps = 1e-13 * L;
+  const double *gc = g + 3 * c;
+  double rmax = -1.0; /* largest vertex distance from g_c, refreshed after a cut */
+  for (int64_t j = 0; j < n; ++j) {
+    if (j == c) continue;
+    if (rmax < 0.0) {
+      double r2 = 0.0;
+      for (int k = 0; k < C->nf; ++k)
+        for (int i = 0; i < C->f[k].nv; ++i) {
+          double e[3];
+          v_sub(C->f[k].v + 3 * i, gc, e);
+          r2 = fmax(r2, v_dot(e, e));
+        }
+      rmax = sqrt(r2);
+    }
+    double nv[3];
+    v_sub(g + 3 * j, gc, nv);
+    const double dist = sqrt(v_dot(nv, nv));
+    /* the bisector is dist/2 from g_c: it cannot cut when every vertex is closer */
+    if (0.5 * dist > rmax + eps) continue;
+    for (int q = 0; q < 3; ++q) nv[q] /= dist;
+    double mid[3] = {0.5 * (g[3 * j] + gc[0]), 0.5 * (g[3 * j + 1] + gc[1]), 0.5 * (g[3 * j + 2] + gc[2])};
+    if (ocell_clip(C, nv, v_dot(nv, mid), j, eps)) rmax = -1.0;
+  }
+}
+
+static void ocell_moments(const ocell_t *C, const double *gc, double *vol, double *cen) {
+  double V = 0.0, S[3] = {0, 0, 0};
+  for (int k = 0; k < C->nf; ++k) {
+    const opoly_t *f = &C->f[k];
+    for (int i = 1; i + 1 < f->nv; ++i) {
+      double a[3], b[3], c[3], x[3];
+      v_sub(f->v, gc, a);
+      v_sub(f->v + 3 * i, gc, b);
+      v_sub(f->v + 3 * (i + 1), gc, c);
+      v_cross(b, c, x);
+      const double t = fabs(v_dot(a, x)) / 6.0;
+      V += t;
+      for (int q = 0; q < 3; ++q) S[q] += t * (a[q] + b[q] + c[q]) / 4.0;
+    }
+  }
+  *vol = V;
+  for (int q = 0; q < 3; ++q) cen[q] = gc[q] + (V > 0.0 ? S[q] / V : 0.0);
+}
+
+/* Cells of all generators.  Per cell: volume, centroid [3]; faces as a CSR
+   (cell_face_off [n+1]) with the face id, its area and its polygon
+   (face_vtx_off [F+1] into face_pts [][3]).  Pass NULL for the face arrays
+   to get only the counts: *n_faces_out, *n_fv_out.  Returns 0. */
+int ora_voronoi(int64_t n, const double *g, const double *lo, const double *hi, double *volume, double *centroid,
+                int64_t *cell_face_off, int64_t *face_id, double *face_area, int64_t *face_vtx_off,
+                double *face_pts, int64_t *n_faces_out, int64_t *n_fv_out) {
+  int64_t *nf = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+  int64_t *nfv = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int64_t c = 0; c < n; ++c) {
+    ocell_t C;
+    ocell_build(n, g, c, lo, hi, &C);
+    ocell_moments(&C, g + 3 * c, &volume[c], centroid + 3 * c);
+    nf[c] = C.nf;
+    for (int k = 0; k < C.nf; ++k) nfv[c] += C.f[k].nv;
+    ocell_free(&C);
+  }
+  int64_t F = 0, FV = 0;
+  for (int64_t c = 0; c < n; ++c) {
+    int64_t a = nf[c], b = nfv[c];
+    nf[c] = F;
+    nfv[c] = FV;
+    F += a;
+    FV += b;
+  }
+  *n_faces_out = F;
+  *n_fv_out = FV;
+  if (cell_face_off) {
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t c = 0; c < n; ++c) {
+      ocell_t C;
+      ocell_build(n, g, c, lo, hi, &C);
+      int64_t f0 = nf[c], p0 = nfv[c];
+      cell_face_off[c] = f0;
+      for (int k = 0; k < C.nf; ++k) {
+        const opoly_t *f = &C.f[k];
+        face_id[f0 + k] = f->id;
+        face_vtx_off[f0 + k] = p0;
+        double A[3] = {0, 0, 0};
+        for (int i = 1; i + 1 < f->nv; ++i) {
+          double a[3], b[3], x[3];
+          v_sub(f->v + 3 * i, f->v, a);
+          v_sub(f->v + 3 * (i + 1), f->v, b);
+          v_cross(a, b, x);
+          for (int q = 0; q < 3; ++q) A[q] += x[q];
+        }
+        face_area[f0 + k] = 0.5 * sqrt(v_dot(A, A));
+        memcpy(face_pts + 3 * p0, f->v, sizeof(double) * 3 * f->nv);
+        p0 += f->nv;
+      }
+      ocell_free(&C);
+    }
+    cell_face_off[n] = F;
+    face_vtx_off[F] = FV;
+  }
+  free(nf);
+  free(nfv);
+  return 0;
+}
+
+/* Lloyd's iteration (Sec. 2.3): every generator moves to the centroid of its
+   cell, iters times.  out [n][3] receives the final generators. */
+void ora_lloyd(int64_t n, const double *g, const double *lo, const double *hi, int32_t iters, double *out) {
+  double *cur = (double *)malloc(sizeof(double) * 3 * (n > 0 ? n : 1));
+  memcpy(cur, g, sizeof(double) * 3 * n);
+  for (int it = 0; it < iters; ++it) {
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t c = 0; c < n; ++c) {
+      ocell_t C;
+      double v;
+      ocell_build(n, cur, c, lo, hi, &C);
+      ocell_moments(&C, cur + 3 * c, &v, out + 3 * c);
+      ocell_free(&C);
+    }
+    memcpy(cur, out, sizeof(double) * 3 * n);
+  }
+  if (iters <= 0) memcpy(out, g, sizeof(double) * 3 * n);
+  free(cur);
+}

@@ -66,6 +66,10 @@ def _lib():
         L.ora_fneu_limit.argtypes = [dbl, dbl]
         L.ora_underresolved.restype = i64
         L.ora_underresolved.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, vp]
+        L.ora_voronoi.restype = ctypes.c_int
+        L.ora_voronoi.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.ora_lloyd.restype = None
+        L.ora_lloyd.argtypes = [i64, vp, vp, vp, i32, vp]
         L.ora_interpolate.restype = None
         L.ora_interpolate.argtypes = [i64, vp, vp, i64, vp, vp, vp, vp, i32, vp]
         _L = L
@@ -271,3 +275,38 @@ def interpolate(pos, owner, entry_pos, entry_h, entry_kind, values):
     out = np.empty((pos.shape[0], k))
     _lib().ora_interpolate(pos.shape[0], _p(pos), _p(owner), len(eh), _p(ex), _p(eh), _p(ek), _p(v), k, _p(out))
     return out[:, 0] if np.asarray(values).ndim == 1 else out
+
+
+def voronoi(gen, box_lo=(0.0, 0.0, 0.0), box_hi=(1.0, 1.0, 1.0)):
+    """Voronoi cells of the generators in the box (Sec. 2.3) by cutting the
+    box with every bisector.  Returns volume [C], centroid [C][3] and the
+    faces: cell_face_off [C+1], face_id [F] (neighbour, or -1..-6 for the
+    box planes x-, x+, y-, y+, z-, z+), face_area [F], face_vtx_off [F+1]
+    and face_pts [FV][3] (each face's polygon in cyclic order)."""
+    g = _c(np.asarray(gen).reshape(-1, 3), np.float64)
+    lo = _c(box_lo, np.float64)
+    hi = _c(box_hi, np.float64)
+    n = g.shape[0]
+    vol = np.empty(n)
+    cen = np.empty((n, 3))
+    F = np.zeros(1, dtype=np.int64)
+    FV = np.zeros(1, dtype=np.int64)
+    _lib().ora_voronoi(n, _p(g), _p(lo), _p(hi), _p(vol), _p(cen), None, None, None, None, None, _p(F), _p(FV))
+    cfo = np.empty(n + 1, dtype=np.int64)
+    fid = np.empty(int(F[0]), dtype=np.int64)
+    farea = np.empty(int(F[0]))
+    fvo = np.empty(int(F[0]) + 1, dtype=np.int64)
+    pts = np.empty((int(FV[0]), 3))
+    _lib().ora_voronoi(n, _p(g), _p(lo), _p(hi), _p(vol), _p(cen), _p(cfo), _p(fid), _p(farea), _p(fvo), _p(pts),
+                       _p(F), _p(FV))
+    return dict(volume=vol, centroid=cen, cell_face_off=cfo, face_id=fid, face_area=farea, face_vtx_off=fvo,
+                face_pts=pts)
+
+
+def lloyd(gen, iters, box_lo=(0.0, 0.0, 0.0), box_hi=(1.0, 1.0, 1.0)):
+    """Generators after `iters` Lloyd iterations (each moves to the centroid
+    of its Voronoi cell, Sec. 2.3)."""
+    g = _c(np.asarray(gen).reshape(-1, 3), np.float64)
+    out = np.empty_like(g)
+    _lib().ora_lloyd(g.shape[0], _p(g), _p(_c(box_lo, np.float64)), _p(_c(box_hi, np.float64)), int(iters), _p(out))
+    return out
