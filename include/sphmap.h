@@ -133,6 +133,40 @@ int sphmap_tess_cell_info(sphmap_ctx *ctx, const sphmap_tess *tess, double *d_vo
                           void *stream);
 
 /* ------------------------------------------------------------------------
+ * Voronoi grid built on the device (Sec. 2.3: the grid of the generation
+ * sites, regularised by Lloyd iterations before the forward mapping).
+ *   d_generators [n][3] (device): the sites, inside [h_box_lo, h_box_hi]
+ *     (host [3] each).  Cell c is the part of the box at least as close to
+ *     site c as to any other.
+ *   n_lloyd: Lloyd iterations first (each moves every site to the centroid
+ *     of its cell; the paper uses 5).
+ *   d_generators_out [n][3] (device, nullable): the sites of the final grid.
+ *   *out: the grid, resident as if uploaded by sphmap_tess_upload; each cell
+ *     owns its faces and vertices; faces record the neighbour they face.
+ * Cuts within 1e-13 of the box size of a vertex leave it in place.
+ * Errors: EINVAL (n < 1, n >= 2^31, a site outside the box, two equal
+ * sites, an empty box), EGEOM (a cell with more than 58 cutting neighbours or
+ * 128 vertices).  Nothing is returned on an error.
+ * ---------------------------------------------------------------------- */
+int sphmap_tess_build_voronoi(sphmap_ctx *ctx, int64_t n, const double *d_generators, const double *h_box_lo,
+                              const double *h_box_hi, int32_t n_lloyd, double *d_generators_out, void *stream,
+                              sphmap_tess **out);
+
+/* Sizes of a resident grid (any pointer may be NULL). */
+int sphmap_tess_counts(const sphmap_tess *tess, int64_t *n_cells, int64_t *n_faces, int64_t *n_face_vertices,
+                       int64_t *n_vertices);
+
+/* Copy a resident grid into caller device buffers (any may be NULL), in the
+   layout of sphmap_tess_upload: d_generators [C][3], d_vertices [V][3],
+   d_cell_face_off [C+1], d_face_vtx_off [F+1], d_face_vtx [FV];
+   d_face_nbr [F]: the neighbouring site of each face, -1..-6 for the box
+   planes x-, x+, y-, y+, z-, z+ (grids built by sphmap_tess_build_voronoi
+   only: EINVAL for an uploaded grid). */
+int sphmap_tess_export(sphmap_ctx *ctx, const sphmap_tess *tess, double *d_generators, double *d_vertices,
+                       int64_t *d_cell_face_off, int64_t *d_face_vtx_off, int32_t *d_face_vtx, int32_t *d_face_nbr,
+                       void *stream);
+
+/* ------------------------------------------------------------------------
  * Forward mapping (Sec. 1; Sec. 2.3 "forward mapping"; kernel Sec. 2.4.2).
  *   d_xyz [n][3], d_h [n], d_m [n]   particle positions, smoothing lengths,
  *                                    masses (binary64, device)
@@ -318,7 +352,8 @@ int interpolate_to_particles(sphmap_ctx *ctx, int64_t n, const double *d_xyz, co
  * Kernel timing: when enabled, HIP events are recorded on the launch stream
  * around each launch of the named kernels ("exact_integral", "exact_redo",
  * "pair_fill", "pair_count", "cell_reduce", "reverse", "transpose",
- * "node_hsolve", "interp").
+ * "node_hsolve", "interp", "voronoi_lloyd", "voronoi_count",
+ * "voronoi_faces").
  * sphmap_kernel_time synchronises on the recorded events and returns the
  * summed milliseconds and the number of launches since the last reset.
  * ---------------------------------------------------------------------- */

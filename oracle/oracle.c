@@ -1174,3 +1174,16 @@ void ora_lloyd(int64_t n, const double *g, const double *lo, const double *hi, i
   if (iters <= 0) memcpy(out, g, sizeof(double) * 3 * n);
   free(cur);
 }
+
+/* Volume and centroid of the cells listed in cells[m] only (same
+   construction as ora_voronoi). */
+void ora_voronoi_cells(int64_t n, const double *g, const double *lo, const double *hi, int64_t m,
+                       const int64_t *cells, double *volume, double *centroid) {
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t k = 0; k < m; ++k) {
+    ocell_t C;
+    ocell_build(n, g, cells[k], lo, hi, &C);
+    ocell_moments(&C, g + 3 * cells[k], &volume[k], centroid + 3 * k);
+    ocell_free(&C);
+  }
+}

@@ -68,6 +68,8 @@ def _lib():
         L.ora_underresolved.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, vp]
         L.ora_voronoi.restype = ctypes.c_int
         L.ora_voronoi.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.ora_voronoi_cells.restype = None
+        L.ora_voronoi_cells.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp]
         L.ora_lloyd.restype = None
         L.ora_lloyd.argtypes = [i64, vp, vp, vp, i32, vp]
         L.ora_interpolate.restype = None
@@ -310,3 +312,15 @@ def lloyd(gen, iters, box_lo=(0.0, 0.0, 0.0), box_hi=(1.0, 1.0, 1.0)):
     out = np.empty_like(g)
     _lib().ora_lloyd(g.shape[0], _p(g), _p(_c(box_lo, np.float64)), _p(_c(box_hi, np.float64)), int(iters), _p(out))
     return out
+
+
+def voronoi_cells(gen, cells, box_lo=(0.0, 0.0, 0.0), box_hi=(1.0, 1.0, 1.0)):
+    """Volume and centroid of the listed cells only."""
+    g = _c(np.asarray(gen).reshape(-1, 3), np.float64)
+    cells = _c(cells, np.int64)
+    vol = np.empty(len(cells))
+    cen = np.empty((len(cells), 3))
+    _lib().ora_voronoi_cells(g.shape[0], _p(g), _p(_c(box_lo, np.float64)), _p(_c(box_hi, np.float64)), len(cells),
+                             _p(cells), _p(vol), _p(cen))
+    return vol, cen
+

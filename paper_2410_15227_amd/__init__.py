@@ -154,6 +154,50 @@ class DeviceTessellation:
                                        p(fv), _stream_handle(stream), ctypes.byref(h)))
         self.handle = h
 
+    @classmethod
+    def _from_handle(cls, ctx: Context, handle) -> "DeviceTessellation":
+        self = cls.__new__(cls)
+        self.ctx = ctx
+        self.handle = handle
+        c = ctypes.c_int64()
+        _native.lib().sphmap_tess_counts(handle, ctypes.byref(c), None, None, None)
+        self.n_cells = c.value
+        return self
+
+    def counts(self) -> dict:
+        c, f, fv, v = (ctypes.c_int64() for _ in range(4))
+        self.ctx.check(_native.lib().sphmap_tess_counts(self.handle, ctypes.byref(c), ctypes.byref(f), ctypes.byref(fv),
+                                                        ctypes.byref(v)))
+        return dict(n_cells=c.value, n_faces=f.value, n_face_vertices=fv.value, n_vertices=v.value)
+
+    def export(self, with_neighbours: bool = True, stream=None):
+        """The grid as host arrays (a workloads.Tessellation); face_nbr holds
+        each face's neighbouring site (-1..-6: box planes) for grids built by
+        build_voronoi."""
+        import numpy as np
+
+        from .workloads import Tessellation
+        torch = _torch()
+        k = self.counts()
+        dev = self.ctx.device
+        g = torch.empty((k["n_cells"], 3), dtype=torch.float64, device=dev)
+        v = torch.empty((max(k["n_vertices"], 1), 3), dtype=torch.float64, device=dev)
+        cfo = torch.empty(k["n_cells"] + 1, dtype=torch.int64, device=dev)
+        fvo = torch.empty(k["n_faces"] + 1, dtype=torch.int64, device=dev)
+        fv = torch.empty(max(k["n_face_vertices"], 1), dtype=torch.int32, device=dev)
+        nb = torch.full((max(k["n_faces"], 1),), -7, dtype=torch.int32, device=dev)
+        self.ctx.check(_native.lib().sphmap_tess_export(self.ctx.handle, self.handle, _ptr(g), _ptr(v), _ptr(cfo),
+                                                        _ptr(fvo), _ptr(fv), _ptr(nb) if with_neighbours else None,
+                                                        _stream_handle(stream)))
+        torch.cuda.synchronize(dev)
+        gn = g.cpu().numpy()
+        vn = v.cpu().numpy()[:k["n_vertices"]]
+        return Tessellation(generators=gn, vertices=vn, cell_face_off=cfo.cpu().numpy(),
+                            face_vtx_off=fvo.cpu().numpy(), face_vtx=fv.cpu().numpy()[:k["n_face_vertices"]],
+                            face_nbr=nb.cpu().numpy()[:k["n_faces"]],
+                            box_lo=np.min(vn, axis=0) if len(vn) else np.zeros(3),
+                            box_hi=np.max(vn, axis=0) if len(vn) else np.ones(3))
+
     def cell_info(self, stream=None):
         torch = _torch()
         vol = torch.empty(self.n_cells, dtype=torch.float64, device=self.ctx.device)
@@ -173,6 +217,22 @@ class DeviceTessellation:
                 self.free()
         except Exception:
             pass
+
+
+def build_voronoi(ctx: Context, generators, box_lo=(0.0, 0.0, 0.0), box_hi=(1.0, 1.0, 1.0), n_lloyd: int = 5,
+                  stream=None):
+    """The Voronoi grid of the sites on the device (Sec. 2.3), after n_lloyd
+    Lloyd iterations.  Returns (DeviceTessellation, final sites [n][3] on the
+    device)."""
+    torch = _torch()
+    g = _dev_f64(generators, ctx.device, 3)
+    out = torch.empty_like(g)
+    lo = (ctypes.c_double * 3)(*[float(x) for x in box_lo])
+    hi = (ctypes.c_double * 3)(*[float(x) for x in box_hi])
+    h = ctypes.c_void_p()
+    ctx.check(_native.lib().sphmap_tess_build_voronoi(ctx.handle, g.shape[0], _ptr(g), lo, hi, int(n_lloyd),
+                                                      _ptr(out), _stream_handle(stream), ctypes.byref(h)))
+    return DeviceTessellation._from_handle(ctx, h), out
 
 
 class Pairs:

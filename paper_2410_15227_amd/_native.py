@@ -21,6 +21,7 @@ EXPORTS = [
     "map_particles_to_cells", "map_particles_to_cells_batch", "sphmap_pairs_info", "sphmap_pairs_export", "sphmap_pairs_free",
     "map_cells_to_particles", "build_pseudo_particles", "build_pseudo_particles_open", "select_underresolved",
     "interpolate_to_particles", "sphmap_sync_status", "sphmap_estimate_footprint",
+    "sphmap_tess_build_voronoi", "sphmap_tess_counts", "sphmap_tess_export",
     "sphmap_set_timing", "sphmap_kernel_time", "sphmap_reset_timing",
     "sphmap_set_counting", "sphmap_work_counters", "sphmap_set_autotune", "sphmap_tuned_shape",
 ]
@@ -97,6 +98,12 @@ def lib():
         L.select_underresolved.restype = ctypes.c_int
         L.select_underresolved.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.c_double, ctypes.c_double, vp,
                                            ctypes.POINTER(i64), vp]
+        L.sphmap_tess_build_voronoi.restype = ctypes.c_int
+        L.sphmap_tess_build_voronoi.argtypes = [vp, i64, vp, vp, vp, i32, vp, vp, ctypes.POINTER(vp)]
+        L.sphmap_tess_counts.restype = ctypes.c_int
+        L.sphmap_tess_counts.argtypes = [vp] + [ctypes.POINTER(i64)] * 4
+        L.sphmap_tess_export.restype = ctypes.c_int
+        L.sphmap_tess_export.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.sphmap_sync_status.restype = ctypes.c_int
         L.sphmap_sync_status.argtypes = [vp, vp, i32, ctypes.POINTER(i32)]
         L.sphmap_estimate_footprint.restype = ctypes.c_int

@@ -153,6 +153,57 @@ int sphmap_tess_upload(sphmap_ctx *ctx, int64_t n_cells, int64_t n_faces, int64_
   return SPHMAP_OK;
 }
 
+int sphmap_tess_build_voronoi(sphmap_ctx *ctx, int64_t n, const double *d_generators, const double *h_box_lo,
+                              const double *h_box_hi, int32_t n_lloyd, double *d_generators_out, void *stream,
+                              sphmap_tess **out) {
+  if (!ctx || !out) return SPHMAP_EINVAL;
+  *out = nullptr;
+  std::unique_ptr<sphmap_tess> T(new sphmap_tess);
+  int rc = guarded(ctx, [&] {
+    SPH_REQUIRE(n >= 1 && n < ((int64_t)1 << 31), SPHMAP_EINVAL, "n out of range [1, 2^31)");
+    SPH_REQUIRE(d_generators && h_box_lo && h_box_hi, SPHMAP_EINVAL, "null array");
+    SPH_REQUIRE(n_lloyd >= 0, SPHMAP_EINVAL, "n_lloyd must be >= 0");
+    for (int a = 0; a < 3; ++a)
+      SPH_REQUIRE(std::isfinite(h_box_lo[a]) && std::isfinite(h_box_hi[a]) && h_box_hi[a] > h_box_lo[a],
+                  SPHMAP_EINVAL, "empty or non-finite box");
+    sphmap::voronoi_build(ctx->c, T->t, n, d_generators, h_box_lo, h_box_hi, n_lloyd, d_generators_out,
+                          as_stream(stream));
+  });
+  if (rc != SPHMAP_OK) return rc;
+  *out = T.release();
+  return SPHMAP_OK;
+}
+
+int sphmap_tess_counts(const sphmap_tess *tess, int64_t *n_cells, int64_t *n_faces, int64_t *n_face_vertices,
+                       int64_t *n_vertices) {
+  if (!tess) return SPHMAP_EINVAL;
+  if (n_cells) *n_cells = tess->t.n_cells;
+  if (n_faces) *n_faces = tess->t.n_faces;
+  if (n_face_vertices) *n_face_vertices = tess->t.n_fv;
+  if (n_vertices) *n_vertices = tess->t.n_vertices;
+  return SPHMAP_OK;
+}
+
+int sphmap_tess_export(sphmap_ctx *ctx, const sphmap_tess *tess, double *d_generators, double *d_vertices,
+                       int64_t *d_cell_face_off, int64_t *d_face_vtx_off, int32_t *d_face_vtx, int32_t *d_face_nbr,
+                       void *stream) {
+  if (!ctx || !tess) return SPHMAP_EINVAL;
+  return guarded(ctx, [&] {
+    const auto &t = tess->t;
+    SPH_REQUIRE(!d_face_nbr || t.face_nbr, SPHMAP_EINVAL, "the grid records no face neighbours");
+    hipStream_t s = as_stream(stream);
+    auto cp = [&](void *dst, const void *src, size_t bytes) {
+      if (dst && bytes) SPH_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+    };
+    cp(d_generators, t.gen, 3 * t.n_cells * sizeof(double));
+    cp(d_vertices, t.vert, 3 * t.n_vertices * sizeof(double));
+    cp(d_cell_face_off, t.cell_face_off, (t.n_cells + 1) * sizeof(int64_t));
+    cp(d_face_vtx_off, t.face_vtx_off, (t.n_faces + 1) * sizeof(int64_t));
+    cp(d_face_vtx, t.face_vtx, t.n_fv * sizeof(int32_t));
+    cp(d_face_nbr, t.face_nbr, t.n_faces * sizeof(int32_t));
+  });
+}
+
 int sphmap_tess_free(sphmap_ctx *ctx, sphmap_tess *tess) {
   if (!ctx || !tess) return SPHMAP_EINVAL;
   (void)hipSetDevice(ctx->c.device);

@@ -159,6 +159,7 @@ struct TessDev {
   float *radius = nullptr;        // [C]
   float4 *gen32 = nullptr;        // [C] fl(g), R_c in w
   int32_t *cell_order = nullptr;  // [C] cells in Morton order of the generators
+  int32_t *face_nbr = nullptr;    // [F] neighbour each face faces (grids built here)
 };
 
 // ---------------------------------------------------------------- pairs
@@ -245,6 +246,9 @@ void pseudo_build(Ctx &ctx, PseudoArgs &a, hipStream_t s);
 int64_t select_underresolved(Ctx &ctx, int64_t n, const int32_t *kind, const uint64_t *label, const double *s_node,
                              const double *fneu, double s_root, double K, uint64_t *out, hipStream_t s);
 
+// Voronoi grid of n generators in the box after n_lloyd Lloyd iterations
+void voronoi_build(Ctx &ctx, TessDev &t, int64_t n, const double *d_gen, const double lo[3], const double hi[3],
+                   int n_lloyd, double *d_gen_out, hipStream_t s);
 // per-particle values from the mixed set (Sec. 3.3)
 void interpolate_particles(Ctx &ctx, int64_t n, const double *xyz, const int64_t *owner, int64_t ne,
                            const double *exyz, const double *eh, const int32_t *ekind, const double *val, int ncomp,
