@@ -78,7 +78,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=30000, help="cells of the oracle CPU baseline (about 10-15 s)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=3, help="timed steps of the plain binary64 path")
-    ap.add_argument("--workload", default="turbulent", choices=["turbulent", "pseudo", "batch", "serve"],
+    ap.add_argument("--workload", default="turbulent", choices=["turbulent", "pseudo", "batch", "serve", "voronoi"],
                     help="turbulent: the 262,144-particle cloud (default); pseudo: 1,048,576 particles collapsed "
                          "to tree-node pseudo-particles around the densest particle, mapped on the mixed set's grid; "
                          "batch: 64 independent instances of 2^12..2^18 particles in one batched call; "
@@ -91,7 +91,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is a design in DESIGN.md, not a measured path", file=sys.stderr)
+              "the multi-GPU sharding is designed but not a measured path", file=sys.stderr)
         sys.exit(2)
     if args.workload == "pseudo":
         return run_pseudo(args)
@@ -99,6 +99,8 @@ def main():
         return run_batch(args)
     if args.workload == "serve":
         return run_serve(args)
+    if args.workload == "voronoi":
+        return run_voronoi(args)
 
     import numpy as np
     import torch
@@ -382,6 +384,103 @@ def run_pseudo(args):
     print(json.dumps(out), flush=True)
     dt_mix.free()
     dt_all.free()
+    ctx.close()
+
+
+def run_voronoi(args):
+    """The grid before the mapping (Sec. 2.3): the Voronoi grid of the
+    262,144 turbulent-cloud particles (seed 2) as sites in the unit box,
+    after 5 Lloyd iterations, built on the device; one timed step = the five
+    iterations and the final grid ready for the mapping.  The forward
+    mapping of the same particles on the regularised grid is timed beside
+    it, as are the host grid builder and the oracle on a sample of cells."""
+    import numpy as np
+    import torch
+
+    import paper_2410_15227_amd as pkg
+    from paper_2410_15227_amd import workloads
+
+    n = args.n
+    t0 = time.time()
+    pos, m, h, rho = workloads.make_cloud("turbulent", n, 2)
+    log(f"inputs: turbulent_{n} (seed 2) in {time.time() - t0:.1f}s")
+    ctx = pkg.Context(0)
+    dev = ctx.device
+    xyz = torch.tensor(pos, dtype=torch.float64, device=dev)
+    hd = torch.tensor(h, dtype=torch.float64, device=dev)
+    md = torch.tensor(m, dtype=torch.float64, device=dev)
+    n_lloyd = 5
+
+    def build():
+        dt, g = pkg.build_voronoi(ctx, xyz, n_lloyd=n_lloyd)
+        return dt, g
+
+    for _ in range(args.warmup):
+        dt, _ = build()
+        dt.free()
+    torch.cuda.synchronize()
+    ctx.reset_timing()
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        dt, g_out = build()
+        if k + 1 < args.steps:
+            dt.free()
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t0) / args.steps
+    kt = {name: ctx.kernel_time(name) for name in ("voronoi_lloyd", "voronoi_count", "voronoi_faces")}
+    ctx.set_timing(False)
+    counts = dt.counts()
+    vol = dt.cell_info()[0]
+    vol_sum = float(vol.sum().item())
+    # the forward mapping on the regularised grid
+    res = pkg.map_particles_to_cells(ctx, dt, xyz, hd, md, precision=args.precision, keep_pairs=True)
+    map_pairs = res.pairs.n_pairs
+    res.pairs.free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        res = pkg.map_particles_to_cells(ctx, dt, xyz, hd, md, precision=args.precision)
+    torch.cuda.synchronize()
+    map_s = (time.perf_counter() - t0) / 3
+    # the host builder (no Lloyd iterations), for reference
+    t0 = time.time()
+    workloads.voronoi(pos)
+    host_s = time.time() - t0
+    out = {
+        "metric": "Voronoi cells built/s (5 Lloyd iterations)",
+        "value": round(n / step_s, 1),
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_s * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"voronoi_turbulent_{n}", "n_sites": n, "lloyd_iterations": n_lloyd,
+                   "box": [[0, 0, 0], [1, 1, 1]]},
+        "grid": {"faces_per_cell": round(counts["n_faces"] / n, 3),
+                 "vertices_per_cell": round(counts["n_vertices"] / n, 3), "volume_sum": vol_sum,
+                 "kernel_ms_per_step": {k: round(v[0] / max(1, args.steps), 3) for k, v in kt.items()},
+                 "map_pairs": int(map_pairs), "map_ms": round(map_s * 1e3, 3),
+                 "map_pairs_per_s": round(map_pairs / map_s, 1), "host_builder_s_no_lloyd": round(host_s, 2)},
+    }
+    if not args.no_cpu:
+        from oracle import oracle
+        rng = np.random.default_rng(1)
+        cells = rng.choice(n, 64, replace=False)
+        t0 = time.perf_counter()
+        oracle.voronoi_cells(pos, cells)
+        cs = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(len(cells) / cs * 1.0 / (n_lloyd + 1), 1), "unit": "cells/s",
+                               "cores": oracle.threads(), "kind": "oracle",
+                               "sample": f"{len(cells)} cells of the {n}-site grid, one construction each, "
+                                         f"rate divided by the {n_lloyd + 1} constructions of a step"}
+    print(json.dumps(out), flush=True)
+    dt.free()
     ctx.close()
 
 

@@ -31,6 +31,7 @@ namespace {
 constexpr int kVP = 64;     // planes per cell: 6 box planes + neighbours
 constexpr int kVT = 128;    // vertices per cell
 constexpr int kVWaves = 4;  // cells per workgroup
+constexpr int kCand = 256;  // sites listed at a time per wave
 
 // error bits
 constexpr int kErrCoincident = 1;
@@ -48,6 +49,7 @@ struct VorLds {
   uint8_t first[kVP];    // a vertex on each plane (valid when it holds it)
   uint8_t outf[kVT];
   uint8_t remap[kVP];
+  int32_t list[kCand];   // sorted-array positions of a group's sites
 };
 
 struct VorGrid {
@@ -313,11 +315,141 @@ __device__ bool vclip(VorLds &L, int &nP, int &nT, double nx, double ny, double 
   return true;
 }
 
-// order of the 26 neighbouring grid cells: faces, edges, corners
-__constant__ int8_t kRing1[26][3] = {
-    {-1, 0, 0},  {1, 0, 0},   {0, -1, 0},  {0, 1, 0},  {0, 0, -1},  {0, 0, 1},   {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
-    {1, 1, 0},   {-1, 0, -1}, {1, 0, -1},  {-1, 0, 1}, {1, 0, 1},   {0, -1, -1}, {0, 1, -1},  {0, -1, 1}, {0, 1, 1},
-    {-1, -1, -1}, {1, -1, -1}, {-1, 1, -1}, {1, 1, -1}, {-1, -1, 1}, {1, -1, 1},  {-1, 1, 1},  {1, 1, 1}};
+// Cut by the candidates of one batch (lane: a position in the sorted site
+// array, or -1), nearest first.  Returns false on an error (bit in *err).
+__device__ bool vbatch(VorLds &L, const VorGrid &Gd, int64_t c, double gx, double gy, double gz, int k, int &nP,
+                       int &nT, double &r2, double eps, int lane, int *err) {
+  int32_t j = -1;
+  double ex = 0.0, ey = 0.0, ez = 0.0, dist = 0.0;
+  if (k >= 0) {
+    j = Gd.sorted[k];
+    ex = Gd.gen[3 * (int64_t)j] - gx;
+    ey = Gd.gen[3 * (int64_t)j + 1] - gy;
+    ez = Gd.gen[3 * (int64_t)j + 2] - gz;
+    dist = sqrt(ex * ex + ey * ey + ez * ez);
+  }
+  const bool cand = j >= 0 && j != (int32_t)c && 0.5 * dist <= sqrt(r2) + eps;
+  const int ncand = __popcll(ballot64(cand));
+  if (ncand == 0) return true;
+  // sort (distance, lane) across the wave
+  uint64_t key = cand ? (((uint64_t)__float_as_uint((float)dist) << 32) | (uint64_t)lane) : ~0ull;
+#pragma unroll
+  for (int kk = 2; kk <= 64; kk <<= 1)
+#pragma unroll
+    for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+      const uint64_t other = (uint64_t)__shfl_xor((long long)key, jj, 64);
+      const bool up = (lane & kk) == 0, lower = (lane & jj) == 0;
+      key = (lower == up) ? (key < other ? key : other) : (key > other ? key : other);
+    }
+  for (int i = 0; i < ncand; ++i) {
+    const int l = __builtin_amdgcn_readlane((int)(uint32_t)key, i) & 63;
+    const double dd = readlane_d(dist, l);
+    if (0.5 * dd > sqrt(r2) + eps) break;
+    if (!(dd > 0.0)) {
+      if (lane == 0) atomicOr(err, kErrCoincident);
+      return false;
+    }
+    const int32_t jj = __builtin_amdgcn_readlane(j, l);
+    const double nx = readlane_d(ex, l) / dd, ny = readlane_d(ey, l) / dd, nz = readlane_d(ez, l) / dd;
+    if (!vclip(L, nP, nT, nx, ny, nz, 0.5 * dd, jj, eps, r2, lane, err)) return false;
+  }
+  return true;
+}
+
+// Sort one 64-bit key per lane across the wave, ascending.
+__device__ inline uint64_t vsort64(uint64_t key, int lane) {
+#pragma unroll
+  for (int kk = 2; kk <= 64; kk <<= 1)
+#pragma unroll
+    for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+      const uint64_t other = (uint64_t)__shfl_xor((long long)key, jj, 64);
+      const bool up = (lane & kk) == 0, lower = (lane & jj) == 0;
+      key = (lower == up) ? (key < other ? key : other) : (key > other ? key : other);
+    }
+  return key;
+}
+
+// Keep the 64 smallest of two ascending 64-lane lists, ascending.
+__device__ inline uint64_t vmerge64(uint64_t best, uint64_t chunk, int lane) {
+  const uint64_t rev = (uint64_t)__shfl((long long)chunk, 63 - lane, 64);
+  uint64_t key = best < rev ? best : rev;  // bitonic: the 64 smallest of both
+#pragma unroll
+  for (int jj = 32; jj > 0; jj >>= 1) {
+    const uint64_t other = (uint64_t)__shfl_xor((long long)key, jj, 64);
+    const bool lower = (lane & jj) == 0;
+    key = lower ? (key < other ? key : other) : (key > other ? key : other);
+  }
+  return key;
+}
+
+// A group of grid cells (lane l: sites [s0, s0 + cnt) of the sorted array,
+// at offset off of the group's tot sites) is listed kCand sites at a time.
+__device__ inline void vwindow(VorLds &L, int s0, int cnt, int off, int w0, int lane) {
+  (void)lane;
+  const int e0 = max(0, w0 - off), e1 = min(cnt, w0 + kCand - off);
+  for (int e = e0; e < e1; ++e) L.list[off + e - w0] = s0 + e;
+  vsync();
+}
+
+// Cut by every site of a group.  With `nearest`, the 64 sites nearest to
+// the generator cut first, so that the cell is close to its final shape
+// before the rest are tested (far sites cutting a large cell first would
+// leave many short-lived faces).
+__device__ bool vgroup(VorLds &L, const VorGrid &Gd, int64_t c, double gx, double gy, double gz, int s0, int cnt,
+                       bool nearest, int &nP, int &nT, double &r2, double eps, int lane, int *err) {
+  const int off = vscan_excl(cnt, lane);
+  const int tot = vsum(cnt);
+  if (nearest) {
+    uint64_t best = ~0ull;
+    for (int w0 = 0; w0 < tot; w0 += kCand) {
+      vwindow(L, s0, cnt, off, w0, lane);
+      const int wn = min(kCand, tot - w0);
+      for (int b = 0; b < wn; b += 64) {
+        uint64_t key = ~0ull;
+        if (b + lane < wn) {
+          const int32_t j = Gd.sorted[L.list[b + lane]];
+          const double ex = Gd.gen[3 * (int64_t)j] - gx, ey = Gd.gen[3 * (int64_t)j + 1] - gy,
+                       ez = Gd.gen[3 * (int64_t)j + 2] - gz;
+          if (j != (int32_t)c)
+            key = ((uint64_t)__float_as_uint((float)sqrt(ex * ex + ey * ey + ez * ez)) << 32) | (uint32_t)j;
+        }
+        best = vmerge64(best, vsort64(key, lane), lane);
+      }
+      vsync();
+    }
+    int32_t j = -1;
+    double ex = 0.0, ey = 0.0, ez = 0.0, dist = 0.0;
+    if (best != ~0ull) {
+      j = (int32_t)(best & 0xffffffffull);
+      ex = Gd.gen[3 * (int64_t)j] - gx;
+      ey = Gd.gen[3 * (int64_t)j + 1] - gy;
+      ez = Gd.gen[3 * (int64_t)j + 2] - gz;
+      dist = sqrt(ex * ex + ey * ey + ez * ez);
+    }
+    const int nb = __popcll(ballot64(j >= 0));
+    for (int l = 0; l < nb; ++l) {
+      const double dd = readlane_d(dist, l);
+      if (0.5 * dd > sqrt(r2) + eps) break;
+      if (!(dd > 0.0)) {
+        if (lane == 0) atomicOr(err, kErrCoincident);
+        return false;
+      }
+      const int32_t jj = __builtin_amdgcn_readlane(j, l);
+      if (!vclip(L, nP, nT, readlane_d(ex, l) / dd, readlane_d(ey, l) / dd, readlane_d(ez, l) / dd, 0.5 * dd, jj,
+                 eps, r2, lane, err))
+        return false;
+    }
+  }
+  for (int w0 = 0; w0 < tot; w0 += kCand) {
+    vwindow(L, s0, cnt, off, w0, lane);
+    const int wn = min(kCand, tot - w0);
+    for (int b = 0; b < wn; b += 64)
+      if (!vbatch(L, Gd, c, gx, gy, gz, b + lane < wn ? L.list[b + lane] : -1, nP, nT, r2, eps, lane, err))
+        return false;
+    vsync();
+  }
+  return true;
+}
 
 __device__ inline int gcell(double x, double lo, double cs, int G) {
   int i = (int)floor((x - lo) / cs);
@@ -368,85 +500,35 @@ __global__ void __launch_bounds__(64 * kVWaves) k_voronoi(VorGrid Gd, int64_t n,
   const int hz = gcell(gz, Gd.lo[2], Gd.cs[2], Gd.G[2]);
   const double csmin = fmin(Gd.cs[0], fmin(Gd.cs[1], Gd.cs[2]));
   const int gmax = max(Gd.G[0], max(Gd.G[1], Gd.G[2]));
-  for (int r = 0; ok && r <= gmax; ++r) {
-    const double R = sqrt(r2);
-    if (r >= 2 && (r - 1) * csmin > 2.0 * R + eps) break;
-    // ring r: the grid cells at Chebyshev distance r (rows of the cube's
-    // shell: whole rows on its top, bottom, front and back, end cells elsewhere)
-    const int nq = r == 0 ? 1 : (r == 1 ? 26 : (2 * r + 1) * (2 * r + 1) * (2 * r + 1));
-    for (int q = 0, dz = -r, dy = -r, dx = -r; ok && q < nq; ++q) {
-      int cx, cy, cz;
-      if (r == 1) {
-        cx = kRing1[q][0];
-        cy = kRing1[q][1];
-        cz = kRing1[q][2];
-      } else {
-        if (dz > r) break;
-        cx = dx;
-        cy = dy;
-        cz = dz;
-        const bool full = r == 0 || abs(dz) == r || abs(dy) == r;
-        dx += full ? 1 : 2 * r;
-        if (dx > r) {
-          dx = -r;
-          if (++dy > r) {
-            dy = -r;
-            ++dz;
+  // Candidates are gathered 64 grid cells at a time (one per lane) into an
+  // LDS list of sorted-array positions; rings 0 and 1 form the first group,
+  // so the nearest sites cut first.
+  for (int level = 0; ok; ++level) {
+    const int r = level == 0 ? 1 : level + 1;
+    if (level >= 1 && r > gmax - 1) break;
+    if (level >= 1 && (r - 1) * csmin > 2.0 * sqrt(r2) + eps) break;
+    const int side = 2 * r + 1, ncube = side * side * side;
+    for (int q0 = 0; ok && q0 < ncube; q0 += 64) {
+      const int q = q0 + lane;
+      int cnt = 0, s0 = 0;
+      if (q < ncube) {
+        const int cx = q % side - r, cy = (q / side) % side - r, cz = q / (side * side) - r;
+        const bool shell = level == 0 || max(abs(cx), max(abs(cy), abs(cz))) == r;
+        const int ix = hx + cx, iy = hy + cy, iz = hz + cz;
+        if (shell && ix >= 0 && iy >= 0 && iz >= 0 && ix < Gd.G[0] && iy < Gd.G[1] && iz < Gd.G[2]) {
+          // nearest point of the grid cell: nothing there can cut beyond 2R
+          const double bx = fmax(fmax(Gd.lo[0] + ix * Gd.cs[0] - gx, gx - (Gd.lo[0] + (ix + 1) * Gd.cs[0])), 0.0);
+          const double by = fmax(fmax(Gd.lo[1] + iy * Gd.cs[1] - gy, gy - (Gd.lo[1] + (iy + 1) * Gd.cs[1])), 0.0);
+          const double bz = fmax(fmax(Gd.lo[2] + iz * Gd.cs[2] - gz, gz - (Gd.lo[2] + (iz + 1) * Gd.cs[2])), 0.0);
+          if (sqrt(bx * bx + by * by + bz * bz) <= 2.0 * sqrt(r2) + eps) {
+            const int64_t cell = ((int64_t)iz * Gd.G[1] + iy) * Gd.G[0] + ix;
+            s0 = Gd.start[cell];
+            cnt = Gd.end[cell] - s0;
           }
         }
       }
-      const int ix = hx + cx, iy = hy + cy, iz = hz + cz;
-      if (ix < 0 || iy < 0 || iz < 0 || ix >= Gd.G[0] || iy >= Gd.G[1] || iz >= Gd.G[2]) continue;
-      // nearest point of the grid cell: nothing there can cut beyond 2R
-      {
-        const double Rn = sqrt(r2);
-        const double bx = fmax(fmax(Gd.lo[0] + ix * Gd.cs[0] - gx, gx - (Gd.lo[0] + (ix + 1) * Gd.cs[0])), 0.0);
-        const double by = fmax(fmax(Gd.lo[1] + iy * Gd.cs[1] - gy, gy - (Gd.lo[1] + (iy + 1) * Gd.cs[1])), 0.0);
-        const double bz = fmax(fmax(Gd.lo[2] + iz * Gd.cs[2] - gz, gz - (Gd.lo[2] + (iz + 1) * Gd.cs[2])), 0.0);
-        if (sqrt(bx * bx + by * by + bz * bz) > 2.0 * Rn + eps) continue;
-      }
-      const int64_t cell = ((int64_t)iz * Gd.G[1] + iy) * Gd.G[0] + ix;
-      const int s0 = Gd.start[cell], s1 = Gd.end[cell];
-      for (int base = s0; ok && base < s1; base += 64) {
-        const int k = base + lane;
-        int32_t j = -1;
-        double ex = 0.0, ey = 0.0, ez = 0.0, dist = 0.0;
-        if (k < s1) {
-          j = Gd.sorted[k];
-          ex = Gd.gen[3 * (int64_t)j] - gx;
-          ey = Gd.gen[3 * (int64_t)j + 1] - gy;
-          ez = Gd.gen[3 * (int64_t)j + 2] - gz;
-          dist = sqrt(ex * ex + ey * ey + ez * ez);
-        }
-        const bool cand = j >= 0 && j != (int32_t)c && 0.5 * dist <= sqrt(r2) + eps;
-        const int ncand = __popcll(ballot64(cand));
-        // nearest first: sort (distance, lane) across the wave
-        uint64_t key = cand ? (((uint64_t)__float_as_uint((float)dist) << 32) | (uint64_t)lane) : ~0ull;
-#pragma unroll
-        for (int kk = 2; kk <= 64; kk <<= 1)
-#pragma unroll
-          for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-            const uint64_t other = (uint64_t)__shfl_xor((long long)key, jj, 64);
-            const bool up = (lane & kk) == 0, lower = (lane & jj) == 0;
-            key = (lower == up) ? (key < other ? key : other) : (key > other ? key : other);
-          }
-        for (int i = 0; i < ncand; ++i) {
-          const uint64_t ki = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(key >> 32), i) << 32) |
-                              (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)key, i);
-          const int l = (int)(ki & 63);
-          const double dd = readlane_d(dist, l);
-          if (0.5 * dd > sqrt(r2) + eps) break;
-          if (!(dd > 0.0)) {
-            if (lane == 0) atomicOr(err, kErrCoincident);
-            ok = false;
-            break;
-          }
-          const int32_t jj = __builtin_amdgcn_readlane(j, l);
-          const double nx = readlane_d(ex, l) / dd, ny = readlane_d(ey, l) / dd, nz = readlane_d(ez, l) / dd;
-          ok = vclip(L, nP, nT, nx, ny, nz, 0.5 * dd, jj, eps, r2, lane, err);
-          if (!ok) break;
-        }
-      }
+      if (!ballot64(cnt > 0)) continue;
+      ok = vgroup(L, Gd, c, gx, gy, gz, s0, cnt, level == 0, nP, nT, r2, eps, lane, err);
     }
   }
   if (!ok) return;
