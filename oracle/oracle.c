@@ -1187,3 +1187,310 @@ void ora_voronoi_cells(int64_t n, const double *g, const double *lo, const doubl
     ocell_free(&C);
   }
 }
+
+/* ------------------------------------------------------------- k-d tree
+   The paper's own tree (Sec. 2.2.1): a binary k-d tree built top down by
+   recursive coordinate bisection.  A node's domain (the root's is the unit
+   cube) is split in two through the centre of mass of its particles along
+   the domain's longest axis (the first such axis on a tie); particles below
+   the split coordinate go left.  Splitting stops when a node holds fewer
+   than leaf_split particles (10 in the paper), at max_depth, or when a split
+   would leave one side empty.  Labels: root 1, children of n are 2n (left)
+   and 2n + 1 (right), so a node of label n lies on level floor(log2 n) and
+   its ancestor on level k is n >> (level - k).
+   Centres of mass are order-free: each m_i and m_i x_i is rounded to a
+   fixed-point integer of 2^-K (K such that every node sum stays below 2^62,
+   from n and the largest mass) and the integer sums are exact, so the
+   split planes do not depend on summation order.  Node mass = its integer
+   sum times 2^-K; size s = largest member distance from the centre of mass.
+
+   Walk (Sec. 2.4.1), depth first, left before right; per source, with
+   r = |com - source|: the node reaches r_part when r - s <= r_part, reaches
+   r_leaf when r - s <= r_leaf, and fails the opening angle when
+   theta^2 r^2 < s^2 (eq. opening_angle).  A node is accepted when it does
+   none of these for any source and is not named in open; an accepted node
+   is emitted (as itself when it has one particle).  A leaf that is not
+   accepted is emitted as its particles (own h) when it reaches r_part, is
+   named in open or holds one particle, and otherwise as a leaf
+   pseudo-particle (leaves in the annulus between r_part and r_leaf, and
+   leaves that fail the opening angle further out).
+
+   Node smoothing lengths: the iteration of eqs. hnode_func to
+   hnode_estval (ora_node_h) over the emitted units (accepted nodes and
+   leaves).  With more than nf_threshold units the sums run over the trial
+   neighbours of the neighbour-find of Sec. 2.4.3 instead of all units:
+   k_mid is the level just above the highest unit; for a target a, r_cut is
+   sqrt(3) times the size of a's ancestor on k_mid, or, when that is below
+   r_2h = 4 h_fact s_a (eq. compact_support_radius), 4 h_fact times the size
+   of a's ancestor up_levels above a; the k_mid nodes whose centres of mass
+   lie within r_cut of a are flagged, and the trial neighbours are the units
+   (in unit order) whose k_mid ancestor is flagged. */
+
+typedef struct {
+  uint64_t label;
+  int32_t level, parent, left, right;
+  int64_t first, count;
+  double lo[3], hi[3];
+  double com[3], M, s2;
+} kdnode_t;
+
+typedef struct {
+  const double *x, *m;
+  int leaf_split, max_depth, K;
+  int64_t *order, *tmp;
+  kdnode_t *nodes;
+  int64_t n_nodes, cap;
+} kdtree_t;
+
+static int kd_scale(int64_t n, const double *m) {
+  double mmax = 0.0;
+  for (int64_t i = 0; i < n; ++i) mmax = fmax(mmax, m[i]);
+  int e = 0;
+  frexp((double)n * mmax, &e);
+  return 62 - e;
+}
+
+static int32_t kd_build(kdtree_t *T, int64_t first, int64_t count, const double lo[3], const double hi[3],
+                        int level, uint64_t label, int32_t parent) {
+  if (T->n_nodes == T->cap) {
+    T->cap = T->cap ? 2 * T->cap : 1024;
+    T->nodes = (kdnode_t *)realloc(T->nodes, sizeof(kdnode_t) * T->cap);
+  }
+  const int32_t id = (int32_t)T->n_nodes++;
+  kdnode_t nd;
+  nd.label = label;
+  nd.level = level;
+  nd.parent = parent;
+  nd.left = nd.right = -1;
+  nd.first = first;
+  nd.count = count;
+  memcpy(nd.lo, lo, sizeof nd.lo);
+  memcpy(nd.hi, hi, sizeof nd.hi);
+  int64_t qm = 0, qx[3] = {0, 0, 0};
+  for (int64_t t = 0; t < count; ++t) {
+    const int64_t j = T->order[first + t];
+    qm += llrint(ldexp(T->m[j], T->K));
+    for (int k = 0; k < 3; ++k) qx[k] += llrint(ldexp(T->m[j] * T->x[3 * j + k], T->K));
+  }
+  for (int k = 0; k < 3; ++k) nd.com[k] = (double)qx[k] / (double)qm;
+  nd.M = ldexp((double)qm, -T->K);
+  nd.s2 = 0.0;
+  for (int64_t t = 0; t < count; ++t) {
+    const int64_t j = T->order[first + t];
+    double e[3];
+    v_sub(T->x + 3 * j, nd.com, e);
+    nd.s2 = fmax(nd.s2, v_dot(e, e));
+  }
+  T->nodes[id] = nd;
+  if (count < T->leaf_split || level >= T->max_depth) return id;
+  int axis = 0;
+  for (int k = 1; k < 3; ++k)
+    if (hi[k] - lo[k] > hi[axis] - lo[axis]) axis = k;
+  const double split = nd.com[axis];
+  int64_t nl = 0, nr = 0;
+  for (int64_t t = 0; t < count; ++t) {
+    const int64_t j = T->order[first + t];
+    if (T->x[3 * j + axis] < split) T->order[first + nl++] = j; else T->tmp[nr++] = j;
+  }
+  memcpy(T->order + first + nl, T->tmp, sizeof(int64_t) * nr);
+  if (nl == 0 || nr == 0) return id;
+  double llo[3], lhi[3], rlo[3], rhi[3];
+  memcpy(llo, lo, sizeof llo);
+  memcpy(lhi, hi, sizeof lhi);
+  memcpy(rlo, lo, sizeof rlo);
+  memcpy(rhi, hi, sizeof rhi);
+  lhi[axis] = split;
+  rlo[axis] = split;
+  const int32_t l = kd_build(T, first, nl, llo, lhi, level + 1, 2 * label, id);
+  const int32_t r = kd_build(T, first + nl, nr, rlo, rhi, level + 1, 2 * label + 1, id);
+  T->nodes[id].left = l;
+  T->nodes[id].right = r;
+  return id;
+}
+
+typedef struct {
+  int n_src;
+  const double *src;
+  double r_part, r_leaf, theta;
+  int64_t n_open;
+  const uint64_t *open;
+  int64_t n, n_units;
+  int32_t *kind, *unit_node, *entry_node;
+  int64_t *first, *count, *owner;
+  double *pos, *mass, *s;
+  uint64_t *label;
+  const double *hp;
+} kdemit_t;
+
+static void kd_walk(const kdtree_t *T, int32_t id, kdemit_t *E) {
+  const kdnode_t *nd = &T->nodes[id];
+  const double s = sqrt(nd->s2);
+  int part = 0, leafz = 0, angle = 0;
+  for (int k = 0; k < E->n_src; ++k) {
+    double e[3];
+    v_sub(nd->com, E->src + 3 * k, e);
+    const double r = sqrt(v_dot(e, e));
+    if (r - s <= E->r_part) part = 1;
+    if (r - s <= E->r_leaf) leafz = 1;
+    if (E->theta * E->theta * r * r < nd->s2) angle = 1;
+  }
+  const int forced = forced_open(nd->label, E->n_open, E->open);
+  const int leaf = nd->left < 0;
+  const int accepted = !(part || leafz || angle || forced);
+  if (!accepted && !leaf) {
+    kd_walk(T, nd->left, E);
+    kd_walk(T, nd->right, E);
+    return;
+  }
+  const int64_t u = E->n_units++;
+  E->unit_node[u] = id;
+  if (nd->count == 1 || (!accepted && (part || forced))) {
+    for (int64_t t = 0; t < nd->count; ++t) { /* members are in ascending index */
+      const int64_t j = T->order[nd->first + t];
+      const int64_t e = E->n++;
+      E->kind[e] = 0;
+      E->first[e] = j;
+      E->count[e] = 1;
+      for (int k = 0; k < 3; ++k) E->pos[3 * e + k] = T->x[3 * j + k];
+      E->mass[e] = T->m[j];
+      E->s[e] = 0.0;
+      E->label[e] = nd->label;
+      E->entry_node[e] = id;
+      E->owner[j] = e;
+    }
+    return;
+  }
+  const int64_t e = E->n++;
+  E->kind[e] = 1;
+  E->first[e] = T->order[nd->first];
+  E->count[e] = nd->count;
+  for (int k = 0; k < 3; ++k) E->pos[3 * e + k] = nd->com[k];
+  E->mass[e] = nd->M;
+  E->s[e] = s;
+  E->label[e] = nd->label;
+  E->entry_node[e] = id;
+  for (int64_t t = 0; t < nd->count; ++t) E->owner[T->order[nd->first + t]] = e;
+}
+
+static int32_t kd_ancestor(const kdtree_t *T, int32_t id, int level) {
+  while (id >= 0 && T->nodes[id].level > level) id = T->nodes[id].parent;
+  return id;
+}
+
+/* Full k-d builder.  Outputs as ora_pseudo_build (capacity n entries), plus
+   level of each entry's node; returns the entry count.  stats_out[4]:
+   nodes, units, k_mid (-1: all units summed), pseudo-particles. */
+int64_t ora_kd_build(int64_t n, const double *x, const double *m, const double *hp, int32_t n_src,
+                     const double *src, double r_part, double r_leaf, double theta, double hfact, double eps,
+                     int32_t leaf_split, int32_t max_depth, int64_t nf_threshold, int32_t up_levels,
+                     int64_t bypass, int64_t n_open, const uint64_t *open, int32_t *kind, int64_t *first,
+                     int64_t *count, double *pos, double *mass, double *h, double *s, int32_t *branch,
+                     uint64_t *label, int32_t *level, int64_t *owner, int64_t *stats_out, double *s_root_out) {
+  kdtree_t T;
+  T.x = x;
+  T.m = m;
+  T.leaf_split = leaf_split;
+  T.max_depth = max_depth;
+  T.K = kd_scale(n, m);
+  T.order = (int64_t *)malloc(sizeof(int64_t) * (n > 0 ? n : 1));
+  T.tmp = (int64_t *)malloc(sizeof(int64_t) * (n > 0 ? n : 1));
+  for (int64_t i = 0; i < n; ++i) T.order[i] = i;
+  T.nodes = NULL;
+  T.n_nodes = T.cap = 0;
+  const double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {1.0, 1.0, 1.0};
+  kd_build(&T, 0, n, lo, hi, 0, 1, -1);
+  uint64_t *open_sorted = (uint64_t *)malloc(sizeof(uint64_t) * (n_open > 0 ? n_open : 1));
+  if (n_open > 0) memcpy(open_sorted, open, sizeof(uint64_t) * n_open);
+  qsort(open_sorted, (size_t)n_open, sizeof(uint64_t), cmp_u64);
+  kdemit_t E;
+  E.n_src = n_src;
+  E.src = src;
+  E.r_part = r_part;
+  E.r_leaf = r_leaf;
+  E.theta = theta;
+  E.n_open = n_open;
+  E.open = open_sorted;
+  E.n = E.n_units = 0;
+  E.kind = kind;
+  E.first = first;
+  E.count = count;
+  E.pos = pos;
+  E.mass = mass;
+  E.s = s;
+  E.label = label;
+  E.owner = owner;
+  E.hp = hp;
+  E.unit_node = (int32_t *)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+  E.entry_node = (int32_t *)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+  kd_walk(&T, 0, &E);
+  const int64_t nu = E.n_units;
+  double *upos = (double *)malloc(sizeof(double) * 3 * (nu > 0 ? nu : 1));
+  int kmin = 1 << 30;
+  for (int64_t u = 0; u < nu; ++u) {
+    const kdnode_t *nd = &T.nodes[E.unit_node[u]];
+    memcpy(upos + 3 * u, nd->com, sizeof(double) * 3);
+    if (nd->level < kmin) kmin = nd->level;
+  }
+  const int use_nf = nu > nf_threshold;
+  const int kmid = use_nf ? (kmin > 0 ? kmin - 1 : 0) : -1;
+  int64_t n_pseudo = 0;
+  for (int64_t e = 0; e < E.n; ++e) {
+    level[e] = T.nodes[E.entry_node[e]].level;
+    if (kind[e] == 0) h[e] = hp[first[e]];
+    n_pseudo += kind[e] == 1;
+  }
+  /* k_mid ancestor of every unit */
+  int32_t *umid = (int32_t *)malloc(sizeof(int32_t) * (nu > 0 ? nu : 1));
+  if (use_nf)
+    for (int64_t u = 0; u < nu; ++u) umid[u] = kd_ancestor(&T, E.unit_node[u], kmid);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t e = 0; e < E.n; ++e) {
+    if (kind[e] != 1) {
+      branch[e] = -1;
+      continue;
+    }
+    if (n_pseudo > bypass) {
+      h[e] = hfact * 2.0 * s[e];
+      branch[e] = 3;
+      continue;
+    }
+    if (!use_nf) {
+      branch[e] = ora_node_h(pos + 3 * e, s[e], nu, upos, hfact, eps, &h[e], NULL);
+      continue;
+    }
+    const int32_t na = E.entry_node[e];
+    const int32_t mid = kd_ancestor(&T, na, kmid);
+    double rcut = sqrt(3.0) * sqrt(T.nodes[mid].s2);
+    if (rcut < 4.0 * hfact * s[e]) {
+      const int lv = T.nodes[na].level - up_levels;
+      rcut = 4.0 * hfact * sqrt(T.nodes[kd_ancestor(&T, na, lv > 0 ? lv : 0)].s2);
+    }
+    double *sub = (double *)malloc(sizeof(double) * 3 * (nu > 0 ? nu : 1));
+    int64_t ns = 0;
+    for (int64_t u = 0; u < nu; ++u) {
+      double d[3];
+      v_sub(pos + 3 * e, T.nodes[umid[u]].com, d);
+      if (sqrt(v_dot(d, d)) < rcut) {
+        memcpy(sub + 3 * ns, upos + 3 * u, sizeof(double) * 3);
+        ++ns;
+      }
+    }
+    branch[e] = ora_node_h(pos + 3 * e, s[e], ns, sub, hfact, eps, &h[e], NULL);
+    free(sub);
+  }
+  stats_out[0] = T.n_nodes;
+  stats_out[1] = nu;
+  stats_out[2] = kmid;
+  stats_out[3] = n_pseudo;
+  *s_root_out = n > 0 ? sqrt(T.nodes[0].s2) : 0.0;
+  const int64_t n_out = E.n;
+  free(umid);
+  free(upos);
+  free(E.unit_node);
+  free(E.entry_node);
+  free(open_sorted);
+  free(T.order);
+  free(T.tmp);
+  free(T.nodes);
+  return n_out;
+}

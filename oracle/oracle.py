@@ -68,6 +68,9 @@ def _lib():
         L.ora_underresolved.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, vp]
         L.ora_voronoi.restype = ctypes.c_int
         L.ora_voronoi.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.ora_kd_build.restype = i64
+        L.ora_kd_build.argtypes = ([i64, vp, vp, vp, i32, vp, dbl, dbl, dbl, dbl, dbl, i32, i32, i64, i32, i64, i64, vp]
+                                   + [vp] * 13)
         L.ora_voronoi_cells.restype = None
         L.ora_voronoi_cells.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp]
         L.ora_lloyd.restype = None
@@ -324,3 +327,37 @@ def voronoi_cells(gen, cells, box_lo=(0.0, 0.0, 0.0), box_hi=(1.0, 1.0, 1.0)):
                              _p(cells), _p(vol), _p(cen))
     return vol, cen
 
+
+
+def kd_build(pos, m, h, sources, r_part=0.2, r_leaf=None, theta=0.5, hfact=1.2, eps=1e-2, leaf_split=10,
+             max_depth=62, nf_threshold=10_000, up_levels=1, bypass=1_000_000, open_labels=None):
+    """Pseudo-particles from the paper's k-d tree (Sec. 2.2.1, 2.4): the
+    entries in emission order, each with its node's label and level, the
+    owner of every particle, and stats (nodes, units, k_mid or -1 when all
+    units are summed, pseudo-particles)."""
+    pos, m, h = _c(pos, np.float64), _c(m, np.float64), _c(h, np.float64)
+    src = _c(np.asarray(sources, float).reshape(-1, 3), np.float64)
+    n = pos.shape[0]
+    r_leaf = r_part if r_leaf is None else r_leaf
+    kind = np.empty(n, dtype=np.int32)
+    first = np.empty(n, dtype=np.int64)
+    count = np.empty(n, dtype=np.int64)
+    opos = np.empty((n, 3))
+    mass = np.empty(n)
+    oh = np.empty(n)
+    s = np.empty(n)
+    branch = np.empty(n, dtype=np.int32)
+    label = np.empty(n, dtype=np.uint64)
+    level = np.empty(n, dtype=np.int32)
+    owner = np.empty(n, dtype=np.int64)
+    st = np.zeros(4, dtype=np.int64)
+    sroot = np.zeros(1)
+    op = np.ascontiguousarray(np.asarray(open_labels if open_labels is not None else [], dtype=np.uint64))
+    k = int(_lib().ora_kd_build(n, _p(pos), _p(m), _p(h), src.shape[0], _p(src), r_part, r_leaf, theta, hfact, eps,
+                                leaf_split, max_depth, nf_threshold, up_levels, bypass, len(op), _p(op), _p(kind),
+                                _p(first), _p(count), _p(opos), _p(mass), _p(oh), _p(s), _p(branch), _p(label),
+                                _p(level), _p(owner), _p(st), _p(sroot)))
+    return dict(kind=kind[:k], first=first[:k], count=count[:k], pos=opos[:k], mass=mass[:k], h=oh[:k], s=s[:k],
+                branch=branch[:k], label=label[:k], level=level[:k], owner=owner,
+                stats=dict(n_nodes=int(st[0]), n_units=int(st[1]), k_mid=int(st[2]), n_pseudo=int(st[3])),
+                s_root=float(sroot[0]))
