@@ -313,6 +313,46 @@ int build_pseudo_particles_open(sphmap_ctx *ctx, int64_t n, const double *d_xyz,
                                 int32_t *d_out_branch, uint64_t *d_out_label, int64_t *d_out_owner,
                                 int64_t *n_out, sphmap_pseudo_stats *stats, void *stream);
 
+/* Pseudo-particles from the paper's own binary k-d tree (Sec. 2.2.1, 2.4).
+ * Tree: recursive coordinate bisection of the unit cube, each node's domain
+ * split through the centre of mass of its particles along the domain's
+ * longest axis (first such axis on a tie; particles below the split go
+ * left), until a node holds fewer than leaf_split particles, reaches
+ * max_depth (<= 62) or a split would leave one side empty.  Centres of mass
+ * are exact sums of m and m x rounded to fixed point 2^-K (K = 62 - the
+ * binary exponent of n * max m), so the tree does not depend on summation
+ * order.  Labels: root 1, children of n: 2n (left), 2n + 1 (right).
+ * Walk (Sec. 2.4.1): per source, with r = |com - source| and s the node
+ * size, a node reaches r_part when r - s <= r_part, r_leaf when
+ * r - s <= r_leaf, and fails the opening angle when theta^2 r^2 < s^2;
+ * accepted when none holds for any source and it is not in d_open_labels.
+ * Emitted: accepted nodes (one particle: as itself), and leaves not
+ * accepted: their particles (own h) when reaching r_part, named or single,
+ * else the leaf as a pseudo-particle (the r_leaf annulus).
+ * Node h: as build_pseudo_particles, over all units, or with more than
+ * nf_threshold units over the trial neighbours of the k_mid neighbour-find
+ * (Sec. 2.4.3): k_mid one level above the highest unit; r_cut = sqrt(3)
+ * s(ancestor on k_mid), or 4 h_fact s(ancestor up_levels above) when that is
+ * below 4 h_fact s (eq. compact_support_radius); trial neighbours: the units
+ * whose k_mid ancestor's centre of mass lies within r_cut.
+ * Arguments and outputs as build_pseudo_particles_open (opts->leaf_max is
+ * unused), plus d_out_level [capacity] (nullable, each entry's node level)
+ * and *k_mid (nullable: the level used, -1 when all units were summed).
+ * Errors: EINVAL also for non-positive or non-finite masses. */
+typedef struct {
+  double r_leaf;          /* >= r_part for the annulus (= r_part: none)      */
+  int32_t leaf_split;     /* split nodes holding at least this many (10)      */
+  int32_t up_levels;      /* ancestor levels for the r_2h fallback (1)        */
+  int64_t nf_threshold;   /* neighbour-find above this many units (10^4)      */
+} sphmap_kd_opts;
+int build_pseudo_particles_kd(sphmap_ctx *ctx, int64_t n, const double *d_xyz, const double *d_h, const double *d_m,
+                              int32_t n_src, const double *h_sources, const sphmap_pseudo_opts *opts,
+                              const sphmap_kd_opts *kd, int64_t n_open, const uint64_t *d_open_labels,
+                              int64_t capacity, double *d_out_xyz, double *d_out_h, double *d_out_m, double *d_out_s,
+                              int32_t *d_out_kind, int64_t *d_out_first, int64_t *d_out_count, int32_t *d_out_branch,
+                              uint64_t *d_out_label, int32_t *d_out_level, int64_t *d_out_owner, int64_t *n_out,
+                              sphmap_pseudo_stats *stats, int32_t *k_mid, void *stream);
+
 /* Resolution check of the adaptive walk (eq. resol_param, Sec. 2.4.1): a
  * pseudo-particle (kind 1) of size s whose neutral fraction f is below
  * f_neu,limit = (1/K) (K - 1 / (s / s_root)) is under-resolved.  Inputs are
@@ -352,7 +392,7 @@ int interpolate_to_particles(sphmap_ctx *ctx, int64_t n, const double *d_xyz, co
  * Kernel timing: when enabled, HIP events are recorded on the launch stream
  * around each launch of the named kernels ("exact_integral", "exact_redo",
  * "pair_fill", "pair_count", "cell_reduce", "reverse", "transpose",
- * "node_hsolve", "interp", "voronoi_lloyd", "voronoi_count",
+ * "node_hsolve", "kd_build", "interp", "voronoi_lloyd", "voronoi_count",
  * "voronoi_faces").
  * sphmap_kernel_time synchronises on the recorded events and returns the
  * summed milliseconds and the number of launches since the last reset.

@@ -359,13 +359,23 @@ def map_cells_to_particles(ctx: Context, pairs: Pairs, cell_values, out=None, st
 
 
 def build_pseudo_particles(ctx: Context, xyz, h, m, sources, r_part: float = 0.2, theta: float = 0.5,
-                           h_fact: float = 1.2, eps_h: float = 1e-2, leaf_max: int = 8, max_depth: int = 21,
-                           bypass_threshold: int = 1_000_000, open_labels=None, stream=None) -> dict:
+                           h_fact: float = 1.2, eps_h: float = 1e-2, leaf_max: int = 8, max_depth: int | None = None,
+                           bypass_threshold: int = 1_000_000, open_labels=None, tree: str = "octree",
+                           r_leaf: float | None = None, leaf_split: int = 10, nf_threshold: int = 10_000,
+                           up_levels: int = 1, stream=None) -> dict:
     """Tree-node pseudo-particles and their smoothing lengths (Sec. 2.4).
-    open_labels: node labels to open whatever the walk criterion says (the
-    failed nodes of an earlier walk).  Returns a dict of device tensors in
-    emission order (with each entry's node 'label'), 'owner' (for every
-    input particle, the entry that holds it) and 'stats'."""
+    tree: "octree" (cubic subdivision, at most leaf_max per leaf) or "kd"
+    (the paper's k-d tree: recursive coordinate bisection, split while
+    holding leaf_split or more; r_leaf annulus; k_mid neighbour-find above
+    nf_threshold units).  open_labels: node labels to open whatever the walk
+    criterion says (the failed nodes of an earlier walk).  Returns a dict of
+    device tensors in emission order (with each entry's node 'label', and
+    'level' for the k-d tree), 'owner' (for every input particle, the entry
+    that holds it) and 'stats'."""
+    if tree not in ("octree", "kd"):
+        raise ValueError("tree must be 'octree' or 'kd'")
+    if max_depth is None:
+        max_depth = 21 if tree == "octree" else 62
     import numpy as np
     torch = _torch()
     dev = ctx.device
@@ -392,16 +402,28 @@ def build_pseudo_particles(ctx: Context, xyz, h, m, sources, r_part: float = 0.2
         ol = None
     n_out = ctypes.c_int64()
     st = _native.PseudoStats()
-    ctx.check(_native.lib().build_pseudo_particles_open(
-        ctx.handle, n, _ptr(xyz), _ptr(h), _ptr(m), src.shape[0], src.ctypes.data_as(ctypes.c_void_p),
-        ctypes.byref(opts), 0 if ol is None else ol.shape[0], _ptr(ol), cap, _ptr(o["xyz"]), _ptr(o["h"]),
-        _ptr(o["m"]), _ptr(o["s"]), _ptr(o["kind"]), _ptr(o["first"]), _ptr(o["count"]), _ptr(o["branch"]),
-        _ptr(o["label"]), _ptr(owner), ctypes.byref(n_out), ctypes.byref(st), _stream_handle(stream)))
+    k_mid = ctypes.c_int32(-1)
+    if tree == "octree":
+        ctx.check(_native.lib().build_pseudo_particles_open(
+            ctx.handle, n, _ptr(xyz), _ptr(h), _ptr(m), src.shape[0], src.ctypes.data_as(ctypes.c_void_p),
+            ctypes.byref(opts), 0 if ol is None else ol.shape[0], _ptr(ol), cap, _ptr(o["xyz"]), _ptr(o["h"]),
+            _ptr(o["m"]), _ptr(o["s"]), _ptr(o["kind"]), _ptr(o["first"]), _ptr(o["count"]), _ptr(o["branch"]),
+            _ptr(o["label"]), _ptr(owner), ctypes.byref(n_out), ctypes.byref(st), _stream_handle(stream)))
+    else:
+        o["level"] = torch.empty(cap, dtype=torch.int32, device=dev)
+        kd = _native.KdOpts(float(r_part if r_leaf is None else r_leaf), int(leaf_split), int(up_levels),
+                            int(nf_threshold))
+        ctx.check(_native.lib().build_pseudo_particles_kd(
+            ctx.handle, n, _ptr(xyz), _ptr(h), _ptr(m), src.shape[0], src.ctypes.data_as(ctypes.c_void_p),
+            ctypes.byref(opts), ctypes.byref(kd), 0 if ol is None else ol.shape[0], _ptr(ol), cap, _ptr(o["xyz"]),
+            _ptr(o["h"]), _ptr(o["m"]), _ptr(o["s"]), _ptr(o["kind"]), _ptr(o["first"]), _ptr(o["count"]),
+            _ptr(o["branch"]), _ptr(o["label"]), _ptr(o["level"]), _ptr(owner), ctypes.byref(n_out),
+            ctypes.byref(st), ctypes.byref(k_mid), _stream_handle(stream)))
     k = n_out.value
     res = {key: val[:k] for key, val in o.items()}
     res["owner"] = owner
     res["stats"] = dict(n_nodes=st.n_nodes, n_units=st.n_units, n_pseudo=st.n_pseudo, n_real=st.n_real,
-                        branch_count=list(st.branch_count), s_root=st.s_root)
+                        branch_count=list(st.branch_count), s_root=st.s_root, k_mid=k_mid.value)
     return res
 
 

@@ -21,7 +21,7 @@ EXPORTS = [
     "map_particles_to_cells", "map_particles_to_cells_batch", "sphmap_pairs_info", "sphmap_pairs_export", "sphmap_pairs_free",
     "map_cells_to_particles", "build_pseudo_particles", "build_pseudo_particles_open", "select_underresolved",
     "interpolate_to_particles", "sphmap_sync_status", "sphmap_estimate_footprint",
-    "sphmap_tess_build_voronoi", "sphmap_tess_counts", "sphmap_tess_export",
+    "sphmap_tess_build_voronoi", "sphmap_tess_counts", "sphmap_tess_export", "build_pseudo_particles_kd",
     "sphmap_set_timing", "sphmap_kernel_time", "sphmap_reset_timing",
     "sphmap_set_counting", "sphmap_work_counters", "sphmap_set_autotune", "sphmap_tuned_shape",
 ]
@@ -36,6 +36,11 @@ class PseudoOpts(ctypes.Structure):
 class PseudoStats(ctypes.Structure):
     _fields_ = [("n_nodes", ctypes.c_int64), ("n_units", ctypes.c_int64), ("n_pseudo", ctypes.c_int64),
                 ("n_real", ctypes.c_int64), ("branch_count", ctypes.c_int64 * 4), ("s_root", ctypes.c_double)]
+
+
+class KdOpts(ctypes.Structure):
+    _fields_ = [("r_leaf", ctypes.c_double), ("leaf_split", ctypes.c_int32), ("up_levels", ctypes.c_int32),
+                ("nf_threshold", ctypes.c_int64)]
 
 
 class Footprint(ctypes.Structure):
@@ -98,6 +103,11 @@ def lib():
         L.select_underresolved.restype = ctypes.c_int
         L.select_underresolved.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.c_double, ctypes.c_double, vp,
                                            ctypes.POINTER(i64), vp]
+        L.build_pseudo_particles_kd.restype = ctypes.c_int
+        L.build_pseudo_particles_kd.argtypes = ([vp, i64, vp, vp, vp, i32, vp, ctypes.POINTER(PseudoOpts),
+                                                 ctypes.POINTER(KdOpts), i64, vp, i64] + [vp] * 11
+                                                + [ctypes.POINTER(i64), ctypes.POINTER(PseudoStats),
+                                                   ctypes.POINTER(i32), vp])
         L.sphmap_tess_build_voronoi.restype = ctypes.c_int
         L.sphmap_tess_build_voronoi.argtypes = [vp, i64, vp, vp, vp, i32, vp, vp, ctypes.POINTER(vp)]
         L.sphmap_tess_counts.restype = ctypes.c_int

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsphmap.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["prim.hip", "tess.hip", "pairs.hip", "exact.hip", "reduce.hip", "pseudo.hip", "interp.hip", "voronoi.hip",
+SOURCES = ["prim.hip", "tess.hip", "pairs.hip", "exact.hip", "reduce.hip", "pseudo.hip", "kdtree.hip", "interp.hip", "voronoi.hip",
            "abi.hip"]
 ARCH = os.environ.get("SPHMAP_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -433,6 +433,59 @@ int build_pseudo_particles(sphmap_ctx *ctx, int64_t n, const double *d_xyz, cons
                                      d_out_branch, nullptr, nullptr, n_out, stats, stream);
 }
 
+int build_pseudo_particles_kd(sphmap_ctx *ctx, int64_t n, const double *d_xyz, const double *d_h, const double *d_m,
+                              int32_t n_src, const double *h_sources, const sphmap_pseudo_opts *opts,
+                              const sphmap_kd_opts *kd, int64_t n_open, const uint64_t *d_open_labels,
+                              int64_t capacity, double *d_out_xyz, double *d_out_h, double *d_out_m, double *d_out_s,
+                              int32_t *d_out_kind, int64_t *d_out_first, int64_t *d_out_count, int32_t *d_out_branch,
+                              uint64_t *d_out_label, int32_t *d_out_level, int64_t *d_out_owner, int64_t *n_out,
+                              sphmap_pseudo_stats *stats, int32_t *k_mid, void *stream) {
+  if (!ctx) return SPHMAP_EINVAL;
+  return guarded(ctx, [&] {
+    SPH_REQUIRE(n >= 1 && n < ((int64_t)1 << 30), SPHMAP_EINVAL, "n out of range [1, 2^30)");
+    SPH_REQUIRE(d_xyz && d_h && d_m, SPHMAP_EINVAL, "null particle array");
+    SPH_REQUIRE(n_src >= 1 && h_sources, SPHMAP_EINVAL, "at least one source is required");
+    SPH_REQUIRE(opts && kd, SPHMAP_EINVAL, "null options");
+    SPH_REQUIRE(opts->theta >= 0 && opts->h_fact > 0 && opts->eps_h > 0 && opts->r_part >= 0, SPHMAP_EINVAL,
+                "bad option value");
+    SPH_REQUIRE(d_out_xyz && d_out_h && d_out_m && n_out, SPHMAP_EINVAL, "null required output");
+    SPH_REQUIRE(n_open >= 0 && (n_open == 0 || d_open_labels), SPHMAP_EINVAL, "null open-label list");
+    sphmap::KdArgs k;
+    sphmap::PseudoArgs &a = k.base;
+    a.n = n;
+    a.xyz = d_xyz;
+    a.h = d_h;
+    a.m = d_m;
+    a.n_src = n_src;
+    a.src = h_sources;
+    a.opts = *opts;
+    a.capacity = capacity;
+    a.o_xyz = d_out_xyz;
+    a.o_h = d_out_h;
+    a.o_m = d_out_m;
+    a.o_s = d_out_s;
+    a.o_kind = d_out_kind;
+    a.o_first = d_out_first;
+    a.o_count = d_out_count;
+    a.o_branch = d_out_branch;
+    a.o_label = d_out_label;
+    a.o_owner = d_out_owner;
+    a.n_open = n_open;
+    a.open_labels = d_open_labels;
+    a.n_out = 0;
+    std::memset(&a.stats, 0, sizeof a.stats);
+    k.r_leaf = kd->r_leaf;
+    k.leaf_split = kd->leaf_split;
+    k.up_levels = kd->up_levels;
+    k.nf_threshold = kd->nf_threshold;
+    k.o_level = d_out_level;
+    sphmap::kd_pseudo_build(ctx->c, k, as_stream(stream));
+    *n_out = a.n_out;
+    if (stats) *stats = a.stats;
+    if (k_mid) *k_mid = k.k_mid;
+  });
+}
+
 int select_underresolved(sphmap_ctx *ctx, int64_t n, const int32_t *d_kind, const uint64_t *d_label,
                          const double *d_s, const double *d_fneu, double s_root, double K, uint64_t *d_out_labels,
                          int64_t *n_found, void *stream) {

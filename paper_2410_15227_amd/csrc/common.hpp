@@ -242,6 +242,22 @@ struct PseudoArgs {
   sphmap_pseudo_stats stats;
 };
 void pseudo_build(Ctx &ctx, PseudoArgs &a, hipStream_t s);
+// node smoothing lengths of the np pseudo-particles plist (entries) over the
+// nu units upos; n_mid > 0: trial neighbours from the k_mid neighbour-find
+void node_hsolve(Ctx &ctx, int64_t np, const int32_t *plist, int64_t nu, const double4 *upos, const double *o_xyz,
+                 const double *o_s, double hfact, double eps, int64_t bypass, double *o_h, int32_t *o_branch,
+                 unsigned long long *bcount, int64_t n_mid, const double4 *mid_com, const int32_t *mid_u0,
+                 const int32_t *mid_u1, const double *rcut, hipStream_t s);
+// pseudo-particles from the k-d tree (recursive coordinate bisection)
+struct KdArgs {
+  PseudoArgs base;  // opts.leaf_max unused; max_depth up to 62
+  double r_leaf;
+  int32_t leaf_split, up_levels;
+  int64_t nf_threshold;
+  int32_t *o_level = nullptr;
+  int32_t k_mid = -1;
+};
+void kd_pseudo_build(Ctx &ctx, KdArgs &a, hipStream_t s);
 // labels of under-resolved pseudo-particles (eq. resol_param), entry order
 int64_t select_underresolved(Ctx &ctx, int64_t n, const int32_t *kind, const uint64_t *label, const double *s_node,
                              const double *fneu, double s_root, double K, uint64_t *out, hipStream_t s);

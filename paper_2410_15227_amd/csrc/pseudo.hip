@@ -438,10 +438,16 @@ constexpr int kHWaves = 4;  // pseudo-particles per workgroup
 // bisection step needs the sums over all units within 2h; the 64 lanes
 // evaluate 64 consecutive units at a time and the terms that are not zero
 // are added in unit order, so the sums are those of a plain sequential loop.
+// With n_mid > 0 the sums run over trial neighbours only: the units of the
+// ranges [mid_u0, mid_u1) of the k_mid nodes whose centres of mass lie
+// within rcut[e] of the target (the ranges follow unit order, so the terms
+// are still added in unit order).
 __global__ void __launch_bounds__(64 * kHWaves) k_hsolve(int64_t np, const int32_t *plist, int64_t nu,
                                                         const double4 *upos, const double *o_xyz, const double *o_s,
                                                         double hfact, double eps, int64_t bypass, double *o_h,
-                                                        int32_t *o_branch, unsigned long long *bcount) {
+                                                        int32_t *o_branch, unsigned long long *bcount, int64_t n_mid,
+                                                        const double4 *mid_com, const int32_t *mid_u0,
+                                                        const int32_t *mid_u1, const double *rcut) {
 #pragma clang fp contract(off)
   const int64_t pid = (int64_t)blockIdx.x * kHWaves + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -467,26 +473,49 @@ __global__ void __launch_bounds__(64 * kHWaves) k_hsolve(int64_t np, const int32
     else if (phase == 3) he = 0.5 * (lo + hi);
     const double ih = 1.0 / he;
     double sw = 0.0, sd = 0.0;
-    for (int64_t b0 = 0; b0 < nu; b0 += 64) {
-      const int64_t u = b0 + lane;
-      double w = 0.0, dt = 0.0;
-      bool hit = false;
-      if (u < nu) {
-        const double4 p = upos[u];
-        const double dx = ax - p.x, dy = ay - p.y, dz = az - p.z;
-        const double qq = sqrt((dx * dx + dy * dy) + dz * dz) * ih;
-        if (qq < 2.0) {
-          hit = true;
-          w = m4w(qq);
-          dt = -(3.0 * w + qq * m4dw(qq));
+    // units [u0, u1) in tiles of 64; non-zero terms added in unit order
+    auto tile_sums = [&](int64_t u0, int64_t u1) {
+      for (int64_t b0 = u0; b0 < u1; b0 += 64) {
+        const int64_t u = b0 + lane;
+        double w = 0.0, dt = 0.0;
+        bool hit = false;
+        if (u < u1) {
+          const double4 p = upos[u];
+          const double dx = ax - p.x, dy = ay - p.y, dz = az - p.z;
+          const double qq = sqrt((dx * dx + dy * dy) + dz * dz) * ih;
+          if (qq < 2.0) {
+            hit = true;
+            w = m4w(qq);
+            dt = -(3.0 * w + qq * m4dw(qq));
+          }
+        }
+        uint64_t mask = __ballot(hit);
+        while (mask) {
+          const int j = __builtin_ctzll(mask);
+          mask &= mask - 1;
+          sw += readlane_d(w, j);
+          sd += readlane_d(dt, j);
         }
       }
-      uint64_t mask = __ballot(hit);
-      while (mask) {
-        const int j = __builtin_ctzll(mask);
-        mask &= mask - 1;
-        sw += readlane_d(w, j);
-        sd += readlane_d(dt, j);
+    };
+    if (n_mid == 0) {
+      tile_sums(0, nu);
+    } else {
+      const double rc = rcut[e];
+      for (int64_t m0 = 0; m0 < n_mid; m0 += 64) {
+        const int64_t mi = m0 + lane;
+        bool flag = false;
+        if (mi < n_mid) {
+          const double4 c = mid_com[mi];
+          const double dx = ax - c.x, dy = ay - c.y, dz = az - c.z;
+          flag = sqrt((dx * dx + dy * dy) + dz * dz) < rc;
+        }
+        uint64_t fm = __ballot(flag);
+        while (fm) {
+          const int j = __builtin_ctzll(fm);
+          fm &= fm - 1;
+          tile_sums(mid_u0[m0 + j], mid_u1[m0 + j]);
+        }
       }
     }
     const double n = sw * ih * ih * ih * kInvPi;
@@ -586,6 +615,19 @@ struct Grow {
 };
 
 }  // namespace
+
+void node_hsolve(Ctx &ctx, int64_t np, const int32_t *plist, int64_t nu, const double4 *upos, const double *o_xyz,
+                 const double *o_s, double hfact, double eps, int64_t bypass, double *o_h, int32_t *o_branch,
+                 unsigned long long *bcount, int64_t n_mid, const double4 *mid_com, const int32_t *mid_u0,
+                 const int32_t *mid_u1, const double *rcut, hipStream_t s) {
+  if (np <= 0) return;
+  KernelTimer kt(&ctx, "node_hsolve", s);
+  k_hsolve<<<(unsigned)div_up(np, kHWaves), 64 * kHWaves, 0, s>>>(np, plist, nu, upos, o_xyz, o_s, hfact, eps, bypass,
+                                                                o_h, o_branch, bcount, n_mid, mid_com, mid_u0, mid_u1,
+                                                                rcut);
+  SPH_LAUNCH_CHECK();
+  kt.done();
+}
 
 void pseudo_build(Ctx &ctx, PseudoArgs &a, hipStream_t s) {
   Arena &ar = ctx.arena;
@@ -740,7 +782,8 @@ void pseudo_build(Ctx &ctx, PseudoArgs &a, hipStream_t s) {
   if (np > 0) {
     KernelTimer kt(&ctx, "node_hsolve", s);
     k_hsolve<<<(unsigned)div_up(np, kHWaves), 64 * kHWaves, 0, s>>>(np, plist, nu, upos, a.o_xyz, o_s, o.h_fact, o.eps_h,
-                                                                o.bypass_threshold, a.o_h, a.o_branch, bcount);
+                                                                o.bypass_threshold, a.o_h, a.o_branch, bcount, 0,
+                                                                nullptr, nullptr, nullptr, nullptr);
     SPH_LAUNCH_CHECK();
     kt.done();
   }
