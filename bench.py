@@ -83,6 +83,8 @@ def main():
                          "to tree-node pseudo-particles around the densest particle, mapped on the mixed set's grid; "
                          "batch: 64 independent instances of 2^12..2^18 particles in one batched call; "
                          "serve: Poisson arrivals of mapping jobs through the continuous-batching server")
+    ap.add_argument("--tree", default="octree", choices=["octree", "kd"], help="pseudo: tree of the builder")
+    ap.add_argument("--r-leaf", type=float, default=None, help="pseudo, k-d tree: r_leaf (default r_part)")
     ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: mean arrival rate (requests/s)")
     ap.add_argument("--slots", type=int, default=4, help="serve: concurrent jobs on the device")
@@ -280,6 +282,8 @@ def run_pseudo(args):
     hd = torch.tensor(h, dtype=torch.float64, device=dev)
     md = torch.tensor(m, dtype=torch.float64, device=dev)
     opts = dict(r_part=0.2, theta=0.5, h_fact=1.2, eps_h=1e-2)
+    if args.tree == "kd":
+        opts.update(tree="kd", r_leaf=args.r_leaf if args.r_leaf is not None else 0.2)
 
     def build():
         return pkg.build_pseudo_particles(ctx, xyz, hd, md, [src], **opts)
@@ -365,9 +369,11 @@ def run_pseudo(args):
         "vs_baseline": None,
         "dtype": "f32+f64" if args.precision == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"pseudo_{n_all}", "n_particles": n_all, "precision": args.precision,
-                   "sigma_lnrho": 1.5, "r_part": 0.2, "theta": 0.5, "h_fact": 1.2, "eps_h": 1e-2},
+        "config": {"workload": f"pseudo_{n_all}" + ("_kd" if args.tree == "kd" else ""), "n_particles": n_all,
+                   "precision": args.precision, "sigma_lnrho": 1.5, "tree": args.tree,
+                   **{k: v for k, v in opts.items() if k != "tree"}},
         "pseudo": {"n_mixed": n_mix, "n_pseudo": ps["stats"]["n_pseudo"], "n_real": ps["stats"]["n_real"],
+                   "n_units": ps["stats"]["n_units"], "k_mid": ps["stats"].get("k_mid", -1),
                    "n_nodes": ps["stats"]["n_nodes"], "h_branches": ps["stats"]["branch_count"],
                    "pairs_all": int(pairs_all), "pairs_mixed": int(pairs_mix),
                    "pair_reduction": round(pairs_all / max(pairs_mix, 1), 3),

@@ -80,19 +80,45 @@ __global__ void k_kd_zero(int64_t b, int64_t e, KdNodes N) {
   N.s2[k] = 0ull;
 }
 
-__global__ void k_kd_sums(int64_t n, const int32_t *perm, const int32_t *nop, int64_t b, int64_t e,
-                          const double *xyz, const double *m, int K, KdNodes N) {
+// Levels with at most kLdsNodes nodes (the top of the tree, where every
+// particle of the level adds to a handful of nodes) accumulate per
+// workgroup in LDS first; integer sums and maxima do not depend on how the
+// additions are grouped.
+constexpr int kLdsNodes = 1024;
+
+__global__ void __launch_bounds__(256) k_kd_sums(int64_t n, const int32_t *perm, const int32_t *nop, int64_t b,
+                                                 int64_t e, const double *xyz, const double *m, int K, KdNodes N) {
 #pragma clang fp contract(off)
+  __shared__ unsigned long long acc[4 * kLdsNodes];
+  const bool lds = e - b <= kLdsNodes;
+  if (lds) {
+    for (int t = threadIdx.x; t < 4 * (e - b); t += blockDim.x) acc[t] = 0ull;
+    __syncthreads();
+  }
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t node = nop[i];
-  if (node < b || node >= e) return;
-  const int64_t j = perm[i];
-  const double mj = m[j];
-  unsigned long long *q = (unsigned long long *)N.q + 4 * node;
-  atomicAdd(q, (unsigned long long)__double2ll_rn(ldexp(mj, K)));
-  for (int k = 0; k < 3; ++k)
-    atomicAdd(q + 1 + k, (unsigned long long)__double2ll_rn(ldexp(mj * xyz[3 * j + k], K)));
+  int64_t node = -1;
+  if (i < n) {
+    node = nop[i];
+    if (node < b || node >= e) node = -1;
+  }
+  if (node >= 0) {
+    const int64_t j = perm[i];
+    const double mj = m[j];
+    unsigned long long v[4];
+    v[0] = (unsigned long long)__double2ll_rn(ldexp(mj, K));
+    for (int k = 0; k < 3; ++k) v[1 + k] = (unsigned long long)__double2ll_rn(ldexp(mj * xyz[3 * j + k], K));
+    if (lds) {
+      for (int k = 0; k < 4; ++k) atomicAdd(&acc[4 * (node - b) + k], v[k]);
+    } else {
+      unsigned long long *q = (unsigned long long *)N.q + 4 * node;
+      for (int k = 0; k < 4; ++k) atomicAdd(q + k, v[k]);
+    }
+  }
+  if (lds) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < 4 * (e - b); t += blockDim.x)
+      if (acc[t]) atomicAdd((unsigned long long *)N.q + 4 * b + t, acc[t]);
+  }
 }
 
 __global__ void k_kd_com(int64_t b, int64_t e, int K, int leaf_split, int max_depth, KdNodes N) {
@@ -122,23 +148,38 @@ __global__ void k_kd_com(int64_t b, int64_t e, int K, int leaf_split, int max_de
   N.left[k] = -1;
 }
 
-__global__ void k_kd_size_flags(int64_t n, const int32_t *perm, const int32_t *nop, int64_t b, int64_t e,
-                                const double *xyz, KdNodes N, int64_t *flag) {
+__global__ void __launch_bounds__(256) k_kd_size_flags(int64_t n, const int32_t *perm, const int32_t *nop,
+                                                       int64_t b, int64_t e, const double *xyz, KdNodes N,
+                                                       int64_t *flag) {
 #pragma clang fp contract(off)
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t node = nop[i];
-  int64_t f = 0;
-  if (node >= b && node < e) {
-    const int64_t j = perm[i];
-    const double4 c = N.com[node];
-    const double dx = xyz[3 * j] - c.x, dy = xyz[3 * j + 1] - c.y, dz = xyz[3 * j + 2] - c.z;
-    const double d2 = (dx * dx + dy * dy) + dz * dz;
-    atomicMax(&N.s2[node], (unsigned long long)__double_as_longlong(d2));
-    const int a = N.axis[node];
-    if (a >= 0) f = xyz[3 * j + a] < N.split[node] ? 1 : 0;
+  __shared__ unsigned long long mx[kLdsNodes];
+  const bool lds = e - b <= kLdsNodes;
+  if (lds) {
+    for (int t = threadIdx.x; t < e - b; t += blockDim.x) mx[t] = 0ull;
+    __syncthreads();
   }
-  flag[i] = f;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const int64_t node = nop[i];
+    int64_t f = 0;
+    if (node >= b && node < e) {
+      const int64_t j = perm[i];
+      const double4 c = N.com[node];
+      const double dx = xyz[3 * j] - c.x, dy = xyz[3 * j + 1] - c.y, dz = xyz[3 * j + 2] - c.z;
+      const double d2 = (dx * dx + dy * dy) + dz * dz;
+      const unsigned long long bits = (unsigned long long)__double_as_longlong(d2);
+      if (lds) atomicMax(&mx[node - b], bits);
+      else atomicMax(&N.s2[node], bits);
+      const int a = N.axis[node];
+      if (a >= 0) f = xyz[3 * j + a] < N.split[node] ? 1 : 0;
+    }
+    flag[i] = f;
+  }
+  if (lds) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < e - b; t += blockDim.x)
+      if (mx[t]) atomicMax(&N.s2[b + t], mx[t]);
+  }
 }
 
 // children per splitting node: 2 when both sides are non-empty
