@@ -380,14 +380,14 @@ void ora_pairs_weights(int64_t n_cells, const double *gen, const double *vert, c
     int64_t cnt = 0;
     for (int64_t i = 0; i < n_part; ++i) {
       if (!canon_pair(xyz + 3 * i, h[i], g, R)) continue;
-      if (w) {
+      if (idx) {
         int64_t o = offsets[k] + cnt;
         idx[o] = (int32_t)i;
-        w[o] = cell_weight(&T, c, xyz + 3 * i, h[i]);
+        if (w) w[o] = cell_weight(&T, c, xyz + 3 * i, h[i]);
       }
       ++cnt;
     }
-    if (!w) counts[k] = cnt;
+    if (!idx) counts[k] = cnt;
   }
 }
 

@@ -147,6 +147,24 @@ def cell_info(t, cells=None):
     return vol, rad
 
 
+def pair_lists(t, pos, h, cells=None):
+    """Canonical candidate pairs of the listed cells without weights:
+    (offsets[len(cells)+1], particle idx)."""
+    cells = np.arange(t.n_cells, dtype=np.int64) if cells is None else _c(cells, np.int64)
+    pos = _c(pos, np.float64)
+    h = _c(h, np.float64)
+    L = _lib()
+    counts = np.zeros(len(cells), dtype=np.int64)
+    L.ora_pairs_weights(*_tess_args(t), pos.shape[0], _p(pos), _p(h), len(cells), _p(cells), _p(counts),
+                        None, None, None)
+    off = np.zeros(len(cells) + 1, dtype=np.int64)
+    np.cumsum(counts, out=off[1:])
+    idx = np.empty(int(off[-1]), dtype=np.int32)
+    L.ora_pairs_weights(*_tess_args(t), pos.shape[0], _p(pos), _p(h), len(cells), _p(cells), _p(counts),
+                        _p(off), _p(idx), None)
+    return off, idx
+
+
 def pairs_weights(t, pos, h, cells=None):
     """Canonical candidate pairs of the listed cells with their weights:
     (offsets[len(cells)+1], particle idx, w)."""
