@@ -125,63 +125,85 @@ __global__ void __launch_bounds__(128) k_pairs(Hier H, int64_t C, const int32_t 
   if (!kFill) counts[c] = cnt;
 }
 
-// Sort each cell's particle list ascending (bitonic in LDS for lists up to
-// kSortCap entries; longer lists by a single-lane heap sort).
+// Sort each cell's particle list ascending: lists of up to kSortCap entries
+// by a bitonic sort in LDS; longer lists (large cells of a mixed set of
+// pseudo-particles) as kSortCap-entry runs sorted the same way, then merged
+// pairwise by the whole workgroup (merge path: each thread finds where its
+// share of the output starts by a binary search and merges it alone),
+// ping-ponging with a scratch copy of the list.  Particle indices within a
+// list are distinct, so the result does not depend on the method.
 constexpr int kSortCap = 4096;
 
-__global__ void __launch_bounds__(256) k_sort_segments(int64_t C, const int64_t *off, int32_t *pair_p) {
+__device__ void sort_run_lds(int32_t *buf, const int32_t *src, int32_t *dst, int n) {
+  int m = 2;
+  while (m < n) m <<= 1;
+  for (int k = threadIdx.x; k < m; k += blockDim.x) buf[k] = k < n ? src[k] : INT32_MAX;
+  __syncthreads();
+  for (int size = 2; size <= m; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int k = threadIdx.x; k < m; k += blockDim.x) {
+        int q = k ^ stride;
+        if (q > k) {
+          bool up = (k & size) == 0;
+          int32_t a = buf[k], b = buf[q];
+          if ((a > b) == up) {
+            buf[k] = b;
+            buf[q] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int k = threadIdx.x; k < n; k += blockDim.x) dst[k] = buf[k];
+  __syncthreads();
+}
+
+// merge sorted A[0, na) and B[0, nb) into out[0, na + nb), all threads
+__device__ void merge_block(const int32_t *A, int na, const int32_t *B, int nb, int32_t *out) {
+  const int total = na + nb;
+  const int per = (total + blockDim.x - 1) / blockDim.x;
+  const int d0 = min((int)threadIdx.x * per, total), d1 = min(d0 + per, total);
+  if (d0 >= d1) return;
+  // merge path: i elements of A and d0 - i of B come before output d0
+  int lo = max(0, d0 - nb), hi = min(d0, na);
+  while (lo < hi) {
+    const int i = (lo + hi) >> 1;
+    if (A[i] < B[d0 - 1 - i]) lo = i + 1;
+    else hi = i;
+  }
+  int i = lo, j = d0 - lo;
+  for (int d = d0; d < d1; ++d) {
+    if (j >= nb || (i < na && A[i] < B[j])) out[d] = A[i++];
+    else out[d] = B[j++];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_sort_segments(int64_t C, const int64_t *off, int32_t *pair_p, int32_t *tmp) {
   __shared__ int32_t buf[kSortCap];
   const int64_t c = blockIdx.x;
   const int64_t s = off[c], e = off[c + 1];
   const int n = (int)(e - s);
   if (n <= 1) return;
+  int32_t *a = pair_p + s;
   if (n <= kSortCap) {
-    int m = 2;
-    while (m < n) m <<= 1;
-    for (int k = threadIdx.x; k < m; k += blockDim.x) buf[k] = k < n ? pair_p[s + k] : INT32_MAX;
-    __syncthreads();
-    for (int size = 2; size <= m; size <<= 1) {
-      for (int stride = size >> 1; stride > 0; stride >>= 1) {
-        for (int k = threadIdx.x; k < m; k += blockDim.x) {
-          int q = k ^ stride;
-          if (q > k) {
-            bool up = (k & size) == 0;
-            int32_t a = buf[k], b = buf[q];
-            if ((a > b) == up) {
-              buf[k] = b;
-              buf[q] = a;
-            }
-          }
-        }
-        __syncthreads();
-      }
-    }
-    for (int k = threadIdx.x; k < n; k += blockDim.x) pair_p[s + k] = buf[k];
-  } else if (threadIdx.x == 0) {
-    int32_t *a = pair_p + s;
-    auto sift = [&](int root, int end) {
-      while (true) {
-        int ch = 2 * root + 1;
-        if (ch >= end) break;
-        if (ch + 1 < end && a[ch] < a[ch + 1]) ++ch;
-        if (a[root] < a[ch]) {
-          int32_t t = a[root];
-          a[root] = a[ch];
-          a[ch] = t;
-          root = ch;
-        } else {
-          break;
-        }
-      }
-    };
-    for (int st = n / 2 - 1; st >= 0; --st) sift(st, n);
-    for (int end = n - 1; end > 0; --end) {
-      int32_t t = a[0];
-      a[0] = a[end];
-      a[end] = t;
-      sift(0, end);
-    }
+    sort_run_lds(buf, a, a, n);
+    return;
   }
+  for (int r0 = 0; r0 < n; r0 += kSortCap) sort_run_lds(buf, a + r0, a + r0, min(kSortCap, n - r0));
+  int32_t *src = a, *dst = tmp + s;
+  for (int w = kSortCap; w < n; w <<= 1) {
+    for (int lo = 0; lo < n; lo += 2 * w) {
+      const int mid = min(lo + w, n), hi = min(lo + 2 * w, n);
+      merge_block(src + lo, mid - lo, src + mid, hi - mid, dst + lo);
+    }
+    __syncthreads();
+    int32_t *t = src;
+    src = dst;
+    dst = t;
+  }
+  if (src != a)
+    for (int k = threadIdx.x; k < n; k += blockDim.x) a[k] = src[k];
 }
 
 }  // namespace
@@ -253,7 +275,8 @@ void find_pairs(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, hipSt
     kt.done();
   }
   if (C > 0) {
-    k_sort_segments<<<(unsigned)C, 256, 0, s>>>(C, P.cell_off, P.pair_p);
+    int32_t *tmp = ar.get<int32_t>("pp_sort_tmp", std::max<int64_t>(total, 1));
+    k_sort_segments<<<(unsigned)C, 256, 0, s>>>(C, P.cell_off, P.pair_p, tmp);
     SPH_LAUNCH_CHECK();
   }
 }

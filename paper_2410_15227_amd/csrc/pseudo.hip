@@ -447,7 +447,8 @@ __global__ void __launch_bounds__(64 * kHWaves) k_hsolve(int64_t np, const int32
                                                         double hfact, double eps, int64_t bypass, double *o_h,
                                                         int32_t *o_branch, unsigned long long *bcount, int64_t n_mid,
                                                         const double4 *mid_com, const int32_t *mid_u0,
-                                                        const int32_t *mid_u1, const double *rcut) {
+                                                        const int32_t *mid_u1, const double *rcut,
+                                                        const double4 *tlo, const double4 *thi) {
 #pragma clang fp contract(off)
   const int64_t pid = (int64_t)blockIdx.x * kHWaves + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -473,31 +474,54 @@ __global__ void __launch_bounds__(64 * kHWaves) k_hsolve(int64_t np, const int32
     else if (phase == 3) he = 0.5 * (lo + hi);
     const double ih = 1.0 / he;
     double sw = 0.0, sd = 0.0;
-    // units [u0, u1) in tiles of 64; non-zero terms added in unit order
-    auto tile_sums = [&](int64_t u0, int64_t u1) {
-      for (int64_t b0 = u0; b0 < u1; b0 += 64) {
-        const int64_t u = b0 + lane;
-        double w = 0.0, dt = 0.0;
-        bool hit = false;
-        if (u < u1) {
-          const double4 p = upos[u];
-          const double dx = ax - p.x, dy = ay - p.y, dz = az - p.z;
-          const double qq = sqrt((dx * dx + dy * dy) + dz * dz) * ih;
-          if (qq < 2.0) {
-            hit = true;
-            w = m4w(qq);
-            dt = -(3.0 * w + qq * m4dw(qq));
-          }
+    // units [ua, ub) of one tile, one per lane
+    auto tile_one = [&](int64_t ua, int64_t ub) {
+      const int64_t u = ua + lane;
+      double w = 0.0, dt = 0.0;
+      bool hit = false;
+      if (u < ub) {
+        const double4 p = upos[u];
+        const double dx = ax - p.x, dy = ay - p.y, dz = az - p.z;
+        const double qq = sqrt((dx * dx + dy * dy) + dz * dz) * ih;
+        if (qq < 2.0) {
+          hit = true;
+          w = m4w(qq);
+          dt = -(3.0 * w + qq * m4dw(qq));
         }
-        uint64_t mask = __ballot(hit);
-        while (mask) {
-          const int j = __builtin_ctzll(mask);
-          mask &= mask - 1;
-          sw += readlane_d(w, j);
-          sd += readlane_d(dt, j);
+      }
+      uint64_t mask = __ballot(hit);
+      while (mask) {
+        const int j = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        sw += readlane_d(w, j);
+        sd += readlane_d(dt, j);
+      }
+    };
+    // units [u0, u1) by tiles of 64 (tile t: units [64 t, 64 t + 64)); a
+    // tile whose bounding box lies beyond 2h holds only zero terms and is
+    // skipped; non-zero terms are added in unit order
+    auto tile_sums = [&](int64_t u0, int64_t u1) {
+      const int64_t t0 = u0 >> 6, t1 = (u1 + 63) >> 6;
+      for (int64_t tb = t0; tb < t1; tb += 64) {
+        const int64_t ti = tb + lane;
+        bool near = false;
+        if (ti < t1) {
+          const double4 lo = tlo[ti], hi = thi[ti];
+          const double bx = fmax(fmax(lo.x - ax, ax - hi.x), 0.0);
+          const double by = fmax(fmax(lo.y - ay, ay - hi.y), 0.0);
+          const double bz = fmax(fmax(lo.z - az, az - hi.z), 0.0);
+          near = ((bx * bx + by * by) + bz * bz) * ih * ih < 4.0 * (1.0 + 1e-9);
+        }
+        uint64_t nm = __ballot(near);
+        while (nm) {
+          const int64_t t = tb + __builtin_ctzll(nm);
+          nm &= nm - 1;
+          const int64_t ua = max(u0, 64 * t), ub = min(u1, 64 * t + 64);
+          tile_one(ua, ub);
         }
       }
     };
+
     if (n_mid == 0) {
       tile_sums(0, nu);
     } else {
@@ -616,15 +640,41 @@ struct Grow {
 
 }  // namespace
 
+namespace {
+__global__ void k_unit_tiles(int64_t nu, const double4 *upos, double4 *tlo, double4 *thi) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t * 64 >= nu) return;
+  double4 lo = make_double4(INFINITY, INFINITY, INFINITY, 0.0), hi = make_double4(-INFINITY, -INFINITY, -INFINITY, 0.0);
+  for (int64_t u = 64 * t; u < min(nu, 64 * t + 64); ++u) {
+    const double4 p = upos[u];
+    lo.x = fmin(lo.x, p.x);
+    lo.y = fmin(lo.y, p.y);
+    lo.z = fmin(lo.z, p.z);
+    hi.x = fmax(hi.x, p.x);
+    hi.y = fmax(hi.y, p.y);
+    hi.z = fmax(hi.z, p.z);
+  }
+  tlo[t] = lo;
+  thi[t] = hi;
+}
+}  // namespace
+
 void node_hsolve(Ctx &ctx, int64_t np, const int32_t *plist, int64_t nu, const double4 *upos, const double *o_xyz,
                  const double *o_s, double hfact, double eps, int64_t bypass, double *o_h, int32_t *o_branch,
                  unsigned long long *bcount, int64_t n_mid, const double4 *mid_com, const int32_t *mid_u0,
                  const int32_t *mid_u1, const double *rcut, hipStream_t s) {
   if (np <= 0) return;
+  const int64_t nt = div_up(nu, 64);
+  double4 *tlo = ctx.arena.get<double4>("hs_tlo", std::max<int64_t>(nt, 1));
+  double4 *thi = ctx.arena.get<double4>("hs_thi", std::max<int64_t>(nt, 1));
+  if (nt > 0) {
+    k_unit_tiles<<<(unsigned)div_up(nt, 256), 256, 0, s>>>(nu, upos, tlo, thi);
+    SPH_LAUNCH_CHECK();
+  }
   KernelTimer kt(&ctx, "node_hsolve", s);
   k_hsolve<<<(unsigned)div_up(np, kHWaves), 64 * kHWaves, 0, s>>>(np, plist, nu, upos, o_xyz, o_s, hfact, eps, bypass,
                                                                 o_h, o_branch, bcount, n_mid, mid_com, mid_u0, mid_u1,
-                                                                rcut);
+                                                                rcut, tlo, thi);
   SPH_LAUNCH_CHECK();
   kt.done();
 }
@@ -779,14 +829,8 @@ void pseudo_build(Ctx &ctx, PseudoArgs &a, hipStream_t s) {
   // node smoothing lengths
   unsigned long long *bcount = ar.get<unsigned long long>("ps_bcount", 4);
   SPH_HIP(hipMemsetAsync(bcount, 0, 4 * sizeof(unsigned long long), s));
-  if (np > 0) {
-    KernelTimer kt(&ctx, "node_hsolve", s);
-    k_hsolve<<<(unsigned)div_up(np, kHWaves), 64 * kHWaves, 0, s>>>(np, plist, nu, upos, a.o_xyz, o_s, o.h_fact, o.eps_h,
-                                                                o.bypass_threshold, a.o_h, a.o_branch, bcount, 0,
-                                                                nullptr, nullptr, nullptr, nullptr);
-    SPH_LAUNCH_CHECK();
-    kt.done();
-  }
+  node_hsolve(ctx, np, plist, nu, upos, a.o_xyz, o_s, o.h_fact, o.eps_h, o.bypass_threshold, a.o_h, a.o_branch,
+              bcount, 0, nullptr, nullptr, nullptr, nullptr, s);
   unsigned long long bc[4] = {0, 0, 0, 0};
   SPH_HIP(hipMemcpyAsync(bc, bcount, sizeof bc, hipMemcpyDeviceToHost, s));
   SPH_HIP(hipStreamSynchronize(s));

@@ -206,3 +206,34 @@ def test_turbulent_262144_sampled(ctx, c2, oracle, precision):
     tot = gm.sum()
     assert 0.95 < tot <= 1.0 + 1e-9
     assert abs(tot - np.dot(c2.m, res.coverage.cpu().numpy())) < 1e-9
+
+
+def test_long_cell_lists(ctx, oracle):
+    """Three slab cells and 12,000 particles: every cell's candidate list is
+    longer than one LDS sort run (4096), so the lists go through the merged
+    path of the per-cell sort.  Lists bit-exact; the cell masses add up to
+    the particles' coverage-weighted mass."""
+    import types
+
+    import paper_2410_15227_amd as pkg
+    say("case: long cell lists, 3 slab cells, 12000 particles")
+    gen = np.array([[0.2, 0.5, 0.5], [0.5, 0.5, 0.5], [0.8, 0.5, 0.5]])
+    v = oracle.voronoi(gen)
+    t = types.SimpleNamespace(n_cells=3, generators=gen, vertices=v["face_pts"], cell_face_off=v["cell_face_off"],
+                              face_vtx_off=v["face_vtx_off"],
+                              face_vtx=np.arange(len(v["face_pts"]), dtype=np.int32))
+    g = np.random.default_rng(31)
+    pos = 0.1 + 0.8 * g.random((12000, 3))  # supports (2h <= 0.06) inside the box
+    h = g.uniform(0.01, 0.03, 12000)
+    m = np.full(12000, 1.0 / 12000)
+    dt = pkg.DeviceTessellation(ctx, t)
+    res = pkg.map_particles_to_cells(ctx, dt, pos, h, m, precision="fp64", keep_pairs=True)
+    goff, gidx, gw = (x.cpu().numpy() for x in res.pairs.export())
+    off, idx = oracle.pair_lists(t, pos, h)
+    assert np.min(np.diff(off)) > 4096
+    assert np.array_equal(goff, off) and np.array_equal(gidx, idx)
+    cov = res.coverage.cpu().numpy()
+    assert abs(res.mass.sum().item() - (m * cov).sum()) < 1e-12
+    assert np.all(np.abs(cov - 1.0) < 1e-12)  # every support lies inside the box and the cells tile it
+    res.pairs.free()
+    dt.free()
