@@ -783,7 +783,9 @@ __device__ inline int drain(EdgeWave &L, float4 *q, unsigned char *o, int len, i
 }
 
 template <bool kCount>
-__global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
+// Three waves per SIMD: the edge phase keeps the next batch's face and edge
+// data in registers (about 165 VGPRs); at four the pipeline would spill.
+__global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
     const ExactInst *insts, const int64_t *chunk0, int n_inst, int per_fetch, int64_t *counters, FaceRec *faces,
     int2 *edges, int32_t *next_chunk, int64_t *redo, int32_t *n_redo) {
   __shared__ EdgeWave lds[kFlatWaves];
@@ -933,21 +935,36 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
     wave_fence();
     // ---------------- A2: one edge per lane; B whenever a queue fills
     int qD = 0, qN = 0;
+    // two-stage pipeline: the records of batch b + 2 and the face and edge
+    // data of batch b + 1 are in flight while batch b is evaluated
     int2 rec_next = lane < n_edge ? er[lane] : make_int2(0, 0);
+    FaceRec fc_next{};
+    float4 ea_next = make_float4(0.f, 0.f, 0.f, 0.f), ee_next = ea_next, em_next = ea_next;
+    if (lane < n_edge) {
+      fc_next = fr[rec_next.y];
+      ea_next = edgeA[rec_next.x];
+      ee_next = edgeE[rec_next.x];
+      em_next = edgeM[rec_next.x];
+    }
+    if (64 + lane < n_edge) rec_next = er[64 + lane];
     for (int b = 0; b < n_edge; b += 64) {
       const int g = b + lane;
       const bool live = g < n_edge;
-      const int2 rec = rec_next;
-      if (g + 64 < n_edge) rec_next = er[g + 64];  // next batch, in flight meanwhile
+      const FaceRec fc = fc_next;
+      const float4 EA = ea_next, EE = ee_next, EM = em_next;
+      if (g + 64 < n_edge) {
+        fc_next = fr[rec_next.y];
+        ea_next = edgeA[rec_next.x];
+        ee_next = edgeE[rec_next.x];
+        em_next = edgeM[rec_next.x];
+        if (g + 128 < n_edge) rec_next = er[g + 128];
+      }
       int owner = 0;
       bool integ = false, cross = false;
       float4 it = make_float4(0.f, 0.f, 0.f, 0.f);
       if (live) {
-        const FaceRec fc = fr[rec.y];
         owner = fc.owner;
-        const float4 EA = edgeA[rec.x];
         if (EA.w > 0.0f) {
-          const float4 EE = edgeE[rec.x], EM = edgeM[rec.x];
           const float dx = fc.px - EA.x, dy = fc.py - EA.y, dz = fc.pz - EA.z;
           const float p = (dx * EM.x + dy * EM.y + dz * EM.z) * fc.ihf;
           if (p != 0.0f) {
