@@ -41,9 +41,15 @@ __global__ void __launch_bounds__(256) k_cell_mass(int64_t C, const int64_t *off
   }
 }
 
-__global__ void k_count_particles(int64_t P, const int32_t *pair_p, unsigned long long *cnt) {
-  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < P) atomicAdd(&cnt[pair_p[k]], 1ull);
+// Particle offsets from the sorted particle keys: position k starts every
+// particle in (key[k-1], key[k]] (particles without pairs start where the
+// next one does); the end, NP, starts every particle after the last key.
+__global__ void k_part_offsets(int64_t NP, int64_t N, const uint32_t *key, int64_t *part_off) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > NP) return;
+  const int64_t lo = k == 0 ? -1 : (int64_t)key[k - 1];
+  const int64_t hi = k == NP ? N : (int64_t)key[k];
+  for (int64_t j = lo + 1; j <= hi; ++j) part_off[j] = k;
 }
 
 __global__ void k_copy_u32(int64_t P, const int32_t *src, uint32_t *dst) {
@@ -144,14 +150,9 @@ void particle_major(Ctx &ctx, PairsDev &P, hipStream_t s) {
   P.pm_w = P.mem.get<double>("pm_w", NP);
   P.coverage = P.mem.get<double>("coverage", N);
   KernelTimer kt(&ctx, "transpose", s);
-  unsigned long long *cnt = ar.get<unsigned long long>("pm_cnt", N + 1);
-  SPH_HIP(hipMemsetAsync(cnt, 0, (N + 1) * sizeof(unsigned long long), s));
   if (NP > 0) {
-    k_count_particles<<<(unsigned)div_up(NP, 256), 256, 0, s>>>(NP, P.pair_p, cnt);
-    SPH_LAUNCH_CHECK();
-  }
-  scan_exclusive_i64(ar, (const int64_t *)cnt, P.part_off, N, true, s);
-  if (NP > 0) {
+    // stable sort of the pair positions by particle: each particle's pairs
+    // keep ascending cell order
     uint32_t *keys = ar.get<uint32_t>("pm_keys", NP);
     int32_t *perm = ar.get<int32_t>("pm_perm", NP);
     k_copy_u32<<<(unsigned)div_up(NP, 256), 256, 0, s>>>(NP, P.pair_p, keys);
@@ -160,10 +161,13 @@ void particle_major(Ctx &ctx, PairsDev &P, hipStream_t s) {
     int bits = 1;
     while (bits < 32 && ((int64_t)1 << bits) < N) ++bits;
     radix_sort_u32(ar, keys, perm, NP, bits, s);
+    k_part_offsets<<<(unsigned)div_up(NP + 1, 256), 256, 0, s>>>(NP, N, keys, P.part_off);
+    SPH_LAUNCH_CHECK();
     k_coverage<<<(unsigned)div_up(N * 64, 256), 256, 0, s>>>(N, P.part_off, perm, P.pair_c, P.w, P.pm_cell, P.pm_w,
                                                              P.coverage);
     SPH_LAUNCH_CHECK();
   } else {
+    fill_i64(P.part_off, 0, N + 1, s);
     SPH_HIP(hipMemsetAsync(P.coverage, 0, N * sizeof(double), s));
   }
   kt.done();
