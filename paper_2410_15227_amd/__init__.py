@@ -469,27 +469,25 @@ def interpolate_to_particles(ctx: Context, xyz, ps: dict, values, stream=None):
 
 
 def adaptive_pseudo_particles(ctx: Context, xyz, h, m, sources, cell_fneu, K: float, max_iter: int = 16,
-                              precision: str = "mixed", **walk) -> tuple:
+                              precision: str = "mixed", n_lloyd: int = 5, **walk) -> tuple:
     """The adaptive tree walk of Sec. 2.4.1.  Each iteration builds the
     pseudo-particles with every node that has failed so far opened, builds the
-    Voronoi grid of the mixed set (host), asks `cell_fneu(generators)` for the
-    neutral fraction of every cell (the radiative transfer's output; here any
-    cell field), maps it back onto the entries (map_cells_to_particles of the
-    forward mapping's weights) and checks eq. resol_param; it stops when no
-    pseudo-particle is under-resolved.  Returns (final build, history); the
-    build also holds the entries' 'fneu' and the labels it 'opened'."""
+    Voronoi grid of the mixed set on the device (n_lloyd Lloyd iterations,
+    Sec. 2.3), asks `cell_fneu(sites)` for the neutral fraction of every cell
+    (the radiative transfer's output; here any cell field), maps it back onto
+    the entries (map_cells_to_particles of the forward mapping's weights) and
+    checks eq. resol_param; it stops when no pseudo-particle is
+    under-resolved.  Returns (final build, history); the build also holds the
+    entries' 'fneu' and the labels it 'opened'."""
     import numpy as np
 
-    from . import workloads
     opened = np.zeros(0, dtype=np.uint64)
     history = []
     for it in range(max_iter):
         ps = build_pseudo_particles(ctx, xyz, h, m, sources, open_labels=opened, **walk)
-        pos = ps["xyz"].cpu().numpy()
-        tess = workloads.voronoi(pos)
-        dt = DeviceTessellation(ctx, tess)
+        dt, sites = build_voronoi(ctx, ps["xyz"], n_lloyd=n_lloyd)
         res = map_particles_to_cells(ctx, dt, ps["xyz"], ps["h"], ps["m"], precision=precision, keep_pairs=True)
-        f_cells = np.asarray(cell_fneu(tess.generators), dtype=np.float64)
+        f_cells = np.asarray(cell_fneu(sites.cpu().numpy()), dtype=np.float64)
         fneu = map_cells_to_particles(ctx, res.pairs, f_cells)
         bad = select_underresolved(ctx, ps, fneu, K)
         history.append(dict(iteration=it, n_entries=int(ps["kind"].shape[0]), n_pseudo=ps["stats"]["n_pseudo"],
