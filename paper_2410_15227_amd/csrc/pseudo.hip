@@ -474,13 +474,11 @@ __global__ void __launch_bounds__(64 * kHWaves) k_hsolve(int64_t np, const int32
     else if (phase == 3) he = 0.5 * (lo + hi);
     const double ih = 1.0 / he;
     double sw = 0.0, sd = 0.0;
-    // units [ua, ub) of one tile, one per lane
-    auto tile_one = [&](int64_t ua, int64_t ub) {
-      const int64_t u = ua + lane;
+    // the terms of one tile's units (one per lane, `live` lanes hold one)
+    auto tile_terms = [&](const double4 &p, bool live) {
       double w = 0.0, dt = 0.0;
       bool hit = false;
-      if (u < ub) {
-        const double4 p = upos[u];
+      if (live) {
         const double dx = ax - p.x, dy = ay - p.y, dz = az - p.z;
         const double qq = sqrt((dx * dx + dy * dy) + dz * dz) * ih;
         if (qq < 2.0) {
@@ -514,10 +512,24 @@ __global__ void __launch_bounds__(64 * kHWaves) k_hsolve(int64_t np, const int32
         }
         uint64_t nm = __ballot(near);
         while (nm) {
-          const int64_t t = tb + __builtin_ctzll(nm);
-          nm &= nm - 1;
-          const int64_t ua = max(u0, 64 * t), ub = min(u1, 64 * t + 64);
-          tile_one(ua, ub);
+          // up to four near tiles at once: their loads are in flight together,
+          // and their terms are added tile after tile
+          int64_t ua[4], ub[4];
+          double4 pv[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            ua[k] = ub[k] = 0;
+            if (nm) {
+              const int64_t t = tb + __builtin_ctzll(nm);
+              nm &= nm - 1;
+              ua[k] = max(u0, 64 * t);
+              ub[k] = min(u1, 64 * t + 64);
+            }
+            if (ua[k] + lane < ub[k]) pv[k] = upos[ua[k] + lane];
+          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (ub[k] > ua[k]) tile_terms(pv[k], ua[k] + lane < ub[k]);
         }
       }
     };
