@@ -875,6 +875,7 @@ int64_t ora_underresolved(int64_t n, const int32_t *kind, const uint64_t *label,
    O(n E) loop, entries in index order.  values and out are [][ncomp]. */
 void ora_interpolate(int64_t n, const double *x, const int64_t *owner, int64_t ne, const double *ex,
                      const double *eh, const int32_t *ekind, const double *val, int32_t ncomp, double *out) {
+  if (ncomp < 1 || ncomp > 16) return; /* the per-particle sums hold at most 16 components */
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t i = 0; i < n; ++i) {
     const int64_t o = owner[i];
