@@ -222,6 +222,9 @@ int sphmap_pairs_info(const sphmap_pairs *pairs, int64_t *n_pairs, int64_t *n_ce
    within each cell), d_w [n_pairs] (binary64 weights w_ic). */
 int sphmap_pairs_export(sphmap_ctx *ctx, const sphmap_pairs *pairs, int64_t *d_cell_off, int32_t *d_particle,
                         double *d_w, void *stream);
+/* Release a retained list.  The context keeps the device memory of up to two
+   freed lists and gives it to the next retained lists (no device allocation
+   in repeated steps); sphmap_destroy releases it. */
 int sphmap_pairs_free(sphmap_ctx *ctx, sphmap_pairs *pairs);
 
 /* ------------------------------------------------------------------------

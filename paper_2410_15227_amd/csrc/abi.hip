@@ -42,6 +42,20 @@ int guarded(sphmap_ctx *ctx, F &&fn) {
 
 inline hipStream_t as_stream(void *s) { return (hipStream_t)s; }
 
+// A new retained pair list takes the device buffers of a freed one when the
+// context keeps any (grow-only buffers: no allocation in steady state).
+sphmap_pairs *new_pairs(sphmap::Ctx &C) {
+  sphmap_pairs *q = new sphmap_pairs;
+  if (!C.recycled.empty()) {
+    q->p.mem.bufs.swap(C.recycled.back()->mem.bufs);
+    delete C.recycled.back();
+    C.recycled.pop_back();
+  }
+  return q;
+}
+
+constexpr size_t kRecycledLists = 2;
+
 }  // namespace
 
 extern "C" {
@@ -78,6 +92,8 @@ int sphmap_destroy(sphmap_ctx *ctx) {
   delete ctx->c.scratch_pairs;
   ctx->c.scratch_pairs = nullptr;
   for (auto *P : ctx->c.scratch_batch) delete P;
+  for (auto *P : ctx->c.recycled) delete P;
+  ctx->c.recycled.clear();
   ctx->c.scratch_batch.clear();
   if (ctx->c.pinned) (void)hipHostFree(ctx->c.pinned);
   ctx->c.pinned = nullptr;
@@ -243,7 +259,7 @@ int map_particles_to_cells(sphmap_ctx *ctx, const sphmap_tess *tess, int64_t n, 
     sphmap::Ctx &C = ctx->c;
     sphmap::PairsDev *P;
     if (pairs_out) {
-      owned.reset(new sphmap_pairs);
+      owned.reset(new_pairs(C));
       P = &owned->p;
     } else {
       if (!C.scratch_pairs) C.scratch_pairs = new sphmap::PairsDev;
@@ -295,7 +311,7 @@ int map_particles_to_cells_batch(sphmap_ctx *ctx, int32_t n_inst, const sphmap_t
     std::vector<sphmap::PairsDev *> P(n_inst);
     if (pairs_out) {
       for (int k = 0; k < n_inst; ++k) {
-        owned.emplace_back(new sphmap_pairs);
+        owned.emplace_back(new_pairs(C));
         P[k] = &owned.back()->p;
       }
     } else {
@@ -360,6 +376,11 @@ int sphmap_pairs_free(sphmap_ctx *ctx, sphmap_pairs *pairs) {
   if (!ctx || !pairs) return SPHMAP_EINVAL;
   (void)hipSetDevice(ctx->c.device);
   (void)hipDeviceSynchronize();
+  if (ctx->c.recycled.size() < kRecycledLists) {
+    sphmap::PairsDev *keep = new sphmap::PairsDev;
+    keep->mem.bufs.swap(pairs->p.mem.bufs);
+    ctx->c.recycled.push_back(keep);
+  }
   delete pairs;
   return SPHMAP_OK;
 }
@@ -540,9 +561,10 @@ int sphmap_estimate_footprint(sphmap_ctx *ctx, int64_t n_particles, int64_t n_pa
     // out whole 2 MiB granules, once per named buffer
     auto grown = [](double b, int n_buffers) { return (size_t)(b * 1.125 + 2097152.0 * n_buffers); };
     // per particle: staged float4, Morton key + index, sorted copy, radix
-    // temporaries, search boxes, transpose counts; per pair: transpose keys,
-    // permutation and radix temporaries; per cell: pair counts
-    const double ws = 16.0 * N + 12.0 * N + 16.0 * N + 12.0 * N + 3.0 * N + 8.0 * N + 16.0 * P + 8.0 * C +
+    // temporaries, search boxes; per pair: transpose keys, permutation and
+    // radix temporaries; per cell: pair counts, the bounded candidate buffer
+    // of the pair search (384 entries), the overflow list
+    const double ws = 16.0 * N + 12.0 * N + 16.0 * N + 12.0 * N + 3.0 * N + 16.0 * P + (8.0 + 1536.0 + 4.0) * C +
                       (double)sphmap::exact_workspace_bytes(ctx->c, P);
     // retained list: cell offsets, pair indices, weights, particle-major
     // copy, particle offsets and coverage

@@ -80,6 +80,7 @@ struct Ctx {
   void *pinned = nullptr;         // pinned host staging for small tables
   size_t pinned_bytes = 0;
   std::vector<PairsDev *> scratch_batch;  // pair lists of batched calls that do not keep them
+  std::vector<PairsDev *> recycled;       // buffers of freed pair lists, reused by the next kept lists
   int n_cu = 0, exact_per_cu = 0;  // compute units; resident Exact workgroups per CU
   bool autotune = false;
   std::map<int, TuneChoice> tuned;  // by floor(log2(pairs)) of the Exact launch

@@ -14,9 +14,11 @@
 // uniform hash grid would be either overfull in dense regions or hold each
 // large-h particle in many buckets; the Morton hierarchy is a uniform grid
 // at every level and adapts to both.  One thread per cell walks it, cells in
-// Morton order of their sites so that a wave's walks stay coherent.  A count
-// pass sizes the CSR, a fill pass writes it, and each cell's list is then
-// sorted by particle index.
+// Morton order of their sites so that a wave's walks stay coherent.  The walk
+// counts every cell's candidates and keeps the first kCap of them in a
+// bounded per-cell buffer; after the scan that sizes the CSR, each list that
+// fitted is sorted by particle index in LDS and written out, and the few
+// longer ones are walked a second time straight into the CSR and sorted.
 #include "ballsearch.hpp"
 
 namespace sphmap {
@@ -73,10 +75,15 @@ __device__ inline bool canon_pair(const float4 &p, const float4 &g) {
   return d2 < s * s;
 }
 
+// Walk modes: kFill writes the list straight into the CSR (offsets known);
+// otherwise the first kCap candidates go to the cell's slot of a bounded
+// buffer and all are counted.
+constexpr int kCap = 384;
+
 template <bool kFill>
 __global__ void __launch_bounds__(128) k_pairs(Hier H, int64_t C, const int32_t *cell_order, const float4 *gen32,
                                               int64_t *counts, const int64_t *off, int32_t *pair_p,
-                                              int32_t *pair_c) {
+                                              int32_t *pair_c, int32_t *buf) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= C) return;
   const int32_t c = cell_order[t];
@@ -107,6 +114,8 @@ __global__ void __launch_bounds__(128) k_pairs(Hier H, int64_t C, const int32_t 
           if (kFill) {
             pair_p[base + cnt] = H.sidx[k];
             pair_c[base + cnt] = c;
+          } else if (cnt < kCap) {
+            buf[(int64_t)c * kCap + cnt] = H.sidx[k];
           }
           ++cnt;
         }
@@ -179,9 +188,32 @@ __device__ void merge_block(const int32_t *A, int na, const int32_t *B, int nb, 
   }
 }
 
-__global__ void __launch_bounds__(256) k_sort_segments(int64_t C, const int64_t *off, int32_t *pair_p, int32_t *tmp) {
-  __shared__ int32_t buf[kSortCap];
+// Lists that fitted the bounded buffer: sorted in LDS and written to the CSR
+// with their cell; the others are listed for a second walk.
+__global__ void __launch_bounds__(256) k_compact_sort(int64_t C, const int64_t *off, const int32_t *buf,
+                                                      int32_t *pair_p, int32_t *pair_c, int32_t *over,
+                                                      int32_t *n_over) {
+  __shared__ int32_t lds[512];
   const int64_t c = blockIdx.x;
+  const int64_t s = off[c];
+  const int n = (int)(off[c + 1] - s);
+  if (n > kCap) {
+    if (threadIdx.x == 0) over[atomicAdd(n_over, 1)] = (int32_t)c;
+    return;
+  }
+  for (int k = threadIdx.x; k < n; k += blockDim.x) pair_c[s + k] = (int32_t)c;
+  if (n == 0) return;
+  if (n == 1) {
+    if (threadIdx.x == 0) pair_p[s] = buf[c * kCap];
+    return;
+  }
+  sort_run_lds(lds, buf + c * kCap, pair_p + s, n);
+}
+
+__global__ void __launch_bounds__(256) k_sort_segments(int64_t C, const int64_t *off, int32_t *pair_p, int32_t *tmp,
+                                                       const int32_t *cells) {
+  __shared__ int32_t buf[kSortCap];
+  const int64_t c = cells ? cells[blockIdx.x] : blockIdx.x;
   const int64_t s = off[c], e = off[c + 1];
   const int n = (int)(e - s);
   if (n <= 1) return;
@@ -251,11 +283,13 @@ void find_pairs(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, hipSt
   P.n_cells = C;
   P.n_particles = N;
   int64_t *counts = ar.get<int64_t>("pp_counts", C + 1);
+  int32_t *buf = ar.get<int32_t>("pp_buf", C * (int64_t)kCap);
   P.cell_off = P.mem.get<int64_t>("cell_off", C + 1);
+  // one walk: up to kCap candidates per cell into the bounded buffer, all counted
   {
     KernelTimer kt(&ctx, "pair_count", s);
     k_pairs<false><<<(unsigned)div_up(C, 128), 128, 0, s>>>(H, C, t.cell_order, t.gen32, counts, nullptr, nullptr,
-                                                             nullptr);
+                                                             nullptr, buf);
     SPH_LAUNCH_CHECK();
     kt.done();
   }
@@ -267,17 +301,29 @@ void find_pairs(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, hipSt
   P.n_pairs = total;
   P.pair_p = P.mem.get<int32_t>("pair_p", total);
   P.pair_c = P.mem.get<int32_t>("pair_c", total);
+  if (C == 0) return;
+  int32_t *over = ar.get<int32_t>("pp_over", C);
+  int32_t *n_over = ar.get<int32_t>("pp_nover", 1);
+  SPH_HIP(hipMemsetAsync(n_over, 0, sizeof(int32_t), s));
   {
     KernelTimer kt(&ctx, "pair_fill", s);
-    k_pairs<true><<<(unsigned)div_up(C, 128), 128, 0, s>>>(H, C, t.cell_order, t.gen32, nullptr, P.cell_off,
-                                                            P.pair_p, P.pair_c);
+    k_compact_sort<<<(unsigned)C, 256, 0, s>>>(C, P.cell_off, buf, P.pair_p, P.pair_c, over, n_over);
     SPH_LAUNCH_CHECK();
     kt.done();
   }
-  if (C > 0) {
-    int32_t *tmp = ar.get<int32_t>("pp_sort_tmp", std::max<int64_t>(total, 1));
-    k_sort_segments<<<(unsigned)C, 256, 0, s>>>(C, P.cell_off, P.pair_p, tmp);
+  int32_t no = 0;
+  SPH_HIP(hipMemcpyAsync(&no, n_over, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  SPH_HIP(hipStreamSynchronize(s));
+  if (no > 0) {
+    // longer lists: walked again straight into the CSR, then sorted
+    KernelTimer kt(&ctx, "pair_fill_long", s);
+    k_pairs<true><<<(unsigned)div_up(no, 128), 128, 0, s>>>(H, no, over, t.gen32, nullptr, P.cell_off, P.pair_p,
+                                                             P.pair_c, nullptr);
     SPH_LAUNCH_CHECK();
+    int32_t *tmp = ar.get<int32_t>("pp_sort_tmp", std::max<int64_t>(total, 1));
+    k_sort_segments<<<(unsigned)no, 256, 0, s>>>(C, P.cell_off, P.pair_p, tmp, over);
+    SPH_LAUNCH_CHECK();
+    kt.done();
   }
 }
 

@@ -113,3 +113,37 @@ def test_footprint_bounds_use(grid):
     res.pairs.free()
     dt.free()
     ctx.close()
+
+
+def test_recycled_pair_lists(grid):
+    """Freed pair lists give their buffers to the next retained lists: repeated
+    steps allocate nothing more after the first and repeat bit for bit."""
+    import paper_2410_15227_amd as pkg
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    say("case: recycled pair lists, uniform 4096")
+    pos, m, h, tess = grid
+    ctx = pkg.Context(0)
+    dt = ctx.upload(tess)
+    xyz = torch.tensor(pos, device="cuda")
+    hd = torch.tensor(h, device="cuda")
+    md = torch.tensor(m, device="cuda")
+    q = torch.ones(tess.n_cells, dtype=torch.float64, device="cuda")
+    first = None
+    free_after = []
+    for step in range(4):
+        res = pkg.map_particles_to_cells(ctx, dt, xyz, hd, md, keep_pairs=True)
+        v = pkg.map_cells_to_particles(ctx, res.pairs, q)
+        w = res.pairs.export()[2].cpu().numpy()
+        out = (res.mass.cpu().numpy(), v.cpu().numpy(), w)
+        if first is None:
+            first = out
+        else:
+            assert all(np.array_equal(a, b) for a, b in zip(first, out))
+        res.pairs.free()
+        torch.cuda.synchronize()
+        free_after.append(torch.cuda.mem_get_info()[0])
+    # steady state from the second step on: no device memory taken or given back
+    assert max(free_after[1:]) - min(free_after[1:]) < (4 << 20)
+    dt.free()
+    ctx.close()
