@@ -733,6 +733,11 @@ struct __align__(16) FaceRec {  // a face within reach of a pair
   int32_t owner;     // lane of the pair
 };
 
+struct EdgeData {  // what one lane reads for its edge: face record and edge geometry
+  FaceRec fc;
+  float4 ea, ee, em;
+};
+
 struct EdgeWave {  // per-wavefront LDS
   double4 wpl[64], wsp[64];  // window of the chunk's faces: plane, bounding sphere
   int wvs[64], wnv[64];      // first vertex slot, vertex count
@@ -741,6 +746,14 @@ struct EdgeWave {  // per-wavefront LDS
   unsigned char oD[kQueue], oN[kQueue];
   int redo[64];
 };
+
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T *;
+
+__device__ inline float4 load4(gptr<float4> p, int i) {
+  const gptr<float> q = (gptr<float>)(p + i);
+  return make_float4(q[0], q[1], q[2], q[3]);
+}
 
 __device__ inline uint64_t lanes_in(int lo, int hi) {  // bits [lo, hi), 0 <= lo <= hi <= 64
   const uint64_t a = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
@@ -810,7 +823,9 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
     const double *const xyz = I.xyz, *const hh = I.hh, *const gen = I.gen;
     const int64_t *const cfo = I.cfo, *const fvo = I.fvo;
     const double4 *const fplane = I.fplane, *const fsphere = I.fsphere;
-    const float4 *const edgeA = I.edgeA, *const edgeE = I.edgeE, *const edgeM = I.edgeM;
+    // global (not generic) address space: the loads then count only against
+    // the vector-memory counter and never hold up waits on LDS traffic
+    const gptr<float4> edgeA = (gptr<float4>)I.edgeA, edgeE = (gptr<float4>)I.edgeE, edgeM = (gptr<float4>)I.edgeM;
     const int64_t P = I.P;
     const int64_t chunk = gchunk - chunk0[ins];
     const int64_t k = chunk * 64 + lane;
@@ -935,30 +950,12 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
     wave_fence();
     // ---------------- A2: one edge per lane; B whenever a queue fills
     int qD = 0, qN = 0;
-    // two-stage pipeline: the records of batch b + 2 and the face and edge
-    // data of batch b + 1 are in flight while batch b is evaluated
-    int2 rec_next = lane < n_edge ? er[lane] : make_int2(0, 0);
-    FaceRec fc_next{};
-    float4 ea_next = make_float4(0.f, 0.f, 0.f, 0.f), ee_next = ea_next, em_next = ea_next;
-    if (lane < n_edge) {
-      fc_next = fr[rec_next.y];
-      ea_next = edgeA[rec_next.x];
-      ee_next = edgeE[rec_next.x];
-      em_next = edgeM[rec_next.x];
-    }
-    if (64 + lane < n_edge) rec_next = er[64 + lane];
-    for (int b = 0; b < n_edge; b += 64) {
+    // Evaluate batch [b, b + 64) from the data d fetched for it.
+    auto batch = [&](int b, const EdgeData &d) {
       const int g = b + lane;
       const bool live = g < n_edge;
-      const FaceRec fc = fc_next;
-      const float4 EA = ea_next, EE = ee_next, EM = em_next;
-      if (g + 64 < n_edge) {
-        fc_next = fr[rec_next.y];
-        ea_next = edgeA[rec_next.x];
-        ee_next = edgeE[rec_next.x];
-        em_next = edgeM[rec_next.x];
-        if (g + 128 < n_edge) rec_next = er[g + 128];
-      }
+      const FaceRec &fc = d.fc;
+      const float4 EA = d.ea, EE = d.ee, EM = d.em;
       int owner = 0;
       bool integ = false, cross = false;
       float4 it = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1011,6 +1008,32 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
       wave_sync();
       if (qD >= 64) qD = drain(L, L.qD, L.oD, qD, 64, true, lane, K.fd);
       if (qN >= 64) qN = drain(L, L.qN, L.oN, qN, 64, false, lane, K.fd);
+    };
+    // Two-stage pipeline: while batch b is evaluated, the data of batch
+    // b + 1 and the records of batch b + 2 are in flight.  The loads are
+    // unconditional, at indices clamped into the chunk's records (beyond
+    // n_edge they fetch valid but unused data), so that no loaded register
+    // has to be merged or copied before the loop's next turn; a copy would
+    // wait for its load.
+    const int last = n_edge - 1;
+    auto fetch = [&](int2 r, EdgeData &d) {
+      d.fc = fr[r.y];
+      d.ea = load4(edgeA, r.x);
+      d.ee = load4(edgeE, r.x);
+      d.em = load4(edgeM, r.x);
+    };
+    EdgeData nxt{};
+    int2 rec = make_int2(0, 0);
+    if (n_edge > 0) {
+      fetch(er[min(lane, last)], nxt);
+      rec = er[min(64 + lane, last)];
+    }
+    for (int b = 0; b < n_edge; b += 64) {
+      const EdgeData d = nxt;
+      const int2 r = rec;
+      rec = er[min(b + 128 + lane, last)];
+      fetch(r, nxt);
+      batch(b, d);
     }
     if (qD > 0) drain(L, L.qD, L.oD, qD, qD, true, lane, K.fd);
     if (qN > 0) drain(L, L.qN, L.oN, qN, qN, false, lane, K.fd);
