@@ -750,9 +750,14 @@ struct EdgeWave {  // per-wavefront LDS
 template <typename T>
 using gptr = const __attribute__((address_space(1))) T *;
 
-__device__ inline float4 load4(gptr<float4> p, int i) {
+__device__ inline float4 load4(gptr<float4> p, int64_t i) {
   const gptr<float> q = (gptr<float>)(p + i);
   return make_float4(q[0], q[1], q[2], q[3]);
+}
+
+__device__ inline double4 load4(gptr<double4> p, int64_t i) {
+  const gptr<double> q = (gptr<double>)(p + i);
+  return make_double4(q[0], q[1], q[2], q[3]);
 }
 
 __device__ inline uint64_t lanes_in(int lo, int hi) {  // bits [lo, hi), 0 <= lo <= hi <= 64
@@ -819,10 +824,12 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
     for (int64_t gchunk = gbase; gchunk < gend; ++gchunk) {
     const int ins = inst_of(chunk0, n_inst, gchunk);
     const ExactInst &I = insts[ins];
-    const int32_t *const pair_c = I.pair_c, *const pair_p = I.pair_p;
-    const double *const xyz = I.xyz, *const hh = I.hh, *const gen = I.gen;
-    const int64_t *const cfo = I.cfo, *const fvo = I.fvo;
-    const double4 *const fplane = I.fplane, *const fsphere = I.fsphere;
+    // all instance arrays through global pointers (see the edge arrays below):
+    // generic loads could alias LDS and would be ordered against its stores
+    const gptr<int32_t> pair_c = (gptr<int32_t>)I.pair_c, pair_p = (gptr<int32_t>)I.pair_p;
+    const gptr<double> xyz = (gptr<double>)I.xyz, hh = (gptr<double>)I.hh, gen = (gptr<double>)I.gen;
+    const gptr<int64_t> cfo = (gptr<int64_t>)I.cfo, fvo = (gptr<int64_t>)I.fvo;
+    const gptr<double4> fplane = (gptr<double4>)I.fplane, fsphere = (gptr<double4>)I.fsphere;
     // global (not generic) address space: the loads then count only against
     // the vector-memory counter and never hold up waits on LDS traffic
     const gptr<float4> edgeA = (gptr<float4>)I.edgeA, edgeE = (gptr<float4>)I.edgeE, edgeM = (gptr<float4>)I.edgeM;
@@ -857,8 +864,8 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
       {
         const int64_t f = wb + lane;
         if (f < F1) {
-          L.wpl[lane] = fplane[f];
-          L.wsp[lane] = fsphere[f];
+          L.wpl[lane] = load4(fplane, f);
+          L.wsp[lane] = load4(fsphere, f);
           const int64_t vs = fvo[f];
           L.wvs[lane] = (int)vs;
           L.wnv[lane] = (int)(fvo[f + 1] - vs);
@@ -912,7 +919,7 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
         if (F1 - F0 > 64) {  // a single window is still staged from the cull
           const int64_t f = wb + lane;
           if (f < F1) {
-            L.wpl[lane] = fplane[f];
+            L.wpl[lane] = load4(fplane, f);
             const int64_t vs = fvo[f];
             L.wvs[lane] = (int)vs;
             L.wnv[lane] = (int)(fvo[f + 1] - vs);
