@@ -963,41 +963,39 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
       const bool live = g < n_edge;
       const FaceRec &fc = d.fc;
       const float4 EA = d.ea, EE = d.ee, EM = d.em;
-      int owner = 0;
-      bool integ = false, cross = false;
-      float4 it = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (live) {
-        owner = fc.owner;
-        if (EA.w > 0.0f) {
-          const float dx = fc.px - EA.x, dy = fc.py - EA.y, dz = fc.pz - EA.z;
-          const float p = (dx * EM.x + dy * EM.y + dz * EM.z) * fc.ihf;
-          if (p != 0.0f) {
-            if (fabsf(p) < kDegenerate) {
-              ++K.n64;
-              L.redo[owner] = 1;  // binary64 geometry for this pair
-            } else {
-              ++K.ne_vis;
-              const float tA = -(dx * EE.x + dy * EE.y + dz * EE.z) * fc.ihf;
-              const float tB = fmaf(EA.w, fc.ihf, tA);
-              const double ap = (double)fabsf(p), dA = (double)tA, dB = (double)tB;
-              const double ad = (double)fabsf(fc.df);
-              const double ang = -fc.dh * MathMixed::span(ap, dA, dB);
-              atomicAdd(&L.acc[owner], to_fixed(((p > 0.0f) == (fc.df > 0.0f)) ? ang : -ang));
-              // within 2h somewhere on [tA, tB], and crossing U = 1 (squares, no roots)
-              const double a2 = ad * ad + ap * ap;
-              const double r2 = 4.0 - a2, s1 = 1.0 - a2;
-              integ = r2 > 0.0 && dA < dB && (dA < 0.0 || dA * dA < r2) && (dB > 0.0 || dB * dB < r2);
-              if (integ && s1 > 0.0) {
-                const bool lo = (dA < 0.0 && dA * dA > s1) && (dB >= 0.0 || dB * dB < s1);
-                const bool hi = (dA < 0.0 || dA * dA < s1) && (dB > 0.0 && dB * dB > s1);
-                cross = lo || hi;
-              }
-              K.ne_int += integ;
-              it = make_float4(fc.df, p, tA, tB);
-            }
-          }
-        }
+      // Branch-free: nearly every lane has a live edge of positive length at
+      // a nonzero distance, so every lane does the arithmetic (the clamped
+      // loads keep it finite) and the tests only select what is kept.
+      const int owner = fc.owner;
+      const float dx = fc.px - EA.x, dy = fc.py - EA.y, dz = fc.pz - EA.z;
+      const float p = (dx * EM.x + dy * EM.y + dz * EM.z) * fc.ihf;
+      const bool act = live & (EA.w > 0.0f) & (p != 0.0f);
+      const bool degen = act & (fabsf(p) < kDegenerate);
+      if (degen) {
+        ++K.n64;
+        L.redo[owner] = 1;  // binary64 geometry for this pair
       }
+      const bool ok = act & !degen;
+      const float tA = -(dx * EE.x + dy * EE.y + dz * EE.z) * fc.ihf;
+      const float tB = fmaf(EA.w, fc.ihf, tA);
+      const double ap = (double)fabsf(p), dA = (double)tA, dB = (double)tB;
+      const double ad = (double)fabsf(fc.df);
+      const double ang = -fc.dh * MathMixed::span(ap, dA, dB);
+      if (ok) atomicAdd(&L.acc[owner], to_fixed(((p > 0.0f) == (fc.df > 0.0f)) ? ang : -ang));
+      // within 2h somewhere on [tA, tB], and crossing U = 1 (squares, no
+      // roots; bitwise logic, so that no test becomes a branch)
+      const double a2 = ad * ad + ap * ap;
+      const double r2 = 4.0 - a2, s1 = 1.0 - a2;
+      const double A2 = dA * dA, B2 = dB * dB;
+      const bool integ = ok & (r2 > 0.0) & (dA < dB) & ((dA < 0.0) | (A2 < r2)) & ((dB > 0.0) | (B2 < r2));
+      const bool lo = (dA < 0.0) & (A2 > s1) & ((dB >= 0.0) | (B2 < s1));
+      const bool hi = ((dA < 0.0) | (A2 < s1)) & (dB > 0.0) & (B2 > s1);
+      const bool cross = (s1 > 0.0) & (lo | hi);
+      if (kCount) {
+        K.ne_vis += ok;
+        K.ne_int += integ;
+      }
+      const float4 it = make_float4(fc.df, p, tA, tB);
       const uint64_t mD = __ballot(integ && cross), mN = __ballot(integ && !cross);
       const uint64_t below = lanes_in(0, lane);
       if (integ) {
