@@ -706,10 +706,11 @@ __device__ inline void wave_fence() {
 //   A1 (lane = pair): the cull over the cell's faces (plane distance, face
 //      sphere against the 2h sphere), kept as a bit mask; the faces within
 //      reach are listed pair-major with their foot point, |d| and
-//      |d| H(|d|), and every edge of the chunk gets a record (vertex slot,
-//      face);
+//      |d| H(|d|); the chunk's edges are numbered in the same order, and a
+//      bit in LDS marks where each listed face's edges begin;
 //   A2 (lane = edge): the wave walks those edges 64 at a time; each lane
-//      forms its edge's in-plane geometry from the precomputed edge frame,
+//      finds its face from the start bits (a population count) and forms
+//      its edge's in-plane geometry from the precomputed edge frame,
 //      adds the angle term -dh (phi_B - phi_A) to its pair, and queues the
 //      edge in LDS when it comes within 2h (one queue for ranges crossing
 //      U = 1, one for the others);
@@ -730,17 +731,26 @@ struct __align__(16) FaceRec {  // a face within reach of a pair
   float df;          // signed |d| / h, binary32
   double dh;         // |d| H(|d|)
   float ihf;         // 1/h of the pair (binary32)
-  int32_t owner;     // lane of the pair
+  uint32_t slot;     // bits 0-23: first vertex slot - the chunk's first; 24-31: lane of the pair
 };
+constexpr int64_t kSlotSpan = 1 << 24;  // vertex slots a chunk's faces may span
 
 struct EdgeData {  // what one lane reads for its edge: face record and edge geometry
   FaceRec fc;
   float4 ea, ee, em;
 };
 
+struct Sphere {
+  double x, y, z, r;
+};
+
 struct EdgeWave {  // per-wavefront LDS
-  double4 wpl[64], wsp[64];  // window of the chunk's faces: plane, bounding sphere
-  int wvs[64], wnv[64];      // first vertex slot, vertex count
+  double4 wpl[64];  // window of the chunk's faces: plane
+  union {
+    Sphere wsp[64];               // cull: the window's bounding spheres
+    unsigned long long sb[256];   // edge walk: bit g set where a face's edges start
+  };
+  int wvs[64], wnv[64];  // first vertex slot, vertex count
   unsigned long long acc[64];
   float4 qD[kQueue], qN[kQueue];
   unsigned char oD[kQueue], oN[kQueue];
@@ -805,20 +815,19 @@ template <bool kCount>
 // data in registers (about 165 VGPRs); at four the pipeline would spill.
 __global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
     const ExactInst *insts, const int64_t *chunk0, int n_inst, int per_fetch, int64_t *counters, FaceRec *faces,
-    int2 *edges, int32_t *next_chunk, int64_t *redo, int32_t *n_redo) {
+    int32_t *next_chunk, int64_t *redo, int32_t *n_redo) {
   __shared__ EdgeWave lds[kFlatWaves];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   EdgeWave &L = lds[wid];
   const int64_t wave = (int64_t)blockIdx.x * kFlatWaves + wid;
   FaceRec *const fr = faces + wave * kEntryCap;
-  int2 *const er = edges + wave * 64 * kEdgeCap;  // per edge of the chunk: vertex slot, face record
   const int64_t n_chunks = chunk0[n_inst];
   Counters K;
   int64_t nfaces = 0;
   while (true) {
     int gbase = 0;
     if (lane == 0) gbase = atomicAdd(next_chunk, per_fetch);
-    gbase = __shfl(gbase, 0, 64);
+    gbase = __builtin_amdgcn_readfirstlane(gbase);  // uniform: chunk state in scalar registers
     if (gbase >= n_chunks) break;
     const int64_t gend = min((int64_t)gbase + per_fetch, n_chunks);
     for (int64_t gchunk = gbase; gchunk < gend; ++gchunk) {
@@ -842,12 +851,16 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
     // [F0, F1); it is staged through LDS 64 faces at a time.
     const int64_t k_last = min(chunk * 64 + 63, P - 1);
     const int64_t F0 = cfo[pair_c[chunk * 64]], F1 = cfo[pair_c[k_last] + 1];
+    // vertex slots of the chunk's faces, kept relative to the first in 24 bits
+    const int64_t VB = fvo[F0];
+    const bool wide = fvo[F1] - VB > kSlotSpan;
     uint64_t mask = 0;
     int nsurv = 0, nedge = 0;
     bool inside = true, on_boundary = false, again = false;
     int64_t f0 = 0, f1 = 0;
     double xr0 = 0.0, xr1 = 0.0, xr2 = 0.0, ih = 0.0, h = 0.0;
     if (valid) {
+      if (wide) again = true;
       const int64_t c = pair_c[k];
       const int64_t i = pair_p[k];
       h = hh[i];
@@ -865,7 +878,8 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
         const int64_t f = wb + lane;
         if (f < F1) {
           L.wpl[lane] = load4(fplane, f);
-          L.wsp[lane] = load4(fsphere, f);
+          const double4 sph = load4(fsphere, f);
+          L.wsp[lane] = Sphere{sph.x, sph.y, sph.z, sph.w};
           const int64_t vs = fvo[f];
           L.wvs[lane] = (int)vs;
           L.wnv[lane] = (int)(fvo[f + 1] - vs);
@@ -874,27 +888,26 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
       wave_sync();
       if (valid && !again) {
         const int64_t ja = max(f0, wb) - wb, jb = min(f1, wb + 64) - wb;
+        // branch-free over the faces: a degenerate face sets again, which
+        // discards the pair's list, so the loop need not stop there
         for (int64_t j = ja; j < jb; ++j) {
           const double4 pl = L.wpl[j];
-          if (!(pl.w > 0.0)) continue;
+          const Sphere sp = L.wsp[j];
+          const bool real = pl.w > 0.0;
           const double dist = pl.w - (pl.x * xr0 + pl.y * xr1 + pl.z * xr2);
-          if (dist < 0.0) inside = false;
-          if (dist == 0.0) {
-            on_boundary = true;
-            continue;
-          }
-          const double4 sp = L.wsp[j];
+          inside &= !(real & (dist < 0.0));
+          on_boundary |= real & (dist == 0.0);
           const double sx = xr0 - sp.x, sy = xr1 - sp.y, sz = xr2 - sp.z;
-          const double reach = sp.w + 2.0 * h;
-          if (fabs(dist) >= 2.0 * h || sx * sx + sy * sy + sz * sz >= reach * reach) continue;
-          if (fabs(dist * ih) < kDegenerate) {
-            ++K.n64;
-            again = true;
-            break;
-          }
-          mask |= 1ull << (wb + j - f0);
-          ++nsurv;
-          nedge += L.wnv[j];
+          const double reach = sp.r + 2.0 * h;
+          const bool near = real & (dist != 0.0) & (fabs(dist) < 2.0 * h) &
+                            (sx * sx + sy * sy + sz * sz < reach * reach);
+          const bool deg = near & (fabs(dist * ih) < kDegenerate);
+          if (kCount) K.n64 += deg & !again;
+          again |= deg;
+          const bool keep = near & !deg & (L.wnv[j] > 0);  // a face without edges adds nothing
+          mask |= (uint64_t)keep << (wb + j - f0);
+          nsurv += keep;
+          nedge += keep ? L.wnv[j] : 0;
         }
       }
       wave_sync();
@@ -909,10 +922,14 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
     const int e_off = wave_scan_excl(nsurv, lane);
     const int x_off = wave_scan_excl(nedge, lane);
     const int n_edge = __shfl(x_off + nedge, 63, 64);
+    const int n_rec = __shfl(e_off + nsurv, 63, 64);
     L.acc[lane] = 0ull;
     L.redo[lane] = again ? 1 : 0;
     if (kCount) K.nf_int += nsurv;
-    // ---------------- A1b: the face list, pair-major, and each edge's record
+    // the start bits of the chunk's edges, n_edge <= 64 kEdgeCap of them
+    for (int w = lane; w < (n_edge + 63) >> 6; w += 64) L.sb[w] = 0ull;
+    wave_sync();
+    // ---------------- A1b: the face list, pair-major, and where each face's edges start
     {
       int e = e_off, start = x_off;
       for (int64_t wb = F0; wb < F1; wb += 64) {
@@ -934,7 +951,6 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
             m &= m - 1;
             const double4 pl = L.wpl[j];
             const double dist = pl.w - (pl.x * xr0 + pl.y * xr1 + pl.z * xr2);
-            const int vs = L.wvs[j], nv = L.wnv[j];
             // |d| rounded to binary32, like the rest of the face's geometry
             const float df = (float)(dist * ih);
             FaceRec rec;
@@ -944,11 +960,11 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
             rec.df = df;
             rec.dh = dH((double)fabsf(df));
             rec.ihf = (float)ih;
-            rec.owner = lane;
+            rec.slot = (uint32_t)(L.wvs[j] - VB) | ((uint32_t)lane << 24);
             fr[e] = rec;
-            for (int q = 0; q < nv; ++q) er[start + q] = make_int2(vs + q, e);
+            atomicOr(&L.sb[start >> 6], 1ull << (start & 63));
             ++e;
-            start += nv;
+            start += L.wnv[j];
           }
         }
         wave_sync();
@@ -966,7 +982,7 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
       // Branch-free: nearly every lane has a live edge of positive length at
       // a nonzero distance, so every lane does the arithmetic (the clamped
       // loads keep it finite) and the tests only select what is kept.
-      const int owner = fc.owner;
+      const int owner = (int)(fc.slot >> 24);
       const float dx = fc.px - EA.x, dy = fc.py - EA.y, dz = fc.pz - EA.z;
       const float p = (dx * EM.x + dy * EM.y + dz * EM.z) * fc.ihf;
       const bool act = live & (EA.w > 0.0f) & (p != 0.0f);
@@ -1014,30 +1030,53 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
       if (qD >= 64) qD = drain(L, L.qD, L.oD, qD, 64, true, lane, K.fd);
       if (qN >= 64) qN = drain(L, L.qN, L.oN, qN, 64, false, lane, K.fd);
     };
-    // Two-stage pipeline: while batch b is evaluated, the data of batch
-    // b + 1 and the records of batch b + 2 are in flight.  The loads are
-    // unconditional, at indices clamped into the chunk's records (beyond
-    // n_edge they fetch valid but unused data), so that no loaded register
-    // has to be merged or copied before the loop's next turn; a copy would
-    // wait for its load.
-    const int last = n_edge - 1;
-    auto fetch = [&](int2 r, EdgeData &d) {
-      d.fc = fr[r.y];
-      d.ea = load4(edgeA, r.x);
-      d.ee = load4(edgeE, r.x);
-      d.em = load4(edgeM, r.x);
+    // Edge g of the chunk belongs to the last face record starting at or
+    // before g: batch [bb, bb + 64) reads one word of start bits, and a lane
+    // counts the starts at or below it.  cnt (records starting before bb)
+    // and qc (the offset of edge bb within its record) carry over.  Lanes
+    // past n_edge take the last record's first edge, so every load stays in
+    // bounds.
+    int cnt = 0, qc = 0;
+    auto locate = [&](int bb, int &rec, int &vq) {
+      const unsigned long long w = L.sb[bb >> 6];  // the same word in every lane
+      const unsigned long long S = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(w >> 32)) << 32) |
+                                   (unsigned)__builtin_amdgcn_readfirstlane((unsigned)w);
+      const unsigned long long upto = S & lanes_in(0, lane + 1);
+      const bool in = bb + lane < n_edge;
+      rec = in ? cnt + __popcll(upto) - 1 : n_rec - 1;
+      vq = !in ? 0 : (upto ? lane - (63 - __builtin_clzll(upto)) : qc + lane);
+      cnt += __popcll(S);
+      qc = S ? __builtin_clzll(S) + 1 : qc + 64;
+    };
+    // Two-stage pipeline: while batch b is evaluated, the records and edge
+    // data of batch b + 1 and the packed vertex slots of batch b + 2 are in
+    // flight.  The loads are unconditional (lanes past n_edge fetch valid
+    // but unused data), so no loaded register is merged or copied before the
+    // loop's next turn; a copy would wait for its load.
+    auto fetch = [&](int rec, int vq, uint32_t slot, EdgeData &d) {
+      d.fc = fr[rec];
+      const int64_t v = VB + (int64_t)(slot & 0xffffffu) + vq;
+      d.ea = load4(edgeA, v);
+      d.ee = load4(edgeE, v);
+      d.em = load4(edgeM, v);
     };
     EdgeData nxt{};
-    int2 rec = make_int2(0, 0);
+    int recN = 0, vqN = 0;
+    uint32_t slotN = 0;
     if (n_edge > 0) {
-      fetch(er[min(lane, last)], nxt);
-      rec = er[min(64 + lane, last)];
+      int r0, q0;
+      locate(0, r0, q0);
+      fetch(r0, q0, fr[r0].slot, nxt);
+      locate(64, recN, vqN);
+      slotN = fr[recN].slot;
     }
     for (int b = 0; b < n_edge; b += 64) {
       const EdgeData d = nxt;
-      const int2 r = rec;
-      rec = er[min(b + 128 + lane, last)];
-      fetch(r, nxt);
+      const int r = recN, q = vqN;
+      const uint32_t sl = slotN;
+      locate(b + 128, recN, vqN);
+      slotN = fr[recN].slot;
+      fetch(r, q, sl, nxt);
       batch(b, d);
     }
     if (qD > 0) drain(L, L.qD, L.oD, qD, qD, true, lane, K.fd);
@@ -1117,14 +1156,13 @@ void exact_integral_batch(Ctx &ctx, const std::vector<ExactJob> &jobs, int preci
     const int64_t grid = std::min<int64_t>((int64_t)n_cu * std::min(blocks_per_cu, per_cu), div_up(n_chunks, kFlatWaves));
     const int64_t waves = grid * kFlatWaves;
     FaceRec *faces = ctx.arena.get<FaceRec>("flat_faces", waves * kEntryCap);
-    int2 *edges = ctx.arena.get<int2>("flat_edges", waves * 64 * kEdgeCap);
     KernelTimer kz(&ctx, "flat_reset", s);
     k_zero_i32<<<1, 64, 0, s>>>(next, 2);
     SPH_LAUNCH_CHECK();
     kz.done();
     KernelTimer kt(&ctx, "exact_integral", s);
     (ctr ? k_exact_edges<true> : k_exact_edges<false>)<<<(unsigned)grid, 64 * kFlatWaves, 0, s>>>(
-        d_inst, d_c0, n_inst, per_fetch, ctr, faces, edges, next, redo, next + 1);
+        d_inst, d_c0, n_inst, per_fetch, ctr, faces, next, redo, next + 1);
     SPH_LAUNCH_CHECK();
     kt.done();
   };
@@ -1167,7 +1205,7 @@ size_t exact_workspace_bytes(Ctx &ctx, int64_t n_pairs) {
   exact_occupancy(ctx);
   const int64_t grid = std::min<int64_t>((int64_t)ctx.n_cu * ctx.exact_per_cu, div_up(div_up(n_pairs, 64), kFlatWaves));
   const int64_t waves = std::max<int64_t>(grid, 1) * kFlatWaves;
-  return (size_t)(waves * (kEntryCap * sizeof(FaceRec) + 64 * kEdgeCap * sizeof(int2)) + n_pairs * sizeof(int64_t));
+  return (size_t)(waves * kEntryCap * sizeof(FaceRec) + n_pairs * sizeof(int64_t));
 }
 
 void exact_integral(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, int precision, hipStream_t s) {
