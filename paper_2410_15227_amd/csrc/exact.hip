@@ -723,7 +723,7 @@ __device__ inline void wave_fence() {
 // binary64 geometry are listed for the one-pair-per-lane kernel.
 constexpr int kMaxFaces = 64;              // faces per cell handled here
 constexpr int kEntryCap = 64 * kMaxFaces;  // face entries per chunk
-constexpr int kEdgeCap = 128;              // candidate edges per pair handled here
+constexpr int kEdgeCap = 256;              // candidate edges per pair handled here
 constexpr int kQueue = 128;                // items per LDS queue
 
 struct __align__(16) FaceRec {  // a face within reach of a pair
@@ -748,7 +748,7 @@ struct EdgeWave {  // per-wavefront LDS
   double4 wpl[64];  // window of the chunk's faces: plane
   union {
     Sphere wsp[64];               // cull: the window's bounding spheres
-    unsigned long long sb[256];   // edge walk: bit g set where a face's edges start
+    unsigned long long sb[kEdgeCap];  // edge walk: bit g set where a face's edges start (64 kEdgeCap bits)
   };
   int wvs[64], wnv[64];  // first vertex slot, vertex count
   unsigned long long acc[64];
@@ -1038,7 +1038,8 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
     // bounds.
     int cnt = 0, qc = 0;
     auto locate = [&](int bb, int &rec, int &vq) {
-      const unsigned long long w = L.sb[bb >> 6];  // the same word in every lane
+      // the same word in every lane; past n_edge (look-ahead) its bits are unused
+      const unsigned long long w = L.sb[min(bb >> 6, kEdgeCap - 1)];
       const unsigned long long S = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(w >> 32)) << 32) |
                                    (unsigned)__builtin_amdgcn_readfirstlane((unsigned)w);
       const unsigned long long upto = S & lanes_in(0, lane + 1);
