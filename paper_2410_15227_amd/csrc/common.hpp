@@ -185,6 +185,10 @@ void scan_exclusive_i64(Arena &ar, const int64_t *in, int64_t *out, int64_t n, b
 // stable LSD radix sort of (key, value) pairs on the low `bits` bits.
 void radix_sort_u64(Arena &ar, uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s);
 void radix_sort_u32(Arena &ar, uint32_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s);
+// Stable sort of n (key, a, b) triples by the low `bits` bits of key, from the
+// input arrays into the output arrays (which must not overlap them).
+void sort_by_key_kv(Arena &ar, int64_t n, int bits, const uint32_t *kin, const int32_t *ain, const double *bin,
+                    uint32_t *kout, int32_t *aout, double *bout, hipStream_t s);
 // 63-bit Morton keys (21 bits per axis) of points in [lo, lo+size)^3,
 // interleaved x (bit 0), y (bit 1), z (bit 2) at each level.
 void morton_keys(const double *xyz, int stride, int64_t n, double lo0, double lo1, double lo2, double size,

@@ -233,6 +233,187 @@ void radix_sort_impl(Arena &ar, K *keys, int32_t *vals, int64_t n, int bits, hip
 
 }  // namespace
 
+// ------------------------------------------- stable sort by key, two payloads
+// LSD passes of up to 10 key bits.  A tile of 2048 items is split into four
+// 512-item runs, one per wavefront, taken 64 at a time in input order; a lane
+// finds the lanes that share its digit from one ballot per digit bit, so its
+// rank is the running count of the digit in its wave plus the matching lanes
+// below it.  The tile is then laid out digit by digit in LDS and written out
+// with consecutive threads on consecutive positions of each digit's run.
+namespace {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kSortWaveItems = kSortTile / 4;
+
+template <int NB>
+__global__ void __launch_bounds__(kSortThreads) k_kv_hist(const uint32_t *key, int64_t n, int shift, int rb,
+                                                         int64_t ntiles, int64_t *hist) {
+  __shared__ unsigned h[NB];
+  const int nd = 1 << rb;
+  for (int d = threadIdx.x; d < nd; d += kSortThreads) h[d] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const unsigned mask = (unsigned)nd - 1u;
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int64_t i = base + (int64_t)j * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(key[i] >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < nd; d += kSortThreads) hist[(int64_t)d * ntiles + blockIdx.x] = h[d];
+}
+
+template <int NB>
+__global__ void __launch_bounds__(kSortThreads) k_kv_scatter(const uint32_t *kin, const int32_t *ain,
+                                                            const double *bin, int64_t n, int shift, int rb,
+                                                            int64_t ntiles, const int64_t *off, uint32_t *kout,
+                                                            int32_t *aout, double *bout) {
+  constexpr int kPer = NB / kSortThreads > 0 ? NB / kSortThreads : 1;  // digits per thread
+  __shared__ unsigned cnt[4][NB];  // per wave: running count, then the wave's offset
+  __shared__ unsigned tex[NB];     // the tile's exclusive offset per digit
+  __shared__ int64_t goff[NB];     // output position of the digit's run minus tex
+  __shared__ uint32_t sk[kSortTile];
+  __shared__ int32_t sa[kSortTile];
+  __shared__ double sbv[kSortTile];
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int nd = 1 << rb;
+  const unsigned mask = (unsigned)nd - 1u;
+  for (int d = t; d < nd; d += kSortThreads) cnt[0][d] = cnt[1][d] = cnt[2][d] = cnt[3][d] = 0u;
+  __syncthreads();
+  const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+  const int64_t wbase = tile0 + (int64_t)w * kSortWaveItems;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes below this one
+  uint32_t kk[kSortItems];
+  int32_t aa[kSortItems];
+  double bb[kSortItems];
+  unsigned rk[kSortItems];  // rank within the wave's run | digit << 16; ~0 for no item
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int64_t i = wbase + (int64_t)j * 64 + lane;
+    const bool valid = i < n;
+    kk[j] = valid ? kin[i] : 0u;
+    aa[j] = valid ? ain[i] : 0;
+    bb[j] = valid ? bin[i] : 0.0;
+    const unsigned d = (kk[j] >> shift) & mask;
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < rb; ++b) {
+      const bool set = (d >> b) & 1u;
+      const uint64_t bal = __ballot(set);
+      peers &= set ? bal : ~bal;
+    }
+    const unsigned r = (unsigned)__popcll(peers & lt);
+    const unsigned c = valid ? cnt[w][d] : 0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (valid && r == 0u) cnt[w][d] = c + (unsigned)__popcll(peers);  // the digit's first lane
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    rk[j] = valid ? ((c + r) | (d << 16)) : ~0u;
+  }
+  __syncthreads();
+  // per digit: each wave's offset inside the digit's run, the run's length,
+  // and an exclusive scan of the lengths over the digits
+  unsigned loc[kPer];
+  unsigned sum = 0u;
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) {
+    const int d = t * kPer + m;
+    loc[m] = 0u;
+    if (d < nd) {
+      const unsigned c0 = cnt[0][d], c1 = cnt[1][d], c2 = cnt[2][d], c3 = cnt[3][d];
+      cnt[0][d] = 0u;
+      cnt[1][d] = c0;
+      cnt[2][d] = c0 + c1;
+      cnt[3][d] = c0 + c1 + c2;
+      loc[m] = c0 + c1 + c2 + c3;
+      sum += loc[m];
+    }
+  }
+  unsigned tot;
+  unsigned ex = block_exclusive_scan<unsigned>(sum, &tot);
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) {
+    const int d = t * kPer + m;
+    if (d < nd) {
+      tex[d] = ex;
+      goff[d] = off[(int64_t)d * ntiles + blockIdx.x] - (int64_t)ex;
+      ex += loc[m];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    if (rk[j] != ~0u) {
+      const unsigned d = rk[j] >> 16;
+      const unsigned p = tex[d] + cnt[w][d] + (rk[j] & 0xffffu);
+      sk[p] = kk[j];
+      sa[p] = aa[j];
+      sbv[p] = bb[j];
+    }
+  }
+  __syncthreads();
+  const int nt = (int)std::min<int64_t>(kSortTile, n - tile0);
+  for (int p = t; p < nt; p += kSortThreads) {
+    const uint32_t k = sk[p];
+    const int64_t g = goff[(k >> shift) & mask] + p;
+    if (g >= 0 && g < n) {  // always true for a consistent histogram; keeps the store in bounds
+      kout[g] = k;
+      aout[g] = sa[p];
+      bout[g] = sbv[p];
+    }
+  }
+}
+
+template <int NB>
+void kv_pass(Arena &ar, int64_t n, int shift, int rb, const uint32_t *kin, const int32_t *ain, const double *bin,
+             uint32_t *kout, int32_t *aout, double *bout, hipStream_t s) {
+  const int64_t ntiles = div_up(n, kSortTile);
+  const int64_t m = ((int64_t)1 << rb) * ntiles;
+  int64_t *hist = ar.get<int64_t>("kv_hist", m + 1);
+  int64_t *off = ar.get<int64_t>("kv_off", m + 1);
+  k_kv_hist<NB><<<(unsigned)ntiles, kSortThreads, 0, s>>>(kin, n, shift, rb, ntiles, hist);
+  SPH_LAUNCH_CHECK();
+  scan_exclusive_i64(ar, hist, off, m, false, s);
+  k_kv_scatter<NB><<<(unsigned)ntiles, kSortThreads, 0, s>>>(kin, ain, bin, n, shift, rb, ntiles, off, kout, aout,
+                                                              bout);
+  SPH_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+void sort_by_key_kv(Arena &ar, int64_t n, int bits, const uint32_t *kin, const int32_t *ain, const double *bin,
+                    uint32_t *kout, int32_t *aout, double *bout, hipStream_t s) {
+  if (n <= 0) return;
+  SPH_REQUIRE(n < ((int64_t)1 << 31), SPHMAP_EINVAL, "sort length out of range");
+  SPH_REQUIRE(bits >= 1 && bits <= 32, SPHMAP_EINVAL, "sort key bits out of range");
+  const int passes = (bits + 9) / 10;
+  const int rb0 = (bits + passes - 1) / passes;
+  uint32_t *kt[2] = {ar.get<uint32_t>("kv_k0", n), passes > 2 ? ar.get<uint32_t>("kv_k1", n) : nullptr};
+  int32_t *at[2] = {ar.get<int32_t>("kv_a0", n), passes > 2 ? ar.get<int32_t>("kv_a1", n) : nullptr};
+  double *bt[2] = {ar.get<double>("kv_b0", n), passes > 2 ? ar.get<double>("kv_b1", n) : nullptr};
+  const uint32_t *ks = kin;
+  const int32_t *as = ain;
+  const double *bs = bin;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = p * rb0, rb = std::min(rb0, bits - shift);
+    const bool last = p == passes - 1;
+    uint32_t *kd = last ? kout : kt[p & 1];
+    int32_t *ad = last ? aout : at[p & 1];
+    double *bd = last ? bout : bt[p & 1];
+    if (rb <= 8)
+      kv_pass<256>(ar, n, shift, rb, ks, as, bs, kd, ad, bd, s);
+    else
+      kv_pass<1024>(ar, n, shift, rb, ks, as, bs, kd, ad, bd, s);
+    ks = kd;
+    as = ad;
+    bs = bd;
+  }
+}
+
 void radix_sort_u64(Arena &ar, uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s) {
   radix_sort_impl<uint64_t>(ar, keys, vals, n, bits, s, "rs64");
 }

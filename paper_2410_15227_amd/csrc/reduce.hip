@@ -52,27 +52,15 @@ __global__ void k_part_offsets(int64_t NP, int64_t N, const uint32_t *key, int64
   for (int64_t j = lo + 1; j <= hi; ++j) part_off[j] = k;
 }
 
-__global__ void k_copy_u32(int64_t P, const int32_t *src, uint32_t *dst) {
-  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < P) dst[k] = (uint32_t)src[k];
-}
-
 // one wave per particle: gather its pairs in ascending cell order
-__global__ void __launch_bounds__(256) k_coverage(int64_t N, const int64_t *poff, const int32_t *perm,
-                                                 const int32_t *pair_c, const double *w, int32_t *pm_cell,
-                                                 double *pm_w, double *cov) {
+// c_i = sum_c w_ic over the particle's run of the particle-major list.
+__global__ void __launch_bounds__(256) k_coverage(int64_t N, const int64_t *poff, const double *pm_w, double *cov) {
   const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (i >= N) return;
   const int64_t s = poff[i], e = poff[i + 1];
   double acc = 0.0;
-  for (int64_t j = s + lane; j < e; j += 64) {
-    const int32_t k = perm[j];
-    const double wk = w[k];
-    pm_cell[j] = pair_c[k];
-    pm_w[j] = wk;
-    acc += wk;
-  }
+  for (int64_t j = s + lane; j < e; j += 64) acc += pm_w[j];
   acc = wave_sum(acc);
   if (lane == 0) cov[i] = acc;
 }
@@ -151,20 +139,16 @@ void particle_major(Ctx &ctx, PairsDev &P, hipStream_t s) {
   P.coverage = P.mem.get<double>("coverage", N);
   KernelTimer kt(&ctx, "transpose", s);
   if (NP > 0) {
-    // stable sort of the pair positions by particle: each particle's pairs
-    // keep ascending cell order
+    // stable sort of the (particle, cell, w) triples by particle: each
+    // particle's pairs keep ascending cell order, and cell and weight move
+    // with the key, so nothing is gathered afterwards
     uint32_t *keys = ar.get<uint32_t>("pm_keys", NP);
-    int32_t *perm = ar.get<int32_t>("pm_perm", NP);
-    k_copy_u32<<<(unsigned)div_up(NP, 256), 256, 0, s>>>(NP, P.pair_p, keys);
-    SPH_LAUNCH_CHECK();
-    iota_i32(perm, NP, s);
     int bits = 1;
     while (bits < 32 && ((int64_t)1 << bits) < N) ++bits;
-    radix_sort_u32(ar, keys, perm, NP, bits, s);
+    sort_by_key_kv(ar, NP, bits, (const uint32_t *)P.pair_p, P.pair_c, P.w, keys, P.pm_cell, P.pm_w, s);
     k_part_offsets<<<(unsigned)div_up(NP + 1, 256), 256, 0, s>>>(NP, N, keys, P.part_off);
     SPH_LAUNCH_CHECK();
-    k_coverage<<<(unsigned)div_up(N * 64, 256), 256, 0, s>>>(N, P.part_off, perm, P.pair_c, P.w, P.pm_cell, P.pm_w,
-                                                             P.coverage);
+    k_coverage<<<(unsigned)div_up(N * 64, 256), 256, 0, s>>>(N, P.part_off, P.pm_w, P.coverage);
     SPH_LAUNCH_CHECK();
   } else {
     fill_i64(P.part_off, 0, N + 1, s);
