@@ -247,6 +247,15 @@ constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kSortWaveItems = kSortTile / 4;
 
+// Workgroups are dealt to the 8 XCDs in turn; give each XCD a contiguous run
+// of tiles, so that neighbouring tiles -- which fill the same output lines
+// of each digit -- share one L2.
+__device__ inline int64_t xcd_tile(int64_t ntiles) {
+  const int64_t b = blockIdx.x, x = b & 7, k = b >> 3;
+  const int64_t q = ntiles >> 3, r = ntiles & 7;  // XCD x takes q + (x < r) tiles
+  return x * q + (x < r ? x : r) + k;
+}
+
 template <int NB>
 __global__ void __launch_bounds__(kSortThreads) k_kv_hist(const uint32_t *key, int64_t n, int shift, int rb,
                                                          int64_t ntiles, int64_t *hist) {
@@ -282,20 +291,27 @@ __global__ void __launch_bounds__(kSortThreads) k_kv_scatter(const uint32_t *kin
   const unsigned mask = (unsigned)nd - 1u;
   for (int d = t; d < nd; d += kSortThreads) cnt[0][d] = cnt[1][d] = cnt[2][d] = cnt[3][d] = 0u;
   __syncthreads();
-  const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+  const int64_t tile = xcd_tile(ntiles);
+  const int64_t tile0 = tile * kSortTile;
   const int64_t wbase = tile0 + (int64_t)w * kSortWaveItems;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes below this one
   uint32_t kk[kSortItems];
   int32_t aa[kSortItems];
   double bb[kSortItems];
   unsigned rk[kSortItems];  // rank within the wave's run | digit << 16; ~0 for no item
+  // all of the wave's loads first, so that they are in flight together
 #pragma unroll
   for (int j = 0; j < kSortItems; ++j) {
-    const int64_t i = wbase + (int64_t)j * 64 + lane;
-    const bool valid = i < n;
-    kk[j] = valid ? kin[i] : 0u;
-    aa[j] = valid ? ain[i] : 0;
-    bb[j] = valid ? bin[i] : 0.0;
+    const int64_t i = std::min(wbase + (int64_t)j * 64 + lane, n - 1);  // past n: read, not used
+    kk[j] = kin[i];
+    aa[j] = ain[i];
+    bb[j] = bin[i];
+  }
+  // rank round by round; a wave's LDS operations complete in order, so the
+  // counter a lane reads is the one the previous round's first lane wrote
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const bool valid = wbase + (int64_t)j * 64 + lane < n;
     const unsigned d = (kk[j] >> shift) & mask;
     uint64_t peers = __ballot(valid);
     for (int b = 0; b < rb; ++b) {
@@ -305,13 +321,7 @@ __global__ void __launch_bounds__(kSortThreads) k_kv_scatter(const uint32_t *kin
     }
     const unsigned r = (unsigned)__popcll(peers & lt);
     const unsigned c = valid ? cnt[w][d] : 0u;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (valid && r == 0u) cnt[w][d] = c + (unsigned)__popcll(peers);  // the digit's first lane
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     rk[j] = valid ? ((c + r) | (d << 16)) : ~0u;
   }
   __syncthreads();
@@ -340,7 +350,7 @@ __global__ void __launch_bounds__(kSortThreads) k_kv_scatter(const uint32_t *kin
     const int d = t * kPer + m;
     if (d < nd) {
       tex[d] = ex;
-      goff[d] = off[(int64_t)d * ntiles + blockIdx.x] - (int64_t)ex;
+      goff[d] = off[(int64_t)d * ntiles + tile] - (int64_t)ex;
       ex += loc[m];
     }
   }
@@ -406,6 +416,8 @@ void sort_by_key_kv(Arena &ar, int64_t n, int bits, const uint32_t *kin, const i
     double *bd = last ? bout : bt[p & 1];
     if (rb <= 8)
       kv_pass<256>(ar, n, shift, rb, ks, as, bs, kd, ad, bd, s);
+    else if (rb == 9)
+      kv_pass<512>(ar, n, shift, rb, ks, as, bs, kd, ad, bd, s);
     else
       kv_pass<1024>(ar, n, shift, rb, ks, as, bs, kd, ad, bd, s);
     ks = kd;
