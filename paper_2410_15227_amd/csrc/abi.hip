@@ -561,18 +561,21 @@ int sphmap_estimate_footprint(sphmap_ctx *ctx, int64_t n_particles, int64_t n_pa
     // out whole 2 MiB granules, once per named buffer
     auto grown = [](double b, int n_buffers) { return (size_t)(b * 1.125 + 2097152.0 * n_buffers); };
     // per particle: staged float4, Morton key + index, sorted copy, radix
-    // temporaries, search boxes; per pair: transpose keys, permutation and
-    // radix temporaries; per cell: pair counts, the bounded candidate buffer
-    // of the pair search (384 entries), the overflow list
-    const double ws = 16.0 * N + 12.0 * N + 16.0 * N + 12.0 * N + 3.0 * N + 16.0 * P + (8.0 + 1536.0 + 4.0) * C +
-                      (double)sphmap::exact_workspace_bytes(ctx->c, P);
+    // temporaries, search boxes; per pair: the transpose's sorted keys, one
+    // set of (key, cell, weight) temporaries (two above 2^20 particles, when
+    // the sort takes three passes) and its digit histograms; per cell: pair
+    // counts, the bounded candidate buffer of the pair search (512 entries),
+    // the overflow list
+    const double per_pair = 4.0 + (N > ((int64_t)1 << 20) ? 32.0 : 16.0) + 8.0;
+    const double ws = 16.0 * N + 12.0 * N + 16.0 * N + 12.0 * N + 3.0 * N + per_pair * P +
+                      (8.0 + 2048.0 + 4.0) * C + (double)sphmap::exact_workspace_bytes(ctx->c, P);
     // retained list: cell offsets, pair indices, weights, particle-major
     // copy, particle offsets and coverage
     const double pr = 8.0 * C + (4.0 + 4.0 + 8.0 + 4.0 + 8.0) * P + 16.0 * N;
     // grid: generators, offsets, orders and volumes per cell; planes, spheres
     // and cell per face; oriented vertices and edge frames per face vertex
     const double tb = 96.0 * C + 96.0 * n_faces + 96.0 * n_face_vertices + 24.0 * n_vertices;
-    out->workspace = grown(ws, 48);
+    out->workspace = grown(ws, 56);
     out->pairs = grown(pr, 8);
     out->tessellation = grown(tb, 24);
   });

@@ -78,7 +78,8 @@ __device__ inline bool canon_pair(const float4 &p, const float4 &g) {
 // Walk modes: kFill writes the list straight into the CSR (offsets known);
 // otherwise the first kCap candidates go to the cell's slot of a bounded
 // buffer and all are counted.
-constexpr int kCap = 384;
+constexpr int kCap = 512;
+static_assert((kCap & (kCap - 1)) == 0, "the LDS sort pads a list to a power of two up to kCap");
 
 template <bool kFill>
 __global__ void __launch_bounds__(128) k_pairs(Hier H, int64_t C, const int32_t *cell_order, const float4 *gen32,
@@ -193,7 +194,7 @@ __device__ void merge_block(const int32_t *A, int na, const int32_t *B, int nb, 
 __global__ void __launch_bounds__(256) k_compact_sort(int64_t C, const int64_t *off, const int32_t *buf,
                                                       int32_t *pair_p, int32_t *pair_c, int32_t *over,
                                                       int32_t *n_over) {
-  __shared__ int32_t lds[512];
+  __shared__ int32_t lds[kCap];
   const int64_t c = blockIdx.x;
   const int64_t s = off[c];
   const int n = (int)(off[c + 1] - s);
