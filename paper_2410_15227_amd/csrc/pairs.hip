@@ -79,7 +79,6 @@ __device__ inline bool canon_pair(const float4 &p, const float4 &g) {
 // otherwise the first kCap candidates go to the cell's slot of a bounded
 // buffer and all are counted.
 constexpr int kCap = 512;
-static_assert((kCap & (kCap - 1)) == 0, "the LDS sort pads a list to a power of two up to kCap");
 
 template <bool kFill>
 __global__ void __launch_bounds__(128) k_pairs(Hier H, int64_t C, const int32_t *cell_order, const float4 *gen32,
@@ -189,26 +188,77 @@ __device__ void merge_block(const int32_t *A, int na, const int32_t *B, int nb, 
   }
 }
 
-// Lists that fitted the bounded buffer: sorted in LDS and written to the CSR
-// with their cell; the others are listed for a second walk.
+// Bitonic sort of 64 R keys held by one wavefront, key r * 64 + lane in
+// v[r]: distances of 64 and more pair registers of the same lane, shorter
+// ones pair lanes (an exchange across lanes); no LDS and no barriers.
+template <int R>
+__device__ inline void wave_bitonic(int32_t (&v)[R], int lane) {
+  constexpr int m = 64 * R;
+#pragma unroll
+  for (int size = 2; size <= m; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      if (stride >= 64) {
+        const int rs = stride >> 6;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if ((r & rs) == 0) {
+            const bool up = ((r * 64) & size) == 0;
+            const int32_t a = v[r], b = v[r | rs];
+            v[r] = up ? min(a, b) : max(a, b);
+            v[r | rs] = up ? max(a, b) : min(a, b);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int32_t o = __shfl_xor(v[r], stride, 64);
+          const bool up = ((r * 64 + lane) & size) == 0;
+          const bool lower = (lane & stride) == 0;
+          v[r] = (lower == up) ? min(v[r], o) : max(v[r], o);
+        }
+      }
+    }
+  }
+}
+
+template <int R>
+__device__ inline void wave_sort_copy(const int32_t *src, int32_t *dst, int n, int lane) {
+  int32_t v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = r * 64 + lane < n ? src[r * 64 + lane] : INT32_MAX;
+  wave_bitonic<R>(v, lane);
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (r * 64 + lane < n) dst[r * 64 + lane] = v[r];
+}
+
+// Lists that fitted the bounded buffer: each sorted by one wavefront in
+// registers and written to the CSR with its cell; the others are listed for
+// a second walk.
+static_assert(kCap <= 512, "a wavefront sorts at most 8 keys per lane");
 __global__ void __launch_bounds__(256) k_compact_sort(int64_t C, const int64_t *off, const int32_t *buf,
                                                       int32_t *pair_p, int32_t *pair_c, int32_t *over,
                                                       int32_t *n_over) {
-  __shared__ int32_t lds[kCap];
-  const int64_t c = blockIdx.x;
+  const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;  // one cell per wavefront
+  const int lane = threadIdx.x & 63;
+  if (c >= C) return;
   const int64_t s = off[c];
   const int n = (int)(off[c + 1] - s);
   if (n > kCap) {
-    if (threadIdx.x == 0) over[atomicAdd(n_over, 1)] = (int32_t)c;
+    if (lane == 0) over[atomicAdd(n_over, 1)] = (int32_t)c;
     return;
   }
-  for (int k = threadIdx.x; k < n; k += blockDim.x) pair_c[s + k] = (int32_t)c;
-  if (n == 0) return;
-  if (n == 1) {
-    if (threadIdx.x == 0) pair_p[s] = buf[c * kCap];
-    return;
-  }
-  sort_run_lds(lds, buf + c * kCap, pair_p + s, n);
+  for (int k = lane; k < n; k += 64) pair_c[s + k] = (int32_t)c;
+  const int32_t *src = buf + c * kCap;
+  if (n <= 64)
+    wave_sort_copy<1>(src, pair_p + s, n, lane);
+  else if (n <= 128)
+    wave_sort_copy<2>(src, pair_p + s, n, lane);
+  else if (n <= 256)
+    wave_sort_copy<4>(src, pair_p + s, n, lane);
+  else
+    wave_sort_copy<8>(src, pair_p + s, n, lane);
 }
 
 __global__ void __launch_bounds__(256) k_sort_segments(int64_t C, const int64_t *off, int32_t *pair_p, int32_t *tmp,
@@ -308,7 +358,7 @@ void find_pairs(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, hipSt
   SPH_HIP(hipMemsetAsync(n_over, 0, sizeof(int32_t), s));
   {
     KernelTimer kt(&ctx, "pair_fill", s);
-    k_compact_sort<<<(unsigned)C, 256, 0, s>>>(C, P.cell_off, buf, P.pair_p, P.pair_c, over, n_over);
+    k_compact_sort<<<(unsigned)div_up(C, 4), 256, 0, s>>>(C, P.cell_off, buf, P.pair_p, P.pair_c, over, n_over);
     SPH_LAUNCH_CHECK();
     kt.done();
   }
