@@ -734,6 +734,7 @@ struct __align__(16) FaceRec {  // a face within reach of a pair
   uint32_t slot;     // bits 0-23: first vertex slot - the chunk's first; 24-31: lane of the pair
 };
 constexpr int64_t kSlotSpan = 1 << 24;  // vertex slots a chunk's faces may span
+static_assert(sizeof(FaceRec) == 32, "records are addressed as index << 5");
 
 struct EdgeData {  // what one lane reads for its edge: face record and edge geometry
   FaceRec fc;
@@ -760,14 +761,40 @@ struct EdgeWave {  // per-wavefront LDS
 template <typename T>
 using gptr = const __attribute__((address_space(1))) T *;
 
+// a value the whole wave holds alike, moved to scalar registers
+__device__ inline int64_t uniform64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ inline float4 load4(gptr<float4> p, int64_t i) {
   const gptr<float> q = (gptr<float>)(p + i);
+  return make_float4(q[0], q[1], q[2], q[3]);
+}
+
+__device__ inline float4 load4(gptr<float4> p, uint32_t i) {
+  const gptr<float> q = (gptr<float>)((gptr<char>)p + (i << 4));  // i < 2^28
   return make_float4(q[0], q[1], q[2], q[3]);
 }
 
 __device__ inline double4 load4(gptr<double4> p, int64_t i) {
   const gptr<double> q = (gptr<double>)(p + i);
   return make_double4(q[0], q[1], q[2], q[3]);
+}
+
+// face record rec of a wave's region (a 32-bit byte offset from its base)
+__device__ inline FaceRec load_rec(gptr<FaceRec> base, int rec) {
+  const gptr<float> q = (gptr<float>)((gptr<char>)base + ((uint32_t)rec << 5));
+  FaceRec r;
+  r.px = q[0];
+  r.py = q[1];
+  r.pz = q[2];
+  r.df = q[3];
+  r.dh = *(gptr<double>)(q + 4);
+  r.ihf = q[6];
+  r.slot = *(gptr<uint32_t>)(q + 7);
+  return r;
 }
 
 __device__ inline uint64_t lanes_in(int lo, int hi) {  // bits [lo, hi), 0 <= lo <= hi <= 64
@@ -814,10 +841,10 @@ template <bool kCount>
 // Three waves per SIMD: the edge phase keeps the next batch's face and edge
 // data in registers (about 165 VGPRs); at four the pipeline would spill.
 __global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
-    const ExactInst *insts, const int64_t *chunk0, int n_inst, int per_fetch, int64_t *counters, FaceRec *faces,
+    const ExactInst *__restrict__ insts, const int64_t *__restrict__ chunk0, int n_inst, int per_fetch, int64_t *counters, FaceRec *faces,
     int32_t *next_chunk, int64_t *redo, int32_t *n_redo) {
   __shared__ EdgeWave lds[kFlatWaves];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   EdgeWave &L = lds[wid];
   const int64_t wave = (int64_t)blockIdx.x * kFlatWaves + wid;
   FaceRec *const fr = faces + wave * kEntryCap;
@@ -850,9 +877,9 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
     // The chunk's pairs are sorted by cell, so their faces are one range
     // [F0, F1); it is staged through LDS 64 faces at a time.
     const int64_t k_last = min(chunk * 64 + 63, P - 1);
-    const int64_t F0 = cfo[pair_c[chunk * 64]], F1 = cfo[pair_c[k_last] + 1];
+    const int64_t F0 = uniform64(cfo[pair_c[chunk * 64]]), F1 = uniform64(cfo[pair_c[k_last] + 1]);
     // vertex slots of the chunk's faces, kept relative to the first in 24 bits
-    const int64_t VB = fvo[F0];
+    const int64_t VB = uniform64(fvo[F0]);
     const bool wide = fvo[F1] - VB > kSlotSpan;
     uint64_t mask = 0;
     int nsurv = 0, nedge = 0;
@@ -921,8 +948,9 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
     }
     const int e_off = wave_scan_excl(nsurv, lane);
     const int x_off = wave_scan_excl(nedge, lane);
-    const int n_edge = __shfl(x_off + nedge, 63, 64);
-    const int n_rec = __shfl(e_off + nsurv, 63, 64);
+    // wave-uniform counts in scalar registers (the edge walk's loop bound)
+    const int n_edge = __builtin_amdgcn_readlane(x_off + nedge, 63);
+    const int n_rec = __builtin_amdgcn_readlane(e_off + nsurv, 63);
     L.acc[lane] = 0ull;
     L.redo[lane] = again ? 1 : 0;
     if (kCount) K.nf_int += nsurv;
@@ -1044,8 +1072,11 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
                                    (unsigned)__builtin_amdgcn_readfirstlane((unsigned)w);
       const unsigned long long upto = S & lanes_in(0, lane + 1);
       const bool in = bb + lane < n_edge;
+      // the last start at or below this lane, or -qc when the edge's face began in an earlier batch
+      const int hb = 63 - __builtin_clzll(upto | 1ull), none = upto == 0ull;
+      const int last = hb - none * (hb + qc);  // arithmetic select: no branch
       rec = in ? cnt + __popcll(upto) - 1 : n_rec - 1;
-      vq = !in ? 0 : (upto ? lane - (63 - __builtin_clzll(upto)) : qc + lane);
+      vq = in ? lane - last : 0;
       cnt += __popcll(S);
       qc = S ? __builtin_clzll(S) + 1 : qc + 64;
     };
@@ -1054,12 +1085,17 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
     // flight.  The loads are unconditional (lanes past n_edge fetch valid
     // but unused data), so no loaded register is merged or copied before the
     // loop's next turn; a copy would wait for its load.
+    // the chunk's edge frames and the wave's face records from scalar bases
+    // and 32-bit offsets (a chunk spans fewer than 2^24 slots, a wave holds
+    // 4096 records)
+    const gptr<FaceRec> frg = (gptr<FaceRec>)fr;
+    const gptr<float4> cA = edgeA + VB, cE = edgeE + VB, cM = edgeM + VB;
     auto fetch = [&](int rec, int vq, uint32_t slot, EdgeData &d) {
-      d.fc = fr[rec];
-      const int64_t v = VB + (int64_t)(slot & 0xffffffu) + vq;
-      d.ea = load4(edgeA, v);
-      d.ee = load4(edgeE, v);
-      d.em = load4(edgeM, v);
+      d.fc = load_rec(frg, rec);
+      const uint32_t v = (slot & 0xffffffu) + (uint32_t)vq;
+      d.ea = load4(cA, v);
+      d.ee = load4(cE, v);
+      d.em = load4(cM, v);
     };
     EdgeData nxt{};
     int recN = 0, vqN = 0;
@@ -1067,16 +1103,16 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
     if (n_edge > 0) {
       int r0, q0;
       locate(0, r0, q0);
-      fetch(r0, q0, fr[r0].slot, nxt);
+      fetch(r0, q0, *(gptr<uint32_t>)((gptr<char>)frg + ((uint32_t)r0 << 5) + 28), nxt);
       locate(64, recN, vqN);
-      slotN = fr[recN].slot;
+      slotN = *(gptr<uint32_t>)((gptr<char>)frg + ((uint32_t)recN << 5) + 28);
     }
     for (int b = 0; b < n_edge; b += 64) {
       const EdgeData d = nxt;
       const int r = recN, q = vqN;
       const uint32_t sl = slotN;
       locate(b + 128, recN, vqN);
-      slotN = fr[recN].slot;
+      slotN = *(gptr<uint32_t>)((gptr<char>)frg + ((uint32_t)recN << 5) + 28);
       fetch(r, q, sl, nxt);
       batch(b, d);
     }
