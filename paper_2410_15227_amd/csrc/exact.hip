@@ -838,9 +838,10 @@ __device__ inline int drain(EdgeWave &L, float4 *q, unsigned char *o, int len, i
 }
 
 template <bool kCount>
-// Three waves per SIMD: the edge phase keeps the next batch's face and edge
-// data in registers (about 165 VGPRs); at four the pipeline would spill.
-__global__ void __launch_bounds__(64 * kFlatWaves, 3) k_exact_edges(
+// Four waves per SIMD (128 VGPRs; 4 workgroups of 38 KB LDS per CU): the
+// few values that spill are the chunk's and the fetch's, stored and reloaded
+// outside the edge walk and the queue evaluation.
+__global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
     const ExactInst *__restrict__ insts, const int64_t *__restrict__ chunk0, int n_inst, int per_fetch, int64_t *counters, FaceRec *faces,
     int32_t *next_chunk, int64_t *redo, int32_t *n_redo) {
   __shared__ EdgeWave lds[kFlatWaves];
