@@ -80,58 +80,82 @@ __device__ inline bool canon_pair(const float4 &p, const float4 &g) {
 // buffer and all are counted.
 constexpr int kCap = 512;
 
+// One wavefront per cell.  A step takes up to four hierarchy nodes of one
+// level from the top of the wave's LDS stack, and its 64 lanes test their
+// 16 children each: boxes that the cell's ball reaches go on the stack,
+// balls that pass the canonical test are appended to the cell's list (in
+// the order of a ballot; the lists are sorted afterwards).  Taking only
+// nodes of the top's level keeps the stack ordered by level with at most
+// 64 nodes pending per level, so 64 kMaxLevels entries always suffice.
+constexpr int kWalkStack = 64 * kMaxLevels;
+
 template <bool kFill>
-__global__ void __launch_bounds__(128) k_pairs(Hier H, int64_t C, const int32_t *cell_order, const float4 *gen32,
+__global__ void __launch_bounds__(256) k_pairs(Hier H, int64_t C, const int32_t *cells, const float4 *gen32,
                                               int64_t *counts, const int64_t *off, int32_t *pair_p,
                                               int32_t *pair_c, int32_t *buf) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ uint32_t stk[4][kWalkStack];  // node << 4 | level
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t t = (int64_t)blockIdx.x * 4 + w;
   if (t >= C) return;
-  const int32_t c = cell_order[t];
+  const int32_t c = cells[t];
   const float4 g = gen32[c];
   const float rr = g.w * 1.00001f + H.margin_abs;
   const float r2 = rr * rr;
+  const int64_t base = kFill ? off[c] : 0;
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));  // lanes below this one
+  uint32_t *S = stk[w];
   int64_t cnt = 0;
-  int64_t base = kFill ? off[c] : 0;
-  // explicit stack of (level, node)
-  int32_t st_node[kFan * kMaxLevels];
-  int8_t st_lvl[kFan * kMaxLevels];
   int sp = 0;
-  const int top = H.levels;
-  for (int64_t j = H.n[top] - 1; j >= 0; --j)
-    if (box_hit(H.lo[top][j], H.hi[top][j], g, r2)) {
-      st_node[sp] = (int32_t)j;
-      st_lvl[sp] = (int8_t)top;
-      ++sp;
-    }
-  while (sp > 0) {
-    --sp;
-    const int l = st_lvl[sp];
-    const int64_t j = st_node[sp];
-    if (l == 1) {
-      const int64_t e = min(H.n[0], (j + 1) * kFan);
-      for (int64_t k = j * kFan; k < e; ++k) {
-        if (canon_pair(H.sx[k], g)) {
-          if (kFill) {
-            pair_p[base + cnt] = H.sidx[k];
-            pair_c[base + cnt] = c;
-          } else if (cnt < kCap) {
-            buf[(int64_t)c * kCap + cnt] = H.sidx[k];
-          }
-          ++cnt;
-        }
-      }
-    } else {
-      const int lc = l - 1;
-      const int64_t e = min(H.n[lc], (j + 1) * kFan);
-      for (int64_t k = e - 1; k >= j * kFan; --k)
-        if (box_hit(H.lo[lc][k], H.hi[lc][k], g, r2)) {
-          st_node[sp] = (int32_t)k;
-          st_lvl[sp] = (int8_t)lc;
-          ++sp;
-        }
-    }
+  {
+    const int top = H.levels;  // at most kFan nodes
+    const bool hit = lane < H.n[top] && box_hit(H.lo[top][lane], H.hi[top][lane], g, r2);
+    const uint64_t m = __ballot(hit);
+    if (hit) S[__popcll(m & lt)] = ((uint32_t)lane << 4) | (uint32_t)top;
+    sp = __popcll(m);
   }
-  if (!kFill) counts[c] = cnt;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  while (sp > 0) {
+    // up to four entries from the top, all of the top entry's level
+    const int lvl = (int)(S[sp - 1] & 15u);
+    const uint32_t peek = lane < 4 && lane < sp ? S[sp - 1 - lane] : 0u;
+    const uint64_t same = __ballot(lane < 4 && lane < sp && (int)(peek & 15u) == lvl);
+    const int take = __builtin_ctzll(~same);  // entries from the top of that level
+    const int q = lane >> 4, ch = lane & 15;
+    const bool act = q < take;
+    const uint32_t e = act ? S[sp - 1 - q] : 0u;
+    sp -= take;
+    const int64_t k = (int64_t)(e >> 4) * kFan + ch;
+    bool ball = false, box = false;
+    if (act) {
+      if (lvl == 1) {
+        ball = k < H.n[0] && canon_pair(H.sx[k], g);
+      } else {
+        const int lc = lvl - 1;
+        box = k < H.n[lc] && box_hit(H.lo[lc][k], H.hi[lc][k], g, r2);
+      }
+    }
+    const uint64_t mb = __ballot(ball);
+    if (ball) {
+      const int64_t pos = cnt + __popcll(mb & lt);
+      const int32_t pid = H.sidx[k];
+      if (kFill) {
+        pair_p[base + pos] = pid;
+        pair_c[base + pos] = c;
+      } else if (pos < kCap) {
+        buf[(int64_t)c * kCap + pos] = pid;
+      }
+    }
+    cnt += __popcll(mb);
+    const uint64_t mx = __ballot(box);
+    if (box) S[sp + __popcll(mx & lt)] = ((uint32_t)k << 4) | (uint32_t)(lvl - 1);
+    sp += __popcll(mx);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  if (!kFill && lane == 0) counts[c] = cnt;
 }
 
 // Sort each cell's particle list ascending: lists of up to kSortCap entries
@@ -339,7 +363,7 @@ void find_pairs(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, hipSt
   // one walk: up to kCap candidates per cell into the bounded buffer, all counted
   {
     KernelTimer kt(&ctx, "pair_count", s);
-    k_pairs<false><<<(unsigned)div_up(C, 128), 128, 0, s>>>(H, C, t.cell_order, t.gen32, counts, nullptr, nullptr,
+    k_pairs<false><<<(unsigned)div_up(C, 4), 256, 0, s>>>(H, C, t.cell_order, t.gen32, counts, nullptr, nullptr,
                                                              nullptr, buf);
     SPH_LAUNCH_CHECK();
     kt.done();
@@ -368,7 +392,7 @@ void find_pairs(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, hipSt
   if (no > 0) {
     // longer lists: walked again straight into the CSR, then sorted
     KernelTimer kt(&ctx, "pair_fill_long", s);
-    k_pairs<true><<<(unsigned)div_up(no, 128), 128, 0, s>>>(H, no, over, t.gen32, nullptr, P.cell_off, P.pair_p,
+    k_pairs<true><<<(unsigned)div_up(no, 4), 256, 0, s>>>(H, no, over, t.gen32, nullptr, P.cell_off, P.pair_p,
                                                              P.pair_c, nullptr);
     SPH_LAUNCH_CHECK();
     int32_t *tmp = ar.get<int32_t>("pp_sort_tmp", std::max<int64_t>(total, 1));
