@@ -235,6 +235,17 @@ __device__ double edge_term(double ad, double p, double tA, double tB, double dh
   return (fb - fa) - dh * (phiB - phiA);
 }
 
+// edge_term with binary64 geometry from the mixed path: the mixed cores seed
+// their square roots, reciprocals and divisions in binary32, so lengths below
+// 1e-15 h (a^2 or p under 1e-30) go to the math library instead.
+template <class M>
+__device__ inline double edge_term_geo64(double ad, double p, double tA, double tB, double dh, bool &integ,
+                                         EdgeCount &cnt) {
+  if (!std::is_same<M, Math64>::value && (ad * ad + p * p < 1e-30 || p < 1e-30))
+    return edge_term<Math64>(ad, p, tA, tB, dh, integ, cnt);
+  return edge_term<M>(ad, p, tA, tB, dh, integ, cnt);
+}
+
 // Signed solid angle of a planar polygon seen from x (Van Oosterom and
 // Strackee 1983 per fan triangle), used only on exact-boundary cases.
 __device__ double solid_angle(const double *V, int nv, double x0, double x1, double x2) {
@@ -268,7 +279,11 @@ __device__ double boundary_S(int64_t f0, int64_t f1, const double4 *fplane, cons
   return om * kInv4Pi;
 }
 
-// One face in binary64: geometry about the generator, particle at xr.
+// One face with binary64 geometry about the generator, particle at xr; the
+// transcendental cores are M's (the math library for the binary64 path, the
+// mixed cores where the mixed path meets a face within 1e-4 h of the
+// particle).
+template <class M>
 __device__ double face_fp64(const double4 pl, double dist, double ih, double xr0, double xr1, double xr2,
                             const double *V, int nv, int &ne_vis, int &ne_int, EdgeCount &cnt) {
   const double d = dist * ih, ad = fabs(d);
@@ -297,7 +312,7 @@ __device__ double face_fp64(const double4 pl, double dist, double ih, double xr0
     const double tA = ((Ax - P0x) * ex + (Ay - P0y) * ey + (Az - P0z) * ez) * ih;
     const double tB = ((Bx - P0x) * ex + (By - P0y) * ey + (Bz - P0z) * ez) * ih;
     bool integ;
-    const double v = edge_term<Math64>(ad, fabs(p), tA, tB, dh, integ, cnt);
+    const double v = edge_term_geo64<M>(ad, fabs(p), tA, tB, dh, integ, cnt);
     anyint |= integ;
     ne_int += integ;
     sum += p > 0.0 ? v : -v;
@@ -379,7 +394,7 @@ __global__ void __launch_bounds__(256) k_exact_fp64(int64_t P, const int32_t *pa
     const double reach = sp.w + 2.0 * h;
     if (sx * sx + sy * sy + sz * sz >= reach * reach) continue;
     ++K.nf_int;
-    acc += face_fp64(pl, dist, ih, xr0, xr1, xr2, fvpos + 3 * fvo[f], (int)(fvo[f + 1] - fvo[f]), K.ne_vis,
+    acc += face_fp64<Math64>(pl, dist, ih, xr0, xr1, xr2, fvpos + 3 * fvo[f], (int)(fvo[f + 1] - fvo[f]), K.ne_vis,
                      K.ne_int, K.fd);
   }
   double S = inside ? 1.0 : 0.0;
@@ -391,134 +406,102 @@ __global__ void __launch_bounds__(256) k_exact_fp64(int64_t P, const int32_t *pa
 // ---------------------------------------------------------- mixed kernel
 constexpr float kDegenerate = 1e-4f;  // p or |d| below this (units of h): binary64 edge
 
-__device__ inline void pair_mixed(int64_t k, const int32_t *pair_c, const int32_t *pair_p, const double *xyz,
-                                  const double *hh, const double *gen, const int64_t *cfo, const int64_t *fvo,
-                                  const double4 *fplane, const float4 *fplane32, const double4 *fsphere,
-                                  const double *fvpos, const float4 *fvpos32, double *w_out, int64_t *counters) {
-  const int64_t c = pair_c[k];
-  const int64_t i = pair_p[k];
-  const double h = hh[i];
-  const double ih = 1.0 / h;
-  const float ihf = (float)ih;
-  const double xr0 = xyz[3 * i] - gen[3 * c], xr1 = xyz[3 * i + 1] - gen[3 * c + 1],
-               xr2 = xyz[3 * i + 2] - gen[3 * c + 2];
-  // particle about the generator, in units of h, binary32
-  const float x0 = (float)(xr0 * ih), x1 = (float)(xr1 * ih), x2 = (float)(xr2 * ih);
-  double acc = 0.0;
-  bool inside = true, on_boundary = false;
-  Counters K;
-  const int64_t f0 = cfo[c], f1 = cfo[c + 1];
-  for (int64_t f = f0; f < f1; ++f) {
-    const double4 pl = fplane[f];
-    if (!(pl.w > 0.0)) continue;
-    const double dist = pl.w - (pl.x * xr0 + pl.y * xr1 + pl.z * xr2);
-    if (dist < 0.0) inside = false;
-    if (dist == 0.0) {
-      on_boundary = true;
-      continue;
-    }
-    if (fabs(dist) >= 2.0 * h) continue;
-    const double4 sp = fsphere[f];
-    const double sx = xr0 - sp.x, sy = xr1 - sp.y, sz = xr2 - sp.z;
-    const double reach = sp.w + 2.0 * h;
-    if (sx * sx + sy * sy + sz * sz >= reach * reach) continue;
-    ++K.nf_int;
-    const int64_t vs = fvo[f];
-    const int nv = (int)(fvo[f + 1] - vs);
-    const double d = dist * ih, ad = fabs(d);
-    if (ad < kDegenerate) {
-      // particle on the face plane to within 1e-4 h: the whole face in binary64
-      K.n64 += nv;
-      acc += face_fp64(pl, dist, ih, xr0, xr1, xr2, fvpos + 3 * vs, nv, K.ne_vis, K.ne_int, K.fd);
-      continue;
-    }
-    const double dh = dH(ad);
-    const float4 pf = fplane32[f];
-    const float df = (float)d;
-    const float P0x = x0 + df * pf.x, P0y = x1 + df * pf.y, P0z = x2 + df * pf.z;
-    double sum = 0.0;
-    bool allpos = true, anyzero = false, anyint = false;
-    float4 A = fvpos32[vs];
-    A.x *= ihf;
-    A.y *= ihf;
-    A.z *= ihf;
-    for (int q = 0; q < nv; ++q) {
-      const int q1 = (q + 1 == nv) ? 0 : q + 1;
-      float4 B = fvpos32[vs + q1];
-      B.x *= ihf;
-      B.y *= ihf;
-      B.z *= ihf;
-      const float abx = B.x - A.x, aby = B.y - A.y, abz = B.z - A.z;
-      const float len2 = abx * abx + aby * aby + abz * abz;
-      if (len2 > 0.0f) {
-        const float il = __builtin_amdgcn_rsqf(len2);
-        const float ex = abx * il, ey = aby * il, ez = abz * il;
-        const float mx = pf.y * ez - pf.z * ey, my = pf.z * ex - pf.x * ez, mz = pf.x * ey - pf.y * ex;
-        const float p = (P0x - A.x) * mx + (P0y - A.y) * my + (P0z - A.z) * mz;
-        if (p <= 0.0f) allpos = false;
-        if (p == 0.0f) {
-          anyzero = true;
-        } else {
-          ++K.ne_vis;
-          bool integ;
-          double v;
-          if (fabsf(p) < kDegenerate) {
-            // foot point within 1e-4 h of the edge line: binary64 geometry
-            ++K.n64;
-            const double *V = fvpos + 3 * vs;
-            const double P0dx = xr0 + dist * pl.x, P0dy = xr1 + dist * pl.y, P0dz = xr2 + dist * pl.z;
-            const double Ax = V[3 * q], Ay = V[3 * q + 1], Az = V[3 * q + 2];
-            const double Bx = V[3 * q1], By = V[3 * q1 + 1], Bz = V[3 * q1 + 2];
-            const double bx = Bx - Ax, by = By - Ay, bz = Bz - Az;
-            const double il64 = 1.0 / sqrt(bx * bx + by * by + bz * bz);
-            const double e0 = bx * il64, e1 = by * il64, e2 = bz * il64;
-            const double m0 = pl.y * e2 - pl.z * e1, m1 = pl.z * e0 - pl.x * e2, m2 = pl.x * e1 - pl.y * e0;
-            const double p64 = ((P0dx - Ax) * m0 + (P0dy - Ay) * m1 + (P0dz - Az) * m2) * ih;
-            const double tA = ((Ax - P0dx) * e0 + (Ay - P0dy) * e1 + (Az - P0dz) * e2) * ih;
-            const double tB = ((Bx - P0dx) * e0 + (By - P0dy) * e1 + (Bz - P0dz) * e2) * ih;
-            if (p64 == 0.0) {
-              v = 0.0;
-              integ = false;
-            } else {
-              v = edge_term<Math64>(ad, fabs(p64), tA, tB, dh, integ, K.fd);
-              if (p64 < 0.0) v = -v;
-            }
+// Face f's share of sum_f sgn(d_f) C_f for the pair whose particle sits at
+// xr about the generator (x in units of h, binary32), with the face's part of
+// the inside and boundary tests; 0 for a face out of reach.
+__device__ inline double face_mixed(int64_t f, double xr0, double xr1, double xr2, double h, double ih, float ihf,
+                                    float x0, float x1, float x2, const int64_t *fvo, const double4 *fplane,
+                                    const float4 *fplane32, const double4 *fsphere, const double *fvpos,
+                                    const float4 *fvpos32, bool &inside, bool &on_boundary, Counters &K) {
+  const double4 pl = fplane[f];
+  if (!(pl.w > 0.0)) return 0.0;
+  const double dist = pl.w - (pl.x * xr0 + pl.y * xr1 + pl.z * xr2);
+  if (dist < 0.0) inside = false;
+  if (dist == 0.0) {
+    on_boundary = true;
+    return 0.0;
+  }
+  if (fabs(dist) >= 2.0 * h) return 0.0;
+  const double4 sp = fsphere[f];
+  const double sx = xr0 - sp.x, sy = xr1 - sp.y, sz = xr2 - sp.z;
+  const double reach = sp.w + 2.0 * h;
+  if (sx * sx + sy * sy + sz * sz >= reach * reach) return 0.0;
+  ++K.nf_int;
+  const int64_t vs = fvo[f];
+  const int nv = (int)(fvo[f + 1] - vs);
+  const double d = dist * ih, ad = fabs(d);
+  if (ad < kDegenerate) {
+    // particle on the face plane to within 1e-4 h: the whole face from binary64 geometry
+    K.n64 += nv;
+    return face_fp64<MathMixed>(pl, dist, ih, xr0, xr1, xr2, fvpos + 3 * vs, nv, K.ne_vis, K.ne_int, K.fd);
+  }
+  const double dh = dH(ad);
+  const float4 pf = fplane32[f];
+  const float df = (float)d;
+  const float P0x = x0 + df * pf.x, P0y = x1 + df * pf.y, P0z = x2 + df * pf.z;
+  double sum = 0.0;
+  bool allpos = true, anyzero = false, anyint = false;
+  float4 A = fvpos32[vs];
+  A.x *= ihf;
+  A.y *= ihf;
+  A.z *= ihf;
+  for (int q = 0; q < nv; ++q) {
+    const int q1 = (q + 1 == nv) ? 0 : q + 1;
+    float4 B = fvpos32[vs + q1];
+    B.x *= ihf;
+    B.y *= ihf;
+    B.z *= ihf;
+    const float abx = B.x - A.x, aby = B.y - A.y, abz = B.z - A.z;
+    const float len2 = abx * abx + aby * aby + abz * abz;
+    if (len2 > 0.0f) {
+      const float il = __builtin_amdgcn_rsqf(len2);
+      const float ex = abx * il, ey = aby * il, ez = abz * il;
+      const float mx = pf.y * ez - pf.z * ey, my = pf.z * ex - pf.x * ez, mz = pf.x * ey - pf.y * ex;
+      const float p = (P0x - A.x) * mx + (P0y - A.y) * my + (P0z - A.z) * mz;
+      if (p <= 0.0f) allpos = false;
+      if (p == 0.0f) {
+        anyzero = true;
+      } else {
+        ++K.ne_vis;
+        bool integ;
+        double v;
+        if (fabsf(p) < kDegenerate) {
+          // foot point within 1e-4 h of the edge line: binary64 geometry
+          ++K.n64;
+          const double *V = fvpos + 3 * vs;
+          const double P0dx = xr0 + dist * pl.x, P0dy = xr1 + dist * pl.y, P0dz = xr2 + dist * pl.z;
+          const double Ax = V[3 * q], Ay = V[3 * q + 1], Az = V[3 * q + 2];
+          const double Bx = V[3 * q1], By = V[3 * q1 + 1], Bz = V[3 * q1 + 2];
+          const double bx = Bx - Ax, by = By - Ay, bz = Bz - Az;
+          const double il64 = 1.0 / sqrt(bx * bx + by * by + bz * bz);
+          const double e0 = bx * il64, e1 = by * il64, e2 = bz * il64;
+          const double m0 = pl.y * e2 - pl.z * e1, m1 = pl.z * e0 - pl.x * e2, m2 = pl.x * e1 - pl.y * e0;
+          const double p64 = ((P0dx - Ax) * m0 + (P0dy - Ay) * m1 + (P0dz - Az) * m2) * ih;
+          const double tA = ((Ax - P0dx) * e0 + (Ay - P0dy) * e1 + (Az - P0dz) * e2) * ih;
+          const double tB = ((Bx - P0dx) * e0 + (By - P0dy) * e1 + (Bz - P0dz) * e2) * ih;
+          if (p64 == 0.0) {
+            v = 0.0;
+            integ = false;
           } else {
-            const float tA = (A.x - P0x) * ex + (A.y - P0y) * ey + (A.z - P0z) * ez;
-            const float tB = (B.x - P0x) * ex + (B.y - P0y) * ey + (B.z - P0z) * ez;
-            v = edge_term<MathMixed>(ad, (double)fabsf(p), (double)tA, (double)tB, dh, integ, K.fd);
-            if (p < 0.0f) v = -v;
+            v = edge_term_geo64<MathMixed>(ad, fabs(p64), tA, tB, dh, integ, K.fd);
+            if (p64 < 0.0) v = -v;
           }
-          anyint |= integ;
-          K.ne_int += integ;
-          sum += v;
+        } else {
+          const float tA = (A.x - P0x) * ex + (A.y - P0y) * ey + (A.z - P0z) * ez;
+          const float tB = (B.x - P0x) * ex + (B.y - P0y) * ey + (B.z - P0z) * ez;
+          v = edge_term<MathMixed>(ad, (double)fabsf(p), (double)tA, (double)tB, dh, integ, K.fd);
+          if (p < 0.0f) v = -v;
         }
+        anyint |= integ;
+        K.ne_int += integ;
+        sum += v;
       }
-      A = B;
     }
-    if (!anyint && !anyzero) sum = -dh * (allpos ? 2.0 * kPi : 0.0);
-    const double Cf = sum * kInv4Pi;
-    acc += d > 0.0 ? Cf : -Cf;
+    A = B;
   }
-  double S = inside ? 1.0 : 0.0;
-  if (inside && on_boundary) S = boundary_S(f0, f1, fplane, fvo, fvpos, xr0, xr1, xr2);
-  w_out[k] = S - acc;
-  if (counters) flush_counters(counters, f1 - f0, K);
-}
-
-// one pair per lane over a device-side list of pairs (its length read on the
-// device): the pairs the two-phase kernel leaves to binary64 geometry
-__global__ void __launch_bounds__(256) k_exact_mixed_list(const int64_t *list, const int32_t *n_list,
-                                                         const ExactInst *insts, const int64_t *chunk0, int n_inst,
-                                                         int64_t *counters) {
-  const int n = *n_list;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-    const int64_t gid = list[t];
-    const int ins = inst_of(chunk0, n_inst, gid >> 6);
-    const ExactInst &I = insts[ins];
-    pair_mixed(gid - chunk0[ins] * 64, I.pair_c, I.pair_p, I.xyz, I.hh, I.gen, I.cfo, I.fvo, I.fplane, I.fplane32,
-               I.fsphere, I.fvpos, I.fvpos32, I.w, counters);
-  }
+  if (!anyint && !anyzero) sum = -dh * (allpos ? 2.0 * kPi : 0.0);
+  const double Cf = sum * kInv4Pi;
+  return d > 0.0 ? Cf : -Cf;
 }
 
 // ------------------------------------------------------- wave helpers
@@ -699,6 +682,61 @@ __device__ inline void wave_fence() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// The pairs the edge-parallel kernel leaves to binary64 geometry, 16 lanes
+// per pair (four pairs per wavefront): lane s takes the cell's faces s,
+// s + 16, ...; each round's 16 shares go through LDS and the group's first
+// lane adds them in face order, so the sum is the serial one.
+__global__ void __launch_bounds__(256) k_exact_mixed_list(const int64_t *list, const int32_t *n_list,
+                                                         const ExactInst *__restrict__ insts,
+                                                         const int64_t *__restrict__ chunk0, int n_inst,
+                                                         int64_t *counters) {
+  __shared__ double share[16][16];
+  const int sub = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  const int lane = threadIdx.x & 63;
+  const uint64_t gmask = 0xffffull << (lane & 48);  // this group's lanes in the wave
+  const int n = *n_list;
+  for (int t = blockIdx.x * 16 + grp; t < n; t += gridDim.x * 16) {
+    const int64_t gid = list[t];
+    const int ins = inst_of(chunk0, n_inst, gid >> 6);
+    const ExactInst &I = insts[ins];
+    const int64_t k = gid - chunk0[ins] * 64;
+    const int64_t c = I.pair_c[k];
+    const int64_t i = I.pair_p[k];
+    const double h = I.hh[i];
+    const double ih = 1.0 / h;
+    const float ihf = (float)ih;
+    const double xr0 = I.xyz[3 * i] - I.gen[3 * c], xr1 = I.xyz[3 * i + 1] - I.gen[3 * c + 1],
+                 xr2 = I.xyz[3 * i + 2] - I.gen[3 * c + 2];
+    // particle about the generator, in units of h, binary32
+    const float x0 = (float)(xr0 * ih), x1 = (float)(xr1 * ih), x2 = (float)(xr2 * ih);
+    double acc = 0.0;
+    bool inside = true, on_boundary = false;
+    Counters K;
+    const int64_t f0 = I.cfo[c], f1 = I.cfo[c + 1];
+    for (int64_t fb = f0; fb < f1; fb += 16) {
+      const int64_t f = fb + sub;
+      share[grp][sub] = f < f1 ? face_mixed(f, xr0, xr1, xr2, h, ih, ihf, x0, x1, x2, I.fvo, I.fplane, I.fplane32,
+                                            I.fsphere, I.fvpos, I.fvpos32, inside, on_boundary, K)
+                               : 0.0;
+      wave_sync();
+      if (sub == 0) {
+        const int m = (int)min((int64_t)16, f1 - fb);
+        for (int j = 0; j < m; ++j) acc += share[grp][j];
+      }
+      wave_sync();
+    }
+    // the group's inside (all faces) and boundary (any face) tests
+    const bool all_in = (__ballot(!inside) & gmask) == 0ull;
+    const bool any_on = (__ballot(on_boundary) & gmask) != 0ull;
+    if (sub == 0) {
+      double S = all_in ? 1.0 : 0.0;
+      if (all_in && any_on) S = boundary_S(f0, f1, I.fplane, I.fvo, I.fvpos, xr0, xr1, xr2);
+      I.w[k] = S - acc;
+    }
+    if (counters) flush_counters(counters, sub == 0 ? f1 - f0 : 0, K);
+  }
 }
 
 // ------------------------------------ edge-parallel wave kernel (mixed)
