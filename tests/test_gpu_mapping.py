@@ -147,6 +147,36 @@ def test_lattice_special_positions(ctx, oracle, precision):
     assert np.max(np.abs(cov[inner] - 1.0)) < (1e-12 if precision == "fp64" else 2e-6)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_near_degenerate_positions(ctx, oracle, precision):
+    """Particles 3e-5 h, 1e-7 h and 1e-11 h off a face plane, an edge line
+    and a corner of the cubic lattice: the cases the mixed path routes to
+    binary64 geometry (|d| or |p| below 1e-4 h), against the oracle."""
+    import paper_2410_15227_amd as pkg
+    say(f"case: near-degenerate positions, precision={precision}")
+    t = lattice(6)
+    a = 1.0 / 6
+    h0 = 0.7 * a
+    pts, hs = [], []
+    for eps in (3e-5, 1e-7, 1e-11):
+        dlt = eps * h0
+        pts += [[2 * a + dlt, 0.513, 0.479],          # face x = 2a
+                [2 * a - dlt, 3 * a + dlt, 0.371],     # edge x = 2a, y = 3a
+                [2 * a + dlt, 3 * a - dlt, 4 * a + dlt]]  # corner
+        hs += [h0, h0, h0]
+    pts = np.array(pts)
+    hs = np.array(hs)
+    m = np.ones(len(pts))
+    wl = type("W", (), dict(tess=t, pos=pts, h=hs, m=m))
+    dt, res = run_map(pkg, ctx, wl, precision)
+    goff, gidx, gw = (x.cpu().numpy() for x in res.pairs.export())
+    off, idx, w = oracle.pairs_weights(t, pts, hs)
+    assert np.array_equal(goff, off) and np.array_equal(gidx, idx)
+    tol = 1e-12 if precision == "fp64" else 2e-6
+    assert np.all(np.isfinite(gw))
+    assert np.max(np.abs(gw - w)) < tol
+
+
 def test_exact_zero_and_one(ctx):
     """A support inside the cell gives exactly 1, a candidate whose support
     misses the cell exactly 0 (every face beyond 2h contributes nothing)."""
