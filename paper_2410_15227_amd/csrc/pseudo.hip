@@ -474,6 +474,8 @@ __global__ void __launch_bounds__(64 * kHWaves) k_hsolve(int64_t np, const int32
     else if (phase == 3) he = 0.5 * (lo + hi);
     const double ih = 1.0 / he;
     double sw = 0.0, sd = 0.0;
+    bool fast = false;  // tile sums in a fixed tree order, sw only
+    int64_t nhit = 0;
     // the terms of one tile's units (one per lane, `live` lanes hold one)
     auto tile_terms = [&](const double4 &p, bool live) {
       double w = 0.0, dt = 0.0;
@@ -486,6 +488,17 @@ __global__ void __launch_bounds__(64 * kHWaves) k_hsolve(int64_t np, const int32
           w = m4w(qq);
           dt = -(3.0 * w + qq * m4dw(qq));
         }
+      }
+      if (fast) {
+        const uint64_t m = __ballot(hit);
+        nhit += __popcll(m);
+        if (m) {
+          double v = hit ? w : 0.0;
+#pragma unroll
+          for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+          sw += readlane_d(v, 0);
+        }
+        return;
       }
       uint64_t mask = __ballot(hit);
       while (mask) {
@@ -534,6 +547,7 @@ __global__ void __launch_bounds__(64 * kHWaves) k_hsolve(int64_t np, const int32
       }
     };
 
+    auto all_sums = [&]() {
     if (n_mid == 0) {
       tile_sums(0, nu);
     } else {
@@ -554,9 +568,25 @@ __global__ void __launch_bounds__(64 * kHWaves) k_hsolve(int64_t np, const int32
         }
       }
     }
-    const double n = sw * ih * ih * ih * kInvPi;
-    const double dn = sd * ih * ih * ih * ih * kInvPi;
-    const double f = hfact * pow(n, -1.0 / 3.0) - he;
+    };
+    // Bracket and bisection steps use only the sign of f (and f == 0), so
+    // they first take sw from tile sums in a fixed tree order.  The terms are
+    // non-negative, so that sum is within 2 nhit 2^-53 sw of the unit-order
+    // one, which moves f by less than nhit 2^-53 he; only when |f| is within
+    // that margin are the sums taken again in unit order.  Every decision,
+    // and so every result, is that of the unit-order sums.
+    fast = phase != 0;
+    double n, dn, f;
+    while (true) {  // at most twice: tree order, then unit order
+      sw = sd = 0.0;
+      nhit = 0;
+      all_sums();
+      n = sw * ih * ih * ih * kInvPi;
+      dn = sd * ih * ih * ih * ih * kInvPi;
+      f = hfact * pow(n, -1.0 / 3.0) - he;
+      if (!fast || fabs(f) > he * (1e-12 + 4.0 * (double)nhit * 0x1p-53)) break;
+      fast = false;
+    }
     if (phase == 0) {
       const double fp = -(1.0 / 3.0) * hfact * dn * pow(n, -4.0 / 3.0) - 1.0;
       bool fail = false;
