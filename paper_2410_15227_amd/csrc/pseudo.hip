@@ -450,8 +450,11 @@ __global__ void __launch_bounds__(64 * kHWaves) k_hsolve(int64_t np, const int32
                                                         const int32_t *mid_u1, const double *rcut,
                                                         const double4 *tlo, const double4 *thi) {
 #pragma clang fp contract(off)
+  __shared__ double2 hbuf[kHWaves][64];  // one tile's non-zero terms, in lane order
   const int64_t pid = (int64_t)blockIdx.x * kHWaves + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
+  double2 *const hb = hbuf[threadIdx.x >> 6];
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   if (pid >= np) return;  // the whole wavefront
   const int32_t e = plist[pid];
   const double ax = o_xyz[3 * (int64_t)e], ay = o_xyz[3 * (int64_t)e + 1], az = o_xyz[3 * (int64_t)e + 2];
@@ -500,12 +503,25 @@ __global__ void __launch_bounds__(64 * kHWaves) k_hsolve(int64_t np, const int32
         }
         return;
       }
-      uint64_t mask = __ballot(hit);
-      while (mask) {
-        const int j = __builtin_ctzll(mask);
-        mask &= mask - 1;
-        sw += readlane_d(w, j);
-        sd += readlane_d(dt, j);
+      // unit order: the tile's hits go to LDS in lane order and lane 0
+      // adds them one after the other (its sums are broadcast at the end)
+      const uint64_t mask = __ballot(hit);
+      if (mask) {
+        if (hit) hb[__popcll(mask & below)] = make_double2(w, dt);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane == 0) {
+          const int cnt = __popcll(mask);
+          for (int k = 0; k < cnt; ++k) {
+            const double2 v = hb[k];
+            sw += v.x;
+            sd += v.y;
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
     };
     // units [u0, u1) by tiles of 64 (tile t: units [64 t, 64 t + 64)); a
@@ -581,6 +597,8 @@ __global__ void __launch_bounds__(64 * kHWaves) k_hsolve(int64_t np, const int32
       sw = sd = 0.0;
       nhit = 0;
       all_sums();
+      sw = readlane_d(sw, 0);  // lane 0 holds the unit-order sums
+      sd = readlane_d(sd, 0);
       n = sw * ih * ih * ih * kInvPi;
       dn = sd * ih * ih * ih * ih * kInvPi;
       f = hfact * pow(n, -1.0 / 3.0) - he;
