@@ -513,7 +513,18 @@ __global__ void __launch_bounds__(64 * kHWaves) k_hsolve(int64_t np, const int32
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (lane == 0) {
           const int cnt = __popcll(mask);
-          for (int k = 0; k < cnt; ++k) {
+          int k = 0;
+          for (; k + 8 <= cnt; k += 8) {  // eight reads in flight, added in order
+            double2 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = hb[k + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              sw += v[u].x;
+              sd += v[u].y;
+            }
+          }
+          for (; k < cnt; ++k) {
             const double2 v = hb[k];
             sw += v.x;
             sd += v.y;
