@@ -263,7 +263,9 @@ __global__ void __launch_bounds__(kSortThreads) k_kv_hist(const uint32_t *key, i
   const int nd = 1 << rb;
   for (int d = threadIdx.x; d < nd; d += kSortThreads) h[d] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  // XCD-aware like the scatter: neighbouring tiles write neighbouring counts
+  const int64_t tile = xcd_tile(ntiles);
+  const int64_t base = tile * kSortTile;
   const unsigned mask = (unsigned)nd - 1u;
 #pragma unroll
   for (int j = 0; j < kSortItems; ++j) {
@@ -271,7 +273,7 @@ __global__ void __launch_bounds__(kSortThreads) k_kv_hist(const uint32_t *key, i
     if (i < n) atomicAdd(&h[(key[i] >> shift) & mask], 1u);
   }
   __syncthreads();
-  for (int d = threadIdx.x; d < nd; d += kSortThreads) hist[(int64_t)d * ntiles + blockIdx.x] = h[d];
+  for (int d = threadIdx.x; d < nd; d += kSortThreads) hist[(int64_t)d * ntiles + tile] = h[d];
 }
 
 template <int NB>
