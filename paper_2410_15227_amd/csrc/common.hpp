@@ -184,6 +184,8 @@ struct PairsDev {
 void scan_exclusive_i64(Arena &ar, const int64_t *in, int64_t *out, int64_t n, bool write_total, hipStream_t s);
 // stable LSD radix sort of (key, value) pairs on the low `bits` bits.
 void radix_sort_u64(Arena &ar, uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s);
+// Stable sort by key bits [lo, hi) only (the order of keys equal there is kept).
+void radix_sort_u64_range(Arena &ar, uint64_t *keys, int32_t *vals, int64_t n, int lo, int hi, hipStream_t s);
 void radix_sort_u32(Arena &ar, uint32_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s);
 // Stable sort of n (key, a, b) triples by the low `bits` bits of key, from the
 // input arrays into the output arrays (which must not overlap them).

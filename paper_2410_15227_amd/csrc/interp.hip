@@ -169,7 +169,7 @@ void interpolate_particles(Ctx &ctx, int64_t n, const double *xyz, const int64_t
   uint64_t *keys = ar.get<uint64_t>("ip_keys", ne);
   int32_t *sidx = ar.get<int32_t>("ip_sidx", ne);
   morton_keys(exyz, 3, ne, 0.0, 0.0, 0.0, 1.0, keys, sidx, s);
-  radix_sort_u64(ar, keys, sidx, ne, 63, s);
+  radix_sort_u64_range(ar, keys, sidx, ne, 33, 63, s);  // top 10 bits per axis
   float4 *sx = ar.get<float4>("ip_sx", ne);
   double4 *sd = ar.get<double4>("ip_sd", ne);
   k_entry_prep<<<(unsigned)div_up(ne, 256), 256, 0, s>>>(ne, sidx, exyz, eh, sx, sd);

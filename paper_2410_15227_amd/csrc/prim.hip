@@ -205,7 +205,8 @@ __global__ void k_copy_pairs(const K *ks, const int32_t *vs, K *kd, int32_t *vd,
 }
 
 template <typename K>
-void radix_sort_impl(Arena &ar, K *keys, int32_t *vals, int64_t n, int bits, hipStream_t s, const char *tag) {
+void radix_sort_impl(Arena &ar, K *keys, int32_t *vals, int64_t n, int bits, hipStream_t s, const char *tag,
+                     int lo = 0) {
   if (n <= 1) return;
   int64_t nb = div_up(n, kTile);
   std::string t(tag);
@@ -216,7 +217,7 @@ void radix_sort_impl(Arena &ar, K *keys, int32_t *vals, int64_t n, int bits, hip
   K *ka = keys, *kb = k2;
   int32_t *va = vals, *vb = v2;
   int passes = 0;
-  for (int shift = 0; shift < bits; shift += kRadixBits, ++passes) {
+  for (int shift = lo; shift < bits; shift += kRadixBits, ++passes) {
     k_radix_hist<K><<<(unsigned)nb, kBlock, 0, s>>>(ka, n, shift, hist, nb);
     SPH_LAUNCH_CHECK();
     scan_exclusive_i64(ar, hist, off, (int64_t)kBins * nb, false, s);
@@ -430,6 +431,10 @@ void sort_by_key_kv(Arena &ar, int64_t n, int bits, const uint32_t *kin, const i
 
 void radix_sort_u64(Arena &ar, uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s) {
   radix_sort_impl<uint64_t>(ar, keys, vals, n, bits, s, "rs64");
+}
+
+void radix_sort_u64_range(Arena &ar, uint64_t *keys, int32_t *vals, int64_t n, int lo, int hi, hipStream_t s) {
+  radix_sort_impl<uint64_t>(ar, keys, vals, n, hi, s, "rs64", lo);
 }
 void radix_sort_u32(Arena &ar, uint32_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s) {
   radix_sort_impl<uint32_t>(ar, keys, vals, n, bits, s, "rs32");
