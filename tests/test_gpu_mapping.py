@@ -177,6 +177,35 @@ def test_near_degenerate_positions(ctx, oracle, precision):
     assert np.max(np.abs(gw - w)) < tol
 
 
+def test_transpose_three_sort_passes(ctx):
+    """More than 2^20 particles: the particle-major copy is then sorted in
+    three passes.  Particles with tiny supports inside a 4^3 lattice each
+    lie in one cell with weight exactly 1, so the inverse mapping of
+    q_c = c must return each particle's own cell index exactly, and its
+    coverage must be exactly 1."""
+    import paper_2410_15227_amd as pkg
+    n = (1 << 20) + 4097
+    say(f"case: transpose of {n} particles (three sort passes)")
+    t = lattice(4)
+    a = 0.25
+    g = np.random.default_rng(11)
+    pos = g.uniform(0.01, 0.99, (n, 3))
+    h = np.full(n, 1e-6)
+    m = np.ones(n)
+    wl = type("W", (), dict(tess=t, pos=pos, h=h, m=m))
+    dt, res = run_map(pkg, ctx, wl, "mixed")
+    ijk = np.floor(pos / a).astype(np.int64)
+    cell = (ijk[:, 0] * 4 + ijk[:, 1]) * 4 + ijk[:, 2]  # lattice() order: i, then j, then k
+    frac = pos / a - ijk
+    inner = np.all((frac > 1e-4) & (frac < 1 - 1e-4), axis=1)
+    assert inner.sum() > n - 1000
+    assert np.array_equal(t.generators[cell[inner]] // a, ijk[inner].astype(float))
+    cov = res.coverage.cpu().numpy()
+    assert np.all(cov[inner] == 1.0)
+    out = pkg.map_cells_to_particles(ctx, res.pairs, np.arange(t.n_cells, dtype=np.float64)).cpu().numpy()
+    assert np.array_equal(out[inner], cell[inner].astype(np.float64))
+
+
 def test_exact_zero_and_one(ctx):
     """A support inside the cell gives exactly 1, a candidate whose support
     misses the cell exactly 0 (every face beyond 2h contributes nothing)."""
