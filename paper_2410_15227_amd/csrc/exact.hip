@@ -830,6 +830,11 @@ __device__ inline FaceRec load_rec(gptr<FaceRec> base, int rec) {
   return r;
 }
 
+// the number of set bits of m in the lanes below this one
+__device__ inline int mbcnt64(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
 __device__ inline uint64_t lanes_in(int lo, int hi) {  // bits [lo, hi), 0 <= lo <= hi <= 64
   const uint64_t a = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
   const uint64_t b = lo >= 64 ? ~0ull : ((1ull << lo) - 1ull);
@@ -1075,16 +1080,13 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
       }
       const float4 it = make_float4(fc.df, p, tA, tB);
       const uint64_t mD = __ballot(integ && cross), mN = __ballot(integ && !cross);
-      const uint64_t below = lanes_in(0, lane);
       if (integ) {
-        const int pos = cross ? qD + __popcll(mD & below) : qN + __popcll(mN & below);
-        if (cross) {
-          L.qD[pos] = it;
-          L.oD[pos] = (unsigned char)owner;
-        } else {
-          L.qN[pos] = it;
-          L.oN[pos] = (unsigned char)owner;
-        }
+        // set bits of the scalar masks below this lane, counted in hardware
+        const int pos = cross ? qD + mbcnt64(mD) : qN + mbcnt64(mN);
+        float4 *const q = cross ? L.qD : L.qN;
+        unsigned char *const o = cross ? L.oD : L.oN;
+        q[pos] = it;
+        o[pos] = (unsigned char)owner;
       }
       qD += __popcll(mD);
       qN += __popcll(mN);
