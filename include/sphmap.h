@@ -413,7 +413,7 @@ int sphmap_reset_timing(sphmap_ctx *ctx);
    outer coefficients (a piece with twice their difference counts as
    inner).  [7] edges or faces
    evaluated from binary64 geometry (mixed path: the pairs holding them are
-   recomputed one pair per lane).  Counting costs time; it is only done when
+   recomputed by a second kernel, 16 lanes per pair).  Counting costs time; it is only done when
    enabled (sphmap_set_counting). */
 int sphmap_set_counting(sphmap_ctx *ctx, int32_t enabled);
 

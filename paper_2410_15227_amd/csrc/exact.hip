@@ -753,7 +753,7 @@ __global__ void __launch_bounds__(256) k_exact_mixed_list(const int64_t *list, c
 // LDS atomics: integer sums do not depend on order, so a weight is a
 // function of its own pair alone and repeats bit for bit.  Pairs with more
 // than 64 faces, more candidate edges than a chunk slot holds, or that need
-// binary64 geometry are listed for the one-pair-per-lane kernel.
+// binary64 geometry are listed for the redo kernel (16 lanes per pair).
 constexpr int kMaxFaces = 64;              // faces per cell handled here
 constexpr int kEntryCap = 64 * kMaxFaces;  // face entries per chunk
 constexpr int kEdgeCap = 256;              // candidate edges per pair handled here
