@@ -222,10 +222,20 @@ int sphmap_pairs_info(const sphmap_pairs *pairs, int64_t *n_pairs, int64_t *n_ce
    within each cell), d_w [n_pairs] (binary64 weights w_ic). */
 int sphmap_pairs_export(sphmap_ctx *ctx, const sphmap_pairs *pairs, int64_t *d_cell_off, int32_t *d_particle,
                         double *d_w, void *stream);
-/* Release a retained list.  The context keeps the device memory of up to two
-   freed lists and gives it to the next retained lists (no device allocation
-   in repeated steps); sphmap_destroy releases it. */
+/* Release a retained list (waits for the device first).  Its device blocks
+   go to the context's pool, from which later retained lists allocate: a
+   block of B bytes serves a request of more than B/2 and at most B bytes,
+   so repeated steps make no device allocation.  The pool keeps at most
+   one eighth of the device's memory by default (sphmap_set_pool_limit);
+   blocks beyond the limit are freed, and all of them are freed before a
+   device allocation that fails is retried, and by sphmap_destroy.  Free
+   every retained list before destroying its context. */
 int sphmap_pairs_free(sphmap_ctx *ctx, sphmap_pairs *pairs);
+/* Largest total of device memory, in bytes, that the context's pool of
+   freed pair-list blocks may keep (0: keep none).  Blocks held beyond a
+   lowered limit are freed at once, after waiting for the device.  For
+   callers that run several contexts on one device under a memory budget. */
+int sphmap_set_pool_limit(sphmap_ctx *ctx, uint64_t bytes);
 
 /* ------------------------------------------------------------------------
  * Inverse mapping (Sec. 2.3, the ionic fractions returned onto the

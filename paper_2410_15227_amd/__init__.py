@@ -118,6 +118,10 @@ class Context:
     def set_counting(self, on: bool = True):
         self.check(_native.lib().sphmap_set_counting(self.handle, 1 if on else 0))
 
+    def set_pool_limit(self, n_bytes: int):
+        """Largest device memory the pool of freed pair-list blocks keeps."""
+        self.check(_native.lib().sphmap_set_pool_limit(self.handle, int(n_bytes)))
+
     def set_autotune(self, on: bool = True):
         """Autotune the Exact launch shape per power-of-two pair-count class."""
         self.check(_native.lib().sphmap_set_autotune(self.handle, 1 if on else 0))

@@ -24,6 +24,7 @@ EXPORTS = [
     "sphmap_tess_build_voronoi", "sphmap_tess_counts", "sphmap_tess_export", "build_pseudo_particles_kd",
     "sphmap_set_timing", "sphmap_kernel_time", "sphmap_reset_timing",
     "sphmap_set_counting", "sphmap_work_counters", "sphmap_set_autotune", "sphmap_tuned_shape",
+    "sphmap_set_pool_limit",
 ]
 
 
@@ -94,6 +95,8 @@ def lib():
         L.sphmap_pairs_export.argtypes = [vp, vp, vp, vp, vp, vp]
         L.sphmap_pairs_free.restype = ctypes.c_int
         L.sphmap_pairs_free.argtypes = [vp, vp]
+        L.sphmap_set_pool_limit.restype = ctypes.c_int
+        L.sphmap_set_pool_limit.argtypes = [vp, ctypes.c_uint64]
         L.map_cells_to_particles.restype = ctypes.c_int
         L.map_cells_to_particles.argtypes = [vp, vp, vp, i32, vp, vp]
         L.build_pseudo_particles_open.restype = ctypes.c_int

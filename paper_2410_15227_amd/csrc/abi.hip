@@ -42,19 +42,13 @@ int guarded(sphmap_ctx *ctx, F &&fn) {
 
 inline hipStream_t as_stream(void *s) { return (hipStream_t)s; }
 
-// A new retained pair list takes the device buffers of a freed one when the
-// context keeps any (grow-only buffers: no allocation in steady state).
+// A retained pair list allocates from the context's block pool and gives
+// its blocks back to it when freed, so repeated steps allocate nothing.
 sphmap_pairs *new_pairs(sphmap::Ctx &C) {
   sphmap_pairs *q = new sphmap_pairs;
-  if (!C.recycled.empty()) {
-    q->p.mem.bufs.swap(C.recycled.back()->mem.bufs);
-    delete C.recycled.back();
-    C.recycled.pop_back();
-  }
+  q->p.mem.pool = &C.pool;
   return q;
 }
-
-constexpr size_t kRecycledLists = 2;
 
 }  // namespace
 
@@ -70,6 +64,9 @@ int sphmap_create(int32_t device, sphmap_ctx **out) {
   std::unique_ptr<sphmap_ctx> ctx(new sphmap_ctx);
   ctx->c.device = device;
   int rc = guarded(ctx.get(), [&] {
+    size_t free_b = 0, total_b = 0;
+    SPH_HIP(hipMemGetInfo(&free_b, &total_b));
+    ctx->c.pool.cap = total_b / 8;
     ctx->c.d_counters = ctx->c.arena.get<int64_t>("counters", 8);
     ctx->c.d_status = ctx->c.arena.get<int>("status", 4);
     SPH_HIP(hipMemset(ctx->c.d_counters, 0, 8 * sizeof(int64_t)));
@@ -92,9 +89,8 @@ int sphmap_destroy(sphmap_ctx *ctx) {
   delete ctx->c.scratch_pairs;
   ctx->c.scratch_pairs = nullptr;
   for (auto *P : ctx->c.scratch_batch) delete P;
-  for (auto *P : ctx->c.recycled) delete P;
-  ctx->c.recycled.clear();
   ctx->c.scratch_batch.clear();
+  ctx->c.pool.release();
   if (ctx->c.pinned) (void)hipHostFree(ctx->c.pinned);
   ctx->c.pinned = nullptr;
   delete ctx;
@@ -376,13 +372,20 @@ int sphmap_pairs_free(sphmap_ctx *ctx, sphmap_pairs *pairs) {
   if (!ctx || !pairs) return SPHMAP_EINVAL;
   (void)hipSetDevice(ctx->c.device);
   (void)hipDeviceSynchronize();
-  if (ctx->c.recycled.size() < kRecycledLists) {
-    sphmap::PairsDev *keep = new sphmap::PairsDev;
-    keep->mem.bufs.swap(pairs->p.mem.bufs);
-    ctx->c.recycled.push_back(keep);
-  }
-  delete pairs;
+  delete pairs;  // its blocks go to the context's pool
   return SPHMAP_OK;
+}
+
+int sphmap_set_pool_limit(sphmap_ctx *ctx, uint64_t bytes) {
+  if (!ctx) return SPHMAP_EINVAL;
+  return guarded(ctx, [&] {
+    sphmap::BlockPool &pool = ctx->c.pool;
+    pool.cap = (size_t)bytes;
+    if (pool.held > pool.cap) {
+      SPH_HIP(hipDeviceSynchronize());
+      pool.release();
+    }
+  });
 }
 
 int map_cells_to_particles(sphmap_ctx *ctx, const sphmap_pairs *pairs, const double *d_cell_values,

@@ -39,10 +39,29 @@ struct Buffer {
   size_t bytes = 0;
 };
 
+// Device blocks given back by freed pair lists, kept by size for the next
+// allocations of the same context (a caching allocator: repeated steps make
+// no hipMalloc or hipFree).  take() hands out the smallest kept block of at
+// least `bytes` and under twice that; put() keeps a block while the kept
+// total stays within `cap` and returns it to the device otherwise.  Only
+// blocks that no queued work still uses may be put back.
+struct BlockPool {
+  std::multimap<size_t, void *> blocks;
+  size_t held = 0;
+  size_t cap = 0;
+  void *take(size_t bytes, size_t &got);
+  void put(void *p, size_t bytes);
+  void release();
+  ~BlockPool() { release(); }
+};
+
 // Grow-only device allocations keyed by purpose, owned by a context or a
-// handle.  get() never shrinks; contents are not preserved on growth.
+// handle.  get() never shrinks; contents are not preserved on growth.  With
+// a pool, first allocations come from it and release() gives the blocks
+// back to it.
 struct Arena {
   std::map<std::string, Buffer> bufs;
+  BlockPool *pool = nullptr;
   void *get(const std::string &name, size_t bytes);
   template <typename T>
   T *get(const std::string &name, size_t count) {
@@ -80,7 +99,7 @@ struct Ctx {
   void *pinned = nullptr;         // pinned host staging for small tables
   size_t pinned_bytes = 0;
   std::vector<PairsDev *> scratch_batch;  // pair lists of batched calls that do not keep them
-  std::vector<PairsDev *> recycled;       // buffers of freed pair lists, reused by the next kept lists
+  BlockPool pool;                         // blocks of freed retained pair lists
   int n_cu = 0, exact_per_cu = 0;  // compute units; resident Exact workgroups per CU
   bool autotune = false;
   std::map<int, TuneChoice> tuned;  // by floor(log2(pairs)) of the Exact launch

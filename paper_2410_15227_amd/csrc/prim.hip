@@ -3,13 +3,54 @@
 
 namespace sphmap {
 
+void *BlockPool::take(size_t bytes, size_t &got) {
+  auto it = blocks.lower_bound(bytes);
+  if (it == blocks.end() || it->first / 2 >= bytes) return nullptr;
+  void *p = it->second;
+  got = it->first;
+  held -= got;
+  blocks.erase(it);
+  return p;
+}
+
+void BlockPool::put(void *p, size_t bytes) {
+  if (held + bytes > cap) {
+    (void)hipFree(p);
+    return;
+  }
+  blocks.emplace(bytes, p);
+  held += bytes;
+}
+
+void BlockPool::release() {
+  for (auto &kv : blocks) (void)hipFree(kv.second);
+  blocks.clear();
+  held = 0;
+}
+
 void *Arena::get(const std::string &name, size_t bytes) {
   Buffer &b = bufs[name];
   if (b.bytes < bytes) {
+    // a block in use may still be read by queued work: hipFree waits for it
     if (b.p) SPH_HIP(hipFree(b.p));
     b.p = nullptr;
+    b.bytes = 0;
     size_t want = bytes + bytes / 8 + 256;
+    if (pool) {
+      size_t got = 0;
+      if (void *q = pool->take(want, got)) {
+        b.p = q;
+        b.bytes = got;
+        return b.p;
+      }
+    }
     hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess && pool && !pool->blocks.empty()) {
+      // the kept blocks first go back to the device
+      (void)hipGetLastError();
+      pool->release();
+      e = hipMalloc(&b.p, want);
+    }
     if (e != hipSuccess) {
       b.p = nullptr;
       b.bytes = 0;
@@ -22,8 +63,15 @@ void *Arena::get(const std::string &name, size_t bytes) {
 }
 
 void Arena::release() {
-  for (auto &kv : bufs)
-    if (kv.second.p) (void)hipFree(kv.second.p);
+  // pooled blocks are handed out again at once: queued work must be done
+  if (pool && !bufs.empty()) (void)hipDeviceSynchronize();
+  for (auto &kv : bufs) {
+    if (!kv.second.p) continue;
+    if (pool)
+      pool->put(kv.second.p, kv.second.bytes);
+    else
+      (void)hipFree(kv.second.p);
+  }
   bufs.clear();
 }
 

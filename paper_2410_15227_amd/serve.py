@@ -54,6 +54,10 @@ class MappingServer:
         self.k = inverse_components
         self.budget = int(hbm_budget)
         self._slots = [(pkg.Context(device), torch.cuda.Stream(device=device)) for _ in range(slots)]
+        # freed pair lists keep their blocks for the slot's next jobs: one
+        # eighth of the budget over all slots, held beside it
+        for ctx, _ in self._slots:
+            ctx.set_pool_limit(self.budget // (8 * slots))
         self._est_ctx = pkg.Context(device)  # footprint queries, under the lock only
         self._cv = threading.Condition()
         self._queue: collections.deque[Job] = collections.deque()
