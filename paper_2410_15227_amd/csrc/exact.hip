@@ -749,7 +749,7 @@ __global__ void __launch_bounds__(256) k_exact_mixed_list(const int64_t *list, c
 //      U = 1, one for the others);
 //   B  (lane = item): whenever a queue holds 64 items the wave evaluates
 //      them together, so every lane runs the same closed form.
-// Each pair's terms are added as 64-bit fixed-point integers (2^-50) with
+// Each pair's terms are added as 64-bit fixed-point integers (2^-46) with
 // LDS atomics: integer sums do not depend on order, so a weight is a
 // function of its own pair alone and repeats bit for bit.  Pairs with more
 // than 64 faces, more candidate edges than a chunk slot holds, or that need
@@ -762,7 +762,8 @@ constexpr int kQueue = 128;                // items per LDS queue
 struct __align__(16) FaceRec {  // a face within reach of a pair
   float px, py, pz;  // foot point about the generator (absolute units)
   float df;          // signed |d| / h, binary32
-  double dh;         // |d| H(|d|)
+  double dhs;        // -sign(d) |d| H(|d|) 2^46, sign(0) = -1: the angle
+                     // term's factor in fixed-point units
   float ihf;         // 1/h of the pair (binary32)
   uint32_t slot;     // bits 0-23: first vertex slot - the chunk's first; 24-31: lane of the pair
 };
@@ -824,7 +825,7 @@ __device__ inline FaceRec load_rec(gptr<FaceRec> base, int rec) {
   r.py = q[1];
   r.pz = q[2];
   r.df = q[3];
-  r.dh = *(gptr<double>)(q + 4);
+  r.dhs = *(gptr<double>)(q + 4);
   r.ihf = q[6];
   r.slot = *(gptr<uint32_t>)(q + 7);
   return r;
@@ -841,19 +842,23 @@ __device__ inline uint64_t lanes_in(int lo, int hi) {  // bits [lo, hi), 0 <= lo
   return a & ~b;
 }
 
-// v in units of 2^-50, rounded down, as a two's-complement 64-bit integer
-// (|v| < 2^13).
-__device__ inline unsigned long long to_fixed(double v) {
-  const double t = v * 0x1p50;
-  const double hi = floor(t * 0x1p-32);
-  const double lo = t - hi * 0x1p32;  // [0, 2^32)
-  return ((unsigned long long)(unsigned)(int)hi << 32) + (unsigned long long)(unsigned)lo;
+// v in units of 2^-46, rounded to nearest, as a two's-complement 64-bit
+// integer, for |v| < 32 (every term is an angle weighted by at most 1 in
+// magnitude).  With 1.5 * 2^52 added, v * 2^46 is rounded once, to an
+// integer, and lies in [2^52, 2^53) where the binary64 spacing is 1, so
+// subtracting the constant's bit pattern from the result's leaves that
+// integer.
+constexpr double kFixMagic = 0x1.8p52;
+// the integer left in t = fma(x, y, kFixMagic), for |x y| < 2^51
+__device__ inline unsigned long long fixed_from(double t) {
+  return (unsigned long long)__double_as_longlong(t) - (unsigned long long)__double_as_longlong(kFixMagic);
 }
+__device__ inline unsigned long long to_fixed(double v) { return fixed_from(fma(v, 0x1p46, kFixMagic)); }
 
 __device__ inline double from_fixed(unsigned long long a) {
   const int hi = (int)(a >> 32);
   const unsigned lo = (unsigned)a;
-  return ((double)hi * 0x1p32 + (double)lo) * 0x1p-50;
+  return ((double)hi * 0x1p32 + (double)lo) * 0x1p-46;
 }
 
 // Evaluate the first n (<= 64) items of a queue and add them to their pairs;
@@ -1025,7 +1030,8 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
             rec.py = (float)(xr1 + dist * pl.y);
             rec.pz = (float)(xr2 + dist * pl.z);
             rec.df = df;
-            rec.dh = dH((double)fabsf(df));
+            const double dh = dH((double)fabsf(df));
+            rec.dhs = (df > 0.0f ? -dh : dh) * 0x1p46;
             rec.ihf = (float)ih;
             rec.slot = (uint32_t)(L.wvs[j] - VB) | ((uint32_t)lane << 24);
             fr[e] = rec;
@@ -1040,6 +1046,11 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
     wave_fence();
     // ---------------- A2: one edge per lane; B whenever a queue fills
     int qD = 0, qN = 0;
+    // the rounding constant of fixed_from in scalar registers (otherwise
+    // rebuilt in vector registers for every batch)
+    uint32_t magic_hi;
+    asm volatile("s_mov_b32 %0, 0x43380000" : "=s"(magic_hi));
+    const double magic = __hiloint2double((int)magic_hi, 0);
     // Evaluate batch [b, b + 64) from the data d fetched for it.
     auto batch = [&](int b, const EdgeData &d) {
       const int g = b + lane;
@@ -1063,8 +1074,12 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
       const float tB = fmaf(EA.w, fc.ihf, tA);
       const double ap = (double)fabsf(p), dA = (double)tA, dB = (double)tB;
       const double ad = (double)fabsf(fc.df);
-      const double ang = -fc.dh * MathMixed::span(ap, dA, dB);
-      if (ok) atomicAdd(&L.acc[owner], to_fixed(((p > 0.0f) == (fc.df > 0.0f)) ? ang : -ang));
+      // the angle term -dh (phi_B - phi_A), negated when the edge and the
+      // face are oriented oppositely (p and d of unequal signs): the record's
+      // factor takes the sign bit of p (p != 0 here) and feeds one fma
+      const double f = __hiloint2double(__double2hiint(fc.dhs) ^ (int)(__float_as_uint(p) & 0x80000000u),
+                                        __double2loint(fc.dhs));
+      if (ok) atomicAdd(&L.acc[owner], fixed_from(fma(MathMixed::span(ap, dA, dB), f, magic)));
       // within 2h somewhere on [tA, tB], and crossing U = 1 (squares, no
       // roots; bitwise logic, so that no test becomes a branch)
       const double a2 = ad * ad + ap * ap;
@@ -1133,24 +1148,32 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
       d.ee = load4(cE, v);
       d.em = load4(cM, v);
     };
-    EdgeData nxt{};
-    int recN = 0, vqN = 0;
-    uint32_t slotN = 0;
+    auto slot_of = [&](int rec) { return *(gptr<uint32_t>)((gptr<char>)frg + ((uint32_t)rec << 5) + 28); };
+    // one turn: evaluate batch b from `cur` while batch b + 64 is fetched
+    // into `nxt` (record and slot in r, q, sl) and the record and slot of
+    // batch b + 128 are found (into rn, qn, sn).  The loop below alternates
+    // the roles of the two sets, so no loaded register is copied.
+    auto turn = [&](int b, const EdgeData &cur, EdgeData &nxt, int r, int q, uint32_t sl, int &rn, int &qn,
+                    uint32_t &sn) {
+      locate(b + 128, rn, qn);
+      sn = slot_of(rn);
+      fetch(r, q, sl, nxt);
+      batch(b, cur);
+    };
+    EdgeData dX{}, dY{};
+    int rX = 0, qX = 0, rY = 0, qY = 0;
+    uint32_t sX = 0, sY = 0;
     if (n_edge > 0) {
       int r0, q0;
       locate(0, r0, q0);
-      fetch(r0, q0, *(gptr<uint32_t>)((gptr<char>)frg + ((uint32_t)r0 << 5) + 28), nxt);
-      locate(64, recN, vqN);
-      slotN = *(gptr<uint32_t>)((gptr<char>)frg + ((uint32_t)recN << 5) + 28);
+      fetch(r0, q0, slot_of(r0), dX);
+      locate(64, rX, qX);
+      sX = slot_of(rX);
     }
-    for (int b = 0; b < n_edge; b += 64) {
-      const EdgeData d = nxt;
-      const int r = recN, q = vqN;
-      const uint32_t sl = slotN;
-      locate(b + 128, recN, vqN);
-      slotN = *(gptr<uint32_t>)((gptr<char>)frg + ((uint32_t)recN << 5) + 28);
-      fetch(r, q, sl, nxt);
-      batch(b, d);
+    for (int b = 0; b < n_edge; b += 128) {
+      turn(b, dX, dY, rX, qX, sX, rY, qY, sY);
+      if (b + 64 >= n_edge) break;
+      turn(b + 64, dY, dX, rY, qY, sY, rX, qX, sX);
     }
     if (qD > 0) drain(L, L.qD, L.oD, qD, qD, true, lane, K.fd);
     if (qN > 0) drain(L, L.qN, L.oN, qN, qN, false, lane, K.fd);
