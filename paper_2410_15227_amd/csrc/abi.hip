@@ -383,7 +383,7 @@ int sphmap_set_pool_limit(sphmap_ctx *ctx, uint64_t bytes) {
     pool.cap = (size_t)bytes;
     if (pool.held > pool.cap) {
       SPH_HIP(hipDeviceSynchronize());
-      pool.release();
+      pool.trim();
     }
   });
 }

@@ -51,6 +51,7 @@ struct BlockPool {
   size_t cap = 0;
   void *take(size_t bytes, size_t &got);
   void put(void *p, size_t bytes);
+  void trim();  // frees the largest blocks until the kept total is within cap
   void release();
   ~BlockPool() { release(); }
 };

@@ -22,6 +22,15 @@ void BlockPool::put(void *p, size_t bytes) {
   held += bytes;
 }
 
+void BlockPool::trim() {
+  while (held > cap && !blocks.empty()) {
+    auto it = std::prev(blocks.end());
+    (void)hipFree(it->second);
+    held -= it->first;
+    blocks.erase(it);
+  }
+}
+
 void BlockPool::release() {
   for (auto &kv : blocks) (void)hipFree(kv.second);
   blocks.clear();
