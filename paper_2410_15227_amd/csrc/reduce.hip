@@ -77,6 +77,9 @@ __global__ void __launch_bounds__(256) k_reverse(int64_t N, int ncomp, const int
   double acc[kComp > 0 ? kComp : 1];
   for (int j = 0; j < (kComp > 0 ? kComp : 1); ++j) acc[j] = 0.0;
   if (kComp > 0) {
+    // unrolled so that several turns' loads are in flight; each lane still
+    // adds its terms in index order
+#pragma unroll 4
     for (int64_t j = s + lane; j < e; j += 16) {
       const double wj = pm_w[j];
       const int64_t c = pm_cell[j];
