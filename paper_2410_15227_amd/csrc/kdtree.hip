@@ -55,11 +55,15 @@ __global__ void k_kd_check(int64_t n, const double *xyz, const double *m, int *b
   else atomicMax(mmax, (unsigned long long)__double_as_longlong(mi));
 }
 
-__global__ void k_kd_init(int64_t n, int32_t *perm, int32_t *nop, KdNodes N) {
+// pxm[i] holds the position and mass of particle perm[i], so that the
+// per-level kernels read their particles contiguously instead of gathering
+__global__ void k_kd_init(int64_t n, const double *xyz, const double *m, int32_t *perm, int32_t *nop,
+                          double4 *pxm, KdNodes N) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     perm[i] = (int32_t)i;
     nop[i] = 0;
+    pxm[i] = make_double4(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], m[i]);
   }
   if (i == 0) {
     N.label[0] = 1;
@@ -86,8 +90,8 @@ __global__ void k_kd_zero(int64_t b, int64_t e, KdNodes N) {
 // additions are grouped.
 constexpr int kLdsNodes = 1024;
 
-__global__ void __launch_bounds__(256) k_kd_sums(int64_t n, const int32_t *perm, const int32_t *nop, int64_t b,
-                                                 int64_t e, const double *xyz, const double *m, int K, KdNodes N) {
+__global__ void __launch_bounds__(256) k_kd_sums(int64_t n, const double4 *pxm, const int32_t *nop, int64_t b,
+                                                 int64_t e, int K, KdNodes N) {
 #pragma clang fp contract(off)
   __shared__ unsigned long long acc[4 * kLdsNodes];
   const bool lds = e - b <= kLdsNodes;
@@ -102,11 +106,13 @@ __global__ void __launch_bounds__(256) k_kd_sums(int64_t n, const int32_t *perm,
     if (node < b || node >= e) node = -1;
   }
   if (node >= 0) {
-    const int64_t j = perm[i];
-    const double mj = m[j];
+    const double4 pj = pxm[i];
+    const double mj = pj.w;
     unsigned long long v[4];
     v[0] = (unsigned long long)__double2ll_rn(ldexp(mj, K));
-    for (int k = 0; k < 3; ++k) v[1 + k] = (unsigned long long)__double2ll_rn(ldexp(mj * xyz[3 * j + k], K));
+    v[1] = (unsigned long long)__double2ll_rn(ldexp(mj * pj.x, K));
+    v[2] = (unsigned long long)__double2ll_rn(ldexp(mj * pj.y, K));
+    v[3] = (unsigned long long)__double2ll_rn(ldexp(mj * pj.z, K));
     if (lds) {
       for (int k = 0; k < 4; ++k) atomicAdd(&acc[4 * (node - b) + k], v[k]);
     } else {
@@ -148,9 +154,8 @@ __global__ void k_kd_com(int64_t b, int64_t e, int K, int leaf_split, int max_de
   N.left[k] = -1;
 }
 
-__global__ void __launch_bounds__(256) k_kd_size_flags(int64_t n, const int32_t *perm, const int32_t *nop,
-                                                       int64_t b, int64_t e, const double *xyz, KdNodes N,
-                                                       int64_t *flag) {
+__global__ void __launch_bounds__(256) k_kd_size_flags(int64_t n, const double4 *pxm, const int32_t *nop,
+                                                       int64_t b, int64_t e, KdNodes N, int64_t *flag) {
 #pragma clang fp contract(off)
   __shared__ unsigned long long mx[kLdsNodes];
   const bool lds = e - b <= kLdsNodes;
@@ -163,15 +168,15 @@ __global__ void __launch_bounds__(256) k_kd_size_flags(int64_t n, const int32_t 
     const int64_t node = nop[i];
     int64_t f = 0;
     if (node >= b && node < e) {
-      const int64_t j = perm[i];
+      const double4 pj = pxm[i];
       const double4 c = N.com[node];
-      const double dx = xyz[3 * j] - c.x, dy = xyz[3 * j + 1] - c.y, dz = xyz[3 * j + 2] - c.z;
+      const double dx = pj.x - c.x, dy = pj.y - c.y, dz = pj.z - c.z;
       const double d2 = (dx * dx + dy * dy) + dz * dz;
       const unsigned long long bits = (unsigned long long)__double_as_longlong(d2);
       if (lds) atomicMax(&mx[node - b], bits);
       else atomicMax(&N.s2[node], bits);
       const int a = N.axis[node];
-      if (a >= 0) f = xyz[3 * j + a] < N.split[node] ? 1 : 0;
+      if (a >= 0) f = (a == 0 ? pj.x : (a == 1 ? pj.y : pj.z)) < N.split[node] ? 1 : 0;
     }
     flag[i] = f;
   }
@@ -227,14 +232,16 @@ __global__ void k_kd_children(int64_t b, int64_t e, int64_t base, const int64_t 
   }
 }
 
-__global__ void k_kd_permute(int64_t n, const int32_t *perm, const int32_t *nop, int32_t *perm2, int32_t *nop2,
-                             int64_t b, int64_t e, const int64_t *scan, const int64_t *flag, KdNodes N) {
+__global__ void k_kd_permute(int64_t n, const int32_t *perm, const int32_t *nop, const double4 *pxm, int32_t *perm2,
+                             int32_t *nop2, double4 *pxm2, int64_t b, int64_t e, const int64_t *scan,
+                             const int64_t *flag, KdNodes N) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t node = nop[i];
   if (node < b || node >= e || N.axis[node] < 0) {
     perm2[i] = perm[i];
     nop2[i] = (int32_t)node;
+    pxm2[i] = pxm[i];
     return;
   }
   const int64_t f = N.first[node];
@@ -250,6 +257,7 @@ __global__ void k_kd_permute(int64_t n, const int32_t *perm, const int32_t *nop,
   }
   perm2[to] = perm[i];
   nop2[to] = child;
+  pxm2[to] = pxm[i];
 }
 
 __device__ inline bool kd_in(uint64_t label, int64_t n_open, const uint64_t *open) {
@@ -475,8 +483,9 @@ void kd_pseudo_build(Ctx &ctx, KdArgs &ka, hipStream_t s) {
   N.split = ar.get<double>("kd_split", cap);
   int32_t *perm = ar.get<int32_t>("kd_perm", n), *perm2 = ar.get<int32_t>("kd_perm2", n);
   int32_t *nop = ar.get<int32_t>("kd_nop", n), *nop2 = ar.get<int32_t>("kd_nop2", n);
+  double4 *pxm = ar.get<double4>("kd_pxm", n), *pxm2 = ar.get<double4>("kd_pxm2", n);
   int64_t *flag = ar.get<int64_t>("kd_flag", n + 1), *scan = ar.get<int64_t>("kd_scan", n + 1);
-  k_kd_init<<<grid_of(n), 256, 0, s>>>(n, perm, nop, N);
+  k_kd_init<<<grid_of(n), 256, 0, s>>>(n, a.xyz, a.m, perm, nop, pxm, N);
   SPH_LAUNCH_CHECK();
   std::vector<int64_t> loff = {0, 1};
   {
@@ -486,11 +495,11 @@ void kd_pseudo_build(Ctx &ctx, KdArgs &ka, hipStream_t s) {
       const int64_t cnt = e - b;
       k_kd_zero<<<grid_of(cnt), 256, 0, s>>>(b, e, N);
       SPH_LAUNCH_CHECK();
-      k_kd_sums<<<grid_of(n), 256, 0, s>>>(n, perm, nop, b, e, a.xyz, a.m, K, N);
+      k_kd_sums<<<grid_of(n), 256, 0, s>>>(n, pxm, nop, b, e, K, N);
       SPH_LAUNCH_CHECK();
       k_kd_com<<<grid_of(cnt), 256, 0, s>>>(b, e, K, ka.leaf_split, o.max_depth, N);
       SPH_LAUNCH_CHECK();
-      k_kd_size_flags<<<grid_of(n), 256, 0, s>>>(n, perm, nop, b, e, a.xyz, N, flag);
+      k_kd_size_flags<<<grid_of(n), 256, 0, s>>>(n, pxm, nop, b, e, N, flag);
       SPH_LAUNCH_CHECK();
       scan_exclusive_i64(ar, flag, scan, n, true, s);
       int64_t *nch = ar.get<int64_t>("kd_nch", cnt + 1), *choff = ar.get<int64_t>("kd_choff", cnt + 1);
@@ -504,10 +513,11 @@ void kd_pseudo_build(Ctx &ctx, KdArgs &ka, hipStream_t s) {
       SPH_REQUIRE(e + tot <= cap, SPHMAP_EINVAL, "k-d tree larger than 2n nodes");
       k_kd_children<<<grid_of(cnt), 256, 0, s>>>(b, e, e, choff, N);
       SPH_LAUNCH_CHECK();
-      k_kd_permute<<<grid_of(n), 256, 0, s>>>(n, perm, nop, perm2, nop2, b, e, scan, flag, N);
+      k_kd_permute<<<grid_of(n), 256, 0, s>>>(n, perm, nop, pxm, perm2, nop2, pxm2, b, e, scan, flag, N);
       SPH_LAUNCH_CHECK();
       std::swap(perm, perm2);
       std::swap(nop, nop2);
+      std::swap(pxm, pxm2);
       loff.push_back(e + tot);
     }
     kt.done();
