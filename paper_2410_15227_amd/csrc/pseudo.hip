@@ -171,7 +171,16 @@ constexpr int kBigNode = 4096;  // members above which a node's size takes a who
 
 // One wave per node of at most kBigNode members: max squared member
 // distance from the centre of mass and the lowest member particle index.
-__global__ void __launch_bounds__(256) k_node_size(NodeArrays N, int64_t nn, const int32_t *sidx, const double *xyz,
+// positions in the sorted order of sidx, so that the node-size kernels read
+// each node's particles contiguously instead of gathering them
+__global__ void k_sorted_xyz(int64_t n, const int32_t *sidx, const double *xyz, double4 *sx) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int64_t j = sidx[t];
+  sx[t] = make_double4(xyz[3 * j], xyz[3 * j + 1], xyz[3 * j + 2], 0.0);
+}
+
+__global__ void __launch_bounds__(256) k_node_size(NodeArrays N, int64_t nn, const int32_t *sidx, const double4 *sx,
                                                   const double4 *com, double *s2, int32_t *minidx) {
 #pragma clang fp contract(off)
   const int64_t node = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -184,7 +193,8 @@ __global__ void __launch_bounds__(256) k_node_size(NodeArrays N, int64_t nn, con
   int32_t mi = INT32_MAX;
   for (int32_t t = f + lane; t < f + c; t += 64) {
     const int32_t j = sidx[t];
-    const double dx = xyz[3 * (int64_t)j] - g.x, dy = xyz[3 * (int64_t)j + 1] - g.y, dz = xyz[3 * (int64_t)j + 2] - g.z;
+    const double4 p = sx[t];
+    const double dx = p.x - g.x, dy = p.y - g.y, dz = p.z - g.z;
     const double s = (dx * dx + dy * dy) + dz * dz;
     mx = fmax(mx, s);
     mi = min(mi, j);
@@ -213,7 +223,7 @@ __global__ void k_list_big(NodeArrays N, int64_t nn, const int64_t *off, int32_t
 // (grid-stride over the device-side list; max and min do not depend on the
 // order in which the waves finish).
 __global__ void __launch_bounds__(1024) k_node_size_big(NodeArrays N, const int32_t *list, const int64_t *n_list,
-                                                       const int32_t *sidx, const double *xyz, const double4 *com,
+                                                       const int32_t *sidx, const double4 *sx, const double4 *com,
                                                        double *s2, int32_t *minidx) {
 #pragma clang fp contract(off)
   __shared__ double smx[16];
@@ -228,8 +238,8 @@ __global__ void __launch_bounds__(1024) k_node_size_big(NodeArrays N, const int3
     int32_t mi = INT32_MAX;
     for (int32_t t = f + (int32_t)threadIdx.x; t < f + c; t += (int32_t)blockDim.x) {
       const int32_t j = sidx[t];
-      const double dx = xyz[3 * (int64_t)j] - g.x, dy = xyz[3 * (int64_t)j + 1] - g.y,
-                   dz = xyz[3 * (int64_t)j + 2] - g.z;
+      const double4 p = sx[t];
+      const double dx = p.x - g.x, dy = p.y - g.y, dz = p.z - g.z;
       const double s = (dx * dx + dy * dy) + dz * dz;
       mx = fmax(mx, s);
       mi = min(mi, j);
@@ -816,7 +826,10 @@ void pseudo_build(Ctx &ctx, PseudoArgs &a, hipStream_t s) {
   }
   k_com<<<(unsigned)div_up(nn, 256), 256, 0, s>>>(nn, M, S, com);
   SPH_LAUNCH_CHECK();
-  k_node_size<<<(unsigned)div_up(nn * 64, 256), 256, 0, s>>>(N, nn, sidx, a.xyz, com, s2, minidx);
+  double4 *sx = ar.get<double4>("ps_sx", n);
+  k_sorted_xyz<<<(unsigned)div_up(n, 256), 256, 0, s>>>(n, sidx, a.xyz, sx);
+  SPH_LAUNCH_CHECK();
+  k_node_size<<<(unsigned)div_up(nn * 64, 256), 256, 0, s>>>(N, nn, sidx, sx, com, s2, minidx);
   SPH_LAUNCH_CHECK();
   {
     int64_t *bflag = ar.get<int64_t>("ps_bflag", nn + 1);
@@ -829,7 +842,7 @@ void pseudo_build(Ctx &ctx, PseudoArgs &a, hipStream_t s) {
     SPH_LAUNCH_CHECK();
     // at most n / kBigNode big nodes per level
     const int64_t bound = std::max<int64_t>(1, (int64_t)(loff.size() - 1) * (n / kBigNode + 1));
-    k_node_size_big<<<(unsigned)std::min<int64_t>(bound, 2048), 1024, 0, s>>>(N, blist, boff + nn, sidx, a.xyz, com,
+    k_node_size_big<<<(unsigned)std::min<int64_t>(bound, 2048), 1024, 0, s>>>(N, blist, boff + nn, sidx, sx, com,
                                                                               s2, minidx);
     SPH_LAUNCH_CHECK();
   }
