@@ -481,6 +481,92 @@ double ora_weight_poly(const double *x, double h, int nf, const int *fsz, const 
   return w;
 }
 
+/* ------------------------------------------- distance of a point to a cell */
+/* Distance from x to the segment [A, B] in space. */
+static double seg_dist(const double *x, const double *A, const double *B) {
+  double ab[3], ax[3];
+  v_sub(B, A, ab);
+  v_sub(x, A, ax);
+  double L2 = v_dot(ab, ab);
+  double t = L2 > 0.0 ? v_dot(ax, ab) / L2 : 0.0;
+  if (t < 0.0) t = 0.0;
+  if (t > 1.0) t = 1.0;
+  double d[3] = {ax[0] - t * ab[0], ax[1] - t * ab[1], ax[2] - t * ab[2]};
+  return sqrt(v_dot(d, d));
+}
+
+/* Signed distance of x to cell c, the quantity that decides the exact 0/1
+   shortcuts of the mapping (a kernel support of radius 2h that stays clear
+   of every face gives w = 0 outside the cell and 1 inside):
+     outside the cell: the distance to the nearest point of the cell
+                       (positive), i.e. the smallest distance to a face
+                       polygon;
+     inside:           minus the distance to the nearest face plane (for a
+                       convex cell that is the distance to the boundary).
+   Faces are oriented outwards from the vertex-incidence average, as in the
+   weight; a face polygon's distance is |d| when the foot point lies inside
+   it, else the smallest edge-segment distance. */
+static double cell_distance(const tess_t *T, int64_t c, const double *x) {
+  int64_t f0 = T->cfo[c], f1 = T->cfo[c + 1];
+  double inside[3] = {0, 0, 0};
+  int64_t k = 0;
+  for (int64_t t = T->fvo[f0]; t < T->fvo[f1]; ++t, ++k)
+    for (int j = 0; j < 3; ++j) inside[j] += T->vert[3 * (int64_t)T->fv[t] + j];
+  for (int j = 0; j < 3; ++j) inside[j] /= (k > 0 ? (double)k : 1.0);
+  double smax = -HUGE_VAL, dmin = HUGE_VAL;
+  for (int64_t f = f0; f < f1; ++f) {
+    int nv = (int)(T->fvo[f + 1] - T->fvo[f]);
+    if (nv < 3) continue;
+    const double *V[512];
+    if (nv > 512) continue;
+    for (int q = 0; q < nv; ++q) V[q] = T->vert + 3 * (int64_t)T->fv[T->fvo[f] + q];
+    double avec[3], cen[3];
+    poly_area_vec(nv, V, avec, cen);
+    double an = sqrt(v_dot(avec, avec));
+    if (an == 0.0) continue;
+    double n[3] = {avec[0] / an, avec[1] / an, avec[2] / an};
+    double gc[3];
+    v_sub(cen, inside, gc);
+    if (v_dot(n, gc) < 0.0)
+      for (int j = 0; j < 3; ++j) n[j] = -n[j];
+    double xc[3];
+    v_sub(x, cen, xc);
+    double s = v_dot(n, xc); /* > 0: x beyond this face's plane */
+    if (s > smax) smax = s;
+    /* the foot point lies inside the polygon iff it is on the inner side of
+       every edge line (the polygon is convex) */
+    double P0[3] = {x[0] - s * n[0], x[1] - s * n[1], x[2] - s * n[2]};
+    int in = 1;
+    double emin = HUGE_VAL;
+    for (int q = 0; q < nv; ++q) {
+      const double *A = V[q], *B = V[(q + 1) % nv];
+      double ab[3], ap[3], cr[3], ac[3];
+      v_sub(B, A, ab);
+      v_sub(P0, A, ap);
+      v_sub(cen, A, ac);
+      v_cross(ab, ap, cr);
+      double side = v_dot(cr, n);
+      v_cross(ab, ac, cr);
+      double ref = v_dot(cr, n); /* the centroid's side of this edge */
+      if (side * ref < 0.0) in = 0;
+      double e = seg_dist(x, A, B);
+      if (e < emin) emin = e;
+    }
+    double dp = in ? fabs(s) : emin;
+    if (dp < dmin) dmin = dp;
+  }
+  if (smax <= 0.0) return smax; /* inside: minus the distance to the nearest plane */
+  return dmin;
+}
+
+void ora_cell_distance(int64_t n_cells, const double *gen, const double *vert, const int64_t *cfo,
+                       const int64_t *fvo, const int32_t *fv, int64_t n_list, const int64_t *cells,
+                       const double *xyz, double *out) {
+  tess_t T = {n_cells, gen, vert, cfo, fvo, fv};
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < n_list; ++k) out[k] = cell_distance(&T, cells[k], xyz + 3 * k);
+}
+
 /* Angular fan integral, exposed for unit tests:
    int_{pa}^{pb} Psi_{ad}(sqrt(ad^2 + p^2 sec^2 phi)) dphi. */
 double ora_fan_integral(double ad, double p, double pa, double pb) {

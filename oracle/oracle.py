@@ -75,6 +75,8 @@ def _lib():
         L.ora_voronoi_cells.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp]
         L.ora_lloyd.restype = None
         L.ora_lloyd.argtypes = [i64, vp, vp, vp, i32, vp]
+        L.ora_cell_distance.restype = None
+        L.ora_cell_distance.argtypes = tess + [i64, vp, vp, vp]
         L.ora_interpolate.restype = None
         L.ora_interpolate.argtypes = [i64, vp, vp, i64, vp, vp, vp, vp, i32, vp]
         _L = L
@@ -136,6 +138,19 @@ def weight_poly(x, h, faces, inside=None) -> float:
 def weight(t, c: int, x, h: float) -> float:
     x = _c(x, np.float64)
     return _lib().ora_weight(*_tess_args(t), int(c), _p(x), float(h))
+
+
+def cell_distance(t, cells, xyz):
+    """Signed distance of point xyz[k] to cell cells[k]: positive outside
+    (distance to the nearest point of the cell), minus the distance to the
+    nearest face plane inside.  The exact 0/1 shortcuts of the mapping hold
+    where it is at least 2h (w = 0) or at most -2h (w = 1)."""
+    cells = _c(cells, np.int64)
+    xyz = _c(np.asarray(xyz, float).reshape(-1, 3), np.float64)
+    assert len(cells) == xyz.shape[0]
+    out = np.empty(len(cells))
+    _lib().ora_cell_distance(*_tess_args(t), len(cells), _p(cells), _p(xyz), _p(out))
+    return out
 
 
 def cell_info(t, cells=None):
