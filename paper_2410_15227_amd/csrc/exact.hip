@@ -773,6 +773,7 @@ static_assert(sizeof(FaceRec) == 32, "records are addressed as index << 5");
 struct EdgeData {  // what one lane reads for its edge: face record and edge geometry
   FaceRec fc;
   float4 ea, ee, em;
+  int rec;  // index of the face record
 };
 
 struct Sphere {
@@ -785,11 +786,19 @@ struct EdgeWave {  // per-wavefront LDS
     Sphere wsp[64];               // cull: the window's bounding spheres
     unsigned long long sb[kEdgeCap];  // edge walk: bit g set where a face's edges start (64 kEdgeCap bits)
   };
-  int wvs[64], wnv[64];  // first vertex slot, vertex count
+  // cull and face list: the window's first vertex slot and vertex count (at
+  // most 128); after the face list, each pair's first face record and its
+  // number of records
+  int wvs[64];
+  unsigned char wnv[64];
   unsigned long long acc[64];
   float4 qD[kQueue], qN[kQueue];
   unsigned char oD[kQueue], oN[kQueue];
-  int redo[64];
+  unsigned char redo[64];    // the pair is left to the redo kernel
+  unsigned char hasint[64];  // some edge of the pair comes within 2h
+  // bit r set when an edge of face record r has its foot point outside
+  // (p < 0): the record's foot point then lies outside its polygon
+  unsigned long long nin[kEntryCap / 64];
 };
 
 template <typename T>
@@ -953,7 +962,7 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
           L.wsp[lane] = Sphere{sph.x, sph.y, sph.z, sph.w};
           const int64_t vs = fvo[f];
           L.wvs[lane] = (int)vs;
-          L.wnv[lane] = (int)(fvo[f + 1] - vs);
+          L.wnv[lane] = (unsigned char)(fvo[f + 1] - vs);
         }
       }
       wave_sync();
@@ -997,6 +1006,8 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
     const int n_rec = __builtin_amdgcn_readlane(e_off + nsurv, 63);
     L.acc[lane] = 0ull;
     L.redo[lane] = again ? 1 : 0;
+    L.hasint[lane] = 0;
+    L.nin[lane] = 0ull;
     if (kCount) K.nf_int += nsurv;
     // the start bits of the chunk's edges, n_edge <= 64 kEdgeCap of them
     for (int w = lane; w < (n_edge + 63) >> 6; w += 64) L.sb[w] = 0ull;
@@ -1011,7 +1022,7 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
             L.wpl[lane] = load4(fplane, f);
             const int64_t vs = fvo[f];
             L.wvs[lane] = (int)vs;
-            L.wnv[lane] = (int)(fvo[f + 1] - vs);
+            L.wnv[lane] = (unsigned char)(fvo[f + 1] - vs);
           }
         }
         wave_sync();
@@ -1044,6 +1055,8 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
       }
     }
     wave_fence();
+    L.wvs[lane] = e_off;
+    L.wnv[lane] = (unsigned char)nsurv;
     // ---------------- A2: one edge per lane; B whenever a queue fills
     int qD = 0, qN = 0;
     // the rounding constant of fixed_from in scalar registers (otherwise
@@ -1063,13 +1076,19 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
       const int owner = (int)(fc.slot >> 24);
       const float dx = fc.px - EA.x, dy = fc.py - EA.y, dz = fc.pz - EA.z;
       const float p = (dx * EM.x + dy * EM.y + dz * EM.z) * fc.ihf;
-      const bool act = live & (EA.w > 0.0f) & (p != 0.0f);
+      // an edge of positive length whose foot point lies within 1e-4 h of
+      // its line (p = 0 included) needs binary64 geometry: the pair goes to
+      // the redo kernel
+      const bool act = live & (EA.w > 0.0f);
       const bool degen = act & (fabsf(p) < kDegenerate);
       if (degen) {
         ++K.n64;
-        L.redo[owner] = 1;  // binary64 geometry for this pair
+        L.redo[owner] = 1;
       }
       const bool ok = act & !degen;
+      // the foot point is outside the record's polygon if any edge sees it
+      // on its outer side
+      if (ok & (p < 0.0f)) atomicOr(&L.nin[d.rec >> 6], 1ull << (d.rec & 63));
       const float tA = -(dx * EE.x + dy * EE.y + dz * EE.z) * fc.ihf;
       const float tB = fmaf(EA.w, fc.ihf, tA);
       const double ap = (double)fabsf(p), dA = (double)tA, dB = (double)tB;
@@ -1096,6 +1115,7 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
       const float4 it = make_float4(fc.df, p, tA, tB);
       const uint64_t mD = __ballot(integ && cross), mN = __ballot(integ && !cross);
       if (integ) {
+        L.hasint[owner] = 1;
         // set bits of the scalar masks below this lane, counted in hardware
         const int pos = cross ? qD + mbcnt64(mD) : qN + mbcnt64(mN);
         float4 *const q = cross ? L.qD : L.qN;
@@ -1142,6 +1162,7 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
     const gptr<FaceRec> frg = (gptr<FaceRec>)fr;
     const gptr<float4> cA = edgeA + VB, cE = edgeE + VB, cM = edgeM + VB;
     auto fetch = [&](int rec, int vq, uint32_t slot, EdgeData &d) {
+      d.rec = rec;
       d.fc = load_rec(frg, rec);
       const uint32_t v = (slot & 0xffffffu) + (uint32_t)vq;
       d.ea = load4(cA, v);
@@ -1179,7 +1200,21 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
     if (qN > 0) drain(L, L.qN, L.oN, qN, qN, false, lane, K.fd);
     wave_sync();
     if (valid && !again && L.redo[lane] == 0) {
-      I.w[k] = (inside ? 1.0 : 0.0) - kInv4Pi * from_fixed(L.acc[lane]);
+      double wk;
+      if (L.hasint[lane]) {
+        wk = (inside ? 1.0 : 0.0) - kInv4Pi * from_fixed(L.acc[lane]);
+      } else {
+        // No edge within 2h: each face's angle terms add up to exactly
+        // 2 pi [foot point inside its polygon] times its factor, so the
+        // weight is formed from those exact sums (a support clear of every
+        // face gives exactly 0 or 1) instead of the rounded per-edge terms.
+        double sum = 0.0;
+        const int r0 = L.wvs[lane], r1 = r0 + L.wnv[lane];
+        for (int r = r0; r < r1; ++r)
+          if (!((L.nin[r >> 6] >> (r & 63)) & 1ull)) sum += load_rec(frg, r).dhs;
+        wk = (inside ? 1.0 : 0.0) - 0.5 * 0x1p-46 * sum;
+      }
+      I.w[k] = wk;
     } else if (valid) {
       redo[atomicAdd(n_redo, 1)] = gchunk * 64 + lane;
     }

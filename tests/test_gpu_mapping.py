@@ -49,6 +49,40 @@ def run_map(pkg, ctx, wl, precision, keep=True):
     return dt, res
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_exact_shortcuts(ctx, c1, c1_oracle, oracle, precision):
+    """A support that stays clear of every face of the cell gives exactly 0
+    (particle outside) or exactly 1 (inside), on both paths: the point-to-cell
+    distance of every candidate pair of uniform_4096 decides which pairs are
+    such, independently of the device path.  A margin of 1e-5 h keeps pairs
+    whose support touches an edge to within binary32 geometry out of it."""
+    import paper_2410_15227_amd as pkg
+    say(f"case: uniform_4096 exact 0/1 shortcuts, precision={precision}")
+    off, idx, w, M, vol, rad = c1_oracle
+    cells = np.repeat(np.arange(c1.tess.n_cells), np.diff(off))
+    dist = oracle.cell_distance(c1.tess, cells, c1.pos[idx])
+    hh = c1.h[idx]
+    clear_out = dist >= 2.0 * hh * (1.0 + 1e-5)
+    clear_in = dist <= -2.0 * hh * (1.0 + 1e-5)
+    say(f"pairs {len(idx)}: support clear outside {clear_out.sum()}, clear inside {clear_in.sum()}")
+    # uniform_4096's supports are larger than its cells, so no support fits
+    # inside one (the exact 1 is pinned by the lattice cases with tiny h)
+    assert clear_out.sum() > 100000
+    dt, res = run_map(pkg, ctx, c1, precision)
+    goff, gidx, gw = (t.cpu().numpy() for t in res.pairs.export())
+    assert np.array_equal(gidx, idx)
+    bad_out = np.flatnonzero(clear_out & (gw != 0.0))
+    bad_in = np.flatnonzero(clear_in & (gw != 1.0))
+    assert len(bad_out) == 0, (len(bad_out), gw[bad_out[:5]], dist[bad_out[:5]] / hh[bad_out[:5]])
+    assert len(bad_in) == 0, (len(bad_in), gw[bad_in[:5]])
+    # the oracle agrees that these weights vanish (it sums every face)
+    assert np.max(np.abs(w[clear_out])) < 1e-13
+    if clear_in.any():
+        assert np.max(np.abs(w[clear_in] - 1.0)) < 1e-13
+    res.pairs.free()
+    dt.free()
+
+
 def test_cell_info_matches(ctx, c1, c1_oracle):
     import paper_2410_15227_amd as pkg
     say("case: uniform_4096 cell info")
@@ -78,6 +112,10 @@ def test_uniform_4096_full(ctx, c1, c1_oracle, precision):
     else:
         assert np.max(np.abs(gw - w)) < 1e-5
         assert np.max(rel) < 1e-5
+    # the oracle sums every face (no shortcut): its exact zeros are pairs
+    # whose terms all vanish; the mixed path's angle terms there carry the
+    # 2e-9 relative error of its binary32-core atan (the exact 0/1 cases
+    # themselves are pinned in test_exact_shortcuts)
     assert np.all(np.abs(gw[w == 0.0]) < (1e-15 if precision == "fp64" else 1e-8))
     np.testing.assert_allclose(res.density.cpu().numpy(), gm / vol, rtol=1e-12)
     # coverage: sum over the particle's cells of the oracle weights
@@ -150,8 +188,10 @@ def test_lattice_special_positions(ctx, oracle, precision):
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_near_degenerate_positions(ctx, oracle, precision):
     """Particles 3e-5 h, 1e-7 h and 1e-11 h off a face plane, an edge line
-    and a corner of the cubic lattice: the cases the mixed path routes to
-    binary64 geometry (|d| or |p| below 1e-4 h), against the oracle."""
+    and a corner of the cubic lattice, and particles whose foot point on a
+    face plane 0.3 h away lies on an edge line or 1e-9 h beside it: the cases
+    the mixed path routes to binary64 geometry (|d| or |p| below 1e-4 h,
+    p = 0 included), against the oracle."""
     import paper_2410_15227_amd as pkg
     say(f"case: near-degenerate positions, precision={precision}")
     t = lattice(6)
@@ -164,6 +204,14 @@ def test_near_degenerate_positions(ctx, oracle, precision):
                 [2 * a - dlt, 3 * a + dlt, 0.371],     # edge x = 2a, y = 3a
                 [2 * a + dlt, 3 * a - dlt, 4 * a + dlt]]  # corner
         hs += [h0, h0, h0]
+    # 0.3 h off the face plane x = 2a with the foot point on the edge line
+    # y = 3a of that face (p = 0 exactly) and 1e-9 h beside it: only the edge
+    # is degenerate, the face is not
+    yb = t.vertices[np.argmin(np.abs(t.vertices[:, 1] - 3 * a)), 1]
+    xb = t.vertices[np.argmin(np.abs(t.vertices[:, 0] - 2 * a)), 0]
+    for eps in (0.0, 1e-9):
+        pts += [[xb + 0.3 * h0, yb + eps * h0, 0.371], [xb - 0.3 * h0, yb - eps * h0, 0.629]]
+        hs += [h0, h0]
     pts = np.array(pts)
     hs = np.array(hs)
     m = np.ones(len(pts))
