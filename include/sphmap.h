@@ -41,7 +41,9 @@ extern "C" {
 
 #define SPHMAP_OK 0
 #define SPHMAP_EINVAL (-1) /* bad argument, size or layout                  */
-#define SPHMAP_ENOMEM (-2) /* device allocation failed                      */
+#define SPHMAP_ENOMEM (-2) /* device allocation failed, or the context's
+                              workspace limit is too small (the bytes the
+                              call needs: sphmap_workspace_info)            */
 #define SPHMAP_EGEOM (-3)  /* tessellation fails validation                 */
 #define SPHMAP_EHIP (-4)   /* HIP runtime error                             */
 #define SPHMAP_ERANGE (-5) /* output capacity too small                     */
@@ -64,8 +66,23 @@ typedef struct sphmap_pairs sphmap_pairs; /* retained pair list and weights   */
 /* Library version (major*10000 + minor*100 + patch). */
 int sphmap_version(void);
 
-/* Create a context on HIP device `device`.  *out receives the handle. */
-int sphmap_create(int32_t device, sphmap_ctx **out);
+/* Create a context on HIP device `device`.  *out receives the handle.
+   workspace_bytes caps the device memory of the context's scratch (pair
+   search, Exact-integral work lists, transpose, and the pair lists of calls
+   that keep none); 0 = no cap, the scratch grows on demand.  The scratch is
+   kept between calls.  A call whose scratch would pass the cap fails with
+   SPHMAP_ENOMEM before it allocates; sphmap_workspace_info then reports an
+   upper bound of the workspace it needs (sphmap_estimate_footprint gives the
+   same bound beforehand).  Retained pair lists (pairs_out) and uploaded
+   grids are not part of the workspace. */
+int sphmap_create(int32_t device, size_t workspace_bytes, sphmap_ctx **out);
+/* Change the workspace cap (0 = none).  Lowering it below what the scratch
+   holds frees the scratch (after waiting for the device). */
+int sphmap_set_workspace_limit(sphmap_ctx *ctx, size_t bytes);
+/* Device bytes the scratch holds now, the cap, and the largest workspace a
+   call refused with SPHMAP_ENOMEM since the cap was last set (0 if none);
+   any pointer may be NULL. */
+int sphmap_workspace_info(sphmap_ctx *ctx, size_t *held, size_t *limit, size_t *required);
 /* Release a context and everything it still owns (tessellations and pair
    lists created from it must be freed first or become invalid). */
 int sphmap_destroy(sphmap_ctx *ctx);
@@ -184,9 +201,15 @@ int sphmap_tess_export(sphmap_ctx *ctx, const sphmap_tess *tess, double *d_gener
  * Candidate pairs (c,i) are those with d2 < s*s evaluated in binary32,
  * round to nearest, without contraction: dx = fl(x_i) - fl(g_x) (same for y,
  * z), d2 = (dx*dx + dy*dy) + dz*dz, s = R_c + 2 fl(h_i).  Every pair whose
- * kernel support overlaps the cell is a candidate; candidates that do not
- * overlap get w = 0 exactly.  Cells take their pairs in ascending particle
- * index and M_c is summed in that order (deterministic).
+ * kernel support overlaps the cell is a candidate; a candidate whose support
+ * stays clear of every face gets w = 0 exactly (1 exactly for a support
+ * inside the cell).  Cells take their pairs in ascending particle index.
+ * M_c is summed in a fixed order that does not depend on the launch: with
+ * the cell's pairs numbered k = 0, 1, ... in that index order, partial sum
+ * l (l = 0..63) adds m_i w_ic over k = l, l + 64, l + 128, ... in turn
+ * (each product rounded, then added), and the 64 partials are combined
+ * pairwise, partial l with partial l + 32, then l + 16, l + 8, l + 4, l + 2,
+ * l + 1 (a butterfly), so results repeat bit for bit.
  * Errors: EINVAL (n < 1, n >= 2^31, null required pointer, bad precision).
  * ---------------------------------------------------------------------- */
 int map_particles_to_cells(sphmap_ctx *ctx, const sphmap_tess *tess, int64_t n, const double *d_xyz,
@@ -240,14 +263,26 @@ int sphmap_set_pool_limit(sphmap_ctx *ctx, uint64_t bytes);
 /* ------------------------------------------------------------------------
  * Inverse mapping (Sec. 2.3, the ionic fractions returned onto the
  * (pseudo-)particles): q_i = sum_c w_ic q_c / c_i, c_i = sum_c w_ic, q_i = 0
- * where c_i = 0.  Uses the weights of a retained pair list.
+ * where c_i = 0.
+ *   pairs (nullable): a retained pair list of the forward mapping; its
+ *     weights are used and tess, d_xyz, d_h and precision are ignored (n
+ *     must be 0 or the list's particle count).  NULL: the weights are
+ *     recomputed from the particles d_xyz [n][3], d_h [n] (device, binary64)
+ *     and the grid tess, as the forward mapping at `precision` would give
+ *     them (pair search, Exact integral), in the context's workspace.
  *   d_cell_values [n_cells][n_components]      (row-major, binary64)
  *   d_particle_values [n][n_components]
- * Each particle's sums run over its cells in ascending cell index
- * (deterministic).  Errors: EINVAL (null pointers, n_components < 1).
- * ---------------------------------------------------------------------- */
-int map_cells_to_particles(sphmap_ctx *ctx, const sphmap_pairs *pairs, const double *d_cell_values,
-                           int32_t n_components, double *d_particle_values, void *stream);
+ * Each particle's sums take its cells in ascending cell index, 16 partial
+ * sums per particle: with the particle's pairs numbered j = 0, 1, ... in
+ * that order, partial l (l = 0..15) adds w_ic q_c over j = l, l + 16, ...
+ * in turn, and the partials are combined pairwise, l with l + 8, then l + 4,
+ * l + 2, l + 1; the sum is then divided by c_i.  Results repeat bit for bit.
+ * Errors: EINVAL (null pointers, n_components < 1, without a list: n out of
+ * [1, 2^31), bad precision), ENOMEM (workspace). */
+int map_cells_to_particles(sphmap_ctx *ctx, const sphmap_tess *tess, int64_t n, const double *d_xyz,
+                           const double *d_h, int32_t precision, const sphmap_pairs *pairs,
+                           const double *d_cell_values, int32_t n_components, double *d_particle_values,
+                           void *stream);
 
 /* ------------------------------------------------------------------------
  * Pseudo-particles (Sec. 2.4).  The particles (positions in [0,1)^3) are

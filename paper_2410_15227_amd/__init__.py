@@ -53,9 +53,10 @@ def _dev_f64(x, device, shape_last=None):
 
 
 class Context:
-    """A library context on one HIP device (torch device index)."""
+    """A library context on one HIP device (torch device index).
+    workspace_bytes: cap on the context's device scratch (0 = none)."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, workspace_bytes: int = 0):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the mapping runs only on the HIP device")
@@ -63,7 +64,7 @@ class Context:
         torch.cuda.set_device(self.device)
         L = _native.lib()
         h = ctypes.c_void_p()
-        _native.check(L.sphmap_create(device, ctypes.byref(h)))
+        _native.check(L.sphmap_create(device, int(workspace_bytes), ctypes.byref(h)))
         self.handle = h
 
     def close(self):
@@ -79,6 +80,16 @@ class Context:
 
     def check(self, rc):
         _native.check(rc, self.handle)
+
+    def set_workspace_limit(self, nbytes: int):
+        self.check(_native.lib().sphmap_set_workspace_limit(self.handle, int(nbytes)))
+
+    def workspace_info(self) -> dict:
+        """held, limit and required (the workspace the last refused call needs)."""
+        a, b, c = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        self.check(_native.lib().sphmap_workspace_info(self.handle, ctypes.byref(a), ctypes.byref(b),
+                                                       ctypes.byref(c)))
+        return dict(held=a.value, limit=b.value, required=c.value)
 
     def upload(self, tess, stream=None) -> "DeviceTessellation":
         return DeviceTessellation(self, tess, stream)
@@ -347,18 +358,35 @@ def map_particles_to_cells_batch(ctx: Context, tess, xyz, h, m, precision: str |
     return out
 
 
-def map_cells_to_particles(ctx: Context, pairs: Pairs, cell_values, out=None, stream=None):
-    """Inverse mapping q_i = sum_c w_ic q_c / c_i ([C] or [C,k] -> [n] or [n,k])."""
+def map_cells_to_particles(ctx: Context, pairs, cell_values, out=None, stream=None, *, tess=None, xyz=None,
+                           h=None, precision: str | int = "mixed"):
+    """Inverse mapping q_i = sum_c w_ic q_c / c_i ([C] or [C,k] -> [n] or [n,k]).
+    pairs: a retained list of the forward mapping, or None to recompute the
+    weights from the particles (xyz, h) and the grid `tess`."""
     torch = _torch()
     q = torch.as_tensor(cell_values, dtype=torch.float64, device=ctx.device).contiguous()
-    if q.shape[0] != pairs.n_cells:
-        raise ValueError("cell_values must have one row per cell")
     k = 1 if q.ndim == 1 else q.shape[1]
-    shape = (pairs.n_particles,) if q.ndim == 1 else (pairs.n_particles, k)
+    if pairs is not None:
+        if q.shape[0] != pairs.n_cells:
+            raise ValueError("cell_values must have one row per cell")
+        n = pairs.n_particles
+        args = (None, 0, None, None, 0, pairs.handle)
+    else:
+        if tess is None or xyz is None or h is None:
+            raise ValueError("without a pair list, tess, xyz and h are needed")
+        if q.shape[0] != tess.n_cells:
+            raise ValueError("cell_values must have one row per cell")
+        xyz = _dev_f64(xyz, ctx.device, 3)
+        h = _dev_f64(h, ctx.device)
+        n = xyz.shape[0]
+        if h.shape != (n,):
+            raise ValueError("h must have shape [n]")
+        prec = {"fp64": PREC_FP64, "mixed": PREC_MIXED}.get(precision, precision)
+        args = (tess.handle, n, _ptr(xyz), _ptr(h), int(prec), None)
+    shape = (n,) if q.ndim == 1 else (n, k)
     if out is None:
         out = torch.empty(shape, dtype=torch.float64, device=ctx.device)
-    ctx.check(_native.lib().map_cells_to_particles(ctx.handle, pairs.handle, _ptr(q), k, _ptr(out),
-                                                   _stream_handle(stream)))
+    ctx.check(_native.lib().map_cells_to_particles(ctx.handle, *args, _ptr(q), k, _ptr(out), _stream_handle(stream)))
     return out
 
 
@@ -447,7 +475,7 @@ def select_underresolved(ctx: Context, ps: dict, fneu, K: float, stream=None):
     return out[:cnt.value].cpu().numpy().view(np.uint64)
 
 
-def interpolate_to_particles(ctx: Context, xyz, ps: dict, values, stream=None):
+def interpolate_to_particles(ctx: Context, xyz, ps: dict, values, stream=None, out=None):
     """Per-particle values from the mixed set `ps` (Sec. 3.3): a particle
     emitted as itself keeps its entry's value; a member of a pseudo-particle
     takes the Shepard-normalised SPH interpolant over the entries whose 2h
@@ -465,10 +493,10 @@ def interpolate_to_particles(ctx: Context, xyz, ps: dict, values, stream=None):
     if v.shape[0] != ne:
         raise ValueError(f"values has {v.shape[0]} rows for {ne} entries")
     n = xyz.shape[0]
-    out = torch.empty((n, k) if v.dim() == 2 else n, dtype=torch.float64, device=dev)
-    ctx.check(_native.lib().interpolate_to_particles(
-        ctx.handle, n, _ptr(xyz), _ptr(ps["owner"]), ne, _ptr(ps["xyz"]), _ptr(ps["h"]), _ptr(ps["kind"]),
-        _ptr(v), k, _ptr(out), _stream_handle(stream)))
+    if out is None:
+        out = torch.empty((n, k) if v.dim() == 2 else n, dtype=torch.float64, device=dev)
+    ctx.check(_native.lib().interpolate_to_particles(ctx.handle, n, _ptr(xyz), _ptr(ps["owner"]), ne, _ptr(ps["xyz"]), _ptr(ps["h"]), _ptr(ps["kind"]),
+                 _ptr(v), k, _ptr(out), _stream_handle(stream)))
     return out
 
 

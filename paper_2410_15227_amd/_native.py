@@ -24,7 +24,7 @@ EXPORTS = [
     "sphmap_tess_build_voronoi", "sphmap_tess_counts", "sphmap_tess_export", "build_pseudo_particles_kd",
     "sphmap_set_timing", "sphmap_kernel_time", "sphmap_reset_timing",
     "sphmap_set_counting", "sphmap_work_counters", "sphmap_set_autotune", "sphmap_tuned_shape",
-    "sphmap_set_pool_limit",
+    "sphmap_set_pool_limit", "sphmap_set_workspace_limit", "sphmap_workspace_info",
 ]
 
 
@@ -69,7 +69,12 @@ def lib():
         L.sphmap_version.restype = ctypes.c_int
         L.sphmap_version.argtypes = []
         L.sphmap_create.restype = ctypes.c_int
-        L.sphmap_create.argtypes = [i32, pp]
+        L.sphmap_create.argtypes = [i32, ctypes.c_size_t, pp]
+        L.sphmap_set_workspace_limit.restype = ctypes.c_int
+        L.sphmap_set_workspace_limit.argtypes = [vp, ctypes.c_size_t]
+        L.sphmap_workspace_info.restype = ctypes.c_int
+        L.sphmap_workspace_info.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                                            ctypes.POINTER(ctypes.c_size_t)]
         L.sphmap_destroy.restype = ctypes.c_int
         L.sphmap_destroy.argtypes = [vp]
         L.sphmap_last_error.restype = ctypes.c_char_p
@@ -98,7 +103,7 @@ def lib():
         L.sphmap_set_pool_limit.restype = ctypes.c_int
         L.sphmap_set_pool_limit.argtypes = [vp, ctypes.c_uint64]
         L.map_cells_to_particles.restype = ctypes.c_int
-        L.map_cells_to_particles.argtypes = [vp, vp, vp, i32, vp, vp]
+        L.map_cells_to_particles.argtypes = [vp, vp, i64, vp, vp, i32, vp, vp, i32, vp, vp]
         L.build_pseudo_particles_open.restype = ctypes.c_int
         L.build_pseudo_particles_open.argtypes = [vp, i64, vp, vp, vp, i32, vp, ctypes.POINTER(PseudoOpts), i64, vp,
                                                   i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i64),

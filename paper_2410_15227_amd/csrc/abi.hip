@@ -50,19 +50,74 @@ sphmap_pairs *new_pairs(sphmap::Ctx &C) {
   return q;
 }
 
+// The context's pair list for calls that keep none (counted in its workspace).
+sphmap::PairsDev *scratch_pairs(sphmap::Ctx &C) {
+  if (!C.scratch_pairs) {
+    C.scratch_pairs = new sphmap::PairsDev;
+    C.scratch_pairs->mem.budget = &C.ws;
+  }
+  return C.scratch_pairs;
+}
+
+// Upper bounds of the device bytes of one forward + inverse mapping (see
+// sphmap_estimate_footprint).
+sphmap_footprint footprint(sphmap::Ctx &C, int64_t n_particles, int64_t n_pairs, int64_t n_cells, int64_t n_faces,
+                           int64_t n_face_vertices, int64_t n_vertices) {
+  const int64_t N = n_particles, Cn = n_cells, P = n_pairs > 0 ? n_pairs : 200 * n_particles;
+  // arena buffers grow to 9/8 of the request; the device allocator hands
+  // out whole 2 MiB granules, once per named buffer
+  auto grown = [](double b, int n_buffers) { return (size_t)(b * 1.125 + 2097152.0 * n_buffers); };
+  // per particle: staged float4, Morton key + index, sorted copy, radix
+  // temporaries, search boxes; per pair: the transpose's sorted keys, one
+  // set of (key, cell, weight) temporaries (two above 2^20 particles, when
+  // the sort takes three passes) and its digit histograms; per cell: pair
+  // counts, the bounded candidate buffer of the pair search (512 entries),
+  // the overflow list
+  const double per_pair = 4.0 + (N > ((int64_t)1 << 20) ? 32.0 : 16.0) + 8.0;
+  const double ws = 16.0 * N + 12.0 * N + 16.0 * N + 12.0 * N + 3.0 * N + per_pair * P +
+                    (8.0 + 2048.0 + 4.0) * Cn + (double)sphmap::exact_workspace_bytes(C, P);
+  // retained list: cell offsets, pair indices, weights, particle-major
+  // copy, particle offsets and coverage
+  const double pr = 8.0 * Cn + (4.0 + 4.0 + 8.0 + 4.0 + 8.0) * P + 16.0 * N;
+  // grid: generators, offsets, orders and volumes per cell; planes, spheres
+  // and cell per face; oriented vertices and edge frames per face vertex
+  const double tb = 96.0 * Cn + 96.0 * n_faces + 96.0 * n_face_vertices + 24.0 * n_vertices;
+  sphmap_footprint f;
+  f.workspace = grown(ws, 56);
+  f.pairs = grown(pr, 8);
+  f.tessellation = grown(tb, 24);
+  return f;
+}
+
+// Workspace a mapping call of N particles on t needs: the scratch, plus
+// the pair list when the call keeps none.  P: the pair count if known.
+size_t workspace_need(sphmap::Ctx &C, int64_t N, int64_t P, const sphmap::TessDev &t, bool scratch_list) {
+  const sphmap_footprint f = footprint(C, N, P, t.n_cells, t.n_faces, t.n_fv, t.n_vertices);
+  return f.workspace + (scratch_list ? f.pairs : 0);
+}
+
+// An ENOMEM from a capped workspace, restated with what the call needs.
+[[noreturn]] void workspace_refused(sphmap::Ctx &C, const sphmap::Error &e, size_t need) {
+  C.ws.required = std::max(C.ws.required, need);
+  throw sphmap::Error{SPHMAP_ENOMEM, e.msg + "; the call needs a workspace of up to " +
+                                         std::to_string(C.ws.required) + " bytes (sphmap_workspace_info)"};
+}
+
 }  // namespace
 
 extern "C" {
 
 int sphmap_version(void) { return 100; }
 
-int sphmap_create(int32_t device, sphmap_ctx **out) {
+int sphmap_create(int32_t device, size_t workspace_bytes, sphmap_ctx **out) {
   if (!out) return SPHMAP_EINVAL;
   *out = nullptr;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SPHMAP_EINVAL;
   std::unique_ptr<sphmap_ctx> ctx(new sphmap_ctx);
   ctx->c.device = device;
+  ctx->c.ws.limit = workspace_bytes;
+  ctx->c.arena.budget = &ctx->c.ws;
   int rc = guarded(ctx.get(), [&] {
     size_t free_b = 0, total_b = 0;
     SPH_HIP(hipMemGetInfo(&free_b, &total_b));
@@ -258,16 +313,21 @@ int map_particles_to_cells(sphmap_ctx *ctx, const sphmap_tess *tess, int64_t n, 
       owned.reset(new_pairs(C));
       P = &owned->p;
     } else {
-      if (!C.scratch_pairs) C.scratch_pairs = new sphmap::PairsDev;
-      P = C.scratch_pairs;
+      P = scratch_pairs(C);
     }
     P->device = C.device;
-    sphmap::PartDev pd{n, d_xyz, d_h, d_m, C.arena.get<float4>("x32", n)};
-    sphmap::particles_prepare(C, pd, s);
-    sphmap::find_pairs(C, tess->t, pd, *P, s);
-    sphmap::exact_integral(C, tess->t, pd, *P, precision, s);
-    sphmap::particle_major(C, *P, s);
-    sphmap::cell_reduce(C, tess->t, pd, *P, normalize != 0, d_cell_mass, d_cell_density, s);
+    P->n_pairs = 0;
+    try {
+      sphmap::PartDev pd{n, d_xyz, d_h, d_m, C.arena.get<float4>("x32", n)};
+      sphmap::particles_prepare(C, pd, s);
+      sphmap::find_pairs(C, tess->t, pd, *P, s);
+      sphmap::exact_integral(C, tess->t, pd, *P, precision, s);
+      sphmap::particle_major(C, *P, s);
+      sphmap::cell_reduce(C, tess->t, pd, *P, normalize != 0, d_cell_mass, d_cell_density, s);
+    } catch (const sphmap::Error &e) {
+      if (e.code != SPHMAP_ENOMEM || !C.ws.limit) throw;
+      workspace_refused(C, e, workspace_need(C, n, P->n_pairs, tess->t, !pairs_out));
+    }
     if (d_coverage)
       SPH_HIP(hipMemcpyAsync(d_coverage, P->coverage, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (C.counting) {
@@ -311,7 +371,10 @@ int map_particles_to_cells_batch(sphmap_ctx *ctx, int32_t n_inst, const sphmap_t
         P[k] = &owned.back()->p;
       }
     } else {
-      while ((int)C.scratch_batch.size() < n_inst) C.scratch_batch.push_back(new sphmap::PairsDev);
+      while ((int)C.scratch_batch.size() < n_inst) {
+        C.scratch_batch.push_back(new sphmap::PairsDev);
+        C.scratch_batch.back()->mem.budget = &C.ws;
+      }
       for (int k = 0; k < n_inst; ++k) P[k] = C.scratch_batch[k];
     }
     float4 *x32 = C.arena.get<float4>("x32", n_max);
@@ -388,16 +451,79 @@ int sphmap_set_pool_limit(sphmap_ctx *ctx, uint64_t bytes) {
   });
 }
 
-int map_cells_to_particles(sphmap_ctx *ctx, const sphmap_pairs *pairs, const double *d_cell_values,
-                           int32_t n_components, double *d_particle_values, void *stream) {
+int map_cells_to_particles(sphmap_ctx *ctx, const sphmap_tess *tess, int64_t n, const double *d_xyz,
+                           const double *d_h, int32_t precision, const sphmap_pairs *pairs,
+                           const double *d_cell_values, int32_t n_components, double *d_particle_values,
+                           void *stream) {
   if (!ctx) return SPHMAP_EINVAL;
   return guarded(ctx, [&] {
-    SPH_REQUIRE(pairs, SPHMAP_EINVAL, "null pair list");
     SPH_REQUIRE(d_cell_values && d_particle_values, SPHMAP_EINVAL, "null value array");
     SPH_REQUIRE(n_components >= 1, SPHMAP_EINVAL, "n_components must be >= 1");
-    SPH_REQUIRE(pairs->p.device == ctx->c.device, SPHMAP_EINVAL, "pair list belongs to another device");
-    sphmap::reverse_map(ctx->c, pairs->p, d_cell_values, n_components, d_particle_values, as_stream(stream));
+    sphmap::Ctx &C = ctx->c;
+    hipStream_t s = as_stream(stream);
+    if (pairs) {
+      SPH_REQUIRE(pairs->p.device == C.device, SPHMAP_EINVAL, "pair list belongs to another device");
+      SPH_REQUIRE(n == 0 || n == pairs->p.n_particles, SPHMAP_EINVAL, "n differs from the pair list's particles");
+      sphmap::reverse_map(C, pairs->p, d_cell_values, n_components, d_particle_values, s);
+      return;
+    }
+    // no retained list: the weights are recomputed from the particles and
+    // the grid (the forward mapping's pair search, Exact integral and
+    // particle-major copy, without the cell sums)
+    SPH_REQUIRE(tess, SPHMAP_EINVAL, "null tessellation (needed when no pair list is given)");
+    SPH_REQUIRE(n >= 1 && n < ((int64_t)1 << 31), SPHMAP_EINVAL, "n out of range [1, 2^31)");
+    SPH_REQUIRE(d_xyz && d_h, SPHMAP_EINVAL, "null particle array (needed when no pair list is given)");
+    SPH_REQUIRE(precision == SPHMAP_PREC_FP64 || precision == SPHMAP_PREC_MIXED, SPHMAP_EINVAL, "bad precision");
+    SPH_REQUIRE(tess->t.device == C.device, SPHMAP_EINVAL, "tessellation belongs to another device");
+    sphmap::PairsDev *P = scratch_pairs(C);
+    P->device = C.device;
+    P->n_pairs = 0;
+    try {
+      sphmap::PartDev pd{n, d_xyz, d_h, nullptr, C.arena.get<float4>("x32", n)};
+      sphmap::particles_prepare(C, pd, s);
+      sphmap::find_pairs(C, tess->t, pd, *P, s);
+      sphmap::exact_integral(C, tess->t, pd, *P, precision, s);
+      sphmap::particle_major(C, *P, s);
+      sphmap::reverse_map(C, *P, d_cell_values, n_components, d_particle_values, s);
+    } catch (const sphmap::Error &e) {
+      if (e.code != SPHMAP_ENOMEM || !C.ws.limit) throw;
+      workspace_refused(C, e, workspace_need(C, n, P->n_pairs, tess->t, true));
+    }
   });
+}
+
+int sphmap_set_workspace_limit(sphmap_ctx *ctx, size_t bytes) {
+  if (!ctx) return SPHMAP_EINVAL;
+  return guarded(ctx, [&] {
+    sphmap::Ctx &C = ctx->c;
+    C.ws.limit = bytes;
+    C.ws.required = 0;
+    if (bytes && C.ws.held > bytes) {
+      // drop the scratch so that later calls grow within the new limit
+      SPH_HIP(hipDeviceSynchronize());
+      if (C.scratch_pairs) C.scratch_pairs->mem.release();
+      for (auto *P : C.scratch_batch) P->mem.release();
+      int64_t *ctr = C.d_counters;
+      int *st = C.d_status;
+      int64_t hc[8];
+      int hs[4];
+      SPH_HIP(hipMemcpy(hc, ctr, sizeof hc, hipMemcpyDeviceToHost));
+      SPH_HIP(hipMemcpy(hs, st, sizeof hs, hipMemcpyDeviceToHost));
+      C.arena.release();
+      C.d_counters = C.arena.get<int64_t>("counters", 8);
+      C.d_status = C.arena.get<int>("status", 4);
+      SPH_HIP(hipMemcpy(C.d_counters, hc, sizeof hc, hipMemcpyHostToDevice));
+      SPH_HIP(hipMemcpy(C.d_status, hs, sizeof hs, hipMemcpyHostToDevice));
+    }
+  });
+}
+
+int sphmap_workspace_info(sphmap_ctx *ctx, size_t *held, size_t *limit, size_t *required) {
+  if (!ctx) return SPHMAP_EINVAL;
+  if (held) *held = ctx->c.ws.held;
+  if (limit) *limit = ctx->c.ws.limit;
+  if (required) *required = ctx->c.ws.required;
+  return SPHMAP_OK;
 }
 
 int build_pseudo_particles_open(sphmap_ctx *ctx, int64_t n, const double *d_xyz, const double *d_h,
@@ -559,28 +685,7 @@ int sphmap_estimate_footprint(sphmap_ctx *ctx, int64_t n_particles, int64_t n_pa
     SPH_REQUIRE(n_particles >= 0 && n_pairs >= 0 && n_cells >= 0 && n_faces >= 0 && n_face_vertices >= 0 &&
                     n_vertices >= 0,
                 SPHMAP_EINVAL, "negative size");
-    const int64_t N = n_particles, C = n_cells, P = n_pairs > 0 ? n_pairs : 200 * n_particles;
-    // arena buffers grow to 9/8 of the request; the device allocator hands
-    // out whole 2 MiB granules, once per named buffer
-    auto grown = [](double b, int n_buffers) { return (size_t)(b * 1.125 + 2097152.0 * n_buffers); };
-    // per particle: staged float4, Morton key + index, sorted copy, radix
-    // temporaries, search boxes; per pair: the transpose's sorted keys, one
-    // set of (key, cell, weight) temporaries (two above 2^20 particles, when
-    // the sort takes three passes) and its digit histograms; per cell: pair
-    // counts, the bounded candidate buffer of the pair search (512 entries),
-    // the overflow list
-    const double per_pair = 4.0 + (N > ((int64_t)1 << 20) ? 32.0 : 16.0) + 8.0;
-    const double ws = 16.0 * N + 12.0 * N + 16.0 * N + 12.0 * N + 3.0 * N + per_pair * P +
-                      (8.0 + 2048.0 + 4.0) * C + (double)sphmap::exact_workspace_bytes(ctx->c, P);
-    // retained list: cell offsets, pair indices, weights, particle-major
-    // copy, particle offsets and coverage
-    const double pr = 8.0 * C + (4.0 + 4.0 + 8.0 + 4.0 + 8.0) * P + 16.0 * N;
-    // grid: generators, offsets, orders and volumes per cell; planes, spheres
-    // and cell per face; oriented vertices and edge frames per face vertex
-    const double tb = 96.0 * C + 96.0 * n_faces + 96.0 * n_face_vertices + 24.0 * n_vertices;
-    out->workspace = grown(ws, 56);
-    out->pairs = grown(pr, 8);
-    out->tessellation = grown(tb, 24);
+    *out = footprint(ctx->c, n_particles, n_pairs, n_cells, n_faces, n_face_vertices, n_vertices);
   });
 }
 

@@ -56,13 +56,23 @@ struct BlockPool {
   ~BlockPool() { release(); }
 };
 
+// A cap on the device bytes a context's scratch may hold (its workspace).
+// limit = 0: no cap.  `required` records the most a refused call asked for.
+struct Budget {
+  size_t limit = 0;
+  size_t held = 0;
+  size_t required = 0;
+};
+
 // Grow-only device allocations keyed by purpose, owned by a context or a
 // handle.  get() never shrinks; contents are not preserved on growth.  With
 // a pool, first allocations come from it and release() gives the blocks
-// back to it.
+// back to it.  With a budget, growth that would take the budget's holdings
+// past its limit fails with SPHMAP_ENOMEM before anything is allocated.
 struct Arena {
   std::map<std::string, Buffer> bufs;
   BlockPool *pool = nullptr;
+  Budget *budget = nullptr;
   void *get(const std::string &name, size_t bytes);
   template <typename T>
   T *get(const std::string &name, size_t count) {
@@ -89,6 +99,7 @@ struct TuneChoice {
 struct Ctx {
   int device = 0;
   PairsDev *scratch_pairs = nullptr;  // pair list of calls that do not keep one
+  Budget ws;                          // workspace cap over arena and scratch pair lists
   Arena arena;
   std::string last_error;
   bool timing = false;
@@ -208,9 +219,10 @@ void radix_sort_u64(Arena &ar, uint64_t *keys, int32_t *vals, int64_t n, int bit
 void radix_sort_u64_range(Arena &ar, uint64_t *keys, int32_t *vals, int64_t n, int lo, int hi, hipStream_t s);
 void radix_sort_u32(Arena &ar, uint32_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s);
 // Stable sort of n (key, a, b) triples by the low `bits` bits of key, from the
-// input arrays into the output arrays (which must not overlap them).
+// input arrays into the output arrays (which must not overlap them).  dn: a
+// device count of at most n items to sort instead (the launches cover n).
 void sort_by_key_kv(Arena &ar, int64_t n, int bits, const uint32_t *kin, const int32_t *ain, const double *bin,
-                    uint32_t *kout, int32_t *aout, double *bout, hipStream_t s);
+                    uint32_t *kout, int32_t *aout, double *bout, hipStream_t s, const int64_t *dn = nullptr);
 // 63-bit Morton keys (21 bits per axis) of points in [lo, lo+size)^3,
 // interleaved x (bit 0), y (bit 1), z (bit 2) at each level.
 void morton_keys(const double *xyz, int stride, int64_t n, double lo0, double lo1, double lo2, double size,

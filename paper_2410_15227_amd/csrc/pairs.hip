@@ -89,15 +89,20 @@ constexpr int kCap = 512;
 // 64 nodes pending per level, so 64 kMaxLevels entries always suffice.
 constexpr int kWalkStack = 64 * kMaxLevels;
 
+// One wavefront per listed cell; the grid's wavefronts step through the
+// list (C entries, or *dC when given: a count known only on the device).
+// The fill skips a cell whose list would end past `cap` pairs.
 template <bool kFill>
 __global__ void __launch_bounds__(256) k_pairs(Hier H, int64_t C, const int32_t *cells, const float4 *gen32,
                                               int64_t *counts, const int64_t *off, int32_t *pair_p,
-                                              int32_t *pair_c, int32_t *buf) {
+                                              int32_t *pair_c, int32_t *buf, const int32_t *dC = nullptr,
+                                              int64_t cap = INT64_MAX) {
   __shared__ uint32_t stk[4][kWalkStack];  // node << 4 | level
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t t = (int64_t)blockIdx.x * 4 + w;
-  if (t >= C) return;
+  const int64_t nt = dC ? (int64_t)*dC : C;
+  for (int64_t t = (int64_t)blockIdx.x * 4 + w; t < nt; t += (int64_t)gridDim.x * 4) {
   const int32_t c = cells[t];
+  if (kFill && off[c + 1] > cap) continue;  // past the capacity: flagged by the caller
   const float4 g = gen32[c];
   const float rr = g.w * 1.00001f + H.margin_abs;
   const float r2 = rr * rr;
@@ -156,6 +161,7 @@ __global__ void __launch_bounds__(256) k_pairs(Hier H, int64_t C, const int32_t 
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   if (!kFill && lane == 0) counts[c] = cnt;
+  }  // listed cells of this wavefront
 }
 
 // Sort each cell's particle list ascending: lists of up to kSortCap entries
@@ -263,11 +269,12 @@ __device__ inline void wave_sort_copy(const int32_t *src, int32_t *dst, int n, i
 static_assert(kCap <= 512, "a wavefront sorts at most 8 keys per lane");
 __global__ void __launch_bounds__(256) k_compact_sort(int64_t C, const int64_t *off, const int32_t *buf,
                                                       int32_t *pair_p, int32_t *pair_c, int32_t *over,
-                                                      int32_t *n_over) {
+                                                      int32_t *n_over, int64_t cap = INT64_MAX) {
   const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;  // one cell per wavefront
   const int lane = threadIdx.x & 63;
   if (c >= C) return;
   const int64_t s = off[c];
+  if (off[c + 1] > cap) return;  // past the capacity: flagged by the caller
   const int n = (int)(off[c + 1] - s);
   if (n > kCap) {
     if (lane == 0) over[atomicAdd(n_over, 1)] = (int32_t)c;
@@ -285,10 +292,28 @@ __global__ void __launch_bounds__(256) k_compact_sort(int64_t C, const int64_t *
     wave_sort_copy<8>(src, pair_p + s, n, lane);
 }
 
+// One workgroup per listed cell (blockIdx.x), or, with a device count dC,
+// the grid's workgroups step through the *dC listed cells.
+__device__ void sort_segment(const int64_t *off, int32_t *pair_p, int32_t *tmp, int64_t c, int32_t *buf);
+
 __global__ void __launch_bounds__(256) k_sort_segments(int64_t C, const int64_t *off, int32_t *pair_p, int32_t *tmp,
-                                                       const int32_t *cells) {
+                                                       const int32_t *cells, const int32_t *dC = nullptr,
+                                                       int64_t cap = INT64_MAX) {
   __shared__ int32_t buf[kSortCap];
-  const int64_t c = cells ? cells[blockIdx.x] : blockIdx.x;
+  if (!dC) {
+    const int64_t c = cells ? cells[blockIdx.x] : blockIdx.x;
+    if (off[c + 1] <= cap) sort_segment(off, pair_p, tmp, c, buf);
+    return;
+  }
+  const int64_t nt = *dC;
+  for (int64_t b = blockIdx.x; b < nt; b += gridDim.x) {  // uniform over the workgroup
+    const int64_t c = cells[b];
+    if (off[c + 1] <= cap) sort_segment(off, pair_p, tmp, c, buf);
+    __syncthreads();
+  }
+}
+
+__device__ void sort_segment(const int64_t *off, int32_t *pair_p, int32_t *tmp, int64_t c, int32_t *buf) {
   const int64_t s = off[c], e = off[c + 1];
   const int n = (int)(e - s);
   if (n <= 1) return;

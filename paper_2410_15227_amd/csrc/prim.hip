@@ -1,4 +1,6 @@
 // Device primitives: exclusive scan, stable LSD radix sort, Morton keys.
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace sphmap {
@@ -40,11 +42,17 @@ void BlockPool::release() {
 void *Arena::get(const std::string &name, size_t bytes) {
   Buffer &b = bufs[name];
   if (b.bytes < bytes) {
+    size_t want = bytes + bytes / 8 + 256;
+    if (budget && budget->limit && budget->held - b.bytes + want > budget->limit) {
+      budget->required = std::max(budget->required, budget->held - b.bytes + want);
+      throw Error{SPHMAP_ENOMEM, "workspace limit of " + std::to_string(budget->limit) + " bytes exceeded by " + name +
+                                     " (" + std::to_string(want) + " bytes)"};
+    }
     // a block in use may still be read by queued work: hipFree waits for it
     if (b.p) SPH_HIP(hipFree(b.p));
+    if (budget) budget->held -= b.bytes;
     b.p = nullptr;
     b.bytes = 0;
-    size_t want = bytes + bytes / 8 + 256;
     if (pool) {
       size_t got = 0;
       if (void *q = pool->take(want, got)) {
@@ -67,6 +75,7 @@ void *Arena::get(const std::string &name, size_t bytes) {
       throw Error{SPHMAP_ENOMEM, "device allocation of " + std::to_string(want) + " bytes for " + name + " failed"};
     }
     b.bytes = want;
+    if (budget) budget->held += want;
   }
   return b.p;
 }
@@ -76,6 +85,7 @@ void Arena::release() {
   if (pool && !bufs.empty()) (void)hipDeviceSynchronize();
   for (auto &kv : bufs) {
     if (!kv.second.p) continue;
+    if (budget) budget->held -= kv.second.bytes;
     if (pool)
       pool->put(kv.second.p, kv.second.bytes);
     else
@@ -314,10 +324,14 @@ __device__ inline int64_t xcd_tile(int64_t ntiles) {
   return x * q + (x < r ? x : r) + k;
 }
 
+// The item count is n, or *dn when dn is given (a count known only on the
+// device, at most n: the launch covers n items' tiles and the tiles past *dn
+// count nothing and write nothing).
 template <int NB>
-__global__ void __launch_bounds__(kSortThreads) k_kv_hist(const uint32_t *key, int64_t n, int shift, int rb,
-                                                         int64_t ntiles, int64_t *hist) {
+__global__ void __launch_bounds__(kSortThreads) k_kv_hist(const uint32_t *key, int64_t n, const int64_t *dn,
+                                                         int shift, int rb, int64_t ntiles, int64_t *hist) {
   __shared__ unsigned h[NB];
+  if (dn) n = *dn;
   const int nd = 1 << rb;
   for (int d = threadIdx.x; d < nd; d += kSortThreads) h[d] = 0;
   __syncthreads();
@@ -336,9 +350,9 @@ __global__ void __launch_bounds__(kSortThreads) k_kv_hist(const uint32_t *key, i
 
 template <int NB>
 __global__ void __launch_bounds__(kSortThreads) k_kv_scatter(const uint32_t *kin, const int32_t *ain,
-                                                            const double *bin, int64_t n, int shift, int rb,
-                                                            int64_t ntiles, const int64_t *off, uint32_t *kout,
-                                                            int32_t *aout, double *bout) {
+                                                            const double *bin, int64_t n, const int64_t *dn,
+                                                            int shift, int rb, int64_t ntiles, const int64_t *off,
+                                                            uint32_t *kout, int32_t *aout, double *bout) {
   constexpr int kPer = NB / kSortThreads > 0 ? NB / kSortThreads : 1;  // digits per thread
   __shared__ unsigned cnt[4][NB];  // per wave: running count, then the wave's offset
   __shared__ unsigned tex[NB];     // the tile's exclusive offset per digit
@@ -353,6 +367,8 @@ __global__ void __launch_bounds__(kSortThreads) k_kv_scatter(const uint32_t *kin
   __syncthreads();
   const int64_t tile = xcd_tile(ntiles);
   const int64_t tile0 = tile * kSortTile;
+  if (dn) n = *dn;
+  if (tile0 >= n) return;  // a tile past the count (uniform over the workgroup)
   const int64_t wbase = tile0 + (int64_t)w * kSortWaveItems;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes below this one
   uint32_t kk[kSortItems];
@@ -439,24 +455,24 @@ __global__ void __launch_bounds__(kSortThreads) k_kv_scatter(const uint32_t *kin
 }
 
 template <int NB>
-void kv_pass(Arena &ar, int64_t n, int shift, int rb, const uint32_t *kin, const int32_t *ain, const double *bin,
-             uint32_t *kout, int32_t *aout, double *bout, hipStream_t s) {
+void kv_pass(Arena &ar, int64_t n, const int64_t *dn, int shift, int rb, const uint32_t *kin, const int32_t *ain,
+             const double *bin, uint32_t *kout, int32_t *aout, double *bout, hipStream_t s) {
   const int64_t ntiles = div_up(n, kSortTile);
   const int64_t m = ((int64_t)1 << rb) * ntiles;
   int64_t *hist = ar.get<int64_t>("kv_hist", m + 1);
   int64_t *off = ar.get<int64_t>("kv_off", m + 1);
-  k_kv_hist<NB><<<(unsigned)ntiles, kSortThreads, 0, s>>>(kin, n, shift, rb, ntiles, hist);
+  k_kv_hist<NB><<<(unsigned)ntiles, kSortThreads, 0, s>>>(kin, n, dn, shift, rb, ntiles, hist);
   SPH_LAUNCH_CHECK();
   scan_exclusive_i64(ar, hist, off, m, false, s);
-  k_kv_scatter<NB><<<(unsigned)ntiles, kSortThreads, 0, s>>>(kin, ain, bin, n, shift, rb, ntiles, off, kout, aout,
-                                                              bout);
+  k_kv_scatter<NB><<<(unsigned)ntiles, kSortThreads, 0, s>>>(kin, ain, bin, n, dn, shift, rb, ntiles, off, kout,
+                                                              aout, bout);
   SPH_LAUNCH_CHECK();
 }
 
 }  // namespace
 
 void sort_by_key_kv(Arena &ar, int64_t n, int bits, const uint32_t *kin, const int32_t *ain, const double *bin,
-                    uint32_t *kout, int32_t *aout, double *bout, hipStream_t s) {
+                    uint32_t *kout, int32_t *aout, double *bout, hipStream_t s, const int64_t *dn) {
   if (n <= 0) return;
   SPH_REQUIRE(n < ((int64_t)1 << 31), SPHMAP_EINVAL, "sort length out of range");
   SPH_REQUIRE(bits >= 1 && bits <= 32, SPHMAP_EINVAL, "sort key bits out of range");
@@ -475,11 +491,11 @@ void sort_by_key_kv(Arena &ar, int64_t n, int bits, const uint32_t *kin, const i
     int32_t *ad = last ? aout : at[p & 1];
     double *bd = last ? bout : bt[p & 1];
     if (rb <= 8)
-      kv_pass<256>(ar, n, shift, rb, ks, as, bs, kd, ad, bd, s);
+      kv_pass<256>(ar, n, dn, shift, rb, ks, as, bs, kd, ad, bd, s);
     else if (rb == 9)
-      kv_pass<512>(ar, n, shift, rb, ks, as, bs, kd, ad, bd, s);
+      kv_pass<512>(ar, n, dn, shift, rb, ks, as, bs, kd, ad, bd, s);
     else
-      kv_pass<1024>(ar, n, shift, rb, ks, as, bs, kd, ad, bd, s);
+      kv_pass<1024>(ar, n, dn, shift, rb, ks, as, bs, kd, ad, bd, s);
     ks = kd;
     as = ad;
     bs = bd;

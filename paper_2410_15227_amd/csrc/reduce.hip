@@ -3,7 +3,9 @@
 //  cell_reduce     M_c = sum_i m_i w_ic (forward mapping, Sec. 2.3) over the
 //                  cell's pairs, rho_c = M_c / V_c.  One wave per cell; lanes
 //                  take the cell's pairs in stride and a fixed butterfly
-//                  combines them, so the result does not depend on the launch.
+//                  combines them, so the result does not depend on the launch
+//                  (products are rounded before they are added, so the order
+//                  stated in include/sphmap.h reproduces the sums exactly).
 //  particle_major  the pair list re-ordered by particle (stable radix sort of
 //                  the particle index, so each particle's cells stay in
 //                  ascending cell order) with c_i = sum_c w_ic.
@@ -22,6 +24,7 @@ __device__ inline double wave_sum(double v) {
 __global__ void __launch_bounds__(256) k_cell_mass(int64_t C, const int64_t *off, const int32_t *pair_p,
                                                   const double *w, const double *m, const double *cov,
                                                   const double *vol, double *mass, double *rho, int *status) {
+#pragma clang fp contract(off)  // each product rounded, then added: the order include/sphmap.h states
   const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (c >= C) return;
@@ -69,6 +72,7 @@ template <int kComp>
 __global__ void __launch_bounds__(256) k_reverse(int64_t N, int ncomp, const int64_t *poff, const int32_t *pm_cell,
                                                 const double *pm_w, const double *cov, const double *q,
                                                 double *out, int *status) {
+#pragma clang fp contract(off)  // each product rounded, then added: the order include/sphmap.h states
   const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
   const int lane = threadIdx.x & 15;  // 16 lanes per particle
   if (i >= N) return;
