@@ -86,7 +86,9 @@ def main():
     ap.add_argument("--tree", default="octree", choices=["octree", "kd"], help="pseudo: tree of the builder")
     ap.add_argument("--r-leaf", type=float, default=None, help="pseudo, k-d tree: r_leaf (default r_part)")
     ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
-    ap.add_argument("--rate", type=float, default=200.0, help="serve: mean arrival rate (requests/s)")
+    ap.add_argument("--rates", default="25,50,100,200",
+                    help="serve: offered Poisson arrival rates (requests/s), one measurement each; the last is "
+                         "the headline")
     ap.add_argument("--slots", type=int, default=4, help="serve: concurrent jobs on the device")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (calibrates HBM byte counters)")
@@ -613,17 +615,20 @@ def run_batch(args):
 
 
 def run_serve(args):
-    """Served mapping: Poisson arrivals (--rate per second) of --requests jobs
-    of round(10^U(4,6)) particles.  Tessellations come from a seeded pool of
-    16 grids of log-uniform size (seed 5), since a host Voronoi build per
-    request is out of the question; a new job takes the pool grid nearest its
-    size (uploaded unless still resident) with that grid's own particles, a
-    repeat job (30%) takes a grid still resident on the device and the same
-    particles with a 1% positional jitter.  Jobs are admitted first come first
-    served by estimated device footprint against a 160 GiB budget on
-    --slots concurrent streams.  Reports p50/p99 latency (arrival to results
-    on the device) and the pair throughput over the whole run, and checks
-    that a sample of jobs gives the same cell masses when run alone."""
+    """Served mapping: Poisson arrivals of mapping jobs of round(10^U(4,6))
+    particles at each offered rate of --rates (requests/s), --requests jobs
+    per rate.  Grids come from a seeded pool of 16 grids of log-uniform size
+    (seed 5), since a host Voronoi build per request is out of the question.
+    A new job takes the pool grid nearest its size, with that grid's own
+    particles (uploaded with the grid unless resident); a repeat job (30%)
+    takes a grid still resident on the device and moves its resident
+    particles by a seeded 1% jitter drawn on the device (no host copy).
+    Jobs are admitted first come first served by estimated device footprint
+    against a 160 GiB budget on --slots concurrent streams.  Per rate:
+    p50/p99 latency (arrival to results on the device), offered and achieved
+    pair throughput.  The headline value is the achieved throughput at the
+    highest rate; a sample of jobs is re-run alone and must give the same
+    cell masses."""
     import numpy as np
     import torch
 
@@ -641,61 +646,79 @@ def run_serve(args):
     log(f"pool: {len(pool)} grids of {pool_n[0]}..{pool_n[-1]} particles built in {host_s:.1f}s")
     logn = np.log10(np.array(pool_n, dtype=float))
     srv = serve.MappingServer(0, slots=args.slots, hbm_budget=160 << 30, precision=args.precision)
+
+    def make_job(g, seed=None, arrival=0.0):
+        return serve.Job(g["key"], g["tess"], g["pos"], g["h"], g["m"], rho=g["rho"], jitter_seed=seed,
+                         arrival=arrival)
+
     # warm the slots' scratch on the largest grid so steady-state calls do not grow it
     big = pool[-1]
     for _ in range(args.slots):
-        srv.submit(serve.Job(big["key"], big["tess"], big["pos"], big["h"], big["m"]))
+        srv.submit(make_job(big))
     srv.drain()
     srv.completed.clear()
-    arrivals = np.cumsum(rng.exponential(1.0 / args.rate, args.requests))
-    jobs = []
-    t_start = time.perf_counter()
-    for i, ta in enumerate(arrivals):
-        now = time.perf_counter() - t_start
-        if ta > now:
-            time.sleep(ta - now)
-        resident = srv.resident_keys()
-        if rng.random() < 0.3 and resident:
-            key = resident[int(rng.integers(len(resident)))]
-            g = next(p for p in pool if p["key"] == key)
-            pos = workloads.jitter(g["pos"], g["m"], g["rho"], seed=90000 + i)
-        else:
-            want = rng.uniform(4.0, 6.0)
-            g = pool[int(np.argmin(np.abs(logn - want)))]
-            pos = g["pos"]
-        jobs.append(srv.submit(serve.Job(g["key"], g["tess"], pos, g["h"], g["m"], arrival=time.perf_counter())))
-        if (i + 1) % 250 == 0:
-            log(f"submitted {i + 1} / {args.requests}; done {len(srv.completed)}")
-    srv.drain()
-    errors = [j.error for j in jobs if j.error]
-    summ = serve.latency_summary(jobs)
+    rates = [float(r) for r in args.rates.split(",")]
+    curve = []
+    last_jobs = []
+    for rate in rates:
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, args.requests))
+        jobs = []
+        t_start = time.perf_counter()
+        for i, ta in enumerate(arrivals):
+            now = time.perf_counter() - t_start
+            if ta > now:
+                time.sleep(ta - now)
+            resident = srv.resident_keys()
+            if rng.random() < 0.3 and resident:
+                key = resident[int(rng.integers(len(resident)))]
+                g = next(p for p in pool if p["key"] == key)
+                jobs.append(srv.submit(make_job(g, seed=int(rng.integers(1 << 40)), arrival=time.perf_counter())))
+            else:
+                g = pool[int(np.argmin(np.abs(logn - rng.uniform(4.0, 6.0))))]
+                jobs.append(srv.submit(make_job(g, arrival=time.perf_counter())))
+        t_sub = time.perf_counter() - t_start
+        srv.drain()
+        errors = [j.error for j in jobs if j.error]
+        summ = serve.latency_summary(jobs)
+        point = {"offered_req_per_s": rate, "requests": len(jobs), "submit_s": round(t_sub, 2),
+                 "achieved_req_per_s": round(len(jobs) / summ["makespan_s"], 2),
+                 "offered_pairs_per_s": round(summ["pairs"] / t_sub, 1),
+                 "achieved_pairs_per_s": round(summ["pairs_per_s"], 1),
+                 "p50_ms": round(summ["p50_ms"], 2), "p99_ms": round(summ["p99_ms"], 2),
+                 "mean_ms": round(summ["mean_ms"], 2), "makespan_s": round(summ["makespan_s"], 2),
+                 "resident_hits": summ["resident_hits"], "repeat_jobs": summ["repeat_jobs"],
+                 "repeat_host_bytes": summ["repeat_host_bytes"], "errors": len(errors)}
+        log(f"rate {rate}: {point}")
+        curve.append(point)
+        last_jobs = jobs
     # the same jobs alone, one at a time, must give the same masses
-    sample = jobs[:: max(1, len(jobs) // 8)][:8]
+    sample = last_jobs[:: max(1, len(last_jobs) // 8)][:8]
     same = True
     for j in sample:
-        solo = srv.submit(serve.Job(j.key, j.tess, j.pos, j.h, j.m))
+        g = next(p for p in pool if p["key"] == j.key)
+        solo = srv.submit(make_job(g, seed=j.jitter_seed))
         solo.done.wait()
         same &= bool(torch.equal(solo.mass, j.mass))
     srv.close()
+    head = curve[-1]
     out = {
         "metric": "particle-cell pair integrals/s",
-        "value": round(summ["pairs_per_s"], 1),
+        "value": head["achieved_pairs_per_s"],
         "unit": "pairs/s",
         "n_gpus": 1,
-        "steps": args.requests,
+        "steps": head["requests"],
         "warmup": args.slots,
-        "ms_per_step": round(summ["makespan_s"] * 1e3 / args.requests, 3),
+        "ms_per_step": round(head["makespan_s"] * 1e3 / head["requests"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64" if args.precision == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"serve_{args.requests}", "rate_per_s": args.rate, "slots": args.slots,
+        "config": {"workload": f"serve_poisson_{int(rates[-1])}_per_s", "slots": args.slots,
                    "sizes": "round(10^U(4,6)) via a 16-grid pool", "repeat_fraction": 0.3,
-                   "precision": args.precision},
-        "serve": {"p50_ms": round(summ["p50_ms"], 2), "p99_ms": round(summ["p99_ms"], 2),
-                  "mean_ms": round(summ["mean_ms"], 2), "makespan_s": round(summ["makespan_s"], 2),
-                  "pairs": summ["pairs"], "resident_hits": summ["resident_hits"], "errors": len(errors),
+                   "repeat_jitter": "1% of (m/rho)^(1/3), drawn on the device", "precision": args.precision,
+                   "requests_per_rate": args.requests},
+        "serve": {"p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"], "curve": curve,
                   "same_alone_and_in_mix": same, "host_pool_s": round(host_s, 1)},
     }
     print(json.dumps(out), flush=True)
