@@ -436,6 +436,23 @@ int interpolate_to_particles(sphmap_ctx *ctx, int64_t n, const double *d_xyz, co
                              const int32_t *d_entry_kind, const double *d_values, int32_t ncomp, double *d_out,
                              void *stream);
 
+/* interpolate_to_particles for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same arguments, results and errors, but every buffer of
+ * the call is carved from a fixed 64 MiB region of device memory that the
+ * library holds on each device for the life of the process; the call makes
+ * no device allocation.  n particles and n_entries entries need up to
+ *   102 n_entries + 16 n bytes (+ about 100 KiB),
+ * e.g. 1,048,576 particles with 167,000 entries take about 34 MB; a call
+ * that needs more than 64 MiB fails with SPHMAP_EINVAL before anything is
+ * enqueued.  All calls on one device share the region: calls that overlap
+ * in time on one device (two streams, two contexts or two host threads)
+ * race and must be serialised by the caller. */
+int interpolate_to_particles_noalloc(sphmap_ctx *ctx, int64_t n, const double *d_xyz, const int64_t *d_owner,
+                                     int64_t n_entries, const double *d_entry_xyz, const double *d_entry_h,
+                                     const int32_t *d_entry_kind, const double *d_values, int32_t ncomp,
+                                     double *d_out, void *stream);
+
 /* ------------------------------------------------------------------------
  * Kernel timing: when enabled, HIP events are recorded on the launch stream
  * around each launch of the named kernels ("exact_integral", "exact_redo",

@@ -475,13 +475,15 @@ def select_underresolved(ctx: Context, ps: dict, fneu, K: float, stream=None):
     return out[:cnt.value].cpu().numpy().view(np.uint64)
 
 
-def interpolate_to_particles(ctx: Context, xyz, ps: dict, values, stream=None, out=None):
+def interpolate_to_particles(ctx: Context, xyz, ps: dict, values, stream=None, out=None, noalloc: bool = False):
     """Per-particle values from the mixed set `ps` (Sec. 3.3): a particle
     emitted as itself keeps its entry's value; a member of a pseudo-particle
     takes the Shepard-normalised SPH interpolant over the entries whose 2h
     spheres reach it, entry j weighted by w(r / h_j) (its volume
     (h_j / h_fact)^3 times W).  values: [E] or [E][k] per entry; returns [n] or
-    [n][k] on the device."""
+    [n][k] on the device.  noalloc: use the entry point that allocates no
+    device memory (its scratch is the library's fixed per-device region; with
+    `out` given, the call allocates nothing at all)."""
     torch = _torch()
     dev = ctx.device
     xyz = _dev_f64(xyz, dev, 3)
@@ -495,7 +497,8 @@ def interpolate_to_particles(ctx: Context, xyz, ps: dict, values, stream=None, o
     n = xyz.shape[0]
     if out is None:
         out = torch.empty((n, k) if v.dim() == 2 else n, dtype=torch.float64, device=dev)
-    ctx.check(_native.lib().interpolate_to_particles(ctx.handle, n, _ptr(xyz), _ptr(ps["owner"]), ne, _ptr(ps["xyz"]), _ptr(ps["h"]), _ptr(ps["kind"]),
+    fn = _native.lib().interpolate_to_particles_noalloc if noalloc else _native.lib().interpolate_to_particles
+    ctx.check(fn(ctx.handle, n, _ptr(xyz), _ptr(ps["owner"]), ne, _ptr(ps["xyz"]), _ptr(ps["h"]), _ptr(ps["kind"]),
                  _ptr(v), k, _ptr(out), _stream_handle(stream)))
     return out
 

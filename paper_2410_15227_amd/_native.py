@@ -25,6 +25,7 @@ EXPORTS = [
     "sphmap_set_timing", "sphmap_kernel_time", "sphmap_reset_timing",
     "sphmap_set_counting", "sphmap_work_counters", "sphmap_set_autotune", "sphmap_tuned_shape",
     "sphmap_set_pool_limit", "sphmap_set_workspace_limit", "sphmap_workspace_info",
+    "interpolate_to_particles_noalloc",
 ]
 
 
@@ -128,6 +129,8 @@ def lib():
         L.sphmap_estimate_footprint.argtypes = [vp, i64, i64, i64, i64, i64, i64, ctypes.POINTER(Footprint)]
         L.interpolate_to_particles.restype = ctypes.c_int
         L.interpolate_to_particles.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp, i32, vp, vp]
+        L.interpolate_to_particles_noalloc.restype = ctypes.c_int
+        L.interpolate_to_particles_noalloc.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp, i32, vp, vp]
         L.build_pseudo_particles.restype = ctypes.c_int
         L.build_pseudo_particles.argtypes = [vp, i64, vp, vp, vp, i32, vp, ctypes.POINTER(PseudoOpts), i64,
                                              vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i64),

@@ -122,6 +122,8 @@ int sphmap_create(int32_t device, size_t workspace_bytes, sphmap_ctx **out) {
     size_t free_b = 0, total_b = 0;
     SPH_HIP(hipMemGetInfo(&free_b, &total_b));
     ctx->c.pool.cap = total_b / 8;
+    // this device's address of the fixed scratch of the no-allocation entry point
+    (void)sphmap::noalloc_scratch_init(device);
     ctx->c.d_counters = ctx->c.arena.get<int64_t>("counters", 8);
     ctx->c.d_status = ctx->c.arena.get<int>("status", 4);
     SPH_HIP(hipMemset(ctx->c.d_counters, 0, 8 * sizeof(int64_t)));
@@ -663,6 +665,23 @@ int interpolate_to_particles(sphmap_ctx *ctx, int64_t n, const double *d_xyz, co
     SPH_REQUIRE(d_entry_xyz && d_entry_h && d_entry_kind && d_values, SPHMAP_EINVAL, "null entry array");
     sphmap::interpolate_particles(ctx->c, n, d_xyz, d_owner, n_entries, d_entry_xyz, d_entry_h, d_entry_kind,
                                   d_values, ncomp, d_out, as_stream(stream));
+  });
+}
+
+int interpolate_to_particles_noalloc(sphmap_ctx *ctx, int64_t n, const double *d_xyz, const int64_t *d_owner,
+                                     int64_t n_entries, const double *d_entry_xyz, const double *d_entry_h,
+                                     const int32_t *d_entry_kind, const double *d_values, int32_t ncomp,
+                                     double *d_out, void *stream) {
+  if (!ctx) return SPHMAP_EINVAL;
+  return guarded(ctx, [&] {
+    SPH_REQUIRE(n >= 0 && n < ((int64_t)1 << 31), SPHMAP_EINVAL, "n out of range [0, 2^31)");
+    SPH_REQUIRE(n_entries >= 1 && n_entries < ((int64_t)1 << 31), SPHMAP_EINVAL,
+                "n_entries out of range [1, 2^31)");
+    SPH_REQUIRE(ncomp >= 1, SPHMAP_EINVAL, "ncomp must be at least 1");
+    SPH_REQUIRE(n == 0 || (d_xyz && d_owner && d_out), SPHMAP_EINVAL, "null particle array");
+    SPH_REQUIRE(d_entry_xyz && d_entry_h && d_entry_kind && d_values, SPHMAP_EINVAL, "null entry array");
+    sphmap::interpolate_particles_noalloc(ctx->c, n, d_xyz, d_owner, n_entries, d_entry_xyz, d_entry_h,
+                                          d_entry_kind, d_values, ncomp, d_out, as_stream(stream));
   });
 }
 

@@ -73,6 +73,13 @@ struct Arena {
   std::map<std::string, Buffer> bufs;
   BlockPool *pool = nullptr;
   Budget *budget = nullptr;
+  // fixed-region mode: buffers are carved in turn (256-byte aligned) from
+  // [region, region + region_cap); nothing is allocated or freed, and a
+  // request past the end fails with SPHMAP_EINVAL
+  char *region = nullptr;
+  size_t region_cap = 0, region_used = 0;
+  // while set, every request goes to that arena instead
+  Arena *redirect = nullptr;
   void *get(const std::string &name, size_t bytes);
   template <typename T>
   T *get(const std::string &name, size_t count) {
@@ -308,6 +315,15 @@ void voronoi_build(Ctx &ctx, TessDev &t, int64_t n, const double *d_gen, const d
 void interpolate_particles(Ctx &ctx, int64_t n, const double *xyz, const int64_t *owner, int64_t ne,
                            const double *exyz, const double *eh, const int32_t *ekind, const double *val, int ncomp,
                            double *out, hipStream_t s);
+// the same with its scratch in the device's fixed region (no allocation)
+void interpolate_particles_noalloc(Ctx &ctx, int64_t n, const double *xyz, const int64_t *owner, int64_t ne,
+                                   const double *exyz, const double *eh, const int32_t *ekind, const double *val,
+                                   int ncomp, double *out, hipStream_t s);
+// this device's address of the fixed scratch (looked up on first use with
+// the device current); its size; the bytes an interpolation needs
+void *noalloc_scratch_init(int device);
+size_t noalloc_scratch_bytes();
+size_t interp_scratch_bound(int64_t n, int64_t ne);
 
 inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

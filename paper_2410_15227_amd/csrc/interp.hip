@@ -21,6 +21,8 @@
 // the particles of one wavefront lie in one or a few neighbouring tree nodes
 // and their walks visit the same boxes.  Candidates pass a binary32 sphere
 // test with the hierarchy's slack before the binary64 distance decides.
+#include <mutex>
+
 #include "ballsearch.hpp"
 
 namespace sphmap {
@@ -147,6 +149,49 @@ __global__ void __launch_bounds__(256) k_interp(Hier H, const double4 *sd, int64
 
 }  // namespace
 
+// ------------------------------------------------- fixed device scratch
+// Device memory for callers that cannot allocate (the no-allocation
+// interpolation entry point): each device holds one copy for the life of
+// the process.  Host code must not pass `scratch` itself to a kernel -- on
+// the host that name is a stand-in, not a device address -- but the address
+// hipGetSymbolAddress returns on each device, looked up once per device.
+constexpr size_t kNoAllocScratch = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Look up this device's copy of the scratch (called with `device` current,
+// by context creation).  Later lookups return the recorded address.
+void *noalloc_scratch_init(int device) {
+  SPH_REQUIRE(device >= 0 && device < kMaxDevices, SPHMAP_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    SPH_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    SPH_REQUIRE(p != nullptr, SPHMAP_EHIP, "no device address for the fixed scratch");
+    g_scratch_ptr[device] = p;
+  }
+  return g_scratch_ptr[device];
+}
+
+size_t noalloc_scratch_bytes() { return kNoAllocScratch; }
+
+// Upper bound of the scratch interpolate_particles carves for n particles
+// and ne entries: Morton keys, index, sorted float4 and double4 copies and
+// radix temporaries per entry; owner keys, index and radix temporaries per
+// particle; the search boxes; digit histograms and scan sums; and 256 bytes
+// of alignment and padding for each of up to 64 named buffers.
+size_t interp_scratch_bound(int64_t n, int64_t ne) {
+  const double per_entry = 8 + 4 + 8 + 4 + 16 + 32 + 2.2 * 16;
+  const double per_part = 4 + 4 + 4 + 4;
+  const double hist = 4.0 * (16.0 * (double)(div_up(std::max(n, ne), 2048) + 1) * 8.0 + 64.0);
+  return (size_t)(per_entry * (double)ne + per_part * (double)n + hist + 64.0 * 512.0 + 65536.0);
+}
+
 void interpolate_particles(Ctx &ctx, int64_t n, const double *xyz, const int64_t *owner, int64_t ne,
                            const double *exyz, const double *eh, const int32_t *ekind, const double *val, int ncomp,
                            double *out, hipStream_t s) {
@@ -195,6 +240,39 @@ void interpolate_particles(Ctx &ctx, int64_t n, const double *xyz, const int64_t
     SPH_LAUNCH_CHECK();
   }
   kt.done();
+}
+
+// The same with every buffer carved from this device's fixed scratch: no
+// device memory is allocated or freed.  Calls on one device share the
+// scratch, so calls that overlap in time on one device race.
+void interpolate_particles_noalloc(Ctx &ctx, int64_t n, const double *xyz, const int64_t *owner, int64_t ne,
+                                   const double *exyz, const double *eh, const int32_t *ekind, const double *val,
+                                   int ncomp, double *out, hipStream_t s) {
+  SPH_REQUIRE(ne > 0 && ne < ((int64_t)1 << 31) && n >= 0 && n < ((int64_t)1 << 31), SPHMAP_EINVAL,
+              "particle or entry count out of range");
+  const size_t need = interp_scratch_bound(n, ne);
+  SPH_REQUIRE(need <= kNoAllocScratch, SPHMAP_EINVAL,
+              "n = " + std::to_string(n) + " particles and " + std::to_string(ne) + " entries need up to " +
+                  std::to_string(need) + " bytes, more than the " + std::to_string(kNoAllocScratch) +
+                  "-byte fixed scratch");
+  void *base = g_scratch_ptr[ctx.device];
+  SPH_REQUIRE(base != nullptr, SPHMAP_EHIP, "the fixed scratch of this device was not looked up");
+  Arena region;
+  region.region = (char *)base;
+  region.region_cap = kNoAllocScratch;
+  struct Swap {  // every request of the call goes to the region; timing off (no events)
+    Ctx &c;
+    bool timing;
+    Swap(Ctx &cc, Arena *r) : c(cc), timing(cc.timing) {
+      c.arena.redirect = r;
+      c.timing = false;
+    }
+    ~Swap() {
+      c.arena.redirect = nullptr;
+      c.timing = timing;
+    }
+  } swap(ctx, &region);
+  interpolate_particles(ctx, n, xyz, owner, ne, exyz, eh, ekind, val, ncomp, out, s);
 }
 
 }  // namespace sphmap

@@ -40,7 +40,19 @@ void BlockPool::release() {
 }
 
 void *Arena::get(const std::string &name, size_t bytes) {
+  if (redirect) return redirect->get(name, bytes);
   Buffer &b = bufs[name];
+  if (region) {
+    if (b.bytes >= bytes) return b.p;
+    const size_t off = (region_used + 255) & ~(size_t)255;
+    if (off > region_cap || bytes > region_cap - off)
+      throw Error{SPHMAP_EINVAL, "the fixed scratch region of " + std::to_string(region_cap) + " bytes is too small (" +
+                                     name + " needs " + std::to_string(bytes) + " more)"};
+    b.p = region + off;
+    b.bytes = bytes;
+    region_used = off + bytes;
+    return b.p;
+  }
   if (b.bytes < bytes) {
     size_t want = bytes + bytes / 8 + 256;
     if (budget && budget->limit && budget->held - b.bytes + want > budget->limit) {
@@ -81,6 +93,11 @@ void *Arena::get(const std::string &name, size_t bytes) {
 }
 
 void Arena::release() {
+  if (region) {  // carved from a region this arena does not own
+    bufs.clear();
+    region_used = 0;
+    return;
+  }
   // pooled blocks are handed out again at once: queued work must be done
   if (pool && !bufs.empty()) (void)hipDeviceSynchronize();
   for (auto &kv : bufs) {
