@@ -238,6 +238,38 @@ int map_particles_to_cells_batch(sphmap_ctx *ctx, int32_t n_inst, const sphmap_t
                                  double *const *d_cell_density, double *const *d_coverage, void *stream,
                                  sphmap_pairs **pairs_out);
 
+/* ------------------------------------------------------------------------
+ * The same batched forward mapping as one captured HIP graph, for repeated
+ * steps over fixed buffers (the mapping is called on every timestep, Sec.
+ * 2.3).  sphmap_batch_create takes the arguments of
+ * map_particles_to_cells_batch (mixed precision; no retained lists), runs
+ * the step once to size each instance's pair lists (its pair count plus
+ * headroom times that count, at least 4096 more), runs it again in that
+ * capacity mode and captures the whole step -- pair search, Exact integral
+ * of every instance in one persistent launch, transpose, coverage and cell
+ * sums, instances dealt to four parallel branches -- into one HIP graph on
+ * `stream`.  The pointers and sizes are fixed by the plan; the particle
+ * arrays may hold new values at every step.
+ * sphmap_batch_run launches the graph once on `stream` (asynchronous; the
+ * outputs are those of map_particles_to_cells_batch on the arrays' current
+ * values, bit for bit).  An instance whose pair count passes its capacity is
+ * left empty (masses 0) and sets the plan's overflow flag;
+ * sphmap_batch_check waits for `stream`, copies each instance's pair count
+ * of the last step to h_pairs [n_inst] (host, nullable), returns the flag
+ * in *overflow (1: at least one step since the last check overflowed;
+ * make a new plan) and clears it.
+ * Errors: as map_particles_to_cells_batch; EINVAL for headroom outside
+ * [0, 16]; EHIP when the capture fails.  Free with sphmap_batch_free before
+ * the context and the tessellations. */
+typedef struct sphmap_batch sphmap_batch;
+int sphmap_batch_create(sphmap_ctx *ctx, int32_t n_inst, const sphmap_tess *const *tess, const int64_t *n,
+                        const double *const *d_xyz, const double *const *d_h, const double *const *d_m,
+                        int32_t normalize, double *const *d_cell_mass, double *const *d_cell_density,
+                        double *const *d_coverage, double headroom, void *stream, sphmap_batch **out);
+int sphmap_batch_run(sphmap_ctx *ctx, sphmap_batch *batch, void *stream);
+int sphmap_batch_check(sphmap_ctx *ctx, sphmap_batch *batch, void *stream, int64_t *h_pairs, int32_t *overflow);
+int sphmap_batch_free(sphmap_ctx *ctx, sphmap_batch *batch);
+
 /* Number of candidate pairs, cells and particles of a retained pair list. */
 int sphmap_pairs_info(const sphmap_pairs *pairs, int64_t *n_pairs, int64_t *n_cells, int64_t *n_particles);
 /* Copy the retained list into caller device buffers (any may be NULL):

@@ -358,6 +358,55 @@ def map_particles_to_cells_batch(ctx: Context, tess, xyz, h, m, precision: str |
     return out
 
 
+class BatchPlan:
+    """A batched forward mapping captured as one HIP graph (sphmap_batch_*):
+    run() launches the whole step once; the particle tensors passed at
+    creation may be updated in place between steps.  Outputs: .mass,
+    .density, .coverage (lists of device tensors, rewritten by each step)."""
+
+    def __init__(self, ctx: Context, tess, xyz, h, m, normalize: bool = False, headroom: float = 0.125,
+                 stream=None):
+        torch = _torch()
+        dev = ctx.device
+        k = len(tess)
+        if not (len(xyz) == len(h) == len(m) == k) or k < 1:
+            raise ValueError("tess, xyz, h and m must be lists of the same non-zero length")
+        self.ctx = ctx
+        self.xyz = [_dev_f64(a, dev, 3) for a in xyz]
+        self.h = [_dev_f64(a, dev) for a in h]
+        self.m = [_dev_f64(a, dev) for a in m]
+        ns = [a.shape[0] for a in self.xyz]
+        self.mass = [torch.empty(t.n_cells, dtype=torch.float64, device=dev) for t in tess]
+        self.density = [torch.empty(t.n_cells, dtype=torch.float64, device=dev) for t in tess]
+        self.coverage = [torch.empty(n, dtype=torch.float64, device=dev) for n in ns]
+        P = ctypes.c_void_p * k
+        arr = lambda ts: P(*[_ptr(t) for t in ts])
+        self._keep = (tess,)
+        h_ = ctypes.c_void_p()
+        ctx.check(_native.lib().sphmap_batch_create(
+            ctx.handle, k, P(*[t.handle for t in tess]), (ctypes.c_int64 * k)(*ns), arr(self.xyz), arr(self.h),
+            arr(self.m), 1 if normalize else 0, arr(self.mass), arr(self.density), arr(self.coverage),
+            float(headroom), _stream_handle(stream), ctypes.byref(h_)))
+        self.handle = h_
+        self.n_inst = k
+
+    def run(self, stream=None):
+        self.ctx.check(_native.lib().sphmap_batch_run(self.ctx.handle, self.handle, _stream_handle(stream)))
+
+    def check(self, stream=None):
+        """(pair count of each instance in the last step, overflow flag)."""
+        counts = (ctypes.c_int64 * self.n_inst)()
+        flag = ctypes.c_int32()
+        self.ctx.check(_native.lib().sphmap_batch_check(self.ctx.handle, self.handle, _stream_handle(stream), counts,
+                                                        ctypes.byref(flag)))
+        return list(counts), bool(flag.value)
+
+    def free(self):
+        if self.handle:
+            _native.lib().sphmap_batch_free(self.ctx.handle, self.handle)
+            self.handle = None
+
+
 def map_cells_to_particles(ctx: Context, pairs, cell_values, out=None, stream=None, *, tess=None, xyz=None,
                            h=None, precision: str | int = "mixed"):
     """Inverse mapping q_i = sum_c w_ic q_c / c_i ([C] or [C,k] -> [n] or [n,k]).

@@ -25,7 +25,8 @@ EXPORTS = [
     "sphmap_set_timing", "sphmap_kernel_time", "sphmap_reset_timing",
     "sphmap_set_counting", "sphmap_work_counters", "sphmap_set_autotune", "sphmap_tuned_shape",
     "sphmap_set_pool_limit", "sphmap_set_workspace_limit", "sphmap_workspace_info",
-    "interpolate_to_particles_noalloc",
+    "interpolate_to_particles_noalloc", "sphmap_batch_create", "sphmap_batch_run", "sphmap_batch_check",
+    "sphmap_batch_free",
 ]
 
 
@@ -129,6 +130,14 @@ def lib():
         L.sphmap_estimate_footprint.argtypes = [vp, i64, i64, i64, i64, i64, i64, ctypes.POINTER(Footprint)]
         L.interpolate_to_particles.restype = ctypes.c_int
         L.interpolate_to_particles.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp, i32, vp, vp]
+        L.sphmap_batch_create.restype = ctypes.c_int
+        L.sphmap_batch_create.argtypes = [vp, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp, dbl, vp, pp]
+        L.sphmap_batch_run.restype = ctypes.c_int
+        L.sphmap_batch_run.argtypes = [vp, vp, vp]
+        L.sphmap_batch_check.restype = ctypes.c_int
+        L.sphmap_batch_check.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i32)]
+        L.sphmap_batch_free.restype = ctypes.c_int
+        L.sphmap_batch_free.argtypes = [vp, vp]
         L.interpolate_to_particles_noalloc.restype = ctypes.c_int
         L.interpolate_to_particles_noalloc.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp, i32, vp, vp]
         L.build_pseudo_particles.restype = ctypes.c_int

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsphmap.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["prim.hip", "tess.hip", "pairs.hip", "exact.hip", "reduce.hip", "pseudo.hip", "kdtree.hip", "interp.hip", "voronoi.hip",
-           "abi.hip"]
+           "batch.hip", "abi.hip"]
 ARCH = os.environ.get("SPHMAP_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",

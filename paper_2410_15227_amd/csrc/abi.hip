@@ -16,6 +16,9 @@ struct sphmap_tess {
 struct sphmap_pairs {
   sphmap::PairsDev p;
 };
+struct sphmap_batch {
+  sphmap::BatchPlan b;
+};
 
 namespace {
 
@@ -408,6 +411,62 @@ int map_particles_to_cells_batch(sphmap_ctx *ctx, int32_t n_inst, const sphmap_t
   if (rc == SPHMAP_OK && pairs_out)
     for (int k = 0; k < n_inst; ++k) pairs_out[k] = owned[k].release();
   return rc;
+}
+
+int sphmap_batch_create(sphmap_ctx *ctx, int32_t n_inst, const sphmap_tess *const *tess, const int64_t *n,
+                        const double *const *d_xyz, const double *const *d_h, const double *const *d_m,
+                        int32_t normalize, double *const *d_cell_mass, double *const *d_cell_density,
+                        double *const *d_coverage, double headroom, void *stream, sphmap_batch **out) {
+  if (!ctx || !out) return SPHMAP_EINVAL;
+  *out = nullptr;
+  std::unique_ptr<sphmap_batch> B(new sphmap_batch);
+  int rc = guarded(ctx, [&] {
+    SPH_REQUIRE(n_inst >= 1, SPHMAP_EINVAL, "n_inst < 1");
+    SPH_REQUIRE(tess && n && d_xyz && d_h && d_m && d_cell_mass, SPHMAP_EINVAL, "null required array");
+    SPH_REQUIRE(normalize == 0 || normalize == 1, SPHMAP_EINVAL, "normalize must be 0 or 1");
+    sphmap::BatchPlan &P = B->b;
+    P.n_inst = n_inst;
+    P.normalize = normalize != 0;
+    for (int k = 0; k < n_inst; ++k) {
+      SPH_REQUIRE(tess[k], SPHMAP_EINVAL, "null tessellation of instance " + std::to_string(k));
+      SPH_REQUIRE(n[k] >= 1 && n[k] < ((int64_t)1 << 31), SPHMAP_EINVAL,
+                  "n out of range [1, 2^31) for instance " + std::to_string(k));
+      SPH_REQUIRE(d_xyz[k] && d_h[k] && d_m[k] && d_cell_mass[k], SPHMAP_EINVAL,
+                  "null required pointer of instance " + std::to_string(k));
+      SPH_REQUIRE(tess[k]->t.device == ctx->c.device, SPHMAP_EINVAL, "tessellation belongs to another device");
+      P.t.push_back(&tess[k]->t);
+      P.pd.push_back(sphmap::PartDev{n[k], d_xyz[k], d_h[k], d_m[k], nullptr});
+      P.P.emplace_back(new sphmap::PairsDev);
+      P.mass.push_back(d_cell_mass[k]);
+      P.dens.push_back(d_cell_density ? d_cell_density[k] : nullptr);
+      P.cov.push_back(d_coverage ? d_coverage[k] : nullptr);
+    }
+    sphmap::batch_plan_build(ctx->c, P, headroom, as_stream(stream));
+  });
+  if (rc != SPHMAP_OK) {
+    (void)hipDeviceSynchronize();
+    return rc;
+  }
+  *out = B.release();
+  return SPHMAP_OK;
+}
+
+int sphmap_batch_run(sphmap_ctx *ctx, sphmap_batch *batch, void *stream) {
+  if (!ctx || !batch) return SPHMAP_EINVAL;
+  return guarded(ctx, [&] { sphmap::batch_plan_run(ctx->c, batch->b, as_stream(stream)); });
+}
+
+int sphmap_batch_check(sphmap_ctx *ctx, sphmap_batch *batch, void *stream, int64_t *h_pairs, int32_t *overflow) {
+  if (!ctx || !batch || !overflow) return SPHMAP_EINVAL;
+  return guarded(ctx, [&] { sphmap::batch_plan_check(ctx->c, batch->b, as_stream(stream), h_pairs, overflow); });
+}
+
+int sphmap_batch_free(sphmap_ctx *ctx, sphmap_batch *batch) {
+  if (!ctx || !batch) return SPHMAP_EINVAL;
+  (void)hipSetDevice(ctx->c.device);
+  (void)hipDeviceSynchronize();
+  delete batch;
+  return SPHMAP_OK;
 }
 
 int sphmap_pairs_info(const sphmap_pairs *pairs, int64_t *n_pairs, int64_t *n_cells, int64_t *n_particles) {

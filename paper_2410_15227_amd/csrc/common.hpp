@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -214,6 +215,12 @@ struct PairsDev {
   int32_t *pm_cell = nullptr;   // [P] particle-major cell index
   double *pm_w = nullptr;       // [P] particle-major weights
   double *coverage = nullptr;   // [N]
+  // capacity mode (graph-captured batches): cap > 0 sizes the lists for cap
+  // pairs and keeps the count on the device
+  int64_t cap = 0;
+  int64_t *d_np = nullptr;      // the pair count (0 when it passed cap)
+  int32_t *d_over = nullptr;    // 1 when the count passed cap (list emptied)
+  int32_t *d_flag = nullptr;    // or-ed with every overflow of the plan
 };
 
 // ---------------------------------------------------------- primitives
@@ -259,7 +266,47 @@ struct ExactJob {
   const PartDev *p;
   PairsDev *P;
 };
-void exact_integral_batch(Ctx &ctx, const std::vector<ExactJob> &jobs, int precision, hipStream_t s);
+// the instance table of a batch whose pair counts stay on the device: the
+// pointer table (uploaded once), chunk offsets, and each instance's count
+struct ExactTable {
+  void *insts = nullptr;
+  int64_t *chunk0 = nullptr;
+  const int64_t **np = nullptr;
+};
+void exact_integral_batch(Ctx &ctx, const std::vector<ExactJob> &jobs, int precision, hipStream_t s,
+                          const ExactTable *tab = nullptr);
+void exact_table_upload(Ctx &ctx, const std::vector<ExactJob> &jobs, ExactTable &tab, hipStream_t s);
+size_t exact_inst_bytes();
+
+// A batch of forward mappings captured as one HIP graph (batch.hip).
+constexpr int kBatchBranches = 4;
+struct BatchPlan {
+  int n_inst = 0;
+  bool normalize = false;
+  std::vector<const TessDev *> t;
+  std::vector<PartDev> pd;
+  std::vector<std::unique_ptr<PairsDev>> P;
+  std::vector<double *> mass, dens, cov;
+  std::vector<Arena> scratch;  // one per branch stream
+  std::vector<int64_t> n_max;  // largest instance of each branch
+  hipStream_t origin = nullptr;  // the stream the step was captured on
+  std::vector<hipStream_t> branch;
+  hipEvent_t ev_fork = nullptr;
+  std::vector<hipEvent_t> ev_join;
+  Arena mem;
+  int64_t *d_np = nullptr;
+  int32_t *d_over = nullptr, *d_flag = nullptr;
+  ExactTable tab;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  BatchPlan() = default;
+  BatchPlan(const BatchPlan &) = delete;
+  BatchPlan &operator=(const BatchPlan &) = delete;
+  ~BatchPlan();
+};
+void batch_plan_build(Ctx &ctx, BatchPlan &B, double headroom, hipStream_t s);
+void batch_plan_run(Ctx &ctx, BatchPlan &B, hipStream_t s);
+void batch_plan_check(Ctx &ctx, BatchPlan &B, hipStream_t s, int64_t *h_pairs, int32_t *overflow);
 // upper bound of the context scratch the Exact integral of n_pairs pairs takes
 size_t exact_workspace_bytes(Ctx &ctx, int64_t n_pairs);
 // transpose + coverage

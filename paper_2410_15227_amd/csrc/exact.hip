@@ -545,6 +545,22 @@ __global__ void k_zero_i32(int32_t *p, int n) {
   if (t < n) p[t] = 0;
 }
 
+// Instance table of a batch whose pair counts are known only on the device:
+// each instance's count *np[k] (0 for an overflowed list) and the first
+// chunk of each instance.  One thread; the table's pointers were uploaded
+// with the plan.
+__global__ void k_exact_table(int n_inst, const int64_t *const *np, ExactInst *insts, int64_t *chunk0) {
+  if (threadIdx.x != 0) return;
+  int64_t c = 0;
+  for (int k = 0; k < n_inst; ++k) {
+    const int64_t P = *np[k];
+    insts[k].P = P;
+    chunk0[k] = c;
+    c += (P + 63) / 64;
+  }
+  chunk0[n_inst] = c;
+}
+
 // atan2(y, x) for any x, from the binary32-core atan
 __device__ inline double atan2_mixed(double y, double x) {
   const double r = atan_mixed(y, fabs(x));  // copysign(pi/2, y) for x = 0
@@ -1235,11 +1251,42 @@ static void exact_occupancy(Ctx &ctx) {
   ctx.exact_per_cu = std::max(ctx.exact_per_cu, 1);
 }
 
-void exact_integral_batch(Ctx &ctx, const std::vector<ExactJob> &jobs, int precision, hipStream_t s) {
+void exact_integral_batch(Ctx &ctx, const std::vector<ExactJob> &jobs, int precision, hipStream_t s,
+                          const ExactTable *tab) {
   int64_t total = 0;
   for (const auto &j : jobs) {
     j.P->w = j.P->mem.get<double>("w", j.P->n_pairs);
     total += j.P->n_pairs;
+  }
+  if (tab) {
+    // pair counts on the device (capacity mode): the table of pointers is
+    // already uploaded; one kernel fills in the counts and chunk offsets,
+    // and the persistent grid takes its full size
+    SPH_REQUIRE(precision == SPHMAP_PREC_MIXED, SPHMAP_EINVAL, "a device-counted batch runs the mixed path");
+    const int n_inst = (int)jobs.size();
+    k_exact_table<<<1, 64, 0, s>>>(n_inst, tab->np, (ExactInst *)tab->insts, tab->chunk0);
+    SPH_LAUNCH_CHECK();
+    exact_occupancy(ctx);
+    int bpc = ctx.exact_per_cu, pf = 1;
+    const int bucket = 63 - __builtin_clzll((unsigned long long)std::max<int64_t>(total, 1));
+    auto it = ctx.tuned.find(bucket);
+    if (it != ctx.tuned.end()) {
+      bpc = it->second.blocks_per_cu;
+      pf = it->second.per_fetch;
+    }
+    const int64_t grid = (int64_t)ctx.n_cu * std::min(bpc, ctx.exact_per_cu);
+    FaceRec *faces = ctx.arena.get<FaceRec>("flat_faces", grid * kFlatWaves * kEntryCap);
+    int32_t *next = ctx.arena.get<int32_t>("flat_next", 2);
+    int64_t *redo = ctx.arena.get<int64_t>("flat_redo", std::max<int64_t>(total, 1));
+    k_zero_i32<<<1, 64, 0, s>>>(next, 2);
+    SPH_LAUNCH_CHECK();
+    k_exact_edges<false><<<(unsigned)grid, 64 * kFlatWaves, 0, s>>>((const ExactInst *)tab->insts, tab->chunk0, n_inst, pf, nullptr,
+                                                                   faces, next, redo, next + 1);
+    SPH_LAUNCH_CHECK();
+    k_exact_mixed_list<<<(unsigned)(ctx.n_cu * 4), 256, 0, s>>>(redo, next + 1, (const ExactInst *)tab->insts, tab->chunk0, n_inst,
+                                                                 nullptr);
+    SPH_LAUNCH_CHECK();
+    return;
   }
   int64_t *ctr = ctx.counting ? ctx.d_counters : nullptr;
   if (ctr) SPH_HIP(hipMemsetAsync(ctr, 0, 8 * sizeof(int64_t), s));
@@ -1331,6 +1378,26 @@ void exact_integral_batch(Ctx &ctx, const std::vector<ExactJob> &jobs, int preci
   SPH_LAUNCH_CHECK();
   kr.done();
 }
+
+// Upload the pointer table of a device-counted batch (before capture).
+void exact_table_upload(Ctx &ctx, const std::vector<ExactJob> &jobs, ExactTable &tab, hipStream_t s) {
+  const int n_inst = (int)jobs.size();
+  std::vector<ExactInst> host(n_inst);
+  std::vector<const int64_t *> np(n_inst);
+  for (int k = 0; k < n_inst; ++k) {
+    const TessDev &t = *jobs[k].t;
+    const PartDev &p = *jobs[k].p;
+    const PairsDev &P = *jobs[k].P;
+    host[k] = ExactInst{P.pair_c, P.pair_p, p.xyz, p.h, t.gen, t.cell_face_off, t.face_vtx_off, t.fplane, t.fsphere,
+                        t.fplane32, t.fvpos32, t.edgeA, t.edgeE, t.edgeM, t.fvpos, P.w, 0};
+    np[k] = P.d_np;
+  }
+  SPH_HIP(hipMemcpyAsync(tab.insts, host.data(), n_inst * sizeof(ExactInst), hipMemcpyHostToDevice, s));
+  SPH_HIP(hipMemcpyAsync((void *)tab.np, np.data(), n_inst * sizeof(int64_t *), hipMemcpyHostToDevice, s));
+  SPH_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
+}
+
+size_t exact_inst_bytes() { return sizeof(ExactInst); }
 
 size_t exact_workspace_bytes(Ctx &ctx, int64_t n_pairs) {
   exact_occupancy(ctx);

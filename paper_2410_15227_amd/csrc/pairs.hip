@@ -363,6 +363,62 @@ void build_hier(Arena &ar, const float4 *sx, int64_t n, float slack, const std::
   H.levels = l;
 }
 
+namespace {
+
+// Capacity mode: the pair count (the scanned total) stays on the device.
+// np = total when it fits the capacity, else 0 with the list's overflow bit
+// and the plan's flag set; the long-list count starts at 0.
+__global__ void k_cap_count(const int64_t *total, int64_t cap, int64_t *np, int32_t *over_bit, int32_t *n_over,
+                            int32_t *flag) {
+  if (threadIdx.x != 0) return;
+  const int64_t tot = *total;
+  const bool over = tot > cap;
+  *np = over ? 0 : tot;
+  *over_bit = over ? 1 : 0;
+  *n_over = 0;
+  if (over) atomicOr(flag, 1);
+}
+
+// An overflowed list is emptied: every cell offset becomes 0.
+__global__ void k_zero_if_over(int64_t *off, int64_t n, const int32_t *over_bit) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && *over_bit) off[i] = 0;
+}
+
+}  // namespace
+
+// find_pairs with the lists sized for P.cap pairs and no host read of the
+// count: cells whose lists would end past the capacity are skipped, and an
+// overflowed list is emptied and flagged (P.d_over, *P.d_flag); later steps
+// read the count P.d_np.  Nothing is allocated here once the buffers have
+// their size, and no buffer is cleared by a memory set, so the work can be
+// captured in a graph.
+static void find_pairs_capped(Ctx &ctx, const TessDev &t, PairsDev &P, const Hier &H, const int32_t *buf,
+                              hipStream_t s) {
+  Arena &ar = ctx.arena;
+  const int64_t C = t.n_cells;
+  P.n_pairs = P.cap;
+  P.pair_p = P.mem.get<int32_t>("pair_p", P.cap);
+  P.pair_c = P.mem.get<int32_t>("pair_c", P.cap);
+  int32_t *over = ar.get<int32_t>("pp_over", std::max<int64_t>(C, 1));
+  int32_t *n_over = ar.get<int32_t>("pp_nover", 1);
+  k_cap_count<<<1, 64, 0, s>>>(P.cell_off + C, P.cap, P.d_np, P.d_over, n_over, P.d_flag);
+  SPH_LAUNCH_CHECK();
+  if (C == 0) return;
+  k_compact_sort<<<(unsigned)div_up(C, 4), 256, 0, s>>>(C, P.cell_off, buf, P.pair_p, P.pair_c, over, n_over, P.cap);
+  SPH_LAUNCH_CHECK();
+  // longer lists: the grid steps through however many the device listed
+  k_pairs<true><<<(unsigned)std::min<int64_t>(div_up(C, 4), 2048), 256, 0, s>>>(
+      H, C, over, t.gen32, nullptr, P.cell_off, P.pair_p, P.pair_c, nullptr, n_over, P.cap);
+  SPH_LAUNCH_CHECK();
+  int32_t *tmp = ar.get<int32_t>("pp_sort_tmp", P.cap);
+  k_sort_segments<<<(unsigned)std::min<int64_t>(C, 1024), 256, 0, s>>>(C, P.cell_off, P.pair_p, tmp, over, n_over,
+                                                                        P.cap);
+  SPH_LAUNCH_CHECK();
+  k_zero_if_over<<<(unsigned)div_up(C + 1, 256), 256, 0, s>>>(P.cell_off, C + 1, P.d_over);
+  SPH_LAUNCH_CHECK();
+}
+
 void find_pairs(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, hipStream_t s) {
   Arena &ar = ctx.arena;
   const int64_t N = p.n, C = t.n_cells;
@@ -397,6 +453,10 @@ void find_pairs(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, hipSt
     kt.done();
   }
   scan_exclusive_i64(ar, counts, P.cell_off, C, true, s);
+  if (P.cap > 0) {
+    find_pairs_capped(ctx, t, P, H, buf, s);
+    return;
+  }
   int64_t total = 0;
   SPH_HIP(hipMemcpyAsync(&total, P.cell_off + C, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   SPH_HIP(hipStreamSynchronize(s));

@@ -47,8 +47,11 @@ __global__ void __launch_bounds__(256) k_cell_mass(int64_t C, const int64_t *off
 // Particle offsets from the sorted particle keys: position k starts every
 // particle in (key[k-1], key[k]] (particles without pairs start where the
 // next one does); the end, NP, starts every particle after the last key.
-__global__ void k_part_offsets(int64_t NP, int64_t N, const uint32_t *key, int64_t *part_off) {
+// (dNP: a pair count known only on the device, at most NP.)
+__global__ void k_part_offsets(int64_t NP, int64_t N, const uint32_t *key, int64_t *part_off,
+                               const int64_t *dNP = nullptr) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (dNP) NP = *dNP;
   if (k > NP) return;
   const int64_t lo = k == 0 ? -1 : (int64_t)key[k - 1];
   const int64_t hi = k == NP ? N : (int64_t)key[k];
@@ -152,8 +155,11 @@ void particle_major(Ctx &ctx, PairsDev &P, hipStream_t s) {
     uint32_t *keys = ar.get<uint32_t>("pm_keys", NP);
     int bits = 1;
     while (bits < 32 && ((int64_t)1 << bits) < N) ++bits;
-    sort_by_key_kv(ar, NP, bits, (const uint32_t *)P.pair_p, P.pair_c, P.w, keys, P.pm_cell, P.pm_w, s);
-    k_part_offsets<<<(unsigned)div_up(NP + 1, 256), 256, 0, s>>>(NP, N, keys, P.part_off);
+    // (capacity mode: NP is the capacity and P.d_np the count on the device)
+    sort_by_key_kv(ar, NP, bits, (const uint32_t *)P.pair_p, P.pair_c, P.w, keys, P.pm_cell, P.pm_w, s,
+                   P.cap > 0 ? P.d_np : nullptr);
+    k_part_offsets<<<(unsigned)div_up(NP + 1, 256), 256, 0, s>>>(NP, N, keys, P.part_off,
+                                                                 P.cap > 0 ? P.d_np : nullptr);
     SPH_LAUNCH_CHECK();
     k_coverage<<<(unsigned)div_up(N * 64, 256), 256, 0, s>>>(N, P.part_off, P.pm_w, P.coverage);
     SPH_LAUNCH_CHECK();

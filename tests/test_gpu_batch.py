@@ -73,3 +73,64 @@ def test_batch_rejects_bad_input(ctx, instances):
     with pytest.raises(Exception):
         pkg.map_particles_to_cells_batch(ctx, [dt], [pos], [h[:-1]], [m])
     dt.free()
+
+
+def test_graph_plan(ctx, instances):
+    """The batch captured as one HIP graph: each replay equals the single
+    calls bit for bit; after the particle arrays are updated in place a
+    replay equals a fresh uncaptured batch on the new values; a step whose
+    pair counts pass the lists' capacity (every h enlarged in place) leaves
+    the lists empty and raises the overflow flag instead of writing past
+    them, and a new plan maps the enlarged supports correctly."""
+    import paper_2410_15227_amd as pkg
+    say(f"case: graph plan of {len(instances)} instances")
+    dts = [pkg.DeviceTessellation(ctx, t) for (_, _, _, t) in instances]
+    xs = [torch.tensor(i[0], device="cuda") for i in instances]
+    hs = [torch.tensor(i[1], device="cuda") for i in instances]
+    ms = [torch.tensor(i[2], device="cuda") for i in instances]
+    singles = []
+    for dt, x, h, m in zip(dts, xs, hs, ms):
+        r = pkg.map_particles_to_cells(ctx, dt, x, h, m, keep_pairs=True)
+        singles.append((r.mass.clone(), r.coverage.clone(), r.density.clone(), r.pairs.n_pairs))
+        r.pairs.free()
+    plan = pkg.BatchPlan(ctx, dts, xs, hs, ms)
+    for rep in range(3):
+        plan.run()
+        counts, over = plan.check()
+        assert not over
+        for k, (M, cov, rho, npairs) in enumerate(singles):
+            assert counts[k] == npairs, (rep, k)
+            assert torch.equal(plan.mass[k], M), (rep, k)
+            assert torch.equal(plan.coverage[k], cov), (rep, k)
+            assert torch.equal(plan.density[k], rho), (rep, k)
+    # new positions in the same buffers (a timestep: each moved by about 2e-3)
+    g = np.random.default_rng(77)
+    for x, (pos, h, m, t) in zip(xs, instances):
+        x.copy_(torch.tensor(np.clip(pos + g.normal(size=pos.shape) * 2e-3, 0.0, np.nextafter(1.0, 0.0)),
+                             device="cuda"))
+    plan.run()
+    counts, over = plan.check()
+    assert not over
+    fresh = pkg.map_particles_to_cells_batch(ctx, dts, xs, hs, ms)
+    for k, r in enumerate(fresh):
+        assert torch.equal(plan.mass[k], r.mass), k
+        assert torch.equal(plan.coverage[k], r.coverage), k
+    # supports 1.6 times larger: more pairs than the lists hold
+    for h in hs:
+        h.mul_(1.6)
+    plan.run()
+    counts, over = plan.check()
+    assert over
+    assert all(float(M.abs().sum()) == 0.0 for M, n in zip(plan.mass, counts) if n == 0)
+    assert any(n == 0 for n in counts)
+    plan.free()
+    plan = pkg.BatchPlan(ctx, dts, xs, hs, ms)
+    plan.run()
+    counts, over = plan.check()
+    assert not over
+    fresh = pkg.map_particles_to_cells_batch(ctx, dts, xs, hs, ms)
+    for k, r in enumerate(fresh):
+        assert torch.equal(plan.mass[k], r.mass), k
+    plan.free()
+    for dt in dts:
+        dt.free()
