@@ -567,6 +567,126 @@ void ora_cell_distance(int64_t n_cells, const double *gen, const double *vert, c
   for (int64_t k = 0; k < n_list; ++k) out[k] = cell_distance(&T, cells[k], xyz + 3 * k);
 }
 
+/* ----------------------------------------------- algorithmic work counts */
+/* What the Exact integral of the canonical pairs of the listed cells must
+   evaluate, in exact (binary64) geometry, summed over the pairs:
+     out[0] pairs
+     out[1] faces of the pairs' cells
+     out[2] faces the support reaches (face polygon closer than 2h)
+     out[3] edges of those faces
+     out[4] edges the support reaches (edge segment closer than 2h)
+     out[5] inner pieces, out[6] outer pieces: the part of a reached edge
+            inside the support splits where U = |r - x|/h crosses 1; a part
+            with U < 1 is an inner piece, one with 1 <= U < 2 an outer piece
+            (a range crossing U = 1 on both sides counts one of each: the
+            outer form over the whole range plus twice the difference over
+            the inner stretch).
+   Each face is oriented outwards as in the weight. */
+void ora_work_counts(int64_t n_cells, const double *gen, const double *vert, const int64_t *cfo,
+                     const int64_t *fvo, const int32_t *fv, int64_t n_part, const double *xyz,
+                     const double *h, int64_t n_list, const int64_t *cells, int64_t *out) {
+  tess_t T = {n_cells, gen, vert, cfo, fvo, fv};
+  int64_t tot[7] = {0, 0, 0, 0, 0, 0, 0};
+#pragma omp parallel
+  {
+    int64_t loc[7] = {0, 0, 0, 0, 0, 0, 0};
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t k = 0; k < n_list; ++k) {
+      int64_t c = cells[k];
+      float R = ora_cell_radius_t(&T, c);
+      const double *g = gen + 3 * c;
+      int64_t f0 = cfo[c], f1 = cfo[c + 1];
+      double inside[3] = {0, 0, 0};
+      int64_t nvtot = 0;
+      for (int64_t t = fvo[f0]; t < fvo[f1]; ++t, ++nvtot)
+        for (int j = 0; j < 3; ++j) inside[j] += vert[3 * (int64_t)fv[t] + j];
+      for (int j = 0; j < 3; ++j) inside[j] /= (nvtot > 0 ? (double)nvtot : 1.0);
+      for (int64_t i = 0; i < n_part; ++i) {
+        const double *x = xyz + 3 * i;
+        if (!canon_pair(x, h[i], g, R)) continue;
+        const double hh = h[i], r2 = 4.0 * hh * hh;
+        loc[0] += 1;
+        loc[1] += f1 - f0;
+        for (int64_t f = f0; f < f1; ++f) {
+          int nv = (int)(fvo[f + 1] - fvo[f]);
+          if (nv < 3 || nv > 512) continue;
+          const double *V[512];
+          for (int q = 0; q < nv; ++q) V[q] = vert + 3 * (int64_t)fv[fvo[f] + q];
+          double avec[3], cen[3];
+          poly_area_vec(nv, V, avec, cen);
+          double an = sqrt(v_dot(avec, avec));
+          if (an == 0.0) continue;
+          double n[3] = {avec[0] / an, avec[1] / an, avec[2] / an};
+          double gc[3];
+          v_sub(cen, inside, gc);
+          if (v_dot(n, gc) < 0.0)
+            for (int j = 0; j < 3; ++j) n[j] = -n[j];
+          double xc[3];
+          v_sub(x, cen, xc);
+          double sd = v_dot(n, xc);
+          if (sd * sd >= r2) continue; /* the plane is beyond the support */
+          double P0[3] = {x[0] - sd * n[0], x[1] - sd * n[1], x[2] - sd * n[2]};
+          int in = 1;
+          double emin = HUGE_VAL;
+          for (int q = 0; q < nv; ++q) {
+            const double *A = V[q], *B = V[(q + 1) % nv];
+            double ab[3], ap[3], ac[3], cr[3];
+            v_sub(B, A, ab);
+            v_sub(P0, A, ap);
+            v_sub(cen, A, ac);
+            v_cross(ab, ap, cr);
+            double side = v_dot(cr, n);
+            v_cross(ab, ac, cr);
+            if (side * v_dot(cr, n) < 0.0) in = 0;
+            double e = seg_dist(x, A, B);
+            if (e < emin) emin = e;
+          }
+          double dp = in ? fabs(sd) : emin;
+          if (dp * dp >= r2) continue; /* the face polygon is beyond the support */
+          loc[2] += 1;
+          for (int q = 0; q < nv; ++q) {
+            const double *A = V[q], *B = V[(q + 1) % nv];
+            double ab[3], ax[3];
+            v_sub(B, A, ab);
+            double L2 = v_dot(ab, ab);
+            if (L2 == 0.0) continue;
+            loc[3] += 1;
+            if (seg_dist(x, A, B) >= 2.0 * hh) continue;
+            loc[4] += 1;
+            /* along the edge line, in units of h: U^2 = a^2 + t^2, t from
+               the foot of x on the line; the segment is [ta, tb] */
+            v_sub(x, A, ax);
+            double L = sqrt(L2);
+            double tf = v_dot(ax, ab) / L; /* foot along the edge from A */
+            double a2 = (v_dot(ax, ax) - tf * tf) / (hh * hh);
+            if (a2 < 0.0) a2 = 0.0;
+            double ta = -tf / hh, tb = (L - tf) / hh;
+            double t2 = sqrt(fmax(4.0 - a2, 0.0));
+            double ca = fmin(fmax(ta, -t2), t2), cb = fmin(fmax(tb, -t2), t2);
+            if (a2 < 1.0) {
+              double t1 = sqrt(1.0 - a2);
+              int lo = ca < -t1 && cb > -t1, hi = ca < t1 && cb > t1;
+              if (lo || hi) {
+                loc[5] += 1;
+                loc[6] += 1;
+              } else {
+                double mid = 0.5 * (ca + cb);
+                if (fabs(mid) < t1) loc[5] += 1;
+                else loc[6] += 1;
+              }
+            } else {
+              loc[6] += 1;
+            }
+          }
+        }
+      }
+    }
+#pragma omp critical
+    for (int j = 0; j < 7; ++j) tot[j] += loc[j];
+  }
+  for (int j = 0; j < 7; ++j) out[j] = tot[j];
+}
+
 /* Angular fan integral, exposed for unit tests:
    int_{pa}^{pb} Psi_{ad}(sqrt(ad^2 + p^2 sec^2 phi)) dphi. */
 double ora_fan_integral(double ad, double p, double pa, double pb) {

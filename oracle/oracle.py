@@ -75,6 +75,8 @@ def _lib():
         L.ora_voronoi_cells.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp]
         L.ora_lloyd.restype = None
         L.ora_lloyd.argtypes = [i64, vp, vp, vp, i32, vp]
+        L.ora_work_counts.restype = None
+        L.ora_work_counts.argtypes = tess + [i64, vp, vp, i64, vp, vp]
         L.ora_cell_distance.restype = None
         L.ora_cell_distance.argtypes = tess + [i64, vp, vp, vp]
         L.ora_interpolate.restype = None
@@ -138,6 +140,18 @@ def weight_poly(x, h, faces, inside=None) -> float:
 def weight(t, c: int, x, h: float) -> float:
     x = _c(x, np.float64)
     return _lib().ora_weight(*_tess_args(t), int(c), _p(x), float(h))
+
+
+def work_counts(t, pos, h, cells):
+    """What the Exact integral of the canonical pairs of the listed cells
+    must evaluate, in exact geometry: [pairs, faces, faces the support
+    reaches, their edges, edges the support reaches, inner pieces, outer
+    pieces] (see ora_work_counts)."""
+    cells = _c(cells, np.int64)
+    pos, h = _c(pos, np.float64), _c(h, np.float64)
+    out = np.zeros(7, dtype=np.int64)
+    _lib().ora_work_counts(*_tess_args(t), pos.shape[0], _p(pos), _p(h), len(cells), _p(cells), _p(out))
+    return out
 
 
 def cell_distance(t, cells, xyz):

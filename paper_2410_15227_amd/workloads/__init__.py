@@ -189,6 +189,44 @@ class Tessellation:
         )
 
 
+def degeneracy_scores(t: Tessellation) -> np.ndarray:
+    """A score per cell of how thin or sliver-like it is, for picking the
+    cells that stress the closed forms in samples: the cell's largest vertex
+    distance from its generator divided by the smaller of (a) the nearest
+    face plane's distance from the generator and (b) the shortest edge.
+    Flat cells, cells with a face nearly through the generator and cells
+    with tiny edges score high."""
+    fvo, fv, cfo = t.face_vtx_off, t.face_vtx.astype(np.int64), t.cell_face_off
+    nf = len(fvo) - 1
+    face_of_slot = np.repeat(np.arange(nf), np.diff(fvo))
+    cell_of_face = np.repeat(np.arange(t.n_cells), np.diff(cfo))
+    V = t.vertices[fv]
+    nxt = np.arange(len(fv)) + 1
+    last = fvo[1:] - 1
+    nxt[last] = fvo[:-1]  # the edge from a face's last vertex closes the polygon
+    W = V[nxt]
+    # face area vector (fan about the first vertex), its unit normal
+    V0 = V[fvo[:-1]][face_of_slot]
+    cr = np.cross(V - V0, W - V0)
+    area = np.zeros((nf, 3))
+    np.add.at(area, face_of_slot, cr)
+    an = np.linalg.norm(area, axis=1)
+    n = area / np.where(an > 0, an, 1.0)[:, None]
+    g = t.generators[cell_of_face]
+    pd = np.abs(np.einsum("ij,ij->i", n, t.vertices[fv[fvo[:-1]]] - g))
+    pd = np.where(an > 0, pd, np.inf)
+    elen = np.linalg.norm(W - V, axis=1)
+    elen = np.where(elen > 0, elen, np.inf)
+    dmin = np.full(t.n_cells, np.inf)
+    np.minimum.at(dmin, cell_of_face, pd)
+    emin = np.full(t.n_cells, np.inf)
+    np.minimum.at(emin, cell_of_face[face_of_slot], elen)
+    rv = np.linalg.norm(V - t.generators[cell_of_face[face_of_slot]], axis=1)
+    rmax = np.zeros(t.n_cells)
+    np.maximum.at(rmax, cell_of_face[face_of_slot], rv)
+    return rmax / np.minimum(dmin, emin)
+
+
 def voronoi(gen: np.ndarray, box_lo=(0.0, 0.0, 0.0), box_hi=(1.0, 1.0, 1.0)) -> Tessellation:
     """Box-clipped Voronoi tessellation of the generators (host, OpenMP)."""
     gen = np.ascontiguousarray(gen, dtype=np.float64)

@@ -114,3 +114,19 @@ def test_canonical_radius_definition(oracle, small_tess, workloads):
         # a binary32 value squared is exact in binary64: the comparisons are exact
         assert np.all(R * R >= r2)
         assert np.all(below * below < r2)
+
+
+@pytest.mark.parametrize("hh, want", [
+    (0.4, [1, 6, 0, 0, 0, 0, 0]),      # support inside the cube: nothing to integrate
+    (0.6, [1, 6, 6, 24, 0, 0, 0]),     # reaches the six faces (distance 1) but no edge (sqrt 2)
+    (0.75, [1, 6, 6, 24, 24, 0, 24]),  # reaches every edge, never within U < 1 of one
+    (1.5, [1, 6, 6, 24, 24, 24, 24]),  # edge line at 0.943 h: U = 1 crossed on both sides
+])
+def test_work_counts_cube(oracle, hh, want):
+    """The algorithmic work histogram on a cube of half-side 1 about the
+    particle, in closed form: faces at distance 1, edges at sqrt(2), corners
+    at sqrt(3); an edge line at a = sqrt(2)/h (units of h) crosses U = 1 at
+    t = +-sqrt(1 - a^2), inside the edge's span +-1/h."""
+    t = _box_tess([-1.0, -1.0, -1.0], [1.0, 1.0, 1.0])
+    got = oracle.work_counts(t, np.zeros((1, 3)), np.array([hh]), np.array([0]))
+    assert list(got) == want
