@@ -25,19 +25,64 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Per-item arithmetic of the Exact integral (FLOPs; a square root, division,
-# reciprocal, atan or log counted as one), multiplied by the device work
-# counters of the same workload:
-FLOP_FACE_TEST = 6        # plane distance of the particle
-FLOP_FACE_INT = 32        # scaled distance, sphere cull, foot point, |d| H(|d|), accumulation
-FLOP_EDGE_VISIT = 46      # edge direction, in-plane normal, p, tau_A, tau_B, angle term
-FLOP_EDGE_INT = 14        # clip to U < 2, regime split
-FLOP_PIECE = 93           # mixed path: one single-regime piece (coefficients, 3 differences, polynomials)
-FLOP_FD = 60              # binary64 path: one antiderivative evaluation (3 transcendentals + polynomials)
-# Vector FMA peak of MI355X for the arithmetic these kernels issue: 256 CUs x
-# 4 SIMDs x 16 lanes x 2 FLOP x 2.4 GHz = 78.6 TFLOP/s, the same for binary64
-# and for unpacked binary32 (the library is built without packed-FP32 code).
+# Work model of the Exact integral per algorithmic unit: arithmetic FLOPs
+# (add, multiply, fused multiply-add = 2, compare, division), with the
+# transcendental functions the closed form needs -- atan, log, square root
+# -- counted apart (TRANS):
+#   face tested:      plane distance of the particle                     6 FLOP
+#   face reached:     scaled distance, foot point, |d| H(|d|), sums     32 FLOP
+#   edge visited:     in-plane p, tau_A, tau_B; the angle term          45 FLOP + 1 TRANS (atan)
+#   edge integrated:  range clipped to U < 2, split at U = 1            13 FLOP + 1 TRANS (sqrt)
+#   piece (mixed):    coefficients, U at both ends, three differences,
+#                     polynomials                                       88 FLOP + 5 TRANS (2 atan, log, 2 sqrt)
+#   antiderivative evaluation (binary64 path)                           55 FLOP + 4 TRANS
+FLOP_FACE_TEST = 6
+FLOP_FACE_INT = 32
+FLOP_EDGE_VISIT, TRANS_EDGE_VISIT = 45, 1
+FLOP_EDGE_INT, TRANS_EDGE_INT = 13, 1
+FLOP_PIECE, TRANS_PIECE = 88, 5
+FLOP_FD, TRANS_FD = 55, 4
+# MI355X vector peaks: 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP x 2.4 GHz =
+# 78.6 TFLOP/s for binary64 and unpacked binary32 (the library is built
+# without packed-FP32 code generation, so this is the rate its instructions
+# can reach); 157.3 with packed binary32; transcendental instructions issue
+# at a quarter of the lane rate, 9.83 T op/s.
 PEAK_TFLOPS = 78.6
+PEAK_TFLOPS_PACKED = 157.3
+PEAK_TRANS = 9.83
+
+
+def work_model(c, precision):
+    """(FLOP, TRANS) of the model over counts c = [pairs, faces tested,
+    faces reached, edges visited, edges integrated, inner pieces, outer
+    pieces] (device work counters or the oracle's histogram)."""
+    per_f, per_t = (FLOP_PIECE, TRANS_PIECE) if precision == "mixed" else (FLOP_FD, TRANS_FD)
+    flop = (FLOP_FACE_TEST * c[1] + FLOP_FACE_INT * c[2] + FLOP_EDGE_VISIT * c[3] + FLOP_EDGE_INT * c[4]
+            + per_f * (c[5] + c[6]))
+    trans = TRANS_EDGE_VISIT * c[3] + TRANS_EDGE_INT * c[4] + per_t * (c[5] + c[6])
+    return float(flop), float(trans)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def baseline_cells(tess, count, seed, worst=200):
+    """A seeded sample of cells plus the `worst` cells by degeneracy score
+    (thin cells, faces nearly through the generator, tiny edges)."""
+    import numpy as np
+
+    from paper_2410_15227_amd import workloads
+    g = np.random.default_rng(seed)
+    cells = g.choice(tess.n_cells, min(count, tess.n_cells), replace=False)
+    bad = np.argsort(workloads.degeneracy_scores(tess))[-worst:]
+    return np.unique(np.concatenate([cells, bad]))
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "exact_integral_turbulent_262144_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2410_15227_amd", "csrc", f) for f in ("exact.hip", "common.hpp")]
 
@@ -73,13 +118,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--precision", default=None, choices=["mixed", "fp64"],
+                    help="default: mixed (fp64 for --workload uniform)")
     ap.add_argument("--n", type=int, default=262144)
     ap.add_argument("--cpu-sample", type=int, default=30000, help="cells of the oracle CPU baseline (about 10-15 s)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=3, help="timed steps of the plain binary64 path")
-    ap.add_argument("--workload", default="turbulent", choices=["turbulent", "pseudo", "batch", "serve", "voronoi"],
-                    help="turbulent: the 262,144-particle cloud (default); pseudo: 1,048,576 particles collapsed "
+    ap.add_argument("--workload", default="turbulent",
+                    choices=["turbulent", "uniform", "pseudo", "batch", "serve", "voronoi"],
+                    help="turbulent: the 262,144-particle cloud (default); uniform: 4,096 uniform particles on the "
+                         "plain binary64 path with the oracle over every cell; pseudo: 1,048,576 particles collapsed "
                          "to tree-node pseudo-particles around the densest particle, mapped on the mixed set's grid; "
                          "batch: 64 independent instances of 2^12..2^18 particles in one batched call; "
                          "serve: Poisson arrivals of mapping jobs through the continuous-batching server")
@@ -93,6 +141,9 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
+    args.precision_given = args.precision
+    if args.precision is None:
+        args.precision = "mixed"
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is designed but not a measured path", file=sys.stderr)
@@ -113,8 +164,18 @@ def main():
     from paper_2410_15227_amd import workloads
 
     t0 = time.time()
-    wl = workloads.turbulent(args.n, seed=2)
-    log(f"inputs: turbulent_{args.n} built in {time.time() - t0:.1f}s "
+    if args.workload == "uniform":
+        # 4,096 uniform particles, the plain binary64 path, the oracle over every cell
+        args.n = 4096
+        if args.precision_given is None:
+            args.precision = "fp64"
+        args.cpu_sample = max(args.cpu_sample, 4096)
+        wl = workloads.uniform_4096(seed=1)
+        workload = "uniform_4096"
+    else:
+        wl = workloads.turbulent(args.n, seed=2)
+        workload = f"turbulent_{args.n}"
+    log(f"inputs: {workload} built in {time.time() - t0:.1f}s "
         f"(faces={wl.tess.n_faces}, h range {wl.h.min():.2e}..{wl.h.max():.2e})")
     ctx = pkg.Context(0)
     dev = ctx.device
@@ -166,21 +227,10 @@ def main():
     ms_step = el * 1e3 / args.steps
     value = n_pairs * args.steps / el
 
-    per_eval = FLOP_PIECE if args.precision == "mixed" else FLOP_FD
-    flop = (FLOP_FACE_TEST * ctr[1] + FLOP_FACE_INT * ctr[2] + FLOP_EDGE_VISIT * ctr[3] + FLOP_EDGE_INT * ctr[4]
-            + per_eval * (ctr[5] + ctr[6]))
-    flop_per_pair = flop / max(n_pairs, 1)
     # the integral is one launch of the main kernel plus, on the mixed path,
     # one launch over the pairs left to binary64 geometry
     redo_ms, redo_n = ctx.kernel_time("exact_redo")
     k_avg_s = (k_ms / max(k_n, 1) + redo_ms / max(redo_n, 1)) / 1e3
-    achieved = flop / k_avg_s / 1e12 if k_avg_s > 0 else 0.0
-    workload = f"turbulent_{args.n}"
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_TFLOPS, 4), "traffic": measured_traffic(args.precision, workload),
-                "kernel": "exact_integral" + (" (k_exact_edges + k_exact_mixed_list)" if args.precision == "mixed"
-                                              else " (k_exact_fp64)"),
-                "kernel_ms": round(k_avg_s * 1e3, 4), "flop_per_pair": round(flop_per_pair, 1)}
 
     # the plain binary64 path on the same GPU and inputs, for comparison
     fp64 = None
@@ -215,19 +265,59 @@ def main():
         del src, dst
 
     cpu = None
+    hist = None
     if not args.no_cpu and args.cpu_sample > 0:
         from oracle import oracle
-        g = np.random.default_rng(99)
-        cells = np.sort(g.choice(C, args.cpu_sample, replace=False))
+        full = args.cpu_sample >= C
+        cells = np.arange(C) if full else baseline_cells(wl.tess, args.cpu_sample, 99)
         t0 = time.perf_counter()
         Mref, _, npairs = oracle.map_cells(wl.tess, wl.pos, wl.h, wl.m, cells)
         cpu_s = time.perf_counter() - t0
         Mg = mass.cpu().numpy()[cells]
+        rel = np.abs(Mg - Mref) / Mref
+        worst = np.argsort(workloads.degeneracy_scores(wl.tess))[-200:]
+        in_worst = np.isin(cells, worst)
         cpu = {"value": round(float(npairs.sum()) / cpu_s, 1), "unit": "pair integrals/s",
-               "cores": oracle.threads(), "kind": "oracle",
-               "sample": f"{args.cpu_sample} seeded cells of turbulent_{args.n} ({int(npairs.sum())} pairs, "
-                         f"brute-force pair test over all particles, {cpu_s:.1f}s)",
-               "max_rel_mass_err_vs_gpu": float(np.max(np.abs(Mg - Mref) / Mref))}
+               "cores": oracle.threads(), "cpu_model": cpu_model(), "kind": "oracle",
+               "sample": (f"all {C} cells" if full else
+                          f"{args.cpu_sample} seeded cells + the 200 most degenerate (thinnest, shortest-edged)")
+                         + f" of {workload} ({len(cells)} cells, {int(npairs.sum())} pairs, brute-force pair test "
+                           f"over all particles, {cpu_s:.1f}s; pairs/s on the sample, not extrapolated)",
+               "max_rel_mass_err_vs_gpu": float(np.max(rel)),
+               "max_rel_mass_err_vs_gpu_degenerate_cells": float(np.max(rel[in_worst])) if in_worst.any() else None}
+        # the method's work on the same cells, from exact geometry
+        hist = oracle.work_counts(wl.tess, wl.pos, wl.h, cells)
+
+    # roofline of the integral: the work model over the oracle's histogram of
+    # what the method must evaluate (per pair on the sample, times the pairs
+    # of the step), next to the same model over the device's own counters
+    dev_flop, dev_trans = work_model(ctr, args.precision)
+    if hist is not None and hist[0] > 0:
+        o_flop, o_trans = work_model(hist, args.precision)
+        flop, trans = o_flop / hist[0] * n_pairs, o_trans / hist[0] * n_pairs
+        basis = "oracle histogram of the sampled cells, per pair, times the step's pairs"
+    else:
+        flop, trans = dev_flop, dev_trans
+        basis = "device work counters (no oracle sample)"
+    achieved = flop / k_avg_s / 1e12 if k_avg_s > 0 else 0.0
+    trans_rate = trans / k_avg_s / 1e12 if k_avg_s > 0 else 0.0
+    t_model = flop / (PEAK_TFLOPS * 1e12) + trans / (PEAK_TRANS * 1e12)
+    per = lambda c: [round(v / max(c[0], 1), 2) for v in c[1:]]
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_TFLOPS, 4), "traffic": measured_traffic(args.precision, workload),
+                "frac_vs_packed_fp32_peak": round(achieved / PEAK_TFLOPS_PACKED, 4),
+                "trans_achieved_Tops": round(trans_rate, 3), "trans_peak_Tops": PEAK_TRANS,
+                "frac_flop_plus_trans": round(t_model / k_avg_s, 4) if k_avg_s > 0 else 0.0,
+                "kernel": "exact_integral" + (" (k_exact_edges + k_exact_mixed_list)" if args.precision == "mixed"
+                                              else " (k_exact_fp64)"),
+                "kernel_ms": round(k_avg_s * 1e3, 4), "work_basis": basis,
+                "flop_per_pair": round(flop / max(n_pairs, 1), 1), "trans_per_pair": round(trans / max(n_pairs, 1), 1),
+                "device_flop_per_pair": round(dev_flop / max(n_pairs, 1), 1),
+                "device_trans_per_pair": round(dev_trans / max(n_pairs, 1), 1),
+                "per_pair_counts_order": ["faces", "faces reached", "edges visited", "edges integrated",
+                                          "inner pieces", "outer pieces"],
+                "oracle_counts_per_pair": per(hist) if hist is not None else None,
+                "device_counts_per_pair": per(ctr[:7])}
 
     out = {
         "metric": "particle-cell pair integrals/s",
@@ -243,7 +333,8 @@ def main():
         "dtype": "f32+f64" if args.precision == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": workload, "n_particles": args.n, "n_cells": C,
-                   "n_pairs": int(n_pairs), "precision": args.precision, "sigma_lnrho": 1.5,
+                   "n_pairs": int(n_pairs), "precision": args.precision,
+                   "cloud": "uniform" if args.workload == "uniform" else "log-normal, sigma_lnrho = 1.5",
                    "tess_upload_ms": round(tess_ms, 2)},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -362,6 +453,74 @@ def run_pseudo(args):
     tot_mix = float(res_mix.mass.sum().item())
     tot_all = float(res_all.mass.sum().item())
     step_s = build_s + mix_s + interp_s
+
+    # accuracy cost of the pseudo-particles: the cell density each grid gives
+    # at 200,000 shared random points (the cell holding a point is the one of
+    # its nearest site), mixed set against all particles, raw and with the
+    # masses normalised by coverage (sum_c M_c = sum_i m_i on both grids)
+    from scipy.spatial import cKDTree
+    pts = np.random.default_rng(31).random((200000, 3))
+    cell_mix = cKDTree(sites_mix.cpu().numpy()).query(pts)[1]
+    cell_all = cKDTree(sites_all.cpu().numpy()).query(pts)[1]
+    acc = {}
+    for norm in (False, True):
+        rm = pkg.map_particles_to_cells(ctx, dt_mix, mix_xyz, mix_hd, mix_md, precision=args.precision,
+                                        normalize=norm)
+        ra = pkg.map_particles_to_cells(ctx, dt_all, xyz, hd, md, precision=args.precision, normalize=norm)
+        dm = rm.density.cpu().numpy()[cell_mix]
+        da = ra.density.cpu().numpy()[cell_all]
+        rel = np.abs(dm - da) / da
+        acc["normalized" if norm else "raw"] = {
+            "mass_on_grid": {"mixed": float(rm.mass.sum().item()), "all": float(ra.mass.sum().item())},
+            "density_rel_err_vs_all_particles": {"median": round(float(np.median(rel)), 5),
+                                                 "p90": round(float(np.percentile(rel, 90)), 5),
+                                                 "p99": round(float(np.percentile(rel, 99)), 5)}}
+    # roofline of the mixed-set mapping's Exact integral
+    ctx.set_counting(True)
+    rc = pkg.map_particles_to_cells(ctx, dt_mix, mix_xyz, mix_hd, mix_md, precision=args.precision)
+    torch.cuda.synchronize()
+    ctr = ctx.work_counters()
+    ctx.set_counting(False)
+    ctx.reset_timing()
+    ctx.set_timing(True)
+    for _ in range(3):
+        pkg.map_particles_to_cells(ctx, dt_mix, mix_xyz, mix_hd, mix_md, precision=args.precision)
+    torch.cuda.synchronize()
+    k_ms, k_n = ctx.kernel_time("exact_integral")
+    r_ms, r_n = ctx.kernel_time("exact_redo")
+    ctx.set_timing(False)
+    k_s = (k_ms / max(k_n, 1) + r_ms / max(r_n, 1)) / 1e3
+    cpu = None
+    hist = None
+    if not args.no_cpu:
+        from oracle import oracle
+        tmix = dt_mix.export()
+        cells = baseline_cells(tmix, 2000, 99)
+        t0 = time.perf_counter()
+        Mref, _, npairs = oracle.map_cells(tmix, mix_pos, mix_h, mix_m, cells)
+        cpu_s = time.perf_counter() - t0
+        Mg = rc.mass.cpu().numpy()[cells]
+        hist = oracle.work_counts(tmix, mix_pos, mix_h, cells)
+        cpu = {"value": round(float(npairs.sum()) / cpu_s, 1), "unit": "pair integrals/s", "cores": oracle.threads(),
+               "cpu_model": cpu_model(), "kind": "oracle",
+               "sample": f"2000 seeded cells + the 200 most degenerate of the mixed set's grid ({len(cells)} cells, "
+                         f"{int(npairs.sum())} pairs, brute-force pair test over all {n_mix} entries, {cpu_s:.1f}s; "
+                         f"pairs/s on the sample)",
+               "max_rel_mass_err_vs_gpu": float(np.max(np.abs(Mg - Mref) / Mref))}
+    if hist is not None and hist[0] > 0:
+        fl, tr = work_model(hist, args.precision)
+        flop, trans = fl / hist[0] * pairs_mix, tr / hist[0] * pairs_mix
+        basis = "oracle histogram of the sampled cells, per pair, times the mapping's pairs"
+    else:
+        flop, trans = work_model(ctr, args.precision)
+        basis = "device work counters"
+    ach = flop / k_s / 1e12
+    roofline = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / PEAK_TFLOPS, 4), "traffic": None,
+                "frac_vs_packed_fp32_peak": round(ach / PEAK_TFLOPS_PACKED, 4),
+                "trans_achieved_Tops": round(trans / k_s / 1e12, 3), "trans_peak_Tops": PEAK_TRANS,
+                "kernel": "exact_integral of the mixed-set mapping", "kernel_ms": round(k_s * 1e3, 4),
+                "work_basis": basis, "flop_per_pair": round(flop / max(pairs_mix, 1), 1)}
     out = {
         "metric": "particle-cell pair integrals/s",
         "value": round(pairs_mix / mix_s, 1),
@@ -391,7 +550,10 @@ def run_pseudo(args):
                                                        "interpolated": round(gap_interp, 6)},
                    "speedup_vs_all_particles": round(all_s / step_s, 3),
                    "mass_mixed_grid": tot_mix, "mass_all_grid": tot_all,
+                   "accuracy_vs_all_particles": acc,
                    "device_voronoi_ms": {"mixed": round(vor_mix_s * 1e3, 2), "all": round(vor_all_s * 1e3, 2)}},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     dt_mix.free()
@@ -499,11 +661,12 @@ def run_voronoi(args):
 def run_batch(args):
     """64 independent mapping instances (sizes round(2^U(12,18)), uniform or
     turbulent clouds with probability 1/2, seeds 4000 + k), each with its own
-    Voronoi grid.  One timed step = the batched forward mapping of all
-    instances (one persistent Exact launch, launch shape autotuned during the
-    warm-up) + the inverse mapping of one cell field per instance.  The same
-    work as 64 single calls, and the batch in plain binary64, are timed
-    beside it."""
+    Voronoi grid.  One timed step = the forward mapping (cell masses,
+    densities, coverages) of all 64 instances as one captured HIP graph
+    (pair search on four parallel branches, one persistent Exact launch over
+    all instances with the launch shape autotuned beforehand, transposes and
+    cell sums).  Timed beside it on the same inputs: the uncaptured batched
+    call, 64 single calls, and the batch in plain binary64."""
     import numpy as np
     import torch
 
@@ -525,93 +688,79 @@ def run_batch(args):
     xs = [torch.tensor(p, dtype=torch.float64, device=dev) for (p, _, _, _) in inst]
     hs = [torch.tensor(h, dtype=torch.float64, device=dev) for (_, h, _, _) in inst]
     ms = [torch.tensor(m, dtype=torch.float64, device=dev) for (_, _, m, _) in inst]
-    qs = [torch.ones(t.n_cells, dtype=torch.float64, device=dev) for (_, _, _, t) in inst]
 
     def batched(precision=args.precision):
-        res = pkg.map_particles_to_cells_batch(ctx, dts, xs, hs, ms, precision=precision, keep_pairs=True)
-        for r, q in zip(res, qs):
-            pkg.map_cells_to_particles(ctx, r.pairs, q)
-        return res
+        return pkg.map_particles_to_cells_batch(ctx, dts, xs, hs, ms, precision=precision)
 
     def singles():
-        out = []
-        for dt, x, h, m, q in zip(dts, xs, hs, ms, qs):
-            r = pkg.map_particles_to_cells(ctx, dt, x, h, m, precision=args.precision, keep_pairs=True)
-            pkg.map_cells_to_particles(ctx, r.pairs, q)
-            out.append(r)
-        return out
+        return [pkg.map_particles_to_cells(ctx, dt, x, h, m, precision=args.precision)
+                for dt, x, h, m in zip(dts, xs, hs, ms)]
 
-    def free(res):
-        for r in res:
-            r.pairs.free()
-
-    ctx.set_autotune(True)
-    for _ in range(max(1, args.warmup)):
-        free(batched())
-    ctx.set_autotune(False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        res = batched()
-        if _ != args.steps - 1:
-            free(res)
-    torch.cuda.synchronize()
-    el = (time.perf_counter() - t0) / args.steps
-    n_pairs = sum(r.pairs.n_pairs for r in res)
-    mass_b = [r.mass.clone() for r in res]
-    free(res)
-    shape = ctx.tuned_shape(n_pairs)
-    free(singles())
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(max(1, args.steps // 2)):
-        res1 = singles()
-        free(res1)
-    torch.cuda.synchronize()
-    el1 = (time.perf_counter() - t0) / max(1, args.steps // 2)
-    same = all(bool(torch.equal(a.mass, b)) for a, b in zip(res1, mass_b))
-    fp64 = None
-    if args.fp64_steps > 0 and args.precision == "mixed":
-        free(batched("fp64"))
+    def timed(fn, steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.fp64_steps):
-            r64 = batched("fp64")
-            if _ != args.fp64_steps - 1:
-                free(r64)
+        out = None
+        for _ in range(steps):
+            out = fn()
         torch.cuda.synchronize()
-        el64 = (time.perf_counter() - t0) / args.fp64_steps
+        return (time.perf_counter() - t0) / steps, out
+
+    # the launch shape of the one Exact launch is tuned on the uncaptured call
+    ctx.set_autotune(True)
+    for _ in range(max(1, args.warmup)):
+        batched()
+    ctx.set_autotune(False)
+    el_b, res_b = timed(batched, args.steps)
+    mass_b = [r.mass.clone() for r in res_b]
+    # the graph
+    t0 = time.perf_counter()
+    plan = pkg.BatchPlan(ctx, dts, xs, hs, ms)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    for _ in range(max(1, args.warmup)):
+        plan.run()
+    el_g, _ = timed(plan.run, args.steps)
+    counts, overflow = plan.check()
+    n_pairs = int(sum(counts))
+    same_graph = (not overflow) and all(bool(torch.equal(a, b)) for a, b in zip(plan.mass, mass_b))
+    plan.free()
+    singles()
+    el_1, res_1 = timed(singles, max(1, args.steps // 2))
+    same = all(bool(torch.equal(a.mass, b)) for a, b in zip(res_1, mass_b))
+    shape = ctx.tuned_shape(n_pairs)
+    fp64 = None
+    if args.fp64_steps > 0 and args.precision == "mixed":
+        batched("fp64")
+        el64, r64 = timed(lambda: batched("fp64"), args.fp64_steps)
         rel = max(float(((a - r.mass).abs() / r.mass.abs().clamp_min(1e-300)).max().item())
                   for a, r in zip(mass_b, r64))
-        free(r64)
         fp64 = {"value": round(n_pairs / el64, 1), "unit": "pairs/s", "ms_per_step": round(el64 * 1e3, 3),
-                "mixed_speedup": round(el64 / el, 3), "max_rel_cell_mass_diff_mixed_vs_fp64": rel}
+                "mixed_speedup": round(el64 / el_g, 3), "max_rel_cell_mass_diff_mixed_vs_fp64": rel}
     out = {
         "metric": "particle-cell pair integrals/s",
-        "value": round(n_pairs / el, 1),
+        "value": round(n_pairs / el_g, 1),
         "unit": "pairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(el * 1e3, 3),
+        "ms_per_step": round(el_g * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64" if args.precision == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": "batch_64", "instances": len(mix), "n_particles": n_tot, "n_pairs": int(n_pairs),
+        "config": {"workload": "batch_64_graph", "instances": len(mix), "n_particles": n_tot, "n_pairs": n_pairs,
                    "sizes": "round(2^U(12,18))", "precision": args.precision},
-        "batch": {"singles_ms_per_step": round(el1 * 1e3, 3), "batch_speedup_vs_singles": round(el1 / el, 3),
-                  "same_masses_as_singles": same,
+        "batch": {"graph_ms_per_step": round(el_g * 1e3, 3), "uncaptured_batch_ms_per_step": round(el_b * 1e3, 3),
+                  "singles_ms_per_step": round(el_1 * 1e3, 3), "graph_speedup_vs_singles": round(el_1 / el_g, 3),
+                  "graph_speedup_vs_uncaptured": round(el_b / el_g, 3), "plan_build_s": round(plan_s, 2),
+                  "graph_same_masses_as_batch": same_graph, "singles_same_masses_as_batch": same,
                   "tuned_shape": None if shape is None else {"blocks_per_cu": shape[0], "chunks_per_fetch": shape[1],
                                                               "ms": round(shape[2], 3)},
                   "host_inputs_s": round(host_s, 1)},
         "fp64_path": fp64,
     }
     print(json.dumps(out), flush=True)
-    for dt in dts:
-        dt.free()
-    ctx.close()
 
 
 def run_serve(args):

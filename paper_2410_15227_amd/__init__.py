@@ -553,7 +553,8 @@ def interpolate_to_particles(ctx: Context, xyz, ps: dict, values, stream=None, o
 
 
 def adaptive_pseudo_particles(ctx: Context, xyz, h, m, sources, cell_fneu, K: float, max_iter: int = 16,
-                              precision: str = "mixed", n_lloyd: int = 5, **walk) -> tuple:
+                              precision: str = "mixed", n_lloyd: int = 5, leaf_remedy: str = "open",
+                              **walk) -> tuple:
     """The adaptive tree walk of Sec. 2.4.1.  Each iteration builds the
     pseudo-particles with every node that has failed so far opened, builds the
     Voronoi grid of the mixed set on the device (n_lloyd Lloyd iterations,
@@ -561,26 +562,59 @@ def adaptive_pseudo_particles(ctx: Context, xyz, h, m, sources, cell_fneu, K: fl
     (the radiative transfer's output; here any cell field), maps it back onto
     the entries (map_cells_to_particles of the forward mapping's weights) and
     checks eq. resol_param; it stops when no pseudo-particle is
-    under-resolved.  Returns (final build, history); the build also holds the
-    entries' 'fneu' and the labels it 'opened'."""
+    under-resolved.  A failed pseudo-particle that is a leaf cannot be
+    resolved further: leaf_remedy "open" opens it into its particles (they are
+    never checked); "grow" is the paper's remedy, which instead increases
+    r_part (and r_leaf by as much) until that leaf lies inside it, so that
+    every node within the new radius is emitted at particle level.  Returns
+    (final build, history); the build also holds the entries' 'fneu', the
+    labels it 'opened' and the final 'r_part' and 'r_leaf'."""
     import numpy as np
 
+    if leaf_remedy not in ("open", "grow"):
+        raise ValueError("leaf_remedy must be 'open' or 'grow'")
+    src = np.asarray(sources, dtype=np.float64).reshape(-1, 3)
+    walk = dict(walk)
+    walk.setdefault("r_part", 0.2)
+    if walk.get("tree", "octree") == "kd":
+        walk.setdefault("r_leaf", walk["r_part"])
+        leaf_below = walk.get("leaf_split", 10)  # a k-d leaf holds fewer than leaf_split
+    else:
+        leaf_below = walk.get("leaf_max", 8) + 1  # an octree leaf holds at most leaf_max
     opened = np.zeros(0, dtype=np.uint64)
     history = []
     for it in range(max_iter):
-        ps = build_pseudo_particles(ctx, xyz, h, m, sources, open_labels=opened, **walk)
+        ps = build_pseudo_particles(ctx, xyz, h, m, src, open_labels=opened, **walk)
         dt, sites = build_voronoi(ctx, ps["xyz"], n_lloyd=n_lloyd)
         res = map_particles_to_cells(ctx, dt, ps["xyz"], ps["h"], ps["m"], precision=precision, keep_pairs=True)
         f_cells = np.asarray(cell_fneu(sites.cpu().numpy()), dtype=np.float64)
         fneu = map_cells_to_particles(ctx, res.pairs, f_cells)
         bad = select_underresolved(ctx, ps, fneu, K)
         history.append(dict(iteration=it, n_entries=int(ps["kind"].shape[0]), n_pseudo=ps["stats"]["n_pseudo"],
-                            n_pairs=res.pairs.n_pairs, n_failed=int(len(bad))))
+                            n_pairs=res.pairs.n_pairs, n_failed=int(len(bad)), r_part=walk["r_part"]))
         res.pairs.free()
         dt.free()
         ps["fneu"] = fneu
         ps["opened"] = opened
+        ps["r_part"] = walk["r_part"]
+        ps["r_leaf"] = walk.get("r_leaf", walk["r_part"])
         if len(bad) == 0:
             return ps, history
+        if leaf_remedy == "grow":
+            lab = ps["label"].cpu().numpy().view(np.uint64)
+            cnt = ps["count"].cpu().numpy()
+            leaf = np.isin(lab, bad) & (cnt < leaf_below) & (ps["kind"].cpu().numpy() == 1)
+            if leaf.any():
+                pos_l = ps["xyz"].cpu().numpy()[leaf]
+                s_l = ps["s"].cpu().numpy()[leaf]
+                # a node reaches r_part when r - s <= r_part for some source
+                r = np.min(np.linalg.norm(pos_l[:, None, :] - src[None, :, :], axis=2), axis=1)
+                grow = float(np.max(r - s_l)) * (1.0 + 1e-12) + 1e-15
+                if grow > walk["r_part"]:
+                    d = grow - walk["r_part"]
+                    walk["r_part"] = grow
+                    if "r_leaf" in walk:
+                        walk["r_leaf"] = walk["r_leaf"] + d
+                bad = np.setdiff1d(bad, lab[leaf])
         opened = np.union1d(opened, bad)
     return ps, history

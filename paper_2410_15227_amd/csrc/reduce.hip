@@ -30,11 +30,26 @@ __global__ void __launch_bounds__(256) k_cell_mass(int64_t C, const int64_t *off
   if (c >= C) return;
   const int64_t s = off[c], e = off[c + 1];
   double acc = 0.0;
-  for (int64_t k = s + lane; k < e; k += 64) {
-    const int32_t i = pair_p[k];
-    double mi = m[i];
-    if (cov) mi = cov[i] > 0.0 ? mi / cov[i] : 0.0;
-    acc += mi * w[k];
+  // four turns of the lane's loop at a time: their index and weight loads,
+  // then their mass gathers, are in flight together; the additions keep the
+  // lane's order
+  for (int64_t k0 = s + lane; k0 < e; k0 += 256) {
+    int32_t i[4];
+    double wk[4], mi[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t k = k0 + 64 * j;
+      i[j] = k < e ? pair_p[k] : 0;
+      wk[j] = k < e ? w[k] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      mi[j] = m[i[j]];
+      if (cov) mi[j] = cov[i[j]] > 0.0 ? mi[j] / cov[i[j]] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (k0 + 64 * j < e) acc += mi[j] * wk[j];
   }
   acc = wave_sum(acc);
   if (lane == 0) {
@@ -66,7 +81,15 @@ __global__ void __launch_bounds__(256) k_coverage(int64_t N, const int64_t *poff
   if (i >= N) return;
   const int64_t s = poff[i], e = poff[i + 1];
   double acc = 0.0;
-  for (int64_t j = s + lane; j < e; j += 64) acc += pm_w[j];
+  // four turns' loads in flight together; the additions keep the lane's order
+  for (int64_t j0 = s + lane; j0 < e; j0 += 256) {
+    double v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = j0 + 64 * q < e ? pm_w[j0 + 64 * q] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (j0 + 64 * q < e) acc += v[q];
+  }
   acc = wave_sum(acc);
   if (lane == 0) cov[i] = acc;
 }

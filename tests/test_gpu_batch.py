@@ -134,3 +134,45 @@ def test_graph_plan(ctx, instances):
     plan.free()
     for dt in dts:
         dt.free()
+
+
+def test_batch_mix_subset_against_oracle(ctx, workloads, oracle):
+    """Eight instances of the 64-instance batch mix (round(2^U(12,18))
+    particles, uniform or turbulent, seeds 4000 + k), one of them above 2^17
+    particles: the captured graph, the uncaptured batch and the single calls
+    give the same masses bit for bit, and sampled cells of every instance
+    (30 seeded plus the 10 most degenerate) match the oracle within 1e-5."""
+    import paper_2410_15227_amd as pkg
+    mix = workloads.batch_mix(64, 4000, 12, 18)
+    big = next(k for k, (n, _, _) in enumerate(mix) if n >= (1 << 17))
+    rest = [k for k in np.random.default_rng(5).permutation(len(mix)) if k != big and mix[k][0] < (1 << 16)][:7]
+    pick = [big] + sorted(rest)
+    say(f"case: batch mix subset {[mix[k] for k in pick]}")
+    inst = []
+    for k in pick:
+        n, kind, seed = mix[k]
+        pos, m, h, rho = workloads.make_cloud(kind, n, seed)
+        inst.append((pos, h, m, workloads.voronoi(pos)))
+    dts = [pkg.DeviceTessellation(ctx, t) for (_, _, _, t) in inst]
+    xs = [torch.tensor(i[0], device="cuda") for i in inst]
+    hs = [torch.tensor(i[1], device="cuda") for i in inst]
+    ms = [torch.tensor(i[2], device="cuda") for i in inst]
+    plan = pkg.BatchPlan(ctx, dts, xs, hs, ms)
+    plan.run()
+    counts, over = plan.check()
+    assert not over
+    batch = pkg.map_particles_to_cells_batch(ctx, dts, xs, hs, ms)
+    for k, (dt, x, h, m) in enumerate(zip(dts, xs, hs, ms)):
+        single = pkg.map_particles_to_cells(ctx, dt, x, h, m)
+        assert torch.equal(plan.mass[k], batch[k].mass) and torch.equal(plan.mass[k], single.mass), k
+    for k, (pos, h, m, t) in enumerate(inst):
+        g = np.random.default_rng(100 + k)
+        cells = np.unique(np.concatenate([g.choice(t.n_cells, 30, replace=False),
+                                          np.argsort(workloads.degeneracy_scores(t))[-10:]]))
+        Mref, _, _ = oracle.map_cells(t, pos, h, m, cells)
+        rel = np.abs(plan.mass[k].cpu().numpy()[cells] - Mref) / Mref
+        say(f"  instance {pick[k]} n={len(pos)} pairs={counts[k]} max_rel={rel.max():.2e}")
+        assert rel.max() < 1e-5
+    plan.free()
+    for dt in dts:
+        dt.free()

@@ -292,10 +292,13 @@ def test_turbulent_262144_sampled(ctx, c2, oracle, precision):
     gm = res.mass.cpu().numpy()
     g = np.random.default_rng(12)
     cells = np.sort(g.choice(c2.tess.n_cells, 160, replace=False))
-    # plus the cells with the most pairs and the smallest / largest volumes
+    # plus the cells with the most pairs, the smallest / largest volumes and
+    # the 200 most degenerate (thinnest, shortest-edged) cells
     npairs = np.diff(goff)
     vol = dt.cell_info()[0].cpu().numpy()
-    extra = np.concatenate([np.argsort(npairs)[-20:], np.argsort(vol)[:10], np.argsort(vol)[-10:]])
+    from paper_2410_15227_amd.workloads import degeneracy_scores
+    extra = np.concatenate([np.argsort(npairs)[-20:], np.argsort(vol)[:10], np.argsort(vol)[-10:],
+                            np.argsort(degeneracy_scores(c2.tess))[-200:]])
     cells = np.unique(np.concatenate([cells, extra]))
     off, idx, w = oracle.pairs_weights(c2.tess, c2.pos, c2.h, cells)
     Mref = np.add.reduceat(c2.m[idx] * w, off[:-1])
@@ -303,12 +306,15 @@ def test_turbulent_262144_sampled(ctx, c2, oracle, precision):
         assert np.array_equal(gidx[goff[c]:goff[c + 1]], idx[off[k]:off[k + 1]]), c
     gws = np.concatenate([gw[goff[c]:goff[c + 1]] for c in cells])
     rel = np.abs(gm[cells] - Mref) / Mref
+    say(f"  pairs={int(goff[-1])} cells={len(cells)} max_rel={np.max(rel):.3e} max|dw|={np.max(np.abs(gws - w)):.3e}")
     if precision == "fp64":
         assert np.max(np.abs(gws - w)) < 1e-12
         assert np.max(rel) < 1e-10
     else:
+        # per pair: binary32 edge geometry (relative 6e-8 of the vertex
+        # coordinates, a few h) moves a weight by at most a few 1e-7
+        assert np.max(np.abs(gws - w)) < 1e-6
         assert np.max(rel) < 1e-5
-    say(f"  pairs={int(goff[-1])} max_rel={np.max(rel):.3e}")
     # whole-grid properties: mass is lost only through the walls
     tot = gm.sum()
     assert 0.95 < tot <= 1.0 + 1e-9
