@@ -38,7 +38,9 @@
 //     coefficients, angles' combination and
 //     every accumulation in binary64.  Edges whose foot point nearly touches
 //     the edge line or whose face plane nearly touches the particle (p or |d|
-//     below 1e-4 h) are recomputed from binary64 geometry.
+//     below 1e-4 h) are recomputed from binary64 geometry; every pair whose
+//     cell is small against the support (R_c < 0.25 h) takes the binary64
+//     path.
 #include <algorithm>
 #include <vector>
 #include <cstdlib>
@@ -327,6 +329,7 @@ __device__ double face_fp64(const double4 pl, double dist, double ih, double xr0
 struct ExactInst {
   const int32_t *pair_c, *pair_p;
   const double *xyz, *hh, *gen;
+  const float *radius;  // binary32 bounding radius R_c of each cell
   const int64_t *cfo, *fvo;
   const double4 *fplane, *fsphere;
   const float4 *fplane32, *fvpos32, *edgeA, *edgeE, *edgeM;
@@ -406,6 +409,13 @@ __global__ void __launch_bounds__(256) k_exact_fp64(int64_t P, const int32_t *pa
 
 // ---------------------------------------------------------- mixed kernel
 constexpr float kDegenerate = 1e-4f;  // p or |d| below this (units of h): binary64 edge
+// A cell smaller than this fraction of h (R_c < 0.25 h) is evaluated as on
+// the binary64 path (binary64 geometry and functions): its faces are small
+// and, seen from a particle far out in the support, their terms cancel far
+// below the mixed path's absolute accuracy (about 1e-8 of w), which matters
+// where a heavy entry grazes a light cell (a pseudo-particle's support over
+// the small cells of the particles near a source).
+constexpr double kSmallCell = 0.25;
 
 // Face f's share of sum_f sgn(d_f) C_f for the pair whose particle sits at
 // xr about the generator (x in units of h, binary32), with the face's part of
@@ -413,7 +423,8 @@ constexpr float kDegenerate = 1e-4f;  // p or |d| below this (units of h): binar
 __device__ inline double face_mixed(int64_t f, double xr0, double xr1, double xr2, double h, double ih, float ihf,
                                     float x0, float x1, float x2, const int64_t *fvo, const double4 *fplane,
                                     const float4 *fplane32, const double4 *fsphere, const double *fvpos,
-                                    const float4 *fvpos32, bool &inside, bool &on_boundary, Counters &K) {
+                                    const float4 *fvpos32, bool &inside, bool &on_boundary, Counters &K,
+                                    bool geo64) {
   const double4 pl = fplane[f];
   if (!(pl.w > 0.0)) return 0.0;
   const double dist = pl.w - (pl.x * xr0 + pl.y * xr1 + pl.z * xr2);
@@ -431,6 +442,13 @@ __device__ inline double face_mixed(int64_t f, double xr0, double xr1, double xr
   const int64_t vs = fvo[f];
   const int nv = (int)(fvo[f + 1] - vs);
   const double d = dist * ih, ad = fabs(d);
+  if (geo64) {
+    // a cell small against the support: binary64 geometry and the math
+    // library's functions (the per-endpoint form's differences of a small
+    // face seen from afar cancel far below the binary32 cores' accuracy)
+    K.n64 += nv;
+    return face_fp64<Math64>(pl, dist, ih, xr0, xr1, xr2, fvpos + 3 * vs, nv, K.ne_vis, K.ne_int, K.fd);
+  }
   if (ad < kDegenerate) {
     // particle on the face plane to within 1e-4 h: the whole face from binary64 geometry
     K.n64 += nv;
@@ -728,11 +746,12 @@ __global__ void __launch_bounds__(256) k_exact_mixed_list(const int64_t *list, c
     double acc = 0.0;
     bool inside = true, on_boundary = false;
     Counters K;
+    const bool geo64 = (double)I.radius[c] < kSmallCell * h;
     const int64_t f0 = I.cfo[c], f1 = I.cfo[c + 1];
     for (int64_t fb = f0; fb < f1; fb += 16) {
       const int64_t f = fb + sub;
       share[grp][sub] = f < f1 ? face_mixed(f, xr0, xr1, xr2, h, ih, ihf, x0, x1, x2, I.fvo, I.fplane, I.fplane32,
-                                            I.fsphere, I.fvpos, I.fvpos32, inside, on_boundary, K)
+                                            I.fsphere, I.fvpos, I.fvpos32, inside, on_boundary, K, geo64)
                                : 0.0;
       wave_sync();
       if (sub == 0) {
@@ -971,6 +990,7 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
       f1 = cfo[c + 1];
       nfaces += f1 - f0;
       if (f1 - f0 > kMaxFaces) again = true;
+      if ((double)((gptr<float>)I.radius)[c] < kSmallCell * h) again = true;  // binary64 geometry
     }
     for (int64_t wb = F0; wb < F1; wb += 64) {
       {
@@ -1319,8 +1339,8 @@ void exact_integral_batch(Ctx &ctx, const std::vector<ExactJob> &jobs, int preci
     const TessDev &t = *jobs[k].t;
     const PartDev &p = *jobs[k].p;
     const PairsDev &P = *jobs[k].P;
-    host[k] = ExactInst{P.pair_c, P.pair_p, p.xyz, p.h, t.gen, t.cell_face_off, t.face_vtx_off, t.fplane, t.fsphere,
-                        t.fplane32, t.fvpos32, t.edgeA, t.edgeE, t.edgeM, t.fvpos, P.w, P.n_pairs};
+    host[k] = ExactInst{P.pair_c, P.pair_p, p.xyz, p.h, t.gen, t.radius, t.cell_face_off, t.face_vtx_off, t.fplane,
+                        t.fsphere, t.fplane32, t.fvpos32, t.edgeA, t.edgeE, t.edgeM, t.fvpos, P.w, P.n_pairs};
     c0[k + 1] = c0[k] + div_up(P.n_pairs, 64);
   }
   ExactInst *d_inst = ctx.arena.get<ExactInst>("flat_insts", n_inst);
@@ -1391,8 +1411,8 @@ void exact_table_upload(Ctx &ctx, const std::vector<ExactJob> &jobs, ExactTable 
     const TessDev &t = *jobs[k].t;
     const PartDev &p = *jobs[k].p;
     const PairsDev &P = *jobs[k].P;
-    host[k] = ExactInst{P.pair_c, P.pair_p, p.xyz, p.h, t.gen, t.cell_face_off, t.face_vtx_off, t.fplane, t.fsphere,
-                        t.fplane32, t.fvpos32, t.edgeA, t.edgeE, t.edgeM, t.fvpos, P.w, 0};
+    host[k] = ExactInst{P.pair_c, P.pair_p, p.xyz, p.h, t.gen, t.radius, t.cell_face_off, t.face_vtx_off, t.fplane,
+                        t.fsphere, t.fplane32, t.fvpos32, t.edgeA, t.edgeE, t.edgeM, t.fvpos, P.w, 0};
     np[k] = P.d_np;
   }
   SPH_HIP(hipMemcpyAsync(tab.insts, host.data(), n_inst * sizeof(ExactInst), hipMemcpyHostToDevice, s));

@@ -171,3 +171,61 @@ def test_adaptive_walk_converges(ctx, oracle, workloads):
     f = ps["fneu"].cpu().numpy()
     assert len(oracle.underresolved(ref["kind"], ref["label"], ref["s"], f, ref["s_root"], K)) == 0
     assert abs(g["m"].sum() - m.sum()) < 1e-11 * m.sum()
+
+
+def test_turbulent_1m_mixed_set_mapping(ctx, oracle, workloads):
+    """The 1,048,576-particle cloud's mixed set (pseudo-particles around the
+    densest particle, r_part 0.2, theta 0.5) mapped onto the Voronoi grid of
+    its own positions built on the device: sampled cells (100 seeded plus
+    the 20 most degenerate) against the oracle's mapping of the same entries
+    on the exported grid, within 1e-5."""
+    import paper_2410_15227_amd as pkg
+    say("case: mixed set of turbulent 1048576 mapped on its device grid")
+    pos, m, h, rho = workloads.make_cloud("turbulent", 1 << 20, seed=3)
+    src = pos[workloads.densest_particle(rho)][None, :]
+    ps = pkg.build_pseudo_particles(ctx, pos, h, m, src, r_part=0.2, theta=0.5)
+    mx, mh, mm = (ps[k].cpu().numpy() for k in ("xyz", "h", "m"))
+    dt, _ = pkg.build_voronoi(ctx, ps["xyz"], n_lloyd=0)
+    res = pkg.map_particles_to_cells(ctx, dt, ps["xyz"], ps["h"], ps["m"], precision="mixed")
+    got = res.mass.cpu().numpy()
+    t = dt.export()
+    g = np.random.default_rng(17)
+    cells = np.unique(np.concatenate([g.choice(t.n_cells, 100, replace=False),
+                                      np.argsort(workloads.degeneracy_scores(t))[-20:]]))
+    Mref, _, npairs = oracle.map_cells(t, mx, mh, mm, cells)
+    rel = np.abs(got[cells] - Mref) / Mref
+    say(f"  entries={len(mm)} cells={len(cells)} pairs={int(npairs.sum())} max_rel={rel.max():.2e}")
+    assert rel.max() < 1e-5
+    dt.free()
+
+
+def test_adaptive_walk_grow_remedy(ctx, oracle, workloads):
+    """The paper's remedy for leaves that fail the resolution check (Sec.
+    2.4.1): r_part grows until the failed leaves lie inside it, instead of
+    opening them one by one.  The loop ends with no under-resolved
+    pseudo-particle, r_part has grown, and the final set is the oracle's walk
+    with the grown r_part and the same nodes opened."""
+    import paper_2410_15227_amd as pkg
+    say("case: adaptive walk with r_part growth, turbulent 20000")
+    pos, m, h, rho = workloads.make_cloud("turbulent", 20000, seed=43)
+    c = pos[workloads.densest_particle(rho)]
+
+    def cell_fneu(gen):
+        r = np.linalg.norm(gen - c, axis=1)
+        return 0.5 * (1.0 + np.tanh((r - 0.25) / 0.02))
+
+    K = 300.0
+    ps, hist = pkg.adaptive_pseudo_particles(ctx, pos, h, m, c[None, :], cell_fneu, K, max_iter=24,
+                                             leaf_remedy="grow", r_part=0.05, theta=0.5)
+    for row in hist:
+        say(f"  {row}")
+    assert hist[-1]["n_failed"] == 0
+    assert ps["r_part"] > 0.05
+    ref, g, st = compare(ctx, oracle, pos, m, h, c[None, :], r_part=ps["r_part"], theta=0.5,
+                         open_labels=ps["opened"])
+    f = ps["fneu"].cpu().numpy()
+    assert len(oracle.underresolved(ref["kind"], ref["label"], ref["s"], f, ref["s_root"], K)) == 0
+    # every particle within the grown r_part is emitted as itself
+    real = set(ref["first"][ref["kind"] == 0].tolist())
+    inside = np.flatnonzero(np.linalg.norm(pos - c, axis=1) < ps["r_part"])
+    assert set(inside.tolist()) <= real
