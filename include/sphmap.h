@@ -149,6 +149,25 @@ int sphmap_tess_free(sphmap_ctx *ctx, sphmap_tess *tess);
 int sphmap_tess_cell_info(sphmap_ctx *ctx, const sphmap_tess *tess, double *d_volume, float *d_radius,
                           void *stream);
 
+/* Declare, for an uploaded grid, the cell on the other side of each face:
+   h_face_nbr [n_faces] (host), a cell index or any negative value for a wall
+   or an unknown neighbour.  A face is treated as shared when the cell it
+   names declares a face back to it with the same bounding sphere (centre and
+   radius, to 1e-9 of the radius) and the opposite normal -- one polygon seen
+   from two cells.  Its term of the Exact sum w = S - sum_f sgn(d_f) C_f
+   (Sec. 1, the analytic volume integral; C_f depends on the polygon and the
+   particle only) is then evaluated once per particle, by the lower-numbered
+   cell, and given to the other with the opposite sign (mixed precision
+   only; the binary64 path evaluates every face from its own side).  Other
+   faces are evaluated from their own side.  The caller vouches that the two
+   faces of a declared pair are the same polygon (true of any Voronoi grid).
+   NULL clears the declaration.  *n_shared (nullable) receives the number of
+   shared faces.  Grids built by sphmap_tess_build_voronoi have their
+   neighbours already.  Errors: EINVAL (a neighbour >= n_cells).
+   The neighbours are also what sphmap_tess_export returns in d_face_nbr. */
+int sphmap_tess_set_face_neighbours(sphmap_ctx *ctx, sphmap_tess *tess, const int32_t *h_face_nbr, void *stream,
+                                    int64_t *n_shared);
+
 /* ------------------------------------------------------------------------
  * Voronoi grid built on the device (Sec. 2.3: the grid of the generation
  * sites, regularised by Lloyd iterations before the forward mapping).
@@ -177,8 +196,9 @@ int sphmap_tess_counts(const sphmap_tess *tess, int64_t *n_cells, int64_t *n_fac
    layout of sphmap_tess_upload: d_generators [C][3], d_vertices [V][3],
    d_cell_face_off [C+1], d_face_vtx_off [F+1], d_face_vtx [FV];
    d_face_nbr [F]: the neighbouring site of each face, -1..-6 for the box
-   planes x-, x+, y-, y+, z-, z+ (grids built by sphmap_tess_build_voronoi
-   only: EINVAL for an uploaded grid). */
+   planes x-, x+, y-, y+, z-, z+ (grids built by sphmap_tess_build_voronoi),
+   or the declared neighbours of an uploaded grid (EINVAL when none were
+   declared). */
 int sphmap_tess_export(sphmap_ctx *ctx, const sphmap_tess *tess, double *d_generators, double *d_vertices,
                        int64_t *d_cell_face_off, int64_t *d_face_vtx_off, int32_t *d_face_vtx, int32_t *d_face_nbr,
                        void *stream);

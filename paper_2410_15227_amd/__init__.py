@@ -91,8 +91,11 @@ class Context:
                                                        ctypes.byref(c)))
         return dict(held=a.value, limit=b.value, required=c.value)
 
-    def upload(self, tess, stream=None) -> "DeviceTessellation":
-        return DeviceTessellation(self, tess, stream)
+    def upload(self, tess, stream=None, neighbours: bool = True) -> "DeviceTessellation":
+        """Upload a host grid; with neighbours (default) its face_nbr, when it
+        has one, is declared (sphmap_tess_set_face_neighbours), so that the
+        mixed path evaluates each shared face once per particle."""
+        return DeviceTessellation(self, tess, stream, neighbours)
 
     # timing / counters -------------------------------------------------
     def sync_status(self, stream=None, clear: bool = True) -> int:
@@ -153,7 +156,7 @@ class Context:
 class DeviceTessellation:
     """A tessellation resident on the device (see include/sphmap.h)."""
 
-    def __init__(self, ctx: Context, tess, stream=None):
+    def __init__(self, ctx: Context, tess, stream=None, neighbours: bool = True):
         import numpy as np
         self.ctx = ctx
         self.n_cells = int(tess.n_cells)
@@ -168,12 +171,32 @@ class DeviceTessellation:
         ctx.check(L.sphmap_tess_upload(ctx.handle, self.n_cells, len(fvo) - 1, len(v), p(g), p(v), p(cfo), p(fvo),
                                        p(fv), _stream_handle(stream), ctypes.byref(h)))
         self.handle = h
+        self.n_shared = 0
+        nbr = getattr(tess, "face_nbr", None)
+        if neighbours and nbr is not None and len(nbr) == len(fvo) - 1:
+            self.set_face_neighbours(nbr, stream)
+
+    def set_face_neighbours(self, face_nbr, stream=None) -> int:
+        """Declare each face's neighbouring cell (negative: wall); None clears.
+        Returns the number of faces found shared."""
+        import numpy as np
+        n = ctypes.c_int64()
+        if face_nbr is None:
+            arg = None
+        else:
+            nb = np.ascontiguousarray(face_nbr, dtype=np.int32)
+            arg = nb.ctypes.data_as(ctypes.c_void_p)
+        self.ctx.check(_native.lib().sphmap_tess_set_face_neighbours(self.ctx.handle, self.handle, arg,
+                                                                     _stream_handle(stream), ctypes.byref(n)))
+        self.n_shared = n.value
+        return n.value
 
     @classmethod
     def _from_handle(cls, ctx: Context, handle) -> "DeviceTessellation":
         self = cls.__new__(cls)
         self.ctx = ctx
         self.handle = handle
+        self.n_shared = None  # a grid built on the device records its neighbours
         c = ctypes.c_int64()
         _native.lib().sphmap_tess_counts(handle, ctypes.byref(c), None, None, None)
         self.n_cells = c.value

@@ -22,6 +22,7 @@ EXPORTS = [
     "map_cells_to_particles", "build_pseudo_particles", "build_pseudo_particles_open", "select_underresolved",
     "interpolate_to_particles", "sphmap_sync_status", "sphmap_estimate_footprint",
     "sphmap_tess_build_voronoi", "sphmap_tess_counts", "sphmap_tess_export", "build_pseudo_particles_kd",
+    "sphmap_tess_set_face_neighbours",
     "sphmap_set_timing", "sphmap_kernel_time", "sphmap_reset_timing",
     "sphmap_set_counting", "sphmap_work_counters", "sphmap_set_autotune", "sphmap_tuned_shape",
     "sphmap_set_pool_limit", "sphmap_set_workspace_limit", "sphmap_workspace_info",
@@ -85,6 +86,8 @@ def lib():
         L.sphmap_tess_upload.argtypes = [vp, i64, i64, i64, vp, vp, vp, vp, vp, vp, pp]
         L.sphmap_tess_free.restype = ctypes.c_int
         L.sphmap_tess_free.argtypes = [vp, vp]
+        L.sphmap_tess_set_face_neighbours.restype = ctypes.c_int
+        L.sphmap_tess_set_face_neighbours.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i64)]
         L.sphmap_tess_cell_info.restype = ctypes.c_int
         L.sphmap_tess_cell_info.argtypes = [vp, vp, vp, vp, vp]
         L.map_particles_to_cells.restype = ctypes.c_int

@@ -225,6 +225,28 @@ int sphmap_tess_upload(sphmap_ctx *ctx, int64_t n_cells, int64_t n_faces, int64_
   return SPHMAP_OK;
 }
 
+int sphmap_tess_set_face_neighbours(sphmap_ctx *ctx, sphmap_tess *tess, const int32_t *h_face_nbr, void *stream,
+                                    int64_t *n_shared) {
+  if (!ctx || !tess) return SPHMAP_EINVAL;
+  return guarded(ctx, [&] {
+    sphmap::TessDev &t = tess->t;
+    hipStream_t s = as_stream(stream);
+    int64_t n = 0;
+    if (!h_face_nbr) {
+      t.face_nbr = nullptr;
+      n = sphmap::tess_set_twins(ctx->c, t, nullptr, s);
+    } else {
+      for (int64_t f = 0; f < t.n_faces; ++f)
+        SPH_REQUIRE(h_face_nbr[f] < t.n_cells, SPHMAP_EINVAL, "face neighbour out of range");
+      t.face_nbr = t.mem.get<int32_t>("fnbr", std::max<int64_t>(t.n_faces, 1));
+      if (t.n_faces)
+        SPH_HIP(hipMemcpyAsync(t.face_nbr, h_face_nbr, t.n_faces * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      n = sphmap::tess_set_twins(ctx->c, t, t.face_nbr, s);
+    }
+    if (n_shared) *n_shared = n;
+  });
+}
+
 int sphmap_tess_build_voronoi(sphmap_ctx *ctx, int64_t n, const double *d_generators, const double *h_box_lo,
                               const double *h_box_hi, int32_t n_lloyd, double *d_generators_out, void *stream,
                               sphmap_tess **out) {

@@ -93,6 +93,7 @@ void enqueue_step(Ctx &ctx, BatchPlan &B, hipStream_t s) {
 }  // namespace
 
 BatchPlan::~BatchPlan() {
+  exact_table_free(tab);
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
   for (hipStream_t b : branch) (void)hipStreamDestroy(b);
@@ -157,7 +158,8 @@ void batch_plan_build(Ctx &ctx, BatchPlan &B, double headroom, hipStream_t s) {
     }
     std::vector<ExactJob> jobs(B.n_inst);
     for (int k = 0; k < B.n_inst; ++k) jobs[k] = ExactJob{B.t[k], &B.pd[k], B.P[k].get()};
-    exact_table_upload(ctx, jobs, B.tab, s);
+    B.tab.flag = B.d_flag;
+    exact_table_upload(ctx, jobs, B.tab, B.mem, headroom, s);
   }
   enqueue_step(ctx, B, s);
   SPH_HIP(hipStreamSynchronize(s));

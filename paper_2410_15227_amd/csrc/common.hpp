@@ -199,7 +199,16 @@ struct TessDev {
   float *radius = nullptr;        // [C]
   float4 *gen32 = nullptr;        // [C] fl(g), R_c in w
   int32_t *cell_order = nullptr;  // [C] cells in Morton order of the generators
-  int32_t *face_nbr = nullptr;    // [F] neighbour each face faces (grids built here)
+  int32_t *face_nbr = nullptr;    // [F] neighbour each face faces (grids built here, or declared)
+  // [F] the other cell of a face shared with it (verified), -1 otherwise;
+  // nullptr when no face is shared (every face is evaluated from its own side)
+  int32_t *face_twin = nullptr;
+  int32_t *twin_face = nullptr;   // [F] the matching face of the twin cell
+  // [F] the face's role in the mixed path: its slot among the cell's shared
+  // faces that it evaluates (>= 0), -1 evaluated for this cell only, or
+  // -2 - s when the twin evaluates it in its slot s
+  int32_t *face_code = nullptr;
+  int32_t *cell_slots = nullptr;  // [C] shared faces the cell evaluates
 };
 
 // ---------------------------------------------------------------- pairs
@@ -246,6 +255,9 @@ void iota_i32(int32_t *p, int64_t n, hipStream_t s);
 
 // ------------------------------------------------------------ launchers
 void tess_prepare(Ctx &ctx, TessDev &t, hipStream_t s);
+// face twins from each face's declared neighbour (d_nbr [F] device; nullptr
+// clears them); returns the number of shared faces
+int64_t tess_set_twins(Ctx &ctx, TessDev &t, const int32_t *d_nbr, hipStream_t s);
 
 struct PartDev {
   int64_t n;
@@ -272,10 +284,15 @@ struct ExactTable {
   void *insts = nullptr;
   int64_t *chunk0 = nullptr;
   const int64_t **np = nullptr;
+  int32_t *flag = nullptr;  // set when a step's gift slots pass their capacity
+  void *gifts = nullptr;    // the plan of the shared faces' gifts (exact.hip)
 };
 void exact_integral_batch(Ctx &ctx, const std::vector<ExactJob> &jobs, int precision, hipStream_t s,
                           const ExactTable *tab = nullptr);
-void exact_table_upload(Ctx &ctx, const std::vector<ExactJob> &jobs, ExactTable &tab, hipStream_t s);
+// gift buffers from `mem` (held with the plan); headroom as for the pair lists
+void exact_table_upload(Ctx &ctx, const std::vector<ExactJob> &jobs, ExactTable &tab, Arena &mem, double headroom,
+                        hipStream_t s);
+void exact_table_free(ExactTable &tab);
 size_t exact_inst_bytes();
 
 // A batch of forward mappings captured as one HIP graph (batch.hip).

@@ -336,7 +336,40 @@ struct ExactInst {
   const double *fvpos;
   double *w;
   int64_t P;
+  // shared faces (mixed path; all null when the grid has none, and in a
+  // device-counted batch): the pair lists' cell offsets; each face's code
+  // (its slot among the shared faces its cell evaluates, -1 a face of this
+  // cell only, -2 the twin's); per cell the number of those slots and where
+  // its gifts start; the gifts, slot-major per cell (slot s of the cell's
+  // pair t at gbase[c] + s n_c + t: the fixed-point total of that face for
+  // that pair); each pair's state after the edge kernel
+  const int64_t *cell_off;
+  const int32_t *fcode, *cslots, *ftwin;
+  const int64_t *gbase;
+  long long *gift;
+  uint8_t *wflag;  // bit 0: S (inside); bit 1: left to the redo kernel
 };
+constexpr uint8_t kFlagInside = 1, kFlagRedo = 2;
+
+// v in units of 2^-46, rounded to nearest, as a two's-complement 64-bit
+// integer, for |v| < 32 (every term is an angle weighted by at most 1 in
+// magnitude).  With 1.5 * 2^52 added, v * 2^46 is rounded once, to an
+// integer, and lies in [2^52, 2^53) where the binary64 spacing is 1, so
+// subtracting the constant's bit pattern from the result's leaves that
+// integer.
+constexpr double kFixMagic = 0x1.8p52;
+// the integer left in t = fma(x, y, kFixMagic), for |x y| < 2^51
+__device__ inline unsigned long long fixed_from(double t) {
+  return (unsigned long long)__double_as_longlong(t) - (unsigned long long)__double_as_longlong(kFixMagic);
+}
+__device__ inline unsigned long long to_fixed(double v) { return fixed_from(fma(v, 0x1p46, kFixMagic)); }
+
+__device__ inline double from_fixed(unsigned long long a) {
+  const int hi = (int)(a >> 32);
+  const unsigned lo = (unsigned)a;
+  return ((double)hi * 0x1p32 + (double)lo) * 0x1p-46;
+}
+
 
 // instance holding global chunk `chunk` (chunk0: first chunk of each
 // instance, ascending, n_inst + 1 entries)
@@ -655,58 +688,45 @@ __device__ inline Coef coef_mix(double ad, double p, double w0, double w1) {
   return c;
 }
 
-// F(cb) - F(ca) of one edge within 2h (p > 0, tA < tB) whose clipped range
-// stays in one regime: one piece.
-__device__ inline double fan_one(double ad, double p, double tA, double tB, EdgeCount &cnt) {
+// One piece of an edge within 2h (p > 0, tA < tB), its range clipped to
+// U <= 2.  Mode 0: the whole clipped range, in the regime of its midpoint.
+// A range that crosses t = -t1 or t = +t1 (U = 1) is evaluated as two
+// items: mode 1 its first piece and mode 2 its second -- split at the
+// crossing, or, across both crossings, the outer coefficients over the
+// whole range (mode 1) plus 2 (F_inner - F_outer) over [0, t1] (mode 2;
+// both antiderivatives are odd in t).  When rounding at the join loses the
+// crossing, mode 1 takes the whole range and mode 2 adds nothing.
+__device__ inline double piece_of(double ad, double p, double tA, double tB, int mode, EdgeCount &cnt) {
   const double a2 = ad * ad + p * p;
   const double t2 = sqrt_mixed(4.0 - a2);
   const double ca = fmin(fmax(tA, -t2), t2), cb = fmin(fmax(tB, -t2), t2);
-  const double Ua = (fabs(ca) == t2) ? 2.0 : sqrt_mixed(fma(ca, ca, a2));
-  const double Ub = (fabs(cb) == t2) ? 2.0 : sqrt_mixed(fma(cb, cb, a2));
-  const double mid = 0.5 * (ca + cb);
-  const bool outer = !(mid * mid < 1.0 - a2);
-  cnt.n0 += !outer;
-  cnt.n1 += outer;
-  return piece(coef_mix(ad, p, outer ? 0.0 : 1.0, outer ? 1.0 : 0.0), ad, p, a2, ca, Ua, cb, Ub);
-}
-
-// The same for a clipped range that crosses t = -t1 or t = +t1 (U = 1):
-// two pieces split at the crossing; across both, the outer coefficients
-// over the whole range plus 2 (F_inner - F_outer) over [0, t1] (odd in t).
-__device__ inline double fan_two(double ad, double p, double tA, double tB, EdgeCount &cnt) {
-  const double a2 = ad * ad + p * p;
-  const double t2 = sqrt_mixed(4.0 - a2);
-  const double ca = fmin(fmax(tA, -t2), t2), cb = fmin(fmax(tB, -t2), t2);
-  const double Ua = (fabs(ca) == t2) ? 2.0 : sqrt_mixed(fma(ca, ca, a2));
-  const double Ub = (fabs(cb) == t2) ? 2.0 : sqrt_mixed(fma(cb, cb, a2));
   const bool in = a2 < 1.0;  // an inner regime exists
   const double t1 = in ? sqrt_mixed(1.0 - a2) : 0.0;
   const bool lo = in && ca < -t1 && cb > -t1, hi = in && ca < t1 && cb > t1;
-  const bool both = lo && hi;
-  // first piece: [ca, s] (or [ca, cb] when both crossings are inside)
+  const bool both = lo && hi, one = mode == 0 || (!lo && !hi);
+  const bool m2 = mode == 2 && !one, m1 = !one && !m2;
   const double s = lo ? -t1 : t1;
-  const bool one = !lo && !hi;  // no crossing after all (rounding at the join)
+  const double u = m2 ? (both ? 0.0 : s) : ca;
+  const double v = one ? cb : (m2 ? (both ? t1 : cb) : (both ? cb : s));
+  // U at the ends: 1 at a crossing, 2 at a clipped end, else from the root
+  const bool u_split = m2 && !both, v_split = (m1 && !both) || (m2 && both);
+  const double Uu = u_split ? 1.0 : (fabs(u) == t2 ? 2.0 : sqrt_mixed(fma(u, u, a2)));
+  const double Uv = v_split ? 1.0 : (fabs(v) == t2 ? 2.0 : sqrt_mixed(fma(v, v, a2)));
+  // regime weights: (1, 0) inner, (0, 1) outer, (2, -2) twice their difference
   const double mid = 0.5 * (ca + cb);
-  const bool outer1 = both || lo || (one && !(mid * mid < 1.0 - a2));
-  const double v1 = (both || one) ? cb : s, V1 = (both || one) ? Ub : 1.0;
-  double r = piece(coef_mix(ad, p, outer1 ? 0.0 : 1.0, outer1 ? 1.0 : 0.0), ad, p, a2, ca, Ua, v1, V1);
-  // second piece: [s, cb], or [0, t1] with 2 (inner - outer)
-  if (!one) {
-    const double w0 = both ? 2.0 : (lo ? 1.0 : 0.0), w1 = both ? -2.0 : (lo ? 0.0 : 1.0);
-    const double u2 = both ? 0.0 : s, W2 = both ? sqrt_mixed(a2) : 1.0;
-    const double v2 = both ? t1 : cb, V2 = both ? 1.0 : Ub;
-    r += piece(coef_mix(ad, p, w0, w1), ad, p, a2, u2, W2, v2, V2);
-    cnt.n0 += w0 != 0.0;
-    cnt.n1 += w0 == 0.0;
-  }
-  cnt.n0 += !outer1;
-  cnt.n1 += outer1;
-  return r;
+  const bool outer = one ? !(mid * mid < 1.0 - a2) : (m1 ? (both || lo) : (!both && !lo));
+  const double w0 = (m2 && both) ? 2.0 : (outer ? 0.0 : 1.0);
+  const double w1 = (m2 && both) ? -2.0 : (outer ? 1.0 : 0.0);
+  const bool none = mode == 2 && one;
+  cnt.n0 += !none && w0 != 0.0;
+  cnt.n1 += !none && w0 == 0.0;
+  const double r = piece(coef_mix(ad, p, w0, w1), ad, p, a2, u, Uu, v, Uv);
+  return none ? 0.0 : r;
 }
 
-__device__ inline double item_value(const float4 it, bool two, EdgeCount &cnt) {
+__device__ inline double item_value(const float4 it, int mode, EdgeCount &cnt) {
   const double ad = (double)fabsf(it.x), p = (double)fabsf(it.y), tA = (double)it.z, tB = (double)it.w;
-  const double v = two ? fan_two(ad, p, tA, tB, cnt) : fan_one(ad, p, tA, tB, cnt);
+  const double v = piece_of(ad, p, tA, tB, mode, cnt);
   return ((it.x < 0.0f) != (it.y < 0.0f)) ? -v : v;
 }
 
@@ -750,9 +770,19 @@ __global__ void __launch_bounds__(256) k_exact_mixed_list(const int64_t *list, c
     const int64_t f0 = I.cfo[c], f1 = I.cfo[c + 1];
     for (int64_t fb = f0; fb < f1; fb += 16) {
       const int64_t f = fb + sub;
-      share[grp][sub] = f < f1 ? face_mixed(f, xr0, xr1, xr2, h, ih, ihf, x0, x1, x2, I.fvo, I.fplane, I.fplane32,
-                                            I.fsphere, I.fvpos, I.fvpos32, inside, on_boundary, K, geo64)
-                               : 0.0;
+      const double v = f < f1 ? face_mixed(f, xr0, xr1, xr2, h, ih, ihf, x0, x1, x2, I.fvo, I.fplane, I.fplane32,
+                                           I.fsphere, I.fvpos, I.fvpos32, inside, on_boundary, K, geo64)
+                              : 0.0;
+      share[grp][sub] = v;
+      // a shared face this cell evaluates: its gift to the twin pair (same
+      // particle, twin cell), replacing the edge kernel's
+      if (I.gift && f < f1) {
+        const int32_t sl = I.fcode[f];
+        if (sl >= 0) {
+          const int64_t cb = I.cell_off[c], nc = I.cell_off[c + 1] - cb;
+          I.gift[I.gbase[c] + (int64_t)sl * nc + (k - cb)] = (long long)to_fixed(4.0 * kPi * v);
+        }
+      }
       wave_sync();
       if (sub == 0) {
         const int m = (int)min((int64_t)16, f1 - fb);
@@ -769,6 +799,133 @@ __global__ void __launch_bounds__(256) k_exact_mixed_list(const int64_t *list, c
       I.w[k] = S - acc;
     }
     if (counters) flush_counters(counters, sub == 0 ? f1 - f0 : 0, K);
+  }
+}
+
+// Gift slots of each cell: its pairs times the shared faces it evaluates.
+__global__ void k_gift_sizes(int64_t C, const int64_t *coff, const int32_t *cslots, int64_t *sz) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < C) sz[c] = (coff[c + 1] - coff[c]) * (int64_t)cslots[c];
+}
+
+// the number of set bits of m in the lanes below this one
+__device__ inline int mbcnt64(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+// A device-counted batch: gifts on while the instance's slots fit the
+// capacity planned for them; else off (its faces are then evaluated from
+// each side) and the plan flagged.
+__global__ void k_gift_check(ExactInst *inst, const int64_t *total, int64_t cap, long long *gift, int32_t *flag) {
+  if (threadIdx.x != 0) return;
+  const bool fits = *total <= cap;
+  inst->gift = fits ? gift : nullptr;
+  if (!fits) *flag = 1;
+}
+
+// w = S - (own + received) / (4 pi) for every pair the edge kernel kept:
+// its own total waits in w as a 64-bit integer until here.  One wavefront
+// per cell takes its pairs kGatherW at a time (their particles in LDS).  The
+// faces of the cell that a twin evaluates are listed first, with the twin's
+// list and the face's gift run (both contiguous); their rows are then read
+// kGatherU blocks of 64 at a time (loads in flight together), and each gift
+// goes, with the opposite sign, to the pair of this cell with the same
+// particle (bisection in LDS).  Integer sums: the order does not matter.
+constexpr int kGatherW = 256;
+constexpr int kGatherWaves = 4;
+constexpr int kGatherU = 4;
+__global__ void __launch_bounds__(64 * kGatherWaves) k_exact_gather(const ExactInst *__restrict__ insts, int ins,
+                                                                    int64_t C) {
+  __shared__ int32_t pl_[kGatherWaves][kGatherW];
+  __shared__ unsigned long long ga_[kGatherWaves][kGatherW];
+  __shared__ int64_t fcb_[kGatherWaves][64], fgs_[kGatherWaves][64];
+  __shared__ int32_t fnc_[kGatherWaves][64];
+  const ExactInst &I = insts[ins];
+  if (!I.gift) return;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int32_t *const pl = pl_[wid];
+  unsigned long long *const ga = ga_[wid];
+  int64_t *const fcb = fcb_[wid], *const fgs = fgs_[wid];
+  int32_t *const fnc = fnc_[wid];
+  const int64_t *coff = I.cell_off;
+  const int32_t *pair_p = I.pair_p;
+  for (int64_t cp = (int64_t)blockIdx.x * kGatherWaves + wid; cp < C; cp += (int64_t)gridDim.x * kGatherWaves) {
+    const int64_t b = coff[cp], n = coff[cp + 1] - b;
+    const int64_t f0 = I.cfo[cp], nf = I.cfo[cp + 1] - f0;
+    for (int64_t w0 = 0; w0 < n; w0 += kGatherW) {
+      const int m = (int)min((int64_t)kGatherW, n - w0);
+      for (int l = lane; l < m; l += 64) {
+        pl[l] = pair_p[b + w0 + l];
+        ga[l] = 0ull;
+      }
+      wave_sync();
+      const int32_t i_lo = pl[0], i_hi = pl[m - 1];
+      for (int64_t fw = 0; fw < nf; fw += 64) {
+        const int64_t f = f0 + fw + lane;
+        const int code = fw + lane < nf ? I.fcode[f] : 0;
+        const bool inc = code <= -2;
+        const uint64_t mk = __ballot(inc);
+        if (inc) {
+          const int pos = mbcnt64(mk);
+          const int64_t tc = I.ftwin[f];
+          const int64_t cb = coff[tc], nc = coff[tc + 1] - cb;
+          fcb[pos] = cb;
+          fnc[pos] = (int32_t)nc;
+          fgs[pos] = I.gbase[tc] + (int64_t)(-2 - code) * nc;
+        }
+        const int nin = __popcll(mk);
+        wave_sync();
+        int j = 0, r = 0;  // next block: rows [64 r, 64 r + 64) of face j's run
+        while (j < nin) {
+          int64_t gs[kGatherU], cb[kGatherU];
+          bool uv[kGatherU];
+#pragma unroll
+          for (int u = 0; u < kGatherU; ++u) {
+            const int64_t t = 64 * (int64_t)r + lane;
+            uv[u] = j < nin && t < fnc[min(j, nin - 1)];
+            gs[u] = j < nin ? fgs[j] + t : 0;
+            cb[u] = j < nin ? fcb[j] + t : 0;
+            if (j < nin) {
+              if (64 * (r + 1) < fnc[j]) {
+                ++r;
+              } else {
+                ++j;
+                r = 0;
+              }
+            }
+          }
+          long long T[kGatherU];
+          int32_t ip[kGatherU];
+#pragma unroll
+          for (int u = 0; u < kGatherU; ++u) {
+            T[u] = uv[u] ? I.gift[gs[u]] : 0;
+            ip[u] = uv[u] ? pair_p[cb[u]] : 0;
+          }
+#pragma unroll
+          for (int u = 0; u < kGatherU; ++u) {
+            if (T[u] != 0 && ip[u] >= i_lo && ip[u] <= i_hi) {
+              int lo = 0, hi = m;
+              while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (pl[mid] < ip[u]) lo = mid + 1;
+                else hi = mid;
+              }
+              if (lo < m && pl[lo] == ip[u]) atomicAdd(&ga[lo], (unsigned long long)(-T[u]));
+            }
+          }
+        }
+        wave_sync();
+      }
+      for (int l = lane; l < m; l += 64) {
+        const int64_t jj = b + w0 + l;
+        const uint8_t fl = I.wflag[jj];
+        if (!(fl & kFlagRedo)) {
+          const unsigned long long tot = (unsigned long long)__double_as_longlong(I.w[jj]) + ga[l];
+          I.w[jj] = ((fl & kFlagInside) ? 1.0 : 0.0) - kInv4Pi * from_fixed(tot);
+        }
+      }
+      wave_sync();
+    }
   }
 }
 
@@ -795,7 +952,9 @@ __global__ void __launch_bounds__(256) k_exact_mixed_list(const int64_t *list, c
 constexpr int kMaxFaces = 64;              // faces per cell handled here
 constexpr int kEntryCap = 64 * kMaxFaces;  // face entries per chunk
 constexpr int kEdgeCap = 256;              // candidate edges per pair handled here
-constexpr int kQueue = 128;                // items per LDS queue
+constexpr int kQueue = 192;                // items in the LDS queue (a batch adds at most 128)
+constexpr int kRing = 128;                 // face records whose sums are open at once
+static_assert(kEntryCap <= 4096, "an item names its record in 12 bits");
 
 struct __align__(16) FaceRec {  // a face within reach of a pair
   float px, py, pz;  // foot point about the generator (absolute units)
@@ -819,24 +978,32 @@ struct Sphere {
 };
 
 struct EdgeWave {  // per-wavefront LDS
-  double4 wpl[64];  // window of the chunk's faces: plane
+  union {
+    double4 wpl[64];  // cull and face list: window of the chunk's faces: plane
+    struct {          // edge walk: each pair's gift run (start and stride)
+      long long gb[64], gn[64];
+    };
+  };
   union {
     Sphere wsp[64];               // cull: the window's bounding spheres
     unsigned long long sb[kEdgeCap];  // edge walk: bit g set where a face's edges start (64 kEdgeCap bits)
   };
-  // cull and face list: the window's first vertex slot and vertex count (at
-  // most 128); after the face list, each pair's first face record and its
-  // number of records
+  // cull and face list: the window's first vertex slot, twin cell (-1: none)
+  // and vertex count (at most 128)
   int wvs[64];
+  int wtw[64];
   unsigned char wnv[64];
-  unsigned long long acc[64];
-  float4 qD[kQueue], qN[kQueue];
-  unsigned char oD[kQueue], oN[kQueue];
-  unsigned char redo[64];    // the pair is left to the redo kernel
-  unsigned char hasint[64];  // some edge of the pair comes within 2h
-  // bit r set when an edge of face record r has its foot point outside
-  // (p < 0): the record's foot point then lies outside its polygon
-  unsigned long long nin[kEntryCap / 64];
+  unsigned long long acc[64];  // per pair: the total of its own face records
+  // items: edge data, and the record (bits 0-11) and mode (bits 12-13)
+  float4 q[kQueue];
+  uint16_t o[kQueue];
+  // open face records, slot r mod kRing: the fixed-point sum of record r's
+  // terms, whether an edge of it comes within 2h, and whether an edge sees
+  // its foot point on the outer side (p < 0: the foot point lies outside
+  // the polygon)
+  unsigned long long racc[kRing];
+  unsigned char rint[kRing], rnin[kRing];
+  unsigned char redo[64];  // the pair is left to the redo kernel
 };
 
 template <typename T>
@@ -878,10 +1045,6 @@ __device__ inline FaceRec load_rec(gptr<FaceRec> base, int rec) {
   return r;
 }
 
-// the number of set bits of m in the lanes below this one
-__device__ inline int mbcnt64(uint64_t m) {
-  return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-}
 
 __device__ inline uint64_t lanes_in(int lo, int hi) {  // bits [lo, hi), 0 <= lo <= hi <= 64
   const uint64_t a = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
@@ -889,56 +1052,52 @@ __device__ inline uint64_t lanes_in(int lo, int hi) {  // bits [lo, hi), 0 <= lo
   return a & ~b;
 }
 
-// v in units of 2^-46, rounded to nearest, as a two's-complement 64-bit
-// integer, for |v| < 32 (every term is an angle weighted by at most 1 in
-// magnitude).  With 1.5 * 2^52 added, v * 2^46 is rounded once, to an
-// integer, and lies in [2^52, 2^53) where the binary64 spacing is 1, so
-// subtracting the constant's bit pattern from the result's leaves that
-// integer.
-constexpr double kFixMagic = 0x1.8p52;
-// the integer left in t = fma(x, y, kFixMagic), for |x y| < 2^51
-__device__ inline unsigned long long fixed_from(double t) {
-  return (unsigned long long)__double_as_longlong(t) - (unsigned long long)__double_as_longlong(kFixMagic);
-}
-__device__ inline unsigned long long to_fixed(double v) { return fixed_from(fma(v, 0x1p46, kFixMagic)); }
-
-__device__ inline double from_fixed(unsigned long long a) {
-  const int hi = (int)(a >> 32);
-  const unsigned lo = (unsigned)a;
-  return ((double)hi * 0x1p32 + (double)lo) * 0x1p-46;
-}
-
-// Evaluate the first n (<= 64) items of a queue and add them to their pairs;
-// move the rest to the front.  Returns the new length.
-__device__ inline int drain(EdgeWave &L, float4 *q, unsigned char *o, int len, int n, bool two, int lane,
-                            EdgeCount &cnt) {
+// Evaluate the first n (<= 64) queued items and add them to their records;
+// move the rest (at most kQueue - 64) to the front.  Returns the new length.
+__device__ inline int drain(EdgeWave &L, int len, int n, int lane, EdgeCount &cnt) {
   if (lane < n) {
-    const double r = item_value(q[lane], two, cnt);
-    atomicAdd(&L.acc[o[lane]], to_fixed(r));
+    const int o = L.o[lane];
+    const double r = item_value(L.q[lane], o >> 12, cnt);
+    atomicAdd(&L.racc[o & (kRing - 1)], to_fixed(r));
   }
   const int rest = len - n;
-  if (lane < rest) {
-    const float4 it = q[n + lane];
-    const unsigned char ow = o[n + lane];
-    q[lane] = it;
-    o[lane] = ow;
+  const bool ha = lane < rest, hb = lane + 64 < rest;
+  float4 a = {}, b = {};
+  uint16_t oa = 0, ob = 0;
+  if (ha) {
+    a = L.q[n + lane];
+    oa = L.o[n + lane];
+  }
+  if (hb) {
+    b = L.q[n + 64 + lane];
+    ob = L.o[n + 64 + lane];
+  }
+  wave_sync();  // every read before any write
+  if (ha) {
+    L.q[lane] = a;
+    L.o[lane] = oa;
+  }
+  if (hb) {
+    L.q[64 + lane] = b;
+    L.o[64 + lane] = ob;
   }
   wave_sync();
   return rest;
 }
 
 template <bool kCount>
-// Four waves per SIMD (128 VGPRs; 4 workgroups of 38 KB LDS per CU): the
+// Four waves per SIMD (128 VGPRs; 4 workgroups of 39 KB LDS per CU): the
 // few values that spill are the chunk's and the fetch's, stored and reloaded
 // outside the edge walk and the queue evaluation.
 __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
-    const ExactInst *__restrict__ insts, const int64_t *__restrict__ chunk0, int n_inst, int per_fetch, int64_t *counters, FaceRec *faces,
-    int32_t *next_chunk, int64_t *redo, int32_t *n_redo) {
+    const ExactInst *__restrict__ insts, const int64_t *__restrict__ chunk0, int n_inst, int per_fetch,
+    int64_t *counters, FaceRec *faces, int32_t *rec_slot, int32_t *next_chunk, int64_t *redo, int32_t *n_redo) {
   __shared__ EdgeWave lds[kFlatWaves];
   const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   EdgeWave &L = lds[wid];
   const int64_t wave = (int64_t)blockIdx.x * kFlatWaves + wid;
   FaceRec *const fr = faces + wave * kEntryCap;
+  int32_t *const rtw = rec_slot + wave * kEntryCap;
   const int64_t n_chunks = chunk0[n_inst];
   Counters K;
   int64_t nfaces = 0;
@@ -960,6 +1119,8 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
     // global (not generic) address space: the loads then count only against
     // the vector-memory counter and never hold up waits on LDS traffic
     const gptr<float4> edgeA = (gptr<float4>)I.edgeA, edgeE = (gptr<float4>)I.edgeE, edgeM = (gptr<float4>)I.edgeM;
+    const gptr<int32_t> fcode = (gptr<int32_t>)I.fcode;
+    const bool shared = I.gift != nullptr;  // the same for the whole wave
     const int64_t P = I.P;
     const int64_t chunk = gchunk - chunk0[ins];
     const int64_t k = chunk * 64 + lane;
@@ -975,11 +1136,11 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
     uint64_t mask = 0;
     int nsurv = 0, nedge = 0;
     bool inside = true, on_boundary = false, again = false;
-    int64_t f0 = 0, f1 = 0;
+    int64_t f0 = 0, f1 = 0, c = 0;
     double xr0 = 0.0, xr1 = 0.0, xr2 = 0.0, ih = 0.0, h = 0.0;
     if (valid) {
       if (wide) again = true;
-      const int64_t c = pair_c[k];
+      c = pair_c[k];
       const int64_t i = pair_p[k];
       h = hh[i];
       ih = 1.0 / h;
@@ -1002,6 +1163,7 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
           const int64_t vs = fvo[f];
           L.wvs[lane] = (int)vs;
           L.wnv[lane] = (unsigned char)(fvo[f + 1] - vs);
+          L.wtw[lane] = shared ? fcode[f] : -1;
         }
       }
       wave_sync();
@@ -1018,7 +1180,10 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
           on_boundary |= real & (dist == 0.0);
           const double sx = xr0 - sp.x, sy = xr1 - sp.y, sz = xr2 - sp.z;
           const double reach = sp.r + 2.0 * h;
-          const bool near = real & (dist != 0.0) & (fabs(dist) < 2.0 * h) &
+          // a shared face is evaluated by the lower-numbered of its two
+          // cells, for both pairs of the particle
+          const bool mine = L.wtw[j] >= -1;
+          const bool near = real & mine & (dist != 0.0) & (fabs(dist) < 2.0 * h) &
                             (sx * sx + sy * sy + sz * sz < reach * reach);
           const bool deg = near & (fabs(dist * ih) < kDegenerate);
           if (kCount) K.n64 += deg & !again;
@@ -1038,6 +1203,18 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
         nsurv = nedge = 0;
       }
     }
+    // the pair's gift run: slot q of its cell at gbl + q gnl, each set to
+    // 0 here and to the face's total when its record closes (the redo
+    // kernel rewrites them for the pairs it recomputes)
+    long long gbl = 0, gnl = 0;
+    if (shared && valid) {
+      const gptr<int64_t> coff = (gptr<int64_t>)I.cell_off;
+      const int64_t cb = coff[c];
+      gnl = coff[c + 1] - cb;
+      gbl = ((gptr<int64_t>)I.gbase)[c] + (k - cb);
+      const int ns = ((gptr<int32_t>)I.cslots)[c];
+      for (int q = 0; q < ns; ++q) I.gift[gbl + (int64_t)q * gnl] = 0;
+    }
     const int e_off = wave_scan_excl(nsurv, lane);
     const int x_off = wave_scan_excl(nedge, lane);
     // wave-uniform counts in scalar registers (the edge walk's loop bound)
@@ -1045,8 +1222,10 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
     const int n_rec = __builtin_amdgcn_readlane(e_off + nsurv, 63);
     L.acc[lane] = 0ull;
     L.redo[lane] = again ? 1 : 0;
-    L.hasint[lane] = 0;
-    L.nin[lane] = 0ull;
+    L.racc[lane] = 0ull;
+    L.racc[lane + 64] = 0ull;
+    L.rint[lane] = L.rint[lane + 64] = 0;
+    L.rnin[lane] = L.rnin[lane + 64] = 0;
     if (kCount) K.nf_int += nsurv;
     // the start bits of the chunk's edges, n_edge <= 64 kEdgeCap of them
     for (int w = lane; w < (n_edge + 63) >> 6; w += 64) L.sb[w] = 0ull;
@@ -1062,6 +1241,7 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
             const int64_t vs = fvo[f];
             L.wvs[lane] = (int)vs;
             L.wnv[lane] = (unsigned char)(fvo[f + 1] - vs);
+            L.wtw[lane] = shared ? fcode[f] : -1;
           }
         }
         wave_sync();
@@ -1085,6 +1265,7 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
             rec.ihf = (float)ih;
             rec.slot = (uint32_t)(L.wvs[j] - VB) | ((uint32_t)lane << 24);
             fr[e] = rec;
+            if (shared) rtw[e] = L.wtw[j];  // the face's gift slot, or -1
             atomicOr(&L.sb[start >> 6], 1ull << (start & 63));
             ++e;
             start += L.wnv[j];
@@ -1094,19 +1275,63 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
       }
     }
     wave_fence();
-    L.wvs[lane] = e_off;
-    L.wnv[lane] = (unsigned char)nsurv;
-    // ---------------- A2: one edge per lane; B whenever a queue fills
-    int qD = 0, qN = 0;
+    L.gb[lane] = gbl;  // the plane window is done with
+    L.gn[lane] = gnl;
+    wave_sync();
+    // ---------------- A2: one edge per lane; B whenever the queue fills
+    int qn = 0;    // queued items
+    int done = 0;  // records below this are closed
     // the rounding constant of fixed_from in scalar registers (otherwise
     // rebuilt in vector registers for every batch)
     uint32_t magic_hi;
     asm volatile("s_mov_b32 %0, 0x43380000" : "=s"(magic_hi));
     const double magic = __hiloint2double((int)magic_hi, 0);
-    // Evaluate batch [b, b + 64) from the data d fetched for it.
-    auto batch = [&](int b, const EdgeData &d) {
+    const gptr<FaceRec> frg = (gptr<FaceRec>)fr;
+    // Close records [done, upto): each one's total -- the sum of its terms,
+    // or, when no edge of it came within 2h, its exact angle sum 2 pi [foot
+    // point inside] times its factor (a face clear of the support adds
+    // exactly 0) -- is added to its pair and, for a shared face, written to
+    // the pair's gift slot; its ring slot is cleared for reuse.
+    auto retire = [&](int upto) {
+      while (done < upto) {
+        const int r = done + lane;
+        if (r < upto) {
+          const int sl = r & (kRing - 1);
+          const FaceRec rc = load_rec(frg, r);
+          const long long T = L.rint[sl] ? (long long)L.racc[sl]
+                                         : (L.rnin[sl] ? 0ll : (long long)fixed_from(fma(rc.dhs, 2.0 * kPi, magic)));
+          const int ow = (int)(rc.slot >> 24);
+          atomicAdd(&L.acc[ow], (unsigned long long)T);
+          if (shared) {
+            const int q = rtw[r];
+            if (q >= 0) I.gift[L.gb[ow] + (int64_t)q * L.gn[ow]] = T;  // after its 0: same wave, in order
+          }
+          L.racc[sl] = 0ull;
+          L.rint[sl] = 0;
+          L.rnin[sl] = 0;
+        }
+        done = min(done + 64, upto);
+        wave_sync();
+      }
+    };
+    // Evaluate batch [b, b + 64) from the data d fetched for it; `walked`
+    // is the first record with an edge past the batch (n_rec after the last).
+    auto batch = [&](int b, const EdgeData &d, int walked) {
       const int g = b + lane;
       const bool live = g < n_edge;
+      // The batch touches records [first, last]; their ring slots must not
+      // hold records still open (an item of record r may wait in the queue):
+      // when they would, everything queued is evaluated and the records
+      // before this batch are closed first.
+      {
+        const int first = __builtin_amdgcn_readfirstlane(d.rec);
+        const int last = __builtin_amdgcn_readlane(d.rec, 63);
+        if (last >= done + kRing) {
+          while (qn > 0) qn = drain(L, qn, min(qn, 64), lane, K.fd);
+          retire(first);
+        }
+      }
+      const int sl = d.rec & (kRing - 1);
       const FaceRec &fc = d.fc;
       const float4 EA = d.ea, EE = d.ee, EM = d.em;
       // Branch-free: nearly every lane has a live edge of positive length at
@@ -1127,7 +1352,7 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
       const bool ok = act & !degen;
       // the foot point is outside the record's polygon if any edge sees it
       // on its outer side
-      if (ok & (p < 0.0f)) atomicOr(&L.nin[d.rec >> 6], 1ull << (d.rec & 63));
+      if (ok & (p < 0.0f)) L.rnin[sl] = 1;
       const float tA = -(dx * EE.x + dy * EE.y + dz * EE.z) * fc.ihf;
       const float tB = fmaf(EA.w, fc.ihf, tA);
       const double ap = (double)fabsf(p), dA = (double)tA, dB = (double)tB;
@@ -1137,7 +1362,7 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
       // factor takes the sign bit of p (p != 0 here) and feeds one fma
       const double f = __hiloint2double(__double2hiint(fc.dhs) ^ (int)(__float_as_uint(p) & 0x80000000u),
                                         __double2loint(fc.dhs));
-      if (ok) atomicAdd(&L.acc[owner], fixed_from(fma(MathMixed::span(ap, dA, dB), f, magic)));
+      if (ok) atomicAdd(&L.racc[sl], fixed_from(fma(MathMixed::span(ap, dA, dB), f, magic)));
       // within 2h somewhere on [tA, tB], and crossing U = 1 (squares, no
       // roots; bitwise logic, so that no test becomes a branch)
       const double a2 = ad * ad + ap * ap;
@@ -1151,22 +1376,28 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
         K.ne_vis += ok;
         K.ne_int += integ;
       }
+      // one item per edge within 2h, two for a range crossing U = 1
       const float4 it = make_float4(fc.df, p, tA, tB);
-      const uint64_t mD = __ballot(integ && cross), mN = __ballot(integ && !cross);
+      const uint64_t m1 = __ballot(integ), m2 = __ballot(integ && cross);
       if (integ) {
-        L.hasint[owner] = 1;
+        L.rint[sl] = 1;
         // set bits of the scalar masks below this lane, counted in hardware
-        const int pos = cross ? qD + mbcnt64(mD) : qN + mbcnt64(mN);
-        float4 *const q = cross ? L.qD : L.qN;
-        unsigned char *const o = cross ? L.oD : L.oN;
-        q[pos] = it;
-        o[pos] = (unsigned char)owner;
+        const int pos = qn + mbcnt64(m1) + mbcnt64(m2);
+        L.q[pos] = it;
+        L.o[pos] = (uint16_t)(d.rec | (cross ? 1 << 12 : 0));
+        if (cross) {
+          L.q[pos + 1] = it;
+          L.o[pos + 1] = (uint16_t)(d.rec | (2 << 12));
+        }
       }
-      qD += __popcll(mD);
-      qN += __popcll(mN);
+      qn += __popcll(m1) + __popcll(m2);
       wave_sync();
-      if (qD >= 64) qD = drain(L, L.qD, L.oD, qD, 64, true, lane, K.fd);
-      if (qN >= 64) qN = drain(L, L.qN, L.oN, qN, 64, false, lane, K.fd);
+      while (qn >= 64) qn = drain(L, qn, 64, lane, K.fd);
+      // records before both the next batch and the oldest queued item are
+      // complete: close them a full round at a time
+      int front = walked;
+      if (qn > 0) front = min(front, (int)__builtin_amdgcn_readfirstlane(L.o[0] & 0xfff));
+      if (front - done >= 64) retire(done + ((front - done) & ~63));
     };
     // Edge g of the chunk belongs to the last face record starting at or
     // before g: batch [bb, bb + 64) reads one word of start bits, and a lane
@@ -1198,7 +1429,6 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
     // the chunk's edge frames and the wave's face records from scalar bases
     // and 32-bit offsets (a chunk spans fewer than 2^24 slots, a wave holds
     // 4096 records)
-    const gptr<FaceRec> frg = (gptr<FaceRec>)fr;
     const gptr<float4> cA = edgeA + VB, cE = edgeE + VB, cM = edgeM + VB;
     auto fetch = [&](int rec, int vq, uint32_t slot, EdgeData &d) {
       d.rec = rec;
@@ -1213,12 +1443,12 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
     // into `nxt` (record and slot in r, q, sl) and the record and slot of
     // batch b + 128 are found (into rn, qn, sn).  The loop below alternates
     // the roles of the two sets, so no loaded register is copied.
-    auto turn = [&](int b, const EdgeData &cur, EdgeData &nxt, int r, int q, uint32_t sl, int &rn, int &qn,
+    auto turn = [&](int b, const EdgeData &cur, EdgeData &nxt, int r, int q, uint32_t sl, int &rn, int &qn_,
                     uint32_t &sn) {
-      locate(b + 128, rn, qn);
+      locate(b + 128, rn, qn_);
       sn = slot_of(rn);
       fetch(r, q, sl, nxt);
-      batch(b, cur);
+      batch(b, cur, b + 64 < n_edge ? __builtin_amdgcn_readfirstlane(r) : n_rec);
     };
     EdgeData dX{}, dY{};
     int rX = 0, qX = 0, rY = 0, qY = 0;
@@ -1235,26 +1465,19 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
       if (b + 64 >= n_edge) break;
       turn(b + 64, dY, dX, rY, qY, sY, rX, qX, sX);
     }
-    if (qD > 0) drain(L, L.qD, L.oD, qD, qD, true, lane, K.fd);
-    if (qN > 0) drain(L, L.qN, L.oN, qN, qN, false, lane, K.fd);
+    while (qn > 0) qn = drain(L, qn, min(qn, 64), lane, K.fd);
+    retire(n_rec);
     wave_sync();
     if (valid && !again && L.redo[lane] == 0) {
-      double wk;
-      if (L.hasint[lane]) {
-        wk = (inside ? 1.0 : 0.0) - kInv4Pi * from_fixed(L.acc[lane]);
+      if (shared) {
+        // the own total until k_exact_gather adds what the twins gave
+        I.w[k] = __longlong_as_double((long long)L.acc[lane]);
+        I.wflag[k] = inside ? kFlagInside : 0;
       } else {
-        // No edge within 2h: each face's angle terms add up to exactly
-        // 2 pi [foot point inside its polygon] times its factor, so the
-        // weight is formed from those exact sums (a support clear of every
-        // face gives exactly 0 or 1) instead of the rounded per-edge terms.
-        double sum = 0.0;
-        const int r0 = L.wvs[lane], r1 = r0 + L.wnv[lane];
-        for (int r = r0; r < r1; ++r)
-          if (!((L.nin[r >> 6] >> (r & 63)) & 1ull)) sum += load_rec(frg, r).dhs;
-        wk = (inside ? 1.0 : 0.0) - 0.5 * 0x1p-46 * sum;
+        I.w[k] = (inside ? 1.0 : 0.0) - kInv4Pi * from_fixed(L.acc[lane]);
       }
-      I.w[k] = wk;
     } else if (valid) {
+      if (shared) I.wflag[k] = kFlagRedo;
       redo[atomicAdd(n_redo, 1)] = gchunk * 64 + lane;
     }
     wave_fence();
@@ -1264,6 +1487,89 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
 }
 
 }  // namespace
+
+struct GiftPlan {
+  int64_t *gbase = nullptr, *gsize = nullptr;
+  long long *gift = nullptr;
+  uint8_t *wflag = nullptr;
+  std::vector<int64_t> gb_off, gift_off, flag_off, cap;  // per instance (-1: no gifts)
+  bool any = false;
+};
+
+// Where the gifts of shared faces go (mixed path): per instance, the start
+// of its cell offsets, gift slots and flags in one buffer each.  Instances
+// whose grid has no shared face take none.  The slot counts are read back
+// (the host knows the pair counts here); `headroom` > 0 plans capacity for
+// a device-counted batch (its counts change from step to step).
+static GiftPlan gift_plan(Ctx &ctx, Arena &mem, const std::vector<ExactJob> &jobs, bool use_cap, double headroom,
+                          hipStream_t s) {
+  GiftPlan G;
+  const int n = (int)jobs.size();
+  G.gb_off.assign(n, -1);
+  G.gift_off.assign(n, -1);
+  G.flag_off.assign(n, -1);
+  G.cap.assign(n, 0);
+  int64_t nb = 0, nf = 0;
+  for (int k = 0; k < n; ++k) {
+    const int64_t np = use_cap ? jobs[k].P->cap : jobs[k].P->n_pairs;
+    if (jobs[k].t->face_code && np > 0) {
+      G.gb_off[k] = nb;
+      G.flag_off[k] = nf;
+      nb += jobs[k].t->n_cells + 1;
+      nf += np;
+      G.any = true;
+    }
+  }
+  if (!G.any) return G;
+  G.gbase = mem.get<int64_t>("gift_base", nb);
+  G.gsize = mem.get<int64_t>("gift_size", nb);
+  G.wflag = mem.get<uint8_t>("gift_flag", nf);
+  std::vector<int64_t> tot(n, 0);
+  for (int k = 0; k < n; ++k) {
+    if (G.gb_off[k] < 0) continue;
+    const TessDev &t = *jobs[k].t;
+    k_gift_sizes<<<(unsigned)div_up(t.n_cells, 256), 256, 0, s>>>(t.n_cells, jobs[k].P->cell_off, t.cell_slots,
+                                                                  G.gsize + G.gb_off[k]);
+    SPH_LAUNCH_CHECK();
+    scan_exclusive_i64(ctx.arena, G.gsize + G.gb_off[k], G.gbase + G.gb_off[k], t.n_cells, true, s);
+    SPH_HIP(hipMemcpyAsync(&tot[k], G.gbase + G.gb_off[k] + t.n_cells, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  }
+  SPH_HIP(hipStreamSynchronize(s));
+  int64_t ng = 0;
+  for (int k = 0; k < n; ++k)
+    if (G.gb_off[k] >= 0) {
+      G.gift_off[k] = ng;
+      G.cap[k] = tot[k] + (headroom > 0.0 ? std::max<int64_t>((int64_t)((double)tot[k] * headroom), 1 << 16) : 0);
+      ng += G.cap[k];
+    }
+  G.gift = mem.get<long long>("gift", std::max<int64_t>(ng, 1));
+  return G;
+}
+
+// one instance's table entry (G: null, or the gifts of its shared faces)
+static ExactInst inst_of_job(const ExactJob &j, const GiftPlan *G, int k) {
+  const TessDev &t = *j.t;
+  const PartDev &p = *j.p;
+  const PairsDev &P = *j.P;
+  const bool sh = G && G->gb_off[k] >= 0;
+  return ExactInst{P.pair_c, P.pair_p, p.xyz, p.h, t.gen, t.radius, t.cell_face_off, t.face_vtx_off, t.fplane,
+                   t.fsphere, t.fplane32, t.fvpos32, t.edgeA, t.edgeE, t.edgeM, t.fvpos, P.w, P.n_pairs,
+                   P.cell_off, sh ? t.face_code : nullptr, sh ? t.cell_slots : nullptr, sh ? t.face_twin : nullptr,
+                   sh ? G->gbase + G->gb_off[k] : nullptr, sh ? G->gift + G->gift_off[k] : nullptr,
+                   sh ? G->wflag + G->flag_off[k] : nullptr};
+}
+
+// the gather pass of every instance with gifts (device table d_inst)
+static void launch_gather(Ctx &ctx, const std::vector<ExactJob> &jobs, const GiftPlan &G, const ExactInst *d_inst,
+                          hipStream_t s) {
+  for (int k = 0; k < (int)jobs.size(); ++k) {
+    if (G.gb_off[k] < 0) continue;
+    const int64_t C = jobs[k].t->n_cells;
+    const int64_t blocks = std::min<int64_t>(div_up(C, kGatherWaves), (int64_t)ctx.n_cu * 8);
+    k_exact_gather<<<(unsigned)blocks, 64 * kGatherWaves, 0, s>>>(d_inst, k, C);
+    SPH_LAUNCH_CHECK();
+  }
+}
 
 // Compute units and resident Exact workgroups per CU, queried once per
 // context (contexts may live on different threads).
@@ -1298,17 +1604,33 @@ void exact_integral_batch(Ctx &ctx, const std::vector<ExactJob> &jobs, int preci
       pf = it->second.per_fetch;
     }
     const int64_t grid = (int64_t)ctx.n_cu * std::min(bpc, ctx.exact_per_cu);
-    FaceRec *faces = ctx.arena.get<FaceRec>("flat_faces", grid * kFlatWaves * kEntryCap);
+    const int64_t waves = grid * kFlatWaves;
+    FaceRec *faces = ctx.arena.get<FaceRec>("flat_faces", waves * kEntryCap);
+    const GiftPlan &G = *(const GiftPlan *)tab->gifts;
+    int32_t *rtw = G.any ? ctx.arena.get<int32_t>("flat_rslot", waves * kEntryCap) : nullptr;
     int32_t *next = ctx.arena.get<int32_t>("flat_next", 2);
     int64_t *redo = ctx.arena.get<int64_t>("flat_redo", std::max<int64_t>(total, 1));
+    ExactInst *d_inst = (ExactInst *)tab->insts;
+    // gift slots from this step's pair counts, within the planned capacity
+    for (int k = 0; k < n_inst; ++k) {
+      if (G.gb_off[k] < 0) continue;
+      const TessDev &t = *jobs[k].t;
+      k_gift_sizes<<<(unsigned)div_up(t.n_cells, 256), 256, 0, s>>>(t.n_cells, jobs[k].P->cell_off, t.cell_slots,
+                                                                    G.gsize + G.gb_off[k]);
+      SPH_LAUNCH_CHECK();
+      scan_exclusive_i64(ctx.arena, G.gsize + G.gb_off[k], G.gbase + G.gb_off[k], t.n_cells, true, s);
+      k_gift_check<<<1, 64, 0, s>>>(d_inst + k, G.gbase + G.gb_off[k] + t.n_cells, G.cap[k], G.gift + G.gift_off[k],
+                                    tab->flag);
+      SPH_LAUNCH_CHECK();
+    }
     k_zero_i32<<<1, 64, 0, s>>>(next, 2);
     SPH_LAUNCH_CHECK();
-    k_exact_edges<false><<<(unsigned)grid, 64 * kFlatWaves, 0, s>>>((const ExactInst *)tab->insts, tab->chunk0, n_inst, pf, nullptr,
-                                                                   faces, next, redo, next + 1);
+    k_exact_edges<false><<<(unsigned)grid, 64 * kFlatWaves, 0, s>>>(d_inst, tab->chunk0, n_inst, pf, nullptr, faces,
+                                                                   rtw, next, redo, next + 1);
     SPH_LAUNCH_CHECK();
-    k_exact_mixed_list<<<(unsigned)(ctx.n_cu * 4), 256, 0, s>>>(redo, next + 1, (const ExactInst *)tab->insts, tab->chunk0, n_inst,
-                                                                 nullptr);
+    k_exact_mixed_list<<<(unsigned)(ctx.n_cu * 4), 256, 0, s>>>(redo, next + 1, d_inst, tab->chunk0, n_inst, nullptr);
     SPH_LAUNCH_CHECK();
+    launch_gather(ctx, jobs, G, d_inst, s);
     return;
   }
   int64_t *ctr = ctx.counting ? ctx.d_counters : nullptr;
@@ -1335,13 +1657,11 @@ void exact_integral_batch(Ctx &ctx, const std::vector<ExactJob> &jobs, int preci
   ExactInst *host = (ExactInst *)stage;
   int64_t *c0 = (int64_t *)(stage + ((n_inst * sizeof(ExactInst) + 63) & ~(size_t)63));
   c0[0] = 0;
+  const GiftPlan G = gift_plan(ctx, ctx.arena, jobs, false, 0.0, s);
+  const bool shared = G.any;
   for (int k = 0; k < n_inst; ++k) {
-    const TessDev &t = *jobs[k].t;
-    const PartDev &p = *jobs[k].p;
-    const PairsDev &P = *jobs[k].P;
-    host[k] = ExactInst{P.pair_c, P.pair_p, p.xyz, p.h, t.gen, t.radius, t.cell_face_off, t.face_vtx_off, t.fplane,
-                        t.fsphere, t.fplane32, t.fvpos32, t.edgeA, t.edgeE, t.edgeM, t.fvpos, P.w, P.n_pairs};
-    c0[k + 1] = c0[k] + div_up(P.n_pairs, 64);
+    host[k] = inst_of_job(jobs[k], &G, k);
+    c0[k + 1] = c0[k] + div_up(jobs[k].P->n_pairs, 64);
   }
   ExactInst *d_inst = ctx.arena.get<ExactInst>("flat_insts", n_inst);
   int64_t *d_c0 = ctx.arena.get<int64_t>("flat_chunk0", n_inst + 1);
@@ -1357,13 +1677,14 @@ void exact_integral_batch(Ctx &ctx, const std::vector<ExactJob> &jobs, int preci
     const int64_t grid = std::min<int64_t>((int64_t)n_cu * std::min(blocks_per_cu, per_cu), div_up(n_chunks, kFlatWaves));
     const int64_t waves = grid * kFlatWaves;
     FaceRec *faces = ctx.arena.get<FaceRec>("flat_faces", waves * kEntryCap);
+    int32_t *rtw = shared ? ctx.arena.get<int32_t>("flat_rslot", waves * kEntryCap) : nullptr;
     KernelTimer kz(&ctx, "flat_reset", s);
     k_zero_i32<<<1, 64, 0, s>>>(next, 2);
     SPH_LAUNCH_CHECK();
     kz.done();
     KernelTimer kt(&ctx, "exact_integral", s);
     (ctr ? k_exact_edges<true> : k_exact_edges<false>)<<<(unsigned)grid, 64 * kFlatWaves, 0, s>>>(
-        d_inst, d_c0, n_inst, per_fetch, ctr, faces, next, redo, next + 1);
+        d_inst, d_c0, n_inst, per_fetch, ctr, faces, rtw, next, redo, next + 1);
     SPH_LAUNCH_CHECK();
     kt.done();
   };
@@ -1400,33 +1721,53 @@ void exact_integral_batch(Ctx &ctx, const std::vector<ExactJob> &jobs, int preci
   k_exact_mixed_list<<<(unsigned)(n_cu * 4), 256, 0, s>>>(redo, next + 1, d_inst, d_c0, n_inst, ctr);
   SPH_LAUNCH_CHECK();
   kr.done();
+  if (shared) {
+    KernelTimer kg(&ctx, "exact_gather", s);
+    launch_gather(ctx, jobs, G, d_inst, s);
+    kg.done();
+  }
 }
 
 // Upload the pointer table of a device-counted batch (before capture).
-void exact_table_upload(Ctx &ctx, const std::vector<ExactJob> &jobs, ExactTable &tab, hipStream_t s) {
+void exact_table_upload(Ctx &ctx, const std::vector<ExactJob> &jobs, ExactTable &tab, Arena &mem, double headroom,
+                        hipStream_t s) {
   const int n_inst = (int)jobs.size();
   std::vector<ExactInst> host(n_inst);
   std::vector<const int64_t *> np(n_inst);
+  // gift slots planned from the planning pass's counts, with headroom; the
+  // step recounts them on the device and switches an instance's gifts off
+  // when they do not fit (k_gift_check)
+  if (!tab.gifts) tab.gifts = new GiftPlan();
+  GiftPlan &G = *(GiftPlan *)tab.gifts;
+  G = gift_plan(ctx, mem, jobs, true, std::max(headroom, 0.05), s);
   for (int k = 0; k < n_inst; ++k) {
-    const TessDev &t = *jobs[k].t;
-    const PartDev &p = *jobs[k].p;
-    const PairsDev &P = *jobs[k].P;
-    host[k] = ExactInst{P.pair_c, P.pair_p, p.xyz, p.h, t.gen, t.radius, t.cell_face_off, t.face_vtx_off, t.fplane,
-                        t.fsphere, t.fplane32, t.fvpos32, t.edgeA, t.edgeE, t.edgeM, t.fvpos, P.w, 0};
-    np[k] = P.d_np;
+    host[k] = inst_of_job(jobs[k], &G, k);
+    host[k].P = 0;
+    np[k] = jobs[k].P->d_np;
   }
   SPH_HIP(hipMemcpyAsync(tab.insts, host.data(), n_inst * sizeof(ExactInst), hipMemcpyHostToDevice, s));
   SPH_HIP(hipMemcpyAsync((void *)tab.np, np.data(), n_inst * sizeof(int64_t *), hipMemcpyHostToDevice, s));
   SPH_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
 }
 
+void exact_table_free(ExactTable &tab) {
+  delete (GiftPlan *)tab.gifts;
+  tab.gifts = nullptr;
+}
+
 size_t exact_inst_bytes() { return sizeof(ExactInst); }
+
+constexpr int64_t kGiftBound = 16;
 
 size_t exact_workspace_bytes(Ctx &ctx, int64_t n_pairs) {
   exact_occupancy(ctx);
   const int64_t grid = std::min<int64_t>((int64_t)ctx.n_cu * ctx.exact_per_cu, div_up(div_up(n_pairs, 64), kFlatWaves));
   const int64_t waves = std::max<int64_t>(grid, 1) * kFlatWaves;
-  return (size_t)(waves * kEntryCap * sizeof(FaceRec) + n_pairs * sizeof(int64_t));
+  // face records, their totals and gift slots per resident wave; per pair
+  // the redo list, the flags and its gifts (at most kGiftBound slots a pair
+  // on average: a cell evaluates about half its faces' shares)
+  return (size_t)(waves * kEntryCap * (sizeof(FaceRec) + sizeof(long long) + sizeof(int32_t)) +
+                  n_pairs * (sizeof(int64_t) + sizeof(uint8_t) + kGiftBound * sizeof(long long)));
 }
 
 void exact_integral(Ctx &ctx, const TessDev &t, const PartDev &p, PairsDev &P, int precision, hipStream_t s) {

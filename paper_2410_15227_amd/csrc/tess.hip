@@ -158,6 +158,67 @@ __global__ void k_cell_prep(int64_t C, const double *gen, const double *vert, co
   gen32[c] = make_float4((float)gx, (float)gy, (float)gz, R);
 }
 
+// Twin of each face: a face is shared when the cell it names has a face
+// naming it back, both planes are valid, the two bounding spheres agree
+// (centres in absolute coordinates and radii, to 1e-9 of the larger radius)
+// and the normals are opposite.  Such a face is one polygon seen from two
+// cells: its share of the Exact sum is the same magnitude from both sides
+// with opposite sign (Sec. 3 of the closed form: C_f depends only on the
+// polygon and the particle, the sign on the side).  twin[f] is the other
+// cell, or -1 (a wall, no declaration, or no match); twin_face[f] the
+// matching face of that cell.
+__global__ void k_face_twin(int64_t F, int64_t C, const int32_t *face_cell, const int64_t *cfo, const int32_t *nbr,
+                            const double *gen, const double4 *fplane, const double4 *fsphere, int32_t *twin,
+                            int32_t *twin_face, unsigned long long *n_shared) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  int32_t tw = -1, tf = -1;
+  const int64_t c = face_cell[f], n = nbr[f];
+  const double4 pa = fplane[f];
+  if (n >= 0 && n < C && n != c && pa.w > 0.0) {
+    const double4 sa = fsphere[f];
+    const double ax = gen[3 * c] + sa.x, ay = gen[3 * c + 1] + sa.y, az = gen[3 * c + 2] + sa.z;
+    for (int64_t g = cfo[n]; g < cfo[n + 1]; ++g) {
+      if (nbr[g] != c) continue;
+      const double4 pb = fplane[g], sb = fsphere[g];
+      const double bx = gen[3 * n] + sb.x, by = gen[3 * n + 1] + sb.y, bz = gen[3 * n + 2] + sb.z;
+      const double tol = 1e-9 * fmax(sa.w, sb.w);
+      const double dx = ax - bx, dy = ay - by, dz = az - bz;
+      if (pb.w > 0.0 && dx * dx + dy * dy + dz * dz <= tol * tol && fabs(sa.w - sb.w) <= tol &&
+          pa.x * pb.x + pa.y * pb.y + pa.z * pb.z < -1.0 + 1e-9) {
+        tw = (int32_t)n;
+        tf = (int32_t)g;
+      }
+      break;
+    }
+  }
+  twin[f] = tw;
+  twin_face[f] = tf;
+  if (tw >= 0) atomicAdd(n_shared, 1ull);
+}
+
+// Per cell: its faces' roles in the mixed path -- code[f] = the face's slot
+// among the cell's shared faces it evaluates (twin cell above it), -1 for a
+// face evaluated for this cell only (wall or unshared) -- and the number of
+// such slots.  A second pass gives each shared face the twin evaluates the
+// code -2 - (its twin's slot).
+__global__ void k_face_slots(int64_t C, const int64_t *cfo, const int32_t *twin, int32_t *code, int32_t *n_slots) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  int32_t n = 0;
+  for (int64_t f = cfo[c]; f < cfo[c + 1]; ++f) {
+    const int32_t tw = twin[f];
+    code[f] = tw < 0 ? -1 : (tw > c ? n++ : -2);
+  }
+  n_slots[c] = n;
+}
+
+__global__ void k_face_slots_in(int64_t F, const int32_t *twin_face, int32_t *code) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F || code[f] != -2) return;
+  code[f] = -2 - code[twin_face[f]];  // the twin's code is a slot (>= 0)
+}
+
 __global__ void k_particles_prep(int64_t n, const double *xyz, const double *h, float4 *x32) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -203,6 +264,41 @@ void tess_prepare(Ctx &ctx, TessDev &t, hipStream_t s) {
   SPH_HIP(hipStreamSynchronize(s));
   SPH_REQUIRE(bad_h == 0, SPHMAP_EGEOM,
               std::to_string(bad_h) + " face(s) have the generation site on their plane (site not strictly inside)");
+  // a grid built here records the neighbour of every face
+  if (t.face_nbr) tess_set_twins(ctx, t, t.face_nbr, s);
+}
+
+int64_t tess_set_twins(Ctx &ctx, TessDev &t, const int32_t *d_nbr, hipStream_t s) {
+  (void)ctx;
+  if (!d_nbr || t.n_faces == 0) {
+    t.face_twin = t.twin_face = t.face_code = t.cell_slots = nullptr;
+    return 0;
+  }
+  int32_t *tw = t.mem.get<int32_t>("ftwin", t.n_faces);
+  int32_t *tf = t.mem.get<int32_t>("ftwinf", t.n_faces);
+  int32_t *code = t.mem.get<int32_t>("fcode", t.n_faces);
+  int32_t *ns = t.mem.get<int32_t>("cslots", t.n_cells);
+  unsigned long long *cnt = t.mem.get<unsigned long long>("ftwin_n", 1);
+  SPH_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s));
+  k_face_twin<<<(unsigned)div_up(t.n_faces, 256), 256, 0, s>>>(t.n_faces, t.n_cells, t.face_cell, t.cell_face_off,
+                                                               d_nbr, t.gen, t.fplane, t.fsphere, tw, tf, cnt);
+  SPH_LAUNCH_CHECK();
+  k_face_slots<<<(unsigned)div_up(t.n_cells, 256), 256, 0, s>>>(t.n_cells, t.cell_face_off, tw, code, ns);
+  SPH_LAUNCH_CHECK();
+  k_face_slots_in<<<(unsigned)div_up(t.n_faces, 256), 256, 0, s>>>(t.n_faces, tf, code);
+  SPH_LAUNCH_CHECK();
+  unsigned long long n = 0;
+  SPH_HIP(hipMemcpyAsync(&n, cnt, sizeof(n), hipMemcpyDeviceToHost, s));
+  SPH_HIP(hipStreamSynchronize(s));
+  if (n) {
+    t.face_twin = tw;
+    t.twin_face = tf;
+    t.face_code = code;
+    t.cell_slots = ns;
+  } else {
+    t.face_twin = t.twin_face = t.face_code = t.cell_slots = nullptr;
+  }
+  return (int64_t)n;
 }
 
 void particles_prepare(Ctx &ctx, PartDev &p, hipStream_t s) {

@@ -163,9 +163,13 @@ class Tessellation:
         return out
 
     def subset(self, cells) -> "Tessellation":
-        """A tessellation holding only the listed cells (same geometry)."""
+        """A tessellation holding only the listed cells (same geometry); a
+        face's neighbour is renumbered into the subset, or -1 when it is not
+        in it."""
         cells = np.asarray(cells, dtype=np.int64)
         gens = self.generators[cells]
+        renum = np.full(self.n_cells, -1, dtype=np.int64)
+        renum[cells] = np.arange(len(cells))
         verts, fvo, fv, fnb, cfo = [], [0], [], [], [0]
         nv = 0
         for c in cells:
@@ -175,7 +179,8 @@ class Tessellation:
                 fv.append(np.arange(nv, nv + len(ids), dtype=np.int32))
                 nv += len(ids)
                 fvo.append(nv)
-                fnb.append(self.face_nbr[f])
+                nb = int(self.face_nbr[f])
+                fnb.append(int(renum[nb]) if nb >= 0 else nb)
             cfo.append(len(fnb))
         return Tessellation(
             generators=np.ascontiguousarray(gens),

@@ -123,6 +123,44 @@ def test_uniform_4096_full(ctx, c1, c1_oracle, precision):
     assert np.max(np.abs(res.coverage.cpu().numpy() - cov_ref)) < (1e-11 if precision == "fp64" else 1e-5)
 
 
+def test_shared_faces_once(ctx, c1, c1_oracle):
+    """Mixed path, faces shared by two cells: with the grid's neighbours
+    declared, the device verifies each face against its twin (same bounding
+    sphere, opposite normal), and each shared face is evaluated once per
+    particle -- by the lower-numbered cell -- and given to the twin pair with
+    the opposite sign (w = S - sum_f sgn(d_f) C_f; C_f depends on the polygon
+    and the particle only).  Against the same grid evaluated face by face from
+    each side: identical pair lists, weights within 2e-7 (two binary32 views
+    of one polygon), both within the mixed bars of the oracle; repeats are
+    bit-identical (integer sums)."""
+    import paper_2410_15227_amd as pkg
+    say("case: uniform_4096 shared faces once vs every face from its own side")
+    off, idx, w, M, vol, rad = c1_oracle
+    interior = int(np.sum(c1.tess.face_nbr >= 0))
+    dt_own = pkg.DeviceTessellation(ctx, c1.tess, neighbours=False)
+    dt_tw = pkg.DeviceTessellation(ctx, c1.tess)
+    say(f"  interior faces {interior}, shared after verification {dt_tw.n_shared}")
+    assert dt_own.n_shared == 0
+    assert interior * 0.99 <= dt_tw.n_shared <= interior
+    out = {}
+    for name, dt in (("own", dt_own), ("twin", dt_tw), ("twin2", dt_tw)):
+        res = pkg.map_particles_to_cells(ctx, dt, c1.pos, c1.h, c1.m, precision="mixed", keep_pairs=True)
+        torch.cuda.synchronize()
+        goff, gidx, gw = (t.cpu().numpy() for t in res.pairs.export())
+        assert np.array_equal(goff, off) and np.array_equal(gidx, idx)
+        out[name] = (gw, res.mass.cpu().numpy(), res.coverage.cpu().numpy())
+    cov_ref = np.bincount(idx, weights=w, minlength=len(c1.pos))
+    for name in ("own", "twin"):
+        gw, gm, cov = out[name]
+        say(f"  {name}: max|dw| {np.max(np.abs(gw - w)):.3e}  max rel dM {np.max(np.abs(gm - M) / M):.3e}  "
+            f"max|dcov| {np.max(np.abs(cov - cov_ref)):.3e}")
+        assert np.max(np.abs(gw - w)) < 1e-5
+        assert np.max(np.abs(gm - M) / M) < 1e-5
+        assert np.max(np.abs(cov - cov_ref)) < 1e-5
+    assert np.max(np.abs(out["twin"][0] - out["own"][0])) < 2e-7
+    assert np.array_equal(out["twin"][0].view(np.int64), out["twin2"][0].view(np.int64))
+
+
 def test_reverse_map(ctx, c1, c1_oracle, oracle):
     import paper_2410_15227_amd as pkg
     say("case: uniform_4096 inverse mapping")
