@@ -223,14 +223,16 @@ def main():
     ctx.set_timing(False)
     k_ms, k_n = ctx.kernel_time("exact_integral")
     other = {name: ctx.kernel_time(name) for name in ["pair_count", "pair_fill", "transpose", "cell_reduce",
-                                                     "reverse", "exact_redo", "flat_reset"]}
+                                                     "reverse", "exact_redo", "exact_gather", "flat_reset"]}
     ms_step = el * 1e3 / args.steps
     value = n_pairs * args.steps / el
 
     # the integral is one launch of the main kernel plus, on the mixed path,
-    # one launch over the pairs left to binary64 geometry
+    # one launch over the pairs left to binary64 geometry and, on a grid with
+    # shared faces, the gather of the twins' gifts
     redo_ms, redo_n = ctx.kernel_time("exact_redo")
-    k_avg_s = (k_ms / max(k_n, 1) + redo_ms / max(redo_n, 1)) / 1e3
+    gat_ms, gat_n = ctx.kernel_time("exact_gather")
+    k_avg_s = (k_ms / max(k_n, 1) + redo_ms / max(redo_n, 1) + gat_ms / max(gat_n, 1)) / 1e3
 
     # the plain binary64 path on the same GPU and inputs, for comparison
     fp64 = None
@@ -286,7 +288,7 @@ def main():
                "max_rel_mass_err_vs_gpu": float(np.max(rel)),
                "max_rel_mass_err_vs_gpu_degenerate_cells": float(np.max(rel[in_worst])) if in_worst.any() else None}
         # the method's work on the same cells, from exact geometry
-        hist = oracle.work_counts(wl.tess, wl.pos, wl.h, cells)
+        hist = oracle.work_counts(wl.tess, wl.pos, wl.h, cells, owned=bool(dt.n_shared))
 
     # roofline of the integral: the work model over the oracle's histogram of
     # what the method must evaluate (per pair on the sample, times the pairs
@@ -308,7 +310,9 @@ def main():
                 "frac_vs_packed_fp32_peak": round(achieved / PEAK_TFLOPS_PACKED, 4),
                 "trans_achieved_Tops": round(trans_rate, 3), "trans_peak_Tops": PEAK_TRANS,
                 "frac_flop_plus_trans": round(t_model / k_avg_s, 4) if k_avg_s > 0 else 0.0,
-                "kernel": "exact_integral" + (" (k_exact_edges + k_exact_mixed_list)" if args.precision == "mixed"
+                "kernel": "exact_integral" + (" (k_exact_edges + k_exact_mixed_list"
+                                              + (" + k_exact_gather)" if gat_n else ")")
+                                              if args.precision == "mixed"
                                               else " (k_exact_fp64)"),
                 "kernel_ms": round(k_avg_s * 1e3, 4), "work_basis": basis,
                 "flop_per_pair": round(flop / max(n_pairs, 1), 1), "trans_per_pair": round(trans / max(n_pairs, 1), 1),
@@ -488,8 +492,9 @@ def run_pseudo(args):
     torch.cuda.synchronize()
     k_ms, k_n = ctx.kernel_time("exact_integral")
     r_ms, r_n = ctx.kernel_time("exact_redo")
+    g_ms, g_n = ctx.kernel_time("exact_gather")
     ctx.set_timing(False)
-    k_s = (k_ms / max(k_n, 1) + r_ms / max(r_n, 1)) / 1e3
+    k_s = (k_ms / max(k_n, 1) + r_ms / max(r_n, 1) + g_ms / max(g_n, 1)) / 1e3
     cpu = None
     hist = None
     if not args.no_cpu:
@@ -500,7 +505,7 @@ def run_pseudo(args):
         Mref, _, npairs = oracle.map_cells(tmix, mix_pos, mix_h, mix_m, cells)
         cpu_s = time.perf_counter() - t0
         Mg = rc.mass.cpu().numpy()[cells]
-        hist = oracle.work_counts(tmix, mix_pos, mix_h, cells)
+        hist = oracle.work_counts(tmix, mix_pos, mix_h, cells, owned=True)  # a device grid shares its faces
         cpu = {"value": round(float(npairs.sum()) / cpu_s, 1), "unit": "pair integrals/s", "cores": oracle.threads(),
                "cpu_model": cpu_model(), "kind": "oracle",
                "sample": f"2000 seeded cells + the 200 most degenerate of the mixed set's grid ({len(cells)} cells, "

@@ -581,10 +581,15 @@ void ora_cell_distance(int64_t n_cells, const double *gen, const double *vert, c
             (a range crossing U = 1 on both sides counts one of each: the
             outer form over the whole range plus twice the difference over
             the inner stretch).
-   Each face is oriented outwards as in the weight. */
+   Each face is oriented outwards as in the weight.  With nbr (the cell on
+   the other side of each face, negative for a wall; nullable), a face shared
+   by two cells is one polygon whose term of the weight is the same from both
+   sides up to its sign, so it is counted (with its edges and pieces) only
+   for the lower-numbered of its cells: the work of evaluating each
+   (particle, face) once. */
 void ora_work_counts(int64_t n_cells, const double *gen, const double *vert, const int64_t *cfo,
                      const int64_t *fvo, const int32_t *fv, int64_t n_part, const double *xyz,
-                     const double *h, int64_t n_list, const int64_t *cells, int64_t *out) {
+                     const double *h, int64_t n_list, const int64_t *cells, const int32_t *nbr, int64_t *out) {
   tess_t T = {n_cells, gen, vert, cfo, fvo, fv};
   int64_t tot[7] = {0, 0, 0, 0, 0, 0, 0};
 #pragma omp parallel
@@ -608,6 +613,7 @@ void ora_work_counts(int64_t n_cells, const double *gen, const double *vert, con
         loc[0] += 1;
         loc[1] += f1 - f0;
         for (int64_t f = f0; f < f1; ++f) {
+          if (nbr && nbr[f] >= 0 && nbr[f] < c) continue; /* the other cell's */
           int nv = (int)(fvo[f + 1] - fvo[f]);
           if (nv < 3 || nv > 512) continue;
           const double *V[512];

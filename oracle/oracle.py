@@ -76,7 +76,7 @@ def _lib():
         L.ora_lloyd.restype = None
         L.ora_lloyd.argtypes = [i64, vp, vp, vp, i32, vp]
         L.ora_work_counts.restype = None
-        L.ora_work_counts.argtypes = tess + [i64, vp, vp, i64, vp, vp]
+        L.ora_work_counts.argtypes = tess + [i64, vp, vp, i64, vp, vp, vp]
         L.ora_cell_distance.restype = None
         L.ora_cell_distance.argtypes = tess + [i64, vp, vp, vp]
         L.ora_interpolate.restype = None
@@ -142,15 +142,18 @@ def weight(t, c: int, x, h: float) -> float:
     return _lib().ora_weight(*_tess_args(t), int(c), _p(x), float(h))
 
 
-def work_counts(t, pos, h, cells):
+def work_counts(t, pos, h, cells, owned: bool = False):
     """What the Exact integral of the canonical pairs of the listed cells
     must evaluate, in exact geometry: [pairs, faces, faces the support
     reaches, their edges, edges the support reaches, inner pieces, outer
-    pieces] (see ora_work_counts)."""
+    pieces] (see ora_work_counts).  owned: a face shared with a cell
+    (t.face_nbr) counts only for the lower-numbered of the two."""
     cells = _c(cells, np.int64)
     pos, h = _c(pos, np.float64), _c(h, np.float64)
     out = np.zeros(7, dtype=np.int64)
-    _lib().ora_work_counts(*_tess_args(t), pos.shape[0], _p(pos), _p(h), len(cells), _p(cells), _p(out))
+    nbr = _c(t.face_nbr, np.int32) if owned else None
+    _lib().ora_work_counts(*_tess_args(t), pos.shape[0], _p(pos), _p(h), len(cells), _p(cells),
+                           _p(nbr) if nbr is not None else None, _p(out))
     return out
 
 

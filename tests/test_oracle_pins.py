@@ -130,3 +130,28 @@ def test_work_counts_cube(oracle, hh, want):
     t = _box_tess([-1.0, -1.0, -1.0], [1.0, 1.0, 1.0])
     got = oracle.work_counts(t, np.zeros((1, 3)), np.array([hh]), np.array([0]))
     assert list(got) == want
+
+
+def test_work_counts_shared_face(oracle, workloads):
+    """Two cubes of half-side 1 sharing the face x = 1, the particle at the
+    first one's centre with h = 0.6: the first cell's six faces are reached
+    at distance 1 (their edges at sqrt 2 are not); of the second cell only
+    the shared face is.  Counted for both pairs, the shared face appears
+    twice; counted once per (particle, face), only for the lower-numbered
+    cell."""
+    box0 = workloads.box_cells([-1.0, -1.0, -1.0], [1.0, 1.0, 1.0])
+    box1 = workloads.box_cells([1.0, -1.0, -1.0], [3.0, 1.0, 1.0])
+    t = workloads.tess_from_cells([[0.0, 0.0, 0.0], [2.0, 0.0, 0.0]], [box0, box1],
+                                  box_lo=(-1, -1, -1), box_hi=(3, 1, 1))
+    # face 1 of each box is its x+ face, face 0 its x- face
+    nbr = -np.ones(12, dtype=np.int32)
+    nbr[1] = 1
+    nbr[6 + 0] = 0
+    t.face_nbr = nbr
+    x, h = np.zeros((1, 3)), np.array([0.6])
+    both = oracle.work_counts(t, x, h, np.array([0, 1]))
+    once = oracle.work_counts(t, x, h, np.array([0, 1]), owned=True)
+    assert list(both) == [2, 12, 7, 28, 0, 0, 0]
+    assert list(once) == [2, 12, 6, 24, 0, 0, 0]
+    # the second cell alone evaluates nothing of its own
+    assert list(oracle.work_counts(t, x, h, np.array([1]), owned=True)) == [1, 6, 0, 0, 0, 0, 0]
