@@ -595,9 +595,19 @@ __device__ inline bool edge_geo64(const double4 pl, double dist, double ih, doub
 constexpr int kFlatWaves = 4;  // wavefronts per workgroup
 
 __global__ void k_zero_i32(int32_t *p, int n) {
-  const int t = threadIdx.x;
-  if (t < n) p[t] = 0;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) p[t] = 0;
 }
+
+// Work counters of the persistent Exact kernel: one per XCD, each on its own
+// 64-byte line, then the redo count.  Workgroups are dispatched to the eight
+// XCDs in turn (workgroup b on XCD b mod 8), so XCD x first takes the x-th
+// eighth of the chunks, in order: consecutive chunks (the pairs of one cell
+// and its neighbours) meet in one L2 and reuse its face and edge data.  An
+// XCD whose eighth runs out takes chunks from the others' in turn.
+constexpr int kXcd = 8;
+constexpr int kCtrStride = 16;
+constexpr int kCtrInts = kXcd * kCtrStride + 1;
+constexpr int kRedoCtr = kXcd * kCtrStride;
 
 // Instance table of a batch whose pair counts are known only on the device:
 // each instance's count *np[k] (0 for an overflowed list) and the first
@@ -1101,12 +1111,20 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
   const int64_t n_chunks = chunk0[n_inst];
   Counters K;
   int64_t nfaces = 0;
+  const int home = blockIdx.x % kXcd;
+  int vict = 0;  // eighths tried after this XCD's own
   while (true) {
+    const int x = (home + vict) % kXcd;
+    const int64_t lo = n_chunks * x / kXcd, hi = n_chunks * (x + 1) / kXcd;
     int gbase = 0;
-    if (lane == 0) gbase = atomicAdd(next_chunk, per_fetch);
+    if (lane == 0) gbase = atomicAdd(next_chunk + x * kCtrStride, per_fetch);
     gbase = __builtin_amdgcn_readfirstlane(gbase);  // uniform: chunk state in scalar registers
-    if (gbase >= n_chunks) break;
-    const int64_t gend = min((int64_t)gbase + per_fetch, n_chunks);
+    if (lo + gbase >= hi) {
+      if (++vict == kXcd) break;
+      continue;
+    }
+    const int64_t gend = min(lo + gbase + per_fetch, hi);
+    gbase = (int)(lo + gbase);
     for (int64_t gchunk = gbase; gchunk < gend; ++gchunk) {
     const int ins = inst_of(chunk0, n_inst, gchunk);
     const ExactInst &I = insts[ins];
@@ -1623,12 +1641,13 @@ void exact_integral_batch(Ctx &ctx, const std::vector<ExactJob> &jobs, int preci
                                     tab->flag);
       SPH_LAUNCH_CHECK();
     }
-    k_zero_i32<<<1, 64, 0, s>>>(next, 2);
+    k_zero_i32<<<1, 64, 0, s>>>(next, kCtrInts);
     SPH_LAUNCH_CHECK();
     k_exact_edges<false><<<(unsigned)grid, 64 * kFlatWaves, 0, s>>>(d_inst, tab->chunk0, n_inst, pf, nullptr, faces,
-                                                                   rtw, next, redo, next + 1);
+                                                                   rtw, next, redo, next + kRedoCtr);
     SPH_LAUNCH_CHECK();
-    k_exact_mixed_list<<<(unsigned)(ctx.n_cu * 4), 256, 0, s>>>(redo, next + 1, d_inst, tab->chunk0, n_inst, nullptr);
+    k_exact_mixed_list<<<(unsigned)(ctx.n_cu * 4), 256, 0, s>>>(redo, next + kRedoCtr, d_inst, tab->chunk0, n_inst,
+                                                                nullptr);
     SPH_LAUNCH_CHECK();
     launch_gather(ctx, jobs, G, d_inst, s);
     return;
@@ -1671,7 +1690,7 @@ void exact_integral_batch(Ctx &ctx, const std::vector<ExactJob> &jobs, int preci
   exact_occupancy(ctx);
   const int n_cu = ctx.n_cu, per_cu = ctx.exact_per_cu;
   const int64_t n_chunks = c0[n_inst];
-  int32_t *next = ctx.arena.get<int32_t>("flat_next", 2);  // work counter, redo count
+  int32_t *next = ctx.arena.get<int32_t>("flat_next", kCtrInts);  // work counters, redo count
   int64_t *redo = ctx.arena.get<int64_t>("flat_redo", total);
   auto launch = [&](int blocks_per_cu, int per_fetch) {
     const int64_t grid = std::min<int64_t>((int64_t)n_cu * std::min(blocks_per_cu, per_cu), div_up(n_chunks, kFlatWaves));
@@ -1679,12 +1698,12 @@ void exact_integral_batch(Ctx &ctx, const std::vector<ExactJob> &jobs, int preci
     FaceRec *faces = ctx.arena.get<FaceRec>("flat_faces", waves * kEntryCap);
     int32_t *rtw = shared ? ctx.arena.get<int32_t>("flat_rslot", waves * kEntryCap) : nullptr;
     KernelTimer kz(&ctx, "flat_reset", s);
-    k_zero_i32<<<1, 64, 0, s>>>(next, 2);
+    k_zero_i32<<<1, 64, 0, s>>>(next, kCtrInts);
     SPH_LAUNCH_CHECK();
     kz.done();
     KernelTimer kt(&ctx, "exact_integral", s);
     (ctr ? k_exact_edges<true> : k_exact_edges<false>)<<<(unsigned)grid, 64 * kFlatWaves, 0, s>>>(
-        d_inst, d_c0, n_inst, per_fetch, ctr, faces, rtw, next, redo, next + 1);
+        d_inst, d_c0, n_inst, per_fetch, ctr, faces, rtw, next, redo, next + kRedoCtr);
     SPH_LAUNCH_CHECK();
     kt.done();
   };
@@ -1718,7 +1737,7 @@ void exact_integral_batch(Ctx &ctx, const std::vector<ExactJob> &jobs, int preci
     launch(per_cu, 1);
   }
   KernelTimer kr(&ctx, "exact_redo", s);
-  k_exact_mixed_list<<<(unsigned)(n_cu * 4), 256, 0, s>>>(redo, next + 1, d_inst, d_c0, n_inst, ctr);
+  k_exact_mixed_list<<<(unsigned)(n_cu * 4), 256, 0, s>>>(redo, next + kRedoCtr, d_inst, d_c0, n_inst, ctr);
   SPH_LAUNCH_CHECK();
   kr.done();
   if (shared) {
