@@ -21,6 +21,18 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Several particles per wavefront in the coverage sum: every lane issues
+// the loads of all of its group's runs before it adds any, so a wavefront
+// keeps many loads in flight instead of waiting out one short run at a time.
+constexpr int kGroup = 4;  // particles per wavefront
+constexpr int kTurns = 4;  // 64-entry turns of each run per round of loads
+
+__device__ inline int64_t uniform_i64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __global__ void __launch_bounds__(256) k_cell_mass(int64_t C, const int64_t *off, const int32_t *pair_p,
                                                   const double *w, const double *m, const double *cov,
                                                   const double *vol, double *mass, double *rho, int *status) {
@@ -65,33 +77,62 @@ __global__ void __launch_bounds__(256) k_cell_mass(int64_t C, const int64_t *off
 // (dNP: a pair count known only on the device, at most NP.)
 __global__ void k_part_offsets(int64_t NP, int64_t N, const uint32_t *key, int64_t *part_off,
                                const int64_t *dNP = nullptr) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // four positions per thread, their keys loaded together
+  const int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   if (dNP) NP = *dNP;
-  if (k > NP) return;
-  const int64_t lo = k == 0 ? -1 : (int64_t)key[k - 1];
-  const int64_t hi = k == NP ? N : (int64_t)key[k];
-  for (int64_t j = lo + 1; j <= hi; ++j) part_off[j] = k;
+  if (k0 > NP) return;
+  int64_t kv[5];
+  kv[0] = k0 == 0 ? -1 : (int64_t)key[k0 - 1];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) kv[q + 1] = k0 + q < NP ? (int64_t)key[k0 + q] : N;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t k = k0 + q;
+    if (k > NP) break;
+    for (int64_t j = kv[q] + 1; j <= kv[q + 1]; ++j) part_off[j] = k;
+  }
 }
 
-// one wave per particle: gather its pairs in ascending cell order
-// c_i = sum_c w_ic over the particle's run of the particle-major list.
+// c_i = sum_c w_ic over each particle's run of the particle-major list
+// (ascending cell order), kGroup particles per wavefront.
 __global__ void __launch_bounds__(256) k_coverage(int64_t N, const int64_t *poff, const double *pm_w, double *cov) {
-  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t i0 = uniform_i64((((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * kGroup);
   const int lane = threadIdx.x & 63;
-  if (i >= N) return;
-  const int64_t s = poff[i], e = poff[i + 1];
-  double acc = 0.0;
-  // four turns' loads in flight together; the additions keep the lane's order
-  for (int64_t j0 = s + lane; j0 < e; j0 += 256) {
-    double v[4];
+  if (i0 >= N) return;
+  int64_t s[kGroup], e[kGroup], len = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = j0 + 64 * q < e ? pm_w[j0 + 64 * q] : 0.0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (j0 + 64 * q < e) acc += v[q];
+  for (int g = 0; g < kGroup; ++g) {
+    const int64_t a = min(i0 + g, N), b = min(i0 + g + 1, N);
+    s[g] = uniform_i64(poff[a]);
+    e[g] = a < N ? uniform_i64(poff[b]) : s[g];
+    len = max(len, e[g] - s[g]);
   }
-  acc = wave_sum(acc);
-  if (lane == 0) cov[i] = acc;
+  double acc[kGroup];
+#pragma unroll
+  for (int g = 0; g < kGroup; ++g) acc[g] = 0.0;
+  for (int64_t t0 = lane; t0 < len; t0 += 64 * kTurns) {
+    double v[kGroup][kTurns];
+#pragma unroll
+    for (int g = 0; g < kGroup; ++g)
+#pragma unroll
+      for (int u = 0; u < kTurns; ++u) {
+        const int64_t j = s[g] + t0 + 64 * u;
+        v[g][u] = j < e[g] ? pm_w[j] : 0.0;
+      }
+#pragma unroll
+    for (int g = 0; g < kGroup; ++g)
+#pragma unroll
+      for (int u = 0; u < kTurns; ++u)
+        if (s[g] + t0 + 64 * u < e[g]) acc[g] += v[g][u];
+  }
+#pragma unroll
+  for (int g = 0; g < kGroup; ++g) acc[g] = wave_sum(acc[g]);
+  if (lane < kGroup) {
+    double a = acc[0];
+#pragma unroll
+    for (int g = 1; g < kGroup; ++g) a = lane == g ? acc[g] : a;
+    if (i0 + lane < N) cov[i0 + lane] = a;
+  }
 }
 
 template <int kComp>
@@ -181,10 +222,10 @@ void particle_major(Ctx &ctx, PairsDev &P, hipStream_t s) {
     // (capacity mode: NP is the capacity and P.d_np the count on the device)
     sort_by_key_kv(ar, NP, bits, (const uint32_t *)P.pair_p, P.pair_c, P.w, keys, P.pm_cell, P.pm_w, s,
                    P.cap > 0 ? P.d_np : nullptr);
-    k_part_offsets<<<(unsigned)div_up(NP + 1, 256), 256, 0, s>>>(NP, N, keys, P.part_off,
+    k_part_offsets<<<(unsigned)div_up(div_up(NP + 1, 4), 256), 256, 0, s>>>(NP, N, keys, P.part_off,
                                                                  P.cap > 0 ? P.d_np : nullptr);
     SPH_LAUNCH_CHECK();
-    k_coverage<<<(unsigned)div_up(N * 64, 256), 256, 0, s>>>(N, P.part_off, P.pm_w, P.coverage);
+    k_coverage<<<(unsigned)div_up(div_up(N, kGroup) * 64, 256), 256, 0, s>>>(N, P.part_off, P.pm_w, P.coverage);
     SPH_LAUNCH_CHECK();
   } else {
     fill_i64(P.part_off, 0, N + 1, s);
