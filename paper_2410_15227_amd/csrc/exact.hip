@@ -36,11 +36,12 @@
 //     binary32 polynomial cores and seeds with binary64 range reduction and
 //     assembly (atan within 4.7e-9, log within 7.3e-10 relative);
 //     coefficients, angles' combination and
-//     every accumulation in binary64.  Edges whose foot point nearly touches
-//     the edge line or whose face plane nearly touches the particle (p or |d|
-//     below 1e-4 h) are recomputed from binary64 geometry; every pair whose
-//     cell is small against the support (R_c < 0.25 h) takes the binary64
-//     path.
+//     every accumulation in binary64.  Edges whose line passes within 1e-2 h
+//     of the particle (d^2 + p^2 below 1e-4 h^2), whose foot point lies on
+//     the edge line (p = 0) or whose face plane nearly touches the particle
+//     (|d| below 1e-4 h) are recomputed from binary64 geometry; every pair
+//     whose cell is small against the support (R_c < 0.25 h) takes the
+//     binary64 path.
 #include <algorithm>
 #include <vector>
 #include <cstdlib>
@@ -442,6 +443,11 @@ __global__ void __launch_bounds__(256) k_exact_fp64(int64_t P, const int32_t *pa
 
 // ---------------------------------------------------------- mixed kernel
 constexpr float kDegenerate = 1e-4f;  // p or |d| below this (units of h): binary64 edge
+// An edge whose line passes within this distance of the particle (in units
+// of h: d^2 + p^2 below its square) is evaluated from binary64 geometry: the
+// fan's terms there vary on the scale sqrt(d^2 + p^2), so the binary32
+// rounding of the foot point and edge frame is amplified by its inverse.
+constexpr float kEdgeNear = 1e-2f;
 // A cell smaller than this fraction of h (R_c < 0.25 h) is evaluated as on
 // the binary64 path (binary64 geometry and functions): its faces are small
 // and, seen from a particle far out in the support, their terms cancel far
@@ -517,8 +523,9 @@ __device__ inline double face_mixed(int64_t f, double xr0, double xr1, double xr
         ++K.ne_vis;
         bool integ;
         double v;
-        if (fabsf(p) < kDegenerate) {
-          // foot point within 1e-4 h of the edge line: binary64 geometry
+        if (fabsf(p) < kDegenerate || (float)(ad * ad) + p * p < kEdgeNear * kEdgeNear) {
+          // foot point within 1e-4 h of the edge line, or the edge line
+          // within 1e-2 h of the particle: binary64 geometry
           ++K.n64;
           const double *V = fvpos + 3 * vs;
           const double P0dx = xr0 + dist * pl.x, P0dy = xr1 + dist * pl.y, P0dz = xr2 + dist * pl.z;
@@ -1358,11 +1365,11 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
       const int owner = (int)(fc.slot >> 24);
       const float dx = fc.px - EA.x, dy = fc.py - EA.y, dz = fc.pz - EA.z;
       const float p = (dx * EM.x + dy * EM.y + dz * EM.z) * fc.ihf;
-      // an edge of positive length whose foot point lies within 1e-4 h of
-      // its line (p = 0 included) needs binary64 geometry: the pair goes to
-      // the redo kernel
+      // an edge of positive length whose line passes within 1e-2 h of the
+      // particle (d^2 + p^2), or whose foot point lies on its line (p = 0),
+      // needs binary64 geometry: the pair goes to the redo kernel
       const bool act = live & (EA.w > 0.0f);
-      const bool degen = act & (fabsf(p) < kDegenerate);
+      const bool degen = act & ((p == 0.0f) | (fmaf(fc.df, fc.df, p * p) < kEdgeNear * kEdgeNear));
       if (degen) {
         ++K.n64;
         L.redo[owner] = 1;

@@ -263,6 +263,49 @@ def test_near_degenerate_positions(ctx, oracle, precision):
     assert np.max(np.abs(gw - w)) < tol
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_near_edge_lines(ctx, oracle, workloads, precision):
+    """Particles 3e-4 h to 3e-3 h off a face plane whose foot point lies
+    1e-4 h to 1e-3 h beside an edge line of the face, so the edge's line
+    passes within about 3e-3 h of the particle (Voronoi cells of 300 random
+    sites): the mixed path takes such edges from binary64 geometry (d^2 +
+    p^2 below (1e-2 h)^2); per-pair weights against the oracle."""
+    import paper_2410_15227_amd as pkg
+    say(f"case: particles near edge lines, precision={precision}")
+    g = np.random.default_rng(7)
+    t = workloads.voronoi(g.random((300, 3)))
+    h = 0.09
+    cfo, fvo, fv, V = t.cell_face_off, t.face_vtx_off, t.face_vtx, t.vertices
+    pts = []
+    for f in g.choice(t.n_faces, 20, replace=False):
+        vs = V[fv[fvo[f]:fvo[f + 1]]]
+        c = np.searchsorted(cfo, f, side="right") - 1
+        n = np.cross(vs[1] - vs[0], vs[2] - vs[0])
+        n /= np.linalg.norm(n)
+        if np.dot(n, vs.mean(0) - t.generators[c]) < 0:
+            n = -n
+        A, B = vs[0], vs[1]
+        mdir = np.cross(n, (B - A) / np.linalg.norm(B - A))
+        if np.dot(mdir, vs.mean(0) - A) < 0:
+            mdir = -mdir
+        for d in (3e-4, 1e-3, 3e-3):
+            for p in (1e-4, 3e-4, 1e-3):
+                for sd in (1.0, -1.0):
+                    x = A + (0.3 + 0.4 * g.random()) * (B - A) + p * h * mdir - sd * d * h * n
+                    if np.all(x > 0.0) and np.all(x < 1.0):
+                        pts.append(x)
+    pts = np.array(pts)
+    hs = np.full(len(pts), h)
+    wl = type("W", (), dict(tess=t, pos=pts, h=hs, m=np.ones(len(pts))))
+    dt, res = run_map(pkg, ctx, wl, precision)
+    goff, gidx, gw = (x.cpu().numpy() for x in res.pairs.export())
+    off, idx, w = oracle.pairs_weights(t, pts, hs)
+    assert np.array_equal(goff, off) and np.array_equal(gidx, idx)
+    err = float(np.max(np.abs(gw - w)))
+    say(f"  {len(pts)} particles, {len(w)} pairs, max |w - w_oracle| = {err:.2e}")
+    assert err < (1e-12 if precision == "fp64" else 5e-6)
+
+
 def test_transpose_three_sort_passes(ctx):
     """More than 2^20 particles: the particle-major copy is then sorted in
     three passes.  Particles with tiny supports inside a 4^3 lattice each
