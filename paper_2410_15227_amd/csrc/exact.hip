@@ -36,12 +36,13 @@
 //     binary32 polynomial cores and seeds with binary64 range reduction and
 //     assembly (atan within 4.7e-9, log within 7.3e-10 relative);
 //     coefficients, angles' combination and
-//     every accumulation in binary64.  Edges whose line passes within 1e-2 h
-//     of the particle (d^2 + p^2 below 1e-4 h^2), whose foot point lies on
-//     the edge line (p = 0) or whose face plane nearly touches the particle
-//     (|d| below 1e-4 h) are recomputed from binary64 geometry; every pair
-//     whose cell is small against the support (R_c < 0.25 h) takes the
-//     binary64 path.
+//     every accumulation in binary64.  A pair with an edge whose line passes
+//     within 1e-2 h of the particle (d^2 + p^2 below 1e-4 h^2) or whose
+//     foot point lies on the edge line (p = 0), or with a face plane through
+//     the particle (|d| below 1e-20 h), goes to a second kernel that
+//     recomputes such edges, and faces within 1e-4 h, from binary64
+//     geometry; every pair whose cell is small against the support (R_c <
+//     0.25 h) takes the binary64 path.
 #include <algorithm>
 #include <vector>
 #include <cstdlib>
@@ -443,6 +444,11 @@ __global__ void __launch_bounds__(256) k_exact_fp64(int64_t P, const int32_t *pa
 
 // ---------------------------------------------------------- mixed kernel
 constexpr float kDegenerate = 1e-4f;  // p or |d| below this (units of h): binary64 edge
+// A face plane closer than this to the particle (units of h) is taken as
+// through it: the edge kernel leaves the pair to the binary64 kernel.  Any
+// larger distance is resolved by the edge kernel's binary32 geometry, whose
+// rounding matters only near edge lines (kEdgeNear below).
+constexpr double kOnPlane = 1e-20;
 // An edge whose line passes within this distance of the particle (in units
 // of h: d^2 + p^2 below its square) is evaluated from binary64 geometry: the
 // fan's terms there vary on the scale sqrt(d^2 + p^2), so the binary32
@@ -1210,7 +1216,7 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
           const bool mine = L.wtw[j] >= -1;
           const bool near = real & mine & (dist != 0.0) & (fabs(dist) < 2.0 * h) &
                             (sx * sx + sy * sy + sz * sz < reach * reach);
-          const bool deg = near & (fabs(dist * ih) < kDegenerate);
+          const bool deg = near & (fabs(dist * ih) < kOnPlane);
           if (kCount) K.n64 += deg & !again;
           again |= deg;
           const bool keep = near & !deg & (L.wnv[j] > 0);  // a face without edges adds nothing

@@ -227,9 +227,9 @@ def test_lattice_special_positions(ctx, oracle, precision):
 def test_near_degenerate_positions(ctx, oracle, precision):
     """Particles 3e-5 h, 1e-7 h and 1e-11 h off a face plane, an edge line
     and a corner of the cubic lattice, and particles whose foot point on a
-    face plane 0.3 h away lies on an edge line or 1e-9 h beside it: the cases
-    the mixed path routes to binary64 geometry (|d| or |p| below 1e-4 h,
-    p = 0 included), against the oracle."""
+    face plane 0.3 h away lies on an edge line or 1e-9 h beside it: cases
+    near the mixed path's binary64 routing (edge lines within 1e-2 h of the
+    particle, p = 0, face planes through the particle), against the oracle."""
     import paper_2410_15227_amd as pkg
     say(f"case: near-degenerate positions, precision={precision}")
     t = lattice(6)
