@@ -21,8 +21,12 @@
 // Each edge term is evaluated with the same angles phi = atan(tau/p) in both
 // of its parts, so rounding in an endpoint angle is multiplied by
 // H(U) - H(|d|), which vanishes where that rounding is largest (foot point
-// next to a vertex).  A face none of whose edges comes within 2h uses the
-// exact angle sum (2pi if P0 is inside the polygon, 0 outside).
+// next to a vertex).  A face none of whose edges comes within 2h, or whose
+// foot point lies outside its bounding sphere by more than 0.1 h, uses the
+// exact angle sum (2pi if P0 is inside the polygon, 0 outside) in place of
+// the per-edge angle terms: far from the vertices the pairing is not needed,
+// and the terms' binary32 rounding would otherwise remain in a face whose
+// plane passes close to the particle while its polygon lies far off.
 //
 // The antiderivative |d| int H(U) dphi is, per regime (U < 1, 1 <= U < 2),
 //     c_phi phi + c_beta beta + c_L L + tau (c_1 + c_3 tau^2)
@@ -985,9 +989,18 @@ struct __align__(16) FaceRec {  // a face within reach of a pair
   double dhs;        // -sign(d) |d| H(|d|) 2^46, sign(0) = -1: the angle
                      // term's factor in fixed-point units
   float ihf;         // 1/h of the pair (binary32)
-  uint32_t slot;     // bits 0-23: first vertex slot - the chunk's first; 24-31: lane of the pair
+  uint32_t slot;     // bits 0-23: first vertex slot - the chunk's first; 24-29: lane of the
+                     // pair; 31: the foot point is far outside the face (kFarFoot)
 };
 constexpr int64_t kSlotSpan = 1 << 24;  // vertex slots a chunk's faces may span
+constexpr uint32_t kFarBit = 1u << 31;    // record flag: the foot point is far outside the face
+// A face whose foot point lies farther than this (in units of h) beyond the
+// face's bounding sphere takes its exact angle part, 0: the per-edge angle
+// terms of such a face sum to 0 in exact arithmetic, but each is of the size
+// of |d| H(|d|) (near 1 for a plane that passes close to the particle) and
+// carries the binary32 geometry's rounding, while the face's true
+// contribution, from the part of the fan within 2h, may be orders smaller.
+constexpr double kFarFoot = 0.1;
 static_assert(sizeof(FaceRec) == 32, "records are addressed as index << 5");
 
 struct EdgeData {  // what one lane reads for its edge: face record and edge geometry
@@ -1164,7 +1177,7 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
     // vertex slots of the chunk's faces, kept relative to the first in 24 bits
     const int64_t VB = uniform64(fvo[F0]);
     const bool wide = fvo[F1] - VB > kSlotSpan;
-    uint64_t mask = 0;
+    uint64_t mask = 0, farmask = 0;
     int nsurv = 0, nedge = 0;
     bool inside = true, on_boundary = false, again = false;
     int64_t f0 = 0, f1 = 0, c = 0;
@@ -1210,17 +1223,24 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
           inside &= !(real & (dist < 0.0));
           on_boundary |= real & (dist == 0.0);
           const double sx = xr0 - sp.x, sy = xr1 - sp.y, sz = xr2 - sp.z;
+          const double s2 = sx * sx + sy * sy + sz * sz;
           const double reach = sp.r + 2.0 * h;
           // a shared face is evaluated by the lower-numbered of its two
           // cells, for both pairs of the particle
           const bool mine = L.wtw[j] >= -1;
-          const bool near = real & mine & (dist != 0.0) & (fabs(dist) < 2.0 * h) &
-                            (sx * sx + sy * sy + sz * sz < reach * reach);
+          const bool near = real & mine & (dist != 0.0) & (fabs(dist) < 2.0 * h) & (s2 < reach * reach);
+          // the sphere's centre lies in the face plane, so the foot point's
+          // squared distance from it is s2 - dist^2: a foot point beyond the
+          // sphere by kFarFoot h is outside the polygon and clear of its
+          // vertices
+          const double rf = sp.r + kFarFoot * h;
+          const bool far = s2 - dist * dist > rf * rf;
           const bool deg = near & (fabs(dist * ih) < kOnPlane);
           if (kCount) K.n64 += deg & !again;
           again |= deg;
           const bool keep = near & !deg & (L.wnv[j] > 0);  // a face without edges adds nothing
           mask |= (uint64_t)keep << (wb + j - f0);
+          farmask |= (uint64_t)(keep & far) << (wb + j - f0);
           nsurv += keep;
           nedge += keep ? L.wnv[j] : 0;
         }
@@ -1280,7 +1300,8 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
         if (mask && ja < jb) {
           uint64_t m = mask & lanes_in((int)(wb + ja - f0), (int)(wb + jb - f0));
           while (m) {
-            const int j = (int)(__builtin_ctzll(m) - (wb - f0));
+            const int bit = __builtin_ctzll(m);
+            const int j = (int)(bit - (wb - f0));
             m &= m - 1;
             const double4 pl = L.wpl[j];
             const double dist = pl.w - (pl.x * xr0 + pl.y * xr1 + pl.z * xr2);
@@ -1294,7 +1315,10 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
             const double dh = dH((double)fabsf(df));
             rec.dhs = (df > 0.0f ? -dh : dh) * 0x1p46;
             rec.ihf = (float)ih;
-            rec.slot = (uint32_t)(L.wvs[j] - VB) | ((uint32_t)lane << 24);
+            // a face whose foot point is far outside it: its angle part is
+            // exactly 0, so its edges add no angle terms
+            const uint32_t fb = (uint32_t)((farmask >> bit) & 1ull) << 31;
+            rec.slot = (uint32_t)(L.wvs[j] - VB) | ((uint32_t)lane << 24) | fb;
             fr[e] = rec;
             if (shared) rtw[e] = L.wtw[j];  // the face's gift slot, or -1
             atomicOr(&L.sb[start >> 6], 1ull << (start & 63));
@@ -1331,7 +1355,7 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
           const FaceRec rc = load_rec(frg, r);
           const long long T = L.rint[sl] ? (long long)L.racc[sl]
                                          : (L.rnin[sl] ? 0ll : (long long)fixed_from(fma(rc.dhs, 2.0 * kPi, magic)));
-          const int ow = (int)(rc.slot >> 24);
+          const int ow = (int)((rc.slot >> 24) & 63u);
           atomicAdd(&L.acc[ow], (unsigned long long)T);
           if (shared) {
             const int q = rtw[r];
@@ -1368,7 +1392,8 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
       // Branch-free: nearly every lane has a live edge of positive length at
       // a nonzero distance, so every lane does the arithmetic (the clamped
       // loads keep it finite) and the tests only select what is kept.
-      const int owner = (int)(fc.slot >> 24);
+      const int owner = (int)((fc.slot >> 24) & 63u);
+      const bool far = (fc.slot & kFarBit) != 0u;
       const float dx = fc.px - EA.x, dy = fc.py - EA.y, dz = fc.pz - EA.z;
       const float p = (dx * EM.x + dy * EM.y + dz * EM.z) * fc.ihf;
       // an edge of positive length whose line passes within 1e-2 h of the
@@ -1393,7 +1418,7 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
       // factor takes the sign bit of p (p != 0 here) and feeds one fma
       const double f = __hiloint2double(__double2hiint(fc.dhs) ^ (int)(__float_as_uint(p) & 0x80000000u),
                                         __double2loint(fc.dhs));
-      if (ok) atomicAdd(&L.racc[sl], fixed_from(fma(MathMixed::span(ap, dA, dB), f, magic)));
+      if (ok & !far) atomicAdd(&L.racc[sl], fixed_from(fma(MathMixed::span(ap, dA, dB), f, magic)));
       // within 2h somewhere on [tA, tB], and crossing U = 1 (squares, no
       // roots; bitwise logic, so that no test becomes a branch)
       const double a2 = ad * ad + ap * ap;
