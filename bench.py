@@ -345,6 +345,9 @@ def main():
         "fp64_path": fp64,
         "kernels_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in other.items()},
         "work_counters": ctr,
+        # pairs the mixed path leaves to its binary64-geometry kernel
+        "binary64_kernel_pairs": {"pairs": int(ctr[7]), "fraction": round(ctr[7] / max(ctr[0], 1), 6)}
+        if args.precision == "mixed" else None,
     }
     print(json.dumps(out), flush=True)
     dt.free()
@@ -559,6 +562,8 @@ def run_pseudo(args):
                    "device_voronoi_ms": {"mixed": round(vor_mix_s * 1e3, 2), "all": round(vor_all_s * 1e3, 2)}},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "binary64_kernel_pairs": {"pairs": int(ctr[7]), "fraction": round(ctr[7] / max(ctr[0], 1), 6)}
+        if args.precision == "mixed" else None,
     }
     print(json.dumps(out), flush=True)
     dt_mix.free()

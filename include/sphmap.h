@@ -525,10 +525,12 @@ int sphmap_reset_timing(sphmap_ctx *ctx);
    (U < 1) and outer (1 <= U < 2) regime; mixed path: single-regime pieces
    (one per integrated edge, two when its range crosses U = 1) with inner /
    outer coefficients (a piece with twice their difference counts as
-   inner).  [7] edges or faces
-   evaluated from binary64 geometry (mixed path: the pairs holding them are
-   recomputed by a second kernel, 16 lanes per pair).  Counting costs time; it is only done when
-   enabled (sphmap_set_counting). */
+   inner).  [7] mixed path: pairs recomputed by the second, binary64-geometry
+   kernel (16 lanes per pair): an edge line within 1e-2 h of the particle, a
+   foot point on an edge line, a face plane through the particle, a cell
+   smaller than h/4, more than 64 faces or 256 candidate edges, a particle
+   on the boundary; binary64 path: 0.  Counting costs time; it is only done
+   when enabled (sphmap_set_counting). */
 int sphmap_set_counting(sphmap_ctx *ctx, int32_t enabled);
 
 /* Launch-shape autotuning of the mixed-path Exact integral (the persistent

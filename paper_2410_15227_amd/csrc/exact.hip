@@ -825,6 +825,7 @@ __global__ void __launch_bounds__(256) k_exact_mixed_list(const int64_t *list, c
       if (all_in && any_on) S = boundary_S(f0, f1, I.fplane, I.fvo, I.fvpos, xr0, xr1, xr2);
       I.w[k] = S - acc;
     }
+    K.n64 = 0;  // counter 7 counts the pairs sent here, in the edge kernel
     if (counters) flush_counters(counters, sub == 0 ? f1 - f0 : 0, K);
   }
 }
@@ -1236,7 +1237,6 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
           const double rf = sp.r + kFarFoot * h;
           const bool far = s2 - dist * dist > rf * rf;
           const bool deg = near & (fabs(dist * ih) < kOnPlane);
-          if (kCount) K.n64 += deg & !again;
           again |= deg;
           const bool keep = near & !deg & (L.wnv[j] > 0);  // a face without edges adds nothing
           mask |= (uint64_t)keep << (wb + j - f0);
@@ -1401,10 +1401,7 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
       // needs binary64 geometry: the pair goes to the redo kernel
       const bool act = live & (EA.w > 0.0f);
       const bool degen = act & ((p == 0.0f) | (fmaf(fc.df, fc.df, p * p) < kEdgeNear * kEdgeNear));
-      if (degen) {
-        ++K.n64;
-        L.redo[owner] = 1;
-      }
+      if (degen) L.redo[owner] = 1;
       const bool ok = act & !degen;
       // the foot point is outside the record's polygon if any edge sees it
       // on its outer side
@@ -1533,6 +1530,7 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
         I.w[k] = (inside ? 1.0 : 0.0) - kInv4Pi * from_fixed(L.acc[lane]);
       }
     } else if (valid) {
+      if (kCount) ++K.n64;  // a pair left to the binary64 kernel
       if (shared) I.wflag[k] = kFlagRedo;
       redo[atomicAdd(n_redo, 1)] = gchunk * 64 + lane;
     }
