@@ -867,14 +867,14 @@ __global__ void __launch_bounds__(64 * kGatherWaves) k_exact_gather(const ExactI
   __shared__ int32_t pl_[kGatherWaves][kGatherW];
   __shared__ unsigned long long ga_[kGatherWaves][kGatherW];
   __shared__ int64_t fcb_[kGatherWaves][64], fgs_[kGatherWaves][64];
-  __shared__ int32_t fnc_[kGatherWaves][64];
+  __shared__ int32_t fra_[kGatherWaves][64], frb_[kGatherWaves][64];
   const ExactInst &I = insts[ins];
   if (!I.gift) return;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   int32_t *const pl = pl_[wid];
   unsigned long long *const ga = ga_[wid];
   int64_t *const fcb = fcb_[wid], *const fgs = fgs_[wid];
-  int32_t *const fnc = fnc_[wid];
+  int32_t *const fra = fra_[wid], *const frb = frb_[wid];
   const int64_t *coff = I.cell_off;
   const int32_t *pair_p = I.pair_p;
   for (int64_t cp = (int64_t)blockIdx.x * kGatherWaves + wid; cp < C; cp += (int64_t)gridDim.x * kGatherWaves) {
@@ -898,23 +898,46 @@ __global__ void __launch_bounds__(64 * kGatherWaves) k_exact_gather(const ExactI
           const int64_t tc = I.ftwin[f];
           const int64_t cb = coff[tc], nc = coff[tc + 1] - cb;
           fcb[pos] = cb;
-          fnc[pos] = (int32_t)nc;
           fgs[pos] = I.gbase[tc] + (int64_t)(-2 - code) * nc;
+          // the twin's rows whose particles fall in this window's range
+          // [i_lo, i_hi] (its list ascends by particle): all of them when the
+          // cell takes one or two windows, else found by bisection, so that a
+          // long list is not read once per window
+          int32_t ra = 0, rb = (int32_t)nc;
+          if (n > 2 * kGatherW) {
+            int32_t lo = 0, hi = (int32_t)nc;
+            while (lo < hi) {
+              const int32_t mid = (lo + hi) >> 1;
+              if (pair_p[cb + mid] < i_lo) lo = mid + 1;
+              else hi = mid;
+            }
+            ra = lo;
+            hi = (int32_t)nc;
+            while (lo < hi) {
+              const int32_t mid = (lo + hi) >> 1;
+              if (pair_p[cb + mid] <= i_hi) lo = mid + 1;
+              else hi = mid;
+            }
+            rb = lo;
+          }
+          fra[pos] = ra;
+          frb[pos] = rb;
         }
         const int nin = __popcll(mk);
         wave_sync();
-        int j = 0, r = 0;  // next block: rows [64 r, 64 r + 64) of face j's run
+        int j = 0, r = 0;  // next block: rows fra[j] + [64 r, 64 r + 64) of face j's run
         while (j < nin) {
           int64_t gs[kGatherU], cb[kGatherU];
           bool uv[kGatherU];
 #pragma unroll
           for (int u = 0; u < kGatherU; ++u) {
-            const int64_t t = 64 * (int64_t)r + lane;
-            uv[u] = j < nin && t < fnc[min(j, nin - 1)];
+            const int jj = min(j, nin - 1);
+            const int64_t t = fra[jj] + 64 * (int64_t)r + lane;
+            uv[u] = j < nin && t < frb[jj];
             gs[u] = j < nin ? fgs[j] + t : 0;
             cb[u] = j < nin ? fcb[j] + t : 0;
             if (j < nin) {
-              if (64 * (r + 1) < fnc[j]) {
+              if (fra[j] + 64 * (r + 1) < frb[j]) {
                 ++r;
               } else {
                 ++j;
