@@ -288,10 +288,18 @@ __device__ double boundary_S(int64_t f0, int64_t f1, const double4 *fplane, cons
   return om * kInv4Pi;
 }
 
+// One edge from binary64 geometry in the difference form of the edge kernel
+// (each piece's angles and logarithm from their differences, the angle term
+// from the span), with the math library's functions: for cells small
+// against the support, whose per-endpoint terms cancel far below the mixed
+// cores' accuracy.  Defined after the pieces.
+struct MathDiff {};
+__device__ double edge_term_diff(double ad, double p, double tA, double tB, double dh, bool &integ, EdgeCount &cnt);
+
 // One face with binary64 geometry about the generator, particle at xr; the
-// transcendental cores are M's (the math library for the binary64 path, the
-// mixed cores where the mixed path meets a face within 1e-4 h of the
-// particle).
+// edges are evaluated with M's transcendental cores (the math library for
+// the binary64 path, the mixed cores where the mixed path meets a face
+// within 1e-4 h of the particle) or, for MathDiff, in the difference form.
 template <class M>
 __device__ double face_fp64(const double4 pl, double dist, double ih, double xr0, double xr1, double xr2,
                             const double *V, int nv, int &ne_vis, int &ne_int, EdgeCount &cnt) {
@@ -321,7 +329,11 @@ __device__ double face_fp64(const double4 pl, double dist, double ih, double xr0
     const double tA = ((Ax - P0x) * ex + (Ay - P0y) * ey + (Az - P0z) * ez) * ih;
     const double tB = ((Bx - P0x) * ex + (By - P0y) * ey + (Bz - P0z) * ez) * ih;
     bool integ;
-    const double v = edge_term_geo64<M>(ad, fabs(p), tA, tB, dh, integ, cnt);
+    double v;
+    if constexpr (std::is_same<M, MathDiff>::value)
+      v = edge_term_diff(ad, fabs(p), tA, tB, dh, integ, cnt);
+    else
+      v = edge_term_geo64<M>(ad, fabs(p), tA, tB, dh, integ, cnt);
     anyint |= integ;
     ne_int += integ;
     sum += p > 0.0 ? v : -v;
@@ -493,10 +505,11 @@ __device__ inline double face_mixed(int64_t f, double xr0, double xr1, double xr
   const double d = dist * ih, ad = fabs(d);
   if (geo64) {
     // a cell small against the support: binary64 geometry and the math
-    // library's functions (the per-endpoint form's differences of a small
-    // face seen from afar cancel far below the binary32 cores' accuracy)
+    // library's functions (the terms of a small face seen from afar cancel
+    // far below the binary32 geometry's and cores' accuracy), in the
+    // difference form
     K.n64 += nv;
-    return face_fp64<Math64>(pl, dist, ih, xr0, xr1, xr2, fvpos + 3 * vs, nv, K.ne_vis, K.ne_int, K.fd);
+    return face_fp64<MathDiff>(pl, dist, ih, xr0, xr1, xr2, fvpos + 3 * vs, nv, K.ne_vis, K.ne_int, K.fd);
   }
   if (ad < kDegenerate) {
     // particle on the face plane to within 1e-4 h: the whole face from binary64 geometry
@@ -672,20 +685,35 @@ __device__ inline double log_ratio_mixed(double num, double den) {
   return (double)e * kLn2 + fma(t * t2, (double)Q, 2.0 * t);
 }
 
+// The functions the pieces take: binary32 cores with binary64 assembly for
+// the edge kernel, the math library for the binary64-geometry kernel's
+// small cells.
+struct PieceMixed {
+  static __device__ inline double atan2_(double y, double x) { return atan2_mixed(y, x); }
+  static __device__ inline double log_ratio(double num, double den) { return log_ratio_mixed(num, den); }
+  static __device__ inline double sqrt_(double v) { return sqrt_mixed(v); }
+};
+struct Piece64 {
+  static __device__ inline double atan2_(double y, double x) { return atan2(y, x); }
+  static __device__ inline double log_ratio(double num, double den) { return log(num / den); }
+  static __device__ inline double sqrt_(double v) { return sqrt(v); }
+};
+
 // F(v) - F(u) over [u, v] inside one regime with coefficients c, from
 // differences: phi(v) - phi(u) and beta(v) - beta(u) as one angle each
 // (atan2 of the tangent-difference numerator and denominator, scaled by
 // positive factors), L(v) - L(u) = log(N(v) / N(u)) with N(t) = t + U(t),
 // written a^2 / (U - t) for t < 0 to avoid cancellation.
+template <class Q>
 __device__ inline double piece(const Coef &c, double ad, double p, double a2, double u, double Uu, double v,
                                double Uv) {
-  const double dphi = atan2_mixed(p * (v - u), fma(u, v, p * p));
-  const double dbeta = atan2_mixed(ad * p * (v * Uu - u * Uv), p * p * Uu * Uv + ad * ad * u * v);
+  const double dphi = Q::atan2_(p * (v - u), fma(u, v, p * p));
+  const double dbeta = Q::atan2_(ad * p * (v * Uu - u * Uv), p * p * Uu * Uv + ad * ad * u * v);
   const bool un = u < 0.0, vn = v < 0.0;
   const double Nv = vn ? Uu - u : v + Uv;
   const double Nu = un ? (vn ? Uv - v : a2) : u + Uu;
   const double num = (un && !vn) ? Nv * (Uu - u) : Nv;
-  const double dL = log_ratio_mixed(num, Nu);
+  const double dL = Q::log_ratio(num, Nu);
   const double u2 = u * u, v2 = v * v;
   const double poly = (v * fma(c.t3, v2, c.t1) - u * fma(c.t3, u2, c.t1)) +
                       (v * Uv * fma(c.t3U, v2, c.tU) - u * Uu * fma(c.t3U, u2, c.tU));
@@ -723,12 +751,13 @@ __device__ inline Coef coef_mix(double ad, double p, double w0, double w1) {
 // whole range (mode 1) plus 2 (F_inner - F_outer) over [0, t1] (mode 2;
 // both antiderivatives are odd in t).  When rounding at the join loses the
 // crossing, mode 1 takes the whole range and mode 2 adds nothing.
+template <class Q>
 __device__ inline double piece_of(double ad, double p, double tA, double tB, int mode, EdgeCount &cnt) {
   const double a2 = ad * ad + p * p;
-  const double t2 = sqrt_mixed(4.0 - a2);
+  const double t2 = Q::sqrt_(4.0 - a2);
   const double ca = fmin(fmax(tA, -t2), t2), cb = fmin(fmax(tB, -t2), t2);
   const bool in = a2 < 1.0;  // an inner regime exists
-  const double t1 = in ? sqrt_mixed(1.0 - a2) : 0.0;
+  const double t1 = in ? Q::sqrt_(1.0 - a2) : 0.0;
   const bool lo = in && ca < -t1 && cb > -t1, hi = in && ca < t1 && cb > t1;
   const bool both = lo && hi, one = mode == 0 || (!lo && !hi);
   const bool m2 = mode == 2 && !one, m1 = !one && !m2;
@@ -737,8 +766,8 @@ __device__ inline double piece_of(double ad, double p, double tA, double tB, int
   const double v = one ? cb : (m2 ? (both ? t1 : cb) : (both ? cb : s));
   // U at the ends: 1 at a crossing, 2 at a clipped end, else from the root
   const bool u_split = m2 && !both, v_split = (m1 && !both) || (m2 && both);
-  const double Uu = u_split ? 1.0 : (fabs(u) == t2 ? 2.0 : sqrt_mixed(fma(u, u, a2)));
-  const double Uv = v_split ? 1.0 : (fabs(v) == t2 ? 2.0 : sqrt_mixed(fma(v, v, a2)));
+  const double Uu = u_split ? 1.0 : (fabs(u) == t2 ? 2.0 : Q::sqrt_(fma(u, u, a2)));
+  const double Uv = v_split ? 1.0 : (fabs(v) == t2 ? 2.0 : Q::sqrt_(fma(v, v, a2)));
   // regime weights: (1, 0) inner, (0, 1) outer, (2, -2) twice their difference
   const double mid = 0.5 * (ca + cb);
   const bool outer = one ? !(mid * mid < 1.0 - a2) : (m1 ? (both || lo) : (!both && !lo));
@@ -747,14 +776,35 @@ __device__ inline double piece_of(double ad, double p, double tA, double tB, int
   const bool none = mode == 2 && one;
   cnt.n0 += !none && w0 != 0.0;
   cnt.n1 += !none && w0 == 0.0;
-  const double r = piece(coef_mix(ad, p, w0, w1), ad, p, a2, u, Uu, v, Uv);
+  const double r = piece<Q>(coef_mix(ad, p, w0, w1), ad, p, a2, u, Uu, v, Uv);
   return none ? 0.0 : r;
 }
 
 __device__ inline double item_value(const float4 it, int mode, EdgeCount &cnt) {
   const double ad = (double)fabsf(it.x), p = (double)fabsf(it.y), tA = (double)it.z, tB = (double)it.w;
-  const double v = piece_of(ad, p, tA, tB, mode, cnt);
+  const double v = piece_of<PieceMixed>(ad, p, tA, tB, mode, cnt);
   return ((it.x < 0.0f) != (it.y < 0.0f)) ? -v : v;
+}
+
+// |d| int [H(U) - H(|d|)] dphi over the fan of one edge (p > 0, tA < tB),
+// binary64 with the math library, in the difference form: the angle term
+// from the span, the part within 2h as the edge kernel's pieces (two when
+// the range crosses U = 1).
+__device__ double edge_term_diff(double ad, double p, double tA, double tB, double dh, bool &integ, EdgeCount &cnt) {
+  const double a2 = ad * ad + p * p;
+  const double r2 = 4.0 - a2, s1 = 1.0 - a2;
+  const double A2 = tA * tA, B2 = tB * tB;
+  integ = (r2 > 0.0) && (tA < tB) && (tA < 0.0 || A2 < r2) && (tB > 0.0 || B2 < r2);
+  double v = -dh * Math64::span(p, tA, tB);
+  if (integ) {
+    const bool lo = tA < 0.0 && A2 > s1 && (tB >= 0.0 || B2 < s1);
+    const bool hi = (tA < 0.0 || A2 < s1) && tB > 0.0 && B2 > s1;
+    if (s1 > 0.0 && (lo || hi))
+      v += piece_of<Piece64>(ad, p, tA, tB, 1, cnt) + piece_of<Piece64>(ad, p, tA, tB, 2, cnt);
+    else
+      v += piece_of<Piece64>(ad, p, tA, tB, 0, cnt);
+  }
+  return v;
 }
 
 __device__ inline void wave_fence() {
@@ -766,8 +816,10 @@ __device__ inline void wave_fence() {
 // The pairs the edge-parallel kernel leaves to binary64 geometry, 16 lanes
 // per pair (four pairs per wavefront): lane s takes the cell's faces s,
 // s + 16, ...; each round's 16 shares go through LDS and the group's first
-// lane adds them in face order, so the sum is the serial one.
-__global__ void __launch_bounds__(256) k_exact_mixed_list(const int64_t *list, const int32_t *n_list,
+// lane adds them in face order, so the sum is the serial one.  Two
+// workgroups per SIMD (at most 256 registers): one leaves the library's
+// binary64 functions without latency hiding.
+__global__ void __launch_bounds__(256, 2) k_exact_mixed_list(const int64_t *list, const int32_t *n_list,
                                                          const ExactInst *__restrict__ insts,
                                                          const int64_t *__restrict__ chunk0, int n_inst,
                                                          int64_t *counters) {
