@@ -442,214 +442,303 @@ __device__ inline double readlane_d(double v, int j) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-constexpr int kHWaves = 4;  // pseudo-particles per workgroup
+// What the node h-solve sums over: the units (their positions and the
+// boxes of their tiles of 64 and of their blocks of 64 tiles) and, with
+// n_mid > 0, the trial-neighbour ranges.
+struct HUnits {
+  int64_t nu;
+  const double4 *upos;
+  const double4 *tlo, *thi;  // tile t: units [64 t, 64 t + 64)
+  const double4 *blo, *bhi;  // block b: tiles [64 b, 64 b + 64)
+  int64_t n_mid;
+  const double4 *mid_com;
+  const int32_t *mid_u0, *mid_u1;
+  const double *rcut;
+};
 
-// Node h-solve: one wavefront per pseudo-particle.  Each Newton or
-// bisection step needs the sums over all units within 2h; the 64 lanes
-// evaluate 64 consecutive units at a time and the terms that are not zero
-// are added in unit order, so the sums are those of a plain sequential loop.
-// With n_mid > 0 the sums run over trial neighbours only: the units of the
-// ranges [mid_u0, mid_u1) of the k_mid nodes whose centres of mass lie
-// within rcut[e] of the target (the ranges follow unit order, so the terms
-// are still added in unit order).
-__global__ void __launch_bounds__(64 * kHWaves) k_hsolve(int64_t np, const int32_t *plist, int64_t nu,
-                                                        const double4 *upos, const double *o_xyz, const double *o_s,
-                                                        double hfact, double eps, int64_t bypass, double *o_h,
-                                                        int32_t *o_branch, unsigned long long *bcount, int64_t n_mid,
-                                                        const double4 *mid_com, const int32_t *mid_u0,
-                                                        const int32_t *mid_u1, const double *rcut,
-                                                        const double4 *tlo, const double4 *thi) {
+// The sums of one h-solve step at node position (ax, ay, az) and length he,
+// over every unit within 2 he, by one wavefront.
+//
+// Unit order (fast == false): the 64 lanes evaluate 64 consecutive units at
+// a time, the tile's non-zero terms go to LDS (hb, 64 entries) in lane order
+// and lane 0 adds them one after the other into sw and sd, so lane 0 holds
+// the sums of a plain sequential loop over the units.
+//
+// Tree order (fast == true): sw only, and only this wave's share, the tiles
+// t with t % step == first: each tile's terms are added by a butterfly and
+// the tiles in order; every lane holds the share, and nhit counts its
+// non-zero terms.
+//
+// A block or tile whose bounding box lies beyond 2 he holds only zero terms
+// and is skipped.  A block's box holds its tiles' boxes and the distance test
+// is monotone in the box bounds, so no tile that passes the test is skipped
+// with its block.  Blocks and tiles are visited in ascending order.  With
+// n_mid > 0 the sums run over trial neighbours only: the units of the ranges
+// [mid_u0, mid_u1) of the nodes whose centres of mass lie within rcut[e] of
+// the target; the ranges follow unit order, so unit-order terms are still
+// added in unit order.
+__device__ __forceinline__ void hsums(const HUnits &U, int32_t e, double ax, double ay, double az, double he,
+                                      bool fast, int first, int step, double2 *hb, double &sw, double &sd,
+                                      int64_t &nhit) {
 #pragma clang fp contract(off)
-  __shared__ double2 hbuf[kHWaves][64];  // one tile's non-zero terms, in lane order
-  const int64_t pid = (int64_t)blockIdx.x * kHWaves + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  double2 *const hb = hbuf[threadIdx.x >> 6];
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  if (pid >= np) return;  // the whole wavefront
-  const int32_t e = plist[pid];
-  const double ax = o_xyz[3 * (int64_t)e], ay = o_xyz[3 * (int64_t)e + 1], az = o_xyz[3 * (int64_t)e + 2];
-  const double s = o_s[e];
-  const double h0 = hfact * 2.0 * s;
-  double lo = 1e-2 * h0, hi = 1e2 * h0;
-  double h = h0, flo = 0.0, hres = h0;
-  int phase = 0;  // 0 Newton, 1 eval lo, 2 eval hi, 3 bisect, 9 done
-  int it = 0, branch = 0;
-  if (np > bypass) {
-    hres = h0;
-    branch = 3;
-    phase = 9;
-  }
-  while (phase != 9) {
-    // point at which the sums are needed
-    double he = h;
-    if (phase == 1) he = lo;
-    else if (phase == 2) he = hi;
-    else if (phase == 3) he = 0.5 * (lo + hi);
-    const double ih = 1.0 / he;
-    double sw = 0.0, sd = 0.0;
-    bool fast = false;  // tile sums in a fixed tree order, sw only
-    int64_t nhit = 0;
-    // the terms of one tile's units (one per lane, `live` lanes hold one)
-    auto tile_terms = [&](const double4 &p, bool live) {
-      double w = 0.0, dt = 0.0;
-      bool hit = false;
-      if (live) {
-        const double dx = ax - p.x, dy = ay - p.y, dz = az - p.z;
-        const double qq = sqrt((dx * dx + dy * dy) + dz * dz) * ih;
-        if (qq < 2.0) {
-          hit = true;
-          w = m4w(qq);
-          dt = -(3.0 * w + qq * m4dw(qq));
-        }
+  const double ih = 1.0 / he;
+  sw = sd = 0.0;
+  nhit = 0;
+  // the terms of one tile's units (one per lane, `live` lanes hold one)
+  auto tile_terms = [&](const double4 &p, bool live) __attribute__((always_inline)) {
+    double w = 0.0, dt = 0.0;
+    bool hit = false;
+    if (live) {
+      const double dx = ax - p.x, dy = ay - p.y, dz = az - p.z;
+      const double qq = sqrt((dx * dx + dy * dy) + dz * dz) * ih;
+      if (qq < 2.0) {
+        hit = true;
+        w = m4w(qq);
+        if (!fast) dt = -(3.0 * w + qq * m4dw(qq));
       }
-      if (fast) {
-        const uint64_t m = __ballot(hit);
-        nhit += __popcll(m);
-        if (m) {
-          double v = hit ? w : 0.0;
-#pragma unroll
-          for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-          sw += readlane_d(v, 0);
-        }
-        return;
-      }
-      // unit order: the tile's hits go to LDS in lane order and lane 0
-      // adds them one after the other (its sums are broadcast at the end)
-      const uint64_t mask = __ballot(hit);
+    }
+    const uint64_t mask = __ballot(hit);
+    if (fast) {
+      nhit += __popcll(mask);
       if (mask) {
-        if (hit) hb[__popcll(mask & below)] = make_double2(w, dt);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (lane == 0) {
-          const int cnt = __popcll(mask);
-          int k = 0;
-          for (; k + 8 <= cnt; k += 8) {  // eight reads in flight, added in order
-            double2 v[8];
+        double v = hit ? w : 0.0;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = hb[k + u];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        sw += readlane_d(v, 0);
+      }
+      return;
+    }
+    if (mask) {
+      if (hit) hb[__popcll(mask & below)] = make_double2(w, dt);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (lane == 0) {
+        const int cnt = __popcll(mask);
+        int k = 0;
+        for (; k + 8 <= cnt; k += 8) {  // eight reads in flight, added in order
+          double2 v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              sw += v[u].x;
-              sd += v[u].y;
-            }
-          }
-          for (; k < cnt; ++k) {
-            const double2 v = hb[k];
-            sw += v.x;
-            sd += v.y;
+          for (int u = 0; u < 8; ++u) v[u] = hb[k + u];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            sw += v[u].x;
+            sd += v[u].y;
           }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (; k < cnt; ++k) {
+          const double2 v = hb[k];
+          sw += v.x;
+          sd += v.y;
+        }
       }
-    };
-    // units [u0, u1) by tiles of 64 (tile t: units [64 t, 64 t + 64)); a
-    // tile whose bounding box lies beyond 2h holds only zero terms and is
-    // skipped; non-zero terms are added in unit order
-    auto tile_sums = [&](int64_t u0, int64_t u1) {
-      const int64_t t0 = u0 >> 6, t1 = (u1 + 63) >> 6;
-      for (int64_t tb = t0; tb < t1; tb += 64) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  };
+  auto beyond = [&](const double4 &lo, const double4 &hi) __attribute__((always_inline)) {
+    const double bx = fmax(fmax(lo.x - ax, ax - hi.x), 0.0);
+    const double by = fmax(fmax(lo.y - ay, ay - hi.y), 0.0);
+    const double bz = fmax(fmax(lo.z - az, az - hi.z), 0.0);
+    return !(((bx * bx + by * by) + bz * bz) * ih * ih < 4.0 * (1.0 + 1e-9));
+  };
+  // units [u0, u1), tiles t with t % step == first
+  auto tile_sums = [&](int64_t u0, int64_t u1) __attribute__((always_inline)) {
+    const int64_t t0 = u0 >> 6, t1 = (u1 + 63) >> 6;
+    const int64_t b0 = t0 >> 6, b1 = (t1 + 63) >> 6;
+    for (int64_t bb = b0; bb < b1; bb += 64) {
+      const int64_t bi = bb + lane;
+      bool bnear = false;
+      if (bi < b1) bnear = !beyond(U.blo[bi], U.bhi[bi]);
+      uint64_t bm = __ballot(bnear);
+      while (bm) {
+        const int64_t tb = 64 * (bb + __builtin_ctzll(bm));
+        bm &= bm - 1;
         const int64_t ti = tb + lane;
         bool near = false;
-        if (ti < t1) {
-          const double4 lo = tlo[ti], hi = thi[ti];
-          const double bx = fmax(fmax(lo.x - ax, ax - hi.x), 0.0);
-          const double by = fmax(fmax(lo.y - ay, ay - hi.y), 0.0);
-          const double bz = fmax(fmax(lo.z - az, az - hi.z), 0.0);
-          near = ((bx * bx + by * by) + bz * bz) * ih * ih < 4.0 * (1.0 + 1e-9);
-        }
+        if (ti >= t0 && ti < t1 && ti % step == first) near = !beyond(U.tlo[ti], U.thi[ti]);
         uint64_t nm = __ballot(near);
         while (nm) {
           // up to four near tiles at once: their loads are in flight together,
           // and their terms are added tile after tile
-          int64_t ua[4], ub[4];
-          double4 pv[4];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            ua[k] = ub[k] = 0;
+          int64_t ua0, ub0, ua1, ub1, ua2, ub2, ua3, ub3;
+          double4 p0, p1, p2, p3;
+          auto take = [&](int64_t &ua, int64_t &ub, double4 &pv) __attribute__((always_inline)) {
+            ua = ub = 0;
             if (nm) {
               const int64_t t = tb + __builtin_ctzll(nm);
               nm &= nm - 1;
-              ua[k] = max(u0, 64 * t);
-              ub[k] = min(u1, 64 * t + 64);
+              ua = max(u0, 64 * t);
+              ub = min(u1, 64 * t + 64);
             }
-            if (ua[k] + lane < ub[k]) pv[k] = upos[ua[k] + lane];
-          }
-#pragma unroll
-          for (int k = 0; k < 4; ++k)
-            if (ub[k] > ua[k]) tile_terms(pv[k], ua[k] + lane < ub[k]);
-        }
-      }
-    };
-
-    auto all_sums = [&]() {
-    if (n_mid == 0) {
-      tile_sums(0, nu);
-    } else {
-      const double rc = rcut[e];
-      for (int64_t m0 = 0; m0 < n_mid; m0 += 64) {
-        const int64_t mi = m0 + lane;
-        bool flag = false;
-        if (mi < n_mid) {
-          const double4 c = mid_com[mi];
-          const double dx = ax - c.x, dy = ay - c.y, dz = az - c.z;
-          flag = sqrt((dx * dx + dy * dy) + dz * dz) < rc;
-        }
-        uint64_t fm = __ballot(flag);
-        while (fm) {
-          const int j = __builtin_ctzll(fm);
-          fm &= fm - 1;
-          tile_sums(mid_u0[m0 + j], mid_u1[m0 + j]);
+            if (ua + lane < ub) pv = U.upos[ua + lane];
+          };
+          take(ua0, ub0, p0);
+          take(ua1, ub1, p1);
+          take(ua2, ub2, p2);
+          take(ua3, ub3, p3);
+          if (ub0 > ua0) tile_terms(p0, ua0 + lane < ub0);
+          if (ub1 > ua1) tile_terms(p1, ua1 + lane < ub1);
+          if (ub2 > ua2) tile_terms(p2, ua2 + lane < ub2);
+          if (ub3 > ua3) tile_terms(p3, ua3 + lane < ub3);
         }
       }
     }
-    };
-    // Bracket and bisection steps use only the sign of f (and f == 0), so
-    // they first take sw from tile sums in a fixed tree order.  The terms are
-    // non-negative, so that sum is within 2 nhit 2^-53 sw of the unit-order
-    // one, which moves f by less than nhit 2^-53 he; only when |f| is within
-    // that margin are the sums taken again in unit order.  Every decision,
-    // and so every result, is that of the unit-order sums.
-    fast = phase != 0;
-    double n, dn, f;
-    while (true) {  // at most twice: tree order, then unit order
-      sw = sd = 0.0;
-      nhit = 0;
-      all_sums();
+  };
+  if (U.n_mid == 0) {
+    tile_sums(0, U.nu);
+  } else {
+    const double rc = U.rcut[e];
+    for (int64_t m0 = 0; m0 < U.n_mid; m0 += 64) {
+      const int64_t mi = m0 + lane;
+      bool flag = false;
+      if (mi < U.n_mid) {
+        const double4 c = U.mid_com[mi];
+        const double dx = ax - c.x, dy = ay - c.y, dz = az - c.z;
+        flag = sqrt((dx * dx + dy * dy) + dz * dz) < rc;
+      }
+      uint64_t fm = __ballot(flag);
+      while (fm) {
+        const int j = __builtin_ctzll(fm);
+        fm &= fm - 1;
+        tile_sums(U.mid_u0[m0 + j], U.mid_u1[m0 + j]);
+      }
+    }
+  }
+}
+
+// f(h) = hfact n(h)^(-1/3) - h and, for Newton, its derivative term, from
+// the unit-order sums (lane 0's)
+__device__ __forceinline__ double h_residual(double sw, double he, double hfact) {
+#pragma clang fp contract(off)
+  const double ih = 1.0 / he;
+  const double n = sw * ih * ih * ih * kInvPi;
+  return hfact * pow(n, -1.0 / 3.0) - he;
+}
+
+constexpr int kHWaves = 4;    // pseudo-particles per workgroup in the Newton kernel
+constexpr int kBWaves = 16;   // wavefronts per pseudo-particle in the bracket kernel
+
+// Node h-solve, first part: up to 30 Newton steps from h0 = 2 hfact s, one
+// wavefront per pseudo-particle, with unit-order sums.  A converged node
+// writes its h (branch 0); a node whose step fails (a vanishing derivative,
+// a step out of [h0/100, 100 h0], or 30 steps) is appended to `fails` for
+// the bracket kernel.  Above `bypass` pseudo-particles every node takes h0
+// (branch 3).
+__global__ void __launch_bounds__(64 * kHWaves) k_hsolve_newton(int64_t np, const int32_t *plist, HUnits U,
+                                                               const double *o_xyz, const double *o_s, double hfact,
+                                                               double eps, int64_t bypass, double *o_h,
+                                                               int32_t *o_branch, unsigned long long *bcount,
+                                                               int32_t *fails, int32_t *n_fails) {
+#pragma clang fp contract(off)
+  __shared__ double2 hbuf[kHWaves][64];
+  const int64_t pid = (int64_t)blockIdx.x * kHWaves + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (pid >= np) return;  // the whole wavefront
+  const int32_t e = plist[pid];
+  const double ax = o_xyz[3 * (int64_t)e], ay = o_xyz[3 * (int64_t)e + 1], az = o_xyz[3 * (int64_t)e + 2];
+  const double h0 = hfact * 2.0 * o_s[e];
+  const double lo = 1e-2 * h0, hi = 1e2 * h0;
+  double hres = h0;
+  int branch = 3;
+  if (np <= bypass) {
+    branch = -1;  // failed unless a step converges
+    double h = h0;
+    for (int it = 0; it < 30; ++it) {
+      double sw, sd;
+      int64_t nhit;
+      hsums(U, e, ax, ay, az, h, false, 0, 1, hbuf[threadIdx.x >> 6], sw, sd, nhit);
       sw = readlane_d(sw, 0);  // lane 0 holds the unit-order sums
       sd = readlane_d(sd, 0);
-      n = sw * ih * ih * ih * kInvPi;
-      dn = sd * ih * ih * ih * ih * kInvPi;
-      f = hfact * pow(n, -1.0 / 3.0) - he;
-      if (!fast || fabs(f) > he * (1e-12 + 4.0 * (double)nhit * 0x1p-53)) break;
-      fast = false;
-    }
-    if (phase == 0) {
+      const double ih = 1.0 / h;
+      const double n = sw * ih * ih * ih * kInvPi;
+      const double dn = sd * ih * ih * ih * ih * kInvPi;
+      const double f = hfact * pow(n, -1.0 / 3.0) - h;
       const double fp = -(1.0 / 3.0) * hfact * dn * pow(n, -4.0 / 3.0) - 1.0;
-      bool fail = false;
-      if (!(fabs(fp) >= 1e-12)) fail = true;
-      double hn = 0.0;
-      if (!fail) {
-        hn = h - f / fp;
-        if (!(hn >= lo && hn <= hi)) fail = true;
-      }
-      if (!fail && fabs(hn - h) / h0 < eps) {
+      if (!(fabs(fp) >= 1e-12)) break;
+      const double hn = h - f / fp;
+      if (!(hn >= lo && hn <= hi)) break;
+      if (fabs(hn - h) / h0 < eps) {
         hres = hn;
         branch = 0;
-        phase = 9;
-      } else if (!fail) {
-        h = hn;
-        if (++it >= 30) phase = 1;
-      } else {
-        phase = 1;
+        break;
       }
-    } else if (phase == 1) {
+      h = hn;
+    }
+  }
+  if (lane == 0) {
+    if (branch < 0) {
+      fails[atomicAdd(n_fails, 1)] = e;
+    } else {
+      o_h[e] = hres;
+      if (o_branch) o_branch[e] = branch;
+      atomicAdd(&bcount[branch], 1ull);
+    }
+  }
+}
+
+// Node h-solve, second part: the bracket [h0/100, 100 h0] and bisection to
+// a width below eps h0, one workgroup of kBWaves wavefronts per node that
+// Newton did not solve.  These steps use only the sign of f (and f == 0), so
+// they first take sw in tree order, each wave summing its share and the
+// shares added in wave order.  The terms are non-negative, so that sum is
+// within 2 nhit 2^-53 sw of the unit-order one, which moves f by less than
+// nhit 2^-53 he; only when |f| is within that margin are the sums taken again
+// in unit order (by the first wave).  Every decision, and so every result,
+// is that of the unit-order sums.
+__global__ void __launch_bounds__(64 * kBWaves) k_hsolve_bracket(const int32_t *fails, const int32_t *n_fails,
+                                                                HUnits U, const double *o_xyz, const double *o_s,
+                                                                double hfact, double eps, double *o_h,
+                                                                int32_t *o_branch, unsigned long long *bcount) {
+#pragma clang fp contract(off)
+  __shared__ double2 hb[64];
+  __shared__ double part_sw[kBWaves];
+  __shared__ long long part_hit[kBWaves];
+  __shared__ double uo_sw;
+  if ((int)blockIdx.x >= *n_fails) return;  // the whole workgroup
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int32_t e = fails[blockIdx.x];
+  const double ax = o_xyz[3 * (int64_t)e], ay = o_xyz[3 * (int64_t)e + 1], az = o_xyz[3 * (int64_t)e + 2];
+  const double h0 = hfact * 2.0 * o_s[e];
+  double lo = 1e-2 * h0, hi = 1e2 * h0;
+  double flo = 0.0, hres = h0;
+  int phase = 1;  // 1 eval lo, 2 eval hi, 3 bisect, 9 done
+  int branch = 1;
+  while (phase != 9) {
+    double he = lo;
+    if (phase == 2) he = hi;
+    else if (phase == 3) he = 0.5 * (lo + hi);
+    double sw, sd;
+    int64_t nhit;
+    hsums(U, e, ax, ay, az, he, true, wid, kBWaves, hb, sw, sd, nhit);
+    if ((threadIdx.x & 63) == 0) {
+      part_sw[wid] = sw;
+      part_hit[wid] = nhit;
+    }
+    __syncthreads();
+    sw = 0.0;
+    nhit = 0;
+    for (int k = 0; k < kBWaves; ++k) {  // in wave order
+      sw += part_sw[k];
+      nhit += part_hit[k];
+    }
+    double f = h_residual(sw, he, hfact);
+    if (!(fabs(f) > he * (1e-12 + 4.0 * (double)nhit * 0x1p-53))) {  // the same in every wave
+      if (wid == 0) {
+        hsums(U, e, ax, ay, az, he, false, 0, 1, hb, sw, sd, nhit);
+        if ((threadIdx.x & 63) == 0) uo_sw = sw;  // lane 0 holds the unit-order sum
+      }
+      __syncthreads();
+      f = h_residual(uo_sw, he, hfact);
+    }
+    __syncthreads();  // every wave has read the shared sums before they are written again
+    if (phase == 1) {
       flo = f;
       if (f == 0.0) {
         hres = lo;
-        branch = 1;
         phase = 9;
       } else {
         phase = 2;
@@ -657,7 +746,6 @@ __global__ void __launch_bounds__(64 * kHWaves) k_hsolve(int64_t np, const int32
     } else if (phase == 2) {
       if (f == 0.0) {
         hres = hi;
-        branch = 1;
         phase = 9;
       } else if ((flo < 0.0) == (f < 0.0)) {
         hres = h0;
@@ -665,7 +753,6 @@ __global__ void __launch_bounds__(64 * kHWaves) k_hsolve(int64_t np, const int32
         phase = 9;
       } else if (!(hi - lo >= eps * h0)) {
         hres = 0.5 * (lo + hi);
-        branch = 1;
         phase = 9;
       } else {
         phase = 3;
@@ -673,7 +760,6 @@ __global__ void __launch_bounds__(64 * kHWaves) k_hsolve(int64_t np, const int32
     } else {  // bisection step at mid = he
       if (f == 0.0) {
         hres = he;
-        branch = 1;
         phase = 9;
       } else {
         if ((f < 0.0) == (flo < 0.0)) {
@@ -684,13 +770,12 @@ __global__ void __launch_bounds__(64 * kHWaves) k_hsolve(int64_t np, const int32
         }
         if (!(hi - lo >= eps * h0)) {
           hres = 0.5 * (lo + hi);
-          branch = 1;
           phase = 9;
         }
       }
     }
   }
-  if (lane == 0) {
+  if (threadIdx.x == 0) {
     o_h[e] = hres;
     if (o_branch) o_branch[e] = branch;
     atomicAdd(&bcount[branch], 1ull);
@@ -738,6 +823,24 @@ __global__ void k_unit_tiles(int64_t nu, const double4 *upos, double4 *tlo, doub
   tlo[t] = lo;
   thi[t] = hi;
 }
+
+// the boxes of blocks of 64 tiles, from the tiles' boxes
+__global__ void k_unit_blocks(int64_t nt, const double4 *tlo, const double4 *thi, double4 *blo, double4 *bhi) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b * 64 >= nt) return;
+  double4 lo = tlo[64 * b], hi = thi[64 * b];
+  for (int64_t t = 64 * b + 1; t < min(nt, 64 * b + 64); ++t) {
+    const double4 l = tlo[t], u = thi[t];
+    lo.x = fmin(lo.x, l.x);
+    lo.y = fmin(lo.y, l.y);
+    lo.z = fmin(lo.z, l.z);
+    hi.x = fmax(hi.x, u.x);
+    hi.y = fmax(hi.y, u.y);
+    hi.z = fmax(hi.z, u.z);
+  }
+  blo[b] = lo;
+  bhi[b] = hi;
+}
 }  // namespace
 
 void node_hsolve(Ctx &ctx, int64_t np, const int32_t *plist, int64_t nu, const double4 *upos, const double *o_xyz,
@@ -748,15 +851,32 @@ void node_hsolve(Ctx &ctx, int64_t np, const int32_t *plist, int64_t nu, const d
   const int64_t nt = div_up(nu, 64);
   double4 *tlo = ctx.arena.get<double4>("hs_tlo", std::max<int64_t>(nt, 1));
   double4 *thi = ctx.arena.get<double4>("hs_thi", std::max<int64_t>(nt, 1));
+  const int64_t nb = div_up(nt, 64);
+  double4 *blo = ctx.arena.get<double4>("hs_blo", std::max<int64_t>(nb, 1));
+  double4 *bhi = ctx.arena.get<double4>("hs_bhi", std::max<int64_t>(nb, 1));
   if (nt > 0) {
     k_unit_tiles<<<(unsigned)div_up(nt, 256), 256, 0, s>>>(nu, upos, tlo, thi);
     SPH_LAUNCH_CHECK();
+    k_unit_blocks<<<(unsigned)div_up(nb, 256), 256, 0, s>>>(nt, tlo, thi, blo, bhi);
+    SPH_LAUNCH_CHECK();
   }
-  KernelTimer kt(&ctx, "node_hsolve", s);
-  k_hsolve<<<(unsigned)div_up(np, kHWaves), 64 * kHWaves, 0, s>>>(np, plist, nu, upos, o_xyz, o_s, hfact, eps, bypass,
-                                                                o_h, o_branch, bcount, n_mid, mid_com, mid_u0, mid_u1,
-                                                                rcut, tlo, thi);
+  int32_t *fails = ctx.arena.get<int32_t>("hs_fails", np);
+  int32_t *n_fails = ctx.arena.get<int32_t>("hs_nfails", 1);
+  k_fill_i32<<<1, 64, 0, s>>>(n_fails, 0, 1);
   SPH_LAUNCH_CHECK();
+  const HUnits U{nu, upos, tlo, thi, blo, bhi, n_mid, mid_com, mid_u0, mid_u1, rcut};
+  KernelTimer kt(&ctx, "node_hsolve", s);
+  KernelTimer kt1(&ctx, "node_hsolve_newton", s);
+  k_hsolve_newton<<<(unsigned)div_up(np, kHWaves), 64 * kHWaves, 0, s>>>(np, plist, U, o_xyz, o_s, hfact, eps, bypass,
+                                                                        o_h, o_branch, bcount, fails, n_fails);
+  SPH_LAUNCH_CHECK();
+  kt1.done();
+  // one workgroup per node that Newton did not solve (the rest exit at once)
+  KernelTimer kt2(&ctx, "node_hsolve_bracket", s);
+  k_hsolve_bracket<<<(unsigned)np, 64 * kBWaves, 0, s>>>(fails, n_fails, U, o_xyz, o_s, hfact, eps, o_h, o_branch,
+                                                         bcount);
+  SPH_LAUNCH_CHECK();
+  kt2.done();
   kt.done();
 }
 
