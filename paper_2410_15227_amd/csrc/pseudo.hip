@@ -461,8 +461,9 @@ struct HUnits {
 //
 // Unit order (fast == false): the 64 lanes evaluate 64 consecutive units at
 // a time, the tile's non-zero terms go to LDS (hb, 64 entries) in lane order
-// and lane 0 adds them one after the other into sw and sd, so lane 0 holds
-// the sums of a plain sequential loop over the units.
+// and lanes 0 and 1 add them one after the other (lane 0 the w terms, lane 1
+// the dt terms), so sw and sd, returned to every lane, are the sums of a
+// plain sequential loop over the units.
 //
 // Tree order (fast == true): sw only, and only this wave's share, the tiles
 // t with t % step == first: each tile's terms are added by a butterfly and
@@ -477,6 +478,8 @@ struct HUnits {
 // [mid_u0, mid_u1) of the nodes whose centres of mass lie within rcut[e] of
 // the target; the ranges follow unit order, so unit-order terms are still
 // added in unit order.
+// kBatch: LDS reads in flight in the unit-order adds.
+template <int kBatch>
 __device__ __forceinline__ void hsums(const HUnits &U, int32_t e, double ax, double ay, double az, double he,
                                       bool fast, int first, int step, double2 *hb, double &sw, double &sd,
                                       int64_t &nhit) {
@@ -484,6 +487,7 @@ __device__ __forceinline__ void hsums(const HUnits &U, int32_t e, double ax, dou
   const int lane = threadIdx.x & 63;
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const double ih = 1.0 / he;
+  double acc = 0.0;  // unit order: lane 0's sw, lane 1's sd
   sw = sd = 0.0;
   nhit = 0;
   // the terms of one tile's units (one per lane, `live` lanes hold one)
@@ -515,24 +519,18 @@ __device__ __forceinline__ void hsums(const HUnits &U, int32_t e, double ax, dou
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      if (lane == 0) {
+      if (lane < 2) {  // lane 0 adds the w terms, lane 1 the dt terms
+        const double *src = reinterpret_cast<const double *>(hb) + lane;
         const int cnt = __popcll(mask);
         int k = 0;
-        for (; k + 8 <= cnt; k += 8) {  // eight reads in flight, added in order
-          double2 v[8];
+        for (; k + kBatch <= cnt; k += kBatch) {  // kBatch reads in flight, added in order
+          double v[kBatch];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) v[u] = hb[k + u];
+          for (int u = 0; u < kBatch; ++u) v[u] = src[2 * (k + u)];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            sw += v[u].x;
-            sd += v[u].y;
-          }
+          for (int u = 0; u < kBatch; ++u) acc += v[u];
         }
-        for (; k < cnt; ++k) {
-          const double2 v = hb[k];
-          sw += v.x;
-          sd += v.y;
-        }
+        for (; k < cnt; ++k) acc += src[2 * k];
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -608,6 +606,10 @@ __device__ __forceinline__ void hsums(const HUnits &U, int32_t e, double ax, dou
       }
     }
   }
+  if (!fast) {
+    sw = readlane_d(acc, 0);
+    sd = readlane_d(acc, 1);
+  }
 }
 
 // f(h) = hfact n(h)^(-1/3) - h and, for Newton, its derivative term, from
@@ -650,9 +652,7 @@ __global__ void __launch_bounds__(64 * kHWaves) k_hsolve_newton(int64_t np, cons
     for (int it = 0; it < 30; ++it) {
       double sw, sd;
       int64_t nhit;
-      hsums(U, e, ax, ay, az, h, false, 0, 1, hbuf[threadIdx.x >> 6], sw, sd, nhit);
-      sw = readlane_d(sw, 0);  // lane 0 holds the unit-order sums
-      sd = readlane_d(sd, 0);
+      hsums<16>(U, e, ax, ay, az, h, false, 0, 1, hbuf[threadIdx.x >> 6], sw, sd, nhit);
       const double ih = 1.0 / h;
       const double n = sw * ih * ih * ih * kInvPi;
       const double dn = sd * ih * ih * ih * ih * kInvPi;
@@ -713,7 +713,7 @@ __global__ void __launch_bounds__(64 * kBWaves) k_hsolve_bracket(const int32_t *
     else if (phase == 3) he = 0.5 * (lo + hi);
     double sw, sd;
     int64_t nhit;
-    hsums(U, e, ax, ay, az, he, true, wid, kBWaves, hb, sw, sd, nhit);
+    hsums<8>(U, e, ax, ay, az, he, true, wid, kBWaves, hb, sw, sd, nhit);
     if ((threadIdx.x & 63) == 0) {
       part_sw[wid] = sw;
       part_hit[wid] = nhit;
@@ -728,8 +728,8 @@ __global__ void __launch_bounds__(64 * kBWaves) k_hsolve_bracket(const int32_t *
     double f = h_residual(sw, he, hfact);
     if (!(fabs(f) > he * (1e-12 + 4.0 * (double)nhit * 0x1p-53))) {  // the same in every wave
       if (wid == 0) {
-        hsums(U, e, ax, ay, az, he, false, 0, 1, hb, sw, sd, nhit);
-        if ((threadIdx.x & 63) == 0) uo_sw = sw;  // lane 0 holds the unit-order sum
+        hsums<8>(U, e, ax, ay, az, he, false, 0, 1, hb, sw, sd, nhit);
+        if ((threadIdx.x & 63) == 0) uo_sw = sw;
       }
       __syncthreads();
       f = h_residual(uo_sw, he, hfact);
