@@ -90,6 +90,42 @@ __global__ void k_kd_zero(int64_t b, int64_t e, KdNodes N) {
 // additions are grouped.
 constexpr int kLdsNodes = 1024;
 
+// Runs of equal keys among a wave's lanes (the particles of a node are
+// contiguous, so a wave holds few runs): each lane's position in its run and
+// the run's inclusive sums or maxima by a segmented scan over the lanes.
+// Returns true in the last lane of each run, which then holds the run's
+// total; the other lanes hold partial results.  Integer sums and maxima do
+// not depend on how they are grouped.
+struct WaveRuns {
+  int lane;
+  int seg;  // lanes [seg, lane] hold the same key
+  __device__ explicit WaveRuns(int64_t key) {
+    lane = threadIdx.x & 63;
+    const int64_t prev = __shfl_up(key, 1, 64);
+    const bool head = lane == 0 || prev != key;
+    const uint64_t heads = __ballot(head);
+    const uint64_t upto = heads & (lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull));
+    seg = 63 - __builtin_clzll(upto);  // lane 0 is always a head
+    next_differs = __shfl_down(key, 1, 64) != key || lane == 63;
+  }
+  bool next_differs;
+  __device__ bool last() const { return next_differs; }
+  __device__ void add(unsigned long long &v) const {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned long long u = __shfl_up(v, o, 64);
+      if (lane - o >= seg) v += u;
+    }
+  }
+  __device__ void max(unsigned long long &v) const {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned long long u = __shfl_up(v, o, 64);
+      if (lane - o >= seg && u > v) v = u;
+    }
+  }
+};
+
 __global__ void __launch_bounds__(256) k_kd_sums(int64_t n, const double4 *pxm, const int32_t *nop, int64_t b,
                                                  int64_t e, int K, KdNodes N) {
 #pragma clang fp contract(off)
@@ -105,14 +141,19 @@ __global__ void __launch_bounds__(256) k_kd_sums(int64_t n, const double4 *pxm, 
     node = nop[i];
     if (node < b || node >= e) node = -1;
   }
+  unsigned long long v[4] = {0ull, 0ull, 0ull, 0ull};
   if (node >= 0) {
     const double4 pj = pxm[i];
     const double mj = pj.w;
-    unsigned long long v[4];
     v[0] = (unsigned long long)__double2ll_rn(ldexp(mj, K));
     v[1] = (unsigned long long)__double2ll_rn(ldexp(mj * pj.x, K));
     v[2] = (unsigned long long)__double2ll_rn(ldexp(mj * pj.y, K));
     v[3] = (unsigned long long)__double2ll_rn(ldexp(mj * pj.z, K));
+  }
+  // one addition per run of the wave's lanes that share a node
+  const WaveRuns runs(node);
+  for (int k = 0; k < 4; ++k) runs.add(v[k]);
+  if (node >= 0 && runs.last()) {
     if (lds) {
       for (int k = 0; k < 4; ++k) atomicAdd(&acc[4 * (node - b) + k], v[k]);
     } else {
@@ -164,21 +205,30 @@ __global__ void __launch_bounds__(256) k_kd_size_flags(int64_t n, const double4 
     __syncthreads();
   }
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t node = -1;
+  unsigned long long bits = 0ull;
   if (i < n) {
-    const int64_t node = nop[i];
+    node = nop[i];
     int64_t f = 0;
     if (node >= b && node < e) {
       const double4 pj = pxm[i];
       const double4 c = N.com[node];
       const double dx = pj.x - c.x, dy = pj.y - c.y, dz = pj.z - c.z;
       const double d2 = (dx * dx + dy * dy) + dz * dz;
-      const unsigned long long bits = (unsigned long long)__double_as_longlong(d2);
-      if (lds) atomicMax(&mx[node - b], bits);
-      else atomicMax(&N.s2[node], bits);
+      bits = (unsigned long long)__double_as_longlong(d2);
       const int a = N.axis[node];
       if (a >= 0) f = (a == 0 ? pj.x : (a == 1 ? pj.y : pj.z)) < N.split[node] ? 1 : 0;
+    } else {
+      node = -1;
     }
     flag[i] = f;
+  }
+  // one maximum per run of the wave's lanes that share a node
+  const WaveRuns runs(node);
+  runs.max(bits);
+  if (node >= 0 && runs.last()) {
+    if (lds) atomicMax(&mx[node - b], bits);
+    else atomicMax(&N.s2[node], bits);
   }
   if (lds) {
     __syncthreads();
