@@ -484,8 +484,7 @@ constexpr double kSmallCell = 0.25;
 __device__ inline double face_mixed(int64_t f, double xr0, double xr1, double xr2, double h, double ih, float ihf,
                                     float x0, float x1, float x2, const int64_t *fvo, const double4 *fplane,
                                     const float4 *fplane32, const double4 *fsphere, const double *fvpos,
-                                    const float4 *fvpos32, bool &inside, bool &on_boundary, Counters &K,
-                                    bool geo64) {
+                                    const float4 *fvpos32, bool &inside, bool &on_boundary, Counters &K) {
   const double4 pl = fplane[f];
   if (!(pl.w > 0.0)) return 0.0;
   const double dist = pl.w - (pl.x * xr0 + pl.y * xr1 + pl.z * xr2);
@@ -503,14 +502,6 @@ __device__ inline double face_mixed(int64_t f, double xr0, double xr1, double xr
   const int64_t vs = fvo[f];
   const int nv = (int)(fvo[f + 1] - vs);
   const double d = dist * ih, ad = fabs(d);
-  if (geo64) {
-    // a cell small against the support: binary64 geometry and the math
-    // library's functions (the terms of a small face seen from afar cancel
-    // far below the binary32 geometry's and cores' accuracy), in the
-    // difference form
-    K.n64 += nv;
-    return face_fp64<MathDiff>(pl, dist, ih, xr0, xr1, xr2, fvpos + 3 * vs, nv, K.ne_vis, K.ne_int, K.fd);
-  }
   if (ad < kDegenerate) {
     // particle on the face plane to within 1e-4 h: the whole face from binary64 geometry
     K.n64 += nv;
@@ -813,17 +804,170 @@ __device__ inline void wave_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// One face of a small cell's window in the binary64-geometry kernel.
+struct SmallFace {
+  double P0x, P0y, P0z;  // foot point of the particle on the face plane, about the generator
+  double nx, ny, nz;     // unit normal
+  double ad, dh;         // |d| / h and |d| H(|d|)
+  const double *V;       // the face's vertices (binary64)
+  int nv;                // vertex count; 0 for a face that adds nothing
+  int off;               // its first edge among the window's edges
+  int dpos;              // d > 0
+  int flags;             // 1: an edge sees the foot point on or beyond it (p <= 0),
+                         // 2: an edge through it (p = 0), 4: an edge within 2h
+  double sum;            // the running sum of its edge terms, in edge order
+};
+
+// The faces [f - sub, f - sub + 16) of a cell small against the support,
+// called by the 16 lanes of a group: binary64 geometry and the math
+// library's functions in the difference form (the terms of a small face
+// seen from afar cancel far below the binary32 geometry's and cores'
+// accuracy), as face_fp64 evaluates them.  Lane sub sets up face f (the
+// tests of face_mixed), the window's edges are taken 16 at a time, one per
+// lane, and the first lane of each face's run in a round adds the run's
+// terms to the face's running sum in edge order.  Returns face f's share
+// of sum_f sgn(d_f) C_f (0 past f1 or for a face beyond the support).
+// F, val and face_of are the group's LDS (16 entries each).
+__device__ double small_window(int64_t f, int64_t f1, double xr0, double xr1, double xr2, double h, double ih,
+                               const int64_t *fvo, const double4 *fplane, const double4 *fsphere, const double *fvpos,
+                               bool &inside, bool &on_boundary, Counters &K, SmallFace *F, double *val,
+                               int8_t *face_of, int sub) {
+  SmallFace &me = F[sub];
+  int nv = 0;
+  if (f < f1) {
+    const double4 pl = fplane[f];
+    if (pl.w > 0.0) {
+      const double dist = pl.w - (pl.x * xr0 + pl.y * xr1 + pl.z * xr2);
+      if (dist < 0.0) inside = false;
+      if (dist == 0.0) {
+        on_boundary = true;
+      } else if (fabs(dist) < 2.0 * h) {
+        const double4 sp = fsphere[f];
+        const double sx = xr0 - sp.x, sy = xr1 - sp.y, sz = xr2 - sp.z;
+        const double reach = sp.w + 2.0 * h;
+        if (sx * sx + sy * sy + sz * sz < reach * reach) {
+          ++K.nf_int;
+          const int64_t vs = fvo[f];
+          nv = (int)(fvo[f + 1] - vs);
+          const double d = dist * ih, ad = fabs(d);
+          me.P0x = xr0 + dist * pl.x;
+          me.P0y = xr1 + dist * pl.y;
+          me.P0z = xr2 + dist * pl.z;
+          me.nx = pl.x;
+          me.ny = pl.y;
+          me.nz = pl.z;
+          me.ad = ad;
+          me.dh = dH(ad);
+          me.V = fvpos + 3 * vs;
+          me.dpos = d > 0.0;
+        }
+      }
+    }
+  }
+  // the faces' first edges: an inclusive scan of the edge counts over the group
+  int incl = nv;
+#pragma unroll
+  for (int o = 1; o < 16; o <<= 1) {
+    const int y = __shfl_up(incl, o, 16);
+    if (sub >= o) incl += y;
+  }
+  const int n_edge = __shfl(incl, 15, 16);
+  me.nv = nv;
+  me.off = incl - nv;
+  me.flags = 0;
+  me.sum = 0.0;
+  wave_sync();
+  for (int eb = 0; eb < n_edge; eb += 16) {
+    const int e = eb + sub;
+    int j = -1;
+    bool has = false;
+    double v = 0.0;
+    if (e < n_edge) {
+      // the face of edge e: the last window face starting at or before it
+      // (faces without edges share their successor's start)
+      int lo = 0, hi = 15;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (F[mid].off <= e) lo = mid;
+        else hi = mid - 1;
+      }
+      j = lo;
+      const SmallFace &fc = F[j];
+      const int q = e - fc.off;
+      const int q1 = (q + 1 == fc.nv) ? 0 : q + 1;
+      const double *V = fc.V;
+      const double Ax = V[3 * q], Ay = V[3 * q + 1], Az = V[3 * q + 2];
+      const double Bx = V[3 * q1], By = V[3 * q1 + 1], Bz = V[3 * q1 + 2];
+      const double abx = Bx - Ax, aby = By - Ay, abz = Bz - Az;
+      const double len2 = abx * abx + aby * aby + abz * abz;
+      int fl = 0;
+      if (len2 != 0.0) {
+        const double il = 1.0 / sqrt(len2);
+        const double ex = abx * il, ey = aby * il, ez = abz * il;
+        // in-plane normal of the edge pointing into the polygon: n x e
+        const double mx = fc.ny * ez - fc.nz * ey, my = fc.nz * ex - fc.nx * ez, mz = fc.nx * ey - fc.ny * ex;
+        const double p = ((fc.P0x - Ax) * mx + (fc.P0y - Ay) * my + (fc.P0z - Az) * mz) * ih;
+        if (p <= 0.0) fl |= 1;
+        if (p == 0.0) {
+          fl |= 2;
+        } else {
+          ++K.ne_vis;
+          const double tA = ((Ax - fc.P0x) * ex + (Ay - fc.P0y) * ey + (Az - fc.P0z) * ez) * ih;
+          const double tB = ((Bx - fc.P0x) * ex + (By - fc.P0y) * ey + (Bz - fc.P0z) * ez) * ih;
+          bool integ;
+          const double t = edge_term_diff(fc.ad, fabs(p), tA, tB, fc.dh, integ, K.fd);
+          if (integ) fl |= 4;
+          K.ne_int += integ;
+          v = p > 0.0 ? t : -t;
+          has = true;
+        }
+      }
+      if (fl) atomicOr(&F[j].flags, fl);
+    }
+    face_of[sub] = (int8_t)(j < 0 ? -1 : (has ? j : j + 16));
+    val[sub] = v;
+    wave_sync();
+    // the first lane of each face's run in this round adds the run's terms
+    auto face_at = [&](int t) { return face_of[t] < 0 ? -1 : (face_of[t] & 15); };
+    if (j >= 0 && (sub == 0 || face_at(sub - 1) != j)) {
+      double acc = F[j].sum;
+      for (int t = sub; t < 16 && face_at(t) == j; ++t)
+        if (face_of[t] < 16) acc += val[t];
+      F[j].sum = acc;
+    }
+    wave_sync();
+  }
+  double r = 0.0;
+  if (nv > 0) {
+    double sum = me.sum;
+    const int fl = me.flags;
+    if (!(fl & 4) && !(fl & 2)) sum = -me.dh * ((fl & 1) ? 0.0 : 2.0 * kPi);
+    const double Cf = sum * kInv4Pi;
+    r = me.dpos ? Cf : -Cf;
+  }
+  wave_sync();  // every lane has read the window before the next one is set up
+  return r;
+}
+
 // The pairs the edge-parallel kernel leaves to binary64 geometry, 16 lanes
-// per pair (four pairs per wavefront): lane s takes the cell's faces s,
-// s + 16, ...; each round's 16 shares go through LDS and the group's first
-// lane adds them in face order, so the sum is the serial one.  Two
-// workgroups per SIMD (at most 256 registers): one leaves the library's
-// binary64 functions without latency hiding.
+// per pair (four pairs per wavefront).  A cell small against the support
+// (every face reached, about five edges each) takes its faces 16 at a time:
+// lane s sets up face s of the window, then the window's edges are dealt
+// out 16 at a time, one per lane, and each face's terms are added in edge
+// order by the first lane of its run; otherwise lane s takes the cell's
+// faces s, s + 16, ... with all their edges.  Each round's 16 face shares
+// go through LDS and the group's first lane adds them in face order, so
+// either way every sum is the serial one.  Two workgroups per SIMD (at
+// most 256 registers): one leaves the library's binary64 functions without
+// latency hiding.
 __global__ void __launch_bounds__(256, 2) k_exact_mixed_list(const int64_t *list, const int32_t *n_list,
                                                          const ExactInst *__restrict__ insts,
                                                          const int64_t *__restrict__ chunk0, int n_inst,
                                                          int64_t *counters) {
   __shared__ double share[16][16];
+  __shared__ SmallFace sface[16][16];  // per group: the window's faces (small cells)
+  __shared__ double sval[16][16];      // per group: this round's edge terms
+  __shared__ int8_t sface_of[16][16];  // per group: the window face of each lane's edge (-1: none)
   const int sub = threadIdx.x & 15, grp = threadIdx.x >> 4;
   const int lane = threadIdx.x & 63;
   const uint64_t gmask = 0xffffull << (lane & 48);  // this group's lanes in the wave
@@ -849,9 +993,13 @@ __global__ void __launch_bounds__(256, 2) k_exact_mixed_list(const int64_t *list
     const int64_t f0 = I.cfo[c], f1 = I.cfo[c + 1];
     for (int64_t fb = f0; fb < f1; fb += 16) {
       const int64_t f = fb + sub;
-      const double v = f < f1 ? face_mixed(f, xr0, xr1, xr2, h, ih, ihf, x0, x1, x2, I.fvo, I.fplane, I.fplane32,
-                                           I.fsphere, I.fvpos, I.fvpos32, inside, on_boundary, K, geo64)
-                              : 0.0;
+      double v = 0.0;
+      if (geo64)
+        v = small_window(f, f1, xr0, xr1, xr2, h, ih, I.fvo, I.fplane, I.fsphere, I.fvpos, inside, on_boundary, K,
+                         sface[grp], sval[grp], sface_of[grp], sub);
+      else if (f < f1)
+        v = face_mixed(f, xr0, xr1, xr2, h, ih, ihf, x0, x1, x2, I.fvo, I.fplane, I.fplane32, I.fsphere, I.fvpos,
+                       I.fvpos32, inside, on_boundary, K);
       share[grp][sub] = v;
       // a shared face this cell evaluates: its gift to the twin pair (same
       // particle, twin cell), replacing the edge kernel's
