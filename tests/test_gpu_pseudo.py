@@ -87,6 +87,33 @@ def test_small_and_degenerate(ctx, oracle, workloads):
     assert np.all(gg["branch"][gg["kind"] == 1] == 3)
 
 
+def clustered_cloud(seed):
+    """A few tight clusters (9-39 particles, spread 0.002-0.02) at random
+    centres plus a sparse background: seeds 11 and 16 give pseudo-particles
+    that Newton solves (branch 0), that the bisection solves (branch 1) and
+    whose f keeps its sign over the bracket (branch 2)."""
+    g = np.random.default_rng(seed)
+    cen = g.uniform(0.1, 0.9, (6, 3))
+    pts = [c + g.normal(size=(int(g.integers(9, 40)), 3)) * g.uniform(0.002, 0.02) for c in cen]
+    bg = g.random((int(g.integers(0, 30)), 3))
+    pos = np.clip(np.concatenate(pts + [bg]), 0.001, 0.999)
+    n = len(pos)
+    return pos, g.uniform(0.5, 1.5, n), np.full(n, 0.02)
+
+
+def test_hsolve_every_branch(ctx, oracle):
+    """Every branch of the node h-solve -- Newton, the bisection and the
+    fallback to h0 -- against the oracle: the Newton kernel hands the nodes it
+    cannot solve to the bracket kernel, which must reach the same verdicts."""
+    for seed in (11, 16):
+        say(f"case: pseudo clustered cloud, seed {seed}")
+        pos, m, h = clustered_cloud(seed)
+        ref, g, st = compare(ctx, oracle, pos, m, h, np.array([[0.02, 0.02, 0.02]]), r_part=0.05, theta=0.8)
+        br = g["branch"][g["kind"] == 1]
+        say(f"  branches={np.bincount(br, minlength=4).tolist()}")
+        assert {0, 1, 2} <= set(br.tolist())
+
+
 @pytest.mark.slow
 def test_turbulent_1m_densest_source(ctx, oracle, workloads):
     """Pseudo-particles of the 1,048,576-particle turbulent cloud with one
