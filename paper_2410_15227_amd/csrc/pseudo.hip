@@ -612,8 +612,7 @@ __device__ __forceinline__ void hsums(const HUnits &U, int32_t e, double ax, dou
   }
 }
 
-// f(h) = hfact n(h)^(-1/3) - h and, for Newton, its derivative term, from
-// the unit-order sums (lane 0's)
+// f(he) = hfact n(he)^(-1/3) - he from sw, the sum of the M4 terms at he
 __device__ __forceinline__ double h_residual(double sw, double he, double hfact) {
 #pragma clang fp contract(off)
   const double ih = 1.0 / he;
@@ -628,8 +627,9 @@ constexpr int kBWaves = 16;   // wavefronts per pseudo-particle in the bracket k
 // wavefront per pseudo-particle, with unit-order sums.  A converged node
 // writes its h (branch 0); a node whose step fails (a vanishing derivative,
 // a step out of [h0/100, 100 h0], or 30 steps) is appended to `fails` for
-// the bracket kernel.  Above `bypass` pseudo-particles every node takes h0
-// (branch 3).
+// the bracket kernel, in whatever order the atomics give (each node's result
+// depends on that node alone).  Above `bypass` pseudo-particles every node
+// takes h0 (branch 3).
 __global__ void __launch_bounds__(64 * kHWaves) k_hsolve_newton(int64_t np, const int32_t *plist, HUnits U,
                                                                const double *o_xyz, const double *o_s, double hfact,
                                                                double eps, int64_t bypass, double *o_h,
