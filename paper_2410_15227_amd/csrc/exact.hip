@@ -416,6 +416,21 @@ __device__ inline void flush_counters(int64_t *counters, int64_t nfaces, const C
   atomicAdd((unsigned long long *)&counters[7], (unsigned long long)k.n64);
 }
 
+// Whether a face can reach the support: the particle (at xr about the
+// generator, dist from the face plane) lies within 2h of the face's bounding
+// disk -- the circle of the bounding sphere's radius about its centre,
+// which lies in the face plane and holds the polygon.  The distance from the
+// disk bounds the distance from the polygon from below, and a face farther
+// than 2h adds exactly 0.  The in-plane distance is taken in binary32 and
+// rounded down by 1e-6, so no face within reach is dropped.
+__device__ inline bool disk_within_2h(double xr0, double xr1, double xr2, double dist, double h, const double4 &sp) {
+  const double sx = xr0 - sp.x, sy = xr1 - sp.y, sz = xr2 - sp.z;
+  const double rho2 = (sx * sx + sy * sy + sz * sz) - dist * dist;
+  const double rho = (double)__builtin_sqrtf((float)fmax(rho2, 0.0)) * (1.0 - 1e-6);
+  const double t = fmax(rho - sp.w, 0.0);
+  return dist * dist + t * t < 4.0 * h * h;
+}
+
 // ------------------------------------------------------- binary64 kernel
 __global__ void __launch_bounds__(256) k_exact_fp64(int64_t P, const int32_t *pair_c, const int32_t *pair_p,
                                                    const double *xyz, const double *hh, const double *gen,
@@ -444,10 +459,7 @@ __global__ void __launch_bounds__(256) k_exact_fp64(int64_t P, const int32_t *pa
       continue;
     }
     if (fabs(dist) >= 2.0 * h) continue;
-    const double4 sp = fsphere[f];
-    const double sx = xr0 - sp.x, sy = xr1 - sp.y, sz = xr2 - sp.z;
-    const double reach = sp.w + 2.0 * h;
-    if (sx * sx + sy * sy + sz * sz >= reach * reach) continue;
+    if (!disk_within_2h(xr0, xr1, xr2, dist, h, fsphere[f])) continue;
     ++K.nf_int;
     acc += face_fp64<Math64>(pl, dist, ih, xr0, xr1, xr2, fvpos + 3 * fvo[f], (int)(fvo[f + 1] - fvo[f]), K.ne_vis,
                      K.ne_int, K.fd);
@@ -494,10 +506,7 @@ __device__ inline double face_mixed(int64_t f, double xr0, double xr1, double xr
     return 0.0;
   }
   if (fabs(dist) >= 2.0 * h) return 0.0;
-  const double4 sp = fsphere[f];
-  const double sx = xr0 - sp.x, sy = xr1 - sp.y, sz = xr2 - sp.z;
-  const double reach = sp.w + 2.0 * h;
-  if (sx * sx + sy * sy + sz * sz >= reach * reach) return 0.0;
+  if (!disk_within_2h(xr0, xr1, xr2, dist, h, fsphere[f])) return 0.0;
   ++K.nf_int;
   const int64_t vs = fvo[f];
   const int nv = (int)(fvo[f + 1] - vs);
@@ -842,10 +851,7 @@ __device__ double small_window(int64_t f, int64_t f1, double xr0, double xr1, do
       if (dist == 0.0) {
         on_boundary = true;
       } else if (fabs(dist) < 2.0 * h) {
-        const double4 sp = fsphere[f];
-        const double sx = xr0 - sp.x, sy = xr1 - sp.y, sz = xr2 - sp.z;
-        const double reach = sp.w + 2.0 * h;
-        if (sx * sx + sy * sy + sz * sz < reach * reach) {
+        if (disk_within_2h(xr0, xr1, xr2, dist, h, fsphere[f])) {
           ++K.nf_int;
           const int64_t vs = fvo[f];
           nv = (int)(fvo[f + 1] - vs);
@@ -1182,8 +1188,9 @@ __global__ void __launch_bounds__(64 * kGatherWaves) k_exact_gather(const ExactI
 
 // ------------------------------------ edge-parallel wave kernel (mixed)
 // A wavefront takes 64 consecutive pairs (one per lane) from a work counter.
-//   A1 (lane = pair): the cull over the cell's faces (plane distance, face
-//      sphere against the 2h sphere), kept as a bit mask; the faces within
+//   A1 (lane = pair): the cull over the cell's faces (plane distance, and
+//      the distance from the face's bounding disk in its plane against 2h),
+//      kept as a bit mask; the faces within
 //      reach are listed pair-major with their foot point, |d| and
 //      |d| H(|d|); the chunk's edges are numbered in the same order, and a
 //      bit in LDS marks where each listed face's edges begin;
@@ -1447,18 +1454,25 @@ __global__ void __launch_bounds__(64 * kFlatWaves, 4) k_exact_edges(
           inside &= !(real & (dist < 0.0));
           on_boundary |= real & (dist == 0.0);
           const double sx = xr0 - sp.x, sy = xr1 - sp.y, sz = xr2 - sp.z;
-          const double s2 = sx * sx + sy * sy + sz * sz;
-          const double reach = sp.r + 2.0 * h;
+          // the sphere's centre lies in the face plane, so the foot point's
+          // squared distance from it is s2 - dist^2
+          const double rho2 = (sx * sx + sy * sy + sz * sz) - dist * dist;
+          // The face's polygon lies in the disk of the sphere's radius about
+          // that centre, so the particle's distance from the disk,
+          // sqrt(dist^2 + max(rho - R, 0)^2), bounds its distance from the
+          // polygon from below; a face farther than 2h adds exactly 0.  rho
+          // is taken in binary32 and rounded down, so that no face within
+          // reach is dropped.
+          const double rho = (double)__builtin_sqrtf((float)fmax(rho2, 0.0)) * (1.0 - 1e-6);
+          const double t = fmax(rho - sp.r, 0.0);
           // a shared face is evaluated by the lower-numbered of its two
           // cells, for both pairs of the particle
           const bool mine = L.wtw[j] >= -1;
-          const bool near = real & mine & (dist != 0.0) & (fabs(dist) < 2.0 * h) & (s2 < reach * reach);
-          // the sphere's centre lies in the face plane, so the foot point's
-          // squared distance from it is s2 - dist^2: a foot point beyond the
-          // sphere by kFarFoot h is outside the polygon and clear of its
-          // vertices
+          const bool near = real & mine & (dist != 0.0) & (fabs(dist) < 2.0 * h) & (dist * dist + t * t < 4.0 * h * h);
+          // a foot point beyond the sphere by kFarFoot h is outside the
+          // polygon and clear of its vertices
           const double rf = sp.r + kFarFoot * h;
-          const bool far = s2 - dist * dist > rf * rf;
+          const bool far = rho2 > rf * rf;
           const bool deg = near & (fabs(dist * ih) < kOnPlane);
           again |= deg;
           const bool keep = near & !deg & (L.wnv[j] > 0);  // a face without edges adds nothing
