@@ -11,7 +11,10 @@ workspace cap, and the summation orders include/sphmap.h states.
     within it;
   - M_c and each particle's inverse-map sum follow the fixed strided-plus-
     butterfly order the header describes: numpy, adding the exported
-    weights in that order, reproduces them bit for bit."""
+    weights in that order, reproduces them bit for bit;
+  - empty and oversized inputs get the errors the header states (EINVAL
+    before any device work, outputs untouched), and interpolation onto no
+    particles is a valid call that writes nothing."""
 import sys
 
 import numpy as np
@@ -144,4 +147,50 @@ def test_documented_summation_orders(ctx, grid):
         v = _strided(pw[s:e] * q[pcell[s:e]], 16)
         assert (v / cov_i if cov_i > 0 else 0.0) == out[i], i
     res.pairs.free()
+    dt.free()
+
+
+def test_empty_and_oversized_inputs(ctx, grid):
+    import paper_2410_15227_amd as pkg
+    from paper_2410_15227_amd import _native
+    say("case: empty and oversized inputs")
+    pos, m, h, tess = grid
+    dt = ctx.upload(tess)
+    none3 = np.zeros((0, 3))
+    none1 = np.zeros(0)
+    # forward map of no particles: EINVAL, the mass buffer left as it was
+    sentinel = torch.full((tess.n_cells,), -7.0, dtype=torch.float64, device="cuda")
+    with pytest.raises(pkg.SphmapError) as e:
+        pkg.map_particles_to_cells(ctx, dt, none3, none1, none1, out_mass=sentinel)
+    assert e.value.code == -1  # SPHMAP_EINVAL
+    torch.cuda.synchronize()
+    assert bool(torch.all(sentinel == -7.0))
+    # n = 2^31 through the C-ABI: refused by its range check before any
+    # pointer is used (the buffers hold one particle)
+    x = torch.as_tensor(pos[:1], dtype=torch.float64, device="cuda").contiguous()
+    hh = torch.as_tensor(h[:1], dtype=torch.float64, device="cuda")
+    mm = torch.as_tensor(m[:1], dtype=torch.float64, device="cuda")
+    rc = _native.lib().map_particles_to_cells(ctx.handle, dt.handle, 1 << 31, x.data_ptr(), hh.data_ptr(),
+                                              mm.data_ptr(), 1, 0, sentinel.data_ptr(), None, None, None, None)
+    assert rc == -1
+    torch.cuda.synchronize()
+    assert bool(torch.all(sentinel == -7.0))
+    # inverse map without a list, of no particles
+    with pytest.raises(pkg.SphmapError) as e:
+        pkg.map_cells_to_particles(ctx, None, np.ones(tess.n_cells), tess=dt, xyz=none3, h=none1)
+    assert e.value.code == -1
+    # pseudo-particle builders and the Voronoi builder on no points
+    for tree in ("octree", "kd"):
+        with pytest.raises(pkg.SphmapError) as e:
+            pkg.build_pseudo_particles(ctx, none3, none1, none1, [[0.5, 0.5, 0.5]], tree=tree)
+        assert e.value.code == -1
+    with pytest.raises(pkg.SphmapError) as e:
+        pkg.build_voronoi(ctx, none3, n_lloyd=0)
+    assert e.value.code == -1
+    # interpolation onto no particles is valid and returns an empty array
+    ps = pkg.build_pseudo_particles(ctx, pos, h, m, [[0.9, 0.9, 0.9]], r_part=0.05, theta=0.8)
+    out = pkg.interpolate_to_particles(ctx, none3, ps, torch.ones(ps["kind"].shape[0], dtype=torch.float64,
+                                                                  device="cuda"))
+    torch.cuda.synchronize()
+    assert out.shape == (0,)
     dt.free()
