@@ -871,12 +871,15 @@ void node_hsolve(Ctx &ctx, int64_t np, const int32_t *plist, int64_t nu, const d
                                                                         o_h, o_branch, bcount, fails, n_fails);
   SPH_LAUNCH_CHECK();
   kt1.done();
-  // one workgroup per node that Newton did not solve (the rest exit at once)
-  KernelTimer kt2(&ctx, "node_hsolve_bracket", s);
-  k_hsolve_bracket<<<(unsigned)np, 64 * kBWaves, 0, s>>>(fails, n_fails, U, o_xyz, o_s, hfact, eps, o_h, o_branch,
-                                                         bcount);
-  SPH_LAUNCH_CHECK();
-  kt2.done();
+  // one workgroup per node that Newton did not solve (the rest exit at
+  // once); above the bypass every node took h0 and none is left
+  if (np <= bypass) {
+    KernelTimer kt2(&ctx, "node_hsolve_bracket", s);
+    k_hsolve_bracket<<<(unsigned)np, 64 * kBWaves, 0, s>>>(fails, n_fails, U, o_xyz, o_s, hfact, eps, o_h, o_branch,
+                                                           bcount);
+    SPH_LAUNCH_CHECK();
+    kt2.done();
+  }
   kt.done();
 }
 
