@@ -112,20 +112,31 @@ __global__ void k_children(NodeArrays N, int64_t b, int64_t e, int level, int64_
   }
 }
 
-// Leaves: sums over members in ascending particle index (selection order).
+// Leaves: sums over members in ascending particle index.  A leaf whose
+// members already lie in ascending index (every leaf at the depth limit:
+// its members share the whole key, and the key sort is stable) is summed in
+// one pass and marked in asc; any other (at most leaf_max members) takes
+// them in order by selection.
 __global__ void k_leaf_moments(NodeArrays N, int64_t nn, const int32_t *sidx, const double *xyz, const double *m,
-                               double *M, double4 *S) {
+                               double *M, double4 *S, int8_t *asc) {
 #pragma clang fp contract(off)
   int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (node >= nn || N.nchild[node] != 0) return;
   const int32_t f = N.first[node], c = N.count[node];
+  bool up = true;
+  for (int32_t u = f + 1; u < f + c && up; ++u) up = sidx[u] > sidx[u - 1];
+  asc[node] = up ? 1 : 0;
   double sm = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
   int32_t prev = -1;
   for (int32_t t = 0; t < c; ++t) {
     int32_t best = INT32_MAX;
-    for (int32_t u = f; u < f + c; ++u) {
-      int32_t j = sidx[u];
-      if (j > prev && j < best) best = j;
+    if (up) {
+      best = sidx[f + t];
+    } else {
+      for (int32_t u = f; u < f + c; ++u) {
+        int32_t j = sidx[u];
+        if (j > prev && j < best) best = j;
+      }
     }
     prev = best;
     const double mj = m[best];
@@ -187,7 +198,13 @@ __global__ void __launch_bounds__(256) k_node_size(NodeArrays N, int64_t nn, con
   const int lane = threadIdx.x & 63;
   if (node >= nn) return;
   const int32_t f = N.first[node], c = N.count[node];
-  if (c > kBigNode) return;
+  if (c > kBigNode) {  // k_node_size_big combines its chunks into these
+    if (lane == 0) {
+      s2[node] = 0.0;
+      minidx[node] = INT32_MAX;
+    }
+    return;
+  }
   const double4 g = com[node];
   double mx = 0.0;
   int32_t mi = INT32_MAX;
@@ -209,22 +226,30 @@ __global__ void __launch_bounds__(256) k_node_size(NodeArrays N, int64_t nn, con
   }
 }
 
+// Chunks of kBigNode members: none for a node handled by k_node_size.
 __global__ void k_flag_big(NodeArrays N, int64_t nn, int64_t *flag) {
   const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (node < nn) flag[node] = N.count[node] > kBigNode ? 1 : 0;
+  if (node < nn) {
+    const int32_t c = N.count[node];
+    flag[node] = c > kBigNode ? (c + kBigNode - 1) / kBigNode : 0;
+  }
 }
 
+// The node of every chunk (off: each node's first chunk).
 __global__ void k_list_big(NodeArrays N, int64_t nn, const int64_t *off, int32_t *list) {
   const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (node < nn && N.count[node] > kBigNode) list[off[node]] = (int32_t)node;
+  if (node < nn && N.count[node] > kBigNode)
+    for (int64_t q = off[node]; q < off[node + 1]; ++q) list[q] = (int32_t)node;
 }
 
-// The same for the nodes above kBigNode members, one workgroup per node
-// (grid-stride over the device-side list; max and min do not depend on the
-// order in which the waves finish).
-__global__ void __launch_bounds__(1024) k_node_size_big(NodeArrays N, const int32_t *list, const int64_t *n_list,
-                                                       const int32_t *sidx, const double4 *sx, const double4 *com,
-                                                       double *s2, int32_t *minidx) {
+// The same for the nodes above kBigNode members, one workgroup per chunk of
+// kBigNode members (grid-stride over the device-side chunk list); the
+// chunks combine by atomic maximum (non-negative binary64 values order as
+// their bit patterns) and minimum, which do not depend on the order in
+// which they finish.
+__global__ void __launch_bounds__(1024) k_node_size_big(NodeArrays N, const int32_t *list, const int64_t *off,
+                                                       const int64_t *n_list, const int32_t *sidx, const double4 *sx,
+                                                       const double4 *com, double *s2, int32_t *minidx) {
 #pragma clang fp contract(off)
   __shared__ double smx[16];
   __shared__ int32_t smi[16];
@@ -232,11 +257,13 @@ __global__ void __launch_bounds__(1024) k_node_size_big(NodeArrays N, const int3
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
     const int32_t node = list[b];
-    const int32_t f = N.first[node], c = N.count[node];
+    const int32_t k = (int32_t)(b - off[node]);  // the chunk within the node
+    const int32_t f0 = N.first[node], c = N.count[node];
+    const int32_t f = f0 + k * kBigNode, fe = min(f0 + c, f + kBigNode);
     const double4 g = com[node];
     double mx = 0.0;
     int32_t mi = INT32_MAX;
-    for (int32_t t = f + (int32_t)threadIdx.x; t < f + c; t += (int32_t)blockDim.x) {
+    for (int32_t t = f + (int32_t)threadIdx.x; t < fe; t += (int32_t)blockDim.x) {
       const int32_t j = sidx[t];
       const double4 p = sx[t];
       const double dx = p.x - g.x, dy = p.y - g.y, dz = p.z - g.z;
@@ -258,8 +285,8 @@ __global__ void __launch_bounds__(1024) k_node_size_big(NodeArrays N, const int3
         mx = fmax(mx, smx[w]);
         mi = min(mi, smi[w]);
       }
-      s2[node] = mx;
-      minidx[node] = mi;
+      atomicMax((unsigned long long *)&s2[node], (unsigned long long)__double_as_longlong(mx));
+      atomicMin(&minidx[node], mi);
     }
     __syncthreads();
   }
@@ -348,7 +375,7 @@ __global__ void k_entries(int64_t nu, const int32_t *units, NodeArrays N, const 
                           const double *m, const double *M, const double4 *com, const double *s2,
                           const int32_t *minidx, double *o_xyz, double *o_h, double *o_m, double *o_s,
                           int32_t *o_kind, int64_t *o_first, int64_t *o_count, int32_t *o_branch, double4 *upos,
-                          int32_t *plist, const uint64_t *label, uint64_t *o_label) {
+                          int32_t *plist, const uint64_t *label, uint64_t *o_label, const int8_t *asc) {
   int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= nu) return;
   const int32_t node = units[u];
@@ -392,9 +419,13 @@ __global__ void k_entries(int64_t nu, const int32_t *units, NodeArrays N, const 
     int32_t prev = -1;
     for (int32_t t = 0; t < c; ++t) {
       int32_t best = INT32_MAX;
-      for (int32_t q = f; q < f + c; ++q) {
-        int32_t j = sidx[q];
-        if (j > prev && j < best) best = j;
+      if (asc[node]) {
+        best = sidx[f + t];
+      } else {
+        for (int32_t q = f; q < f + c; ++q) {
+          int32_t j = sidx[q];
+          if (j > prev && j < best) best = j;
+        }
       }
       prev = best;
       emit_real(best);
@@ -406,7 +437,8 @@ __global__ void k_entries(int64_t nu, const int32_t *units, NodeArrays N, const 
 // starting at or before it; an opened leaf's particles are its entries in
 // ascending index, so a particle's entry is offset by its rank among them.
 __global__ void k_owner(int64_t n, const int64_t *flag, const int64_t *uoff, const int32_t *units, NodeArrays N,
-                        const int8_t *acc, const int64_t *eoff, const int32_t *sidx, int64_t *owner) {
+                        const int8_t *acc, const int64_t *eoff, const int32_t *sidx, const int8_t *asc,
+                        int64_t *owner) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
   const int64_t u = uoff[q] + flag[q] - 1;
@@ -415,7 +447,9 @@ __global__ void k_owner(int64_t n, const int64_t *flag, const int64_t *uoff, con
   int64_t e = eoff[u];
   if (!acc[node]) {
     const int32_t f = N.first[node], c = N.count[node];
-    for (int32_t t = f; t < f + c; ++t) e += sidx[t] < j;
+    if (asc[node]) e += q - f;  // members in ascending index: the rank is the position
+    else
+      for (int32_t t = f; t < f + c; ++t) e += sidx[t] < j;
   }
   owner[j] = e;
 }
@@ -938,7 +972,8 @@ void pseudo_build(Ctx &ctx, PseudoArgs &a, hipStream_t s) {
   double *s2 = ar.get<double>("ps_s2", nn);
   int32_t *minidx = ar.get<int32_t>("ps_minidx", nn);
   int8_t *acc = ar.get<int8_t>("ps_acc", nn);
-  k_leaf_moments<<<(unsigned)div_up(nn, 256), 256, 0, s>>>(N, nn, sidx, a.xyz, a.m, M, S);
+  int8_t *asc = ar.get<int8_t>("ps_asc", nn);
+  k_leaf_moments<<<(unsigned)div_up(nn, 256), 256, 0, s>>>(N, nn, sidx, a.xyz, a.m, M, S, asc);
   SPH_LAUNCH_CHECK();
   for (int level = (int)loff.size() - 2; level >= 0; --level) {
     const int64_t b = loff[level], e = loff[level + 1];
@@ -957,16 +992,17 @@ void pseudo_build(Ctx &ctx, PseudoArgs &a, hipStream_t s) {
   {
     int64_t *bflag = ar.get<int64_t>("ps_bflag", nn + 1);
     int64_t *boff = ar.get<int64_t>("ps_boff", nn + 1);
-    int32_t *blist = ar.get<int32_t>("ps_blist", std::max<int64_t>(nn, 1));
+    // the nodes of a level are disjoint, so its big nodes hold at most
+    // n / kBigNode + (their number, itself at most n / kBigNode) chunks
+    const int64_t bound = std::max<int64_t>(1, (int64_t)(loff.size() - 1) * (2 * (n / kBigNode) + 1));
+    int32_t *blist = ar.get<int32_t>("ps_blist", bound);
     k_flag_big<<<(unsigned)div_up(nn, 256), 256, 0, s>>>(N, nn, bflag);
     SPH_LAUNCH_CHECK();
     scan_exclusive_i64(ar, bflag, boff, nn, true, s);
     k_list_big<<<(unsigned)div_up(nn, 256), 256, 0, s>>>(N, nn, boff, blist);
     SPH_LAUNCH_CHECK();
-    // at most n / kBigNode big nodes per level
-    const int64_t bound = std::max<int64_t>(1, (int64_t)(loff.size() - 1) * (n / kBigNode + 1));
-    k_node_size_big<<<(unsigned)std::min<int64_t>(bound, 2048), 1024, 0, s>>>(N, blist, boff + nn, sidx, sx, com,
-                                                                              s2, minidx);
+    k_node_size_big<<<(unsigned)std::min<int64_t>(bound, 2048), 1024, 0, s>>>(N, blist, boff, boff + nn, sidx, sx,
+                                                                              com, s2, minidx);
     SPH_LAUNCH_CHECK();
   }
   double *src = ar.get<double>("ps_src", 3 * a.n_src);
@@ -1026,10 +1062,10 @@ void pseudo_build(Ctx &ctx, PseudoArgs &a, hipStream_t s) {
   double *o_s = a.o_s ? a.o_s : ar.get<double>("ps_os", n_out);
   k_entries<<<(unsigned)div_up(nu, 256), 256, 0, s>>>(nu, units, N, acc, eoff, poff, sidx, a.xyz, a.h, a.m, M, com,
                                                       s2, minidx, a.o_xyz, a.o_h, a.o_m, o_s, a.o_kind, a.o_first,
-                                                      a.o_count, a.o_branch, upos, plist, label, a.o_label);
+                                                      a.o_count, a.o_branch, upos, plist, label, a.o_label, asc);
   SPH_LAUNCH_CHECK();
   if (a.o_owner && n > 0) {
-    k_owner<<<(unsigned)div_up(n, 256), 256, 0, s>>>(n, flag, uoff, units, N, acc, eoff, sidx, a.o_owner);
+    k_owner<<<(unsigned)div_up(n, 256), 256, 0, s>>>(n, flag, uoff, units, N, acc, eoff, sidx, asc, a.o_owner);
     SPH_LAUNCH_CHECK();
   }
 

@@ -114,6 +114,23 @@ def test_hsolve_every_branch(ctx, oracle):
         assert {0, 1, 2} <= set(br.tolist())
 
 
+def test_coincident_particles(ctx, oracle):
+    """200,000 particles at one point over a sparse background: the octree
+    runs to its depth limit through a chain of single-child nodes of more
+    than 4,096 members each, whose sizes are reduced in chunks (more chunks
+    than the tree has nodes)."""
+    say("case: pseudo 200000 coincident particles + 2000 background")
+    g = np.random.default_rng(12)
+    pos = np.concatenate([np.full((200000, 3), 0.3712345), g.random((2000, 3))])
+    m = g.uniform(0.5, 1.5, len(pos))
+    h = np.full(len(pos), 0.02)
+    ref, gg, st = compare(ctx, oracle, pos, m, h, np.array([[0.9, 0.9, 0.9]]), r_part=0.05, theta=0.5)
+    say(f"  entries={len(gg['m'])} nodes={st['n_nodes']} branches={st['branch_count']}")
+    # the chain alone takes 21 levels x ceil(200000 / 4096) chunks, more
+    # than the tree's nodes: the case a node-sized chunk list would overflow
+    assert st["n_nodes"] < 21 * -(-200000 // 4096)
+
+
 @pytest.mark.slow
 def test_turbulent_1m_densest_source(ctx, oracle, workloads):
     """Pseudo-particles of the 1,048,576-particle turbulent cloud with one
