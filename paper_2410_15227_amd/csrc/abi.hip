@@ -153,6 +153,11 @@ int sphmap_destroy(sphmap_ctx *ctx) {
   ctx->c.pool.release();
   if (ctx->c.pinned) (void)hipHostFree(ctx->c.pinned);
   ctx->c.pinned = nullptr;
+  if (ctx->c.side) {
+    (void)hipEventDestroy(ctx->c.ev_fork);
+    (void)hipEventDestroy(ctx->c.ev_join);
+    (void)hipStreamDestroy(ctx->c.side);
+  }
   delete ctx;
   return SPHMAP_OK;
 }
@@ -349,8 +354,25 @@ int map_particles_to_cells(sphmap_ctx *ctx, const sphmap_tess *tess, int64_t n, 
       sphmap::particles_prepare(C, pd, s);
       sphmap::find_pairs(C, tess->t, pd, *P, s);
       sphmap::exact_integral(C, tess->t, pd, *P, precision, s);
-      sphmap::particle_major(C, *P, s);
-      sphmap::cell_reduce(C, tess->t, pd, *P, normalize != 0, d_cell_mass, d_cell_density, s);
+      if (normalize == 0) {
+        // the cell sums need only the weights: they run on the side stream
+        // while the particle-major copy runs on the caller's
+        hipStream_t s2 = C.side_stream();
+        SPH_HIP(hipEventRecord(C.ev_fork, s));
+        SPH_HIP(hipStreamWaitEvent(s2, C.ev_fork, 0));
+        sphmap::cell_reduce(C, tess->t, pd, *P, false, d_cell_mass, d_cell_density, s2);
+        SPH_HIP(hipEventRecord(C.ev_join, s2));
+        try {
+          sphmap::particle_major(C, *P, s);
+        } catch (...) {  // joined on the error path too
+          (void)hipStreamWaitEvent(s, C.ev_join, 0);
+          throw;
+        }
+        SPH_HIP(hipStreamWaitEvent(s, C.ev_join, 0));
+      } else {  // normalised sums divide by the coverage the copy computes
+        sphmap::particle_major(C, *P, s);
+        sphmap::cell_reduce(C, tess->t, pd, *P, true, d_cell_mass, d_cell_density, s);
+      }
     } catch (const sphmap::Error &e) {
       if (e.code != SPHMAP_ENOMEM || !C.ws.limit) throw;
       workspace_refused(C, e, workspace_need(C, n, P->n_pairs, tess->t, !pairs_out));

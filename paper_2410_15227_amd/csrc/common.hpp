@@ -123,6 +123,18 @@ struct Ctx {
   int n_cu = 0, exact_per_cu = 0;  // compute units; resident Exact workgroups per CU
   bool autotune = false;
   std::map<int, TuneChoice> tuned;  // by floor(log2(pairs)) of the Exact launch
+  // A second stream (default priority) for work that can overlap the
+  // caller's, forked from and joined back to it by the two events.
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t side_stream() {
+    if (!side) {
+      SPH_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+      SPH_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+      SPH_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+    }
+    return side;
+  }
   // Pinned host staging of at least `bytes`.  Its previous contents must no
   // longer be needed by queued copies (every forward call synchronises its
   // stream once, for the pair count, before it stages a table).
