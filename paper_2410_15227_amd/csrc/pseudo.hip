@@ -24,8 +24,12 @@
 // particles; self term included).  Newton from h0 = h_fact 2 s to
 // |h_new - h| / h0 < eps_h; Newton fails after 30 steps, when an iterate
 // leaves [1e-2 h0, 1e2 h0] or when |f'| < 1e-12; then bisection on
-// [1e-2 h0, 1e2 h0] when f changes sign there, else h0.  The sums over units
-// run in unit order, tiled through LDS, one thread per pseudo-particle.
+// [1e-2 h0, 1e2 h0] when f changes sign there, else h0.  Newton's sums over
+// units run in unit order, one wavefront per pseudo-particle; the nodes it
+// leaves go to a second kernel, 16 wavefronts per node, whose bracket and
+// bisection steps decide from fixed-order tree sums (falling back to the
+// unit-order sums within their rounding margin), so every decision is that
+// of the unit-order sums.
 #include "common.hpp"
 
 namespace sphmap {
