@@ -327,13 +327,14 @@ void radix_sort_impl(Arena &ar, K *keys, int32_t *vals, int64_t n, int bits, hip
 // with consecutive threads on consecutive positions of each digit's run.
 namespace {
 
-// 4,096 items per tile: a 9-bit digit's runs then average 8 items, so the
-// scatter's stores touch half as many lines as with 2,048 (the tile's LDS,
-// 78 KB at 512 digits, still lets two workgroups share a CU)
+// IT items per thread: 8 (2,048 per tile), or 16 (4,096) for a long sort
+// by 9-bit digits -- a digit's runs then average 8 items, as 8-bit digits'
+// do in the smaller tile, so the scatter's stores touch half as many lines,
+// and the tile's LDS (78 KB) still lets two workgroups share a CU.  Short
+// sorts keep the smaller tiles for more workgroups in flight; 10-bit digits
+// keep them for their LDS.
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
-constexpr int kSortTile = kSortThreads * kSortItems;
-constexpr int kSortWaveItems = kSortTile / 4;
+constexpr int64_t kLongSort = (int64_t)1 << 23;  // items from which 4,096-item tiles are used
 
 // Workgroups are dealt to the 8 XCDs in turn; give each XCD a contiguous run
 // of tiles, so that neighbouring tiles -- which fill the same output lines
@@ -347,9 +348,10 @@ __device__ inline int64_t xcd_tile(int64_t ntiles) {
 // The item count is n, or *dn when dn is given (a count known only on the
 // device, at most n: the launch covers n items' tiles and the tiles past *dn
 // count nothing and write nothing).
-template <int NB>
+template <int NB, int IT>
 __global__ void __launch_bounds__(kSortThreads) k_kv_hist(const uint32_t *key, int64_t n, const int64_t *dn,
                                                          int shift, int rb, int64_t ntiles, int64_t *hist) {
+  constexpr int kTileN = kSortThreads * IT;  // items per tile
   __shared__ unsigned h[NB];
   if (dn) n = *dn;
   const int nd = 1 << rb;
@@ -357,10 +359,10 @@ __global__ void __launch_bounds__(kSortThreads) k_kv_hist(const uint32_t *key, i
   __syncthreads();
   // XCD-aware like the scatter: neighbouring tiles write neighbouring counts
   const int64_t tile = xcd_tile(ntiles);
-  const int64_t base = tile * kSortTile;
+  const int64_t base = tile * kTileN;
   const unsigned mask = (unsigned)nd - 1u;
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
+  for (int j = 0; j < IT; ++j) {
     const int64_t i = base + (int64_t)j * kSortThreads + threadIdx.x;
     if (i < n) atomicAdd(&h[(key[i] >> shift) & mask], 1u);
   }
@@ -368,36 +370,37 @@ __global__ void __launch_bounds__(kSortThreads) k_kv_hist(const uint32_t *key, i
   for (int d = threadIdx.x; d < nd; d += kSortThreads) hist[(int64_t)d * ntiles + tile] = h[d];
 }
 
-template <int NB>
+template <int NB, int IT>
 __global__ void __launch_bounds__(kSortThreads) k_kv_scatter(const uint32_t *kin, const int32_t *ain,
                                                             const double *bin, int64_t n, const int64_t *dn,
                                                             int shift, int rb, int64_t ntiles, const int64_t *off,
                                                             uint32_t *kout, int32_t *aout, double *bout) {
+  constexpr int kTileN = kSortThreads * IT;  // items per tile
   constexpr int kPer = NB / kSortThreads > 0 ? NB / kSortThreads : 1;  // digits per thread
   __shared__ unsigned cnt[4][NB];  // per wave: running count, then the wave's offset
   __shared__ unsigned tex[NB];     // the tile's exclusive offset per digit
   __shared__ int64_t goff[NB];     // output position of the digit's run minus tex
-  __shared__ uint32_t sk[kSortTile];
-  __shared__ int32_t sa[kSortTile];
-  __shared__ double sbv[kSortTile];
+  __shared__ uint32_t sk[kTileN];
+  __shared__ int32_t sa[kTileN];
+  __shared__ double sbv[kTileN];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int nd = 1 << rb;
   const unsigned mask = (unsigned)nd - 1u;
   for (int d = t; d < nd; d += kSortThreads) cnt[0][d] = cnt[1][d] = cnt[2][d] = cnt[3][d] = 0u;
   __syncthreads();
   const int64_t tile = xcd_tile(ntiles);
-  const int64_t tile0 = tile * kSortTile;
+  const int64_t tile0 = tile * kTileN;
   if (dn) n = *dn;
   if (tile0 >= n) return;  // a tile past the count (uniform over the workgroup)
-  const int64_t wbase = tile0 + (int64_t)w * kSortWaveItems;
+  const int64_t wbase = tile0 + (int64_t)w * (kTileN / 4);
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes below this one
-  uint32_t kk[kSortItems];
-  int32_t aa[kSortItems];
-  double bb[kSortItems];
-  unsigned rk[kSortItems];  // rank within the wave's run | digit << 16; ~0 for no item
+  uint32_t kk[IT];
+  int32_t aa[IT];
+  double bb[IT];
+  unsigned rk[IT];  // rank within the wave's run | digit << 16; ~0 for no item
   // all of the wave's loads first, so that they are in flight together
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
+  for (int j = 0; j < IT; ++j) {
     const int64_t i = std::min(wbase + (int64_t)j * 64 + lane, n - 1);  // past n: read, not used
     kk[j] = kin[i];
     aa[j] = ain[i];
@@ -406,7 +409,7 @@ __global__ void __launch_bounds__(kSortThreads) k_kv_scatter(const uint32_t *kin
   // rank round by round; a wave's LDS operations complete in order, so the
   // counter a lane reads is the one the previous round's first lane wrote
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
+  for (int j = 0; j < IT; ++j) {
     const bool valid = wbase + (int64_t)j * 64 + lane < n;
     const unsigned d = (kk[j] >> shift) & mask;
     uint64_t peers = __ballot(valid);
@@ -452,7 +455,7 @@ __global__ void __launch_bounds__(kSortThreads) k_kv_scatter(const uint32_t *kin
   }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
+  for (int j = 0; j < IT; ++j) {
     if (rk[j] != ~0u) {
       const unsigned d = rk[j] >> 16;
       const unsigned p = tex[d] + cnt[w][d] + (rk[j] & 0xffffu);
@@ -462,7 +465,7 @@ __global__ void __launch_bounds__(kSortThreads) k_kv_scatter(const uint32_t *kin
     }
   }
   __syncthreads();
-  const int nt = (int)std::min<int64_t>(kSortTile, n - tile0);
+  const int nt = (int)std::min<int64_t>(kTileN, n - tile0);
   for (int p = t; p < nt; p += kSortThreads) {
     const uint32_t k = sk[p];
     const int64_t g = goff[(k >> shift) & mask] + p;
@@ -474,17 +477,18 @@ __global__ void __launch_bounds__(kSortThreads) k_kv_scatter(const uint32_t *kin
   }
 }
 
-template <int NB>
+template <int NB, int IT>
 void kv_pass(Arena &ar, int64_t n, const int64_t *dn, int shift, int rb, const uint32_t *kin, const int32_t *ain,
              const double *bin, uint32_t *kout, int32_t *aout, double *bout, hipStream_t s) {
-  const int64_t ntiles = div_up(n, kSortTile);
+  constexpr int kTileN = kSortThreads * IT;
+  const int64_t ntiles = div_up(n, kTileN);
   const int64_t m = ((int64_t)1 << rb) * ntiles;
   int64_t *hist = ar.get<int64_t>("kv_hist", m + 1);
   int64_t *off = ar.get<int64_t>("kv_off", m + 1);
-  k_kv_hist<NB><<<(unsigned)ntiles, kSortThreads, 0, s>>>(kin, n, dn, shift, rb, ntiles, hist);
+  k_kv_hist<NB, IT><<<(unsigned)ntiles, kSortThreads, 0, s>>>(kin, n, dn, shift, rb, ntiles, hist);
   SPH_LAUNCH_CHECK();
   scan_exclusive_i64(ar, hist, off, m, false, s);
-  k_kv_scatter<NB><<<(unsigned)ntiles, kSortThreads, 0, s>>>(kin, ain, bin, n, dn, shift, rb, ntiles, off, kout,
+  k_kv_scatter<NB, IT><<<(unsigned)ntiles, kSortThreads, 0, s>>>(kin, ain, bin, n, dn, shift, rb, ntiles, off, kout,
                                                               aout, bout);
   SPH_LAUNCH_CHECK();
 }
@@ -511,11 +515,13 @@ void sort_by_key_kv(Arena &ar, int64_t n, int bits, const uint32_t *kin, const i
     int32_t *ad = last ? aout : at[p & 1];
     double *bd = last ? bout : bt[p & 1];
     if (rb <= 8)
-      kv_pass<256>(ar, n, dn, shift, rb, ks, as, bs, kd, ad, bd, s);
+      kv_pass<256, 8>(ar, n, dn, shift, rb, ks, as, bs, kd, ad, bd, s);
+    else if (rb == 9 && n >= kLongSort)
+      kv_pass<512, 16>(ar, n, dn, shift, rb, ks, as, bs, kd, ad, bd, s);
     else if (rb == 9)
-      kv_pass<512>(ar, n, dn, shift, rb, ks, as, bs, kd, ad, bd, s);
+      kv_pass<512, 8>(ar, n, dn, shift, rb, ks, as, bs, kd, ad, bd, s);
     else
-      kv_pass<1024>(ar, n, dn, shift, rb, ks, as, bs, kd, ad, bd, s);
+      kv_pass<1024, 8>(ar, n, dn, shift, rb, ks, as, bs, kd, ad, bd, s);
     ks = kd;
     as = ad;
     bs = bd;
