@@ -288,18 +288,10 @@ __device__ double boundary_S(int64_t f0, int64_t f1, const double4 *fplane, cons
   return om * kInv4Pi;
 }
 
-// One edge from binary64 geometry in the difference form of the edge kernel
-// (each piece's angles and logarithm from their differences, the angle term
-// from the span), with the math library's functions: for cells small
-// against the support, whose per-endpoint terms cancel far below the mixed
-// cores' accuracy.  Defined after the pieces.
-struct MathDiff {};
-__device__ double edge_term_diff(double ad, double p, double tA, double tB, double dh, bool &integ, EdgeCount &cnt);
-
 // One face with binary64 geometry about the generator, particle at xr; the
 // edges are evaluated with M's transcendental cores (the math library for
 // the binary64 path, the mixed cores where the mixed path meets a face
-// within 1e-4 h of the particle) or, for MathDiff, in the difference form.
+// within 1e-4 h of the particle).
 template <class M>
 __device__ double face_fp64(const double4 pl, double dist, double ih, double xr0, double xr1, double xr2,
                             const double *V, int nv, int &ne_vis, int &ne_int, EdgeCount &cnt) {
@@ -329,11 +321,7 @@ __device__ double face_fp64(const double4 pl, double dist, double ih, double xr0
     const double tA = ((Ax - P0x) * ex + (Ay - P0y) * ey + (Az - P0z) * ez) * ih;
     const double tB = ((Bx - P0x) * ex + (By - P0y) * ey + (Bz - P0z) * ez) * ih;
     bool integ;
-    double v;
-    if constexpr (std::is_same<M, MathDiff>::value)
-      v = edge_term_diff(ad, fabs(p), tA, tB, dh, integ, cnt);
-    else
-      v = edge_term_geo64<M>(ad, fabs(p), tA, tB, dh, integ, cnt);
+    const double v = edge_term_geo64<M>(ad, fabs(p), tA, tB, dh, integ, cnt);
     anyint |= integ;
     ne_int += integ;
     sum += p > 0.0 ? v : -v;
@@ -789,7 +777,8 @@ __device__ inline double item_value(const float4 it, int mode, EdgeCount &cnt) {
 // |d| int [H(U) - H(|d|)] dphi over the fan of one edge (p > 0, tA < tB),
 // binary64 with the math library, in the difference form: the angle term
 // from the span, the part within 2h as the edge kernel's pieces (two when
-// the range crosses U = 1).
+// the range crosses U = 1).  For cells small against the support, whose
+// per-endpoint terms cancel far below the mixed cores' accuracy.
 __device__ double edge_term_diff(double ad, double p, double tA, double tB, double dh, bool &integ, EdgeCount &cnt) {
   const double a2 = ad * ad + p * p;
   const double r2 = 4.0 - a2, s1 = 1.0 - a2;
