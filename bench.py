@@ -145,7 +145,7 @@ def main():
     if args.precision is None:
         args.precision = "mixed"
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is designed but not a measured path", file=sys.stderr)
         sys.exit(2)
     if args.workload == "pseudo":
