@@ -97,20 +97,15 @@ __global__ void __launch_bounds__(256) k_interp(Hier H, const double4 *sd, int64
   const float r2box = H.margin_abs * H.margin_abs;
   double den = 0.0;
   double num[kCompPass] = {0.0, 0.0, 0.0, 0.0};
-  int32_t st_node[kFan * kMaxLevels];
-  int8_t st_lvl[kFan * kMaxLevels];
+  uint32_t st[kFan * kMaxLevels];  // node << 4 | level (a level-1 node index is below 2^27)
   int sp = 0;
   const int top = H.levels;
   for (int64_t j = H.n[top] - 1; j >= 0; --j)
-    if (box_hit(H.lo[top][j], H.hi[top][j], g, r2box)) {
-      st_node[sp] = (int32_t)j;
-      st_lvl[sp] = (int8_t)top;
-      ++sp;
-    }
+    if (box_hit(H.lo[top][j], H.hi[top][j], g, r2box)) st[sp++] = ((uint32_t)j << 4) | (uint32_t)top;
   while (sp > 0) {
     --sp;
-    const int l = st_lvl[sp];
-    const int64_t j = st_node[sp];
+    const int l = (int)(st[sp] & 15u);
+    const int64_t j = (int64_t)(st[sp] >> 4);
     if (l == 1) {
       const int64_t e = min(H.n[0], (j + 1) * kFan);
       for (int64_t k = j * kFan; k < e; ++k) {
@@ -131,11 +126,7 @@ __global__ void __launch_bounds__(256) k_interp(Hier H, const double4 *sd, int64
       const int lc = l - 1;
       const int64_t e = min(H.n[lc], (j + 1) * kFan);
       for (int64_t k = e - 1; k >= j * kFan; --k)
-        if (box_hit(H.lo[lc][k], H.hi[lc][k], g, r2box)) {
-          st_node[sp] = (int32_t)k;
-          st_lvl[sp] = (int8_t)lc;
-          ++sp;
-        }
+        if (box_hit(H.lo[lc][k], H.hi[lc][k], g, r2box)) st[sp++] = ((uint32_t)k << 4) | (uint32_t)lc;
     }
   }
   int bad = 0;
